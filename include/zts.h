@@ -1,0 +1,228 @@
+/*
+ * zts.h - exhaustive zero-mean NCC template search on one MI355X (gfx950).
+ *
+ * The library finds, for a uint8 template t (m x n) and a resident uint8
+ * search image I (p x q), the location maximising the correlation coefficient
+ * rho(t, r) of Eq. 1 over all (p-m+1)(q-n+1) valid blocks r, and reports how
+ * many locations were computed and how many were skipped.  Methods follow
+ * Mahmood, Mian, Owens, "Optimizing Auto-correlation for Fast Target Search in
+ * Large Search Space" (arXiv 1407.3535):
+ *   - transitive elimination of group members (section II, Eq. 2 and Eq. 5)
+ *     with the two-scan early threshold (section VI);
+ *   - Efficient Group Size (section III-D, Alg. 2, Eq. 15-17);
+ *   - OptA conditioning by controlled non-uniform blur (sections IV-V,
+ *     Alg. 3, Prop. 4.3, Eq. 28).
+ * Every mode returns the answer of an exhaustive search: the same location,
+ * the same exact integers and the same binary64 rho.
+ *
+ * Pure C.  No C++ types, exceptions or globals cross this interface.
+ *
+ * Conventions (all entry points):
+ *   - Pixels are row-major uint8; `stride` is the row pitch in bytes (>= cols).
+ *   - Coordinates are 0-based (row y, column x) of the top-left corner of a
+ *     block.  The linear location index is y*(q-n+1) + x.
+ *   - Host pointers are read (or written) before the call returns; the caller
+ *     keeps ownership.  Device pointers are borrowed for the duration of the
+ *     call only.  The library owns every device buffer it allocates and frees
+ *     them in zts_destroy / zts_image_unload.
+ *   - NULL or out-of-range arguments return ZTS_E_ARG; m > rows or n > cols
+ *     returns ZTS_E_SIZE; a template with zero variance returns
+ *     ZTS_E_DEGENERATE.  Nothing is written to outputs on error.
+ *   - A `void* stream` is a hipStream_t (NULL = the context's own stream).
+ *   - Calls on one context are serialised by the context (thread safe).
+ */
+#ifndef ZTS_H
+#define ZTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct zts_ctx zts_ctx;
+
+typedef enum {
+    ZTS_OK = 0,
+    ZTS_E_ARG = -1,
+    ZTS_E_SIZE = -2,
+    ZTS_E_DEGENERATE = -3,
+    ZTS_E_NOIMAGE = -4,
+    ZTS_E_BUDGET = -5,
+    ZTS_E_AGAIN = -6,
+    ZTS_E_BUSY = -7,
+    ZTS_E_TIMEOUT = -8,
+    ZTS_E_CANCELLED = -9,
+    ZTS_E_DEVICE = -10,
+    ZTS_E_NOMEM = -11,
+    ZTS_E_NOTPREPARED = -12
+} zts_status;
+
+/* Search modes.
+ *   ZTS_FULL      every location computed (Eq. 1 everywhere); the plain
+ *                 baseline.
+ *   ZTS_TE_FIXED  transitive elimination with a caller-given group size
+ *                 (section II; the earlier algorithm's user parameter).
+ *   ZTS_EGS       transitive elimination with the group size chosen by
+ *                 Alg. 2 on the image.
+ *   ZTS_OPTA      Alg. 3 conditions a blurred copy of the image; the search
+ *                 scans the blurred group centres, refines on the original
+ *                 image around the best one (section IV-C) and bounds every
+ *                 original location through the triangle inequality on
+ *                 angles (Eq. 2 with Prop. 4.3's blur correlation added), so
+ *                 the result is still exact. */
+typedef enum { ZTS_FULL = 0, ZTS_TE_FIXED = 2, ZTS_EGS = 3, ZTS_OPTA = 4 } zts_mode;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal */
+    uint64_t hbm_budget_bytes; /* cap on the library's device allocations, 0 = none */
+} zts_ctx_params;
+
+/* Method parameters; zts_params_default fills the paper's values. */
+typedef struct {
+    double rho_th;          /* initial threshold used by the estimates, 0.80 (section VII) */
+    double rho_max;         /* assumed peak for Prop. 4.3, 0.95 (section VII) */
+    double margin;          /* strict elimination margin delta, 1e-9 */
+    double xi;              /* relative cost decrement to continue, 0.005 (section III-D) */
+    int32_t group_h, group_w;               /* ZTS_TE_FIXED group size, 5x5 (section VII) */
+    int32_t h0, w0, dh, dw, h_max;          /* EGS start, step and cap: 3, 3, 2, 2, 33 */
+    int32_t blur_kind;      /* 0: the paper's W = {1,4,10,4,1}/20 each iteration;
+                               1: Gaussian with total sigma = sigma_step * k at iteration k */
+    double sigma_step;      /* 0.5 */
+    double sigma_max;       /* 3.0 */
+    int32_t max_iters;      /* OptA iteration cap, 6 */
+    int32_t refine_radius;  /* >0: also match every location within this Chebyshev
+                               distance of the best centre before scan 2 (raises the
+                               threshold; exactness unaffected).  0: section VI as printed.
+                               In ZTS_OPTA the window radius is max(this, cumulative blur
+                               radius, capped at 8). */
+} zts_params;
+
+/* Result of one search.  Valid only when status == ZTS_OK. */
+typedef struct {
+    int32_t y, x;            /* best location (ties: smallest linear index) */
+    double rho;              /* canonical binary64 rho at (y, x) */
+    float rho32;             /* binary32 rho from the same exact integers */
+    int32_t pad0;
+    int64_t num, den_t, den_r; /* exact N = mn*sum(t r) - sum(t) sum(r), D_t, D_r at (y, x) */
+    int64_t n_locations;     /* (p-m+1)(q-n+1) */
+    int64_t n_centres;       /* group centres matched in scan 1 */
+    int64_t n_eliminated;    /* locations skipped by the bound */
+    int64_t n_survivors;     /* members that failed the elimination test and were matched */
+    int64_t n_computed;      /* locations of I whose rho was computed */
+    int32_t group_h, group_w;
+    double best0;            /* threshold used by scan 2 (an attained rho) */
+    int32_t best0_y, best0_x;/* best group centre of scan 1 */
+    float device_ms;         /* device time of the search (HIP events) */
+    zts_status status;
+} zts_result;
+
+typedef struct {
+    int32_t h, w;
+    int64_t cc, cr, ct;      /* groups, retained members, estimated cost mn*(cc+cr) */
+    int32_t accepted;
+    int32_t pad0;
+} zts_egs_step;
+
+typedef struct {
+    int32_t k, d, passes, h, w, accepted;
+    double sigma;
+    int64_t reverted, cost;
+} zts_opta_step;
+
+/* What zts_prepare decided for one (image, m, n, mode). */
+typedef struct {
+    int32_t mode, m, n, group_h, group_w, radius;
+    int64_t cost;
+    int32_t n_egs;           /* trace of the final EGS run */
+    int32_t n_opta;          /* OptA iterations (entry 0 = the unblurred image) */
+    zts_egs_step egs[32];
+    zts_opta_step opta[16];
+    float prepare_ms;        /* wall time of zts_prepare */
+    int32_t pad0;
+} zts_prep_info;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Fills *p with the paper's parameters. */
+void zts_params_default(zts_params *p);
+
+/* Creates a context on params->device (NULL params: device 0, no budget). */
+zts_status zts_create(const zts_ctx_params *params, zts_ctx **out);
+
+/* Waits for outstanding work and frees every device buffer of the context. */
+void zts_destroy(zts_ctx *ctx);
+
+/* Static text for a status code. */
+const char *zts_status_str(zts_status s);
+
+/* ---- images ------------------------------------------------------------ */
+
+/* Copies a host image to the device and builds its running sums (the
+ * Run-Sum of section III-A / Alg. 3) of x-128 and (x-128)^2.  *id receives
+ * a handle.  ZTS_E_BUDGET when the copy would exceed the HBM budget. */
+zts_status zts_image_load(zts_ctx *ctx, const uint8_t *host, int32_t rows, int32_t cols, int64_t stride,
+                          int32_t *id);
+
+/* Same from device memory (copied device-to-device on `stream`). */
+zts_status zts_image_load_device(zts_ctx *ctx, const void *dev, int32_t rows, int32_t cols, int64_t stride,
+                                 void *stream, int32_t *id);
+
+/* Frees an image and everything prepared for it. */
+zts_status zts_image_unload(zts_ctx *ctx, int32_t id);
+
+/* ---- preparation ------------------------------------------------------- */
+
+/* Builds and keeps the per-(image, m, n, mode) tables that searches of that
+ * template size use: the group size (given, or chosen by Alg. 2), the angle
+ * of every location to its group centre (Alg. 1, stored as binary32 angles
+ * plus the exact integer sums), per-group angle ranges, and for ZTS_OPTA the
+ * conditioned image of Alg. 3 with the angle of every blurred block to its
+ * original.  ZTS_FULL needs no preparation.  Searches prepare on demand;
+ * calling this first keeps preparation out of the search time. */
+zts_status zts_prepare(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, const zts_params *params,
+                       void *stream);
+
+/* Reports what zts_prepare decided (group size, EGS and OptA traces). */
+zts_status zts_prep_query(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, zts_prep_info *out);
+
+/* Copies the conditioned image of a ZTS_OPTA preparation to host memory
+ * (rows*cols bytes, pitch cols). */
+zts_status zts_prep_image(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, uint8_t *host_out);
+
+/* ---- search ------------------------------------------------------------ */
+
+/* Synchronous search of one host template.  `decision` (nullable, one byte
+ * per location) receives 1 for a scan-1 centre, 3 for a refinement-window
+ * location, 2 for a survivor, 0 for an eliminated location (ZTS_FULL: all 2). */
+zts_status zts_search(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
+                      zts_mode mode, const zts_params *params, zts_result *out, int8_t *decision);
+
+/* Same with the template already in device memory; work is enqueued on
+ * `stream` and the call returns when the result is on the host. */
+zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tpl_dev, int32_t m, int32_t n,
+                             int64_t stride, zts_mode mode, const zts_params *params, void *stream,
+                             zts_result *out);
+
+/* ---- parity helpers ------------------------------------------------------ */
+
+/* Every location's exact N and D_r and binary32 rho for one template
+ * (ZTS_FULL kernel with its maps written out).  Any output may be NULL. */
+zts_status zts_debug_full_map(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n,
+                              int64_t stride, int64_t *num_out, int64_t *den_r_out, float *rho_out);
+
+/* Alg. 1 on the device: for group size (h, w), every location's exact
+ * N_co, D_c and D_o against its group centre (int64 arrays of L entries). */
+zts_status zts_debug_autocorr(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, int32_t h, int32_t w,
+                              int64_t *num_out, int64_t *dc_out, int64_t *do_out);
+
+/* Eq. 18 on the device: blurs a host image with separable integer taps
+ * (2d+1 of them), clamp-to-edge borders, rounded half up. */
+zts_status zts_debug_blur(zts_ctx *ctx, const uint8_t *host_in, int32_t rows, int32_t cols, const int32_t *taps,
+                          int32_t d, uint8_t *host_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZTS_H */

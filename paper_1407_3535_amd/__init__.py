@@ -1,0 +1,331 @@
+"""Python binding of libzts (exhaustive ZNCC template search on MI355X).
+
+A thin ctypes layer over the C ABI declared in ``include/zts.h``: the
+functions below carry the same names and only marshal arguments (numpy
+arrays and torch tensors to pointers, structs to dicts).  Every step of a
+search runs in the library's HIP kernels; there is no fallback.  The library
+must have been built (``python -m paper_1407_3535_amd.build`` or
+``__graft_entry__.build()``); loading fails loudly otherwise.
+
+torch is imported first so that the library binds to the HIP runtime torch
+already loaded (one runtime per process); torch provides device memory and
+streams for the ``*_device`` entry points.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # one HIP runtime per process: torch's, when torch is present
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzts.so")
+
+ZTS_FULL, ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA = 0, 2, 3, 4
+MODES = {"full": ZTS_FULL, "te_fixed": ZTS_TE_FIXED, "egs": ZTS_EGS, "opta": ZTS_OPTA}
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template", -4: "unknown image",
+          -5: "HBM budget exhausted", -6: "not ready", -7: "busy", -8: "timed out", -9: "cancelled",
+          -10: "device error", -11: "out of memory", -12: "not prepared"}
+
+EXPORTS = ["zts_params_default", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
+           "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
+           "zts_search", "zts_search_device", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
+
+
+class ZtsError(RuntimeError):
+    def __init__(self, code, where=""):
+        super().__init__(f"{where}: zts status {code} ({STATUS.get(code, '?')})")
+        self.code = code
+
+
+class CtxParams(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_uint64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("rho_th", C.c_double), ("rho_max", C.c_double), ("margin", C.c_double), ("xi", C.c_double),
+                ("group_h", C.c_int32), ("group_w", C.c_int32), ("h0", C.c_int32), ("w0", C.c_int32),
+                ("dh", C.c_int32), ("dw", C.c_int32), ("h_max", C.c_int32), ("blur_kind", C.c_int32),
+                ("sigma_step", C.c_double), ("sigma_max", C.c_double), ("max_iters", C.c_int32),
+                ("refine_radius", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("y", C.c_int32), ("x", C.c_int32), ("rho", C.c_double), ("rho32", C.c_float),
+                ("pad0", C.c_int32), ("num", C.c_int64), ("den_t", C.c_int64), ("den_r", C.c_int64),
+                ("n_locations", C.c_int64), ("n_centres", C.c_int64), ("n_eliminated", C.c_int64),
+                ("n_survivors", C.c_int64), ("n_computed", C.c_int64), ("group_h", C.c_int32),
+                ("group_w", C.c_int32), ("best0", C.c_double), ("best0_y", C.c_int32), ("best0_x", C.c_int32),
+                ("device_ms", C.c_float), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
+
+
+class EgsStep(C.Structure):
+    _fields_ = [("h", C.c_int32), ("w", C.c_int32), ("cc", C.c_int64), ("cr", C.c_int64), ("ct", C.c_int64),
+                ("accepted", C.c_int32), ("pad0", C.c_int32)]
+
+
+class OptaStep(C.Structure):
+    _fields_ = [("k", C.c_int32), ("d", C.c_int32), ("passes", C.c_int32), ("h", C.c_int32), ("w", C.c_int32),
+                ("accepted", C.c_int32), ("sigma", C.c_double), ("reverted", C.c_int64), ("cost", C.c_int64)]
+
+
+class PrepInfo(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("m", C.c_int32), ("n", C.c_int32), ("group_h", C.c_int32),
+                ("group_w", C.c_int32), ("radius", C.c_int32), ("cost", C.c_int64), ("n_egs", C.c_int32),
+                ("n_opta", C.c_int32), ("egs", EgsStep * 32), ("opta", OptaStep * 16), ("prepare_ms", C.c_float),
+                ("pad0", C.c_int32)]
+
+    def as_dict(self):
+        egs = [dict(h=s.h, w=s.w, cc=s.cc, cr=s.cr, ct=s.ct, accepted=bool(s.accepted))
+               for s in self.egs[:self.n_egs]]
+        opta = [dict(k=s.k, d=s.d, sigma=s.sigma, passes=s.passes, reverted=s.reverted, h=s.h, w=s.w,
+                     cost=s.cost, accepted=bool(s.accepted)) for s in self.opta[:self.n_opta]]
+        return dict(mode=self.mode, m=self.m, n=self.n, h=self.group_h, w=self.group_w, radius=self.radius,
+                    cost=self.cost, egs=egs, opta=opta, prepare_ms=self.prepare_ms)
+
+
+_lib = None
+
+
+def lib():
+    """Loads libzts.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1407_3535_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.zts_params_default.argtypes = [C.POINTER(Params)]
+        L.zts_params_default.restype = None
+        L.zts_create.argtypes = [C.POINTER(CtxParams), C.POINTER(vp)]
+        L.zts_destroy.argtypes = [vp]
+        L.zts_destroy.restype = None
+        L.zts_status_str.argtypes = [i32]
+        L.zts_status_str.restype = C.c_char_p
+        L.zts_image_load.argtypes = [vp, vp, i32, i32, i64, C.POINTER(i32)]
+        L.zts_image_load_device.argtypes = [vp, vp, i32, i32, i64, vp, C.POINTER(i32)]
+        L.zts_image_unload.argtypes = [vp, i32]
+        L.zts_prepare.argtypes = [vp, i32, i32, i32, i32, C.POINTER(Params), vp]
+        L.zts_prep_query.argtypes = [vp, i32, i32, i32, i32, C.POINTER(PrepInfo)]
+        L.zts_prep_image.argtypes = [vp, i32, i32, i32, vp]
+        L.zts_search.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(Result), vp]
+        L.zts_search_device.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), vp,
+                                        C.POINTER(Result)]
+        L.zts_debug_full_map.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
+        L.zts_debug_autocorr.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp]
+        L.zts_debug_blur.argtypes = [vp, vp, i32, i32, vp, i32, vp]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is C.c_int:
+                f.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise ZtsError(rc, where)
+
+
+def _u8(a):
+    a = np.asarray(a)
+    if a.dtype != np.uint8 or a.ndim != 2 or a.strides[1] != 1:
+        a = np.ascontiguousarray(a, dtype=np.uint8)
+    return a
+
+
+def _mode(mode):
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def zts_params_default(**overrides) -> Params:
+    p = Params()
+    lib().zts_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def zts_status_str(code: int) -> str:
+    return lib().zts_status_str(code).decode()
+
+
+def zts_create(device: int = 0, hbm_budget_bytes: int = 0):
+    h = C.c_void_p()
+    _check(lib().zts_create(C.byref(CtxParams(device, hbm_budget_bytes)), C.byref(h)), "zts_create")
+    return h
+
+
+def zts_destroy(ctx) -> None:
+    lib().zts_destroy(ctx)
+
+
+def zts_image_load(ctx, img) -> int:
+    img = _u8(img)
+    i = C.c_int32()
+    _check(lib().zts_image_load(ctx, img.ctypes.data, img.shape[0], img.shape[1], img.strides[0], C.byref(i)),
+           "zts_image_load")
+    return i.value
+
+
+def zts_image_load_device(ctx, tensor, stream=None) -> int:
+    """tensor: a 2-D uint8 torch tensor on the GPU (rows may be strided)."""
+    rows, cols = tensor.shape
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    i = C.c_int32()
+    _check(lib().zts_image_load_device(ctx, tensor.data_ptr(), rows, cols, tensor.stride(0), s, C.byref(i)),
+           "zts_image_load_device")
+    return i.value
+
+
+def zts_image_unload(ctx, image: int) -> None:
+    _check(lib().zts_image_unload(ctx, image), "zts_image_unload")
+
+
+def zts_prepare(ctx, image: int, m: int, n: int, mode, params: Params | None = None) -> None:
+    p = params if params is not None else zts_params_default()
+    _check(lib().zts_prepare(ctx, image, m, n, _mode(mode), C.byref(p), None), "zts_prepare")
+
+
+def zts_prep_query(ctx, image: int, m: int, n: int, mode) -> dict:
+    info = PrepInfo()
+    _check(lib().zts_prep_query(ctx, image, m, n, _mode(mode), C.byref(info)), "zts_prep_query")
+    return info.as_dict()
+
+
+def zts_prep_image(ctx, image: int, m: int, n: int, shape) -> np.ndarray:
+    out = np.zeros(shape, np.uint8)
+    _check(lib().zts_prep_image(ctx, image, m, n, out.ctypes.data), "zts_prep_image")
+    return out
+
+
+def zts_search(ctx, image: int, tpl, mode, params: Params | None = None) -> dict:
+    tpl = _u8(tpl)
+    p = params if params is not None else zts_params_default()
+    r = Result()
+    rc = lib().zts_search(ctx, image, tpl.ctypes.data, tpl.shape[0], tpl.shape[1], tpl.strides[0], _mode(mode),
+                          C.byref(p), C.byref(r), None)
+    _check(rc, "zts_search")
+    return r.as_dict()
+
+
+def zts_search_decision(ctx, image: int, image_shape, tpl, mode, params: Params | None = None):
+    """zts_search with the per-location decision map (1 centre, 3 window, 2 survivor, 0 eliminated)."""
+    tpl = _u8(tpl)
+    p = params if params is not None else zts_params_default()
+    r = Result()
+    Ly, Lx = image_shape[0] - tpl.shape[0] + 1, image_shape[1] - tpl.shape[1] + 1
+    if Ly < 1 or Lx < 1:
+        raise ZtsError(-2, "zts_search")
+    dec = np.full((Ly, Lx), -1, np.int8)
+    rc = lib().zts_search(ctx, image, tpl.ctypes.data, tpl.shape[0], tpl.shape[1], tpl.strides[0], _mode(mode),
+                          C.byref(p), C.byref(r), dec.ctypes.data)
+    _check(rc, "zts_search")
+    return r.as_dict(), dec
+
+
+def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None = None, stream=None) -> dict:
+    p = params if params is not None else zts_params_default()
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    r = Result()
+    m, n = tpl_tensor.shape
+    _check(lib().zts_search_device(ctx, image, tpl_tensor.data_ptr(), m, n, tpl_tensor.stride(0), _mode(mode),
+                                   C.byref(p), s, C.byref(r)), "zts_search_device")
+    return r.as_dict()
+
+
+def zts_debug_full_map(ctx, image: int, image_shape, tpl):
+    tpl = _u8(tpl)
+    Ly, Lx = image_shape[0] - tpl.shape[0] + 1, image_shape[1] - tpl.shape[1] + 1
+    if Ly < 1 or Lx < 1:
+        raise ZtsError(-2, "zts_debug_full_map")
+    num = np.zeros((Ly, Lx), np.int64)
+    dr = np.zeros((Ly, Lx), np.int64)
+    rho = np.zeros((Ly, Lx), np.float32)
+    _check(lib().zts_debug_full_map(ctx, image, tpl.ctypes.data, tpl.shape[0], tpl.shape[1], tpl.strides[0],
+                                    num.ctypes.data, dr.ctypes.data, rho.ctypes.data), "zts_debug_full_map")
+    return num, dr, rho
+
+
+def zts_debug_autocorr(ctx, image: int, image_shape, m: int, n: int, h: int, w: int):
+    Ly, Lx = image_shape[0] - m + 1, image_shape[1] - n + 1
+    if Ly < 1 or Lx < 1:
+        raise ZtsError(-2, "zts_debug_autocorr")
+    arrs = [np.zeros(Ly * Lx, np.int64) for _ in range(3)]
+    _check(lib().zts_debug_autocorr(ctx, image, m, n, h, w, *(a.ctypes.data for a in arrs)), "zts_debug_autocorr")
+    return tuple(arrs)
+
+
+def zts_debug_blur(ctx, img, taps) -> np.ndarray:
+    img = np.ascontiguousarray(_u8(img))
+    taps = np.ascontiguousarray(taps, np.int32)
+    d = (len(taps) - 1) // 2
+    out = np.zeros_like(img)
+    _check(lib().zts_debug_blur(ctx, img.ctypes.data, img.shape[0], img.shape[1], taps.ctypes.data, d,
+                                out.ctypes.data), "zts_debug_blur")
+    return out
+
+
+class Searcher:
+    """Convenience owner of one context: load images, search templates."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.ctx = zts_create(device, hbm_budget_bytes)
+        self.shapes = {}
+
+    def close(self):
+        if self.ctx:
+            zts_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, img) -> int:
+        img = _u8(img)
+        i = zts_image_load(self.ctx, img)
+        self.shapes[i] = img.shape
+        return i
+
+    def load_device(self, tensor) -> int:
+        i = zts_image_load_device(self.ctx, tensor)
+        self.shapes[i] = tuple(tensor.shape)
+        return i
+
+    def unload(self, image):
+        zts_image_unload(self.ctx, image)
+        self.shapes.pop(image, None)
+
+    def prepare(self, image, m, n, mode, **params):
+        zts_prepare(self.ctx, image, m, n, mode, zts_params_default(**params))
+        if _mode(mode) != ZTS_FULL:
+            return zts_prep_query(self.ctx, image, m, n, mode)
+        return None
+
+    def search(self, image, tpl, mode="egs", decision=False, **params):
+        p = zts_params_default(**params)
+        if decision:
+            return zts_search_decision(self.ctx, image, self.shapes[image], tpl, mode, p)
+        return zts_search(self.ctx, image, tpl, mode, p)
+
+    def prep_image(self, image, m, n):
+        return zts_prep_image(self.ctx, image, m, n, self.shapes[image])

@@ -1,0 +1,291 @@
+// Device helpers shared by the zts kernels (gfx950, wave64).
+//
+// Pixels are kept as uint8 and read as int8 after flipping the top bit
+// (x' = x - 128 = x ^ 0x80).  For blocks a, b of mn pixels the integers
+//   N = mn*sum(a'b') - sum(a')sum(b'),   D_a = mn*sum(a'^2) - sum(a')^2
+// equal the same expressions on the unshifted pixels, so every decision is
+// taken on exact integers.  sum(a'b') fits int32 for mn <= 2^14.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zts_shared.h"
+
+namespace zts {
+
+constexpr int kWave = 64;
+constexpr float kEpsTheta = 1e-5f;  // guard band on binary32 angles (rad)
+constexpr float kEpsRho = 1e-5f;    // guard band on binary32 correlations
+
+// ---------------------------------------------------------------- int8 words
+
+__device__ __forceinline__ uint32_t flip4(uint32_t w) { return w ^ 0x80808080u; }
+
+__device__ __forceinline__ int dot4(uint32_t a, uint32_t b, int acc)
+{
+    return __builtin_amdgcn_sdot4((int)a, (int)b, acc, false);
+}
+
+// The 4 bytes starting `sh` bytes into `lo`, continuing into `hi`.
+__device__ __forceinline__ uint32_t bytes_at(uint32_t hi, uint32_t lo, uint32_t sh)
+{
+    return __builtin_amdgcn_alignbyte(hi, lo, sh);
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------- 128-bit integers
+
+struct u128 {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ u128 mul_u64(uint64_t a, uint64_t b)
+{
+    u128 r;
+    r.lo = a * b;
+    r.hi = __umul64hi(a, b);
+    return r;
+}
+
+// a - b, clamped at 0 when b > a.
+__device__ __forceinline__ u128 sub_sat(u128 a, u128 b)
+{
+    if (a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo))
+        return u128{0, 0};
+    u128 r;
+    r.lo = a.lo - b.lo;
+    r.hi = a.hi - b.hi - (a.lo < b.lo ? 1 : 0);
+    return r;
+}
+
+// Round-to-nearest-even conversion: keep the top 64 significant bits, fold
+// every dropped bit into a sticky bit 0, let the (correctly rounded) u64
+// conversion round, then scale exactly.
+__device__ __forceinline__ double u128_to_f64(u128 v)
+{
+    if (v.hi == 0)
+        return (double)v.lo;
+    int lz = __clzll(v.hi);
+    int s = 64 - lz;
+    uint64_t top, dropped;
+    if (lz == 0) {
+        top = v.hi;
+        dropped = v.lo;
+    } else {
+        top = (v.hi << lz) | (v.lo >> s);
+        dropped = v.lo & ((1ull << s) - 1ull);
+    }
+    top |= (dropped != 0) ? 1ull : 0ull;
+    return ldexp((double)top, s);
+}
+
+// ---------------------------------------------------------------- canonical binary64
+
+// rho = N / sqrt(D_a * D_b) (Eq. 1 with the 1/mn factors cancelled); a flat
+// block has rho := 0.  Three correctly rounded operations in this order.
+__device__ __forceinline__ double rho64(int64_t num, int64_t da, int64_t db)
+{
+    if (da == 0 || db == 0)
+        return 0.0;
+    double den = (double)da * (double)db;
+    return (double)num / __builtin_sqrt(den);
+}
+
+// sqrt(1 - rho^2) as sqrt((D_a D_b - N^2) / (D_a D_b)) with the numerator
+// exact in 128 bits; a flat block has s := 1.
+__device__ __forceinline__ double sin64(int64_t num, int64_t da, int64_t db)
+{
+    if (da == 0 || db == 0)
+        return 1.0;
+    uint64_t an = num < 0 ? (uint64_t)(-num) : (uint64_t)num;
+    u128 d = sub_sat(mul_u64((uint64_t)da, (uint64_t)db), mul_u64(an, an));
+    double nd = u128_to_f64(d);
+    return __builtin_sqrt(nd / ((double)da * (double)db));
+}
+
+// Upper bound of rho_to from the angle triangle |A - B| - C (cos/sin pairs);
+// returns false when no bound below 1 exists.  With C = (1, 0) this is the
+// transitive bound of Eq. 2, rho_a*rho_b + s_a*s_b.
+__device__ __forceinline__ bool ub_general(double ra, double sa, double rb, double sb, double rc, double sc,
+                                           double *ub)
+{
+    double rab = ra * rb + sa * sb;
+    double sab = fabs(sa * rb - ra * sb);
+    if (rab >= rc)
+        return false;
+    *ub = rab * rc + sab * sc;
+    return true;
+}
+
+// ---------------------------------------------------------------- binary32 prefilter values
+
+__device__ __forceinline__ float rho32(int64_t num, int64_t da, int64_t db)
+{
+    if (da == 0 || db == 0)
+        return 0.0f;
+    return (float)num / sqrtf((float)da * (float)db);
+}
+
+// Angle between two mean-centred blocks, atan2(s, rho) in binary32 from the
+// exact integers; NaN for a flat block.  Absolute error below 2e-6 rad.
+__device__ __forceinline__ float theta32(int64_t num, int64_t da, int64_t db)
+{
+    if (da == 0 || db == 0)
+        return __int_as_float(0x7fc00000);
+    uint64_t an = num < 0 ? (uint64_t)(-num) : (uint64_t)num;
+    u128 d = sub_sat(mul_u64((uint64_t)da, (uint64_t)db), mul_u64(an, an));
+    float den = (float)da * (float)db;
+    float s = sqrtf((float)u128_to_f64(d) / den);
+    float r = (float)num / sqrtf(den);
+    return atan2f(s, r);
+}
+
+// ---------------------------------------------------------------- block statistics
+
+// Per-location statistics for one block size: S' = sum(x') (int32) and
+// Q' = sum(x'^2) (uint32 bits).  D = mn Q' - S'^2 is exact in int64.
+__device__ __forceinline__ int64_t var_num(int64_t mn, int2 st)
+{
+    return mn * (int64_t)(uint32_t)st.y - (int64_t)st.x * (int64_t)st.x;
+}
+
+// ---------------------------------------------------------------- window dot products
+
+// Work split of an m-row by n4-word window over the 64 lanes of a wave:
+// lanes_per_row lanes share a row, rows_per_pass rows are covered at once.
+struct WaveSplit {
+    int lpr, rpp, wps;
+};
+
+__device__ __forceinline__ WaveSplit wave_split(int m, int n4)
+{
+    int lpr = kWave / m;
+    if (lpr < 1)
+        lpr = 1;
+    if (lpr > n4)
+        lpr = n4;
+    WaveSplit s;
+    s.lpr = lpr;
+    s.rpp = kWave / lpr;
+    s.wps = (n4 + lpr - 1) / lpr;
+    return s;
+}
+
+// sum over the m x n block at (y, x) of t' * r', with the template held in
+// LDS as flipped int8 words (n4 words per row, zero beyond column n).  The
+// image row segment is read as aligned dwords and realigned with
+// v_alignbyte.  Every lane returns the full sum.
+__device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, int n4, const uint8_t *__restrict__ img,
+                                            int64_t pitch, int y, int x, int m, WaveSplit ws, int lane)
+{
+    int acc = 0;
+    int r = lane / ws.lpr, seg = lane - r * ws.lpr;
+    int j0 = seg * ws.wps;
+    int j1 = min(n4, j0 + ws.wps);
+    if (r < ws.rpp && j0 < j1) {
+        for (int i = r; i < m; i += ws.rpp) {
+            int64_t a = (int64_t)(y + i) * pitch + x + 4 * j0;
+            const uint32_t *p = (const uint32_t *)(img + (a & ~(int64_t)3));
+            uint32_t sh = (uint32_t)(a & 3);
+            const uint32_t *t = tplw + i * n4;
+            uint32_t lo = p[0];
+            for (int j = j0; j < j1; j++) {
+                uint32_t hi = p[j - j0 + 1];
+                acc = dot4(flip4(bytes_at(hi, lo, sh)), t[j], acc);
+                lo = hi;
+            }
+        }
+    }
+    return wave_sum(acc);
+}
+
+// sum over m x n of a' * b' for the block of A at (ya, xa) and of B at
+// (yb, xb); bytes past column n of the last word are masked off.
+__device__ __forceinline__ int wave_dot_img(const uint8_t *__restrict__ A, int64_t pa, int ya, int xa,
+                                            const uint8_t *__restrict__ B, int64_t pb, int yb, int xb, int m, int n,
+                                            WaveSplit ws, int lane)
+{
+    int n4 = (n + 3) >> 2;
+    uint32_t last_mask = (n & 3) ? ((1u << (8 * (n & 3))) - 1u) : 0xffffffffu;
+    int acc = 0;
+    int r = lane / ws.lpr, seg = lane - r * ws.lpr;
+    int j0 = seg * ws.wps;
+    int j1 = min(n4, j0 + ws.wps);
+    if (r < ws.rpp && j0 < j1) {
+        for (int i = r; i < m; i += ws.rpp) {
+            int64_t a = (int64_t)(ya + i) * pa + xa + 4 * j0;
+            int64_t b = (int64_t)(yb + i) * pb + xb + 4 * j0;
+            const uint32_t *pA = (const uint32_t *)(A + (a & ~(int64_t)3));
+            const uint32_t *pB = (const uint32_t *)(B + (b & ~(int64_t)3));
+            uint32_t sa = (uint32_t)(a & 3), sb = (uint32_t)(b & 3);
+            uint32_t loA = pA[0], loB = pB[0];
+            for (int j = j0; j < j1; j++) {
+                uint32_t hiA = pA[j - j0 + 1], hiB = pB[j - j0 + 1];
+                uint32_t va = flip4(bytes_at(hiA, loA, sa));
+                uint32_t vb = flip4(bytes_at(hiB, loB, sb));
+                if (j == n4 - 1)
+                    va &= last_mask;
+                acc = dot4(va, vb, acc);
+                loA = hiA;
+                loB = hiB;
+            }
+        }
+    }
+    return wave_sum(acc);
+}
+
+// ---------------------------------------------------------------- best-location records
+
+__device__ __forceinline__ bool rec_better(double r1, int64_t l1, double r2, int64_t l2)
+{
+    return r1 > r2 || (r1 == r2 && l1 < l2);
+}
+
+__device__ __forceinline__ RecPod rec_empty()
+{
+    RecPod r;
+    r.rho = -2.0;
+    r.l = INT64_MAX;
+    r.num = 0;
+    r.dr = 0;
+    r.r32max = -2.0f;
+    r.valid = 0;
+    return r;
+}
+
+__device__ __forceinline__ void rec_merge(RecPod &a, const RecPod &b)
+{
+    float m = fmaxf(a.r32max, b.r32max);
+    if (b.valid && (!a.valid || rec_better(b.rho, b.l, a.rho, a.l)))
+        a = b;
+    a.r32max = m;
+}
+
+// Streaming band selection: a candidate is evaluated in binary64 when its
+// binary32 rho is within kEpsRho of the largest binary32 rho seen so far by
+// this owner.  The running maximum only grows, so every candidate within the
+// band of the final maximum is evaluated.
+__device__ __forceinline__ void rec_offer(RecPod &r, float r32, int64_t l, int64_t num, int64_t dt, int64_t dr)
+{
+    if (r32 >= r.r32max - kEpsRho) {
+        double rho = rho64(num, dt, dr);
+        if (!r.valid || rec_better(rho, l, r.rho, r.l)) {
+            r.rho = rho;
+            r.l = l;
+            r.num = num;
+            r.dr = dr;
+            r.valid = 1;
+        }
+    }
+    r.r32max = fmaxf(r.r32max, r32);
+}
+
+}  // namespace zts

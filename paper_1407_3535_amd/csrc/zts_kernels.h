@@ -1,0 +1,159 @@
+// Kernel argument blocks and launch wrappers (host side of zts_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zts_shared.h"
+
+namespace zts {
+
+// Dense search: every location of the image.
+struct FullArgs {
+    const uint8_t *img;
+    int64_t pitch;
+    int p, q;
+    const int2 *stat;  // per-location (sum x', sum x'^2) for (m, n)
+    const uint8_t *tpl;
+    int64_t ts;
+    int m, n, n4w;
+    int Ly, Lx;
+    RecPod *recs;
+    QState *qs;
+    int64_t *num_map;  // optional outputs (parity checks)
+    int64_t *dr_map;
+    float *rho_map;
+    int8_t *dec;
+};
+
+// Scan 1: group centres of the searched image.
+struct ScanArgs {
+    const uint8_t *img;
+    int64_t pitch;
+    const int2 *stat;
+    const uint8_t *tpl;
+    int64_t ts;
+    int m, n, Ly, Lx, h, w, Gy, Gx;
+    int64_t *g_num;
+    float *g_theta;
+    RecPod *recs;
+    QState *qs;
+    int8_t *dec;
+    double delta;
+    int set_thr;  // no refinement follows: set the scan-2 threshold here
+};
+
+// Refinement window on the original image.
+struct WinArgs {
+    const uint8_t *img;
+    int64_t pitch;
+    const int2 *stat;
+    const uint8_t *tpl;
+    int64_t ts;
+    int m, n, Ly, Lx, h, w;
+    int radius;
+    int skip_centres;   // scan 1 ran on this image: its centres are already matched
+    int include_best0;  // the scan-1 best is an original-image rho
+    RecPod *recs;
+    int rec_off;
+    QState *qs;
+    int8_t *dec;
+    double delta;
+};
+
+// Scan 2: group and member tests, survivors matched on the original image.
+struct MemArgs {
+    const uint8_t *I;
+    int64_t pI;
+    const int2 *statI;  // original image statistics
+    const int2 *statS;  // statistics of the image scan 1 searched (I, or the blurred J)
+    const uint8_t *tpl;
+    int64_t ts;
+    int m, n, Ly, Lx, h, w, Gy, Gx;
+    const int64_t *g_num;
+    const float *g_theta;
+    const GroupSum *gsum;
+    const float *theta_b;   // member vs its centre on the searched image
+    const int32_t *x_b;
+    const float *theta_c;   // searched-image block vs original block (opta)
+    const int32_t *x_c;
+    int opta;
+    int radius;  // window radius, -1 when there is none
+    RecPod *recs;
+    int rec_off;
+    int final_from;
+    QState *qs;
+    int8_t *dec;
+};
+
+enum { AC_DEBUG = 0, AC_COUNT = 1, AC_COUNT_BLUR = 2, AC_BUILD = 3 };
+
+struct AcArgs {
+    const uint8_t *J;
+    int64_t pJ;
+    const int2 *statJ;
+    const int2 *statI;
+    int m, n, Ly, Lx, h, w;
+    int mode;
+    int64_t *num_out, *dc_out, *do_out;
+    float *theta_b;
+    int32_t *x_b;
+    const float *theta_c;
+    const int32_t *x_c;
+    double thr;                  // sqrt(1 - rho_th^2)
+    float thr_lo, thr_hi;        // thr -/+ guard band
+    float alo_lo, alo_hi;        // acos(thr) -/+ guard band
+    float ahi_lo, ahi_hi;        // 2 pi - acos(thr) -/+ guard band
+    unsigned long long *counter;
+};
+
+struct GsumArgs {
+    const float *theta_b;
+    const float *theta_c;
+    int Ly, Lx, h, w, Gy, Gx;
+    int opta;
+    GroupSum *gsum;
+};
+
+enum { BC_VIOL = 0, BC_BUILD = 1, BC_DEBUG = 2 };
+
+struct BcArgs {
+    const uint8_t *J;
+    const uint8_t *I;
+    int64_t pitch;
+    const int2 *statJ;
+    const int2 *statI;
+    int m, n, Ly, Lx;
+    int mode;
+    uint8_t *viol;
+    unsigned long long *counter;
+    double lambda;
+    float lam_lo, lam_hi;
+    float *theta_c;
+    int32_t *x_c;
+    int64_t *num_out, *dj_out, *di_out;
+};
+
+hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);
+hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s);
+
+int full_record_count(int Ly, int Lx);
+size_t full_lds_bytes(int m, int n);
+hipError_t launch_full(FullArgs a, hipStream_t s);
+
+int centres_record_count(int G);
+hipError_t launch_centres(ScanArgs a, hipStream_t s);
+int window_record_count(int radius);
+hipError_t launch_window(WinArgs a, hipStream_t s);
+int members_record_count(int Gy, int Gx);
+hipError_t launch_members(MemArgs a, hipStream_t s);
+
+hipError_t launch_autocorr(AcArgs a, hipStream_t s);
+hipError_t launch_gsum(GsumArgs a, hipStream_t s);
+hipError_t launch_blur(const uint8_t *src, uint8_t *dst, int64_t pitch, int p, int q, const Taps &tp,
+                       uint32_t *tmp, hipStream_t s);
+hipError_t launch_blurcorr(BcArgs a, hipStream_t s);
+hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, int Ly, int Lx, int m, int n,
+                         const uint8_t *I, uint8_t *J, int64_t pitch, unsigned long long *counter, hipStream_t s);
+
+}  // namespace zts

@@ -1,0 +1,1088 @@
+// HIP kernels for exhaustive ZNCC template search with transitive elimination
+// (gfx950, wave64).  Launch wrappers at the end are what the host library
+// calls; nothing here allocates.
+#include "zts_kernels.h"
+
+#include "zts_device.h"
+
+namespace zts {
+
+// ============================================================== block helpers
+
+__device__ __forceinline__ int block_sum_int(int v, int *red)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0)
+        red[w] = v;
+    __syncthreads();
+    int s = 0;
+    for (int k = 0; k < nw; k++)
+        s += red[k];
+    return s;
+}
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long *red)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off);
+    __syncthreads();
+    if (lane == 0)
+        red[w] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int k = 0; k < nw; k++)
+        s += red[k];
+    return s;
+}
+
+// Loads an m x n uint8 template into LDS as flipped int8 words, n4w words per
+// row, rows [off, off+m) of rows_lds; everything else zero.  Returns sum(t')
+// and sum(t'^2) to every thread.
+__device__ void load_template(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int n4w, int off,
+                              int rows_lds, uint32_t *lds, int *red, int64_t *st, int64_t *sq)
+{
+    int total = rows_lds * n4w;
+    int s = 0, s2 = 0;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int r = idx / n4w - off, j = idx - (idx / n4w) * n4w;
+        uint32_t w = 0;
+        if (r >= 0 && r < m) {
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                int c = 4 * j + b;
+                if (c < n) {
+                    int v = (int)tpl[(int64_t)r * ts + c] - 128;
+                    w |= ((uint32_t)(v & 0xff)) << (8 * b);
+                    s += v;
+                    s2 += v * v;
+                }
+            }
+        }
+        lds[idx] = w;
+    }
+    *st = block_sum_int(s, red);
+    *sq = block_sum_int(s2, red);
+    __syncthreads();
+}
+
+// Merges per-thread records of the block; thread 0 gets the result.
+__device__ RecPod block_rec(RecPod r, RecPod *red)
+{
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            rec_merge(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    RecPod out = red[0];
+    __syncthreads();
+    return out;
+}
+
+// Whole-block reduction of a record range (run by the last block only).
+__device__ RecPod reduce_records(const RecPod *recs, int lo, int hi, RecPod *red)
+{
+    RecPod r = rec_empty();
+    for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        RecPod b = recs[k];
+        rec_merge(r, b);
+    }
+    return block_rec(r, red);
+}
+
+// Last-block ticket: true in exactly one block, after every block's writes
+// before this call are visible to it.
+__device__ bool last_block(unsigned int *ticket, int *flag)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int total = gridDim.x * gridDim.y * gridDim.z;
+        unsigned int prev = atomicAdd(ticket, 1u);
+        *flag = (prev == total - 1);
+    }
+    __syncthreads();
+    bool last = *flag != 0;
+    if (last) {
+        __threadfence();
+        if (threadIdx.x == 0)
+            *ticket = 0;
+    }
+    return last;
+}
+
+__device__ void set_threshold(QState *qs, double best, int64_t best_l, double delta)
+{
+    qs->best = best;
+    qs->best_l = best_l;
+    double thr = best - delta;
+    qs->thr64 = thr;
+    double c = thr > 1.0 ? 1.0 : (thr < -1.0 ? -1.0 : thr);
+    float th = (float)acos(c);
+    qs->thr_lo = th - kEpsTheta;
+    qs->thr_hi = th + kEpsTheta;
+}
+
+__device__ __forceinline__ void group_geom(int g, int Gx, int Ly, int Lx, int h, int w, int &oy, int &ox, int &hh,
+                                           int &ww, int &cy, int &cx)
+{
+    int gy = g / Gx, gx = g - (g / Gx) * Gx;
+    oy = gy * h;
+    ox = gx * w;
+    hh = min(h, Ly - oy);
+    ww = min(w, Lx - ox);
+    cy = oy + (hh - 1) / 2;
+    cx = ox + (ww - 1) / 2;
+}
+
+__device__ __forceinline__ int64_t centre_of(int y, int x, int Ly, int Lx, int h, int w)
+{
+    int oy = (y / h) * h, ox = (x / w) * w;
+    int hh = min(h, Ly - oy), ww = min(w, Lx - ox);
+    return (int64_t)(oy + (hh - 1) / 2) * Lx + (ox + (ww - 1) / 2);
+}
+
+// ============================================================== running sums
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t u = __shfl_up(v, off);
+        if (lane >= off)
+            v += u;
+    }
+    return v;
+}
+
+// Row pass: sat[(y+1)(q+1) + x+1] = sum over row y, columns <= x, of x' and
+// x'^2 (uint32, modulo 2^32; box sums of fewer than 2^14 pixels are exact).
+__global__ __launch_bounds__(256) void k_sat_rows(const uint8_t *__restrict__ img, int64_t pitch, int p, int q,
+                                                  uint2 *__restrict__ sat)
+{
+    __shared__ uint32_t wa[4], wb[4];
+    int y = blockIdx.x;
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint8_t *row = img + (int64_t)y * pitch;
+    uint2 *out = sat + (int64_t)(y + 1) * (q + 1);
+    if (t == 0)
+        out[0] = make_uint2(0u, 0u);
+    uint32_t ca = 0, cb = 0;
+    for (int base = 0; base < q; base += 256) {
+        int x = base + t;
+        int v = x < q ? (int)row[x] - 128 : 0;
+        uint32_t a = wave_incl_scan((uint32_t)v, lane);
+        uint32_t b = wave_incl_scan((uint32_t)(v * v), lane);
+        if (lane == 63) {
+            wa[wv] = a;
+            wb[wv] = b;
+        }
+        __syncthreads();
+        uint32_t pa = ca, pb = cb;
+        for (int k = 0; k < wv; k++) {
+            pa += wa[k];
+            pb += wb[k];
+        }
+        if (x < q)
+            out[x + 1] = make_uint2(pa + a, pb + b);
+        for (int k = 0; k < 4; k++) {
+            ca += wa[k];
+            cb += wb[k];
+        }
+        __syncthreads();
+    }
+}
+
+// Column pass: 64 columns by 16 row chunks per block.
+__global__ __launch_bounds__(1024) void k_sat_cols(uint2 *__restrict__ sat, int p, int q)
+{
+    __shared__ uint2 tot[16][64];
+    int tx = threadIdx.x, k = threadIdx.y;
+    int c = blockIdx.x * 64 + tx;
+    int per = (p + 15) / 16;
+    int r0 = 1 + k * per, r1 = min(p + 1, r0 + per);
+    int64_t W = q + 1;
+    uint32_t a = 0, b = 0;
+    if (c <= q)
+        for (int r = r0; r < r1; r++) {
+            uint2 v = sat[(int64_t)r * W + c];
+            a += v.x;
+            b += v.y;
+        }
+    tot[k][tx] = make_uint2(a, b);
+    __syncthreads();
+    uint32_t ea = 0, eb = 0;
+    for (int kk = 0; kk < k; kk++) {
+        ea += tot[kk][tx].x;
+        eb += tot[kk][tx].y;
+    }
+    if (c <= q)
+        for (int r = r0; r < r1; r++) {
+            int64_t i = (int64_t)r * W + c;
+            uint2 v = sat[i];
+            ea += v.x;
+            eb += v.y;
+            sat[i] = make_uint2(ea, eb);
+        }
+}
+
+// Per-location box statistics for an m x n block from four table entries.
+__global__ __launch_bounds__(256) void k_stats(const uint2 *__restrict__ sat, int q, int Ly, int Lx, int m, int n,
+                                               int2 *__restrict__ stat)
+{
+    int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (l >= (int64_t)Ly * Lx)
+        return;
+    int y = (int)(l / Lx), x = (int)(l - (l / Lx) * Lx);
+    int64_t W = q + 1;
+    uint2 a = sat[(int64_t)y * W + x], b = sat[(int64_t)y * W + x + n];
+    uint2 c = sat[(int64_t)(y + m) * W + x], d = sat[(int64_t)(y + m) * W + x + n];
+    uint32_t S = d.x - b.x - c.x + a.x;
+    uint32_t Q = d.y - b.y - c.y + a.y;
+    stat[l] = make_int2((int)S, (int)Q);
+}
+
+// ============================================================== dense search (every location)
+
+// Tile: 64 lanes x 4 adjacent columns = 256 locations wide, 4 waves x R rows
+// high.  The image tile (flipped to int8) and the template (padded with R-1
+// zero rows above and below) sit in LDS.  For image row k of the wave's
+// window and each 16-byte template chunk, a lane realigns its 5 image words
+// into the 16 words its 4 columns need (v_alignbyte) and issues 16 v_dot4
+// per output row.
+template <int R>
+__global__ __launch_bounds__(256) void k_full(FullArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[8];
+    __shared__ int lastflag;
+    const int n4w = a.n4w;
+    const int TR = 4 * R + a.m - 1;
+    const int TWW = 64 + n4w;
+    uint32_t *img_l = smem;
+    uint32_t *tpl_l = smem + TR * TWW;
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int x0 = blockIdx.x * 256, y0 = blockIdx.y * (4 * R);
+
+    int64_t st, sq;
+    load_template(a.tpl, a.ts, a.m, a.n, n4w, R - 1, a.m + 2 * R - 2, tpl_l, red, &st, &sq);
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int64_t dt = mn * sq - st * st;
+    if (dt == 0) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
+            a.qs->degenerate = 1;
+        return;
+    }
+    for (int idx = t; idx < TR * TWW; idx += 256) {
+        int r = idx / TWW, c = idx - (idx / TWW) * TWW;
+        int gy = y0 + r;
+        int64_t gx = (int64_t)x0 + 4 * c;
+        uint32_t w = 0;
+        if (gy < a.p && gx + 4 <= a.pitch)
+            w = flip4(*(const uint32_t *)(a.img + (int64_t)gy * a.pitch + gx));
+        img_l[idx] = w;
+    }
+    __syncthreads();
+
+    int acc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+            acc[r][s] = 0;
+
+    for (int k = 0; k < R + a.m - 1; k++) {
+        const uint32_t *irow = img_l + (wv * R + k) * TWW + lane;
+        const uint32_t *tbase = tpl_l + (k + R - 1) * n4w;
+        uint32_t w0 = irow[0];
+        for (int jc = 0; jc < n4w; jc += 4) {
+            uint32_t w1 = irow[jc + 1], w2 = irow[jc + 2], w3 = irow[jc + 3], w4 = irow[jc + 4];
+            uint32_t sv[4][4];
+            sv[0][0] = w0; sv[0][1] = bytes_at(w1, w0, 1); sv[0][2] = bytes_at(w1, w0, 2); sv[0][3] = bytes_at(w1, w0, 3);
+            sv[1][0] = w1; sv[1][1] = bytes_at(w2, w1, 1); sv[1][2] = bytes_at(w2, w1, 2); sv[1][3] = bytes_at(w2, w1, 3);
+            sv[2][0] = w2; sv[2][1] = bytes_at(w3, w2, 1); sv[2][2] = bytes_at(w3, w2, 2); sv[2][3] = bytes_at(w3, w2, 3);
+            sv[3][0] = w3; sv[3][1] = bytes_at(w4, w3, 1); sv[3][2] = bytes_at(w4, w3, 2); sv[3][3] = bytes_at(w4, w3, 3);
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                uint4 tw = *(const uint4 *)(tbase - r * n4w + jc);
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    int v = acc[r][s];
+                    v = dot4(sv[0][s], tw.x, v);
+                    v = dot4(sv[1][s], tw.y, v);
+                    v = dot4(sv[2][s], tw.z, v);
+                    v = dot4(sv[3][s], tw.w, v);
+                    acc[r][s] = v;
+                }
+            }
+            w0 = w4;
+        }
+    }
+
+    RecPod rec = rec_empty();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int y = y0 + wv * R + r;
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            int x = x0 + 4 * lane + s;
+            if (y < a.Ly && x < a.Lx) {
+                int64_t l = (int64_t)y * a.Lx + x;
+                int2 stl = a.stat[l];
+                int64_t dr = var_num(mn, stl);
+                int64_t num = mn * (int64_t)acc[r][s] - st * (int64_t)stl.x;
+                float r32 = rho32(num, dt, dr);
+                rec_offer(rec, r32, l, num, dt, dr);
+                if (a.num_map)
+                    a.num_map[l] = num;
+                if (a.dr_map)
+                    a.dr_map[l] = dr;
+                if (a.rho_map)
+                    a.rho_map[l] = r32;
+                if (a.dec)
+                    a.dec[l] = 2;
+            }
+        }
+    }
+    __syncthreads();
+    RecPod *rred = (RecPod *)smem;
+    RecPod b = block_rec(rec, rred);
+    int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    if (t == 0)
+        a.recs[bid] = b;
+    if (last_block(&a.qs->done[0], &lastflag)) {
+        RecPod f = reduce_records(a.recs, 0, gridDim.x * gridDim.y, rred);
+        if (t == 0) {
+            a.qs->st = st;
+            a.qs->dt = dt;
+            a.qs->fin = f;
+            a.qs->fin_r32 = rho32(f.num, dt, f.dr);
+        }
+    }
+}
+
+// ============================================================== scan 1: group centres
+
+// Each wave matches the template against 8 group centres of the searched
+// image.  Per group it keeps the exact N_tc and the binary32 angle A.
+__global__ __launch_bounds__(256) void k_centres(ScanArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[8];
+    __shared__ RecPod wrec[4];
+    __shared__ RecPod rred[256];
+    __shared__ int lastflag;
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int n4 = (a.n + 3) >> 2;
+    int64_t st, sq;
+    load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int64_t dt = mn * sq - st * st;
+    if (dt == 0) {
+        if (blockIdx.x == 0 && t == 0)
+            a.qs->degenerate = 1;
+        return;
+    }
+    WaveSplit ws = wave_split(a.m, n4);
+    RecPod rec = rec_empty();
+    int G = a.Gy * a.Gx;
+    for (int k = 0; k < 8; k++) {
+        int g = blockIdx.x * 32 + wv * 8 + k;
+        if (g >= G)
+            break;
+        int oy, ox, hh, ww, cy, cx;
+        group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
+        int X = wave_dot_tpl(smem, n4, a.img, a.pitch, cy, cx, a.m, ws, lane);
+        if (lane == 0) {
+            int64_t l = (int64_t)cy * a.Lx + cx;
+            int2 sc = a.stat[l];
+            int64_t dc = var_num(mn, sc);
+            int64_t num = mn * (int64_t)X - st * (int64_t)sc.x;
+            a.g_num[g] = num;
+            a.g_theta[g] = theta32(num, dt, dc);
+            rec_offer(rec, rho32(num, dt, dc), l, num, dt, dc);
+            if (a.dec)
+                a.dec[l] = 1;
+        }
+    }
+    if (lane == 0)
+        wrec[wv] = rec;
+    __syncthreads();
+    if (t == 0) {
+        RecPod b = wrec[0];
+        for (int k = 1; k < 4; k++)
+            rec_merge(b, wrec[k]);
+        a.recs[blockIdx.x] = b;
+    }
+    if (last_block(&a.qs->done[0], &lastflag)) {
+        RecPod f = reduce_records(a.recs, 0, gridDim.x, rred);
+        if (t == 0) {
+            a.qs->st = st;
+            a.qs->dt = dt;
+            a.qs->best0 = f.rho;
+            a.qs->best0_l = f.l;
+            if (a.set_thr)
+                set_threshold(a.qs, f.rho, f.l, a.delta);
+        }
+    }
+}
+
+// ============================================================== refinement window
+
+// Matches the template on the original image at every location within
+// `radius` of the best scan-1 centre (skipping locations scan 1 already
+// matched when it ran on the same image), then sets the scan-2 threshold to
+// the best rho among the window (and the centres, when they were on I).
+__global__ __launch_bounds__(256) void k_window(WinArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[8];
+    __shared__ RecPod wrec[4];
+    __shared__ RecPod rred[256];
+    __shared__ int lastflag;
+    __shared__ unsigned long long ured[8];
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (a.qs->degenerate)
+        return;
+    int n4 = (a.n + 3) >> 2;
+    int64_t st, sq;
+    load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int64_t dt = mn * sq - st * st;
+    WaveSplit ws = wave_split(a.m, n4);
+    int64_t c0 = a.qs->best0_l;
+    int cy0 = (int)(c0 / a.Lx), cx0 = (int)(c0 - (c0 / a.Lx) * a.Lx);
+    int W = 2 * a.radius + 1;
+    int total = W * W;
+    RecPod rec = rec_empty();
+    unsigned long long cnt = 0;
+    int waves = gridDim.x * 4;
+    for (int k = blockIdx.x * 4 + wv; k < total; k += waves) {
+        int y = cy0 - a.radius + k / W, x = cx0 - a.radius + (k - (k / W) * W);
+        if (y < 0 || y >= a.Ly || x < 0 || x >= a.Lx)
+            continue;
+        int64_t l = (int64_t)y * a.Lx + x;
+        if (a.skip_centres && centre_of(y, x, a.Ly, a.Lx, a.h, a.w) == l)
+            continue;
+        int X = wave_dot_tpl(smem, n4, a.img, a.pitch, y, x, a.m, ws, lane);
+        if (lane == 0) {
+            int2 so = a.stat[l];
+            int64_t dr = var_num(mn, so);
+            int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
+            rec_offer(rec, rho32(num, dt, dr), l, num, dt, dr);
+            cnt++;
+            if (a.dec)
+                a.dec[l] = 3;
+        }
+    }
+    if (lane == 0)
+        wrec[wv] = rec;
+    unsigned long long c = block_sum_u64(lane == 0 ? cnt : 0ull, ured);
+    if (t == 0) {
+        RecPod b = wrec[0];
+        for (int k = 1; k < 4; k++)
+            rec_merge(b, wrec[k]);
+        a.recs[a.rec_off + blockIdx.x] = b;
+        atomicAdd(&a.qs->n_window, c);
+    }
+    if (last_block(&a.qs->done[1], &lastflag)) {
+        RecPod f = reduce_records(a.recs, a.rec_off, a.rec_off + gridDim.x, rred);
+        if (t == 0) {
+            double best = f.valid ? f.rho : -2.0;
+            int64_t bl = f.valid ? f.l : INT64_MAX;
+            if (a.include_best0 && rec_better(a.qs->best0, a.qs->best0_l, best, bl)) {
+                best = a.qs->best0;
+                bl = a.qs->best0_l;
+            }
+            set_threshold(a.qs, best, bl, a.delta);
+        }
+    }
+}
+
+// ============================================================== scan 2: members
+
+__device__ __forceinline__ bool in_window(int y, int x, int wy, int wx, int radius)
+{
+    return radius >= 0 && abs(y - wy) <= radius && abs(x - wx) <= radius;
+}
+
+// Canonical binary64 elimination test (the transitive bound of Eq. 2, or
+// its angle-triangle form with the blur angle C when a.opta).  True: keep.
+__device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t c, int g, int64_t mn, int64_t dt, double thr64)
+{
+    int2 sc = a.statS[c], so = a.statS[o];
+    int64_t dc = var_num(mn, sc), dso = var_num(mn, so);
+    int64_t dio = dso;
+    int2 si = so;
+    if (a.opta) {
+        si = a.statI[o];
+        dio = var_num(mn, si);
+    }
+    if (dc == 0 || dso == 0 || dio == 0)
+        return true;
+    int64_t ntc = a.g_num[g];
+    double ra = rho64(ntc, dt, dc), sa = sin64(ntc, dt, dc);
+    int64_t nco = mn * (int64_t)a.x_b[o] - (int64_t)sc.x * (int64_t)so.x;
+    double rb = rho64(nco, dc, dso), sb = sin64(nco, dc, dso);
+    double rc = 1.0, sc2 = 0.0;
+    if (a.opta) {
+        int64_t noo = mn * (int64_t)a.x_c[o] - (int64_t)so.x * (int64_t)si.x;
+        rc = rho64(noo, dso, dio);
+        sc2 = sin64(noo, dso, dio);
+    }
+    double ub;
+    if (ub_general(ra, sa, rb, sb, rc, sc2, &ub) && ub < thr64)
+        return false;
+    return true;
+}
+
+// Tile of 16 x 4 groups per block.  Phase 1: one lane per group drops the
+// whole group when the interval of its member angles lies beyond the
+// threshold angle from A.  Phase 2: the members of the other groups are
+// tested one per thread (binary32 angles, canonical binary64 inside the guard
+// band); survivors go to an LDS list.  Phase 3: each wave matches survivors
+// on the original image.  The last block reduces all records of the query.
+__global__ __launch_bounds__(256) void k_members(MemArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[8];
+    __shared__ int s_cnt[64], s_pref[65], s_gid[64];
+    __shared__ int64_t s_list[256];
+    __shared__ int s_nsurv, s_total;
+    __shared__ RecPod wrec[4];
+    __shared__ RecPod rred[256];
+    __shared__ unsigned long long ured[8];
+    __shared__ int lastflag;
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (a.qs->degenerate)
+        return;
+    int n4 = (a.n + 3) >> 2;
+    int64_t st, sq;
+    load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int64_t dt = mn * sq - st * st;
+    WaveSplit ws = wave_split(a.m, n4);
+    const float lo = a.qs->thr_lo, hi = a.qs->thr_hi;
+    const double thr64 = a.qs->thr64;
+    int wy = -1, wx = -1;
+    if (a.radius >= 0) {
+        int64_t c0 = a.qs->best0_l;
+        wy = (int)(c0 / a.Lx);
+        wx = (int)(c0 - (c0 / a.Lx) * a.Lx);
+    }
+    unsigned long long n_elim = 0, n_surv = 0;
+
+    if (t < 64) {
+        int gy = blockIdx.y * 4 + (t >> 4), gx = blockIdx.x * 16 + (t & 15);
+        int cnt = 0;
+        if (gy < a.Gy && gx < a.Gx) {
+            int g = gy * a.Gx + gx;
+            int oy, ox, hh, ww, cy, cx;
+            group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
+            float A = a.g_theta[g];
+            GroupSum s = a.gsum[g];
+            bool drop = false;
+            if (!(s.flags & 1)) {
+                float d = 0.0f;
+                bool outside = true;
+                if (A < s.bmin)
+                    d = s.bmin - A;
+                else if (A > s.bmax)
+                    d = A - s.bmax;
+                else
+                    outside = false;
+                if (outside && (d - s.cmax) > hi)
+                    drop = true;
+            }
+            if (drop) {
+                // every member except the centre (plain scan) and window locations
+                for (int yy = oy; yy < oy + hh; yy++)
+                    for (int xx = ox; xx < ox + ww; xx++) {
+                        if (!a.opta && yy == cy && xx == cx)
+                            continue;
+                        if (in_window(yy, xx, wy, wx, a.radius))
+                            continue;
+                        n_elim++;
+                        if (a.dec)
+                            a.dec[(int64_t)yy * a.Lx + xx] = 0;
+                    }
+            } else {
+                cnt = hh * ww;
+            }
+            s_gid[t] = g;
+        }
+        s_cnt[t] = cnt;
+    }
+    if (t == 0)
+        s_nsurv = 0;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int k = 0; k < 64; k++) {
+            s_pref[k] = acc;
+            acc += s_cnt[k];
+        }
+        s_pref[64] = acc;
+        s_total = acc;
+    }
+    __syncthreads();
+    RecPod rec = rec_empty();
+    int total = s_total;
+    for (int base = 0; base < total; base += 256) {
+        int idx = base + t;
+        if (idx < total) {
+            int u = 0;
+            for (int step = 32; step > 0; step >>= 1)
+                if (u + step < 64 && s_pref[u + step] <= idx)
+                    u += step;
+            int g = s_gid[u];
+            int k = idx - s_pref[u];
+            int oy, ox, hh, ww, cy, cx;
+            group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
+            int my = k / ww, mx = k - (k / ww) * ww;
+            int y = oy + my, x = ox + mx;
+            bool skip = (!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius);
+            if (!skip) {
+                int64_t o = (int64_t)y * a.Lx + x;
+                int64_t c = (int64_t)cy * a.Lx + cx;
+                float A = a.g_theta[g];
+                float B = a.theta_b[o];
+                float C = a.opta ? a.theta_c[o] : 0.0f;
+                float e = fabsf(A - B) - C;
+                bool keep;
+                if (e > hi)
+                    keep = false;
+                else if (e < lo)
+                    keep = true;
+                else
+                    keep = keep_canonical(a, o, c, g, mn, dt, thr64);
+                if (keep) {
+                    int pos = atomicAdd(&s_nsurv, 1);
+                    s_list[pos] = o;
+                    n_surv++;
+                } else {
+                    n_elim++;
+                }
+                if (a.dec)
+                    a.dec[o] = keep ? 2 : 0;
+            }
+        }
+        __syncthreads();
+        int ns = s_nsurv;
+        for (int k = wv; k < ns; k += 4) {
+            int64_t o = s_list[k];
+            int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+            int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, ws, lane);
+            if (lane == 0) {
+                int2 so = a.statI[o];
+                int64_t dr = var_num(mn, so);
+                int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
+                rec_offer(rec, rho32(num, dt, dr), o, num, dt, dr);
+            }
+        }
+        __syncthreads();
+        if (t == 0)
+            s_nsurv = 0;
+        __syncthreads();
+    }
+    if (lane == 0)
+        wrec[wv] = rec;
+    unsigned long long ce = block_sum_u64(n_elim, ured);
+    unsigned long long cs = block_sum_u64(n_surv, ured);
+    if (t == 0) {
+        RecPod b = wrec[0];
+        for (int k = 1; k < 4; k++)
+            rec_merge(b, wrec[k]);
+        a.recs[a.rec_off + blockIdx.y * gridDim.x + blockIdx.x] = b;
+        atomicAdd(&a.qs->n_elim, ce);
+        atomicAdd(&a.qs->n_surv, cs);
+    }
+    if (last_block(&a.qs->done[2], &lastflag)) {
+        RecPod f = reduce_records(a.recs, a.final_from, a.rec_off + gridDim.x * gridDim.y, rred);
+        if (t == 0) {
+            a.qs->st = st;
+            a.qs->dt = dt;
+            a.qs->fin = f;
+            a.qs->fin_r32 = rho32(f.num, dt, f.dr);
+        }
+    }
+}
+
+// ============================================================== Alg. 1: auto-correlation with the centre
+
+// One wave per location: sum(r_c' r_o') over the m x n blocks of the
+// location and its group centre, then per mode: exact integers out (debug),
+// retained count (EGS, Eq. 15), or angle and exact sum (scan-2 tables).
+__global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
+{
+    __shared__ unsigned long long ured[8];
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t L = (int64_t)a.Ly * a.Lx;
+    const int64_t mn = (int64_t)a.m * a.n;
+    WaveSplit ws = wave_split(a.m, (a.n + 3) >> 2);
+    unsigned long long cnt = 0;
+    for (int k = 0; k < 16; k++) {
+        int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
+        if (o >= L)
+            break;
+        int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        int64_t c = centre_of(y, x, a.Ly, a.Lx, a.h, a.w);
+        int cy = (int)(c / a.Lx), cx = (int)(c - (c / a.Lx) * a.Lx);
+        int2 sc = a.statJ[c], so = a.statJ[o];
+        int X;
+        if (c == o)
+            X = sc.y;  // sum of squares of the centre block
+        else
+            X = wave_dot_img(a.J, a.pJ, cy, cx, a.J, a.pJ, y, x, a.m, a.n, ws, lane);
+        if (lane != 0)
+            continue;
+        int64_t dc = var_num(mn, sc), dov = var_num(mn, so);
+        int64_t num = mn * (int64_t)X - (int64_t)sc.x * (int64_t)so.x;
+        if (a.mode == AC_DEBUG) {
+            a.num_out[o] = num;
+            a.dc_out[o] = dc;
+            a.do_out[o] = dov;
+        } else if (a.mode == AC_BUILD) {
+            a.theta_b[o] = theta32(num, dc, dov);
+            a.x_b[o] = X;
+        } else if (a.mode == AC_COUNT) {
+            if (c == o)
+                continue;
+            bool ret;
+            if (dc == 0 || dov == 0)
+                ret = true;
+            else {
+                float r = rho32(num, dc, dov);
+                if (r < a.thr_lo)
+                    ret = true;
+                else if (r > a.thr_hi)
+                    ret = false;
+                else
+                    ret = rho64(num, dc, dov) < a.thr;
+            }
+            cnt += ret;
+        } else {  // AC_COUNT_BLUR: every location, angle to the original added
+            int2 si = a.statI[o];
+            int64_t di = var_num(mn, si);
+            bool ret;
+            if (dc == 0 || dov == 0 || di == 0)
+                ret = true;
+            else {
+                float s = theta32(num, dc, dov) + a.theta_c[o];
+                if (s > a.alo_hi && s < a.ahi_lo)
+                    ret = true;
+                else if (s < a.alo_lo || s > a.ahi_hi)
+                    ret = false;
+                else {
+                    int64_t noo = mn * (int64_t)a.x_c[o] - (int64_t)so.x * (int64_t)si.x;
+                    double rb = rho64(num, dc, dov), sb = sin64(num, dc, dov);
+                    double rc = rho64(noo, dov, di), sc2 = sin64(noo, dov, di);
+                    ret = (rb * rc - sb * sc2) < a.thr;
+                }
+            }
+            cnt += ret;
+        }
+    }
+    if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR) {
+        unsigned long long s = block_sum_u64(cnt, ured);
+        if (t == 0 && s)
+            atomicAdd(a.counter, s);
+    }
+}
+
+// Per-group range of member angles B (and largest C) for scan 2's group test.
+__global__ __launch_bounds__(256) void k_gsum(GsumArgs a)
+{
+    int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= a.Gy * a.Gx)
+        return;
+    int oy, ox, hh, ww, cy, cx;
+    group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
+    float bmin = __int_as_float(0x7f800000), bmax = -bmin, cmax = 0.0f;
+    int flags = 0;
+    for (int y = oy; y < oy + hh; y++)
+        for (int x = ox; x < ox + ww; x++) {
+            if (!a.opta && y == cy && x == cx)
+                continue;
+            int64_t o = (int64_t)y * a.Lx + x;
+            float B = a.theta_b[o];
+            float C = a.opta ? a.theta_c[o] : 0.0f;
+            if (isnan(B) || isnan(C)) {
+                flags |= 1;
+                continue;
+            }
+            bmin = fminf(bmin, B);
+            bmax = fmaxf(bmax, B);
+            cmax = fmaxf(cmax, C);
+        }
+    GroupSum s;
+    s.bmin = bmin;
+    s.bmax = bmax;
+    s.cmax = cmax;
+    s.flags = flags;
+    a.gsum[g] = s;
+}
+
+// ============================================================== blur (Eq. 18)
+
+__global__ __launch_bounds__(256) void k_blur_h(const uint8_t *__restrict__ src, int64_t pitch, int p, int q, Taps tp,
+                                                uint32_t *__restrict__ tmp)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)p * q)
+        return;
+    int y = (int)(i / q), x = (int)(i - (i / q) * q);
+    const uint8_t *row = src + (int64_t)y * pitch;
+    uint32_t v = 0;
+    for (int j = -tp.d; j <= tp.d; j++) {
+        int xx = min(max(x + j, 0), q - 1);
+        v += (uint32_t)tp.w[j + tp.d] * row[xx];
+    }
+    tmp[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_blur_v(const uint32_t *__restrict__ tmp, int p, int q, Taps tp,
+                                                uint32_t T, uint8_t *__restrict__ dst, int64_t pitch)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)p * q)
+        return;
+    int y = (int)(i / q), x = (int)(i - (i / q) * q);
+    uint32_t v = 0;
+    for (int j = -tp.d; j <= tp.d; j++) {
+        int yy = min(max(y + j, 0), p - 1);
+        v += (uint32_t)tp.w[j + tp.d] * tmp[(int64_t)yy * q + x];
+    }
+    dst[(int64_t)y * pitch + x] = (uint8_t)((v + T / 2) / T);
+}
+
+// ============================================================== blur correlation and revert (Alg. 3)
+
+// One wave per location: the m x n block of J against the same block of I.
+__global__ __launch_bounds__(256) void k_blurcorr(BcArgs a)
+{
+    __shared__ unsigned long long ured[8];
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t L = (int64_t)a.Ly * a.Lx;
+    const int64_t mn = (int64_t)a.m * a.n;
+    WaveSplit ws = wave_split(a.m, (a.n + 3) >> 2);
+    unsigned long long cnt = 0;
+    for (int k = 0; k < 16; k++) {
+        int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
+        if (o >= L)
+            break;
+        int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        int X = wave_dot_img(a.J, a.pitch, y, x, a.I, a.pitch, y, x, a.m, a.n, ws, lane);
+        if (lane != 0)
+            continue;
+        int2 sj = a.statJ[o], si = a.statI[o];
+        int64_t dj = var_num(mn, sj), di = var_num(mn, si);
+        int64_t num = mn * (int64_t)X - (int64_t)sj.x * (int64_t)si.x;
+        if (a.mode == BC_VIOL) {
+            bool v;
+            if (dj == 0 || di == 0)
+                v = true;
+            else {
+                float r = rho32(num, dj, di);
+                if (r < a.lam_lo)
+                    v = true;
+                else if (r > a.lam_hi)
+                    v = false;
+                else
+                    v = rho64(num, dj, di) < a.lambda;
+            }
+            a.viol[o] = v ? 1 : 0;
+            cnt += v;
+        } else if (a.mode == BC_BUILD) {
+            a.theta_c[o] = theta32(num, dj, di);
+            a.x_c[o] = X;
+        } else {
+            a.num_out[o] = num;
+            a.dj_out[o] = dj;
+            a.di_out[o] = di;
+        }
+    }
+    if (a.mode == BC_VIOL) {
+        unsigned long long s = block_sum_u64(cnt, ured);
+        if (t == 0 && s)
+            atomicAdd(a.counter, s);
+    }
+}
+
+// colmask(y, lx) = 1 when a violating location in column lx covers pixel row y.
+__global__ __launch_bounds__(256) void k_dilate_rows(const uint8_t *__restrict__ viol, int p, int Ly, int Lx, int m,
+                                                     uint8_t *__restrict__ colmask)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)p * Lx)
+        return;
+    int y = (int)(i / Lx), lx = (int)(i - (i / Lx) * Lx);
+    int lo = max(0, y - m + 1), hi = min(Ly - 1, y);
+    uint8_t v = 0;
+    for (int ly = lo; ly <= hi && !v; ly++)
+        v = viol[(int64_t)ly * Lx + lx];
+    colmask[i] = v;
+}
+
+// Copies I into J at every pixel covered by a violating block; counts the
+// pixels that changed.
+__global__ __launch_bounds__(256) void k_revert(const uint8_t *__restrict__ colmask, int p, int q, int Lx, int n,
+                                                const uint8_t *__restrict__ I, uint8_t *__restrict__ J,
+                                                int64_t pitch, unsigned long long *counter)
+{
+    __shared__ unsigned long long ured[8];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned long long changed = 0;
+    if (i < (int64_t)p * q) {
+        int y = (int)(i / q), x = (int)(i - (i / q) * q);
+        int lo = max(0, x - n + 1), hi = min(Lx - 1, x);
+        uint8_t v = 0;
+        for (int lx = lo; lx <= hi && !v; lx++)
+            v = colmask[(int64_t)y * Lx + lx];
+        if (v) {
+            int64_t a = (int64_t)y * pitch + x;
+            uint8_t iv = I[a];
+            if (J[a] != iv) {
+                J[a] = iv;
+                changed = 1;
+            }
+        }
+    }
+    unsigned long long s = block_sum_u64(changed, ured);
+    if (threadIdx.x == 0 && s)
+        atomicAdd(counter, s);
+}
+
+// ============================================================== launch wrappers
+
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(sat, 0, sizeof(uint2) * (size_t)(q + 1), s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sat_rows, dim3(p), dim3(256), 0, s, img, pitch, p, q, sat);
+    hipLaunchKernelGGL(k_sat_cols, dim3(blocks_for(q + 1, 64)), dim3(64, 16), 0, s, sat, p, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stats, dim3(blocks_for((int64_t)Ly * Lx, 256)), dim3(256), 0, s, sat, q, Ly, Lx, m, n,
+                       stat);
+    return hipGetLastError();
+}
+
+static constexpr int kFullR = 8;
+
+int full_record_count(int Ly, int Lx) { return (int)(blocks_for(Lx, 256) * blocks_for(Ly, 4 * kFullR)); }
+
+size_t full_lds_bytes(int m, int n)
+{
+    int n4w = (((n + 3) / 4) + 3) / 4 * 4;
+    size_t tile = (size_t)(4 * kFullR + m - 1) * (64 + n4w) * 4 + (size_t)(m + 2 * kFullR - 2) * n4w * 4;
+    size_t red = 256 * sizeof(RecPod);
+    return tile > red ? tile : red;
+}
+
+hipError_t launch_full(FullArgs a, hipStream_t s)
+{
+    a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
+    dim3 grid(blocks_for(a.Lx, 256), blocks_for(a.Ly, 4 * kFullR));
+    size_t lds = full_lds_bytes(a.m, a.n);
+    if (lds > 160 * 1024)
+        return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_full<kFullR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_full<kFullR>, grid, dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+int centres_record_count(int G) { return (int)blocks_for(G, 32); }
+
+hipError_t launch_centres(ScanArgs a, hipStream_t s)
+{
+    int G = a.Gy * a.Gx;
+    size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
+    hipLaunchKernelGGL(k_centres, dim3(blocks_for(G, 32)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+int window_record_count(int radius)
+{
+    int W = 2 * radius + 1;
+    int nb = (int)blocks_for(W * W, 16);
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_window(WinArgs a, hipStream_t s)
+{
+    size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
+    hipLaunchKernelGGL(k_window, dim3(window_record_count(a.radius)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+int members_record_count(int Gy, int Gx) { return (int)(blocks_for(Gx, 16) * blocks_for(Gy, 4)); }
+
+hipError_t launch_members(MemArgs a, hipStream_t s)
+{
+    size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
+    dim3 grid(blocks_for(a.Gx, 16), blocks_for(a.Gy, 4));
+    hipLaunchKernelGGL(k_members, grid, dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_autocorr(AcArgs a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_autocorr, dim3(blocks_for((int64_t)a.Ly * a.Lx, 64)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gsum(GsumArgs a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gsum, dim3(blocks_for((int64_t)a.Gy * a.Gx, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur(const uint8_t *src, uint8_t *dst, int64_t pitch, int p, int q, const Taps &tp,
+                       uint32_t *tmp, hipStream_t s)
+{
+    uint32_t tsum = 0;
+    for (int j = 0; j <= 2 * tp.d; j++)
+        tsum += (uint32_t)tp.w[j];
+    uint32_t T = tsum * tsum;
+    unsigned nb = blocks_for((int64_t)p * q, 256);
+    hipLaunchKernelGGL(k_blur_h, dim3(nb), dim3(256), 0, s, src, pitch, p, q, tp, tmp);
+    hipLaunchKernelGGL(k_blur_v, dim3(nb), dim3(256), 0, s, (const uint32_t *)tmp, p, q, tp, T, dst, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_blurcorr(BcArgs a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_blurcorr, dim3(blocks_for((int64_t)a.Ly * a.Lx, 64)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, int Ly, int Lx, int m, int n,
+                         const uint8_t *I, uint8_t *J, int64_t pitch, unsigned long long *counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dilate_rows, dim3(blocks_for((int64_t)p * Lx, 256)), dim3(256), 0, s, viol, p, Ly, Lx, m,
+                       colmask);
+    hipLaunchKernelGGL(k_revert, dim3(blocks_for((int64_t)p * q, 256)), dim3(256), 0, s,
+                       (const uint8_t *)colmask, p, q, Lx, n, I, J, pitch, counter);
+    return hipGetLastError();
+}
+
+}  // namespace zts

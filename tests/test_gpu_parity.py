@@ -1,0 +1,268 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Integer sums, locations, counts, group sizes, traces and blurred images must
+be bit-exact; the binary64 rho of the answer is bit-identical (same
+correctly-rounded operations on the same exact integers); binary32 rho is
+within 1e-6 of the oracle's binary64 value.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import aerial_image, cut_template, spectral_image, workload
+
+pytestmark = pytest.mark.gpu
+
+Z = pytest.importorskip("paper_1407_3535_amd")
+
+RHO32_TOL = 1e-6
+KEYS = ("y", "x", "rho", "num", "den_t", "den_r")
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = Z.Searcher(0)
+    yield s
+    s.close()
+
+
+def same_answer(g, o, what=""):
+    for k in KEYS:
+        assert g[k] == o[k], f"{what}: {k} gpu={g[k]} oracle={o[k]}"
+    assert abs(g["rho32"] - o["rho"]) <= RHO32_TOL, what
+
+
+def same_counts(g, o, what=""):
+    for k in ("n_locations", "n_centres", "n_eliminated", "n_survivors", "n_computed", "group_h", "group_w"):
+        assert g[k] == o[k], f"{what}: {k} gpu={g[k]} oracle={o[k]}"
+    assert g["best0"] == o["best0"], what
+
+
+def small_cases():
+    out = []
+    rng = np.random.default_rng(7)
+    shapes = [(40, 50, 7, 9), (64, 64, 16, 16), (33, 70, 5, 13), (90, 47, 12, 10), (300, 280, 32, 32),
+              (130, 129, 21, 3), (50, 50, 50, 50), (17, 300, 4, 65)]
+    for k, (p, q, m, n) in enumerate(shapes):
+        img = spectral_image(p, q, 2.0, 1000 + k)
+        if k % 3 == 1:
+            img[: p // 3, : q // 3] = 211  # flat block: degenerate windows
+        y0, x0 = int(rng.integers(0, p - m + 1)), int(rng.integers(0, q - n + 1))
+        tpl = np.clip(img[y0:y0 + m, x0:x0 + n].astype(int) + rng.integers(-5, 6, (m, n)), 0, 255).astype(np.uint8)
+        if tpl.std() == 0:
+            tpl[0, 0] ^= 1
+        out.append((img, tpl))
+    return out
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("k", range(len(CASES)))
+def test_full_maps_bit_exact(S, k):
+    img, tpl = CASES[k]
+    print(f"case {k} img {img.shape} tpl {tpl.shape}", flush=True)
+    i = S.load(img)
+    num, dr, rho32 = Z.zts_debug_full_map(S.ctx, i, img.shape, tpl)
+    o = O.full_search(img, tpl, maps=True)
+    assert np.array_equal(num, o["num_map"])
+    assert np.array_equal(dr, o["dr_map"])
+    assert np.abs(rho32.astype(np.float64) - o["rho_map"]).max() <= RHO32_TOL
+    g = S.search(i, tpl, "full")
+    same_answer(g, o, f"full case {k}")
+    assert g["n_computed"] == g["n_locations"] == o["rho_map"].size
+    S.unload(i)
+
+
+def test_workload1_full_and_te(S):
+    w = workload(1)
+    img = w["images"][0]
+    tpl, loc, _ = w["templates"][0]
+    i = S.load(img)
+    o = O.full_search(img, tpl)
+    same_answer(S.search(i, tpl, "full"), o, "full")
+    assert (o["y"], o["x"]) == loc
+    ot = O.te_search(img, tpl, 3, 3, decision=True)
+    g, dec = S.search(i, tpl, "te_fixed", decision=True, group_h=3, group_w=3)
+    same_answer(g, o, "te 3x3")
+    same_counts(g, ot, "te 3x3")
+    assert np.array_equal(dec, ot["decision"])
+    S.unload(i)
+
+
+@pytest.mark.parametrize("k", range(len(CASES)))
+@pytest.mark.parametrize("hw", [(3, 3), (4, 2), (5, 5)])
+def test_autocorr_bit_exact(S, k, hw):
+    img, tpl = CASES[k]
+    m, n = tpl.shape
+    h, w = hw
+    i = S.load(img)
+    g = Z.zts_debug_autocorr(S.ctx, i, img.shape, m, n, h, w)
+    o = O.autocorr(img, m, n, h, w)
+    for a, b in zip(g, o):
+        assert np.array_equal(a, b)
+    S.unload(i)
+
+
+@pytest.mark.parametrize("taps", ["paper", 0.5, 0.5 * math.sqrt(3), 1.5, 0.5 * math.sqrt(11)])
+def test_blur_bit_exact(S, taps):
+    img = aerial_image(97, 131, 5)
+    t = O.PAPER_W if taps == "paper" else O.gauss_taps(taps)[0]
+    assert np.array_equal(Z.zts_debug_blur(S.ctx, img, t), O.blur(img, t))
+
+
+@pytest.mark.parametrize("k", range(len(CASES)))
+@pytest.mark.parametrize("hw,radius", [((3, 3), 0), ((4, 6), 0), ((5, 5), 2), ((1, 1), 0), ((2, 3), 1)])
+def test_te_fixed_parity(S, k, hw, radius):
+    img, tpl = CASES[k]
+    h, w = hw
+    print(f"case {k} {img.shape} {tpl.shape} hw={hw} r={radius}", flush=True)
+    i = S.load(img)
+    full = O.full_search(img, tpl)
+    ot = O.te_search(img, tpl, h, w, decision=True, radius=radius)
+    g, dec = S.search(i, tpl, "te_fixed", decision=True, group_h=h, group_w=w, refine_radius=radius)
+    same_answer(g, full, "te vs full")
+    same_counts(g, ot, "te vs oracle te")
+    assert np.array_equal(dec, ot["decision"])
+    S.unload(i)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_egs_parity(S, seed):
+    img = aerial_image(160, 200, 300 + seed, beta=(1.8, 2.6))
+    m = n = 16
+    i = S.load(img)
+    info = S.prepare(i, m, n, "egs")
+    oe = O.egs(img, m, n)
+    assert (info["h"], info["w"], info["cost"]) == (oe["h"], oe["w"], oe["cost"])
+    assert info["egs"] == oe["trace"]
+    for k in range(3):
+        tpl, _ = cut_template(img, m, n, 40 + k, 6.0, affine=True)
+        for radius in (0, 2):
+            g, dec = S.search(i, tpl, "egs", decision=True, refine_radius=radius)
+            ot = O.te_search(img, tpl, oe["h"], oe["w"], decision=True, radius=radius)
+            same_answer(g, ot, "egs")
+            same_counts(g, ot, "egs")
+            assert np.array_equal(dec, ot["decision"])
+    S.unload(i)
+
+
+@pytest.mark.parametrize("seed,blur_kind", [(0, 1), (1, 1), (2, 0)])
+def test_opta_parity(S, seed, blur_kind):
+    img = aerial_image(140, 150, 500 + seed, beta=2.8 if seed else 2.2)
+    m = n = 12
+    i = S.load(img)
+    info = S.prepare(i, m, n, "opta", blur_kind=blur_kind, max_iters=4)
+    oo = O.opta(img, m, n, blur_kind=blur_kind, max_iters=4)
+    assert (info["h"], info["w"], info["cost"], info["radius"]) == (oo["h"], oo["w"], oo["cost"], oo["radius"])
+    gt = [{k: s[k] for k in ("k", "d", "passes", "reverted", "h", "w", "cost", "accepted")} for s in info["opta"]]
+    ot = [{k: s[k] for k in ("k", "d", "passes", "reverted", "h", "w", "cost", "accepted")} for s in oo["trace"]]
+    assert gt == ot
+    J = S.prep_image(i, m, n)
+    assert np.array_equal(J, oo["image"])
+    for k in range(3):
+        tpl, _ = cut_template(img, m, n, 70 + k, 8.0, affine=True)
+        for extra in (0, 3):
+            radius = max(oo["radius"], extra)
+            g, dec = S.search(i, tpl, "opta", decision=True, blur_kind=blur_kind, max_iters=4,
+                              refine_radius=extra)
+            os_ = O.opta_search(img, oo["image"], tpl, oo["h"], oo["w"], radius, decision=True)
+            full = O.full_search(img, tpl)
+            same_answer(g, full, "opta vs full")
+            same_counts(g, os_, "opta vs oracle opta")
+            odec = os_["decision"].copy()
+            odec[odec == 1] = 3
+            assert np.array_equal(dec, odec)
+    S.unload(i)
+
+
+def test_ties_go_to_smallest_index(S):
+    rng = np.random.default_rng(3)
+    tile = rng.integers(0, 256, (6, 7), dtype=np.uint8)
+    img = np.tile(tile, (12, 12))[:70, :80].copy()
+    tpl = img[12:24, 14:28].copy()
+    o = O.full_search(img, tpl, maps=True)
+    assert (o["rho_map"] == o["rho"]).sum() > 1
+    i = S.load(img)
+    for mode, kw in [("full", {}), ("te_fixed", dict(group_h=3, group_w=3)), ("egs", {}),
+                     ("te_fixed", dict(group_h=5, group_w=4, refine_radius=2))]:
+        same_answer(S.search(i, tpl, mode, **kw), o, mode)
+    S.unload(i)
+
+
+def test_errors(S):
+    img = spectral_image(40, 40, 2.0, 1)
+    i = S.load(img)
+    with pytest.raises(Z.ZtsError) as e:
+        S.search(i, np.full((5, 5), 7, np.uint8), "full")
+    assert e.value.code == -3
+    with pytest.raises(Z.ZtsError) as e:
+        S.search(i, np.full((5, 5), 7, np.uint8), "egs")
+    assert e.value.code == -3
+    with pytest.raises(Z.ZtsError) as e:
+        S.search(i, np.zeros((41, 5), np.uint8), "full")
+    assert e.value.code == -2
+    with pytest.raises(Z.ZtsError) as e:
+        S.search(i + 99, img[:5, :5], "full")
+    assert e.value.code == -4
+    S.unload(i)
+    with pytest.raises(Z.ZtsError) as e:
+        S.search(i, img[:5, :5], "full")
+    assert e.value.code == -4
+    big = spectral_image(300, 300, 2.0, 2)
+    j = S.load(big)
+    with pytest.raises(Z.ZtsError) as e:
+        S.search(j, big[:129, :129], "full")
+    assert e.value.code == -2
+    S.unload(j)
+
+
+def test_device_entry_points_match_host_ones(S):
+    import torch
+    img = aerial_image(200, 220, 8)
+    tpl, _ = cut_template(img, 24, 24, 9, 5.0)
+    i = S.load(img)
+    j = S.load_device(torch.from_numpy(img).cuda())
+    t = torch.from_numpy(tpl).cuda()
+    a = S.search(i, tpl, "egs")
+    b = Z.zts_search_device(S.ctx, j, t, "egs")
+    for k in KEYS + ("n_eliminated", "n_survivors", "n_computed"):
+        assert a[k] == b[k]
+    S.unload(i)
+    S.unload(j)
+
+
+def test_workload2_full_size_sampled(S):
+    """The named 2048x2048 / 64x64 workload at full size, as the benchmark runs it."""
+    w = workload(2)
+    img = w["images"][0]
+    tpl, loc, _ = w["templates"][0]
+    i = S.load(img)
+    o = O.full_search(img, tpl)
+    assert (o["y"], o["x"]) == loc
+    same_answer(S.search(i, tpl, "full"), o, "full")
+    oe = O.egs(img, 64, 64)
+    info = S.prepare(i, 64, 64, "egs")
+    assert info["egs"] == oe["trace"]
+    for radius in (0, 2):
+        ot = O.te_search(img, tpl, oe["h"], oe["w"], radius=radius)
+        g = S.search(i, tpl, "egs", refine_radius=radius)
+        same_answer(g, o, "egs")
+        same_counts(g, ot, "egs")
+    # sampled exact sums at full size
+    num, dr, rho32 = Z.zts_debug_full_map(S.ctx, i, img.shape, tpl)
+    rng = np.random.default_rng(11)
+    Ly, Lx = num.shape
+    for _ in range(200):
+        y, x = int(rng.integers(0, Ly)), int(rng.integers(0, Lx))
+        blk = img[y:y + 64, x:x + 64]
+        sub = O.full_search(blk, tpl)
+        assert (num[y, x], dr[y, x]) == (sub["num"], sub["den_r"])
+        assert abs(rho32[y, x] - sub["rho"]) <= RHO32_TOL
+    S.unload(i)
