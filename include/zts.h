@@ -115,6 +115,10 @@ typedef struct {
     int32_t best0_y, best0_x;/* best group centre of scan 1 */
     float device_ms;         /* device time of the search (HIP events) */
     zts_status status;
+    float phase_ms[4];       /* device time per kernel, HIP events on the library's stream:
+                                ZTS_FULL: [0] dense kernel; other modes: [0] scan 1 (centres),
+                                [1] refinement window, [2] scan 2 (members and survivors) */
+    int32_t pad1;
 } zts_result;
 
 typedef struct {

@@ -63,10 +63,13 @@ class Result(C.Structure):
                 ("n_locations", C.c_int64), ("n_centres", C.c_int64), ("n_eliminated", C.c_int64),
                 ("n_survivors", C.c_int64), ("n_computed", C.c_int64), ("group_h", C.c_int32),
                 ("group_w", C.c_int32), ("best0", C.c_double), ("best0_y", C.c_int32), ("best0_x", C.c_int32),
-                ("device_ms", C.c_float), ("status", C.c_int32)]
+                ("device_ms", C.c_float), ("status", C.c_int32), ("phase_ms", C.c_float * 4),
+                ("pad1", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
 
 
 class EgsStep(C.Structure):

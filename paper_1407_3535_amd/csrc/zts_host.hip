@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -28,8 +30,11 @@ struct ZtsError {
 
 inline void hip_check(hipError_t e)
 {
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        if (std::getenv("ZTS_DEBUG"))
+            std::fprintf(stderr, "zts: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
         throw ZtsError{ZTS_E_DEVICE};
+    }
 }
 
 // ------------------------------------------------------------------ device buffers
@@ -78,6 +83,7 @@ struct Ctx {
     uint64_t used = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evp[4] = {nullptr, nullptr, nullptr, nullptr};
     int next_id = 1;
     std::map<int, std::unique_ptr<Image>> images;
     // per-query scratch, grown on demand
@@ -582,8 +588,8 @@ Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_para
     if (mode == ZTS_TE_FIXED) {
         if (pr.group_h < 1 || pr.group_w < 1)
             throw ZtsError{ZTS_E_ARG};
-        P->h = std::min(pr.group_h, Ly);
-        P->w = std::min(pr.group_w, Lx);
+        P->h = pr.group_h;
+        P->w = pr.group_w;
         build_tables(c, *P, SI, Ly, Lx);
     } else if (mode == ZTS_EGS) {
         int nt;
@@ -666,6 +672,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         a.rho_map = rho_map;
         a.dec = d_dec;
         hip_check(launch_full(a, c->stream));
+        hip_check(hipEventRecord(c->evp[0], c->stream));
     } else {
         bool opta = mode == ZTS_OPTA;
         G = P->Gy * P->Gx;
@@ -704,6 +711,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         s.delta = pr.margin;
         s.set_thr = radius < 0;
         hip_check(launch_centres(s, c->stream));
+        hip_check(hipEventRecord(c->evp[0], c->stream));
         if (radius >= 0) {
             WinArgs wa;
             std::memset(&wa, 0, sizeof wa);
@@ -728,6 +736,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
             wa.delta = pr.margin;
             hip_check(launch_window(wa, c->stream));
         }
+        hip_check(hipEventRecord(c->evp[1], c->stream));
         MemArgs ma;
         std::memset(&ma, 0, sizeof ma);
         ma.I = im->img.as<uint8_t>();
@@ -759,6 +768,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         ma.qs = qs;
         ma.dec = d_dec;
         hip_check(launch_members(ma, c->stream));
+        hip_check(hipEventRecord(c->evp[2], c->stream));
     }
     hip_check(hipEventRecord(c->ev1, c->stream));
     hip_check(hipMemcpyAsync(c->h_qs, c->qs.ptr, sizeof(QState), hipMemcpyDeviceToHost, c->stream));
@@ -800,6 +810,13 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
     float ms = 0.0f;
     hip_check(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     r.device_ms = ms;
+    if (mode == ZTS_FULL) {
+        hip_check(hipEventElapsedTime(&r.phase_ms[0], c->ev0, c->evp[0]));
+    } else {
+        hip_check(hipEventElapsedTime(&r.phase_ms[0], c->ev0, c->evp[0]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[1], c->evp[0], c->evp[1]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[2], c->evp[1], c->evp[2]));
+    }
     r.status = ZTS_OK;
     *out = r;
 }
@@ -924,6 +941,8 @@ zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
     }
     if (hipSetDevice(c.device) != hipSuccess || hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&c.ev0) != hipSuccess || hipEventCreate(&c.ev1) != hipSuccess ||
+        hipEventCreate(&c.evp[0]) != hipSuccess || hipEventCreate(&c.evp[1]) != hipSuccess ||
+        hipEventCreate(&c.evp[2]) != hipSuccess || hipEventCreate(&c.evp[3]) != hipSuccess ||
         hipHostMalloc((void **)&c.h_qs, sizeof(QState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c.h_cnt, 64, hipHostMallocDefault) != hipSuccess) {
         delete z;
@@ -951,6 +970,8 @@ void zts_destroy(zts_ctx *z)
         if (c.h_cnt) (void)hipHostFree(c.h_cnt);
         if (c.ev0) (void)hipEventDestroy(c.ev0);
         if (c.ev1) (void)hipEventDestroy(c.ev1);
+        for (int k = 0; k < 4; k++)
+            if (c.evp[k]) (void)hipEventDestroy(c.evp[k]);
         if (c.stream) (void)hipStreamDestroy(c.stream);
     }
     delete z;

@@ -998,13 +998,13 @@ hipError_t launch_full(FullArgs a, hipStream_t s)
     size_t lds = full_lds_bytes(a.m, a.n);
     if (lds > 160 * 1024)
         return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static size_t attr_bytes = 64 * 1024;
+    if (lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k_full<kFullR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
+                                           (int)lds);
         if (e != hipSuccess)
             return e;
-        attr_set = true;
+        attr_bytes = lds;
     }
     hipLaunchKernelGGL(k_full<kFullR>, grid, dim3(256), lds, s, a);
     return hipGetLastError();
