@@ -75,18 +75,18 @@ def main():
     tdev = torch.from_numpy(tpl).cuda()
     torch.cuda.synchronize()
 
-    def query(mode, refine=0):
-        return Z.zts_search_device(S.ctx, i, tdev, mode, Z.zts_params_default(refine_radius=refine))
+    def query(mode, refine=0, **kw):
+        return Z.zts_search_device(S.ctx, i, tdev, mode, Z.zts_params_default(refine_radius=refine, **kw))
 
-    def run(mode, refine, steps, warmup):
+    def run(mode, refine, steps, warmup, **kw):
         for _ in range(warmup):
-            query(mode, refine)
+            query(mode, refine, **kw)
         torch.cuda.synchronize()
         lat, phases = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
             a = time.perf_counter()
-            r = query(mode, refine)
+            r = query(mode, refine, **kw)
             lat.append((time.perf_counter() - a) * 1e3)
             phases.append(r["phase_ms"])
         torch.cuda.synchronize()
@@ -98,9 +98,10 @@ def main():
 
     modes = {}
     if not args.no_modes:
-        for name, mode, ref in [("full", "full", 0), ("egs", "egs", 0), ("egs_refine2", "egs", 2),
-                                ("opta", "opta", 0), ("opta_refine2", "opta", 2)]:
-            rr, mms, ll, pp = run(mode, ref, 20, 3)
+        for name, mode, ref, kw in [("full", "full", 0, {}), ("egs", "egs", 0, {}), ("egs_refine2", "egs", 2, {}),
+                                    ("opta", "opta", 0, {}), ("opta_refine2", "opta", 2, {}),
+                                    ("egs_rho_th0.95_refine2", "egs", 2, {"rho_th": 0.95})]:
+            rr, mms, ll, pp = run(mode, ref, 20, 3, **kw)
             modes[name] = {"ms_per_query": round(mms, 4), "locations_per_s": L / (mms / 1e3),
                            "device_ms": round(rr["device_ms"], 4), "phase_ms": [round(x, 4) for x in pp[:3]],
                            "n_computed": rr["n_computed"], "n_centres": rr["n_centres"],

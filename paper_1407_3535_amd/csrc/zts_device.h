@@ -159,49 +159,31 @@ __device__ __forceinline__ int64_t var_num(int64_t mn, int2 st)
 
 // ---------------------------------------------------------------- window dot products
 
-// Work split of an m-row by n4-word window over the 64 lanes of a wave:
-// lanes_per_row lanes share a row, rows_per_pass rows are covered at once.
-struct WaveSplit {
-    int lpr, rpp, wps;
-};
+// Window dot products, one wave per location.  Lane -> (row in pass, word):
+// ceil(n/4) consecutive lanes read consecutive words of one image row
+// (coalesced) and the matching template words (consecutive LDS banks);
+// 64 / ceil(n/4) rows are covered per pass.  The byte misalignment of the
+// block is the same for every lane and row (pitch is a multiple of 4), so
+// one v_alignbyte per word realigns it.
 
-__device__ __forceinline__ WaveSplit wave_split(int m, int n4)
-{
-    int lpr = kWave / m;
-    if (lpr < 1)
-        lpr = 1;
-    if (lpr > n4)
-        lpr = n4;
-    WaveSplit s;
-    s.lpr = lpr;
-    s.rpp = kWave / lpr;
-    s.wps = (n4 + lpr - 1) / lpr;
-    return s;
-}
-
-// sum over the m x n block at (y, x) of t' * r', with the template held in
-// LDS as flipped int8 words (n4 words per row, zero beyond column n).  The
-// image row segment is read as aligned dwords and realigned with
-// v_alignbyte.  Every lane returns the full sum.
+// sum over the m x n block at (y, x) of t' * r'; the template is in LDS as
+// flipped int8 words, n4 = ceil(n/4) per row, zero past column n.  Every
+// lane returns the full sum.
 __device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, int n4, const uint8_t *__restrict__ img,
-                                            int64_t pitch, int y, int x, int m, WaveSplit ws, int lane)
+                                            int64_t pitch, int y, int x, int m, int lane)
 {
+    int rp = kWave / n4;
+    int r0 = lane / n4, j = lane - r0 * n4;
     int acc = 0;
-    int r = lane / ws.lpr, seg = lane - r * ws.lpr;
-    int j0 = seg * ws.wps;
-    int j1 = min(n4, j0 + ws.wps);
-    if (r < ws.rpp && j0 < j1) {
-        for (int i = r; i < m; i += ws.rpp) {
-            int64_t a = (int64_t)(y + i) * pitch + x + 4 * j0;
-            const uint32_t *p = (const uint32_t *)(img + (a & ~(int64_t)3));
-            uint32_t sh = (uint32_t)(a & 3);
-            const uint32_t *t = tplw + i * n4;
-            uint32_t lo = p[0];
-            for (int j = j0; j < j1; j++) {
-                uint32_t hi = p[j - j0 + 1];
-                acc = dot4(flip4(bytes_at(hi, lo, sh)), t[j], acc);
-                lo = hi;
-            }
+    if (r0 < rp) {
+        int64_t a0 = (int64_t)y * pitch + x + 4 * j;
+        uint32_t sh = (uint32_t)(x & 3);
+        const uint32_t *base = (const uint32_t *)(img + (a0 & ~(int64_t)3));
+        int64_t pw = pitch >> 2;
+#pragma unroll 4
+        for (int i = r0; i < m; i += rp) {
+            const uint32_t *pr = base + (int64_t)i * pw;
+            acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), tplw[i * n4 + j], acc);
         }
     }
     return wave_sum(acc);
@@ -211,32 +193,27 @@ __device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, i
 // (yb, xb); bytes past column n of the last word are masked off.
 __device__ __forceinline__ int wave_dot_img(const uint8_t *__restrict__ A, int64_t pa, int ya, int xa,
                                             const uint8_t *__restrict__ B, int64_t pb, int yb, int xb, int m, int n,
-                                            WaveSplit ws, int lane)
+                                            int lane)
 {
     int n4 = (n + 3) >> 2;
-    uint32_t last_mask = (n & 3) ? ((1u << (8 * (n & 3))) - 1u) : 0xffffffffu;
+    int rp = kWave / n4;
+    int r0 = lane / n4, j = lane - r0 * n4;
+    uint32_t mask = (j == n4 - 1 && (n & 3)) ? ((1u << (8 * (n & 3))) - 1u) : 0xffffffffu;
     int acc = 0;
-    int r = lane / ws.lpr, seg = lane - r * ws.lpr;
-    int j0 = seg * ws.wps;
-    int j1 = min(n4, j0 + ws.wps);
-    if (r < ws.rpp && j0 < j1) {
-        for (int i = r; i < m; i += ws.rpp) {
-            int64_t a = (int64_t)(ya + i) * pa + xa + 4 * j0;
-            int64_t b = (int64_t)(yb + i) * pb + xb + 4 * j0;
-            const uint32_t *pA = (const uint32_t *)(A + (a & ~(int64_t)3));
-            const uint32_t *pB = (const uint32_t *)(B + (b & ~(int64_t)3));
-            uint32_t sa = (uint32_t)(a & 3), sb = (uint32_t)(b & 3);
-            uint32_t loA = pA[0], loB = pB[0];
-            for (int j = j0; j < j1; j++) {
-                uint32_t hiA = pA[j - j0 + 1], hiB = pB[j - j0 + 1];
-                uint32_t va = flip4(bytes_at(hiA, loA, sa));
-                uint32_t vb = flip4(bytes_at(hiB, loB, sb));
-                if (j == n4 - 1)
-                    va &= last_mask;
-                acc = dot4(va, vb, acc);
-                loA = hiA;
-                loB = hiB;
-            }
+    if (r0 < rp) {
+        int64_t a0 = (int64_t)ya * pa + xa + 4 * j;
+        int64_t b0 = (int64_t)yb * pb + xb + 4 * j;
+        uint32_t sa = (uint32_t)(xa & 3), sb = (uint32_t)(xb & 3);
+        const uint32_t *ba = (const uint32_t *)(A + (a0 & ~(int64_t)3));
+        const uint32_t *bb = (const uint32_t *)(B + (b0 & ~(int64_t)3));
+        int64_t pwa = pa >> 2, pwb = pb >> 2;
+#pragma unroll 4
+        for (int i = r0; i < m; i += rp) {
+            const uint32_t *pA = ba + (int64_t)i * pwa;
+            const uint32_t *pB = bb + (int64_t)i * pwb;
+            uint32_t va = flip4(bytes_at(pA[1], pA[0], sa)) & mask;
+            uint32_t vb = flip4(bytes_at(pB[1], pB[0], sb));
+            acc = dot4(va, vb, acc);
         }
     }
     return wave_sum(acc);

@@ -64,7 +64,8 @@ struct Prepared {
     zts_params params;
     DBuf theta_b, x_b, gsum;       // member vs centre on the searched image
     DBuf J, Jsat, Jstat;           // OptA: conditioned image and its statistics
-    DBuf theta_c, x_c;             // OptA: conditioned block vs original block
+    DBuf theta_c, x_c;             // OptA: conditioned block vs original block (row-major)
+    DBuf theta_cg, x_cg;           // the same in the group-major layout of (h, w)
     zts_prep_info info;
 };
 
@@ -350,9 +351,17 @@ void run_egs(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, const zts_
 // Angle tables of every location to its group centre on S, and group summaries.
 void build_tables(Ctx *c, Prepared &P, const Searched &S, int Ly, int Lx)
 {
-    size_t L = (size_t)Ly * Lx;
-    dalloc(c, P.theta_b, sizeof(float) * L);
-    dalloc(c, P.x_b, sizeof(int32_t) * L);
+    P.Gy = (Ly + P.h - 1) / P.h;
+    P.Gx = (Lx + P.w - 1) / P.w;
+    size_t slots = (size_t)P.Gy * P.Gx * P.h * P.w;  // group-major: slot g*h*w + my*w + mx
+    dalloc(c, P.theta_b, sizeof(float) * slots);
+    dalloc(c, P.x_b, sizeof(int32_t) * slots);
+    if (P.mode == ZTS_OPTA) {
+        dalloc(c, P.theta_cg, sizeof(float) * slots);
+        dalloc(c, P.x_cg, sizeof(int32_t) * slots);
+        hip_check(launch_regroup(P.theta_c.ptr, P.theta_cg.ptr, Ly, Lx, P.h, P.w, c->stream));
+        hip_check(launch_regroup(P.x_c.ptr, P.x_cg.ptr, Ly, Lx, P.h, P.w, c->stream));
+    }
     AcArgs a;
     std::memset(&a, 0, sizeof a);
     a.J = S.px;
@@ -368,12 +377,10 @@ void build_tables(Ctx *c, Prepared &P, const Searched &S, int Ly, int Lx)
     a.theta_b = P.theta_b.as<float>();
     a.x_b = P.x_b.as<int32_t>();
     hip_check(launch_autocorr(a, c->stream));
-    P.Gy = (Ly + P.h - 1) / P.h;
-    P.Gx = (Lx + P.w - 1) / P.w;
     dalloc(c, P.gsum, sizeof(GroupSum) * (size_t)P.Gy * P.Gx);
     GsumArgs g;
     g.theta_b = P.theta_b.as<float>();
-    g.theta_c = P.theta_c.ptr ? P.theta_c.as<float>() : nullptr;
+    g.theta_c = P.mode == ZTS_OPTA ? P.theta_cg.as<float>() : nullptr;
     g.Ly = Ly;
     g.Lx = Lx;
     g.h = P.h;
@@ -672,11 +679,13 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         a.rho_map = rho_map;
         a.dec = d_dec;
         hip_check(launch_full(a, c->stream));
+        hip_check(launch_reduce(c->recs.as<RecPod>(), 0, full_record_count(Ly, Lx), qs, RD_FINAL, 0, pr.margin,
+                                c->stream));
         hip_check(hipEventRecord(c->evp[0], c->stream));
     } else {
         bool opta = mode == ZTS_OPTA;
         G = P->Gy * P->Gx;
-        int n1 = centres_record_count(G);
+        int n1 = centres_record_count(P->Gy, P->Gx, n);
         if (opta)
             radius = std::max(P->radius, std::max(pr.refine_radius, 0));
         else
@@ -711,6 +720,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         s.delta = pr.margin;
         s.set_thr = radius < 0;
         hip_check(launch_centres(s, c->stream));
+        hip_check(launch_reduce(c->recs.as<RecPod>(), 0, n1, qs, RD_BEST0, radius < 0, pr.margin, c->stream));
         hip_check(hipEventRecord(c->evp[0], c->stream));
         if (radius >= 0) {
             WinArgs wa;
@@ -735,6 +745,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
             wa.dec = d_dec;
             wa.delta = pr.margin;
             hip_check(launch_window(wa, c->stream));
+            hip_check(launch_reduce(c->recs.as<RecPod>(), n1, n1 + n2, qs, RD_WINDOW, !opta, pr.margin, c->stream));
         }
         hip_check(hipEventRecord(c->evp[1], c->stream));
         MemArgs ma;
@@ -758,8 +769,8 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         ma.gsum = P->gsum.as<GroupSum>();
         ma.theta_b = P->theta_b.as<float>();
         ma.x_b = P->x_b.as<int32_t>();
-        ma.theta_c = opta ? P->theta_c.as<float>() : nullptr;
-        ma.x_c = opta ? P->x_c.as<int32_t>() : nullptr;
+        ma.theta_c = opta ? P->theta_cg.as<float>() : nullptr;
+        ma.x_c = opta ? P->x_cg.as<int32_t>() : nullptr;
         ma.opta = opta;
         ma.radius = radius;
         ma.recs = c->recs.as<RecPod>();
@@ -768,6 +779,8 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         ma.qs = qs;
         ma.dec = d_dec;
         hip_check(launch_members(ma, c->stream));
+        hip_check(launch_reduce(c->recs.as<RecPod>(), opta ? n1 : 0, n1 + n2 + n3, qs, RD_FINAL, 0, pr.margin,
+                                c->stream));
         hip_check(hipEventRecord(c->evp[2], c->stream));
     }
     hip_check(hipEventRecord(c->ev1, c->stream));
@@ -865,6 +878,8 @@ zts_status load_common(Ctx *c, const void *src, int rows, int cols, int64_t stri
 {
     if (!src || !id || rows < 1 || cols < 1 || stride < cols)
         return ZTS_E_ARG;
+    if (rows > 32767 || cols > 32767)  // group geometry is packed in 16-bit fields
+        return ZTS_E_SIZE;
     return guarded(c, [&] {
         auto im = std::make_unique<Image>();
         im->rows = rows;

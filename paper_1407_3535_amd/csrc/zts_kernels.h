@@ -33,7 +33,7 @@ struct ScanArgs {
     const int2 *stat;
     const uint8_t *tpl;
     int64_t ts;
-    int m, n, Ly, Lx, h, w, Gy, Gx;
+    int m, n, n4w, Ly, Lx, h, w, Gy, Gx;
     int64_t *g_num;
     float *g_theta;
     RecPod *recs;
@@ -73,9 +73,9 @@ struct MemArgs {
     const int64_t *g_num;
     const float *g_theta;
     const GroupSum *gsum;
-    const float *theta_b;   // member vs its centre on the searched image
+    const float *theta_b;   // member vs its centre on the searched image (group-major)
     const int32_t *x_b;
-    const float *theta_c;   // searched-image block vs original block (opta)
+    const float *theta_c;   // searched-image block vs original block (opta, group-major)
     const int32_t *x_c;
     int opta;
     int radius;  // window radius, -1 when there is none
@@ -134,6 +134,8 @@ struct BcArgs {
     int64_t *num_out, *dj_out, *di_out;
 };
 
+enum { RD_BEST0 = 0, RD_WINDOW = 1, RD_FINAL = 2 };
+hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, int stage, int flag, double delta, hipStream_t s);
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);
 hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s);
 
@@ -141,12 +143,13 @@ int full_record_count(int Ly, int Lx);
 size_t full_lds_bytes(int m, int n);
 hipError_t launch_full(FullArgs a, hipStream_t s);
 
-int centres_record_count(int G);
+int centres_record_count(int Gy, int Gx, int n);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);
 int members_record_count(int Gy, int Gx);
 hipError_t launch_members(MemArgs a, hipStream_t s);
+hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int w, hipStream_t s);
 
 hipError_t launch_autocorr(AcArgs a, hipStream_t s);
 hipError_t launch_gsum(GsumArgs a, hipStream_t s);

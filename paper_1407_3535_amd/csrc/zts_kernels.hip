@@ -95,27 +95,6 @@ __device__ RecPod reduce_records(const RecPod *recs, int lo, int hi, RecPod *red
     return block_rec(r, red);
 }
 
-// Last-block ticket: true in exactly one block, after every block's writes
-// before this call are visible to it.
-__device__ bool last_block(unsigned int *ticket, int *flag)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int total = gridDim.x * gridDim.y * gridDim.z;
-        unsigned int prev = atomicAdd(ticket, 1u);
-        *flag = (prev == total - 1);
-    }
-    __syncthreads();
-    bool last = *flag != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0)
-            *ticket = 0;
-    }
-    return last;
-}
-
 __device__ void set_threshold(QState *qs, double best, int64_t best_l, double delta)
 {
     qs->best = best;
@@ -260,7 +239,6 @@ __global__ __launch_bounds__(256) void k_full(FullArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
-    __shared__ int lastflag;
     const int n4w = a.n4w;
     const int TR = 4 * R + a.m - 1;
     const int TWW = 64 + n4w;
@@ -353,53 +331,132 @@ __global__ __launch_bounds__(256) void k_full(FullArgs a)
     RecPod *rred = (RecPod *)smem;
     RecPod b = block_rec(rec, rred);
     int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (t == 0)
+    if (t == 0) {
         a.recs[bid] = b;
-    if (last_block(&a.qs->done[0], &lastflag)) {
-        RecPod f = reduce_records(a.recs, 0, gridDim.x * gridDim.y, rred);
-        if (t == 0) {
+        if (bid == 0) {
             a.qs->st = st;
             a.qs->dt = dt;
-            a.qs->fin = f;
-            a.qs->fin_r32 = rho32(f.num, dt, f.dr);
         }
     }
 }
 
 // ============================================================== scan 1: group centres
 
-// Each wave matches the template against 8 group centres of the searched
-// image.  Per group it keeps the exact N_tc and the binary32 angle A.
+// Strided tile: lane = one centre column, the wave holds R centre rows in
+// registers and sweeps the image rows their windows cover once.  For each
+// image row and 16-byte template chunk a lane loads 5 words at its centre's
+// column, realigns them (v_alignbyte) and issues 4 v_dot4 for every centre
+// row whose window contains that image row.  The waves of a block split the
+// template chunks and sum their partial products through LDS.  Per group it
+// keeps the exact N_tc and the binary32 angle A.
+template <int R>
 __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
-    __shared__ RecPod wrec[4];
     __shared__ RecPod rred[256];
-    __shared__ int lastflag;
+    const int n4w = a.n4w;
+    const int nw = blockDim.x >> 6;
+    uint32_t *tpl = smem;
+    int *xs = (int *)(smem + a.m * n4w);  // [nw][R][64]
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    int n4 = (a.n + 3) >> 2;
     int64_t st, sq;
-    load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
+    load_template(a.tpl, a.ts, a.m, a.n, n4w, 0, a.m, tpl, red, &st, &sq);
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t dt = mn * sq - st * st;
     if (dt == 0) {
-        if (blockIdx.x == 0 && t == 0)
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
             a.qs->degenerate = 1;
         return;
     }
-    WaveSplit ws = wave_split(a.m, n4);
+    const int gx = blockIdx.x * 64 + lane;
+    const bool colok = gx < a.Gx;
+    int cx = 0;
+    if (colok) {
+        int ox = gx * a.w;
+        int ww = min(a.w, a.Lx - ox);
+        cx = ox + (ww - 1) / 2;
+    }
+    const uint32_t sh = (uint32_t)(cx & 3);
+    const int64_t pw = a.pitch >> 2;
+    const uint32_t *colbase = (const uint32_t *)a.img + (cx >> 2);
+    const int gy0 = blockIdx.y * R;
+    const int nvalid = min(R, a.Gy - gy0);
+    int cy[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int gy = min(gy0 + r, a.Gy - 1);
+        int oy = gy * a.h;
+        int hh = min(a.h, a.Ly - oy);
+        cy[r] = oy + (hh - 1) / 2;
+    }
+    int acc[R];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        acc[r] = 0;
+    const int nch = n4w >> 2;
+    int ylo = cy[0], yhi = cy[0] + a.m;
+#pragma unroll
+    for (int r = 1; r < R; r++)
+        if (r < nvalid)
+            yhi = cy[r] + a.m;
+    for (int c = wv; c < nch; c += nw) {
+        // four image rows of words are loaded at once, then used
+        const uint32_t *pc = colbase + (int64_t)ylo * pw + 4 * c;
+        for (int yy = ylo; yy < yhi; yy += 4, pc += 4 * pw) {
+            uint32_t W[4][5];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (yy + u < yhi) {
+#pragma unroll
+                    for (int k = 0; k < 5; k++)
+                        W[u][k] = pc[u * pw + k];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (yy + u >= yhi)
+                    break;
+                uint32_t s0 = flip4(bytes_at(W[u][1], W[u][0], sh));
+                uint32_t s1 = flip4(bytes_at(W[u][2], W[u][1], sh));
+                uint32_t s2 = flip4(bytes_at(W[u][3], W[u][2], sh));
+                uint32_t s3 = flip4(bytes_at(W[u][4], W[u][3], sh));
+                // all template reads first (row clamped into range), then
+                // the products of the centre rows this image row belongs to
+                uint4 tw[R];
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    int i = min(max(yy + u - cy[r], 0), a.m - 1);
+                    tw[r] = *(const uint4 *)(tpl + i * n4w + 4 * c);
+                }
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    int i = yy + u - cy[r];
+                    if (r < nvalid && i >= 0 && i < a.m) {
+                        int v = acc[r];
+                        v = dot4(s0, tw[r].x, v);
+                        v = dot4(s1, tw[r].y, v);
+                        v = dot4(s2, tw[r].z, v);
+                        v = dot4(s3, tw[r].w, v);
+                        acc[r] = v;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        xs[(wv * R + r) * 64 + lane] = acc[r];
+    __syncthreads();
     RecPod rec = rec_empty();
-    int G = a.Gy * a.Gx;
-    for (int k = 0; k < 8; k++) {
-        int g = blockIdx.x * 32 + wv * 8 + k;
-        if (g >= G)
-            break;
-        int oy, ox, hh, ww, cy, cx;
-        group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
-        int X = wave_dot_tpl(smem, n4, a.img, a.pitch, cy, cx, a.m, ws, lane);
-        if (lane == 0) {
-            int64_t l = (int64_t)cy * a.Lx + cx;
+    for (int r = wv; r < nvalid; r += nw) {
+        int X = 0;
+        for (int k = 0; k < nw; k++)
+            X += xs[(k * R + r) * 64 + lane];
+        if (colok) {
+            int g = (gy0 + r) * a.Gx + gx;
+            int oy = (gy0 + r) * a.h;
+            int hh = min(a.h, a.Ly - oy);
+            int64_t l = (int64_t)(oy + (hh - 1) / 2) * a.Lx + cx;
             int2 sc = a.stat[l];
             int64_t dc = var_num(mn, sc);
             int64_t num = mn * (int64_t)X - st * (int64_t)sc.x;
@@ -410,24 +467,13 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
                 a.dec[l] = 1;
         }
     }
-    if (lane == 0)
-        wrec[wv] = rec;
-    __syncthreads();
+    RecPod b = block_rec(rec, rred);
+    int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if (t == 0) {
-        RecPod b = wrec[0];
-        for (int k = 1; k < 4; k++)
-            rec_merge(b, wrec[k]);
-        a.recs[blockIdx.x] = b;
-    }
-    if (last_block(&a.qs->done[0], &lastflag)) {
-        RecPod f = reduce_records(a.recs, 0, gridDim.x, rred);
-        if (t == 0) {
+        a.recs[bid] = b;
+        if (bid == 0) {
             a.qs->st = st;
             a.qs->dt = dt;
-            a.qs->best0 = f.rho;
-            a.qs->best0_l = f.l;
-            if (a.set_thr)
-                set_threshold(a.qs, f.rho, f.l, a.delta);
         }
     }
 }
@@ -443,8 +489,6 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
     __shared__ RecPod wrec[4];
-    __shared__ RecPod rred[256];
-    __shared__ int lastflag;
     __shared__ unsigned long long ured[8];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (a.qs->degenerate)
@@ -454,7 +498,6 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
     load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t dt = mn * sq - st * st;
-    WaveSplit ws = wave_split(a.m, n4);
     int64_t c0 = a.qs->best0_l;
     int cy0 = (int)(c0 / a.Lx), cx0 = (int)(c0 - (c0 / a.Lx) * a.Lx);
     int W = 2 * a.radius + 1;
@@ -469,7 +512,7 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
         int64_t l = (int64_t)y * a.Lx + x;
         if (a.skip_centres && centre_of(y, x, a.Ly, a.Lx, a.h, a.w) == l)
             continue;
-        int X = wave_dot_tpl(smem, n4, a.img, a.pitch, y, x, a.m, ws, lane);
+        int X = wave_dot_tpl(smem, n4, a.img, a.pitch, y, x, a.m, lane);
         if (lane == 0) {
             int2 so = a.stat[l];
             int64_t dr = var_num(mn, so);
@@ -490,18 +533,6 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
         a.recs[a.rec_off + blockIdx.x] = b;
         atomicAdd(&a.qs->n_window, c);
     }
-    if (last_block(&a.qs->done[1], &lastflag)) {
-        RecPod f = reduce_records(a.recs, a.rec_off, a.rec_off + gridDim.x, rred);
-        if (t == 0) {
-            double best = f.valid ? f.rho : -2.0;
-            int64_t bl = f.valid ? f.l : INT64_MAX;
-            if (a.include_best0 && rec_better(a.qs->best0, a.qs->best0_l, best, bl)) {
-                best = a.qs->best0;
-                bl = a.qs->best0_l;
-            }
-            set_threshold(a.qs, best, bl, a.delta);
-        }
-    }
 }
 
 // ============================================================== scan 2: members
@@ -511,9 +542,28 @@ __device__ __forceinline__ bool in_window(int y, int x, int wy, int wx, int radi
     return radius >= 0 && abs(y - wy) <= radius && abs(x - wx) <= radius;
 }
 
+// Loads the template words only (statistics come from scan 1).
+__device__ void load_template_words(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int n4,
+                                    uint32_t *lds)
+{
+    for (int idx = threadIdx.x; idx < m * n4; idx += blockDim.x) {
+        int r = idx / n4, j = idx - (idx / n4) * n4;
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            int c = 4 * j + b;
+            if (c < n)
+                w |= ((uint32_t)(((int)tpl[(int64_t)r * ts + c] - 128) & 0xff)) << (8 * b);
+        }
+        lds[idx] = w;
+    }
+}
+
 // Canonical binary64 elimination test (the transitive bound of Eq. 2, or
 // its angle-triangle form with the blur angle C when a.opta).  True: keep.
-__device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t c, int g, int64_t mn, int64_t dt, double thr64)
+// o: location, s: its slot in the group-major tables, c: centre location.
+__device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t s, int64_t c, int g, int64_t mn, int64_t dt,
+                               double thr64)
 {
     int2 sc = a.statS[c], so = a.statS[o];
     int64_t dc = var_num(mn, sc), dso = var_num(mn, so);
@@ -527,11 +577,11 @@ __device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t c, int g, in
         return true;
     int64_t ntc = a.g_num[g];
     double ra = rho64(ntc, dt, dc), sa = sin64(ntc, dt, dc);
-    int64_t nco = mn * (int64_t)a.x_b[o] - (int64_t)sc.x * (int64_t)so.x;
+    int64_t nco = mn * (int64_t)a.x_b[s] - (int64_t)sc.x * (int64_t)so.x;
     double rb = rho64(nco, dc, dso), sb = sin64(nco, dc, dso);
     double rc = 1.0, sc2 = 0.0;
     if (a.opta) {
-        int64_t noo = mn * (int64_t)a.x_c[o] - (int64_t)so.x * (int64_t)si.x;
+        int64_t noo = mn * (int64_t)a.x_c[s] - (int64_t)so.x * (int64_t)si.x;
         rc = rho64(noo, dso, dio);
         sc2 = sin64(noo, dso, dio);
     }
@@ -541,34 +591,59 @@ __device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t c, int g, in
     return true;
 }
 
-// Tile of 16 x 4 groups per block.  Phase 1: one lane per group drops the
+__device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
+{
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(incl, off);
+        if (lane >= off)
+            incl += u;
+    }
+    if (lane == 63)
+        tmp[wv] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int k = 0; k < 4; k++) {
+        if (k < wv)
+            base += tmp[k];
+        tot += tmp[k];
+    }
+    *total = tot;
+    __syncthreads();
+    return base + incl - v;
+}
+
+// 256 consecutive groups per block.  Phase 1: one thread per group drops the
 // whole group when the interval of its member angles lies beyond the
-// threshold angle from A.  Phase 2: the members of the other groups are
-// tested one per thread (binary32 angles, canonical binary64 inside the guard
-// band); survivors go to an LDS list.  Phase 3: each wave matches survivors
-// on the original image.  The last block reduces all records of the query.
+// threshold angle from A.  Phase 2: the members of the remaining groups are
+// tested one per thread, reading the group-major angle tables contiguously
+// (binary32 angles; canonical binary64 inside the guard band); survivors go
+// to an LDS list.  Phase 3: one wave per survivor matches it on the original
+// image (template loaded only by blocks that have survivors).  The last
+// block reduces every record of the query.
 __global__ __launch_bounds__(256) void k_members(MemArgs a)
 {
+    constexpr int CAP = 2048;
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[8];
-    __shared__ int s_cnt[64], s_pref[65], s_gid[64];
-    __shared__ int64_t s_list[256];
-    __shared__ int s_nsurv, s_total;
+    __shared__ int s_pref[257];
+    __shared__ int s_tmp[4];
+    __shared__ int s_geo[256][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
+    __shared__ int s_list[CAP];
+    __shared__ int s_nsurv, s_tpl;
     __shared__ RecPod wrec[4];
-    __shared__ RecPod rred[256];
     __shared__ unsigned long long ured[8];
-    __shared__ int lastflag;
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (a.qs->degenerate)
         return;
-    int n4 = (a.n + 3) >> 2;
-    int64_t st, sq;
-    load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
+    const int n4 = (a.n + 3) >> 2;
     const int64_t mn = (int64_t)a.m * a.n;
-    const int64_t dt = mn * sq - st * st;
-    WaveSplit ws = wave_split(a.m, n4);
+    const int64_t st = a.qs->st, dt = a.qs->dt;
     const float lo = a.qs->thr_lo, hi = a.qs->thr_hi;
     const double thr64 = a.qs->thr64;
+    const int hw = a.h * a.w;
+    const int G = a.Gy * a.Gx;
     int wy = -1, wx = -1;
     if (a.radius >= 0) {
         int64_t c0 = a.qs->best0_l;
@@ -576,108 +651,116 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         wx = (int)(c0 - (c0 / a.Lx) * a.Lx);
     }
     unsigned long long n_elim = 0, n_surv = 0;
+    const int g0 = blockIdx.x * 256;
 
-    if (t < 64) {
-        int gy = blockIdx.y * 4 + (t >> 4), gx = blockIdx.x * 16 + (t & 15);
-        int cnt = 0;
-        if (gy < a.Gy && gx < a.Gx) {
-            int g = gy * a.Gx + gx;
+    int cnt = 0;
+    {
+        int g = g0 + t;
+        if (g < G) {
             int oy, ox, hh, ww, cy, cx;
             group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
             float A = a.g_theta[g];
-            GroupSum s = a.gsum[g];
+            s_geo[t][0] = (oy << 16) | ox;
+            s_geo[t][1] = (hh << 16) | ww;
+            s_geo[t][2] = (cy << 16) | cx;
+            s_geo[t][3] = __float_as_int(A);
+            GroupSum gs = a.gsum[g];
             bool drop = false;
-            if (!(s.flags & 1)) {
+            if (!(gs.flags & 1)) {
                 float d = 0.0f;
                 bool outside = true;
-                if (A < s.bmin)
-                    d = s.bmin - A;
-                else if (A > s.bmax)
-                    d = A - s.bmax;
+                if (A < gs.bmin)
+                    d = gs.bmin - A;
+                else if (A > gs.bmax)
+                    d = A - gs.bmax;
                 else
                     outside = false;
-                if (outside && (d - s.cmax) > hi)
+                if (outside && (d - gs.cmax) > hi)
                     drop = true;
             }
             if (drop) {
-                // every member except the centre (plain scan) and window locations
-                for (int yy = oy; yy < oy + hh; yy++)
-                    for (int xx = ox; xx < ox + ww; xx++) {
-                        if (!a.opta && yy == cy && xx == cx)
-                            continue;
-                        if (in_window(yy, xx, wy, wx, a.radius))
-                            continue;
-                        n_elim++;
-                        if (a.dec)
+                int inter = 0, cin = 0;
+                if (a.radius >= 0) {
+                    int y0 = max(oy, wy - a.radius), y1 = min(oy + hh - 1, wy + a.radius);
+                    int x0 = max(ox, wx - a.radius), x1 = min(ox + ww - 1, wx + a.radius);
+                    if (y0 <= y1 && x0 <= x1)
+                        inter = (y1 - y0 + 1) * (x1 - x0 + 1);
+                    cin = in_window(cy, cx, wy, wx, a.radius) ? 1 : 0;
+                }
+                n_elim += a.opta ? (hh * ww - inter) : (hh * ww - 1 - (inter - cin));
+                if (a.dec)
+                    for (int yy = oy; yy < oy + hh; yy++)
+                        for (int xx = ox; xx < ox + ww; xx++) {
+                            if ((!a.opta && yy == cy && xx == cx) || in_window(yy, xx, wy, wx, a.radius))
+                                continue;
                             a.dec[(int64_t)yy * a.Lx + xx] = 0;
-                    }
+                        }
             } else {
                 cnt = hh * ww;
             }
-            s_gid[t] = g;
         }
-        s_cnt[t] = cnt;
     }
-    if (t == 0)
-        s_nsurv = 0;
-    __syncthreads();
+    int total;
+    s_pref[t] = block_excl_scan(cnt, s_tmp, &total);
     if (t == 0) {
-        int acc = 0;
-        for (int k = 0; k < 64; k++) {
-            s_pref[k] = acc;
-            acc += s_cnt[k];
-        }
-        s_pref[64] = acc;
-        s_total = acc;
+        s_pref[256] = total;
+        s_nsurv = 0;
+        s_tpl = 0;
     }
     __syncthreads();
     RecPod rec = rec_empty();
-    int total = s_total;
-    for (int base = 0; base < total; base += 256) {
-        int idx = base + t;
-        if (idx < total) {
+    for (int base = 0; base < total; base += CAP) {
+        int end = min(total, base + CAP);
+        for (int idx = base + t; idx < end; idx += 256) {
             int u = 0;
-            for (int step = 32; step > 0; step >>= 1)
-                if (u + step < 64 && s_pref[u + step] <= idx)
+            for (int step = 128; step > 0; step >>= 1)
+                if (s_pref[u + step] <= idx)
                     u += step;
-            int g = s_gid[u];
+            int g = g0 + u;
             int k = idx - s_pref[u];
-            int oy, ox, hh, ww, cy, cx;
-            group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
-            int my = k / ww, mx = k - (k / ww) * ww;
+            int oy = s_geo[u][0] >> 16, ox = s_geo[u][0] & 0xffff;
+            int ww = s_geo[u][1] & 0xffff;
+            int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+            int my = k / ww, mx = k - my * ww;
             int y = oy + my, x = ox + mx;
             bool skip = (!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius);
-            if (!skip) {
-                int64_t o = (int64_t)y * a.Lx + x;
-                int64_t c = (int64_t)cy * a.Lx + cx;
-                float A = a.g_theta[g];
-                float B = a.theta_b[o];
-                float C = a.opta ? a.theta_c[o] : 0.0f;
-                float e = fabsf(A - B) - C;
-                bool keep;
-                if (e > hi)
-                    keep = false;
-                else if (e < lo)
-                    keep = true;
-                else
-                    keep = keep_canonical(a, o, c, g, mn, dt, thr64);
-                if (keep) {
-                    int pos = atomicAdd(&s_nsurv, 1);
-                    s_list[pos] = o;
-                    n_surv++;
-                } else {
-                    n_elim++;
-                }
-                if (a.dec)
-                    a.dec[o] = keep ? 2 : 0;
+            if (skip)
+                continue;
+            int64_t o = (int64_t)y * a.Lx + x;
+            int64_t sl = (int64_t)g * hw + my * a.w + mx;
+            float A = __int_as_float(s_geo[u][3]);
+            float B = a.theta_b[sl];
+            float C = a.opta ? a.theta_c[sl] : 0.0f;
+            float e = fabsf(A - B) - C;
+            bool keep;
+            if (e > hi)
+                keep = false;
+            else if (e < lo)
+                keep = true;
+            else
+                keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g, mn, dt, thr64);
+            if (keep) {
+                int pos = atomicAdd(&s_nsurv, 1);
+                s_list[pos] = (int)o;
+                n_surv++;
+            } else {
+                n_elim++;
             }
+            if (a.dec)
+                a.dec[o] = keep ? 2 : 0;
         }
         __syncthreads();
         int ns = s_nsurv;
+        if (ns > 0 && !s_tpl) {
+            load_template_words(a.tpl, a.ts, a.m, a.n, n4, smem);
+            __syncthreads();
+            if (t == 0)
+                s_tpl = 1;
+        }
         for (int k = wv; k < ns; k += 4) {
             int64_t o = s_list[k];
             int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
-            int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, ws, lane);
+            int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, lane);
             if (lane == 0) {
                 int2 so = a.statI[o];
                 int64_t dr = var_num(mn, so);
@@ -698,19 +781,25 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         RecPod b = wrec[0];
         for (int k = 1; k < 4; k++)
             rec_merge(b, wrec[k]);
-        a.recs[a.rec_off + blockIdx.y * gridDim.x + blockIdx.x] = b;
+        a.recs[a.rec_off + blockIdx.x] = b;
         atomicAdd(&a.qs->n_elim, ce);
         atomicAdd(&a.qs->n_surv, cs);
     }
-    if (last_block(&a.qs->done[2], &lastflag)) {
-        RecPod f = reduce_records(a.recs, a.final_from, a.rec_off + gridDim.x * gridDim.y, rred);
-        if (t == 0) {
-            a.qs->st = st;
-            a.qs->dt = dt;
-            a.qs->fin = f;
-            a.qs->fin_r32 = rho32(f.num, dt, f.dr);
-        }
-    }
+}
+
+// Copies a row-major per-location table into the group-major layout of
+// group size (h, w): slot g*h*w + my*w + mx.
+__global__ __launch_bounds__(256) void k_regroup(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, int Ly,
+                                                 int Lx, int h, int w)
+{
+    int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (o >= (int64_t)Ly * Lx)
+        return;
+    int y = (int)(o / Lx), x = (int)(o - (o / Lx) * Lx);
+    int gy = y / h, gx = x / w;
+    int Gx = (Lx + w - 1) / w;
+    int64_t sl = ((int64_t)gy * Gx + gx) * (h * w) + (y - gy * h) * w + (x - gx * w);
+    out[sl] = in[o];
 }
 
 // ============================================================== Alg. 1: auto-correlation with the centre
@@ -724,7 +813,6 @@ __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t L = (int64_t)a.Ly * a.Lx;
     const int64_t mn = (int64_t)a.m * a.n;
-    WaveSplit ws = wave_split(a.m, (a.n + 3) >> 2);
     unsigned long long cnt = 0;
     for (int k = 0; k < 16; k++) {
         int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
@@ -738,7 +826,7 @@ __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
         if (c == o)
             X = sc.y;  // sum of squares of the centre block
         else
-            X = wave_dot_img(a.J, a.pJ, cy, cx, a.J, a.pJ, y, x, a.m, a.n, ws, lane);
+            X = wave_dot_img(a.J, a.pJ, cy, cx, a.J, a.pJ, y, x, a.m, a.n, lane);
         if (lane != 0)
             continue;
         int64_t dc = var_num(mn, sc), dov = var_num(mn, so);
@@ -748,8 +836,11 @@ __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
             a.dc_out[o] = dc;
             a.do_out[o] = dov;
         } else if (a.mode == AC_BUILD) {
-            a.theta_b[o] = theta32(num, dc, dov);
-            a.x_b[o] = X;
+            int gy = y / a.h, gx = x / a.w;
+            int64_t sl = ((int64_t)gy * ((a.Lx + a.w - 1) / a.w) + gx) * (a.h * a.w) + (y - gy * a.h) * a.w +
+                         (x - gx * a.w);
+            a.theta_b[sl] = theta32(num, dc, dov);
+            a.x_b[sl] = X;
         } else if (a.mode == AC_COUNT) {
             if (c == o)
                 continue;
@@ -809,9 +900,9 @@ __global__ __launch_bounds__(256) void k_gsum(GsumArgs a)
         for (int x = ox; x < ox + ww; x++) {
             if (!a.opta && y == cy && x == cx)
                 continue;
-            int64_t o = (int64_t)y * a.Lx + x;
-            float B = a.theta_b[o];
-            float C = a.opta ? a.theta_c[o] : 0.0f;
+            int64_t sl = (int64_t)g * (a.h * a.w) + (y - oy) * a.w + (x - ox);
+            float B = a.theta_b[sl];
+            float C = a.opta ? a.theta_c[sl] : 0.0f;
             if (isnan(B) || isnan(C)) {
                 flags |= 1;
                 continue;
@@ -870,14 +961,13 @@ __global__ __launch_bounds__(256) void k_blurcorr(BcArgs a)
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t L = (int64_t)a.Ly * a.Lx;
     const int64_t mn = (int64_t)a.m * a.n;
-    WaveSplit ws = wave_split(a.m, (a.n + 3) >> 2);
     unsigned long long cnt = 0;
     for (int k = 0; k < 16; k++) {
         int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
         if (o >= L)
             break;
         int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
-        int X = wave_dot_img(a.J, a.pitch, y, x, a.I, a.pitch, y, x, a.m, a.n, ws, lane);
+        int X = wave_dot_img(a.J, a.pitch, y, x, a.I, a.pitch, y, x, a.m, a.n, lane);
         if (lane != 0)
             continue;
         int2 sj = a.statJ[o], si = a.statI[o];
@@ -958,9 +1048,50 @@ __global__ __launch_bounds__(256) void k_revert(const uint8_t *__restrict__ colm
         atomicAdd(counter, s);
 }
 
+// ============================================================== record reductions
+
+// One block folds a range of per-block records after the kernel that wrote
+// them has finished (the kernel boundary makes them visible on every XCD).
+//   RD_BEST0: the scan-1 best -> best0 (and the threshold when set_thr);
+//   RD_WINDOW: the window best, with best0 when include_best0 -> threshold;
+//   RD_FINAL: the answer.
+__global__ __launch_bounds__(256) void k_reduce(RecPod *__restrict__ recs, int lo, int hi, QState *qs, int stage,
+                                                int flag, double delta)
+{
+    __shared__ RecPod rred[256];
+    if (qs->degenerate)
+        return;
+    RecPod f = reduce_records(recs, lo, hi, rred);
+    if (threadIdx.x != 0)
+        return;
+    if (stage == RD_BEST0) {
+        qs->best0 = f.rho;
+        qs->best0_l = f.l;
+        if (flag)
+            set_threshold(qs, f.rho, f.l, delta);
+    } else if (stage == RD_WINDOW) {
+        double best = f.valid ? f.rho : -2.0;
+        int64_t bl = f.valid ? f.l : INT64_MAX;
+        if (flag && rec_better(qs->best0, qs->best0_l, best, bl)) {
+            best = qs->best0;
+            bl = qs->best0_l;
+        }
+        set_threshold(qs, best, bl, delta);
+    } else {
+        qs->fin = f;
+        qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
+    }
+}
+
 // ============================================================== launch wrappers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, int stage, int flag, double delta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, recs, lo, hi, qs, stage, flag, delta);
+    return hipGetLastError();
+}
 
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s)
 {
@@ -1010,13 +1141,36 @@ hipError_t launch_full(FullArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-int centres_record_count(int G) { return (int)blocks_for(G, 32); }
+static int centre_waves(int n)
+{
+    int nch = ((((n + 3) / 4) + 3) / 4 * 4) / 4;
+    return nch >= 4 ? 4 : (nch >= 2 ? 2 : 1);
+}
+
+// Eight centre rows per wave when that still gives enough waves to fill
+// the chip, four otherwise.
+static int centre_rows(int Gy, int Gx, int n)
+{
+    int64_t waves8 = (int64_t)blocks_for(Gx, 64) * blocks_for(Gy, 8) * centre_waves(n);
+    return waves8 >= 4096 ? 8 : 4;
+}
+
+int centres_record_count(int Gy, int Gx, int n)
+{
+    return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(Gy, Gx, n)));
+}
 
 hipError_t launch_centres(ScanArgs a, hipStream_t s)
 {
-    int G = a.Gy * a.Gx;
-    size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
-    hipLaunchKernelGGL(k_centres, dim3(blocks_for(G, 32)), dim3(256), lds, s, a);
+    a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
+    int nw = centre_waves(a.n);
+    int R = centre_rows(a.Gy, a.Gx, a.n);
+    size_t lds = (size_t)a.m * a.n4w * 4 + (size_t)nw * R * 64 * 4;
+    dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, R));
+    if (R == 8)
+        hipLaunchKernelGGL(k_centres<8>, grid, dim3(64 * nw), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_centres<4>, grid, dim3(64 * nw), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1034,13 +1188,19 @@ hipError_t launch_window(WinArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-int members_record_count(int Gy, int Gx) { return (int)(blocks_for(Gx, 16) * blocks_for(Gy, 4)); }
+int members_record_count(int Gy, int Gx) { return (int)blocks_for((int64_t)Gy * Gx, 256); }
 
 hipError_t launch_members(MemArgs a, hipStream_t s)
 {
     size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
-    dim3 grid(blocks_for(a.Gx, 16), blocks_for(a.Gy, 4));
-    hipLaunchKernelGGL(k_members, grid, dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_members, dim3(members_record_count(a.Gy, a.Gx)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_regroup, dim3(blocks_for((int64_t)Ly * Lx, 256)), dim3(256), 0, s, (const uint32_t *)in,
+                       (uint32_t *)out, Ly, Lx, h, w);
     return hipGetLastError();
 }
 
