@@ -41,7 +41,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", default="opta", choices=["full", "te_fixed", "egs", "opta"])
-    ap.add_argument("--refine", type=int, default=0, help="threshold refinement radius (0 = as printed)")
+    ap.add_argument("--refine", type=int, default=2,
+                    help="threshold refinement radius around the best centre (0 = section VI as printed)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")

@@ -235,15 +235,20 @@ __device__ __forceinline__ RecPod rec_empty()
     r.dr = 0;
     r.r32max = -2.0f;
     r.valid = 0;
+    r.n_elim = r.n_surv = r.n_window = 0;
     return r;
 }
 
 __device__ __forceinline__ void rec_merge(RecPod &a, const RecPod &b)
 {
     float m = fmaxf(a.r32max, b.r32max);
+    unsigned long long e = a.n_elim + b.n_elim, s = a.n_surv + b.n_surv, w = a.n_window + b.n_window;
     if (b.valid && (!a.valid || rec_better(b.rho, b.l, a.rho, a.l)))
         a = b;
     a.r32max = m;
+    a.n_elim = e;
+    a.n_surv = s;
+    a.n_window = w;
 }
 
 // Streaming band selection: a candidate is evaluated in binary64 when its

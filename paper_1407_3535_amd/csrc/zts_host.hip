@@ -685,7 +685,7 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
     } else {
         bool opta = mode == ZTS_OPTA;
         G = P->Gy * P->Gx;
-        int n1 = centres_record_count(P->Gy, P->Gx, n);
+        int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h);
         if (opta)
             radius = std::max(P->radius, std::max(pr.refine_radius, 0));
         else

@@ -33,7 +33,7 @@ struct ScanArgs {
     const int2 *stat;
     const uint8_t *tpl;
     int64_t ts;
-    int m, n, n4w, Ly, Lx, h, w, Gy, Gx;
+    int m, n, n4w, pad, Ly, Lx, h, w, Gy, Gx;
     int64_t *g_num;
     float *g_theta;
     RecPod *recs;
@@ -143,7 +143,7 @@ int full_record_count(int Ly, int Lx);
 size_t full_lds_bytes(int m, int n);
 hipError_t launch_full(FullArgs a, hipStream_t s);
 
-int centres_record_count(int Gy, int Gx, int n);
+int centres_record_count(int Gy, int Gx, int m, int n, int h);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);

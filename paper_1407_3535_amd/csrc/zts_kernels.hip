@@ -357,11 +357,12 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
     __shared__ RecPod rred[256];
     const int n4w = a.n4w;
     const int nw = blockDim.x >> 6;
+    const int pad = a.pad;  // zero template rows above and below: >= cy[R-1] - cy[0]
     uint32_t *tpl = smem;
-    int *xs = (int *)(smem + a.m * n4w);  // [nw][R][64]
+    int *xs = (int *)(smem + (a.m + 2 * pad) * n4w);  // [nw][R][64]
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     int64_t st, sq;
-    load_template(a.tpl, a.ts, a.m, a.n, n4w, 0, a.m, tpl, red, &st, &sq);
+    load_template(a.tpl, a.ts, a.m, a.n, n4w, pad, a.m + 2 * pad, tpl, red, &st, &sq);
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t dt = mn * sq - st * st;
     if (dt == 0) {
@@ -382,6 +383,8 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
     const uint32_t *colbase = (const uint32_t *)a.img + (cx >> 2);
     const int gy0 = blockIdx.y * R;
     const int nvalid = min(R, a.Gy - gy0);
+    // centre rows of the wave; rows past the grid repeat the last one (their
+    // results are discarded)
     int cy[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -395,15 +398,13 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
     for (int r = 0; r < R; r++)
         acc[r] = 0;
     const int nch = n4w >> 2;
-    int ylo = cy[0], yhi = cy[0] + a.m;
-#pragma unroll
-    for (int r = 1; r < R; r++)
-        if (r < nvalid)
-            yhi = cy[r] + a.m;
+    const int ylo = cy[0], yhi = cy[R - 1] + a.m;
     for (int c = wv; c < nch; c += nw) {
-        // four image rows of words are loaded at once, then used
+        // padded template row of centre row r for image row yy + u is
+        // pad + (yy + u) - cy[r]; tb points at row pad + (yy - ylo)
+        const uint32_t *tb = tpl + pad * n4w + 4 * c;
         const uint32_t *pc = colbase + (int64_t)ylo * pw + 4 * c;
-        for (int yy = ylo; yy < yhi; yy += 4, pc += 4 * pw) {
+        for (int yy = ylo; yy < yhi; yy += 4, pc += 4 * pw, tb += 4 * n4w) {
             uint32_t W[4][5];
 #pragma unroll
             for (int u = 0; u < 4; u++)
@@ -416,30 +417,26 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
             for (int u = 0; u < 4; u++) {
                 if (yy + u >= yhi)
                     break;
-                uint32_t s0 = flip4(bytes_at(W[u][1], W[u][0], sh));
-                uint32_t s1 = flip4(bytes_at(W[u][2], W[u][1], sh));
-                uint32_t s2 = flip4(bytes_at(W[u][3], W[u][2], sh));
-                uint32_t s3 = flip4(bytes_at(W[u][4], W[u][3], sh));
-                // all template reads first (row clamped into range), then
-                // the products of the centre rows this image row belongs to
+                uint32_t sv[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    sv[k] = flip4(bytes_at(W[u][k + 1], W[u][k], sh));
                 uint4 tw[R];
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    int i = min(max(yy + u - cy[r], 0), a.m - 1);
-                    tw[r] = *(const uint4 *)(tpl + i * n4w + 4 * c);
-                }
+                for (int r = 0; r < R; r++)
+                    tw[r] = *(const uint4 *)(tb + (u - (cy[r] - ylo)) * n4w);
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    int i = yy + u - cy[r];
-                    if (r < nvalid && i >= 0 && i < a.m) {
-                        int v = acc[r];
-                        v = dot4(s0, tw[r].x, v);
-                        v = dot4(s1, tw[r].y, v);
-                        v = dot4(s2, tw[r].z, v);
-                        v = dot4(s3, tw[r].w, v);
-                        acc[r] = v;
-                    }
-                }
+                for (int r = 0; r < R; r++)
+                    acc[r] = dot4(sv[0], tw[r].x, acc[r]);
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    acc[r] = dot4(sv[1], tw[r].y, acc[r]);
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    acc[r] = dot4(sv[2], tw[r].z, acc[r]);
+#pragma unroll
+                for (int r = 0; r < R; r++)
+                    acc[r] = dot4(sv[3], tw[r].w, acc[r]);
             }
         }
     }
@@ -530,8 +527,8 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
         RecPod b = wrec[0];
         for (int k = 1; k < 4; k++)
             rec_merge(b, wrec[k]);
+        b.n_window = c;
         a.recs[a.rec_off + blockIdx.x] = b;
-        atomicAdd(&a.qs->n_window, c);
     }
 }
 
@@ -711,34 +708,51 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     RecPod rec = rec_empty();
     for (int base = 0; base < total; base += CAP) {
         int end = min(total, base + CAP);
-        for (int idx = base + t; idx < end; idx += 256) {
+        // locate this thread's (up to 8) members and load their angles first
+        int64_t o8[CAP / 256], sl8[CAP / 256];
+        int u8[CAP / 256];
+        float B8[CAP / 256], C8[CAP / 256];
+#pragma unroll
+        for (int q = 0; q < CAP / 256; q++) {
+            int idx = base + t + 256 * q;
+            o8[q] = -1;
+            if (idx >= end)
+                continue;
             int u = 0;
             for (int step = 128; step > 0; step >>= 1)
                 if (s_pref[u + step] <= idx)
                     u += step;
-            int g = g0 + u;
             int k = idx - s_pref[u];
             int oy = s_geo[u][0] >> 16, ox = s_geo[u][0] & 0xffff;
             int ww = s_geo[u][1] & 0xffff;
             int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
             int my = k / ww, mx = k - my * ww;
             int y = oy + my, x = ox + mx;
-            bool skip = (!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius);
-            if (skip)
+            if ((!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius))
                 continue;
-            int64_t o = (int64_t)y * a.Lx + x;
-            int64_t sl = (int64_t)g * hw + my * a.w + mx;
+            o8[q] = (int64_t)y * a.Lx + x;
+            sl8[q] = (int64_t)(g0 + u) * hw + my * a.w + mx;
+            u8[q] = u;
+            B8[q] = a.theta_b[sl8[q]];
+            C8[q] = a.opta ? a.theta_c[sl8[q]] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < CAP / 256; q++) {
+            if (o8[q] < 0)
+                continue;
+            int u = u8[q];
+            int64_t o = o8[q], sl = sl8[q];
             float A = __int_as_float(s_geo[u][3]);
-            float B = a.theta_b[sl];
-            float C = a.opta ? a.theta_c[sl] : 0.0f;
-            float e = fabsf(A - B) - C;
+            float e = fabsf(A - B8[q]) - C8[q];
             bool keep;
             if (e > hi)
                 keep = false;
             else if (e < lo)
                 keep = true;
-            else
-                keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g, mn, dt, thr64);
+            else {
+                int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+                keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g0 + u, mn, dt, thr64);
+            }
             if (keep) {
                 int pos = atomicAdd(&s_nsurv, 1);
                 s_list[pos] = (int)o;
@@ -781,9 +795,9 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         RecPod b = wrec[0];
         for (int k = 1; k < 4; k++)
             rec_merge(b, wrec[k]);
+        b.n_elim = ce;
+        b.n_surv = cs;
         a.recs[a.rec_off + blockIdx.x] = b;
-        atomicAdd(&a.qs->n_elim, ce);
-        atomicAdd(&a.qs->n_surv, cs);
     }
 }
 
@@ -1080,6 +1094,9 @@ __global__ __launch_bounds__(256) void k_reduce(RecPod *__restrict__ recs, int l
     } else {
         qs->fin = f;
         qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
+        qs->n_elim = f.n_elim;
+        qs->n_surv = f.n_surv;
+        qs->n_window = f.n_window;
     }
 }
 
@@ -1147,30 +1164,37 @@ static int centre_waves(int n)
     return nch >= 4 ? 4 : (nch >= 2 ? 2 : 1);
 }
 
-// Eight centre rows per wave when that still gives enough waves to fill
-// the chip, four otherwise.
-static int centre_rows(int Gy, int Gx, int n)
+// Centre rows per wave: the most (8, 4, 2 or 1) whose zero-padded template
+// rows cost at most a third of the useful ones, (R-1) h <= m/3, and whose
+// padded template fits 48 KB of LDS.
+static int centre_rows(int m, int n, int h)
 {
-    int64_t waves8 = (int64_t)blocks_for(Gx, 64) * blocks_for(Gy, 8) * centre_waves(n);
-    return waves8 >= 4096 ? 8 : 4;
+    int n4w = (((n + 3) / 4) + 3) / 4 * 4;
+    for (int R = 8; R > 1; R >>= 1)
+        if (3 * (R - 1) * h <= m && (size_t)(m + 2 * (R - 1) * h) * n4w * 4 <= 48 * 1024)
+            return R;
+    return 1;
 }
 
-int centres_record_count(int Gy, int Gx, int n)
+int centres_record_count(int Gy, int Gx, int m, int n, int h)
 {
-    return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(Gy, Gx, n)));
+    return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(m, n, h)));
 }
 
 hipError_t launch_centres(ScanArgs a, hipStream_t s)
 {
     a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
     int nw = centre_waves(a.n);
-    int R = centre_rows(a.Gy, a.Gx, a.n);
-    size_t lds = (size_t)a.m * a.n4w * 4 + (size_t)nw * R * 64 * 4;
+    int R = centre_rows(a.m, a.n, a.h);
+    a.pad = (R - 1) * a.h;
+    size_t lds = (size_t)(a.m + 2 * a.pad) * a.n4w * 4 + (size_t)nw * R * 64 * 4;
     dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, R));
-    if (R == 8)
-        hipLaunchKernelGGL(k_centres<8>, grid, dim3(64 * nw), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_centres<4>, grid, dim3(64 * nw), lds, s, a);
+    switch (R) {
+    case 8: hipLaunchKernelGGL(k_centres<8>, grid, dim3(64 * nw), lds, s, a); break;
+    case 4: hipLaunchKernelGGL(k_centres<4>, grid, dim3(64 * nw), lds, s, a); break;
+    case 2: hipLaunchKernelGGL(k_centres<2>, grid, dim3(64 * nw), lds, s, a); break;
+    default: hipLaunchKernelGGL(k_centres<1>, grid, dim3(64 * nw), lds, s, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@ struct RecPod {
     int64_t dr;    // exact D_r at l
     float r32max;  // largest binary32 rho among the candidates of the block
     int32_t valid;
+    // location counts of the block, summed when records are merged
+    unsigned long long n_elim, n_surv, n_window;
 };
 
 // Per-query state in device memory; the host reads it back once at the end.
