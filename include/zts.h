@@ -117,7 +117,8 @@ typedef struct {
     zts_status status;
     float phase_ms[4];       /* device time per kernel, HIP events on the library's stream:
                                 ZTS_FULL: [0] dense kernel; other modes: [0] scan 1 (centres),
-                                [1] refinement window, [2] scan 2 (members and survivors) */
+                                [1] refinement window, [2] scan 2 (members and survivors);
+                                [3] the one-block record reductions between them */
     int32_t pad1;
 } zts_result;
 

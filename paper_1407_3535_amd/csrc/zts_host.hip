@@ -84,7 +84,7 @@ struct Ctx {
     uint64_t used = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t evp[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t evp[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int next_id = 1;
     std::map<int, std::unique_ptr<Image>> images;
     // per-query scratch, grown on demand
@@ -679,9 +679,10 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         a.rho_map = rho_map;
         a.dec = d_dec;
         hip_check(launch_full(a, c->stream));
+        hip_check(hipEventRecord(c->evp[0], c->stream));
         hip_check(launch_reduce(c->recs.as<RecPod>(), 0, full_record_count(Ly, Lx), qs, RD_FINAL, 0, pr.margin,
                                 c->stream));
-        hip_check(hipEventRecord(c->evp[0], c->stream));
+        hip_check(hipEventRecord(c->evp[1], c->stream));
     } else {
         bool opta = mode == ZTS_OPTA;
         G = P->Gy * P->Gx;
@@ -720,8 +721,9 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         s.delta = pr.margin;
         s.set_thr = radius < 0;
         hip_check(launch_centres(s, c->stream));
-        hip_check(launch_reduce(c->recs.as<RecPod>(), 0, n1, qs, RD_BEST0, radius < 0, pr.margin, c->stream));
         hip_check(hipEventRecord(c->evp[0], c->stream));
+        hip_check(launch_reduce(c->recs.as<RecPod>(), 0, n1, qs, RD_BEST0, radius < 0, pr.margin, c->stream));
+        hip_check(hipEventRecord(c->evp[1], c->stream));
         if (radius >= 0) {
             WinArgs wa;
             std::memset(&wa, 0, sizeof wa);
@@ -745,9 +747,11 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
             wa.dec = d_dec;
             wa.delta = pr.margin;
             hip_check(launch_window(wa, c->stream));
-            hip_check(launch_reduce(c->recs.as<RecPod>(), n1, n1 + n2, qs, RD_WINDOW, !opta, pr.margin, c->stream));
         }
-        hip_check(hipEventRecord(c->evp[1], c->stream));
+        hip_check(hipEventRecord(c->evp[2], c->stream));
+        if (radius >= 0)
+            hip_check(launch_reduce(c->recs.as<RecPod>(), n1, n1 + n2, qs, RD_WINDOW, !opta, pr.margin, c->stream));
+        hip_check(hipEventRecord(c->evp[3], c->stream));
         MemArgs ma;
         std::memset(&ma, 0, sizeof ma);
         ma.I = im->img.as<uint8_t>();
@@ -779,9 +783,10 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         ma.qs = qs;
         ma.dec = d_dec;
         hip_check(launch_members(ma, c->stream));
+        hip_check(hipEventRecord(c->evp[4], c->stream));
         hip_check(launch_reduce(c->recs.as<RecPod>(), opta ? n1 : 0, n1 + n2 + n3, qs, RD_FINAL, 0, pr.margin,
                                 c->stream));
-        hip_check(hipEventRecord(c->evp[2], c->stream));
+        hip_check(hipEventRecord(c->evp[5], c->stream));
     }
     hip_check(hipEventRecord(c->ev1, c->stream));
     hip_check(hipMemcpyAsync(c->h_qs, c->qs.ptr, sizeof(QState), hipMemcpyDeviceToHost, c->stream));
@@ -825,10 +830,16 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
     r.device_ms = ms;
     if (mode == ZTS_FULL) {
         hip_check(hipEventElapsedTime(&r.phase_ms[0], c->ev0, c->evp[0]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[3], c->evp[0], c->evp[1]));
     } else {
+        float r1, r2, r3;
         hip_check(hipEventElapsedTime(&r.phase_ms[0], c->ev0, c->evp[0]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[1], c->evp[0], c->evp[1]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[2], c->evp[1], c->evp[2]));
+        hip_check(hipEventElapsedTime(&r1, c->evp[0], c->evp[1]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[1], c->evp[1], c->evp[2]));
+        hip_check(hipEventElapsedTime(&r2, c->evp[2], c->evp[3]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[2], c->evp[3], c->evp[4]));
+        hip_check(hipEventElapsedTime(&r3, c->evp[4], c->evp[5]));
+        r.phase_ms[3] = r1 + r2 + r3;
     }
     r.status = ZTS_OK;
     *out = r;
@@ -958,6 +969,8 @@ zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
         hipEventCreate(&c.ev0) != hipSuccess || hipEventCreate(&c.ev1) != hipSuccess ||
         hipEventCreate(&c.evp[0]) != hipSuccess || hipEventCreate(&c.evp[1]) != hipSuccess ||
         hipEventCreate(&c.evp[2]) != hipSuccess || hipEventCreate(&c.evp[3]) != hipSuccess ||
+        hipEventCreate(&c.evp[4]) != hipSuccess || hipEventCreate(&c.evp[5]) != hipSuccess ||
+        hipEventCreate(&c.evp[6]) != hipSuccess || hipEventCreate(&c.evp[7]) != hipSuccess ||
         hipHostMalloc((void **)&c.h_qs, sizeof(QState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c.h_cnt, 64, hipHostMallocDefault) != hipSuccess) {
         delete z;
@@ -985,7 +998,7 @@ void zts_destroy(zts_ctx *z)
         if (c.h_cnt) (void)hipHostFree(c.h_cnt);
         if (c.ev0) (void)hipEventDestroy(c.ev0);
         if (c.ev1) (void)hipEventDestroy(c.ev1);
-        for (int k = 0; k < 4; k++)
+        for (int k = 0; k < 8; k++)
             if (c.evp[k]) (void)hipEventDestroy(c.evp[k]);
         if (c.stream) (void)hipStreamDestroy(c.stream);
     }
