@@ -209,6 +209,19 @@ zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tpl_dev, i
                              int64_t stride, zts_mode mode, const zts_params *params, void *stream,
                              zts_result *out);
 
+/* Exhaustive search (ZTS_FULL semantics, Eq. 1 at every location) of `count`
+ * host templates against one image in one call.  Templates are grouped by
+ * size; each group of up to 16 runs as an implicit GEMM on int8 MFMA
+ * (v_mfma_i32_16x16x64_i8, int32 accumulation): M = 16 locations of a row,
+ * N = 16 templates, K = 4 image rows x 16 columns.  tpls[k] points to an
+ * m[k] x n[k] template with row pitch strides[k] bytes.  out[k] receives
+ * template k's answer; a template with zero variance gets
+ * out[k].status = ZTS_E_DEGENERATE while the call returns ZTS_OK.  Counts:
+ * every location computed.  device_ms of every entry is the device time of
+ * the whole call. */
+zts_status zts_search_batch(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
+                            const int32_t *n, const int64_t *strides, zts_result *out);
+
 /* ---- parity helpers ------------------------------------------------------ */
 
 /* Every location's exact N and D_r and binary32 rho for one template

@@ -36,7 +36,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template"
 
 EXPORTS = ["zts_params_default", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
            "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
-           "zts_search", "zts_search_device", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
+           "zts_search", "zts_search_device", "zts_search_batch", "zts_debug_full_map", "zts_debug_autocorr",
+           "zts_debug_blur"]
 
 
 class ZtsError(RuntimeError):
@@ -124,6 +125,7 @@ def lib():
         L.zts_search.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(Result), vp]
         L.zts_search_device.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), vp,
                                         C.POINTER(Result)]
+        L.zts_search_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.zts_debug_full_map.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
         L.zts_debug_autocorr.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp]
         L.zts_debug_blur.argtypes = [vp, vp, i32, i32, vp, i32, vp]
@@ -247,6 +249,19 @@ def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None =
     return r.as_dict()
 
 
+def zts_search_batch(ctx, image: int, tpls) -> list:
+    """Exhaustive search of many host templates in one call (int8 MFMA); one dict per template."""
+    tpls = [_u8(t) for t in tpls]
+    k = len(tpls)
+    ptrs = (C.c_void_p * k)(*[t.ctypes.data for t in tpls])
+    ms = (C.c_int32 * k)(*[t.shape[0] for t in tpls])
+    ns = (C.c_int32 * k)(*[t.shape[1] for t in tpls])
+    st = (C.c_int64 * k)(*[t.strides[0] for t in tpls])
+    out = (Result * k)()
+    _check(lib().zts_search_batch(ctx, image, k, ptrs, ms, ns, st, out), "zts_search_batch")
+    return [r.as_dict() for r in out]
+
+
 def zts_debug_full_map(ctx, image: int, image_shape, tpl):
     tpl = _u8(tpl)
     Ly, Lx = image_shape[0] - tpl.shape[0] + 1, image_shape[1] - tpl.shape[1] + 1
@@ -329,6 +344,9 @@ class Searcher:
         if decision:
             return zts_search_decision(self.ctx, image, self.shapes[image], tpl, mode, p)
         return zts_search(self.ctx, image, tpl, mode, p)
+
+    def search_batch(self, image, tpls):
+        return zts_search_batch(self.ctx, image, tpls)
 
     def prep_image(self, image, m, n):
         return zts_prep_image(self.ctx, image, m, n, self.shapes[image])

@@ -1130,6 +1130,129 @@ zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_dev, int
     });
 }
 
+zts_status zts_search_batch(zts_ctx *z, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
+                            const int32_t *n, const int64_t *strides, zts_result *out)
+{
+    if (!z || !tpls || !m || !n || !strides || !out || count < 1)
+        return ZTS_E_ARG;
+    return guarded(&z->c, [&] {
+        Ctx *c = &z->c;
+        Image *im = find_image(c, image);
+        std::map<std::pair<int, int>, std::vector<int>> buckets;
+        for (int k = 0; k < count; k++) {
+            check_template_args(im, tpls[k], m[k], n[k], strides[k]);
+            buckets[std::make_pair(m[k], n[k])].push_back(k);
+        }
+        // stage every bucket's templates: [T][m][n16] with 0x80 past column n
+        struct Job {
+            int m, n, n16, T, Ly, Lx;
+            size_t off, tst_off, res_off, rec_off;
+            std::vector<int> idx;
+        };
+        std::vector<Job> jobs;
+        size_t tbytes = 0, nres = 0, nrec = 0;
+        for (auto &kv : buckets) {
+            Job j;
+            j.m = kv.first.first;
+            j.n = kv.first.second;
+            j.n16 = (j.n + 15) / 16 * 16;
+            j.T = (int)kv.second.size();
+            j.Ly = im->rows - j.m + 1;
+            j.Lx = im->cols - j.n + 1;
+            j.idx = kv.second;
+            j.off = tbytes;
+            tbytes += ((size_t)j.T * j.m * j.n16 + 255) / 256 * 256;
+            j.res_off = nres;
+            nres += j.T;
+            j.rec_off = nrec;
+            nrec += (size_t)((j.T + 15) / 16) * batch_blocks_per_tile(j.Ly, j.Lx) * 16;
+            jobs.push_back(j);
+        }
+        if (c->h_tpl_bytes < tbytes) {
+            if (c->h_tpl)
+                (void)hipHostFree(c->h_tpl);
+            c->h_tpl = nullptr;
+            hip_check(hipHostMalloc((void **)&c->h_tpl, tbytes, hipHostMallocDefault));
+            c->h_tpl_bytes = tbytes;
+        }
+        for (auto &j : jobs)
+            for (int t = 0; t < j.T; t++) {
+                int k = j.idx[t];
+                uint8_t *dst = c->h_tpl + j.off + (size_t)t * j.m * j.n16;
+                for (int r = 0; r < j.m; r++) {
+                    std::memcpy(dst + (size_t)r * j.n16, tpls[k] + (size_t)r * strides[k], j.n);
+                    std::memset(dst + (size_t)r * j.n16 + j.n, 0x80, j.n16 - j.n);
+                }
+            }
+        DBuf dt, dtst, dres, drec;
+        dalloc(c, dt, tbytes);
+        dalloc(c, dtst, sizeof(int64_t) * 2 * nres);
+        dalloc(c, dres, sizeof(RecPod) * nres);
+        dalloc(c, drec, sizeof(RecPod) * nrec);
+        hip_check(hipMemcpyAsync(dt.ptr, c->h_tpl, tbytes, hipMemcpyHostToDevice, c->stream));
+        std::vector<const int2 *> stats;
+        for (auto &j : jobs)
+            stats.push_back(stats_for(c, im, j.m, j.n));
+        hip_check(hipEventRecord(c->ev0, c->stream));
+        for (size_t q = 0; q < jobs.size(); q++) {
+            Job &j = jobs[q];
+            BatchArgs a;
+            std::memset(&a, 0, sizeof a);
+            a.img = im->img.as<uint8_t>();
+            a.pitch = im->pitch;
+            a.p = im->rows;
+            a.q = im->cols;
+            a.stat = stats[q];
+            a.tpl = dt.as<uint8_t>() + j.off;
+            a.tst = dtst.as<int64_t>() + 2 * j.res_off;
+            a.T = j.T;
+            a.m = j.m;
+            a.n = j.n;
+            a.Ly = j.Ly;
+            a.Lx = j.Lx;
+            a.recs = drec.as<RecPod>() + j.rec_off;
+            hip_check(launch_batch(a, dres.as<RecPod>() + j.res_off, c->stream));
+        }
+        hip_check(hipEventRecord(c->ev1, c->stream));
+        std::vector<RecPod> res(nres);
+        std::vector<int64_t> tst(2 * nres);
+        hip_check(hipMemcpyAsync(res.data(), dres.ptr, sizeof(RecPod) * nres, hipMemcpyDeviceToHost, c->stream));
+        hip_check(hipMemcpyAsync(tst.data(), dtst.ptr, sizeof(int64_t) * 2 * nres, hipMemcpyDeviceToHost, c->stream));
+        hip_check(hipStreamSynchronize(c->stream));
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        for (auto &j : jobs)
+            for (int t = 0; t < j.T; t++) {
+                const RecPod &f = res[j.res_off + t];
+                int64_t D_t = tst[2 * (j.res_off + t) + 1];
+                zts_result r;
+                std::memset(&r, 0, sizeof r);
+                int64_t L = (int64_t)j.Ly * j.Lx;
+                r.n_locations = L;
+                r.device_ms = ms;
+                r.phase_ms[0] = ms;
+                if (D_t == 0) {
+                    r.status = ZTS_E_DEGENERATE;
+                } else {
+                    r.y = (int32_t)(f.l / j.Lx);
+                    r.x = (int32_t)(f.l % j.Lx);
+                    r.rho = f.rho;
+                    r.rho32 = f.r32max;
+                    r.num = f.num;
+                    r.den_t = D_t;
+                    r.den_r = f.dr;
+                    r.n_computed = L;
+                    r.group_h = r.group_w = 1;
+                    r.best0 = f.rho;
+                    r.best0_y = r.y;
+                    r.best0_x = r.x;
+                    r.status = ZTS_OK;
+                }
+                out[j.idx[t]] = r;
+            }
+    });
+}
+
 zts_status zts_debug_full_map(zts_ctx *z, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
                               int64_t *num_out, int64_t *den_r_out, float *rho_out)
 {

@@ -134,6 +134,21 @@ struct BcArgs {
     int64_t *num_out, *dj_out, *di_out;
 };
 
+// Batch of up to many templates of one size on int8 MFMA.
+struct BatchArgs {
+    const uint8_t *img;
+    int64_t pitch;
+    int p, q;
+    const int2 *stat;     // per-location statistics for (m, n)
+    const uint8_t *tpl;   // uint8 templates, [T][m][n16], 0x80 past column n
+    int64_t *tst;         // per template: sum(t'), D_t (written by the launch)
+    int T, m, n, n16, Ly, Lx;
+    RecPod *recs;         // [tiles of 16 templates][blocks][16]
+};
+
+int batch_blocks_per_tile(int Ly, int Lx);
+hipError_t launch_batch(BatchArgs a, RecPod *results, hipStream_t s);
+
 enum { RD_BEST0 = 0, RD_WINDOW = 1, RD_FINAL = 2 };
 hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, int stage, int flag, double delta, hipStream_t s);
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);

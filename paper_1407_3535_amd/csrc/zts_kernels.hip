@@ -1062,6 +1062,165 @@ __global__ __launch_bounds__(256) void k_revert(const uint8_t *__restrict__ colm
         atomicAdd(counter, s);
 }
 
+// ============================================================== batched templates on int8 MFMA
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Template statistics of a batch: one block per template (layout [T][m][n16],
+// columns past n hold 0x80, i.e. int8 zero): tst[2t] = sum(t'), tst[2t+1] = D_t.
+__global__ __launch_bounds__(256) void k_tstats(const uint8_t *__restrict__ tpl, int m, int n, int n16,
+                                                int64_t *__restrict__ tst)
+{
+    __shared__ int red[8];
+    const uint8_t *tp = tpl + (int64_t)blockIdx.x * m * n16;
+    int s = 0, s2 = 0;
+    for (int idx = threadIdx.x; idx < m * n16; idx += 256) {
+        int v = (int)tp[idx] - 128;
+        s += v;
+        s2 += v * v;
+    }
+    int64_t S = block_sum_int(s, red), Q = block_sum_int(s2, red);
+    if (threadIdx.x == 0) {
+        tst[2 * blockIdx.x] = S;
+        tst[2 * blockIdx.x + 1] = (int64_t)m * n * Q - S * S;
+    }
+}
+
+// Cross-correlation of up to 16 templates of one size at every location as
+// an implicit GEMM on v_mfma_i32_16x16x64_i8: M = 16 locations of one row,
+// N = 16 templates, K = 64 = 4 consecutive image rows x 16 columns.  A wave
+// keeps R output rows x 4 M-tiles (64 columns) of int32 accumulators; each
+// realigned A fragment (image rows yy..yy+3) feeds the R output rows, each
+// with the template rows that line up with it.  Per 4-row step the block
+// stages the 4 image rows and the R+3 template rows they meet in LDS.  The
+// epilogue forms N, rho32 and a per-template band-argmax record per block.
+template <int R>
+__global__ __launch_bounds__(256) void k_batch(BatchArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int n16 = a.n16, nb16 = n16 >> 4;
+    const int WB = 256 + n16 + 16;  // image bytes per staged row
+    const int WW = WB >> 2;
+    const int TROWS = R + 3;
+    const int TBW = TROWS * 16 * n16 / 4;  // template words per step
+    uint32_t *imgl = smem;
+    uint32_t *tpll = smem + 4 * WW;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int x0 = blockIdx.x * 256, y0 = blockIdx.y * R, tz = blockIdx.z * 16;
+    const int steps = (R + a.m - 1 + 3) >> 2;
+    const uint32_t *tplg = (const uint32_t *)a.tpl;
+    const int nw16 = n16 >> 2;
+
+    v4i acc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+            acc[r][mt] = v4i{0, 0, 0, 0};
+
+    for (int s = 0; s < steps; s++) {
+        __syncthreads();
+        for (int idx = t; idx < 4 * WW; idx += 256) {
+            int g = idx / WW, c = idx - g * WW;
+            int gy = y0 + 4 * s + g;
+            int64_t gx = (int64_t)x0 + 4 * c;
+            uint32_t w = 0;
+            if (gy < a.p && gx + 4 <= a.pitch)
+                w = flip4(*(const uint32_t *)(a.img + (int64_t)gy * a.pitch + gx));
+            imgl[idx] = w;
+        }
+        for (int idx = t; idx < TBW; idx += 256) {
+            int j = idx / (16 * nw16);
+            int rem = idx - j * (16 * nw16);
+            int tt = rem / nw16, c4 = rem - tt * nw16;
+            int ti = 4 * s + j - (R - 1), tg = tz + tt;
+            uint32_t w = 0;
+            if (ti >= 0 && ti < a.m && tg < a.T)
+                w = flip4(tplg[((int64_t)tg * a.m + ti) * nw16 + c4]);
+            tpll[idx] = w;
+        }
+        __syncthreads();
+        const int g = lane >> 4, mrow = lane & 15;
+        for (int cb = 0; cb < nb16; cb++) {
+            v4i A[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++) {
+                int c = 64 * wv + 16 * mt + mrow + 16 * cb;
+                const uint32_t *rp = imgl + g * WW + (c >> 2);
+                uint32_t sh = (uint32_t)(c & 3);
+                uint32_t d0 = rp[0], d1 = rp[1], d2 = rp[2], d3 = rp[3], d4 = rp[4];
+                A[mt] = v4i{(int)bytes_at(d1, d0, sh), (int)bytes_at(d2, d1, sh), (int)bytes_at(d3, d2, sh),
+                            (int)bytes_at(d4, d3, sh)};
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                int j = g - r + R - 1;
+                v4i B = *(const v4i *)((const uint8_t *)tpll + ((j * 16 + mrow) * n16 + 16 * cb));
+#pragma unroll
+                for (int mt = 0; mt < 4; mt++)
+                    acc[r][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B, acc[r][mt], 0, 0, 0);
+            }
+        }
+    }
+
+    // epilogue: lane holds template tz + (lane & 15), locations rows y0 + r,
+    // columns x0 + 64 wv + 16 mt + 4 (lane >> 4) + v
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int tn = tz + (lane & 15);
+    int64_t St = 0, Dt = 0;
+    if (tn < a.T) {
+        St = a.tst[2 * tn];
+        Dt = a.tst[2 * tn + 1];
+    }
+    RecPod rec = rec_empty();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        int y = y0 + r;
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                int x = x0 + 64 * wv + 16 * mt + 4 * (lane >> 4) + v;
+                if (tn < a.T && Dt != 0 && y < a.Ly && x < a.Lx) {
+                    int64_t l = (int64_t)y * a.Lx + x;
+                    int2 stl = a.stat[l];
+                    int64_t dr = var_num(mn, stl);
+                    int64_t num = mn * (int64_t)acc[r][mt][v] - St * (int64_t)stl.x;
+                    rec_offer(rec, rho32(num, Dt, dr), l, num, Dt, dr);
+                }
+            }
+    }
+    __syncthreads();
+    RecPod *wr = (RecPod *)smem;
+    wr[t] = rec;
+    __syncthreads();
+    if (t < 16) {
+        RecPod b = rec_empty();
+        for (int w = 0; w < 4; w++)
+            for (int gg = 0; gg < 4; gg++)
+                rec_merge(b, wr[w * 64 + gg * 16 + t]);
+        int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        a.recs[(int64_t)bid * 16 + t] = b;
+    }
+}
+
+// One block per template: fold the template's block records into its answer.
+// The answer's r32max field is replaced by the binary32 rho of the answer.
+__global__ __launch_bounds__(256) void k_reduce_batch(const RecPod *__restrict__ recs, int blocks_per_tile,
+                                                      const int64_t *__restrict__ tst, RecPod *__restrict__ out)
+{
+    __shared__ RecPod rred[256];
+    int tmpl = blockIdx.x, z = tmpl >> 4, col = tmpl & 15;
+    RecPod r = rec_empty();
+    for (int b = threadIdx.x; b < blocks_per_tile; b += blockDim.x)
+        rec_merge(r, recs[((int64_t)z * blocks_per_tile + b) * 16 + col]);
+    RecPod f = block_rec(r, rred);
+    if (threadIdx.x == 0) {
+        f.r32max = f.valid ? rho32(f.num, tst[2 * tmpl + 1], f.dr) : 0.0f;
+        out[tmpl] = f;
+    }
+}
+
 // ============================================================== record reductions
 
 // One block folds a range of per-block records after the kernel that wrote
@@ -1266,6 +1425,26 @@ hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, in
                        colmask);
     hipLaunchKernelGGL(k_revert, dim3(blocks_for((int64_t)p * q, 256)), dim3(256), 0, s,
                        (const uint8_t *)colmask, p, q, Lx, n, I, J, pitch, counter);
+    return hipGetLastError();
+}
+
+
+static constexpr int kBatchR = 4;
+
+int batch_blocks_per_tile(int Ly, int Lx) { return (int)(blocks_for(Lx, 256) * blocks_for(Ly, kBatchR)); }
+
+hipError_t launch_batch(BatchArgs a, RecPod *results, hipStream_t s)
+{
+    a.n16 = (a.n + 15) / 16 * 16;
+    hipLaunchKernelGGL(k_tstats, dim3(a.T), dim3(256), 0, s, a.tpl, a.m, a.n, a.n16, a.tst);
+    int WB = 256 + a.n16 + 16;
+    size_t lds = (size_t)4 * WB + (size_t)(kBatchR + 3) * 16 * a.n16;
+    if (lds < 256 * sizeof(RecPod))
+        lds = 256 * sizeof(RecPod);
+    dim3 grid(blocks_for(a.Lx, 256), blocks_for(a.Ly, kBatchR), blocks_for(a.T, 16));
+    hipLaunchKernelGGL(k_batch<kBatchR>, grid, dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_reduce_batch, dim3(a.T), dim3(256), 0, s, (const RecPod *)a.recs,
+                       batch_blocks_per_tile(a.Ly, a.Lx), (const int64_t *)a.tst, results);
     return hipGetLastError();
 }
 

@@ -266,3 +266,45 @@ def test_workload2_full_size_sampled(S):
         assert (num[y, x], dr[y, x]) == (sub["num"], sub["den_r"])
         assert abs(rho32[y, x] - sub["rho"]) <= RHO32_TOL
     S.unload(i)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_batch_mfma_matches_oracle(S, seed):
+    """Mixed sizes (several templates per size, a 17-template group, ragged n) in one call."""
+    rng = np.random.default_rng(900 + seed)
+    img = aerial_image(150, 170, 60 + seed)
+    sizes = [(16, 16)] * 17 + [(32, 32)] * 3 + [(20, 36)] * 2 + [(48, 48), (7, 5), (64, 64)]
+    tpls = []
+    for k, (m, n) in enumerate(sizes):
+        t, _ = cut_template(img, m, n, 1000 * seed + k, 6.0)
+        tpls.append(t)
+    tpls.append(np.full((9, 9), 5, np.uint8))  # flat: per-template error
+    i = S.load(img)
+    res = S.search_batch(i, tpls)
+    for k, t in enumerate(tpls):
+        if k == len(tpls) - 1:
+            assert res[k]["status"] == -3
+            continue
+        o = O.full_search(img, t)
+        assert res[k]["status"] == 0
+        same_answer(res[k], o, f"batch template {k} {t.shape}")
+        assert res[k]["n_computed"] == o["n_locations"]
+    S.unload(i)
+
+
+def test_batch_mfma_workload4_sample(S):
+    """The 4096x4096 batched workload: a sample of its templates checked against the oracle."""
+    w = workload(4)
+    img = w["images"][0]
+    tpls = [t for t, _, _ in w["templates"]]
+    i = S.load(img)
+    res = S.search_batch(i, tpls)
+    for k in (0, 5, 17, 40, 63):
+        t, loc, _ = w["templates"][k]
+        assert (res[k]["y"], res[k]["x"]) == loc
+        y, x = loc
+        m, n = t.shape
+        # exact sums at the answer and rho against the oracle on the block
+        sub = O.full_search(img[y:y + m, x:x + n], t)
+        assert (res[k]["num"], res[k]["den_r"], res[k]["rho"]) == (sub["num"], sub["den_r"], sub["rho"])
+    S.unload(i)
