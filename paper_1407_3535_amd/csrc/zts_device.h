@@ -255,18 +255,22 @@ __device__ __forceinline__ void rec_merge(RecPod &a, const RecPod &b)
 // binary32 rho is within kEpsRho of the largest binary32 rho seen so far by
 // this owner.  The running maximum only grows, so every candidate within the
 // band of the final maximum is evaluated.
+__device__ __noinline__ void rec_offer_band(RecPod &r, int64_t l, int64_t num, int64_t dt, int64_t dr)
+{
+    double rho = rho64(num, dt, dr);
+    if (!r.valid || rec_better(rho, l, r.rho, r.l)) {
+        r.rho = rho;
+        r.l = l;
+        r.num = num;
+        r.dr = dr;
+        r.valid = 1;
+    }
+}
+
 __device__ __forceinline__ void rec_offer(RecPod &r, float r32, int64_t l, int64_t num, int64_t dt, int64_t dr)
 {
-    if (r32 >= r.r32max - kEpsRho) {
-        double rho = rho64(num, dt, dr);
-        if (!r.valid || rec_better(rho, l, r.rho, r.l)) {
-            r.rho = rho;
-            r.l = l;
-            r.num = num;
-            r.dr = dr;
-            r.valid = 1;
-        }
-    }
+    if (r32 >= r.r32max - kEpsRho)
+        rec_offer_band(r, l, num, dt, dr);
     r.r32max = fmaxf(r.r32max, r32);
 }
 

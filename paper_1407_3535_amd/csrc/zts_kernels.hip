@@ -1094,22 +1094,43 @@ __global__ __launch_bounds__(256) void k_tstats(const uint8_t *__restrict__ tpl,
 // with the template rows that line up with it.  Per 4-row step the block
 // stages the 4 image rows and the R+3 template rows they meet in LDS.  The
 // epilogue forms N, rho32 and a per-template band-argmax record per block.
+// Epilogue LDS (dwords): S' and 1/sqrt(D_r) per location of the block (R x
+// 256 each), 64 block maxima, the candidate counter, then the candidate list
+// (4 dwords each) and its binary64 results (6 dwords each).
+constexpr int kBatchRows = 8;
+constexpr int kBatchCandCap = 512;
+constexpr int kBatchEpiList = 2 * kBatchRows * 256 + 68;
+constexpr int kBatchEpiWords = kBatchEpiList + 4 * kBatchCandCap + 6 * kBatchCandCap;
+static_assert(kBatchEpiList % 4 == 0, "candidate list is 16-byte aligned");
+
+// Dword stride of one template row in the LDS ring: an odd number of 16-byte
+// units, so the 16 lanes of a B-fragment read (16 templates, one row) fall
+// on distinct banks.
+__host__ __device__ inline int batch_tstride(int nw16) { return ((nw16 >> 2) & 1) ? nw16 : nw16 + 4; }
+
+// Dword stride of one byte-shifted image row copy: 8 mod 16, so the 16 lanes
+// of an A-fragment read (4 copies x 4 consecutive words, 2 dwords each) and
+// the next 16 lanes (next row, 4 strides on) fall on distinct banks.
+__host__ __device__ inline int batch_copy_stride(int ww) { return ww + ((8 - ww) & 15); }
+
 template <int R>
-__global__ __launch_bounds__(256) void k_batch(BatchArgs a)
+__global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a)
 {
+    static_assert(R + 3 + 4 <= 16, "template ring holds 16 rows");
+    static_assert(R == kBatchRows, "epilogue LDS layout is sized for kBatchRows");
     extern __shared__ __align__(16) uint32_t smem[];
-    const int n16 = a.n16, nb16 = n16 >> 4;
-    const int WB = 256 + n16 + 16;  // image bytes per staged row
-    const int WW = WB >> 2;
-    const int TROWS = R + 3;
-    const int TBW = TROWS * 16 * n16 / 4;  // template words per step
-    uint32_t *imgl = smem;
-    uint32_t *tpll = smem + 4 * WW;
+    constexpr int TNEW = (4 * 16 * 32 + 255) / 256;  // new template words per thread and step, n16 <= 128
+    const int n16 = a.n16, nb16 = n16 >> 4, nw16 = n16 >> 2;
+    const int WW = (256 + n16 + 16) >> 2;  // dwords per staged image row
+    const int CS = batch_copy_stride(WW);  // dwords per (row, byte shift) copy
+    const int IMGW = 16 * CS;              // [4 rows][4 byte shifts][CS]
+    const int tstr = batch_tstride(nw16);
+    uint32_t *ring = smem + 2 * IMGW;      // 16 template rows x 16 templates x tstr; row ti in slot (ti + R - 1) & 15
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int x0 = blockIdx.x * 256, y0 = blockIdx.y * R, tz = blockIdx.z * 16;
     const int steps = (R + a.m - 1 + 3) >> 2;
     const uint32_t *tplg = (const uint32_t *)a.tpl;
-    const int nw16 = n16 >> 2;
+    const int rowwords = 16 * nw16;      // words of one template row across the 16 templates (global)
 
     v4i acc[R][4];
 #pragma unroll
@@ -1118,53 +1139,125 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a)
         for (int mt = 0; mt < 4; mt++)
             acc[r][mt] = v4i{0, 0, 0, 0};
 
-    for (int s = 0; s < steps; s++) {
-        __syncthreads();
-        for (int idx = t; idx < 4 * WW; idx += 256) {
-            int g = idx / WW, c = idx - g * WW;
-            int gy = y0 + 4 * s + g;
-            int64_t gx = (int64_t)x0 + 4 * c;
-            uint32_t w = 0;
-            if (gy < a.p && gx + 4 <= a.pitch)
-                w = flip4(*(const uint32_t *)(a.img + (int64_t)gy * a.pitch + gx));
-            imgl[idx] = w;
-        }
-        for (int idx = t; idx < TBW; idx += 256) {
-            int j = idx / (16 * nw16);
-            int rem = idx - j * (16 * nw16);
+    // this thread's share of the 4 new template rows of a step: (row q, template tt, word c4)
+    int tq[TNEW], toff[TNEW], tdst[TNEW];
+#pragma unroll
+    for (int k = 0; k < TNEW; k++) {
+        int idx = t + 256 * k;
+        tq[k] = -1;
+        toff[k] = 0;
+        tdst[k] = 0;
+        if (idx < 4 * rowwords) {
+            int q = idx / rowwords, rem = idx - q * rowwords;
             int tt = rem / nw16, c4 = rem - tt * nw16;
-            int ti = 4 * s + j - (R - 1), tg = tz + tt;
-            uint32_t w = 0;
-            if (ti >= 0 && ti < a.m && tg < a.T)
-                w = flip4(tplg[((int64_t)tg * a.m + ti) * nw16 + c4]);
-            tpll[idx] = w;
+            tdst[k] = tt * tstr + c4;
+            if (tz + tt < a.T) {
+                tq[k] = q;
+                toff[k] = (tz + tt) * a.m * nw16 + c4;
+            }
         }
-        __syncthreads();
-        const int g = lane >> 4, mrow = lane & 15;
+    }
+    uint32_t ri[2][2];
+    uint32_t rt[TNEW];
+    auto gload = [&](int s) {
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            int idx = t + 256 * k;
+            ri[k][0] = ri[k][1] = 0x80808080u;
+            if (idx < 4 * WW) {
+                int g = idx / WW, w = idx - g * WW;
+                int gy = y0 + 4 * s + g;
+                int64_t gx = (int64_t)x0 + 4 * w;
+                if (gy < a.p) {
+                    const uint8_t *rp = a.img + (int64_t)gy * a.pitch;
+                    if (gx + 4 <= a.pitch)
+                        ri[k][0] = *(const uint32_t *)(rp + gx);
+                    if (gx + 8 <= a.pitch)
+                        ri[k][1] = *(const uint32_t *)(rp + gx + 4);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TNEW; k++) {
+            rt[k] = 0;
+            int ti = 4 * s + tq[k];
+            if (tq[k] >= 0 && ti < a.m)
+                rt[k] = flip4(tplg[toff[k] + (int64_t)ti * nw16]);
+        }
+    };
+    // image buffer of step s at smem + (s & 1) * IMGW (offsets, not a pointer
+    // table, so the accesses stay LDS instructions)
+    auto lstore = [&](int s) {
+        uint32_t *b = smem + (s & 1) * IMGW;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            int idx = t + 256 * k;
+            if (idx < 4 * WW) {
+                int g = idx / WW, w = idx - g * WW;
+                uint32_t lo = flip4(ri[k][0]), hi = flip4(ri[k][1]);
+                b[(g * 4 + 0) * CS + w] = lo;
+                b[(g * 4 + 1) * CS + w] = bytes_at(hi, lo, 1);
+                b[(g * 4 + 2) * CS + w] = bytes_at(hi, lo, 2);
+                b[(g * 4 + 3) * CS + w] = bytes_at(hi, lo, 3);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TNEW; k++) {
+            int idx = t + 256 * k;
+            if (idx < 4 * rowwords) {
+                int q = idx / rowwords;
+                int slot = (4 * s + q + R - 1) & 15;
+                ring[slot * 16 * tstr + tdst[k]] = rt[k];
+            }
+        }
+    };
+
+    // template rows before row 0 read as zero
+    for (int idx = t; idx < 16 * 16 * tstr; idx += 256)
+        ring[idx] = 0;
+    __syncthreads();
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    const int g = lane >> 4, mrow = lane & 15;
+    for (int s = 0; s < steps; s++) {
+        const uint32_t *cur = smem + (s & 1) * IMGW;
+        if (s + 1 < steps)
+            gload(s + 1);
+        const int slot0 = 4 * s + g + R - 1;  // slot of template row 4s + g - r is (slot0 - r) & 15
         for (int cb = 0; cb < nb16; cb++) {
             v4i A[4];
 #pragma unroll
             for (int mt = 0; mt < 4; mt++) {
+                // 16 image bytes at column c: copy (c & 3) holds them 4-byte aligned
                 int c = 64 * wv + 16 * mt + mrow + 16 * cb;
-                const uint32_t *rp = imgl + g * WW + (c >> 2);
-                uint32_t sh = (uint32_t)(c & 3);
-                uint32_t d0 = rp[0], d1 = rp[1], d2 = rp[2], d3 = rp[3], d4 = rp[4];
-                A[mt] = v4i{(int)bytes_at(d1, d0, sh), (int)bytes_at(d2, d1, sh), (int)bytes_at(d3, d2, sh),
-                            (int)bytes_at(d4, d3, sh)};
+                __builtin_memcpy(&A[mt], cur + (g * 4 + (c & 3)) * CS + (c >> 2), 16);
             }
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                int j = g - r + R - 1;
-                v4i B = *(const v4i *)((const uint8_t *)tpll + ((j * 16 + mrow) * n16 + 16 * cb));
+                int slot = (slot0 - r) & 15;
+                v4i B = *(const v4i *)((const uint8_t *)(ring + (slot * 16 + mrow) * tstr) + 16 * cb);
 #pragma unroll
                 for (int mt = 0; mt < 4; mt++)
                     acc[r][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B, acc[r][mt], 0, 0, 0);
             }
         }
+        if (s + 1 < steps)
+            lstore(s + 1);
+        __syncthreads();
     }
 
-    // epilogue: lane holds template tz + (lane & 15), locations rows y0 + r,
-    // columns x0 + 64 wv + 16 mt + 4 (lane >> 4) + v
+    // Epilogue.  Lane holds template tz + (lane & 15) at rows y0 + r and
+    // columns x0 + 64 wv + 16 mt + 4 (lane >> 4) + v.
+    //  pass 0: per location of the block, S' and 1 / sqrt(D_r) into LDS
+    //          (NaN marks a location past the map, 0 a flat block);
+    //  pass 1: est = N / sqrt(D_t D_r) in binary32 from the exact N (binary64
+    //          fma of exact products, |N| < 2^44); block maximum per template;
+    //  pass 2: pairs with est >= max - kEpsRho go to an LDS candidate list;
+    //  then the candidates' canonical binary64 rho picks each template's best.
+    // est is within 5e-7 of rho, so the exact best of the block is always a
+    // candidate.  A list overflow (many near-equal values, e.g. flat images)
+    // falls back to the streaming band selection over every pair.
     const int64_t mn = (int64_t)a.m * a.n;
     const int tn = tz + (lane & 15);
     int64_t St = 0, Dt = 0;
@@ -1172,23 +1265,136 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a)
         St = a.tst[2 * tn];
         Dt = a.tst[2 * tn + 1];
     }
-    RecPod rec = rec_empty();
+    const float qnan = __int_as_float(0x7fc00000);
+    int *sxs = (int *)smem;                              // [R][256]
+    float *irss = (float *)(smem + R * 256);             // [R][256]
+    float *bmx = (float *)(smem + 2 * R * 256);          // [4 waves][16 templates]
+    int *ccnt = (int *)(smem + 2 * R * 256 + 64);
+    int4 *clist = (int4 *)(smem + kBatchEpiList);        // (template, location in block, acc, 0)
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        int y = y0 + r;
+        int y = y0 + r, x = x0 + t, sx = 0;
+        float ir = qnan;
+        if (y < a.Ly && x < a.Lx) {
+            int2 st = a.stat[(int64_t)y * a.Lx + x];
+            int64_t dr = var_num(mn, st);
+            sx = st.x;
+            ir = dr > 0 ? 1.0f / sqrtf((float)dr) : 0.0f;
+        }
+        sxs[r * 256 + t] = sx;
+        irss[r * 256 + t] = ir;
+    }
+    if (t == 0)
+        *ccnt = 0;
+    __syncthreads();
+    const bool tok = tn < a.T && Dt != 0;
+    const double nst = -(double)St, mnd = (double)mn;
+    const float irt = tok ? 1.0f / sqrtf((float)Dt) : qnan;
+    auto est_of = [&](int accv, int sx, float ir) -> float {
+        double nd = fma(mnd, (double)accv, nst * (double)sx);
+        return (float)nd * ir * irt;
+    };
+    const int g4 = lane >> 4;
+    float bm = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            int li = r * 256 + 64 * wv + 16 * mt + 4 * g4;
+            int4 sx4 = *(const int4 *)(sxs + li);
+            float4 ir4 = *(const float4 *)(irss + li);
+            bm = fmaxf(bm, est_of(acc[r][mt][0], sx4.x, ir4.x));
+            bm = fmaxf(bm, est_of(acc[r][mt][1], sx4.y, ir4.y));
+            bm = fmaxf(bm, est_of(acc[r][mt][2], sx4.z, ir4.z));
+            bm = fmaxf(bm, est_of(acc[r][mt][3], sx4.w, ir4.w));
+        }
+    bm = fmaxf(bm, __shfl_xor(bm, 16));
+    bm = fmaxf(bm, __shfl_xor(bm, 32));
+    if (lane < 16)
+        bmx[wv * 16 + lane] = bm;
+    __syncthreads();
+    const int tl = lane & 15;
+    const float thr = fmaxf(fmaxf(bmx[tl], bmx[16 + tl]), fmaxf(bmx[32 + tl], bmx[48 + tl])) - kEpsRho;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++) {
+            int li = r * 256 + 64 * wv + 16 * mt + 4 * g4;
+            int4 sx4 = *(const int4 *)(sxs + li);
+            float4 ir4 = *(const float4 *)(irss + li);
+            int sxv[4] = {sx4.x, sx4.y, sx4.z, sx4.w};
+            float irv[4] = {ir4.x, ir4.y, ir4.z, ir4.w};
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                if (est_of(acc[r][mt][v], sxv[v], irv[v]) >= thr) {
+                    int k = atomicAdd(ccnt, 1);
+                    if (k < kBatchCandCap)
+                        clist[k] = make_int4(tl, li + v, acc[r][mt][v], 0);
+                }
+        }
+    __syncthreads();
+    const int ncand = *ccnt;
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (ncand <= kBatchCandCap) {
+        double *crho = (double *)(smem + kBatchEpiList + 4 * kBatchCandCap);
+        int64_t *cnum = (int64_t *)(crho + kBatchCandCap);
+        int64_t *cdr = cnum + kBatchCandCap;
+        for (int e = t; e < ncand; e += 256) {
+            int4 c = clist[e];
+            int tg = tz + c.x;
+            int64_t l = (int64_t)(y0 + (c.y >> 8)) * a.Lx + x0 + (c.y & 255);
+            int2 st = a.stat[l];
+            int64_t dr = var_num(mn, st);
+            int64_t num = mn * (int64_t)c.z - a.tst[2 * tg] * (int64_t)st.x;
+            crho[e] = rho64(num, a.tst[2 * tg + 1], dr);
+            cnum[e] = num;
+            cdr[e] = dr;
+        }
+        __syncthreads();
+        if (t < 16) {
+            RecPod b = rec_empty();
+            for (int e = 0; e < ncand; e++) {
+                int4 c = clist[e];
+                if (c.x != t)
+                    continue;
+                int64_t l = (int64_t)(y0 + (c.y >> 8)) * a.Lx + x0 + (c.y & 255);
+                if (!b.valid || rec_better(crho[e], l, b.rho, b.l)) {
+                    b.rho = crho[e];
+                    b.l = l;
+                    b.num = cnum[e];
+                    b.dr = cdr[e];
+                    b.valid = 1;
+                }
+            }
+            a.recs[(int64_t)bid * 16 + t] = b;
+        }
+        return;
+    }
+
+    // overflow: streaming band selection over every pair, one output row at a
+    // time through this wave's LDS slice
+    RecPod rec = rec_empty();
+    int *slice = (int *)smem + wv * 16 * 64;  // 16 values x 64 lanes per wave
+#pragma unroll
+    for (int r = 0; r < R; r++) {
 #pragma unroll
         for (int mt = 0; mt < 4; mt++)
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                int x = x0 + 64 * wv + 16 * mt + 4 * (lane >> 4) + v;
-                if (tn < a.T && Dt != 0 && y < a.Ly && x < a.Lx) {
-                    int64_t l = (int64_t)y * a.Lx + x;
-                    int2 stl = a.stat[l];
-                    int64_t dr = var_num(mn, stl);
-                    int64_t num = mn * (int64_t)acc[r][mt][v] - St * (int64_t)stl.x;
-                    rec_offer(rec, rho32(num, Dt, dr), l, num, Dt, dr);
-                }
+            for (int v = 0; v < 4; v++)
+                slice[(mt * 4 + v) * 64 + lane] = acc[r][mt][v];
+        int y = y0 + r;
+#pragma unroll 1
+        for (int e = 0; e < 16; e++) {
+            int mt = e >> 2, v = e & 3;
+            int x = x0 + 64 * wv + 16 * mt + 4 * g4 + v;
+            if (tok && y < a.Ly && x < a.Lx) {
+                int64_t l = (int64_t)y * a.Lx + x;
+                int2 stl = a.stat[l];
+                int64_t dr = var_num(mn, stl);
+                int64_t num = mn * (int64_t)slice[e * 64 + lane] - St * (int64_t)stl.x;
+                rec_offer(rec, rho32(num, Dt, dr), l, num, Dt, dr);
             }
+        }
     }
     __syncthreads();
     RecPod *wr = (RecPod *)smem;
@@ -1199,7 +1405,6 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a)
         for (int w = 0; w < 4; w++)
             for (int gg = 0; gg < 4; gg++)
                 rec_merge(b, wr[w * 64 + gg * 16 + t]);
-        int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
         a.recs[(int64_t)bid * 16 + t] = b;
     }
 }
@@ -1429,7 +1634,7 @@ hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, in
 }
 
 
-static constexpr int kBatchR = 4;
+static constexpr int kBatchR = kBatchRows;
 
 int batch_blocks_per_tile(int Ly, int Lx) { return (int)(blocks_for(Lx, 256) * blocks_for(Ly, kBatchR)); }
 
@@ -1437,10 +1642,14 @@ hipError_t launch_batch(BatchArgs a, RecPod *results, hipStream_t s)
 {
     a.n16 = (a.n + 15) / 16 * 16;
     hipLaunchKernelGGL(k_tstats, dim3(a.T), dim3(256), 0, s, a.tpl, a.m, a.n, a.n16, a.tst);
-    int WB = 256 + a.n16 + 16;
-    size_t lds = (size_t)4 * WB + (size_t)(kBatchR + 3) * 16 * a.n16;
+    if (a.n16 > 128)
+        return hipErrorInvalidValue;
+    int WW = (256 + a.n16 + 16) / 4;
+    size_t lds = ((size_t)2 * 16 * batch_copy_stride(WW) + (size_t)16 * 16 * batch_tstride(a.n16 / 4)) * 4;
     if (lds < 256 * sizeof(RecPod))
         lds = 256 * sizeof(RecPod);
+    if (lds < (size_t)kBatchEpiWords * 4)
+        lds = (size_t)kBatchEpiWords * 4;
     dim3 grid(blocks_for(a.Lx, 256), blocks_for(a.Ly, kBatchR), blocks_for(a.T, 16));
     hipLaunchKernelGGL(k_batch<kBatchR>, grid, dim3(256), lds, s, a);
     hipLaunchKernelGGL(k_reduce_batch, dim3(a.T), dim3(256), 0, s, (const RecPod *)a.recs,

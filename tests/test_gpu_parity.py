@@ -308,3 +308,46 @@ def test_batch_mfma_workload4_sample(S):
         sub = O.full_search(img[y:y + m, x:x + n], t)
         assert (res[k]["num"], res[k]["den_r"], res[k]["rho"]) == (sub["num"], sub["den_r"], sub["rho"])
     S.unload(i)
+
+
+@pytest.mark.parametrize("period", [8, 4])
+def test_batch_mfma_ties(S, period):
+    """A periodic image: every template matches exactly at many locations, so
+    the answer is the smallest-index tie.  Period 8 keeps a block's candidate
+    list within its capacity; period 4 overflows it and takes the streaming
+    fallback."""
+    rng = np.random.default_rng(31 + period)
+    base = rng.integers(0, 256, (period, period), dtype=np.uint8)
+    img = np.ascontiguousarray(np.tile(base, (300 // period + 1, 600 // period + 1))[:300, :600])
+    tpls = []
+    for k in range(18):
+        m, n = (16, 16) if k < 16 else (24, 40)
+        y, x = rng.integers(0, 300 - m), rng.integers(0, 600 - n)
+        tpls.append(np.ascontiguousarray(img[y:y + m, x:x + n]))
+    i = S.load(img)
+    res = S.search_batch(i, tpls)
+    for k, t in enumerate(tpls):
+        o = O.full_search(img, t)
+        same_answer(res[k], o, f"periodic {period} template {k}")
+    S.unload(i)
+
+
+def test_batch_mfma_flat_regions(S):
+    """Flat image regions (rho := 0 there): a fully flat image, where every
+    location ties at 0, and an image flat on its left half."""
+    rng = np.random.default_rng(77)
+    flat = np.full((120, 400), 93, np.uint8)
+    half = aerial_image(120, 400, 5)
+    half[:, :200] = 40
+    for img in (flat, half):
+        tpls = [cut_template(aerial_image(120, 400, 6), 16, 16, k, 4.0)[0] for k in range(16)]
+        tpls.append(np.ascontiguousarray(img[10:42, 180:212]))  # flat on the flat image
+        i = S.load(img)
+        res = S.search_batch(i, tpls)
+        for k, t in enumerate(tpls):
+            if t.min() == t.max():
+                assert res[k]["status"] == -3
+                continue
+            o = O.full_search(img, t)
+            same_answer(res[k], o, f"flat-region template {k}")
+        S.unload(i)
