@@ -29,7 +29,9 @@
  *     returns ZTS_E_SIZE; a template with zero variance returns
  *     ZTS_E_DEGENERATE.  Nothing is written to outputs on error.
  *   - A `void* stream` is a hipStream_t (NULL = the context's own stream).
- *   - Calls on one context are serialised by the context (thread safe).
+ *   - Every entry point is thread safe.  Synchronous calls on one context are
+ *     serialised; submitted requests run concurrently on the context's worker
+ *     slots (see "serving" below).
  */
 #ifndef ZTS_H
 #define ZTS_H
@@ -38,6 +40,12 @@
 
 #ifdef __cplusplus
 extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ZTS_API __attribute__((visibility("default")))
+#else
+#define ZTS_API
 #endif
 
 typedef struct zts_ctx zts_ctx;
@@ -60,7 +68,10 @@ typedef enum {
 
 /* Search modes.
  *   ZTS_FULL      every location computed (Eq. 1 everywhere); the plain
- *                 baseline.
+ *                 baseline (one template per launch, v_dot4 on the VALU).
+ *   ZTS_FULL_MFMA every location computed, as an implicit GEMM on int8 MFMA
+ *                 (v_mfma_i32_16x16x64_i8, int32 accumulation); templates
+ *                 submitted together share launches.  n <= 128.
  *   ZTS_TE_FIXED  transitive elimination with a caller-given group size
  *                 (section II; the earlier algorithm's user parameter).
  *   ZTS_EGS       transitive elimination with the group size chosen by
@@ -71,11 +82,15 @@ typedef enum {
  *                 original location through the triangle inequality on
  *                 angles (Eq. 2 with Prop. 4.3's blur correlation added), so
  *                 the result is still exact. */
-typedef enum { ZTS_FULL = 0, ZTS_TE_FIXED = 2, ZTS_EGS = 3, ZTS_OPTA = 4 } zts_mode;
+typedef enum { ZTS_FULL = 0, ZTS_FULL_MFMA = 1, ZTS_TE_FIXED = 2, ZTS_EGS = 3, ZTS_OPTA = 4 } zts_mode;
 
 typedef struct {
     int32_t device;            /* HIP device ordinal */
     uint64_t hbm_budget_bytes; /* cap on the library's device allocations, 0 = none */
+    int32_t max_inflight;      /* serving: worker slots, i.e. launches on the device at once (one
+                                  stream each), 0 = 4, at most 64 */
+    int32_t max_queued;        /* serving: submitted requests not yet started beyond which
+                                  zts_submit returns ZTS_E_AGAIN, 0 = 4096 */
 } zts_ctx_params;
 
 /* Method parameters; zts_params_default fills the paper's values. */
@@ -116,9 +131,13 @@ typedef struct {
     float device_ms;         /* device time of the search (HIP events) */
     zts_status status;
     float phase_ms[4];       /* device time per kernel, HIP events on the library's stream:
-                                ZTS_FULL: [0] dense kernel; other modes: [0] scan 1 (centres),
-                                [1] refinement window, [2] scan 2 (members and survivors);
-                                [3] the one-block record reductions between them */
+                                ZTS_FULL: [0] dense kernel; ZTS_FULL_MFMA: [0] the batched launch;
+                                other modes: [0] scan 1 (centres), [1] refinement window,
+                                [2] scan 2 (members and survivors); [3] the one-block record
+                                reductions between them */
+    float latency_ms;        /* submitted requests: submission to result ready (host clock) */
+    float queue_ms;          /* submitted requests: submission to the start of its launch */
+    int32_t batch_size;      /* templates in the launch that produced this result */
     int32_t pad1;
 } zts_result;
 
@@ -150,31 +169,31 @@ typedef struct {
 /* ---- context ----------------------------------------------------------- */
 
 /* Fills *p with the paper's parameters. */
-void zts_params_default(zts_params *p);
+ZTS_API void zts_params_default(zts_params *p);
 
 /* Creates a context on params->device (NULL params: device 0, no budget). */
-zts_status zts_create(const zts_ctx_params *params, zts_ctx **out);
+ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out);
 
 /* Waits for outstanding work and frees every device buffer of the context. */
-void zts_destroy(zts_ctx *ctx);
+ZTS_API void zts_destroy(zts_ctx *ctx);
 
 /* Static text for a status code. */
-const char *zts_status_str(zts_status s);
+ZTS_API const char *zts_status_str(zts_status s);
 
 /* ---- images ------------------------------------------------------------ */
 
 /* Copies a host image to the device and builds its running sums (the
  * Run-Sum of section III-A / Alg. 3) of x-128 and (x-128)^2.  *id receives
  * a handle.  ZTS_E_BUDGET when the copy would exceed the HBM budget. */
-zts_status zts_image_load(zts_ctx *ctx, const uint8_t *host, int32_t rows, int32_t cols, int64_t stride,
+ZTS_API zts_status zts_image_load(zts_ctx *ctx, const uint8_t *host, int32_t rows, int32_t cols, int64_t stride,
                           int32_t *id);
 
 /* Same from device memory (copied device-to-device on `stream`). */
-zts_status zts_image_load_device(zts_ctx *ctx, const void *dev, int32_t rows, int32_t cols, int64_t stride,
+ZTS_API zts_status zts_image_load_device(zts_ctx *ctx, const void *dev, int32_t rows, int32_t cols, int64_t stride,
                                  void *stream, int32_t *id);
 
 /* Frees an image and everything prepared for it. */
-zts_status zts_image_unload(zts_ctx *ctx, int32_t id);
+ZTS_API zts_status zts_image_unload(zts_ctx *ctx, int32_t id);
 
 /* ---- preparation ------------------------------------------------------- */
 
@@ -185,27 +204,27 @@ zts_status zts_image_unload(zts_ctx *ctx, int32_t id);
  * conditioned image of Alg. 3 with the angle of every blurred block to its
  * original.  ZTS_FULL needs no preparation.  Searches prepare on demand;
  * calling this first keeps preparation out of the search time. */
-zts_status zts_prepare(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, const zts_params *params,
+ZTS_API zts_status zts_prepare(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, const zts_params *params,
                        void *stream);
 
 /* Reports what zts_prepare decided (group size, EGS and OptA traces). */
-zts_status zts_prep_query(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, zts_prep_info *out);
+ZTS_API zts_status zts_prep_query(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, zts_prep_info *out);
 
 /* Copies the conditioned image of a ZTS_OPTA preparation to host memory
  * (rows*cols bytes, pitch cols). */
-zts_status zts_prep_image(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, uint8_t *host_out);
+ZTS_API zts_status zts_prep_image(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, uint8_t *host_out);
 
 /* ---- search ------------------------------------------------------------ */
 
 /* Synchronous search of one host template.  `decision` (nullable, one byte
  * per location) receives 1 for a scan-1 centre, 3 for a refinement-window
  * location, 2 for a survivor, 0 for an eliminated location (ZTS_FULL: all 2). */
-zts_status zts_search(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
+ZTS_API zts_status zts_search(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
                       zts_mode mode, const zts_params *params, zts_result *out, int8_t *decision);
 
 /* Same with the template already in device memory; work is enqueued on
  * `stream` and the call returns when the result is on the host. */
-zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tpl_dev, int32_t m, int32_t n,
+ZTS_API zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tpl_dev, int32_t m, int32_t n,
                              int64_t stride, zts_mode mode, const zts_params *params, void *stream,
                              zts_result *out);
 
@@ -219,24 +238,73 @@ zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tpl_dev, i
  * out[k].status = ZTS_E_DEGENERATE while the call returns ZTS_OK.  Counts:
  * every location computed.  device_ms of every entry is the device time of
  * the whole call. */
-zts_status zts_search_batch(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
+ZTS_API zts_status zts_search_batch(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
                             const int32_t *n, const int64_t *strides, zts_result *out);
+
+/* ---- serving ------------------------------------------------------------ */
+
+/* Asynchronous requests.  The context runs max_inflight worker slots, each
+ * with its own HIP stream and scratch; requests start in submission order as
+ * slots become free, so work admitted while other work runs overlaps with it
+ * on the device.  A worker that starts a ZTS_FULL_MFMA request also takes
+ * every other queued ZTS_FULL_MFMA request (any image, any size, up to 64
+ * templates) into the same fused batched launch.  Other modes run one request
+ * per launch and prepare on demand (ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA).
+ *
+ * Device memory: a launch's scratch and the per-size tables it needs are
+ * charged against hbm_budget_bytes.  When they do not fit, cached tables that
+ * no running work holds are freed, least recently used first; if that is not
+ * enough the request goes back to the head of the queue and starts when
+ * running work completes and releases memory.  It fails with ZTS_E_BUDGET
+ * only when nothing else runs.
+ *
+ * Each result equals that of the synchronous call with the same inputs (same
+ * location, integers and binary64 rho), alone or in any mix. */
+
+/* Copies the template, queues the request and returns its ticket.
+ * ZTS_E_AGAIN when max_queued requests wait already; argument errors as for
+ * zts_search (ZTS_FULL_MFMA also needs n <= 128). */
+ZTS_API zts_status zts_submit(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
+                      zts_mode mode, const zts_params *params, uint64_t *ticket);
+
+/* Queues `count` templates (all or none); tickets first_ticket ..
+ * first_ticket + count - 1 in order. */
+ZTS_API zts_status zts_submit_batch(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls,
+                            const int32_t *m, const int32_t *n, const int64_t *strides, zts_mode mode,
+                            const zts_params *params, uint64_t *first_ticket);
+
+/* ZTS_E_AGAIN while the request is queued or running.  Once it has ended,
+ * writes its result to *out, forgets the ticket and returns the request's
+ * status (ZTS_OK, or e.g. ZTS_E_DEGENERATE, ZTS_E_CANCELLED, ZTS_E_BUDGET).
+ * An unknown or already collected ticket gives ZTS_E_ARG. */
+ZTS_API zts_status zts_poll(zts_ctx *ctx, uint64_t ticket, zts_result *out);
+
+/* As zts_poll, blocking up to timeout_ns (negative: no limit);
+ * ZTS_E_TIMEOUT leaves the ticket valid. */
+ZTS_API zts_status zts_wait(zts_ctx *ctx, uint64_t ticket, int64_t timeout_ns, zts_result *out);
+
+/* Cancels a request that has not started: it ends with ZTS_E_CANCELLED (still
+ * to be collected).  ZTS_E_BUSY once it has started or ended. */
+ZTS_API zts_status zts_cancel(zts_ctx *ctx, uint64_t ticket);
+
+/* Requests waiting in the queue and worker slots executing work right now. */
+ZTS_API zts_status zts_pending(zts_ctx *ctx, int32_t *queued, int32_t *running);
 
 /* ---- parity helpers ------------------------------------------------------ */
 
 /* Every location's exact N and D_r and binary32 rho for one template
  * (ZTS_FULL kernel with its maps written out).  Any output may be NULL. */
-zts_status zts_debug_full_map(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n,
+ZTS_API zts_status zts_debug_full_map(zts_ctx *ctx, int32_t image, const uint8_t *tpl, int32_t m, int32_t n,
                               int64_t stride, int64_t *num_out, int64_t *den_r_out, float *rho_out);
 
 /* Alg. 1 on the device: for group size (h, w), every location's exact
  * N_co, D_c and D_o against its group centre (int64 arrays of L entries). */
-zts_status zts_debug_autocorr(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, int32_t h, int32_t w,
+ZTS_API zts_status zts_debug_autocorr(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, int32_t h, int32_t w,
                               int64_t *num_out, int64_t *dc_out, int64_t *do_out);
 
 /* Eq. 18 on the device: blurs a host image with separable integer taps
  * (2d+1 of them), clamp-to-edge borders, rounded half up. */
-zts_status zts_debug_blur(zts_ctx *ctx, const uint8_t *host_in, int32_t rows, int32_t cols, const int32_t *taps,
+ZTS_API zts_status zts_debug_blur(zts_ctx *ctx, const uint8_t *host_in, int32_t rows, int32_t cols, const int32_t *taps,
                           int32_t d, uint8_t *host_out);
 
 #ifdef __cplusplus

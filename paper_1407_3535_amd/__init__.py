@@ -27,8 +27,8 @@ except Exception:  # pragma: no cover
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzts.so")
 
-ZTS_FULL, ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA = 0, 2, 3, 4
-MODES = {"full": ZTS_FULL, "te_fixed": ZTS_TE_FIXED, "egs": ZTS_EGS, "opta": ZTS_OPTA}
+ZTS_FULL, ZTS_FULL_MFMA, ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA = 0, 1, 2, 3, 4
+MODES = {"full": ZTS_FULL, "full_mfma": ZTS_FULL_MFMA, "te_fixed": ZTS_TE_FIXED, "egs": ZTS_EGS, "opta": ZTS_OPTA}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template", -4: "unknown image",
           -5: "HBM budget exhausted", -6: "not ready", -7: "busy", -8: "timed out", -9: "cancelled",
@@ -36,8 +36,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template"
 
 EXPORTS = ["zts_params_default", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
            "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
-           "zts_search", "zts_search_device", "zts_search_batch", "zts_debug_full_map", "zts_debug_autocorr",
-           "zts_debug_blur"]
+           "zts_search", "zts_search_device", "zts_search_batch", "zts_submit", "zts_submit_batch", "zts_poll",
+           "zts_wait", "zts_cancel", "zts_pending", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
 
 
 class ZtsError(RuntimeError):
@@ -47,7 +47,8 @@ class ZtsError(RuntimeError):
 
 
 class CtxParams(C.Structure):
-    _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_uint64)]
+    _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_uint64), ("max_inflight", C.c_int32),
+                ("max_queued", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -65,7 +66,7 @@ class Result(C.Structure):
                 ("n_survivors", C.c_int64), ("n_computed", C.c_int64), ("group_h", C.c_int32),
                 ("group_w", C.c_int32), ("best0", C.c_double), ("best0_y", C.c_int32), ("best0_x", C.c_int32),
                 ("device_ms", C.c_float), ("status", C.c_int32), ("phase_ms", C.c_float * 4),
-                ("pad1", C.c_int32)]
+                ("latency_ms", C.c_float), ("queue_ms", C.c_float), ("batch_size", C.c_int32), ("pad1", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
@@ -126,6 +127,12 @@ def lib():
         L.zts_search_device.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), vp,
                                         C.POINTER(Result)]
         L.zts_search_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.zts_submit.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
+        L.zts_submit_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
+        L.zts_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
+        L.zts_wait.argtypes = [vp, C.c_uint64, i64, C.POINTER(Result)]
+        L.zts_cancel.argtypes = [vp, C.c_uint64]
+        L.zts_pending.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.zts_debug_full_map.argtypes = [vp, i32, vp, i32, i32, i64, vp, vp, vp]
         L.zts_debug_autocorr.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp, vp]
         L.zts_debug_blur.argtypes = [vp, vp, i32, i32, vp, i32, vp]
@@ -165,9 +172,10 @@ def zts_status_str(code: int) -> str:
     return lib().zts_status_str(code).decode()
 
 
-def zts_create(device: int = 0, hbm_budget_bytes: int = 0):
+def zts_create(device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0, max_queued: int = 0):
     h = C.c_void_p()
-    _check(lib().zts_create(C.byref(CtxParams(device, hbm_budget_bytes)), C.byref(h)), "zts_create")
+    _check(lib().zts_create(C.byref(CtxParams(device, hbm_budget_bytes, max_inflight, max_queued)), C.byref(h)),
+           "zts_create")
     return h
 
 
@@ -251,15 +259,70 @@ def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None =
 
 def zts_search_batch(ctx, image: int, tpls) -> list:
     """Exhaustive search of many host templates in one call (int8 MFMA); one dict per template."""
+    tpls, ptrs, ms, ns, st = _tpl_arrays(tpls)
+    k = len(tpls)
+    out = (Result * k)()
+    _check(lib().zts_search_batch(ctx, image, k, ptrs, ms, ns, st, out), "zts_search_batch")
+    return [r.as_dict() for r in out]
+
+
+def _tpl_arrays(tpls):
     tpls = [_u8(t) for t in tpls]
     k = len(tpls)
     ptrs = (C.c_void_p * k)(*[t.ctypes.data for t in tpls])
     ms = (C.c_int32 * k)(*[t.shape[0] for t in tpls])
     ns = (C.c_int32 * k)(*[t.shape[1] for t in tpls])
     st = (C.c_int64 * k)(*[t.strides[0] for t in tpls])
-    out = (Result * k)()
-    _check(lib().zts_search_batch(ctx, image, k, ptrs, ms, ns, st, out), "zts_search_batch")
-    return [r.as_dict() for r in out]
+    return tpls, ptrs, ms, ns, st
+
+
+def zts_submit(ctx, image: int, tpl, mode, params: Params | None = None) -> int:
+    """Queues one search; returns its ticket (the template is copied before returning)."""
+    tpl = _u8(tpl)
+    p = params if params is not None else zts_params_default()
+    t = C.c_uint64()
+    _check(lib().zts_submit(ctx, image, tpl.ctypes.data, tpl.shape[0], tpl.shape[1], tpl.strides[0], _mode(mode),
+                            C.byref(p), C.byref(t)), "zts_submit")
+    return t.value
+
+
+def zts_submit_batch(ctx, image: int, tpls, mode, params: Params | None = None) -> list:
+    tpls, ptrs, ms, ns, st = _tpl_arrays(tpls)
+    p = params if params is not None else zts_params_default()
+    t = C.c_uint64()
+    _check(lib().zts_submit_batch(ctx, image, len(tpls), ptrs, ms, ns, st, _mode(mode), C.byref(p), C.byref(t)),
+           "zts_submit_batch")
+    return list(range(t.value, t.value + len(tpls)))
+
+
+def zts_poll(ctx, ticket: int):
+    """None while the request runs; then (status, result dict)."""
+    r = Result()
+    rc = lib().zts_poll(ctx, ticket, C.byref(r))
+    if rc == -6:
+        return None
+    if rc == -1:
+        raise ZtsError(rc, "zts_poll")
+    return rc, r.as_dict()
+
+
+def zts_wait(ctx, ticket: int, timeout_ns: int = -1):
+    """(status, result dict) once the request has ended; raises ZtsError(-8) on time-out."""
+    r = Result()
+    rc = lib().zts_wait(ctx, ticket, timeout_ns, C.byref(r))
+    if rc in (-1, -8):
+        raise ZtsError(rc, "zts_wait")
+    return rc, r.as_dict()
+
+
+def zts_cancel(ctx, ticket: int) -> None:
+    _check(lib().zts_cancel(ctx, ticket), "zts_cancel")
+
+
+def zts_pending(ctx):
+    q, r = C.c_int32(), C.c_int32()
+    _check(lib().zts_pending(ctx, C.byref(q), C.byref(r)), "zts_pending")
+    return q.value, r.value
 
 
 def zts_debug_full_map(ctx, image: int, image_shape, tpl):
@@ -297,8 +360,8 @@ def zts_debug_blur(ctx, img, taps) -> np.ndarray:
 class Searcher:
     """Convenience owner of one context: load images, search templates."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
-        self.ctx = zts_create(device, hbm_budget_bytes)
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0, max_queued: int = 0):
+        self.ctx = zts_create(device, hbm_budget_bytes, max_inflight, max_queued)
         self.shapes = {}
 
     def close(self):
@@ -335,7 +398,7 @@ class Searcher:
 
     def prepare(self, image, m, n, mode, **params):
         zts_prepare(self.ctx, image, m, n, mode, zts_params_default(**params))
-        if _mode(mode) != ZTS_FULL:
+        if _mode(mode) not in (ZTS_FULL, ZTS_FULL_MFMA):
             return zts_prep_query(self.ctx, image, m, n, mode)
         return None
 
@@ -347,6 +410,24 @@ class Searcher:
 
     def search_batch(self, image, tpls):
         return zts_search_batch(self.ctx, image, tpls)
+
+    def submit(self, image, tpl, mode="full_mfma", **params):
+        return zts_submit(self.ctx, image, tpl, mode, zts_params_default(**params))
+
+    def submit_batch(self, image, tpls, mode="full_mfma", **params):
+        return zts_submit_batch(self.ctx, image, tpls, mode, zts_params_default(**params))
+
+    def poll(self, ticket):
+        return zts_poll(self.ctx, ticket)
+
+    def wait(self, ticket, timeout_ns=-1):
+        return zts_wait(self.ctx, ticket, timeout_ns)
+
+    def cancel(self, ticket):
+        zts_cancel(self.ctx, ticket)
+
+    def pending(self):
+        return zts_pending(self.ctx)
 
     def prep_image(self, image, m, n):
         return zts_prep_image(self.ctx, image, m, n, self.shapes[image])

@@ -7,8 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libzts.so")
-SOURCES = ["zts_kernels.hip", "zts_host.hip"]
-HEADERS = ["zts_device.h", "zts_kernels.h", "zts_shared.h"]
+SOURCES = ["zts_kernels.hip", "zts_host.hip", "zts_serve.hip"]
+HEADERS = ["zts_device.h", "zts_kernels.h", "zts_shared.h", "zts_runtime.h"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
@@ -16,6 +16,8 @@ FLAGS = [
     "-ffp-contract=off",          # every binary64 decision is evaluated exactly as written
     "-fPIC",
     "-shared",
+    "-fvisibility=hidden",        # only the ZTS_API entry points are exported
+    "-pthread",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",

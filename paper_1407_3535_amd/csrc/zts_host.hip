@@ -1,34 +1,21 @@
 // Host side of libzts: context, resident images, preparation (group size by
-// EGS, OptA conditioning) and query orchestration behind the C ABI of zts.h.
-#include <hip/hip_runtime.h>
-
+// EGS, OptA conditioning), query and batched-launch orchestration, and the
+// synchronous entry points of zts.h.  The serving loop (submit / poll / wait)
+// is in zts_serve.hip.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <map>
-#include <memory>
-#include <mutex>
 #include <new>
-#include <tuple>
-#include <vector>
 
-#include "../../include/zts.h"
-#include "zts_kernels.h"
+#include "zts_runtime.h"
 
-using namespace zts;
+namespace zts {
 
-namespace {
+// ------------------------------------------------------------------ errors and buffers
 
-// ------------------------------------------------------------------ errors
-
-struct ZtsError {
-    zts_status st;
-};
-
-inline void hip_check(hipError_t e)
+void hip_check(hipError_t e)
 {
     if (e != hipSuccess) {
         if (std::getenv("ZTS_DEBUG"))
@@ -36,64 +23,6 @@ inline void hip_check(hipError_t e)
         throw ZtsError{ZTS_E_DEVICE};
     }
 }
-
-// ------------------------------------------------------------------ device buffers
-
-struct Ctx;
-
-// A device allocation charged against the context's HBM budget.
-struct DBuf {
-    Ctx *ctx = nullptr;
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    DBuf() = default;
-    DBuf(const DBuf &) = delete;
-    DBuf &operator=(const DBuf &) = delete;
-    ~DBuf() { reset(); }
-    void reset();
-    template <class T> T *as() const { return (T *)ptr; }
-};
-
-struct Stats {
-    DBuf stat;  // int2 per location
-};
-
-struct Prepared {
-    zts_mode mode;
-    int m, n, h, w, Gy, Gx, radius;
-    zts_params params;
-    DBuf theta_b, x_b, gsum;       // member vs centre on the searched image
-    DBuf J, Jsat, Jstat;           // OptA: conditioned image and its statistics
-    DBuf theta_c, x_c;             // OptA: conditioned block vs original block (row-major)
-    DBuf theta_cg, x_cg;           // the same in the group-major layout of (h, w)
-    zts_prep_info info;
-};
-
-struct Image {
-    int rows, cols;
-    int64_t pitch;
-    DBuf img, sat;
-    std::map<std::pair<int, int>, std::unique_ptr<Stats>> stats;
-    std::map<std::tuple<int, int, int>, std::unique_ptr<Prepared>> prep;
-};
-
-struct Ctx {
-    std::mutex mu;
-    int device = 0;
-    uint64_t budget = 0;
-    uint64_t used = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t evp[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    int next_id = 1;
-    std::map<int, std::unique_ptr<Image>> images;
-    // per-query scratch, grown on demand
-    DBuf qs, recs, gnum, gtheta, tpl, dec, counter, tmp32, viol, colmask;
-    QState *h_qs = nullptr;
-    uint8_t *h_tpl = nullptr;
-    size_t h_tpl_bytes = 0;
-    unsigned long long *h_cnt = nullptr;
-};
 
 void DBuf::reset()
 {
@@ -106,6 +35,120 @@ void DBuf::reset()
     bytes = 0;
 }
 
+void HostBuf::reset()
+{
+    if (ptr)
+        (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void HostBuf::grow(size_t n)
+{
+    if (ptr && bytes >= n)
+        return;
+    reset();
+    n = (std::max(n, (size_t)64) + 4095) & ~(size_t)4095;
+    if (hipHostMalloc(&ptr, n, hipHostMallocDefault) != hipSuccess) {
+        ptr = nullptr;
+        throw ZtsError{ZTS_E_NOMEM};
+    }
+    bytes = n;
+}
+
+void Slot::init()
+{
+    hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    hip_check(hipEventCreate(&ev0));
+    hip_check(hipEventCreate(&ev1));
+    for (auto &e : evp)
+        hip_check(hipEventCreate(&e));
+    h_qs.grow(sizeof(QState));
+}
+
+void Slot::release_scratch()
+{
+    qs.reset();
+    recs.reset();
+    gnum.reset();
+    gtheta.reset();
+    tpl.reset();
+    dec.reset();
+    bdata.reset();
+    bres.reset();
+    brec.reset();
+}
+
+void Slot::destroy()
+{
+    if (stream)
+        (void)hipStreamSynchronize(stream);
+    release_scratch();
+    h_qs.reset();
+    h_stage.reset();
+    h_out.reset();
+    if (ev0)
+        (void)hipEventDestroy(ev0);
+    if (ev1)
+        (void)hipEventDestroy(ev1);
+    for (auto &e : evp)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (stream)
+        (void)hipStreamDestroy(stream);
+    stream = nullptr;
+    ev0 = ev1 = nullptr;
+    for (auto &e : evp)
+        e = nullptr;
+}
+
+Stats::~Stats()
+{
+    if (ready)
+        (void)hipEventDestroy(ready);
+}
+
+namespace {
+
+// Frees cached per-size tables that no running work holds, least recently
+// used first, until `need` more bytes fit the budget.
+bool evict_for(Ctx *c, size_t need)
+{
+    while (c->used + need > c->budget) {
+        Image *victim = nullptr;
+        bool is_stats = false;
+        uint64_t oldest = UINT64_MAX;
+        std::pair<int, int> skey;
+        std::tuple<int, int, int> pkey;
+        for (auto &kv : c->images) {
+            Image *im = kv.second.get();
+            for (auto &s : im->stats)
+                if (!s.second->pins && s.second->last_use < oldest) {
+                    oldest = s.second->last_use;
+                    victim = im;
+                    is_stats = true;
+                    skey = s.first;
+                }
+            for (auto &p : im->prep)
+                if (!p.second->pins && p.second->last_use < oldest) {
+                    oldest = p.second->last_use;
+                    victim = im;
+                    is_stats = false;
+                    pkey = p.first;
+                }
+        }
+        if (!victim)
+            return false;
+        if (is_stats)
+            victim->stats.erase(skey);
+        else
+            victim->prep.erase(pkey);
+    }
+    return true;
+}
+
+}  // namespace
+
 void dalloc(Ctx *c, DBuf &b, size_t bytes)
 {
     if (b.ptr && b.bytes >= bytes)
@@ -114,7 +157,7 @@ void dalloc(Ctx *c, DBuf &b, size_t bytes)
     if (bytes == 0)
         bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
-    if (c->budget && c->used + bytes > c->budget)
+    if (c->budget && c->used + bytes > c->budget && !evict_for(c, bytes))
         throw ZtsError{ZTS_E_BUDGET};
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess)
@@ -123,6 +166,14 @@ void dalloc(Ctx *c, DBuf &b, size_t bytes)
     b.ptr = p;
     b.bytes = bytes;
     c->used += bytes;
+}
+
+zts_result error_result(zts_status st)
+{
+    zts_result r;
+    std::memset(&r, 0, sizeof r);
+    r.status = st;
+    return r;
 }
 
 // ------------------------------------------------------------------ parameters and taps
@@ -213,7 +264,7 @@ double lambda_of(double rho_th, double rho_max)
     return rho_th * rho_max + std::sqrt(r);
 }
 
-// ------------------------------------------------------------------ helpers
+// ------------------------------------------------------------------ images and statistics
 
 Image *find_image(Ctx *c, int id)
 {
@@ -238,26 +289,38 @@ void build_sat(Ctx *c, const uint8_t *img, int64_t pitch, int rows, int cols, DB
     hip_check(launch_sat(img, pitch, rows, cols, sat.as<uint2>(), c->stream));
 }
 
-const int2 *stats_for(Ctx *c, Image *im, int m, int n)
+Stats *stats_entry(Ctx *c, Image *im, int m, int n, hipStream_t s)
 {
     auto key = std::make_pair(m, n);
     auto it = im->stats.find(key);
-    if (it != im->stats.end())
-        return it->second->stat.as<int2>();
+    if (it != im->stats.end()) {
+        Stats *st = it->second.get();
+        st->last_use = ++c->clock;
+        hip_check(hipStreamWaitEvent(s, st->ready, 0));
+        return st;
+    }
     auto st = std::make_unique<Stats>();
     int Ly = im->rows - m + 1, Lx = im->cols - n + 1;
     dalloc(c, st->stat, sizeof(int2) * (size_t)Ly * Lx);
-    hip_check(launch_stats(im->sat.as<uint2>(), im->cols, Ly, Lx, m, n, st->stat.as<int2>(), c->stream));
-    const int2 *p = st->stat.as<int2>();
+    hip_check(launch_stats(im->sat.as<uint2>(), im->cols, Ly, Lx, m, n, st->stat.as<int2>(), s));
+    hip_check(hipEventCreateWithFlags(&st->ready, hipEventDisableTiming));
+    hip_check(hipEventRecord(st->ready, s));
+    st->last_use = ++c->clock;
+    Stats *p = st.get();
     im->stats[key] = std::move(st);
     return p;
 }
 
+// Statistics for work on the main stream (preparation).
+const int2 *stats_for(Ctx *c, Image *im, int m, int n) { return stats_entry(c, im, m, n, c->stream)->stat.as<int2>(); }
+
 unsigned long long read_counter(Ctx *c)
 {
-    hip_check(hipMemcpyAsync(c->h_cnt, c->counter.ptr, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    c->h_cnt.grow(64);
+    hip_check(hipMemcpyAsync(c->h_cnt.ptr, c->counter.ptr, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
     hip_check(hipStreamSynchronize(c->stream));
-    return *c->h_cnt;
+    return *c->h_cnt.as<unsigned long long>();
 }
 
 void zero_counter(Ctx *c)
@@ -265,6 +328,8 @@ void zero_counter(Ctx *c)
     dalloc(c, c->counter, 64);
     hip_check(hipMemsetAsync(c->counter.ptr, 0, sizeof(unsigned long long), c->stream));
 }
+
+// ------------------------------------------------------------------ preparation
 
 // The image a group tiling is built on, with its statistics.
 struct Searched {
@@ -572,18 +637,31 @@ bool same_prep_params(const Prepared &P, zts_mode mode, const zts_params &a)
            a.sigma_max == b.sigma_max && a.max_iters == b.max_iters;
 }
 
+// Holds a pin for the lifetime of a scope.
+struct PinGuard {
+    int &pins;
+    explicit PinGuard(int &p) : pins(p) { pins++; }
+    ~PinGuard() { pins--; }
+};
+
 Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr)
 {
     auto key = std::make_tuple(m, n, (int)mode);
     auto it = im->prep.find(key);
     if (it != im->prep.end()) {
-        if (same_prep_params(*it->second, mode, pr))
+        if (same_prep_params(*it->second, mode, pr)) {
+            it->second->last_use = ++c->clock;
             return it->second.get();
+        }
+        if (it->second->pins)  // running work still reads the tables made with other parameters
+            throw ZtsError{ZTS_E_BUSY};
         im->prep.erase(it);
     }
     auto t0 = std::chrono::steady_clock::now();
     int Ly = im->rows - m + 1, Lx = im->cols - n + 1;
-    const int2 *statI = stats_for(c, im, m, n);
+    Stats *sI = stats_entry(c, im, m, n, c->stream);
+    PinGuard pin(sI->pins);  // preparation's own allocations may evict cached tables, never these
+    const int2 *statI = sI->stat.as<int2>();
     auto P = std::make_unique<Prepared>();
     std::memset(&P->info, 0, sizeof P->info);
     P->mode = mode;
@@ -621,6 +699,7 @@ Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_para
     P->info.radius = P->radius;
     P->info.prepare_ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
     Prepared *raw = P.get();
+    raw->last_use = ++c->clock;
     im->prep[key] = std::move(P);
     return raw;
 }
@@ -635,30 +714,112 @@ void check_template_args(Image *im, const void *tpl, int m, int n, int64_t strid
         throw ZtsError{ZTS_E_SIZE};
 }
 
-// Runs one query with the template already at c->tpl (m x n, pitch n).
-void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr, zts_result *out, int8_t *dec,
-               int64_t *num_map, int64_t *dr_map, float *rho_map)
+// ------------------------------------------------------------------ one query
+
+namespace {
+
+int query_radius(const QueryPlan &q)
 {
-    int Ly = im->rows - m + 1, Lx = im->cols - n + 1;
-    int64_t L = (int64_t)Ly * Lx;
-    const int2 *statI = stats_for(c, im, m, n);
-    Prepared *P = nullptr;
-    if (mode != ZTS_FULL)
-        P = prepare(c, im, m, n, mode, pr);
-    dalloc(c, c->qs, sizeof(QState));
-    hip_check(hipMemsetAsync(c->qs.ptr, 0, sizeof(QState), c->stream));
-    int8_t *d_dec = nullptr;
-    if (dec) {
-        dalloc(c, c->dec, (size_t)L);
-        hip_check(hipMemsetAsync(c->dec.ptr, 0x7f, (size_t)L, c->stream));
-        d_dec = c->dec.as<int8_t>();
+    if (q.mode == ZTS_OPTA)
+        return std::max(q.P->radius, std::max(q.pr.refine_radius, 0));
+    return q.pr.refine_radius > 0 ? q.pr.refine_radius : -1;
+}
+
+}  // namespace
+
+void unpin_query(QueryPlan &q)
+{
+    if (q.st)
+        q.st->pins--;
+    if (q.P)
+        q.P->pins--;
+    q.st = nullptr;
+    q.P = nullptr;
+}
+
+QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, const zts_params &pr, bool want_dec)
+{
+    QueryPlan q;
+    q.im = im;
+    q.m = m;
+    q.n = n;
+    q.Ly = im->rows - m + 1;
+    q.Lx = im->cols - n + 1;
+    q.mode = mode;
+    q.pr = pr;
+    q.want_dec = want_dec;
+    q.st = stats_entry(c, im, m, n, S.stream);
+    q.st->pins++;
+    try {
+        if (mode != ZTS_FULL) {
+            q.P = prepare(c, im, m, n, mode, pr);
+            q.P->pins++;
+            q.P->last_use = ++c->clock;
+        }
+        int64_t L = (int64_t)q.Ly * q.Lx;
+        dalloc(c, S.qs, sizeof(QState));
+        dalloc(c, S.tpl, (size_t)m * n);
+        if (want_dec)
+            dalloc(c, S.dec, (size_t)L);
+        if (mode == ZTS_FULL) {
+            dalloc(c, S.recs, sizeof(RecPod) * (size_t)full_record_count(q.Ly, q.Lx));
+        } else {
+            const Prepared *P = q.P;
+            int radius = query_radius(q);
+            int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h);
+            int n2 = radius >= 0 ? window_record_count(radius) : 0;
+            int n3 = members_record_count(P->Gy, P->Gx);
+            dalloc(c, S.recs, sizeof(RecPod) * (size_t)(n1 + n2 + n3));
+            dalloc(c, S.gnum, sizeof(int64_t) * (size_t)P->Gy * P->Gx);
+            dalloc(c, S.gtheta, sizeof(float) * (size_t)P->Gy * P->Gx);
+        }
+    } catch (...) {
+        unpin_query(q);
+        throw;
     }
-    QState *qs = c->qs.as<QState>();
-    const uint8_t *tpl = c->tpl.as<uint8_t>();
-    hip_check(hipEventRecord(c->ev0, c->stream));
-    int G = 0, radius = -1;
-    if (mode == ZTS_FULL) {
-        dalloc(c, c->recs, sizeof(RecPod) * (size_t)full_record_count(Ly, Lx));
+    return q;
+}
+
+void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride, bool device, hipStream_t caller)
+{
+    size_t bytes = (size_t)m * n;
+    if (device) {
+        hip_check(hipMemcpy2DAsync(S.tpl.ptr, n, tpl, stride, n, m, hipMemcpyDeviceToDevice,
+                                   caller ? caller : S.stream));
+        if (caller && caller != S.stream)
+            hip_check(hipStreamSynchronize(caller));
+        return;
+    }
+    S.h_stage.grow(bytes);
+    uint8_t *h = S.h_stage.as<uint8_t>();
+    for (int i = 0; i < m; i++)
+        std::memcpy(h + (size_t)i * n, tpl + (size_t)i * stride, n);
+    hip_check(hipMemcpyAsync(S.tpl.ptr, h, bytes, hipMemcpyHostToDevice, S.stream));
+}
+
+// Enqueues one query on S.stream: scan 1 and its reduction, the optional
+// refinement window, scan 2 with survivors, the final reduction, and the copy
+// of the query state to pinned host memory.
+void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
+{
+    Image *im = q.im;
+    const int m = q.m, n = q.n, Ly = q.Ly, Lx = q.Lx;
+    const int64_t L = (int64_t)Ly * Lx;
+    const zts_params &pr = q.pr;
+    const Prepared *P = q.P;
+    const int2 *statI = q.st->stat.as<int2>();
+    hipStream_t st = S.stream;
+    hip_check(hipMemsetAsync(S.qs.ptr, 0, sizeof(QState), st));
+    int8_t *d_dec = nullptr;
+    if (q.want_dec) {
+        hip_check(hipMemsetAsync(S.dec.ptr, 0x7f, (size_t)L, st));
+        d_dec = S.dec.as<int8_t>();
+    }
+    QState *qs = S.qs.as<QState>();
+    const uint8_t *tpl = S.tpl.as<uint8_t>();
+    RecPod *recs = S.recs.as<RecPod>();
+    hip_check(hipEventRecord(S.ev0, st));
+    if (q.mode == ZTS_FULL) {
         FullArgs a;
         std::memset(&a, 0, sizeof a);
         a.img = im->img.as<uint8_t>();
@@ -672,37 +833,29 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         a.n = n;
         a.Ly = Ly;
         a.Lx = Lx;
-        a.recs = c->recs.as<RecPod>();
+        a.recs = recs;
         a.qs = qs;
-        a.num_map = num_map;
-        a.dr_map = dr_map;
-        a.rho_map = rho_map;
+        a.num_map = q.num_map;
+        a.dr_map = q.dr_map;
+        a.rho_map = q.rho_map;
         a.dec = d_dec;
-        hip_check(launch_full(a, c->stream));
-        hip_check(hipEventRecord(c->evp[0], c->stream));
-        hip_check(launch_reduce(c->recs.as<RecPod>(), 0, full_record_count(Ly, Lx), qs, RD_FINAL, 0, pr.margin,
-                                c->stream));
-        hip_check(hipEventRecord(c->evp[1], c->stream));
+        hip_check(launch_full(a, st));
+        hip_check(hipEventRecord(S.evp[0], st));
+        hip_check(launch_reduce(recs, 0, full_record_count(Ly, Lx), qs, RD_FINAL, 0, pr.margin, st));
+        hip_check(hipEventRecord(S.evp[1], st));
     } else {
-        bool opta = mode == ZTS_OPTA;
-        G = P->Gy * P->Gx;
+        bool opta = q.mode == ZTS_OPTA;
+        int radius = query_radius(q);
         int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h);
-        if (opta)
-            radius = std::max(P->radius, std::max(pr.refine_radius, 0));
-        else
-            radius = pr.refine_radius > 0 ? pr.refine_radius : -1;
         int n2 = radius >= 0 ? window_record_count(radius) : 0;
         int n3 = members_record_count(P->Gy, P->Gx);
-        dalloc(c, c->recs, sizeof(RecPod) * (size_t)(n1 + n2 + n3));
-        dalloc(c, c->gnum, sizeof(int64_t) * (size_t)G);
-        dalloc(c, c->gtheta, sizeof(float) * (size_t)G);
-        Searched S = opta ? Searched{P->J.as<uint8_t>(), im->pitch, P->Jstat.as<int2>()}
-                          : Searched{im->img.as<uint8_t>(), im->pitch, statI};
+        const uint8_t *spx = opta ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
+        const int2 *sstat = opta ? P->Jstat.as<int2>() : statI;
         ScanArgs s;
         std::memset(&s, 0, sizeof s);
-        s.img = S.px;
-        s.pitch = S.pitch;
-        s.stat = S.stat;
+        s.img = spx;
+        s.pitch = im->pitch;
+        s.stat = sstat;
         s.tpl = tpl;
         s.ts = n;
         s.m = m;
@@ -713,17 +866,17 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         s.w = P->w;
         s.Gy = P->Gy;
         s.Gx = P->Gx;
-        s.g_num = c->gnum.as<int64_t>();
-        s.g_theta = c->gtheta.as<float>();
-        s.recs = c->recs.as<RecPod>();
+        s.g_num = S.gnum.as<int64_t>();
+        s.g_theta = S.gtheta.as<float>();
+        s.recs = recs;
         s.qs = qs;
         s.dec = opta ? nullptr : d_dec;
         s.delta = pr.margin;
         s.set_thr = radius < 0;
-        hip_check(launch_centres(s, c->stream));
-        hip_check(hipEventRecord(c->evp[0], c->stream));
-        hip_check(launch_reduce(c->recs.as<RecPod>(), 0, n1, qs, RD_BEST0, radius < 0, pr.margin, c->stream));
-        hip_check(hipEventRecord(c->evp[1], c->stream));
+        hip_check(launch_centres(s, st));
+        hip_check(hipEventRecord(S.evp[0], st));
+        hip_check(launch_reduce(recs, 0, n1, qs, RD_BEST0, radius < 0, pr.margin, st));
+        hip_check(hipEventRecord(S.evp[1], st));
         if (radius >= 0) {
             WinArgs wa;
             std::memset(&wa, 0, sizeof wa);
@@ -741,23 +894,23 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
             wa.radius = radius;
             wa.skip_centres = !opta;
             wa.include_best0 = !opta;
-            wa.recs = c->recs.as<RecPod>();
+            wa.recs = recs;
             wa.rec_off = n1;
             wa.qs = qs;
             wa.dec = d_dec;
             wa.delta = pr.margin;
-            hip_check(launch_window(wa, c->stream));
+            hip_check(launch_window(wa, st));
         }
-        hip_check(hipEventRecord(c->evp[2], c->stream));
+        hip_check(hipEventRecord(S.evp[2], st));
         if (radius >= 0)
-            hip_check(launch_reduce(c->recs.as<RecPod>(), n1, n1 + n2, qs, RD_WINDOW, !opta, pr.margin, c->stream));
-        hip_check(hipEventRecord(c->evp[3], c->stream));
+            hip_check(launch_reduce(recs, n1, n1 + n2, qs, RD_WINDOW, !opta, pr.margin, st));
+        hip_check(hipEventRecord(S.evp[3], st));
         MemArgs ma;
         std::memset(&ma, 0, sizeof ma);
         ma.I = im->img.as<uint8_t>();
         ma.pI = im->pitch;
         ma.statI = statI;
-        ma.statS = S.stat;
+        ma.statS = sstat;
         ma.tpl = tpl;
         ma.ts = n;
         ma.m = m;
@@ -768,8 +921,8 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         ma.w = P->w;
         ma.Gy = P->Gy;
         ma.Gx = P->Gx;
-        ma.g_num = c->gnum.as<int64_t>();
-        ma.g_theta = c->gtheta.as<float>();
+        ma.g_num = S.gnum.as<int64_t>();
+        ma.g_theta = S.gtheta.as<float>();
         ma.gsum = P->gsum.as<GroupSum>();
         ma.theta_b = P->theta_b.as<float>();
         ma.x_b = P->x_b.as<int32_t>();
@@ -777,25 +930,31 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
         ma.x_c = opta ? P->x_cg.as<int32_t>() : nullptr;
         ma.opta = opta;
         ma.radius = radius;
-        ma.recs = c->recs.as<RecPod>();
+        ma.recs = recs;
         ma.rec_off = n1 + n2;
         ma.final_from = opta ? n1 : 0;
         ma.qs = qs;
         ma.dec = d_dec;
-        hip_check(launch_members(ma, c->stream));
-        hip_check(hipEventRecord(c->evp[4], c->stream));
-        hip_check(launch_reduce(c->recs.as<RecPod>(), opta ? n1 : 0, n1 + n2 + n3, qs, RD_FINAL, 0, pr.margin,
-                                c->stream));
-        hip_check(hipEventRecord(c->evp[5], c->stream));
+        hip_check(launch_members(ma, st));
+        hip_check(hipEventRecord(S.evp[4], st));
+        hip_check(launch_reduce(recs, opta ? n1 : 0, n1 + n2 + n3, qs, RD_FINAL, 0, pr.margin, st));
+        hip_check(hipEventRecord(S.evp[5], st));
     }
-    hip_check(hipEventRecord(c->ev1, c->stream));
-    hip_check(hipMemcpyAsync(c->h_qs, c->qs.ptr, sizeof(QState), hipMemcpyDeviceToHost, c->stream));
-    if (dec)
-        hip_check(hipMemcpyAsync(dec, c->dec.ptr, (size_t)L, hipMemcpyDeviceToHost, c->stream));
-    hip_check(hipStreamSynchronize(c->stream));
-    const QState &h = *c->h_qs;
+    hip_check(hipEventRecord(S.ev1, st));
+    hip_check(hipMemcpyAsync(S.h_qs.ptr, S.qs.ptr, sizeof(QState), hipMemcpyDeviceToHost, st));
+    if (dec_host)
+        hip_check(hipMemcpyAsync(dec_host, S.dec.ptr, (size_t)L, hipMemcpyDeviceToHost, st));
+}
+
+// Waits for the query on S.stream and assembles its result.
+zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out)
+{
+    hip_check(hipStreamSynchronize(S.stream));
+    const QState &h = *S.h_qs.as<QState>();
     if (h.degenerate)
-        throw ZtsError{ZTS_E_DEGENERATE};
+        return ZTS_E_DEGENERATE;
+    const int Lx = q.Lx;
+    const int64_t L = (int64_t)q.Ly * Lx;
     zts_result r;
     std::memset(&r, 0, sizeof r);
     r.y = (int32_t)(h.fin.l / Lx);
@@ -806,67 +965,223 @@ void run_query(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params 
     r.den_t = h.dt;
     r.den_r = h.fin.dr;
     r.n_locations = L;
-    if (mode == ZTS_FULL) {
+    r.batch_size = 1;
+    if (q.mode == ZTS_FULL) {
         r.n_computed = L;
         r.group_h = r.group_w = 1;
         r.best0 = h.fin.rho;
         r.best0_y = r.y;
         r.best0_x = r.x;
     } else {
+        const Prepared *P = q.P;
+        int64_t G = (int64_t)P->Gy * P->Gx;
         r.n_centres = G;
         r.n_eliminated = (int64_t)h.n_elim;
         r.n_survivors = (int64_t)h.n_surv;
-        r.n_computed = (int64_t)h.n_window + (int64_t)h.n_surv + (mode == ZTS_OPTA ? 0 : G);
+        r.n_computed = (int64_t)h.n_window + (int64_t)h.n_surv + (q.mode == ZTS_OPTA ? 0 : G);
         r.group_h = P->h;
         r.group_w = P->w;
         r.best0 = h.best;
         r.best0_y = (int32_t)(h.best0_l / Lx);
         r.best0_x = (int32_t)(h.best0_l % Lx);
         if (r.n_computed + r.n_eliminated != L)
-            throw ZtsError{ZTS_E_DEVICE};
+            return ZTS_E_DEVICE;
     }
     float ms = 0.0f;
-    hip_check(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    hip_check(hipEventElapsedTime(&ms, S.ev0, S.ev1));
     r.device_ms = ms;
-    if (mode == ZTS_FULL) {
-        hip_check(hipEventElapsedTime(&r.phase_ms[0], c->ev0, c->evp[0]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[3], c->evp[0], c->evp[1]));
+    if (q.mode == ZTS_FULL) {
+        hip_check(hipEventElapsedTime(&r.phase_ms[0], S.ev0, S.evp[0]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[3], S.evp[0], S.evp[1]));
     } else {
         float r1, r2, r3;
-        hip_check(hipEventElapsedTime(&r.phase_ms[0], c->ev0, c->evp[0]));
-        hip_check(hipEventElapsedTime(&r1, c->evp[0], c->evp[1]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[1], c->evp[1], c->evp[2]));
-        hip_check(hipEventElapsedTime(&r2, c->evp[2], c->evp[3]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[2], c->evp[3], c->evp[4]));
-        hip_check(hipEventElapsedTime(&r3, c->evp[4], c->evp[5]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[0], S.ev0, S.evp[0]));
+        hip_check(hipEventElapsedTime(&r1, S.evp[0], S.evp[1]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[1], S.evp[1], S.evp[2]));
+        hip_check(hipEventElapsedTime(&r2, S.evp[2], S.evp[3]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[2], S.evp[3], S.evp[4]));
+        hip_check(hipEventElapsedTime(&r3, S.evp[4], S.evp[5]));
         r.phase_ms[3] = r1 + r2 + r3;
     }
     r.status = ZTS_OK;
     *out = r;
+    return ZTS_OK;
 }
 
-void stage_template(Ctx *c, const uint8_t *tpl, int m, int n, int64_t stride, bool device, hipStream_t caller)
+// ------------------------------------------------------------------ batched launches
+
+void unpin_batch(BatchPlan &b)
 {
-    size_t bytes = (size_t)m * n;
-    dalloc(c, c->tpl, bytes);
-    if (device) {
-        hip_check(hipMemcpy2DAsync(c->tpl.ptr, n, tpl, stride, n, m, hipMemcpyDeviceToDevice,
-                                   caller ? caller : c->stream));
-        if (caller && caller != c->stream)
-            hip_check(hipStreamSynchronize(caller));
-        return;
-    }
-    if (c->h_tpl_bytes < bytes) {
-        if (c->h_tpl)
-            (void)hipHostFree(c->h_tpl);
-        c->h_tpl = nullptr;
-        hip_check(hipHostMalloc((void **)&c->h_tpl, bytes, hipHostMallocDefault));
-        c->h_tpl_bytes = bytes;
-    }
-    for (int i = 0; i < m; i++)
-        std::memcpy(c->h_tpl + (size_t)i * n, tpl + (size_t)i * stride, n);
-    hip_check(hipMemcpyAsync(c->tpl.ptr, c->h_tpl, bytes, hipMemcpyHostToDevice, c->stream));
+    for (Stats *s : b.stats)
+        if (s)
+            s->pins--;
+    b.stats.clear();
 }
+
+// Groups the items by (image, m, n) into jobs, pins their statistics, sizes
+// the slot's batch buffers and fills the job table with device addresses.
+// Device data layout of S.bdata: [job table][templates of every job][tst].
+BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items)
+{
+    BatchPlan b;
+    b.items = std::move(items);
+    std::map<std::tuple<Image *, int, int>, int> jid;
+    for (int k = 0; k < (int)b.items.size(); k++) {
+        const BatchItem &it = b.items[k];
+        auto key = std::make_tuple(it.im, it.m, it.n);
+        auto f = jid.find(key);
+        int j;
+        if (f == jid.end()) {
+            j = (int)b.jobs.size();
+            jid[key] = j;
+            BatchJob J;
+            std::memset(&J, 0, sizeof J);
+            J.img = it.im->img.as<uint8_t>();
+            J.pitch = it.im->pitch;
+            J.p = it.im->rows;
+            J.q = it.im->cols;
+            J.m = it.m;
+            J.n = it.n;
+            J.Ly = it.im->rows - it.m + 1;
+            J.Lx = it.im->cols - it.n + 1;
+            b.jobs.push_back(J);
+            b.members.emplace_back();
+        } else {
+            j = f->second;
+        }
+        b.members[j].push_back(k);
+    }
+    const size_t njobs = b.jobs.size();
+    b.table_bytes = (njobs * sizeof(BatchJob) + 255) & ~(size_t)255;
+    size_t off = b.table_bytes;
+    std::vector<size_t> tpl_off(njobs), rec_off(njobs);
+    int block0 = 0, fold0 = 0, tmpl0 = 0;
+    size_t nrec = 0;
+    for (size_t j = 0; j < njobs; j++) {
+        BatchJob &J = b.jobs[j];
+        J.T = (int)b.members[j].size();
+        if (!batch_job_geometry(J))
+            throw ZtsError{ZTS_E_SIZE};
+        int64_t nb = (int64_t)block0 + (int64_t)J.gx * J.gy * J.gz;
+        if (nb > INT32_MAX)
+            throw ZtsError{ZTS_E_SIZE};
+        J.block0 = block0;
+        block0 = (int)nb;
+        J.fold0 = fold0;
+        fold0 += J.gz * J.chunks;
+        J.tmpl0 = tmpl0;
+        tmpl0 += J.T;
+        tpl_off[j] = off;
+        off += ((size_t)J.T * J.m * J.n16 + 255) & ~(size_t)255;
+        rec_off[j] = nrec;
+        nrec += batch_job_records(J);
+    }
+    b.tpl_bytes = off;
+    b.nrec = nrec;
+    b.ntpl = tmpl0;
+    try {
+        for (size_t j = 0; j < njobs; j++) {
+            const BatchItem &it = b.items[b.members[j][0]];
+            Stats *st = stats_entry(c, it.im, it.m, it.n, S.stream);
+            st->pins++;
+            b.stats.push_back(st);
+        }
+        dalloc(c, S.bdata, b.tpl_bytes + sizeof(int64_t) * 2 * (size_t)b.ntpl);
+        dalloc(c, S.bres, sizeof(RecPod) * (size_t)b.ntpl);
+        dalloc(c, S.brec, sizeof(RecPod) * b.nrec);
+        S.h_stage.grow(b.tpl_bytes);
+        S.h_out.grow((sizeof(RecPod) + 2 * sizeof(int64_t)) * (size_t)b.ntpl);
+    } catch (...) {
+        unpin_batch(b);
+        throw;
+    }
+    uint8_t *base = S.bdata.as<uint8_t>();
+    int64_t *tst = (int64_t *)(base + b.tpl_bytes);
+    for (size_t j = 0; j < njobs; j++) {
+        BatchJob &J = b.jobs[j];
+        J.stat = b.stats[j]->stat.as<int2>();
+        J.tpl = base + tpl_off[j];
+        J.tst = tst + 2 * (size_t)J.tmpl0;
+        J.recs = S.brec.as<RecPod>() + rec_off[j];
+        J.out = S.bres.as<RecPod>() + J.tmpl0;
+    }
+    return b;
+}
+
+// Stages the templates (0x80 past column n) and the job table in pinned
+// memory, copies them in one transfer and enqueues the fused launch.
+void launch_batch_plan(BatchPlan &b, Slot &S)
+{
+    uint8_t *h = S.h_stage.as<uint8_t>();
+    std::memcpy(h, b.jobs.data(), b.jobs.size() * sizeof(BatchJob));
+    const uint8_t *dbase = S.bdata.as<uint8_t>();
+    for (size_t j = 0; j < b.jobs.size(); j++) {
+        const BatchJob &J = b.jobs[j];
+        uint8_t *dst0 = h + (J.tpl - dbase);
+        for (int t = 0; t < J.T; t++) {
+            const BatchItem &it = b.items[b.members[j][t]];
+            uint8_t *dst = dst0 + (size_t)t * J.m * J.n16;
+            for (int r = 0; r < J.m; r++) {
+                std::memcpy(dst + (size_t)r * J.n16, it.tpl + (size_t)r * it.stride, J.n);
+                std::memset(dst + (size_t)r * J.n16 + J.n, 0x80, J.n16 - J.n);
+            }
+        }
+    }
+    hipStream_t st = S.stream;
+    hip_check(hipMemcpyAsync(S.bdata.ptr, h, b.tpl_bytes, hipMemcpyHostToDevice, st));
+    hip_check(hipEventRecord(S.ev0, st));
+    hip_check(launch_batch_jobs(S.bdata.as<BatchJob>(), b.jobs.data(), (int)b.jobs.size(), st));
+    hip_check(hipEventRecord(S.ev1, st));
+    uint8_t *ho = S.h_out.as<uint8_t>();
+    hip_check(hipMemcpyAsync(ho, S.bres.ptr, sizeof(RecPod) * (size_t)b.ntpl, hipMemcpyDeviceToHost, st));
+    hip_check(hipMemcpyAsync(ho + sizeof(RecPod) * (size_t)b.ntpl, S.bdata.as<uint8_t>() + b.tpl_bytes,
+                             sizeof(int64_t) * 2 * (size_t)b.ntpl, hipMemcpyDeviceToHost, st));
+}
+
+void finish_batch(const BatchPlan &b, Slot &S, zts_result *out)
+{
+    hip_check(hipStreamSynchronize(S.stream));
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, S.ev0, S.ev1));
+    const RecPod *res = S.h_out.as<RecPod>();
+    const int64_t *tst = (const int64_t *)(S.h_out.as<uint8_t>() + sizeof(RecPod) * (size_t)b.ntpl);
+    for (size_t j = 0; j < b.jobs.size(); j++) {
+        const BatchJob &J = b.jobs[j];
+        for (int t = 0; t < J.T; t++) {
+            const RecPod &f = res[J.tmpl0 + t];
+            int64_t D_t = tst[2 * (J.tmpl0 + t) + 1];
+            zts_result r;
+            std::memset(&r, 0, sizeof r);
+            int64_t L = (int64_t)J.Ly * J.Lx;
+            r.n_locations = L;
+            r.device_ms = ms;
+            r.phase_ms[0] = ms;
+            r.batch_size = (int32_t)b.items.size();
+            if (D_t == 0 || !f.valid) {
+                r.status = D_t == 0 ? ZTS_E_DEGENERATE : ZTS_E_DEVICE;
+            } else {
+                r.y = (int32_t)(f.l / J.Lx);
+                r.x = (int32_t)(f.l % J.Lx);
+                r.rho = f.rho;
+                r.rho32 = f.r32max;
+                r.num = f.num;
+                r.den_t = D_t;
+                r.den_r = f.dr;
+                r.n_computed = L;
+                r.group_h = r.group_w = 1;
+                r.best0 = f.rho;
+                r.best0_y = r.y;
+                r.best0_x = r.x;
+                r.status = ZTS_OK;
+            }
+            out[b.members[j][t]] = r;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ synchronous helpers
+
+namespace {
 
 template <class F> zts_status guarded(Ctx *c, F &&f)
 {
@@ -882,6 +1197,43 @@ template <class F> zts_status guarded(Ctx *c, F &&f)
     } catch (const std::bad_alloc &) {
         return ZTS_E_NOMEM;
     }
+}
+
+// One query on the main slot (context lock held).
+void run_query_main(Ctx *c, Image *im, const uint8_t *tpl, int m, int n, int64_t stride, bool device,
+                    hipStream_t caller, zts_mode mode, const zts_params &pr, zts_result *out, int8_t *dec,
+                    int64_t *num_map = nullptr, int64_t *dr_map = nullptr, float *rho_map = nullptr)
+{
+    QueryPlan q = plan_query(c, c->main, im, m, n, mode, pr, dec != nullptr);
+    q.num_map = num_map;
+    q.dr_map = dr_map;
+    q.rho_map = rho_map;
+    zts_status st;
+    try {
+        stage_template(c->main, tpl, m, n, stride, device, caller);
+        launch_query(q, c->main, dec);
+        st = finish_query(q, c->main, out);
+    } catch (...) {
+        unpin_query(q);
+        throw;
+    }
+    unpin_query(q);
+    if (st != ZTS_OK)
+        throw ZtsError{st};
+}
+
+// A batch on the main slot (context lock held).
+void run_batch_main(Ctx *c, std::vector<BatchItem> items, zts_result *out)
+{
+    BatchPlan b = plan_batch(c, c->main, std::move(items));
+    try {
+        launch_batch_plan(b, c->main);
+        finish_batch(b, c->main, out);
+    } catch (...) {
+        unpin_batch(b);
+        throw;
+    }
+    unpin_batch(b);
 }
 
 zts_status load_common(Ctx *c, const void *src, int rows, int cols, int64_t stride, bool device, hipStream_t caller,
@@ -914,23 +1266,28 @@ zts_status load_common(Ctx *c, const void *src, int rows, int cols, int64_t stri
     });
 }
 
+bool valid_mode(zts_mode mode)
+{
+    return mode == ZTS_FULL || mode == ZTS_FULL_MFMA || mode == ZTS_TE_FIXED || mode == ZTS_EGS || mode == ZTS_OPTA;
+}
+
 }  // namespace
+
+}  // namespace zts
 
 // ====================================================================== C ABI
 
-struct zts_ctx {
-    Ctx c;
-};
+using namespace zts;
 
 extern "C" {
 
-void zts_params_default(zts_params *p)
+ZTS_API void zts_params_default(zts_params *p)
 {
     if (p)
         fill_default(p);
 }
 
-const char *zts_status_str(zts_status s)
+ZTS_API const char *zts_status_str(zts_status s)
 {
     switch (s) {
     case ZTS_OK: return "ok";
@@ -950,9 +1307,11 @@ const char *zts_status_str(zts_status s)
     return "unknown status";
 }
 
-zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
+ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
 {
     if (!out)
+        return ZTS_E_ARG;
+    if (params && (params->max_inflight < 0 || params->max_inflight > 64 || params->max_queued < 0))
         return ZTS_E_ARG;
     zts_ctx *z = new (std::nothrow) zts_ctx;
     if (!z)
@@ -960,82 +1319,85 @@ zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
     Ctx &c = z->c;
     c.device = params ? params->device : 0;
     c.budget = params ? params->hbm_budget_bytes : 0;
+    if (params && params->max_inflight > 0)
+        c.max_inflight = params->max_inflight;
+    if (params && params->max_queued > 0)
+        c.max_queued = params->max_queued;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) {
         delete z;
         return ZTS_E_DEVICE;
     }
-    if (hipSetDevice(c.device) != hipSuccess || hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreate(&c.ev0) != hipSuccess || hipEventCreate(&c.ev1) != hipSuccess ||
-        hipEventCreate(&c.evp[0]) != hipSuccess || hipEventCreate(&c.evp[1]) != hipSuccess ||
-        hipEventCreate(&c.evp[2]) != hipSuccess || hipEventCreate(&c.evp[3]) != hipSuccess ||
-        hipEventCreate(&c.evp[4]) != hipSuccess || hipEventCreate(&c.evp[5]) != hipSuccess ||
-        hipEventCreate(&c.evp[6]) != hipSuccess || hipEventCreate(&c.evp[7]) != hipSuccess ||
-        hipHostMalloc((void **)&c.h_qs, sizeof(QState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c.h_cnt, 64, hipHostMallocDefault) != hipSuccess) {
+    try {
+        hip_check(hipSetDevice(c.device));
+        c.main.init();
+        c.stream = c.main.stream;
+        c.h_cnt.grow(64);
+    } catch (const ZtsError &e) {
+        c.main.destroy();
         delete z;
-        return ZTS_E_DEVICE;
+        return e.st;
     }
     *out = z;
     return ZTS_OK;
 }
 
-void zts_destroy(zts_ctx *z)
+ZTS_API void zts_destroy(zts_ctx *z)
 {
     if (!z)
         return;
     Ctx &c = z->c;
+    server_shutdown(&c);
     {
         std::lock_guard<std::mutex> lk(c.mu);
         (void)hipSetDevice(c.device);
         if (c.stream)
             (void)hipStreamSynchronize(c.stream);
         c.images.clear();
-        c.qs.reset(); c.recs.reset(); c.gnum.reset(); c.gtheta.reset(); c.tpl.reset(); c.dec.reset();
-        c.counter.reset(); c.tmp32.reset(); c.viol.reset(); c.colmask.reset();
-        if (c.h_qs) (void)hipHostFree(c.h_qs);
-        if (c.h_tpl) (void)hipHostFree(c.h_tpl);
-        if (c.h_cnt) (void)hipHostFree(c.h_cnt);
-        if (c.ev0) (void)hipEventDestroy(c.ev0);
-        if (c.ev1) (void)hipEventDestroy(c.ev1);
-        for (int k = 0; k < 8; k++)
-            if (c.evp[k]) (void)hipEventDestroy(c.evp[k]);
-        if (c.stream) (void)hipStreamDestroy(c.stream);
+        c.counter.reset();
+        c.tmp32.reset();
+        c.viol.reset();
+        c.colmask.reset();
+        c.h_cnt.reset();
+        c.main.destroy();
     }
     delete z;
 }
 
-zts_status zts_image_load(zts_ctx *z, const uint8_t *host, int32_t rows, int32_t cols, int64_t stride, int32_t *id)
+ZTS_API zts_status zts_image_load(zts_ctx *z, const uint8_t *host, int32_t rows, int32_t cols, int64_t stride,
+                                  int32_t *id)
 {
     if (!z)
         return ZTS_E_ARG;
     return load_common(&z->c, host, rows, cols, stride, false, nullptr, id);
 }
 
-zts_status zts_image_load_device(zts_ctx *z, const void *dev, int32_t rows, int32_t cols, int64_t stride,
-                                 void *stream, int32_t *id)
+ZTS_API zts_status zts_image_load_device(zts_ctx *z, const void *dev, int32_t rows, int32_t cols, int64_t stride,
+                                         void *stream, int32_t *id)
 {
     if (!z)
         return ZTS_E_ARG;
     return load_common(&z->c, dev, rows, cols, stride, true, (hipStream_t)stream, id);
 }
 
-zts_status zts_image_unload(zts_ctx *z, int32_t id)
+ZTS_API zts_status zts_image_unload(zts_ctx *z, int32_t id)
 {
     if (!z)
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
-        find_image(c, id);
+        Image *im = find_image(c, id);
+        if (im->busy)
+            throw ZtsError{ZTS_E_BUSY};
         hip_check(hipStreamSynchronize(c->stream));
         c->images.erase(id);
     });
 }
 
-zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode mode, const zts_params *params,
-                       void *stream)
+ZTS_API zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode mode,
+                               const zts_params *params, void *stream)
 {
-    if (!z)
+    if (!z || !valid_mode(mode))
         return ZTS_E_ARG;
     (void)stream;
     return guarded(&z->c, [&] {
@@ -1050,8 +1412,8 @@ zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode
             pr = *params;
         else
             fill_default(&pr);
-        if (mode == ZTS_FULL) {
-            stats_for(c, im, m, n);
+        if (mode == ZTS_FULL || mode == ZTS_FULL_MFMA) {
+            stats_entry(c, im, m, n, c->stream);
             hip_check(hipStreamSynchronize(c->stream));
             return;
         }
@@ -1059,7 +1421,8 @@ zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode
     });
 }
 
-zts_status zts_prep_query(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode mode, zts_prep_info *out)
+ZTS_API zts_status zts_prep_query(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode mode,
+                                  zts_prep_info *out)
 {
     if (!z || !out)
         return ZTS_E_ARG;
@@ -1072,7 +1435,7 @@ zts_status zts_prep_query(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_m
     });
 }
 
-zts_status zts_prep_image(zts_ctx *z, int32_t image, int32_t m, int32_t n, uint8_t *host_out)
+ZTS_API zts_status zts_prep_image(zts_ctx *z, int32_t image, int32_t m, int32_t n, uint8_t *host_out)
 {
     if (!z || !host_out)
         return ZTS_E_ARG;
@@ -1088,12 +1451,10 @@ zts_status zts_prep_image(zts_ctx *z, int32_t image, int32_t m, int32_t n, uint8
     });
 }
 
-zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
-                      zts_mode mode, const zts_params *params, zts_result *out, int8_t *decision)
+ZTS_API zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
+                              zts_mode mode, const zts_params *params, zts_result *out, int8_t *decision)
 {
-    if (!z || !out)
-        return ZTS_E_ARG;
-    if (mode != ZTS_FULL && mode != ZTS_TE_FIXED && mode != ZTS_EGS && mode != ZTS_OPTA)
+    if (!z || !out || !valid_mode(mode))
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
@@ -1104,17 +1465,25 @@ zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int32_t m, 
             pr = *params;
         else
             fill_default(&pr);
-        stage_template(c, tpl, m, n, stride, false, nullptr);
-        run_query(c, im, m, n, mode, pr, out, decision, nullptr, nullptr, nullptr);
+        if (mode == ZTS_FULL_MFMA) {
+            zts_result r;
+            run_batch_main(c, {BatchItem{im, tpl, m, n, stride}}, &r);
+            if (r.status != ZTS_OK)
+                throw ZtsError{r.status};
+            if (decision)
+                std::memset(decision, 2, (size_t)(im->rows - m + 1) * (im->cols - n + 1));
+            *out = r;
+            return;
+        }
+        run_query_main(c, im, tpl, m, n, stride, false, nullptr, mode, pr, out, decision);
     });
 }
 
-zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_dev, int32_t m, int32_t n, int64_t stride,
-                             zts_mode mode, const zts_params *params, void *stream, zts_result *out)
+ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_dev, int32_t m, int32_t n,
+                                     int64_t stride, zts_mode mode, const zts_params *params, void *stream,
+                                     zts_result *out)
 {
-    if (!z || !out)
-        return ZTS_E_ARG;
-    if (mode != ZTS_FULL && mode != ZTS_TE_FIXED && mode != ZTS_EGS && mode != ZTS_OPTA)
+    if (!z || !out || !valid_mode(mode) || mode == ZTS_FULL_MFMA)
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
@@ -1125,136 +1494,37 @@ zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_dev, int
             pr = *params;
         else
             fill_default(&pr);
-        stage_template(c, (const uint8_t *)tpl_dev, m, n, stride, true, (hipStream_t)stream);
-        run_query(c, im, m, n, mode, pr, out, nullptr, nullptr, nullptr, nullptr);
+        run_query_main(c, im, (const uint8_t *)tpl_dev, m, n, stride, true, (hipStream_t)stream, mode, pr, out,
+                       nullptr);
     });
 }
 
-zts_status zts_search_batch(zts_ctx *z, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
-                            const int32_t *n, const int64_t *strides, zts_result *out)
+ZTS_API zts_status zts_search_batch(zts_ctx *z, int32_t image, int32_t count, const uint8_t *const *tpls,
+                                    const int32_t *m, const int32_t *n, const int64_t *strides, zts_result *out)
 {
     if (!z || !tpls || !m || !n || !strides || !out || count < 1)
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
         Image *im = find_image(c, image);
-        std::map<std::pair<int, int>, std::vector<int>> buckets;
+        std::vector<BatchItem> items;
         for (int k = 0; k < count; k++) {
             check_template_args(im, tpls[k], m[k], n[k], strides[k]);
-            buckets[std::make_pair(m[k], n[k])].push_back(k);
+            if (n[k] > 128)
+                throw ZtsError{ZTS_E_SIZE};
+            items.push_back(BatchItem{im, tpls[k], m[k], n[k], strides[k]});
         }
-        // stage every bucket's templates: [T][m][n16] with 0x80 past column n
-        struct Job {
-            int m, n, n16, T, Ly, Lx;
-            size_t off, tst_off, res_off, rec_off;
-            std::vector<int> idx;
-        };
-        std::vector<Job> jobs;
-        size_t tbytes = 0, nres = 0, nrec = 0;
-        for (auto &kv : buckets) {
-            Job j;
-            j.m = kv.first.first;
-            j.n = kv.first.second;
-            j.n16 = (j.n + 15) / 16 * 16;
-            j.T = (int)kv.second.size();
-            j.Ly = im->rows - j.m + 1;
-            j.Lx = im->cols - j.n + 1;
-            j.idx = kv.second;
-            j.off = tbytes;
-            tbytes += ((size_t)j.T * j.m * j.n16 + 255) / 256 * 256;
-            j.res_off = nres;
-            nres += j.T;
-            j.rec_off = nrec;
-            nrec += (size_t)((j.T + 15) / 16) * batch_blocks_per_tile(j.Ly, j.Lx) * 16;
-            jobs.push_back(j);
-        }
-        if (c->h_tpl_bytes < tbytes) {
-            if (c->h_tpl)
-                (void)hipHostFree(c->h_tpl);
-            c->h_tpl = nullptr;
-            hip_check(hipHostMalloc((void **)&c->h_tpl, tbytes, hipHostMallocDefault));
-            c->h_tpl_bytes = tbytes;
-        }
-        for (auto &j : jobs)
-            for (int t = 0; t < j.T; t++) {
-                int k = j.idx[t];
-                uint8_t *dst = c->h_tpl + j.off + (size_t)t * j.m * j.n16;
-                for (int r = 0; r < j.m; r++) {
-                    std::memcpy(dst + (size_t)r * j.n16, tpls[k] + (size_t)r * strides[k], j.n);
-                    std::memset(dst + (size_t)r * j.n16 + j.n, 0x80, j.n16 - j.n);
-                }
-            }
-        DBuf dt, dtst, dres, drec;
-        dalloc(c, dt, tbytes);
-        dalloc(c, dtst, sizeof(int64_t) * 2 * nres);
-        dalloc(c, dres, sizeof(RecPod) * nres);
-        dalloc(c, drec, sizeof(RecPod) * nrec);
-        hip_check(hipMemcpyAsync(dt.ptr, c->h_tpl, tbytes, hipMemcpyHostToDevice, c->stream));
-        std::vector<const int2 *> stats;
-        for (auto &j : jobs)
-            stats.push_back(stats_for(c, im, j.m, j.n));
-        hip_check(hipEventRecord(c->ev0, c->stream));
-        for (size_t q = 0; q < jobs.size(); q++) {
-            Job &j = jobs[q];
-            BatchArgs a;
-            std::memset(&a, 0, sizeof a);
-            a.img = im->img.as<uint8_t>();
-            a.pitch = im->pitch;
-            a.p = im->rows;
-            a.q = im->cols;
-            a.stat = stats[q];
-            a.tpl = dt.as<uint8_t>() + j.off;
-            a.tst = dtst.as<int64_t>() + 2 * j.res_off;
-            a.T = j.T;
-            a.m = j.m;
-            a.n = j.n;
-            a.Ly = j.Ly;
-            a.Lx = j.Lx;
-            a.recs = drec.as<RecPod>() + j.rec_off;
-            hip_check(launch_batch(a, dres.as<RecPod>() + j.res_off, c->stream));
-        }
-        hip_check(hipEventRecord(c->ev1, c->stream));
-        std::vector<RecPod> res(nres);
-        std::vector<int64_t> tst(2 * nres);
-        hip_check(hipMemcpyAsync(res.data(), dres.ptr, sizeof(RecPod) * nres, hipMemcpyDeviceToHost, c->stream));
-        hip_check(hipMemcpyAsync(tst.data(), dtst.ptr, sizeof(int64_t) * 2 * nres, hipMemcpyDeviceToHost, c->stream));
-        hip_check(hipStreamSynchronize(c->stream));
-        float ms = 0.0f;
-        hip_check(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        for (auto &j : jobs)
-            for (int t = 0; t < j.T; t++) {
-                const RecPod &f = res[j.res_off + t];
-                int64_t D_t = tst[2 * (j.res_off + t) + 1];
-                zts_result r;
-                std::memset(&r, 0, sizeof r);
-                int64_t L = (int64_t)j.Ly * j.Lx;
-                r.n_locations = L;
-                r.device_ms = ms;
-                r.phase_ms[0] = ms;
-                if (D_t == 0) {
-                    r.status = ZTS_E_DEGENERATE;
-                } else {
-                    r.y = (int32_t)(f.l / j.Lx);
-                    r.x = (int32_t)(f.l % j.Lx);
-                    r.rho = f.rho;
-                    r.rho32 = f.r32max;
-                    r.num = f.num;
-                    r.den_t = D_t;
-                    r.den_r = f.dr;
-                    r.n_computed = L;
-                    r.group_h = r.group_w = 1;
-                    r.best0 = f.rho;
-                    r.best0_y = r.y;
-                    r.best0_x = r.x;
-                    r.status = ZTS_OK;
-                }
-                out[j.idx[t]] = r;
-            }
+        std::vector<zts_result> res(count);
+        run_batch_main(c, std::move(items), res.data());
+        for (auto &r : res)
+            if (r.status == ZTS_E_DEVICE)
+                throw ZtsError{ZTS_E_DEVICE};
+        std::copy(res.begin(), res.end(), out);
     });
 }
 
-zts_status zts_debug_full_map(zts_ctx *z, int32_t image, const uint8_t *tpl, int32_t m, int32_t n, int64_t stride,
-                              int64_t *num_out, int64_t *den_r_out, float *rho_out)
+ZTS_API zts_status zts_debug_full_map(zts_ctx *z, int32_t image, const uint8_t *tpl, int32_t m, int32_t n,
+                                      int64_t stride, int64_t *num_out, int64_t *den_r_out, float *rho_out)
 {
     if (!z)
         return ZTS_E_ARG;
@@ -1272,9 +1542,9 @@ zts_status zts_debug_full_map(zts_ctx *z, int32_t image, const uint8_t *tpl, int
             dalloc(c, dr, L * 4);
         zts_params pr;
         fill_default(&pr);
-        stage_template(c, tpl, m, n, stride, false, nullptr);
         zts_result res;
-        run_query(c, im, m, n, ZTS_FULL, pr, &res, nullptr, dn.as<int64_t>(), dd.as<int64_t>(), dr.as<float>());
+        run_query_main(c, im, tpl, m, n, stride, false, nullptr, ZTS_FULL, pr, &res, nullptr, dn.as<int64_t>(),
+                       dd.as<int64_t>(), dr.as<float>());
         if (num_out)
             hip_check(hipMemcpy(num_out, dn.ptr, L * 8, hipMemcpyDeviceToHost));
         if (den_r_out)
@@ -1284,8 +1554,8 @@ zts_status zts_debug_full_map(zts_ctx *z, int32_t image, const uint8_t *tpl, int
     });
 }
 
-zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int32_t n, int32_t h, int32_t w,
-                              int64_t *num_out, int64_t *dc_out, int64_t *do_out)
+ZTS_API zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int32_t n, int32_t h, int32_t w,
+                                      int64_t *num_out, int64_t *dc_out, int64_t *do_out)
 {
     if (!z || !num_out || !dc_out || !do_out || h < 1 || w < 1)
         return ZTS_E_ARG;
@@ -1298,7 +1568,8 @@ zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int32_t n, i
             throw ZtsError{ZTS_E_SIZE};
         int Ly = im->rows - m + 1, Lx = im->cols - n + 1;
         size_t L = (size_t)Ly * Lx;
-        const int2 *st = stats_for(c, im, m, n);
+        Stats *st = stats_entry(c, im, m, n, c->stream);
+        PinGuard pin(st->pins);
         DBuf a1, a2, a3;
         dalloc(c, a1, L * 8);
         dalloc(c, a2, L * 8);
@@ -1307,7 +1578,7 @@ zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int32_t n, i
         std::memset(&a, 0, sizeof a);
         a.J = im->img.as<uint8_t>();
         a.pJ = im->pitch;
-        a.statJ = st;
+        a.statJ = st->stat.as<int2>();
         a.m = m;
         a.n = n;
         a.Ly = Ly;
@@ -1326,8 +1597,8 @@ zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int32_t n, i
     });
 }
 
-zts_status zts_debug_blur(zts_ctx *z, const uint8_t *host_in, int32_t rows, int32_t cols, const int32_t *taps,
-                          int32_t d, uint8_t *host_out)
+ZTS_API zts_status zts_debug_blur(zts_ctx *z, const uint8_t *host_in, int32_t rows, int32_t cols,
+                                  const int32_t *taps, int32_t d, uint8_t *host_out)
 {
     if (!z || !host_in || !taps || !host_out || rows < 1 || cols < 1 || d < 0 || d > 32)
         return ZTS_E_ARG;

@@ -134,20 +134,32 @@ struct BcArgs {
     int64_t *num_out, *dj_out, *di_out;
 };
 
-// Batch of up to many templates of one size on int8 MFMA.
-struct BatchArgs {
+// One bucket of a batched launch: the templates of one size searched in one
+// image.  A launch takes a device table of jobs; each kernel's flattened
+// block index selects its job (block0 / fold0 / tmpl0 are the job's first
+// block of k_batch, of the first fold and its first template).
+struct BatchJob {
     const uint8_t *img;
     int64_t pitch;
     int p, q;
-    const int2 *stat;     // per-location statistics for (m, n)
+    const int2 *stat;     // per-location statistics of img for (m, n)
     const uint8_t *tpl;   // uint8 templates, [T][m][n16], 0x80 past column n
     int64_t *tst;         // per template: sum(t'), D_t (written by the launch)
     int T, m, n, n16, Ly, Lx;
-    RecPod *recs;         // [tiles of 16 templates][blocks][16]
+    int gx, gy, gz;       // k_batch blocks: 256-column strips, row strips, tiles of 16 templates
+    int chunks;           // first-fold blocks per tile
+    int block0, fold0, tmpl0;
+    int pad;
+    RecPod *recs;         // batch_job_records(job) records: [gz][gy*gx][16], then [gz][chunks][16]
+    RecPod *out;          // [T] answers
 };
 
-int batch_blocks_per_tile(int Ly, int Lx);
-hipError_t launch_batch(BatchArgs a, RecPod *results, hipStream_t s);
+// Fills n16, gx, gy, gz and chunks from T, m, n, Ly, Lx; false when n > 128.
+bool batch_job_geometry(BatchJob &j);
+size_t batch_job_records(const BatchJob &j);
+// Runs template statistics, the MFMA search, and the two record folds for
+// every job of the table (d_jobs on the device, h_jobs its host copy).
+hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s);
 
 enum { RD_BEST0 = 0, RD_WINDOW = 1, RD_FINAL = 2 };
 hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, int stage, int flag, double delta, hipStream_t s);

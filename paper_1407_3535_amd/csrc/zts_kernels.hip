@@ -3,6 +3,8 @@
 // calls; nothing here allocates.
 #include "zts_kernels.h"
 
+#include <algorithm>
+
 #include "zts_device.h"
 
 namespace zts {
@@ -1068,21 +1070,40 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Template statistics of a batch: one block per template (layout [T][m][n16],
 // columns past n hold 0x80, i.e. int8 zero): tst[2t] = sum(t'), tst[2t+1] = D_t.
-__global__ __launch_bounds__(256) void k_tstats(const uint8_t *__restrict__ tpl, int m, int n, int n16,
-                                                int64_t *__restrict__ tst)
+// Job of a flattened block index: the last job whose first index (block0,
+// fold0 or tmpl0 by F) is <= idx.  The scan is uniform across the block.
+template <int F> __device__ __forceinline__ int batch_job_of(const BatchJob *jobs, int njobs, int idx)
+{
+    int j = 0;
+    while (j + 1 < njobs && (F == 0 ? jobs[j + 1].block0 : F == 1 ? jobs[j + 1].fold0 : jobs[j + 1].tmpl0) <= idx)
+        j++;
+    return j;
+}
+
+// Template statistics of a batch: one block per template (layout [T][m][n16],
+// columns past n hold 0x80, i.e. int8 zero): tst[2t] = sum(t'), tst[2t+1] = D_t.
+__global__ __launch_bounds__(256) void k_tstats(const BatchJob *__restrict__ jobs, int njobs)
 {
     __shared__ int red[8];
-    const uint8_t *tp = tpl + (int64_t)blockIdx.x * m * n16;
+    const BatchJob &a = jobs[batch_job_of<2>(jobs, njobs, blockIdx.x)];
+    const int tt = blockIdx.x - a.tmpl0, m = a.m, n16 = a.n16;
+    // m * n16 is a multiple of 16 and each template starts 16-byte aligned
+    const uint4 *tp = (const uint4 *)(a.tpl + (int64_t)tt * m * n16);
+    const uint32_t ones = 0x01010101u;
     int s = 0, s2 = 0;
-    for (int idx = threadIdx.x; idx < m * n16; idx += 256) {
-        int v = (int)tp[idx] - 128;
-        s += v;
-        s2 += v * v;
+    for (int idx = threadIdx.x; idx < (m * n16) >> 4; idx += 256) {
+        uint4 v = tp[idx];
+        uint32_t w[4] = {flip4(v.x), flip4(v.y), flip4(v.z), flip4(v.w)};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            s = dot4(w[k], ones, s);
+            s2 = dot4(w[k], w[k], s2);
+        }
     }
     int64_t S = block_sum_int(s, red), Q = block_sum_int(s2, red);
     if (threadIdx.x == 0) {
-        tst[2 * blockIdx.x] = S;
-        tst[2 * blockIdx.x + 1] = (int64_t)m * n * Q - S * S;
+        a.tst[2 * tt] = S;
+        a.tst[2 * tt + 1] = (int64_t)m * a.n * Q - S * S;
     }
 }
 
@@ -1114,11 +1135,13 @@ __host__ __device__ inline int batch_tstride(int nw16) { return ((nw16 >> 2) & 1
 __host__ __device__ inline int batch_copy_stride(int ww) { return ww + ((8 - ww) & 15); }
 
 template <int R>
-__global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a)
+__global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ jobs, int njobs)
 {
     static_assert(R + 3 + 4 <= 16, "template ring holds 16 rows");
     static_assert(R == kBatchRows, "epilogue LDS layout is sized for kBatchRows");
     extern __shared__ __align__(16) uint32_t smem[];
+    const BatchJob a = jobs[batch_job_of<0>(jobs, njobs, blockIdx.x)];
+    const int lb = blockIdx.x - a.block0, bx = lb % a.gx, by = (lb / a.gx) % a.gy, bz = lb / (a.gx * a.gy);
     constexpr int TNEW = (4 * 16 * 32 + 255) / 256;  // new template words per thread and step, n16 <= 128
     const int n16 = a.n16, nb16 = n16 >> 4, nw16 = n16 >> 2;
     const int WW = (256 + n16 + 16) >> 2;  // dwords per staged image row
@@ -1127,7 +1150,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a)
     const int tstr = batch_tstride(nw16);
     uint32_t *ring = smem + 2 * IMGW;      // 16 template rows x 16 templates x tstr; row ti in slot (ti + R - 1) & 15
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int x0 = blockIdx.x * 256, y0 = blockIdx.y * R, tz = blockIdx.z * 16;
+    const int x0 = bx * 256, y0 = by * R, tz = bz * 16;
     const int steps = (R + a.m - 1 + 3) >> 2;
     const uint32_t *tplg = (const uint32_t *)a.tpl;
     const int rowwords = 16 * nw16;      // words of one template row across the 16 templates (global)
@@ -1334,7 +1357,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a)
         }
     __syncthreads();
     const int ncand = *ccnt;
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int bid = lb;  // record index of this block within its job
     if (ncand <= kBatchCandCap) {
         double *crho = (double *)(smem + kBatchEpiList + 4 * kBatchCandCap);
         int64_t *cnum = (int64_t *)(crho + kBatchCandCap);
@@ -1409,20 +1432,48 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a)
     }
 }
 
-// One block per template: fold the template's block records into its answer.
-// The answer's r32max field is replaced by the binary32 rho of the answer.
-__global__ __launch_bounds__(256) void k_reduce_batch(const RecPod *__restrict__ recs, int blocks_per_tile,
-                                                      const int64_t *__restrict__ tst, RecPod *__restrict__ out)
+// First fold of the per-block records: fold block c of tile z merges the
+// records of blocks 64c .. 64c+63 of the tile for its 16 templates
+// (coalesced: 16 consecutive records per block row) into part[z][c][16].
+__global__ __launch_bounds__(256) void k_fold_batch(const BatchJob *__restrict__ jobs, int njobs)
+{
+    __shared__ RecPod red[256];
+    const BatchJob &a = jobs[batch_job_of<1>(jobs, njobs, blockIdx.x)];
+    const int lb = blockIdx.x - a.fold0, c = lb % a.chunks, z = lb / a.chunks;
+    const int bpt = a.gx * a.gy;
+    const RecPod *recs = a.recs;
+    RecPod *part = a.recs + (size_t)a.gz * bpt * 16;
+    const int t = threadIdx.x, col = t & 15;
+    const int hi = min(bpt, 64 * c + 64);
+    RecPod r = rec_empty();
+    for (int b = 64 * c + (t >> 4); b < hi; b += 16)
+        rec_merge(r, recs[((int64_t)z * bpt + b) * 16 + col]);
+    red[t] = r;
+    __syncthreads();
+    if (t < 16) {
+        RecPod f = red[t];
+        for (int k = 1; k < 16; k++)
+            rec_merge(f, red[t + 16 * k]);
+        part[((int64_t)z * a.chunks + c) * 16 + t] = f;
+    }
+}
+
+// One block per template: fold the template's partial records into its
+// answer.  The answer's r32max field is replaced by the binary32 rho of the
+// answer.
+__global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict__ jobs, int njobs)
 {
     __shared__ RecPod rred[256];
-    int tmpl = blockIdx.x, z = tmpl >> 4, col = tmpl & 15;
+    const BatchJob &a = jobs[batch_job_of<2>(jobs, njobs, blockIdx.x)];
+    const int tt = blockIdx.x - a.tmpl0, z = tt >> 4, col = tt & 15;
+    const RecPod *part = a.recs + (size_t)a.gz * a.gx * a.gy * 16;
     RecPod r = rec_empty();
-    for (int b = threadIdx.x; b < blocks_per_tile; b += blockDim.x)
-        rec_merge(r, recs[((int64_t)z * blocks_per_tile + b) * 16 + col]);
+    for (int b = threadIdx.x; b < a.chunks; b += blockDim.x)
+        rec_merge(r, part[((int64_t)z * a.chunks + b) * 16 + col]);
     RecPod f = block_rec(r, rred);
     if (threadIdx.x == 0) {
-        f.r32max = f.valid ? rho32(f.num, tst[2 * tmpl + 1], f.dr) : 0.0f;
-        out[tmpl] = f;
+        f.r32max = f.valid ? rho32(f.num, a.tst[2 * tt + 1], f.dr) : 0.0f;
+        a.out[tt] = f;
     }
 }
 
@@ -1636,24 +1687,48 @@ hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, in
 
 static constexpr int kBatchR = kBatchRows;
 
-int batch_blocks_per_tile(int Ly, int Lx) { return (int)(blocks_for(Lx, 256) * blocks_for(Ly, kBatchR)); }
-
-hipError_t launch_batch(BatchArgs a, RecPod *results, hipStream_t s)
+bool batch_job_geometry(BatchJob &j)
 {
-    a.n16 = (a.n + 15) / 16 * 16;
-    hipLaunchKernelGGL(k_tstats, dim3(a.T), dim3(256), 0, s, a.tpl, a.m, a.n, a.n16, a.tst);
-    if (a.n16 > 128)
+    j.n16 = (j.n + 15) / 16 * 16;
+    if (j.n16 > 128 || j.T < 1)
+        return false;
+    j.gx = (int)blocks_for(j.Lx, 256);
+    j.gy = (int)blocks_for(j.Ly, kBatchR);
+    j.gz = (int)blocks_for(j.T, 16);
+    j.chunks = (int)blocks_for((int64_t)j.gx * j.gy, 64);
+    return true;
+}
+
+size_t batch_job_records(const BatchJob &j) { return (size_t)j.gz * 16 * ((size_t)j.gx * j.gy + (size_t)j.chunks); }
+
+static size_t batch_lds_bytes(int n16)
+{
+    int WW = (256 + n16 + 16) / 4;
+    size_t lds = ((size_t)2 * 16 * batch_copy_stride(WW) + (size_t)16 * 16 * batch_tstride(n16 / 4)) * 4;
+    lds = std::max(lds, 256 * sizeof(RecPod));
+    return std::max(lds, (size_t)kBatchEpiWords * 4);
+}
+
+hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s)
+{
+    if (njobs < 1)
         return hipErrorInvalidValue;
-    int WW = (256 + a.n16 + 16) / 4;
-    size_t lds = ((size_t)2 * 16 * batch_copy_stride(WW) + (size_t)16 * 16 * batch_tstride(a.n16 / 4)) * 4;
-    if (lds < 256 * sizeof(RecPod))
-        lds = 256 * sizeof(RecPod);
-    if (lds < (size_t)kBatchEpiWords * 4)
-        lds = (size_t)kBatchEpiWords * 4;
-    dim3 grid(blocks_for(a.Lx, 256), blocks_for(a.Ly, kBatchR), blocks_for(a.T, 16));
-    hipLaunchKernelGGL(k_batch<kBatchR>, grid, dim3(256), lds, s, a);
-    hipLaunchKernelGGL(k_reduce_batch, dim3(a.T), dim3(256), 0, s, (const RecPod *)a.recs,
-                       batch_blocks_per_tile(a.Ly, a.Lx), (const int64_t *)a.tst, results);
+    size_t lds = 0;
+    for (int k = 0; k < njobs; k++) {
+        if (h_jobs[k].n16 > 128)
+            return hipErrorInvalidValue;
+        lds = std::max(lds, batch_lds_bytes(h_jobs[k].n16));
+    }
+    const BatchJob &e = h_jobs[njobs - 1];
+    const int ntpl = e.tmpl0 + e.T;
+    const int64_t nblocks = (int64_t)e.block0 + (int64_t)e.gx * e.gy * e.gz;
+    const int64_t nfold = (int64_t)e.fold0 + (int64_t)e.gz * e.chunks;
+    if (nblocks > INT32_MAX || nfold > INT32_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tstats, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
+    hipLaunchKernelGGL(k_batch<kBatchR>, dim3((unsigned)nblocks), dim3(256), lds, s, d_jobs, njobs);
+    hipLaunchKernelGGL(k_fold_batch, dim3((unsigned)nfold), dim3(256), 0, s, d_jobs, njobs);
+    hipLaunchKernelGGL(k_reduce_batch, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
     return hipGetLastError();
 }
 

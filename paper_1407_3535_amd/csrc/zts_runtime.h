@@ -1,0 +1,217 @@
+// Host runtime shared by the library's translation units (not part of the C
+// ABI): errors, budgeted device buffers, execution slots, resident images with
+// their cached per-size tables, and the request queue of the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/zts.h"
+#include "zts_kernels.h"
+
+namespace zts {
+
+struct ZtsError {
+    zts_status st;
+};
+
+void hip_check(hipError_t e);
+
+struct Ctx;
+
+// A device allocation charged against the context's HBM budget.  Allocation,
+// release and the budget counter are guarded by the context mutex.
+struct DBuf {
+    Ctx *ctx = nullptr;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { reset(); }
+    void reset();
+    template <class T> T *as() const { return (T *)ptr; }
+};
+
+// Grows b to at least `bytes`.  Over the budget it first evicts cached tables
+// that no running work holds (least recently used first); ZTS_E_BUDGET if
+// that is not enough.
+void dalloc(Ctx *c, DBuf &b, size_t bytes);
+
+// Pinned host staging that grows on demand.
+struct HostBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { reset(); }
+    void reset();
+    void grow(size_t n);
+    template <class T> T *as() const { return (T *)ptr; }
+};
+
+// Everything one in-flight search needs of its own: a stream (default
+// priority, non-blocking), its timing events, device scratch grown on demand
+// and pinned host staging.  The synchronous entry points use the context's
+// main slot; every serving worker owns one.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evp[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    DBuf qs, recs, gnum, gtheta, tpl, dec;       // one query
+    DBuf bdata, bres, brec;                      // one batched launch
+    HostBuf h_qs, h_stage, h_out;
+    void init();      // throws ZTS_E_DEVICE
+    void destroy();   // waits for the stream first
+    void release_scratch();
+};
+
+struct Stats {
+    DBuf stat;                    // int2 per location: (sum x', sum x'^2)
+    hipEvent_t ready = nullptr;   // recorded after the kernel that builds it
+    int pins = 0;
+    uint64_t last_use = 0;
+    ~Stats();
+};
+
+struct Prepared {
+    zts_mode mode;
+    int m, n, h, w, Gy, Gx, radius;
+    zts_params params;
+    DBuf theta_b, x_b, gsum;       // member vs centre on the searched image
+    DBuf J, Jsat, Jstat;           // OptA: conditioned image and its statistics
+    DBuf theta_c, x_c;             // OptA: conditioned block vs original block (row-major)
+    DBuf theta_cg, x_cg;           // the same in the group-major layout of (h, w)
+    zts_prep_info info;
+    int pins = 0;
+    uint64_t last_use = 0;
+};
+
+struct Image {
+    int rows, cols;
+    int64_t pitch;
+    DBuf img, sat;
+    int busy = 0;  // submitted requests not yet finished
+    std::map<std::pair<int, int>, std::unique_ptr<Stats>> stats;
+    std::map<std::tuple<int, int, int>, std::unique_ptr<Prepared>> prep;
+};
+
+// ------------------------------------------------------------------ serving
+
+enum { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2 };
+
+struct Request {
+    uint64_t ticket;
+    int image;
+    Image *im;
+    std::vector<uint8_t> tpl;  // m x n, pitch n
+    int m, n;
+    zts_mode mode;
+    zts_params pr;
+    int state = RQ_QUEUED;
+    zts_result res;
+    std::chrono::steady_clock::time_point t_submit, t_start;
+};
+
+struct Server {
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::vector<std::thread> workers;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::condition_variable cv_work, cv_done;
+    uint64_t next_ticket = 1;
+    uint64_t completions = 0;  // units of work finished
+    int running = 0;           // workers executing a unit of work
+    int need_memory = 0;       // workers waiting for device memory
+    bool stop = false;
+};
+
+// ------------------------------------------------------------------ context
+
+struct Ctx {
+    std::mutex mu;
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    uint64_t clock = 0;           // LRU stamps
+    Slot main;
+    hipStream_t stream = nullptr; // main.stream: loads, preparation, synchronous searches
+    DBuf counter, tmp32, viol, colmask;  // preparation scratch
+    HostBuf h_cnt;
+    int next_id = 1;
+    std::map<int, std::unique_ptr<Image>> images;
+    int max_inflight = 4;
+    int max_queued = 4096;
+    std::unique_ptr<Server> srv;
+};
+
+Image *find_image(Ctx *c, int id);
+void fill_default(zts_params *p);
+void check_template_args(Image *im, const void *tpl, int m, int n, int64_t stride);
+
+// Per-(m, n) statistics of an image, built on `s` if missing (stream `s` is
+// then ordered after the build; other streams wait on st->ready).
+Stats *stats_entry(Ctx *c, Image *im, int m, int n, hipStream_t s);
+Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr);
+
+// One query, split so that only planning and finishing hold the context lock.
+struct QueryPlan {
+    Image *im = nullptr;
+    Stats *st = nullptr;
+    Prepared *P = nullptr;
+    int m = 0, n = 0, Ly = 0, Lx = 0;
+    zts_mode mode = ZTS_FULL;
+    zts_params pr;
+    bool want_dec = false;
+    int64_t *num_map = nullptr, *dr_map = nullptr;
+    float *rho_map = nullptr;
+};
+QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, const zts_params &pr, bool want_dec);
+void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride, bool device, hipStream_t caller);
+void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host);
+zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out);
+void unpin_query(QueryPlan &q);
+
+// Many templates, possibly of several sizes and images, in one fused launch
+// of the batched MFMA kernels.
+struct BatchItem {
+    Image *im;
+    const uint8_t *tpl;
+    int m, n;
+    int64_t stride;
+};
+struct BatchPlan {
+    std::vector<BatchItem> items;
+    std::vector<BatchJob> jobs;
+    std::vector<std::vector<int>> members;  // item indices of each job, in template order
+    std::vector<Stats *> stats;
+    size_t table_bytes = 0, tpl_bytes = 0, nrec = 0;
+    int ntpl = 0;
+};
+BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items);
+void launch_batch_plan(BatchPlan &b, Slot &S);
+void finish_batch(const BatchPlan &b, Slot &S, zts_result *out);  // out[k] for items[k]
+void unpin_batch(BatchPlan &b);
+
+zts_result error_result(zts_status st);
+
+// Stops the serving workers: queued requests end as ZTS_E_CANCELLED, running
+// ones finish.  Called by zts_destroy before anything is freed.
+void server_shutdown(Ctx *c);
+
+}  // namespace zts
+
+struct zts_ctx {
+    zts::Ctx c;
+};

@@ -1,0 +1,234 @@
+"""GPU tests of the serving entry points (zts_submit / zts_poll / zts_wait /
+zts_cancel) and of ZTS_FULL_MFMA: every served result equals the synchronous
+call's and the oracle's, alone and in a mix, and the queue, cancellation,
+unload, admission and HBM-budget rules hold."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import aerial_image, cut_template
+
+pytestmark = pytest.mark.gpu
+
+Z = pytest.importorskip("paper_1407_3535_amd")
+
+KEYS = ("y", "x", "rho", "num", "den_t", "den_r")
+RHO32_TOL = 1e-6
+
+
+def gpu_or_skip():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def same(a, b, what=""):
+    for k in KEYS:
+        assert a[k] == b[k], f"{what}: {k} {a[k]} != {b[k]}"
+
+
+def same_as_oracle(g, o, what=""):
+    for k in KEYS:
+        assert g[k] == o[k], f"{what}: {k} gpu={g[k]} oracle={o[k]}"
+    assert abs(g["rho32"] - o["rho"]) <= RHO32_TOL, what
+
+
+def mixed_requests(img, seed, count):
+    """(template, mode) pairs: several sizes, modes and a ragged n."""
+    rng = np.random.default_rng(seed)
+    modes = ["full_mfma", "full_mfma", "full_mfma", "full", "egs", "opta", "te_fixed"]
+    out = []
+    for k in range(count):
+        m = int(rng.integers(8, 40))
+        n = int(rng.integers(8, 40))
+        t, _ = cut_template(img, m, n, 7000 + 31 * seed + k, 5.0)
+        out.append((t, modes[k % len(modes)]))
+    return out
+
+
+def test_full_mfma_single_search_matches_oracle():
+    gpu_or_skip()
+    img = aerial_image(140, 230, 11)
+    with Z.Searcher(0) as S:
+        i = S.load(img)
+        for k, (m, n) in enumerate([(16, 16), (9, 33), (40, 17), (1, 5), (64, 128), (130, 24)]):
+            t, _ = cut_template(img, m, n, 300 + k, 4.0)
+            g = S.search(i, t, "full_mfma")
+            o = O.full_search(img, t)
+            same_as_oracle(g, o, f"full_mfma {m}x{n}")
+            assert g["n_computed"] == o["n_locations"] and g["batch_size"] == 1
+        with pytest.raises(Z.ZtsError) as e:
+            S.search(i, np.full((4, 129), 3, np.uint8) + np.eye(4, 129, dtype=np.uint8), "full_mfma")
+        assert e.value.code == -2
+
+
+def test_served_results_equal_sync_and_oracle_alone_and_in_mix():
+    """Each request alone (submit then wait), then all in one burst: identical
+    results, and equal to the synchronous call and to the oracle."""
+    gpu_or_skip()
+    img_a = aerial_image(200, 260, 21)
+    img_b = aerial_image(160, 300, 22)
+    with Z.Searcher(0, max_inflight=3) as S:
+        ia, ib = S.load(img_a), S.load(img_b)
+        reqs = [(ia, img_a, t, md) for t, md in mixed_requests(img_a, 1, 14)]
+        reqs += [(ib, img_b, t, md) for t, md in mixed_requests(img_b, 2, 14)]
+        alone = []
+        for i, _, t, md in reqs:
+            st, r = S.wait(S.submit(i, t, md))
+            assert st == 0, (md, t.shape, st)
+            alone.append(r)
+        tickets = [S.submit(i, t, md) for i, _, t, md in reqs]
+        mix = [S.wait(tk) for tk in tickets]
+        batched = 0
+        for k, ((i, img, t, md), a, (st, b)) in enumerate(zip(reqs, alone, mix)):
+            assert st == 0
+            same(a, b, f"request {k} alone vs mix")
+            for f in ("n_computed", "n_eliminated", "n_survivors", "group_h", "group_w"):
+                assert a[f] == b[f], (k, f)
+            sync = S.search(i, t, md)
+            same(a, sync, f"request {k} served vs sync")
+            o = O.full_search(img, t)
+            same_as_oracle(b, o, f"request {k} ({md})")
+            assert b["latency_ms"] >= b["queue_ms"] >= 0.0
+            batched = max(batched, b["batch_size"])
+        assert batched > 1  # MFMA requests queued together shared a launch
+
+
+def test_mfma_batch_across_images_and_sizes():
+    """One fused launch over templates of two images and several sizes."""
+    gpu_or_skip()
+    imgs = [aerial_image(130, 170, 31), aerial_image(150, 120, 32)]
+    with Z.Searcher(0, max_inflight=1) as S:
+        ids = [S.load(im) for im in imgs]
+        blocker = cut_template(imgs[0], 48, 48, 5, 4.0)[0]
+        first = S.submit(ids[0], blocker, "full")  # keeps the one slot busy while the rest queue
+        items = []
+        for k in range(20):
+            j = k % 2
+            m, n = [(16, 16), (20, 40), (33, 7)][k % 3]
+            t, _ = cut_template(imgs[j], m, n, 900 + k, 5.0)
+            items.append((j, t, S.submit(ids[j], t, "full_mfma")))
+        assert S.wait(first)[0] == 0
+        sizes = []
+        for j, t, tk in items:
+            st, r = S.wait(tk)
+            assert st == 0
+            same_as_oracle(r, O.full_search(imgs[j], t), f"image {j} {t.shape}")
+            sizes.append(r["batch_size"])
+        assert max(sizes) > 1
+
+
+def test_poll_wait_timeout_cancel_and_tickets():
+    """One worker slot busy with three exhaustive 128x128 searches over a
+    2048x2048 image (milliseconds each): requests submitted behind them are
+    still queued when the test waits with a zero time-out and cancels."""
+    gpu_or_skip()
+    img = aerial_image(2048, 2048, 41)
+    with Z.Searcher(0, max_inflight=1) as S:
+        i = S.load(img)
+        big = [cut_template(img, 128, 128, k, 4.0)[0] for k in range(3)]
+        small = cut_template(img, 16, 16, 9, 4.0)[0]
+        S.prepare(i, 128, 128, "full")
+        S.prepare(i, 16, 16, "full")
+        t_big = [S.submit(i, t, "full") for t in big]
+        t_q1 = S.submit(i, small, "full")
+        t_q2 = S.submit(i, small, "full")
+        with pytest.raises(Z.ZtsError) as e:
+            S.wait(t_q2, timeout_ns=0)
+        assert e.value.code == -8          # time-out leaves the ticket valid
+        S.cancel(t_q2)
+        assert S.wait(t_q2)[0] == -9       # ends cancelled ...
+        with pytest.raises(Z.ZtsError) as e:
+            S.wait(t_q2)                   # ... and is collected once
+        assert e.value.code == -1
+        with pytest.raises(Z.ZtsError) as e:
+            S.cancel(t_big[0])             # started (or ended): not cancellable
+        assert e.value.code == -7
+        for tk in t_big:
+            st, r = S.wait(tk)
+            assert st == 0 and r["n_computed"] == r["n_locations"]
+        while True:
+            got = S.poll(t_q1)
+            if got is not None:
+                break
+            time.sleep(0.0005)
+        assert got[0] == 0
+        same(got[1], S.search(i, small, "full"), "polled result")
+        with pytest.raises(Z.ZtsError) as e:
+            S.poll(t_q1)                   # collected by the poll above
+        assert e.value.code == -1
+        with pytest.raises(Z.ZtsError) as e:
+            S.poll(12345678)
+        assert e.value.code == -1
+        assert S.pending() == (0, 0)
+
+
+def test_unload_refused_while_requests_reference_the_image():
+    gpu_or_skip()
+    img = aerial_image(600, 600, 51)
+    with Z.Searcher(0, max_inflight=1) as S:
+        i = S.load(img)
+        tks = [S.submit(i, cut_template(img, 64, 64, k, 4.0)[0], "full") for k in range(3)]
+        with pytest.raises(Z.ZtsError) as e:
+            S.unload(i)
+        assert e.value.code == -7
+        for tk in tks:
+            assert S.wait(tk)[0] == 0
+        S.unload(i)
+
+
+def test_queue_limit_and_argument_errors():
+    gpu_or_skip()
+    img = aerial_image(120, 120, 61)
+    with Z.Searcher(0, max_inflight=1, max_queued=4) as S:
+        i = S.load(img)
+        t = cut_template(img, 16, 16, 1, 4.0)[0]
+        with pytest.raises(Z.ZtsError) as e:
+            S.submit_batch(i, [t] * 5)
+        assert e.value.code == -6
+        with pytest.raises(Z.ZtsError) as e:
+            S.submit(i, np.zeros((8, 200), np.uint8), "full_mfma")  # wider than the image
+        assert e.value.code == -2
+        with pytest.raises(Z.ZtsError) as e:
+            S.submit(99, t)
+        assert e.value.code == -4
+        flat = np.full((12, 12), 7, np.uint8)
+        tks = S.submit_batch(i, [t, flat, t])
+        res = [S.wait(k) for k in tks]
+        assert [r[0] for r in res] == [0, -3, 0]
+        same(res[0][1], res[2][1], "same template twice in one batch")
+
+
+def test_budget_eviction_and_budget_error():
+    """A budget that holds the image and a few per-size tables: queries of
+    many sizes still succeed (least recently used tables are evicted); a
+    request that cannot fit even alone fails with ZTS_E_BUDGET."""
+    gpu_or_skip()
+    img = aerial_image(256, 256, 71)
+    budget = 5 << 20
+    with Z.Searcher(0, hbm_budget_bytes=budget, max_inflight=2) as S:
+        i = S.load(img)
+        tpls = [cut_template(img, 8 + 3 * k, 8 + 2 * k, 100 + k, 4.0)[0] for k in range(16)]
+        tks = [S.submit(i, t, "full_mfma" if k % 2 else "full") for k, t in enumerate(tpls)]
+        for t, tk in zip(tpls, tks):
+            st, r = S.wait(tk)
+            assert st == 0
+            same_as_oracle(r, O.full_search(img, t), f"budgeted {t.shape}")
+    with Z.Searcher(0, hbm_budget_bytes=1 << 20) as S:
+        i = S.load(aerial_image(200, 200, 72))  # ~0.36 MB of image and running sums
+        t = cut_template(aerial_image(200, 200, 72), 16, 16, 3, 4.0)[0]
+        st, _ = S.wait(S.submit(i, t, "opta"))
+        assert st == -5
+
+
+def test_destroy_with_work_in_flight():
+    gpu_or_skip()
+    img = aerial_image(700, 700, 81)
+    S = Z.Searcher(0, max_inflight=2)
+    i = S.load(img)
+    for k in range(12):
+        S.submit(i, cut_template(img, 48, 48, k, 4.0)[0], "full_mfma" if k % 2 else "full")
+    S.close()  # cancels what has not started, waits for the rest
