@@ -64,9 +64,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
-    ap.add_argument("--workload", default="query", choices=["query", "batch"],
+    ap.add_argument("--workload", default="query", choices=["query", "batch", "serve"],
                     help="query: 2048x2048 image, one 64x64 template per step; batch: 4096x4096 image, "
-                         "64 templates of sizes 16..128 per step on int8 MFMA")
+                         "64 templates of sizes 16..128 per step on int8 MFMA; serve: 2 resident 4096x4096 "
+                         "and 2 resident 8192x8192 images, queries of sizes 16..128 arriving as a Poisson "
+                         "process, p50/p99 latency at fixed QPS")
+    ap.add_argument("--serve-queries", type=int, default=1000, help="measured queries per load level")
+    ap.add_argument("--serve-slots", type=int, default=4, help="worker slots (launches in flight)")
+    ap.add_argument("--serve-budget-gb", type=int, default=32, help="HBM budget of the serving context")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MB",
                     help="only copy MB megabytes device to device 5 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -92,6 +97,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     w = workload(2)
     img = w["images"][0]
@@ -283,6 +290,134 @@ def bench_batch(args):
         "cpu_baseline": None,
     }
     S.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Serving: resident images, exhaustive searches on int8 MFMA submitted as
+    they arrive (a seeded Poisson process), batched by the library's workers.
+    Capacity X_max is measured closed-loop first, then open-loop latency at
+    0.5 and 0.8 X_max.  Latency runs from the scheduled arrival to the result."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch  # noqa: F401
+
+    import paper_1407_3535_amd as Z
+    from synth import poisson_arrivals, serving_queries, workload
+
+    WARM = 200
+    imgs = workload(5)["images"]
+    nq = args.serve_queries
+    qs = serving_queries(imgs, WARM + nq)
+    warm, meas = qs[:WARM], qs[WARM:]
+    S = Z.Searcher(0, hbm_budget_bytes=args.serve_budget_gb << 30, max_inflight=args.serve_slots)
+    ids = [S.load(im) for im in imgs]
+
+    def L_of(t, j):
+        return (imgs[j].shape[0] - t.shape[0] + 1) * (imgs[j].shape[1] - t.shape[1] + 1)
+
+    def closed_loop(mode, items, window=32):
+        out = [None] * len(items)
+        pending = []
+        t0 = time.perf_counter()
+        k = 0
+        while k < len(items) and len(pending) < window:
+            t, j, _ = items[k]
+            pending.append((k, S.submit(ids[j], t, mode)))
+            k += 1
+        while pending:
+            i, tk = pending.pop(0)
+            out[i] = S.wait(tk)
+            if k < len(items):
+                t, j, _ = items[k]
+                pending.append((k, S.submit(ids[j], t, mode)))
+                k += 1
+        return len(items) / (time.perf_counter() - t0), out
+
+    def open_loop(mode, items, qps, seed):
+        arr = poisson_arrivals(len(items), qps, seed)
+        fifo = queue.Queue()
+        got = [None] * len(items)
+
+        def collect():
+            while True:
+                e = fifo.get()
+                if e is None:
+                    return
+                i, tk, lag = e
+                st, r = S.wait(tk)
+                got[i] = (st, r, lag)
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for i, (t, j, _) in enumerate(items):
+            target = t0 + arr[i]
+            while True:
+                d = target - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(d if d > 0.002 else 0)
+            lag = time.perf_counter() - target
+            fifo.put((i, S.submit(ids[j], t, mode), lag))
+        fifo.put(None)
+        th.join()
+        wall = time.perf_counter() - t0
+        lat = [g[2] * 1e3 + g[1]["latency_ms"] for g in got]
+        assert all(g[0] == 0 for g in got), "a served search failed"
+        locs = sum(L_of(t, j) for t, j, _ in items)
+        per_q = [L_of(t, j) / (l / 1e3) for (t, j, _), l in zip(items, lat)]
+        return {"qps": round(qps, 2), "achieved_qps": round(len(items) / wall, 2),
+                "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+                "loc_per_s": locs / wall, "per_query_loc_per_s_median": percentile(per_q, 50),
+                "mean_batch": float(np.mean([g[1]["batch_size"] for g in got])),
+                "queue_p99_ms": round(percentile([g[1]["queue_ms"] for g in got], 99), 3)}, got
+
+    def note(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    note("images resident; warming up")
+    closed_loop("full_mfma", warm)
+    xmax, cres = closed_loop("full_mfma", meas)
+    note(f"closed-loop capacity {xmax:.1f} queries/s")
+    hits = sum(1 for (t, j, loc), (st, r) in zip(meas, cres) if loc is not None and (r["y"], r["x"]) == loc)
+    cuts = sum(1 for _, _, loc in meas if loc is not None)
+    # device work while serving: launch device time (each result carries its launch's time)
+    dev_s = sum(r["device_ms"] / max(1, r["batch_size"]) for _, r in cres) / 1e3
+    ops = sum(2.0 * L_of(t, j) * t.size for t, j, _ in meas)
+    sub = meas[:max(50, nq // 5)]
+    xmax_full, _ = closed_loop("full", sub)
+    note(f"plain full ZNCC capacity {xmax_full:.1f} queries/s")
+    loads = []
+    for frac, seed in ((0.5, 1), (0.8, 2)):
+        res, _ = open_loop("full_mfma", meas, frac * xmax, 14073535 + 5999 + seed)
+        res["load"] = frac
+        loads.append(res)
+        note(f"open loop at {frac} x capacity: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms")
+    hi = loads[-1]
+    S.close()
+    achieved = ops / dev_s / 1e12
+    out = {
+        "metric": "served exhaustive search: locations/s and p50/p99 latency at fixed QPS",
+        "value": hi["loc_per_s"], "unit": "locations/s", "n_gpus": 1, "steps": nq, "warmup": WARM,
+        "ms_per_step": 1e3 / hi["achieved_qps"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "2 resident 4096x4096 + 2 resident 8192x8192 uint8 images; square queries of "
+                               "sizes uniform in 16..128, image uniform, 50% cut + N(0,8), 50% beta=2 noise "
+                               "patches; Poisson arrivals at 0.5 and 0.8 of the closed-loop capacity",
+                   "mode": "full_mfma", "slots": args.serve_slots, "hbm_budget_gb": args.serve_budget_gb},
+        "capacity_qps": {"full_mfma": round(xmax, 2), "full": round(xmax_full, 2)},
+        "vs_full_zncc": round(xmax / xmax_full, 3),
+        "loads": loads,
+        "cut_queries_found": [hits, cuts],
+        "roofline": {"kernel": "k_batch (fused launches, + k_tstats, k_fold_batch, k_reduce_batch)",
+                     "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_MFMA_I8_TOPS, "unit": "TOP/s",
+                     "frac": round(achieved / PEAK_MFMA_I8_TOPS, 4), "traffic": None,
+                     "algorithmic_ops": ops, "device_s": round(dev_s, 4)},
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

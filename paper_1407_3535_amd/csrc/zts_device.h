@@ -219,7 +219,35 @@ __device__ __forceinline__ int wave_dot_img(const uint8_t *__restrict__ A, int64
     return wave_sum(acc);
 }
 
+// ---------------------------------------------------------------- address spaces
+
+// Pointers read from a device-side table are generic to the compiler, which
+// then emits flat accesses; those count on the LDS counter too, so a wait for
+// LDS data would also wait for outstanding global loads.  Casting to the
+// global address space keeps them global_load / global_store.
+template <class T> __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+// Global loads and stores of the vector and record types (the cast applies to
+// scalar types only).
+__device__ __forceinline__ int2 ld_int2(const int2 *p)
+{
+    uint64_t v = *gptr((const uint64_t *)p);
+    return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
+}
+
 // ---------------------------------------------------------------- best-location records
+
+__device__ __forceinline__ void st_rec(RecPod *p, const RecPod &r)
+{
+    static_assert(sizeof(RecPod) % 8 == 0, "records are stored as 8-byte words");
+    const uint64_t *w = (const uint64_t *)&r;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(RecPod) / 8); k++)
+        gptr((uint64_t *)p)[k] = w[k];
+}
 
 __device__ __forceinline__ bool rec_better(double r1, int64_t l1, double r2, int64_t l2)
 {

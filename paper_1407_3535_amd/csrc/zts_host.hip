@@ -27,12 +27,22 @@ void hip_check(hipError_t e)
 void DBuf::reset()
 {
     if (ptr) {
-        (void)hipFree(ptr);
         if (ctx)
-            ctx->used -= bytes;
+            ctx->free_blocks.emplace(bytes, ptr);  // stays charged to the budget until freed
+        else
+            (void)hipFree(ptr);
     }
     ptr = nullptr;
     bytes = 0;
+}
+
+void release_free_blocks(Ctx *c)
+{
+    for (auto &kv : c->free_blocks) {
+        (void)hipFree(kv.second);
+        c->used -= kv.first;
+    }
+    c->free_blocks.clear();
 }
 
 void HostBuf::reset()
@@ -110,41 +120,51 @@ Stats::~Stats()
 
 namespace {
 
-// Frees cached per-size tables that no running work holds, least recently
-// used first, until `need` more bytes fit the budget.
-bool evict_for(Ctx *c, size_t need)
+// Evicts the least recently used cached per-size table that no running work
+// holds (its buffers go to the free list).  False when there is none.
+bool evict_one(Ctx *c)
 {
-    while (c->used + need > c->budget) {
-        Image *victim = nullptr;
-        bool is_stats = false;
-        uint64_t oldest = UINT64_MAX;
-        std::pair<int, int> skey;
-        std::tuple<int, int, int> pkey;
-        for (auto &kv : c->images) {
-            Image *im = kv.second.get();
-            for (auto &s : im->stats)
-                if (!s.second->pins && s.second->last_use < oldest) {
-                    oldest = s.second->last_use;
-                    victim = im;
-                    is_stats = true;
-                    skey = s.first;
-                }
-            for (auto &p : im->prep)
-                if (!p.second->pins && p.second->last_use < oldest) {
-                    oldest = p.second->last_use;
-                    victim = im;
-                    is_stats = false;
-                    pkey = p.first;
-                }
-        }
-        if (!victim)
-            return false;
-        if (is_stats)
-            victim->stats.erase(skey);
-        else
-            victim->prep.erase(pkey);
+    Image *victim = nullptr;
+    bool is_stats = false;
+    uint64_t oldest = UINT64_MAX;
+    std::pair<int, int> skey;
+    std::tuple<int, int, int> pkey;
+    for (auto &kv : c->images) {
+        Image *im = kv.second.get();
+        for (auto &s : im->stats)
+            if (!s.second->pins && s.second->last_use < oldest) {
+                oldest = s.second->last_use;
+                victim = im;
+                is_stats = true;
+                skey = s.first;
+            }
+        for (auto &p : im->prep)
+            if (!p.second->pins && p.second->last_use < oldest) {
+                oldest = p.second->last_use;
+                victim = im;
+                is_stats = false;
+                pkey = p.first;
+            }
     }
+    if (!victim)
+        return false;
+    if (is_stats)
+        victim->stats.erase(skey);
+    else
+        victim->prep.erase(pkey);
     return true;
+}
+
+// A cached free block of `bytes` .. 2 `bytes`, removed from the list.
+void *take_free_block(Ctx *c, size_t bytes, size_t *got)
+{
+    auto it = c->free_blocks.lower_bound(bytes);
+    if (it == c->free_blocks.end() || it->first > 2 * bytes)
+        return nullptr;
+    void *p = it->second;
+    *got = it->first;
+    c->free_blocks.erase(it);
+    return p;
 }
 
 }  // namespace
@@ -157,15 +177,32 @@ void dalloc(Ctx *c, DBuf &b, size_t bytes)
     if (bytes == 0)
         bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
-    if (c->budget && c->used + bytes > c->budget && !evict_for(c, bytes))
-        throw ZtsError{ZTS_E_BUDGET};
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess)
-        throw ZtsError{ZTS_E_NOMEM};
+    size_t got = 0;
+    void *p = take_free_block(c, bytes, &got);
+    while (!p && c->budget && c->used + bytes > c->budget) {
+        if (evict_one(c)) {
+            p = take_free_block(c, bytes, &got);
+            continue;
+        }
+        if (c->free_blocks.empty())
+            throw ZtsError{ZTS_E_BUDGET};
+        auto big = std::prev(c->free_blocks.end());  // give back the largest cached block
+        (void)hipFree(big->second);
+        c->used -= big->first;
+        c->free_blocks.erase(big);
+    }
+    if (!p) {
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            release_free_blocks(c);
+            if (hipMalloc(&p, bytes) != hipSuccess)
+                throw ZtsError{ZTS_E_NOMEM};
+        }
+        got = bytes;
+        c->used += bytes;
+    }
     b.ctx = c;
     b.ptr = p;
-    b.bytes = bytes;
-    c->used += bytes;
+    b.bytes = got;
 }
 
 zts_result error_result(zts_status st)
@@ -1025,32 +1062,56 @@ BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items)
 {
     BatchPlan b;
     b.items = std::move(items);
-    std::map<std::tuple<Image *, int, int>, int> jid;
+    // buckets of (image, m, n) in first-appearance order
+    std::map<std::tuple<Image *, int, int>, int> bid;
+    std::vector<std::vector<int>> buckets;
     for (int k = 0; k < (int)b.items.size(); k++) {
         const BatchItem &it = b.items[k];
         auto key = std::make_tuple(it.im, it.m, it.n);
-        auto f = jid.find(key);
-        int j;
-        if (f == jid.end()) {
-            j = (int)b.jobs.size();
-            jid[key] = j;
-            BatchJob J;
-            std::memset(&J, 0, sizeof J);
-            J.img = it.im->img.as<uint8_t>();
-            J.pitch = it.im->pitch;
-            J.p = it.im->rows;
-            J.q = it.im->cols;
-            J.m = it.m;
-            J.n = it.n;
-            J.Ly = it.im->rows - it.m + 1;
-            J.Lx = it.im->cols - it.n + 1;
-            b.jobs.push_back(J);
-            b.members.emplace_back();
+        auto f = bid.find(key);
+        if (f == bid.end()) {
+            bid[key] = (int)buckets.size();
+            buckets.emplace_back();
+            buckets.back().push_back(k);
         } else {
-            j = f->second;
+            buckets[f->second].push_back(k);
         }
-        b.members[j].push_back(k);
     }
+    // A bucket of enough templates shares 16-wide template tiles (k_batch);
+    // smaller ones run each template on its own (k_single, no empty template
+    // columns).  On MI355X a shared tile costs as much as 3 + 0.055 s single
+    // searches, s = sqrt(m n16) (measured for square sizes 16..128 on a
+    // 4096x4096 image).  BATCH_MULTI jobs come first in the table.
+    auto multi_min = [](int m, int n) {
+        double sz = std::sqrt((double)m * ((n + 15) / 16 * 16));
+        return std::max(2, (int)std::ceil(3.0 + 0.055 * sz));
+    };
+    auto add_job = [&](const std::vector<int> &mem, int kind) {
+        const BatchItem &it = b.items[mem[0]];
+        BatchJob J;
+        std::memset(&J, 0, sizeof J);
+        J.img = it.im->img.as<uint8_t>();
+        J.pitch = it.im->pitch;
+        J.p = it.im->rows;
+        J.q = it.im->cols;
+        J.m = it.m;
+        J.n = it.n;
+        J.Ly = it.im->rows - it.m + 1;
+        J.Lx = it.im->cols - it.n + 1;
+        J.kind = kind;
+        b.jobs.push_back(J);
+        b.members.push_back(mem);
+    };
+    for (int pass = 0; pass < 2; pass++)
+        for (auto &bk : buckets) {
+            const BatchItem &it = b.items[bk[0]];
+            bool multi = (int)bk.size() >= multi_min(it.m, it.n) || !batch_single_fits(it.m, it.n);
+            if (pass == 0 && multi)
+                add_job(bk, BATCH_MULTI);
+            if (pass == 1 && !multi)
+                for (int k : bk)
+                    add_job(std::vector<int>{k}, BATCH_SINGLE);
+        }
     const size_t njobs = b.jobs.size();
     b.table_bytes = (njobs * sizeof(BatchJob) + 255) & ~(size_t)255;
     size_t off = b.table_bytes;
@@ -1062,6 +1123,8 @@ BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items)
         J.T = (int)b.members[j].size();
         if (!batch_job_geometry(J))
             throw ZtsError{ZTS_E_SIZE};
+        if (j > 0 && J.kind != b.jobs[j - 1].kind)
+            block0 = 0;  // each kernel numbers its own blocks
         int64_t nb = (int64_t)block0 + (int64_t)J.gx * J.gy * J.gz;
         if (nb > INT32_MAX)
             throw ZtsError{ZTS_E_SIZE};
@@ -1360,6 +1423,7 @@ ZTS_API void zts_destroy(zts_ctx *z)
         c.colmask.reset();
         c.h_cnt.reset();
         c.main.destroy();
+        release_free_blocks(&c);
     }
     delete z;
 }
@@ -1391,6 +1455,7 @@ ZTS_API zts_status zts_image_unload(zts_ctx *z, int32_t id)
             throw ZtsError{ZTS_E_BUSY};
         hip_check(hipStreamSynchronize(c->stream));
         c->images.erase(id);
+        release_free_blocks(c);  // give the image's memory back now
     });
 }
 

@@ -146,19 +146,26 @@ struct BatchJob {
     const uint8_t *tpl;   // uint8 templates, [T][m][n16], 0x80 past column n
     int64_t *tst;         // per template: sum(t'), D_t (written by the launch)
     int T, m, n, n16, Ly, Lx;
-    int gx, gy, gz;       // k_batch blocks: 256-column strips, row strips, tiles of 16 templates
+    int gx, gy, gz;       // blocks: 256-column strips, row strips, tiles of 16 templates
     int chunks;           // first-fold blocks per tile
-    int block0, fold0, tmpl0;
-    int pad;
+    int block0, fold0, tmpl0;  // block0 counts within the kernel that runs the job
+    int kind;             // BATCH_MULTI: up to 16 templates of one size per tile (N = templates);
+                          // BATCH_SINGLE: one template (N = 16 output rows)
     RecPod *recs;         // batch_job_records(job) records: [gz][gy*gx][16], then [gz][chunks][16]
     RecPod *out;          // [T] answers
 };
 
-// Fills n16, gx, gy, gz and chunks from T, m, n, Ly, Lx; false when n > 128.
+enum { BATCH_MULTI = 0, BATCH_SINGLE = 1 };
+
+// Fills n16, gx, gy, gz and chunks from kind, T, m, n, Ly, Lx; false when
+// n > 128 (or, for BATCH_SINGLE, T != 1 or the template does not fit LDS).
 bool batch_job_geometry(BatchJob &j);
+// Whether one m x n template fits the single-template kernel's LDS.
+bool batch_single_fits(int m, int n);
 size_t batch_job_records(const BatchJob &j);
 // Runs template statistics, the MFMA search, and the two record folds for
-// every job of the table (d_jobs on the device, h_jobs its host copy).
+// every job of the table (d_jobs on the device, h_jobs its host copy).  The
+// table lists the BATCH_MULTI jobs first, then the BATCH_SINGLE ones.
 hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s);
 
 enum { RD_BEST0 = 0, RD_WINDOW = 1, RD_FINAL = 2 };

@@ -1194,9 +1194,9 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
                 if (gy < a.p) {
                     const uint8_t *rp = a.img + (int64_t)gy * a.pitch;
                     if (gx + 4 <= a.pitch)
-                        ri[k][0] = *(const uint32_t *)(rp + gx);
+                        ri[k][0] = *gptr((const uint32_t *)(rp + gx));
                     if (gx + 8 <= a.pitch)
-                        ri[k][1] = *(const uint32_t *)(rp + gx + 4);
+                        ri[k][1] = *gptr((const uint32_t *)(rp + gx + 4));
                 }
             }
         }
@@ -1205,7 +1205,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
             rt[k] = 0;
             int ti = 4 * s + tq[k];
             if (tq[k] >= 0 && ti < a.m)
-                rt[k] = flip4(tplg[toff[k] + (int64_t)ti * nw16]);
+                rt[k] = flip4(gptr(tplg)[toff[k] + (int64_t)ti * nw16]);
         }
     };
     // image buffer of step s at smem + (s & 1) * IMGW (offsets, not a pointer
@@ -1285,8 +1285,8 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
     const int tn = tz + (lane & 15);
     int64_t St = 0, Dt = 0;
     if (tn < a.T) {
-        St = a.tst[2 * tn];
-        Dt = a.tst[2 * tn + 1];
+        St = gptr(a.tst)[2 * tn];
+        Dt = gptr(a.tst)[2 * tn + 1];
     }
     const float qnan = __int_as_float(0x7fc00000);
     int *sxs = (int *)smem;                              // [R][256]
@@ -1294,18 +1294,20 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
     float *bmx = (float *)(smem + 2 * R * 256);          // [4 waves][16 templates]
     int *ccnt = (int *)(smem + 2 * R * 256 + 64);
     int4 *clist = (int4 *)(smem + kBatchEpiList);        // (template, location in block, acc, 0)
+    {
+        // every load unconditional (clamped to the map) so all R are in flight together
+        int2 stv[R];
+        const int xc = min(x0 + t, a.Lx - 1);
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        int y = y0 + r, x = x0 + t, sx = 0;
-        float ir = qnan;
-        if (y < a.Ly && x < a.Lx) {
-            int2 st = a.stat[(int64_t)y * a.Lx + x];
-            int64_t dr = var_num(mn, st);
-            sx = st.x;
-            ir = dr > 0 ? 1.0f / sqrtf((float)dr) : 0.0f;
+        for (int r = 0; r < R; r++)
+            stv[r] = ld_int2(a.stat + ((int64_t)min(y0 + r, a.Ly - 1) * a.Lx + xc));
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            bool in = y0 + r < a.Ly && x0 + t < a.Lx;
+            int64_t dr = var_num(mn, stv[r]);
+            sxs[r * 256 + t] = in ? stv[r].x : 0;
+            irss[r * 256 + t] = !in ? qnan : dr > 0 ? 1.0f / sqrtf((float)dr) : 0.0f;
         }
-        sxs[r * 256 + t] = sx;
-        irss[r * 256 + t] = ir;
     }
     if (t == 0)
         *ccnt = 0;
@@ -1366,10 +1368,10 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
             int4 c = clist[e];
             int tg = tz + c.x;
             int64_t l = (int64_t)(y0 + (c.y >> 8)) * a.Lx + x0 + (c.y & 255);
-            int2 st = a.stat[l];
+            int2 st = ld_int2(a.stat + (l));
             int64_t dr = var_num(mn, st);
-            int64_t num = mn * (int64_t)c.z - a.tst[2 * tg] * (int64_t)st.x;
-            crho[e] = rho64(num, a.tst[2 * tg + 1], dr);
+            int64_t num = mn * (int64_t)c.z - gptr(a.tst)[2 * tg] * (int64_t)st.x;
+            crho[e] = rho64(num, gptr(a.tst)[2 * tg + 1], dr);
             cnum[e] = num;
             cdr[e] = dr;
         }
@@ -1389,7 +1391,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
                     b.valid = 1;
                 }
             }
-            a.recs[(int64_t)bid * 16 + t] = b;
+            st_rec(a.recs + (int64_t)bid * 16 + t, b);
         }
         return;
     }
@@ -1412,7 +1414,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
             int x = x0 + 64 * wv + 16 * mt + 4 * g4 + v;
             if (tok && y < a.Ly && x < a.Lx) {
                 int64_t l = (int64_t)y * a.Lx + x;
-                int2 stl = a.stat[l];
+                int2 stl = ld_int2(a.stat + (l));
                 int64_t dr = var_num(mn, stl);
                 int64_t num = mn * (int64_t)slice[e * 64 + lane] - St * (int64_t)stl.x;
                 rec_offer(rec, rho32(num, Dt, dr), l, num, Dt, dr);
@@ -1428,8 +1430,304 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
         for (int w = 0; w < 4; w++)
             for (int gg = 0; gg < 4; gg++)
                 rec_merge(b, wr[w * 64 + gg * 16 + t]);
-        a.recs[(int64_t)bid * 16 + t] = b;
+        st_rec(a.recs + (int64_t)bid * 16 + t, b);
     }
+}
+
+// Cross-correlation of ONE template at every location as an implicit GEMM on
+// v_mfma_i32_16x16x64_i8 with M = 16 locations of a row, N = 16 consecutive
+// output rows and K = 4 image rows x 16 columns.  For image rows 4s..4s+3
+// and output row y0 + 16 rg + j, lane (j, g) of the B fragment carries
+// template row 4s + g - 16 rg - j (a Toeplitz arrangement; rows outside the
+// template read an all-zero row), so one A fragment feeds every row group.
+// The template is staged whole in LDS once; the image streams through LDS
+// in 4-row steps as in k_batch.  A wave holds RG row groups x MT M-tiles; the
+// block's four waves sit side by side: 16 RG rows x 256 columns per block.
+// Row groups that meet no template row in a step skip their MFMAs.
+constexpr int kSingleRG = 8;
+constexpr int kSingleRows = 16 * kSingleRG;
+constexpr int kSingleCap = 256;   // candidate list entries (one per thread)
+// Epilogue LDS (dwords): per wave a 16 x 64 value slice (overflow path) and a
+// statistics buffer of 64 lanes x 36 dwords (a lane's 16 int2 contiguous, the
+// lane stride padded for conflict-free 16-byte reads), then the candidate
+// list, 4 maxima and a counter.  The 256 block records of the final
+// reduction reuse the slices and buffers.
+constexpr int kSingleLaneStride = 36;
+constexpr int kSingleEpiStats = 4 * 16 * 64;
+constexpr int kSingleEpiList = kSingleEpiStats + 4 * 64 * kSingleLaneStride;
+constexpr int kSingleEpiMax = kSingleEpiList + 4 * kSingleCap;
+constexpr int kSingleLdsWords = kSingleEpiMax + 8;
+static_assert(256 * sizeof(RecPod) / 4 <= kSingleEpiList, "records fit below the candidate list");
+
+__host__ __device__ inline int single_tpl_words(int m, int n16) { return (m + 1) * batch_tstride(n16 >> 2); }
+
+template <int RG>
+__global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ jobs, int njobs)
+{
+    static_assert(RG * 16 == kSingleRows, "block rows");
+    constexpr int MT = 4;
+    extern __shared__ __align__(16) uint32_t smem[];
+    const BatchJob a = jobs[batch_job_of<0>(jobs, njobs, blockIdx.x)];
+    const int lb = blockIdx.x - a.block0, bx = lb % a.gx, by = lb / a.gx;
+    const int m = a.m, n16 = a.n16, nb16 = n16 >> 4, nw16 = n16 >> 2;
+    const int WW = (256 + n16 + 16) >> 2;
+    const int CS = batch_copy_stride(WW);
+    const int IMGW = 16 * CS;
+    const int tstr = batch_tstride(nw16);
+    uint32_t *tpl_l = smem + 2 * IMGW;  // rows 0..m-1, then the zero row m
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int x0 = bx * 256, y0 = by * kSingleRows;
+    const int steps = (kSingleRows + m - 1 + 3) >> 2;
+    const uint32_t *tplg = (const uint32_t *)a.tpl;
+
+    for (int idx = t; idx < m * nw16; idx += 256) {
+        int r = idx / nw16, c = idx - r * nw16;
+        tpl_l[r * tstr + c] = flip4(gptr(tplg)[idx]);
+    }
+    for (int idx = t; idx < nw16; idx += 256)
+        tpl_l[m * tstr + idx] = 0;
+
+    uint32_t ri[2][2];
+    auto gload = [&](int s) {
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            int idx = t + 256 * k;
+            ri[k][0] = ri[k][1] = 0x80808080u;
+            if (idx < 4 * WW) {
+                int g = idx / WW, w = idx - g * WW;
+                int gy = y0 + 4 * s + g;
+                int64_t gx = (int64_t)x0 + 4 * w;
+                if (gy < a.p) {
+                    const uint8_t *rp = a.img + (int64_t)gy * a.pitch;
+                    if (gx + 4 <= a.pitch)
+                        ri[k][0] = *gptr((const uint32_t *)(rp + gx));
+                    if (gx + 8 <= a.pitch)
+                        ri[k][1] = *gptr((const uint32_t *)(rp + gx + 4));
+                }
+            }
+        }
+    };
+    auto lstore = [&](int s) {
+        uint32_t *b = smem + (s & 1) * IMGW;
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            int idx = t + 256 * k;
+            if (idx < 4 * WW) {
+                int g = idx / WW, w = idx - g * WW;
+                uint32_t lo = flip4(ri[k][0]), hi = flip4(ri[k][1]);
+                b[(g * 4 + 0) * CS + w] = lo;
+                b[(g * 4 + 1) * CS + w] = bytes_at(hi, lo, 1);
+                b[(g * 4 + 2) * CS + w] = bytes_at(hi, lo, 2);
+                b[(g * 4 + 3) * CS + w] = bytes_at(hi, lo, 3);
+            }
+        }
+    };
+
+    v4i acc[RG][MT];
+#pragma unroll
+    for (int r = 0; r < RG; r++)
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++)
+            acc[r][mt] = v4i{0, 0, 0, 0};
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    const int g = lane >> 4, jr = lane & 15;
+    for (int s = 0; s < steps; s++) {
+        const uint32_t *cur = smem + (s & 1) * IMGW;
+        if (s + 1 < steps)
+            gload(s + 1);
+        for (int cb = 0; cb < nb16; cb++) {
+            v4i A[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++) {
+                int c = 64 * wv + 16 * mt + jr + 16 * cb;
+                __builtin_memcpy(&A[mt], cur + (g * 4 + (c & 3)) * CS + (c >> 2), 16);
+            }
+            // All B fragments first (rows outside the template read the zero
+            // row), so the reads overlap; then the MFMAs of the groups that
+            // meet template rows 4s - 16 rg - 15 .. 4s + 3 - 16 rg.
+            v4i B[RG];
+#pragma unroll
+            for (int rg = 0; rg < RG; rg++) {
+                int tr = 4 * s + g - 16 * rg - jr;
+                int row = (unsigned)tr < (unsigned)m ? tr : m;
+                B[rg] = *(const v4i *)(tpl_l + row * tstr + 4 * cb);
+            }
+#pragma unroll
+            for (int rg = 0; rg < RG; rg++) {
+                if (4 * s + 3 - 16 * rg < 0 || 4 * s - 16 * rg - 15 >= m)
+                    continue;
+#pragma unroll
+                for (int mt = 0; mt < MT; mt++)
+                    acc[rg][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B[rg], acc[rg][mt], 0, 0, 0);
+            }
+        }
+        if (s + 1 < steps)
+            lstore(s + 1);
+        __syncthreads();
+    }
+
+    // Epilogue.  Lane holds rows y0 + 16 rg + (lane & 15), columns
+    // x0 + 64 wv + 16 mt + 4 (lane >> 4) + v.  est = N / sqrt(D_t D_r) in
+    // binary32 from the exact N (as in k_batch); the block maximum over the
+    // one template; the lanes holding values within kEpsRho of it list them;
+    // the listed candidates' canonical binary64 rho gives the block's record.
+    const int64_t mn = (int64_t)m * a.n;
+    const int64_t St = gptr(a.tst)[0], Dt = gptr(a.tst)[1];
+    RecPod *out = a.recs + (int64_t)lb * 16;
+    if (Dt == 0) {  // degenerate template: the host reports it from tst
+        if (t < 16)
+            st_rec(out + t, rec_empty());
+        return;
+    }
+    int4 *clist = (int4 *)(smem + kSingleEpiList);           // (row in block, column, acc, 0)
+    RecPod *red = (RecPod *)smem;
+    float *bmx = (float *)(smem + kSingleEpiMax);
+    int *ccnt = (int *)(smem + kSingleEpiMax + 4);
+    int *slice = (int *)smem + wv * 16 * 64;
+    uint32_t *stb = smem + kSingleEpiStats + wv * 64 * kSingleLaneStride;
+    const double nst = -(double)St, mnd = (double)mn;
+    const float irt = 1.0f / sqrtf((float)Dt);
+    const float qnan = __int_as_float(0x7fc00000);
+    // est from the exact integers: D_r = mn Q - S^2 and N = mn X - S_t S are
+    // exact in binary64 (every term below 2^53), each rounded once to
+    // binary32; 1/sqrt(D_r) by v_rsq_f32 (about 1 ulp), so est is within
+    // 1e-6 of rho, far inside kEpsRho.  D_r = 0 (flat block) gives est = 0.
+    auto est_one = [&](int y, int x, int2 st, int accv) -> float {
+        const double S = (double)st.x;
+        const float drf = (float)fma(mnd, (double)(uint32_t)st.y, -S * S);
+        const float ir = drf > 0.0f ? __builtin_amdgcn_rsqf(drf) : 0.0f;
+        const double nd = fma(mnd, (double)accv, nst * S);
+        return (y < a.Ly && x < a.Lx) ? (float)nd * ir * irt : qnan;
+    };
+    // Statistics of this wave's 16 rows x 64 columns of a row group: lane c
+    // loads column c of every row (512 contiguous bytes per load), then they
+    // are regrouped in LDS so that lane (j, g) finds the 16 values of row j,
+    // columns 16 mt + 4 g + v, contiguous at stb[36 (4 j + g) ..].
+    const int cg = (lane >> 2) & 3, cq = 4 * (lane >> 4) + (lane & 3);
+    const uint32_t *src = stb + kSingleLaneStride * (4 * jr + g);
+    // block-uniform base and 32-bit offsets (rows and columns clamped into
+    // the map; the block's rows span at most 144 x 32767 entries)
+    const int2 *sbase = a.stat + ((int64_t)y0 * a.Lx + x0 + 64 * wv);
+    const int rmax = a.Ly - 1 - y0, lcol = min(lane, a.Lx - 1 - x0 - 64 * wv);
+#define ZTS_STAGE_STATS(rg)                                                                      \
+    {                                                                                            \
+        int2 sv[16];                                                                             \
+        _Pragma("unroll") for (int r = 0; r < 16; r++) sv[r] =                                   \
+            ld_int2(sbase + (min(16 * (rg) + r, rmax) * a.Lx + lcol));                           \
+        _Pragma("unroll") for (int r = 0; r < 16; r++)                                           \
+            *(int2 *)(stb + kSingleLaneStride * (4 * r + cg) + 2 * cq) = sv[r];                  \
+    }
+    // one row group's 16 accumulators into this wave's slice ([value][lane])
+#define ZTS_SLICE_CASE(r)                                                                        \
+    case r:                                                                                      \
+        _Pragma("unroll") for (int q = 0; q < 16; q++) slice[q * 64 + lane] = acc[r][q >> 2][q & 3]; \
+        break;
+    auto to_slice = [&](int rg) {
+        switch (rg) {
+            ZTS_SLICE_CASE(0)
+            ZTS_SLICE_CASE(1)
+            ZTS_SLICE_CASE(2)
+            ZTS_SLICE_CASE(3)
+            ZTS_SLICE_CASE(4)
+            ZTS_SLICE_CASE(5)
+            ZTS_SLICE_CASE(6)
+            ZTS_SLICE_CASE(7)
+        }
+    };
+#undef ZTS_SLICE_CASE
+    static_assert(RG == 8, "to_slice has one case per row group");
+    if (t == 0)
+        *ccnt = 0;
+    // pass 1: block maximum (a rolled loop, so that loads of later row groups
+    // are not hoisted and register pressure stays that of one group)
+    float bm = -INFINITY;
+#pragma unroll 1
+    for (int rg = 0; rg < RG; rg++) {
+        to_slice(rg);
+        ZTS_STAGE_STATS(rg)
+        const int y = y0 + 16 * rg + jr;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            int x = x0 + 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3);
+            int2 st = *(const int2 *)(src + 2 * q);
+            bm = fmaxf(bm, est_one(y, x, st, slice[q * 64 + lane]));
+        }
+    }
+    float wm = bm;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        wm = fmaxf(wm, __shfl_xor(wm, o));
+    if (lane == 0)
+        bmx[wv] = wm;
+    __syncthreads();
+    const float thr = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3])) - kEpsRho;
+    // pass 2 in the waves holding a value near the maximum (normally one)
+    if (__any(bm >= thr)) {
+#pragma unroll 1
+        for (int rg = 0; rg < RG; rg++) {
+            to_slice(rg);
+            ZTS_STAGE_STATS(rg)
+            const int y = y0 + 16 * rg + jr;
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                int xc = 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3);
+                int2 st = *(const int2 *)(src + 2 * q);
+                int accv = slice[q * 64 + lane];
+                if (est_one(y, x0 + xc, st, accv) >= thr) {
+                    int k = atomicAdd(ccnt, 1);
+                    if (k < kSingleCap)
+                        clist[k] = make_int4(16 * rg + jr, xc, accv, 0);
+                }
+            }
+        }
+    }
+#undef ZTS_STAGE_STATS
+    __syncthreads();
+    const int ncand = *ccnt;
+    RecPod r = rec_empty();
+    if (ncand <= kSingleCap) {
+        if (t < ncand) {
+            int4 c = clist[t];
+            int64_t l = (int64_t)(y0 + c.x) * a.Lx + x0 + c.y;
+            int2 st = ld_int2(a.stat + (l));
+            int64_t dr = var_num(mn, st);
+            int64_t num = mn * (int64_t)c.z - St * (int64_t)st.x;
+            r.rho = rho64(num, Dt, dr);
+            r.l = l;
+            r.num = num;
+            r.dr = dr;
+            r.valid = 1;
+        }
+    } else {
+        // overflow: streaming band selection over every value of the lane,
+        // one row group at a time through this wave's LDS slice
+#pragma unroll
+        for (int rg = 0; rg < RG; rg++) {
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    slice[(mt * 4 + v) * 64 + lane] = acc[rg][mt][v];
+            int y = y0 + 16 * rg + jr;
+#pragma unroll 1
+            for (int e = 0; e < 16; e++) {
+                int x = x0 + 64 * wv + 16 * (e >> 2) + 4 * g + (e & 3);
+                if (y < a.Ly && x < a.Lx) {
+                    int64_t l = (int64_t)y * a.Lx + x;
+                    int2 st = ld_int2(a.stat + (l));
+                    int64_t dr = var_num(mn, st);
+                    int64_t num = mn * (int64_t)slice[e * 64 + lane] - St * (int64_t)st.x;
+                    rec_offer(r, rho32(num, Dt, dr), l, num, Dt, dr);
+                }
+            }
+        }
+    }
+    __syncthreads();  // the records below reuse the slices and buffers
+    RecPod best = block_rec(r, red);
+    if (t < 16)
+        st_rec(out + t, t == 0 ? best : rec_empty());
 }
 
 // First fold of the per-block records: fold block c of tile z merges the
@@ -1687,14 +1985,31 @@ hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, in
 
 static constexpr int kBatchR = kBatchRows;
 
+bool batch_single_fits(int m, int n)
+{
+    int n16 = (n + 15) / 16 * 16;
+    if (n16 > 128 || m < 1 || m > 2048)
+        return false;
+    int WW = (256 + n16 + 16) / 4;
+    size_t words = (size_t)2 * 16 * batch_copy_stride(WW) + (size_t)single_tpl_words(m, n16);
+    return words * 4 <= 64 * 1024;
+}
+
 bool batch_job_geometry(BatchJob &j)
 {
     j.n16 = (j.n + 15) / 16 * 16;
     if (j.n16 > 128 || j.T < 1)
         return false;
     j.gx = (int)blocks_for(j.Lx, 256);
-    j.gy = (int)blocks_for(j.Ly, kBatchR);
-    j.gz = (int)blocks_for(j.T, 16);
+    if (j.kind == BATCH_SINGLE) {
+        if (j.T != 1 || !batch_single_fits(j.m, j.n))
+            return false;
+        j.gy = (int)blocks_for(j.Ly, kSingleRows);
+        j.gz = 1;
+    } else {
+        j.gy = (int)blocks_for(j.Ly, kBatchR);
+        j.gz = (int)blocks_for(j.T, 16);
+    }
     j.chunks = (int)blocks_for((int64_t)j.gx * j.gy, 64);
     return true;
 }
@@ -1709,24 +2024,46 @@ static size_t batch_lds_bytes(int n16)
     return std::max(lds, (size_t)kBatchEpiWords * 4);
 }
 
+static size_t single_lds_bytes(int m, int n16)
+{
+    int WW = (256 + n16 + 16) / 4;
+    size_t lds = ((size_t)2 * 16 * batch_copy_stride(WW) + (size_t)single_tpl_words(m, n16)) * 4;
+    return std::max(lds, (size_t)kSingleLdsWords * 4);
+}
+
 hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s)
 {
     if (njobs < 1)
         return hipErrorInvalidValue;
-    size_t lds = 0;
+    int nm = 0;
+    while (nm < njobs && h_jobs[nm].kind == BATCH_MULTI)
+        nm++;
+    size_t lds_m = 0, lds_s = 0;
+    int64_t blocks_m = 0, blocks_s = 0;
     for (int k = 0; k < njobs; k++) {
-        if (h_jobs[k].n16 > 128)
+        const BatchJob &j = h_jobs[k];
+        if (j.n16 > 128 || (k >= nm && j.kind != BATCH_SINGLE))
             return hipErrorInvalidValue;
-        lds = std::max(lds, batch_lds_bytes(h_jobs[k].n16));
+        int64_t end = (int64_t)j.block0 + (int64_t)j.gx * j.gy * j.gz;
+        if (k < nm) {
+            lds_m = std::max(lds_m, batch_lds_bytes(j.n16));
+            blocks_m = end;
+        } else {
+            lds_s = std::max(lds_s, single_lds_bytes(j.m, j.n16));
+            blocks_s = end;
+        }
     }
     const BatchJob &e = h_jobs[njobs - 1];
     const int ntpl = e.tmpl0 + e.T;
-    const int64_t nblocks = (int64_t)e.block0 + (int64_t)e.gx * e.gy * e.gz;
     const int64_t nfold = (int64_t)e.fold0 + (int64_t)e.gz * e.chunks;
-    if (nblocks > INT32_MAX || nfold > INT32_MAX)
+    if (blocks_m > INT32_MAX || blocks_s > INT32_MAX || nfold > INT32_MAX || lds_m > 65536 || lds_s > 65536)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_tstats, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
-    hipLaunchKernelGGL(k_batch<kBatchR>, dim3((unsigned)nblocks), dim3(256), lds, s, d_jobs, njobs);
+    if (nm > 0)
+        hipLaunchKernelGGL(k_batch<kBatchR>, dim3((unsigned)blocks_m), dim3(256), lds_m, s, d_jobs, nm);
+    if (nm < njobs)
+        hipLaunchKernelGGL(k_single<kSingleRG>, dim3((unsigned)blocks_s), dim3(256), lds_s, s, d_jobs + nm,
+                           njobs - nm);
     hipLaunchKernelGGL(k_fold_batch, dim3((unsigned)nfold), dim3(256), 0, s, d_jobs, njobs);
     hipLaunchKernelGGL(k_reduce_batch, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
     return hipGetLastError();

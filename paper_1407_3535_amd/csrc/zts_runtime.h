@@ -43,10 +43,12 @@ struct DBuf {
     template <class T> T *as() const { return (T *)ptr; }
 };
 
-// Grows b to at least `bytes`.  Over the budget it first evicts cached tables
-// that no running work holds (least recently used first); ZTS_E_BUDGET if
-// that is not enough.
+// Grows b to at least `bytes`: a cached free block of at most twice the size
+// if there is one, else a new allocation.  Over the budget it evicts cached
+// tables that no running work holds (least recently used first), then frees
+// cached blocks; ZTS_E_BUDGET if that is not enough.
 void dalloc(Ctx *c, DBuf &b, size_t bytes);
+void release_free_blocks(Ctx *c);
 
 // Pinned host staging that grows on demand.
 struct HostBuf {
@@ -143,7 +145,11 @@ struct Ctx {
     std::mutex mu;
     int device = 0;
     uint64_t budget = 0;
-    uint64_t used = 0;
+    uint64_t used = 0;            // live buffers and cached free blocks
+    // Released device blocks kept for reuse (size -> pointer): hipFree waits
+    // for the whole device, so blocks are recycled instead and only freed when
+    // the budget needs the room.
+    std::multimap<size_t, void *> free_blocks;
     uint64_t clock = 0;           // LRU stamps
     Slot main;
     hipStream_t stream = nullptr; // main.stream: loads, preparation, synchronous searches

@@ -22,4 +22,6 @@ from .gen import (  # noqa: F401
     cut_template,
     noise_template,
     workload,
+    serving_queries,
+    poisson_arrivals,
 )

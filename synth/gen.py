@@ -187,4 +187,35 @@ def workload(cfg: int):
             t, loc = cut_template(img, int(s), int(s), config_seed(4, "template", k), 6.0)
             tpls.append((t, loc, 0))
         return {"images": [img], "templates": tpls}
+    if cfg == 5:
+        imgs = [aerial_image(4096, 4096, config_seed(5, "image", 0), beta=2.0),
+                aerial_image(4096, 4096, config_seed(5, "image", 1), beta=2.0),
+                aerial_image(8192, 8192, config_seed(5, "image", 2), beta=2.0, clouds=True),
+                aerial_image(8192, 8192, config_seed(5, "image", 3), beta=2.0, clouds=True)]
+        return {"images": imgs, "templates": []}
     raise ValueError(f"unknown workload {cfg}")
+
+
+def serving_queries(images, count: int, seed: int = None):
+    """Query stream of the serving workload: square sizes uniform in 16..128,
+    image chosen uniformly, half cut from the image + N(0, 8), half an
+    independent beta=2 noise patch (no true match).  Returns a list of
+    (template, image index, cut location or None)."""
+    rng = np.random.default_rng(config_seed(5, "template", 0) if seed is None else seed)
+    out = []
+    for k in range(count):
+        s = int(rng.integers(16, 129))
+        j = int(rng.integers(0, len(images)))
+        qseed = int(rng.integers(0, 2**31 - 1))
+        if rng.random() < 0.5:
+            t, loc = cut_template(images[j], s, s, qseed, 8.0)
+            out.append((t, j, loc))
+        else:
+            out.append((noise_template(s, s, qseed), j, None))
+    return out
+
+
+def poisson_arrivals(count: int, qps: float, seed: int = None) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process at rate qps."""
+    rng = np.random.default_rng(config_seed(5, "arrivals") if seed is None else seed)
+    return np.cumsum(rng.exponential(1.0 / qps, size=count))

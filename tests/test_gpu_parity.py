@@ -310,12 +310,14 @@ def test_batch_mfma_workload4_sample(S):
     S.unload(i)
 
 
-@pytest.mark.parametrize("period", [8, 4])
+@pytest.mark.parametrize("period", [16, 8, 4])
 def test_batch_mfma_ties(S, period):
     """A periodic image: every template matches exactly at many locations, so
-    the answer is the smallest-index tie.  Period 8 keeps a block's candidate
-    list within its capacity; period 4 overflows it and takes the streaming
-    fallback."""
+    the answer is the smallest-index tie.  16 templates of one size share
+    template tiles; the two of another size run one per launch block row.
+    Period 16 keeps every block's candidate list within its capacity, period
+    8 overflows the single-template lists, period 4 overflows both kinds and
+    takes the streaming fallbacks."""
     rng = np.random.default_rng(31 + period)
     base = rng.integers(0, 256, (period, period), dtype=np.uint8)
     img = np.ascontiguousarray(np.tile(base, (300 // period + 1, 600 // period + 1))[:300, :600])
@@ -341,6 +343,7 @@ def test_batch_mfma_flat_regions(S):
     half[:, :200] = 40
     for img in (flat, half):
         tpls = [cut_template(aerial_image(120, 400, 6), 16, 16, k, 4.0)[0] for k in range(16)]
+        tpls += [cut_template(aerial_image(120, 400, 6), 20 + k, 12 + 3 * k, 50 + k, 4.0)[0] for k in range(3)]
         tpls.append(np.ascontiguousarray(img[10:42, 180:212]))  # flat on the flat image
         i = S.load(img)
         res = S.search_batch(i, tpls)
