@@ -286,7 +286,8 @@ def bench_batch(args):
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "roofline": {"kernel": "k_batch (+k_tstats, k_reduce_batch)", "bound": "mfma", "achieved": round(achieved, 2),
                      "peak": PEAK_MFMA_I8_TOPS, "unit": "TOP/s", "frac": round(achieved / PEAK_MFMA_I8_TOPS, 4),
-                     "traffic": None, "kernel_ms": round(kms, 4), "algorithmic_ops": 2 * macs},
+                     "traffic": measured_traffic("k_batch"), "kernel_ms": round(kms, 4),
+                     "algorithmic_ops": 2 * macs},
         "cpu_baseline": None,
     }
     S.close()

@@ -268,6 +268,34 @@ def test_workload2_full_size_sampled(S):
     S.unload(i)
 
 
+def test_workload3_full_size(S):
+    """The 8192x8192 workload (clouds, 8 templates of 32, 64 and 128 px with noise and a contrast /
+    brightness change), full OptA.  A dense oracle run is out of reach at this size, so: the exact
+    OptA answer equals both exhaustive GPU searches (v_dot4 and int8 MFMA), the oracle recomputes the
+    exact integers and the binary64 rho at that location, binary32 rho is within 1e-6 of it, the
+    counts cover every location."""
+    w = workload(3)
+    img = w["images"][0]
+    i = S.load(img)
+    found = 0
+    for t, loc, _ in w["templates"]:
+        m, n = t.shape
+        g = S.search(i, t, "opta", refine_radius=2)
+        full = S.search(i, t, "full")
+        mfma = S.search(i, t, "full_mfma")
+        for k in ("y", "x", "rho", "num", "den_t", "den_r"):
+            assert g[k] == full[k] == mfma[k], (t.shape, k)
+        y, x = g["y"], g["x"]
+        sub = O.full_search(img[y:y + m, x:x + n], t)
+        assert (g["num"], g["den_t"], g["den_r"], g["rho"]) == (sub["num"], sub["den_t"], sub["den_r"], sub["rho"])
+        assert abs(g["rho32"] - sub["rho"]) <= RHO32_TOL
+        assert g["n_computed"] + g["n_eliminated"] == g["n_locations"] == (8192 - m + 1) * (8192 - n + 1)
+        found += (y, x) == loc
+    # the hit rate of the cut locations depends on the data only (the answer is exact)
+    print(f"workload 3: {found} of {len(w['templates'])} cut locations found")
+    S.unload(i)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_batch_mfma_matches_oracle(S, seed):
     """Mixed sizes (several templates per size, a 17-template group, ragged n) in one call."""
