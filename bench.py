@@ -141,7 +141,8 @@ def main():
 
     modes = {}
     if not args.no_modes:
-        for name, mode, ref, kw in [("full", "full", 0, {}), ("egs", "egs", 0, {}), ("egs_refine2", "egs", 2, {}),
+        for name, mode, ref, kw in [("full", "full", 0, {}), ("full_mfma", "full_mfma", 0, {}),
+                                    ("egs", "egs", 0, {}), ("egs_refine2", "egs", 2, {}),
                                     ("opta", "opta", 0, {}), ("opta_refine2", "opta", 2, {}),
                                     ("egs_rho_th0.95_refine2", "egs", 2, {"rho_th": 0.95})]:
             rr, mms, ll, pp = run(mode, ref, 20, 3, **kw)

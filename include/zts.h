@@ -133,8 +133,9 @@ typedef struct {
     float phase_ms[4];       /* device time per kernel, HIP events on the library's stream:
                                 ZTS_FULL: [0] dense kernel; ZTS_FULL_MFMA: [0] the batched launch;
                                 other modes: [0] scan 1 (centres), [1] refinement window,
-                                [2] scan 2 (members and survivors); [3] the one-block record
-                                reductions between them */
+                                [2] scan 2 (members and survivors; each block derives the
+                                threshold from the earlier kernels' records), [3] the
+                                one-block reduction to the answer */
     float latency_ms;        /* submitted requests: submission to result ready (host clock) */
     float queue_ms;          /* submitted requests: submission to the start of its launch */
     int32_t batch_size;      /* templates in the launch that produced this result */

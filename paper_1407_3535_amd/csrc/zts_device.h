@@ -219,6 +219,20 @@ __device__ __forceinline__ int wave_dot_img(const uint8_t *__restrict__ A, int64
     return wave_sum(acc);
 }
 
+// ---------------------------------------------------------------- MFMA operands and LDS strides
+
+typedef int v4i __attribute__((ext_vector_type(4)));  // one int8 MFMA operand or accumulator tile
+
+// Dword stride of one template row in the LDS ring: an odd number of 16-byte
+// units, so the 16 lanes of a B-fragment read (16 templates, one row) fall
+// on distinct banks.
+__host__ __device__ inline int batch_tstride(int nw16) { return ((nw16 >> 2) & 1) ? nw16 : nw16 + 4; }
+
+// Dword stride of one byte-shifted image row copy: 8 mod 16, so the 16 lanes
+// of an A-fragment read (4 copies x 4 consecutive words, 2 dwords each) and
+// the next 16 lanes (next row, 4 strides on) fall on distinct banks.
+__host__ __device__ inline int batch_copy_stride(int ww) { return ww + ((8 - ww) & 15); }
+
 // ---------------------------------------------------------------- address spaces
 
 // Pointers read from a device-side table are generic to the compiler, which

@@ -803,7 +803,7 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
         } else {
             const Prepared *P = q.P;
             int radius = query_radius(q);
-            int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h);
+            int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
             int n2 = radius >= 0 ? window_record_count(radius) : 0;
             int n3 = members_record_count(P->Gy, P->Gx);
             dalloc(c, S.recs, sizeof(RecPod) * (size_t)(n1 + n2 + n3));
@@ -878,12 +878,12 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
         a.dec = d_dec;
         hip_check(launch_full(a, st));
         hip_check(hipEventRecord(S.evp[0], st));
-        hip_check(launch_reduce(recs, 0, full_record_count(Ly, Lx), qs, RD_FINAL, 0, pr.margin, st));
+        hip_check(launch_reduce(recs, 0, full_record_count(Ly, Lx), qs, st));
         hip_check(hipEventRecord(S.evp[1], st));
     } else {
         bool opta = q.mode == ZTS_OPTA;
         int radius = query_radius(q);
-        int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h);
+        int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
         int n2 = radius >= 0 ? window_record_count(radius) : 0;
         int n3 = members_record_count(P->Gy, P->Gx);
         const uint8_t *spx = opta ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
@@ -909,11 +909,8 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
         s.qs = qs;
         s.dec = opta ? nullptr : d_dec;
         s.delta = pr.margin;
-        s.set_thr = radius < 0;
         hip_check(launch_centres(s, st));
         hip_check(hipEventRecord(S.evp[0], st));
-        hip_check(launch_reduce(recs, 0, n1, qs, RD_BEST0, radius < 0, pr.margin, st));
-        hip_check(hipEventRecord(S.evp[1], st));
         if (radius >= 0) {
             WinArgs wa;
             std::memset(&wa, 0, sizeof wa);
@@ -938,10 +935,7 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
             wa.delta = pr.margin;
             hip_check(launch_window(wa, st));
         }
-        hip_check(hipEventRecord(S.evp[2], st));
-        if (radius >= 0)
-            hip_check(launch_reduce(recs, n1, n1 + n2, qs, RD_WINDOW, !opta, pr.margin, st));
-        hip_check(hipEventRecord(S.evp[3], st));
+        hip_check(hipEventRecord(S.evp[1], st));
         MemArgs ma;
         std::memset(&ma, 0, sizeof ma);
         ma.I = im->img.as<uint8_t>();
@@ -972,10 +966,14 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
         ma.final_from = opta ? n1 : 0;
         ma.qs = qs;
         ma.dec = d_dec;
+        ma.n_best0 = n1;
+        ma.n_win = n2;
+        ma.include_best0 = !opta;
+        ma.delta = pr.margin;
         hip_check(launch_members(ma, st));
-        hip_check(hipEventRecord(S.evp[4], st));
-        hip_check(launch_reduce(recs, opta ? n1 : 0, n1 + n2 + n3, qs, RD_FINAL, 0, pr.margin, st));
-        hip_check(hipEventRecord(S.evp[5], st));
+        hip_check(hipEventRecord(S.evp[2], st));
+        hip_check(launch_reduce(recs, opta ? n1 : 0, n1 + n2 + n3, qs, st));
+        hip_check(hipEventRecord(S.evp[3], st));
     }
     hip_check(hipEventRecord(S.ev1, st));
     hip_check(hipMemcpyAsync(S.h_qs.ptr, S.qs.ptr, sizeof(QState), hipMemcpyDeviceToHost, st));
@@ -1031,14 +1029,10 @@ zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out)
         hip_check(hipEventElapsedTime(&r.phase_ms[0], S.ev0, S.evp[0]));
         hip_check(hipEventElapsedTime(&r.phase_ms[3], S.evp[0], S.evp[1]));
     } else {
-        float r1, r2, r3;
         hip_check(hipEventElapsedTime(&r.phase_ms[0], S.ev0, S.evp[0]));
-        hip_check(hipEventElapsedTime(&r1, S.evp[0], S.evp[1]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[1], S.evp[1], S.evp[2]));
-        hip_check(hipEventElapsedTime(&r2, S.evp[2], S.evp[3]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[2], S.evp[3], S.evp[4]));
-        hip_check(hipEventElapsedTime(&r3, S.evp[4], S.evp[5]));
-        r.phase_ms[3] = r1 + r2 + r3;
+        hip_check(hipEventElapsedTime(&r.phase_ms[1], S.evp[0], S.evp[1]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[2], S.evp[1], S.evp[2]));
+        hip_check(hipEventElapsedTime(&r.phase_ms[3], S.evp[2], S.evp[3]));
     }
     r.status = ZTS_OK;
     *out = r;
@@ -1184,6 +1178,10 @@ void launch_batch_plan(BatchPlan &b, Slot &S)
         for (int t = 0; t < J.T; t++) {
             const BatchItem &it = b.items[b.members[j][t]];
             uint8_t *dst = dst0 + (size_t)t * J.m * J.n16;
+            if (it.device) {  // copied device to device below; columns past n stay 0x80
+                std::memset(dst, 0x80, (size_t)J.m * J.n16);
+                continue;
+            }
             for (int r = 0; r < J.m; r++) {
                 std::memcpy(dst + (size_t)r * J.n16, it.tpl + (size_t)r * it.stride, J.n);
                 std::memset(dst + (size_t)r * J.n16 + J.n, 0x80, J.n16 - J.n);
@@ -1192,6 +1190,15 @@ void launch_batch_plan(BatchPlan &b, Slot &S)
     }
     hipStream_t st = S.stream;
     hip_check(hipMemcpyAsync(S.bdata.ptr, h, b.tpl_bytes, hipMemcpyHostToDevice, st));
+    for (size_t j = 0; j < b.jobs.size(); j++) {
+        const BatchJob &J = b.jobs[j];
+        for (int t = 0; t < J.T; t++) {
+            const BatchItem &it = b.items[b.members[j][t]];
+            if (it.device)
+                hip_check(hipMemcpy2DAsync((uint8_t *)J.tpl + (size_t)t * J.m * J.n16, J.n16, it.tpl, it.stride, J.n,
+                                           J.m, hipMemcpyDeviceToDevice, st));
+        }
+    }
     hip_check(hipEventRecord(S.ev0, st));
     hip_check(launch_batch_jobs(S.bdata.as<BatchJob>(), b.jobs.data(), (int)b.jobs.size(), st));
     hip_check(hipEventRecord(S.ev1, st));
@@ -1531,6 +1538,8 @@ ZTS_API zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int
         else
             fill_default(&pr);
         if (mode == ZTS_FULL_MFMA) {
+            if (n > 128)
+                throw ZtsError{ZTS_E_SIZE};
             zts_result r;
             run_batch_main(c, {BatchItem{im, tpl, m, n, stride}}, &r);
             if (r.status != ZTS_OK)
@@ -1548,7 +1557,7 @@ ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_
                                      int64_t stride, zts_mode mode, const zts_params *params, void *stream,
                                      zts_result *out)
 {
-    if (!z || !out || !valid_mode(mode) || mode == ZTS_FULL_MFMA)
+    if (!z || !out || !valid_mode(mode))
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
@@ -1559,6 +1568,20 @@ ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_
             pr = *params;
         else
             fill_default(&pr);
+        if (mode == ZTS_FULL_MFMA) {
+            if (n > 128)
+                throw ZtsError{ZTS_E_SIZE};
+            if (stream && (hipStream_t)stream != c->stream)  // the template is ready on the caller's stream
+                hip_check(hipStreamSynchronize((hipStream_t)stream));
+            BatchItem it{im, (const uint8_t *)tpl_dev, m, n, stride};
+            it.device = true;
+            zts_result r;
+            run_batch_main(c, {it}, &r);
+            if (r.status != ZTS_OK)
+                throw ZtsError{r.status};
+            *out = r;
+            return;
+        }
         run_query_main(c, im, (const uint8_t *)tpl_dev, m, n, stride, true, (hipStream_t)stream, mode, pr, out,
                        nullptr);
     });

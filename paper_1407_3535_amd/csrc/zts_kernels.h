@@ -40,7 +40,7 @@ struct ScanArgs {
     QState *qs;
     int8_t *dec;
     double delta;
-    int set_thr;  // no refinement follows: set the scan-2 threshold here
+    int cwd;      // MFMA form: dwords per staged image row of a block's region
 };
 
 // Refinement window on the original image.
@@ -54,7 +54,7 @@ struct WinArgs {
     int radius;
     int skip_centres;   // scan 1 ran on this image: its centres are already matched
     int include_best0;  // the scan-1 best is an original-image rho
-    RecPod *recs;
+    RecPod *recs;       // scan-1 records [0, rec_off), then this kernel's
     int rec_off;
     QState *qs;
     int8_t *dec;
@@ -84,6 +84,11 @@ struct MemArgs {
     int final_from;
     QState *qs;
     int8_t *dec;
+    // the threshold comes from the records of scan 1 [0, n_best0) and of the
+    // window [n_best0, n_best0 + n_win); include_best0: the scan-1 best is an
+    // original-image rho and competes with the window's
+    int n_best0, n_win, include_best0;
+    double delta;
 };
 
 enum { AC_DEBUG = 0, AC_COUNT = 1, AC_COUNT_BLUR = 2, AC_BUILD = 3 };
@@ -168,8 +173,7 @@ size_t batch_job_records(const BatchJob &j);
 // table lists the BATCH_MULTI jobs first, then the BATCH_SINGLE ones.
 hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s);
 
-enum { RD_BEST0 = 0, RD_WINDOW = 1, RD_FINAL = 2 };
-hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, int stage, int flag, double delta, hipStream_t s);
+hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, hipStream_t s);
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);
 hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s);
 
@@ -177,7 +181,10 @@ int full_record_count(int Ly, int Lx);
 size_t full_lds_bytes(int m, int n);
 hipError_t launch_full(FullArgs a, hipStream_t s);
 
-int centres_record_count(int Gy, int Gx, int m, int n, int h);
+// Scan 1 runs on int8 MFMA (k_centres_mfma) when the region a block's windows
+// cover fits its LDS budget, else on v_dot4 (k_centres); both write one
+// record per block.
+int centres_record_count(int Gy, int Gx, int m, int n, int h, int w);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);

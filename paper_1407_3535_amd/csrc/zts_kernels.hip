@@ -44,25 +44,38 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
 // Loads an m x n uint8 template into LDS as flipped int8 words, n4w words per
 // row, rows [off, off+m) of rows_lds; everything else zero.  Returns sum(t')
 // and sum(t'^2) to every thread.
+// One template word (4 columns from 4j) flipped to int8, zero past column n;
+// a whole-word load when the rows are word-aligned.
+__device__ __forceinline__ uint32_t tpl_word(const uint8_t *__restrict__ tpl, int64_t ts, int n, int r, int j,
+                                             bool words)
+{
+    if (4 * j >= n)
+        return 0;
+    const int nb = min(4, n - 4 * j);
+    uint32_t w = 0;
+    if (words) {
+        w = flip4(*gptr((const uint32_t *)(tpl + (int64_t)r * ts + 4 * j)));
+    } else {
+        for (int b = 0; b < nb; b++)
+            w |= ((uint32_t)gptr(tpl)[(int64_t)r * ts + 4 * j + b] ^ 0x80u) << (8 * b);
+    }
+    return nb < 4 ? (w & ((1u << (8 * nb)) - 1u)) : w;
+}
+
 __device__ void load_template(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int n4w, int off,
                               int rows_lds, uint32_t *lds, int *red, int64_t *st, int64_t *sq)
 {
+    const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
+    const uint32_t ones = 0x01010101u;
     int total = rows_lds * n4w;
     int s = 0, s2 = 0;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         int r = idx / n4w - off, j = idx - (idx / n4w) * n4w;
         uint32_t w = 0;
         if (r >= 0 && r < m) {
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                int c = 4 * j + b;
-                if (c < n) {
-                    int v = (int)tpl[(int64_t)r * ts + c] - 128;
-                    w |= ((uint32_t)(v & 0xff)) << (8 * b);
-                    s += v;
-                    s2 += v * v;
-                }
-            }
+            w = tpl_word(tpl, ts, n, r, j, words);
+            s = dot4(w, ones, s);
+            s2 = dot4(w, w, s2);
         }
         lds[idx] = w;
     }
@@ -97,16 +110,94 @@ __device__ RecPod reduce_records(const RecPod *recs, int lo, int hi, RecPod *red
     return block_rec(r, red);
 }
 
-__device__ void set_threshold(QState *qs, double best, int64_t best_l, double delta)
+// Best (rho, l) of a record range, computed by every block that calls it
+// (all threads call it; red holds one entry per wave).  The order is total
+// (rho, then the smaller index), so every block gets the same answer, which
+// is the best the one-block record reductions would find; an empty or
+// all-invalid range gives rho = -2, l = INT64_MAX.
+struct Best {
+    double rho;
+    int64_t l;
+    int valid;
+};
+
+__device__ __forceinline__ void best_merge(Best &a, double rho, int64_t l, int valid)
 {
-    qs->best = best;
-    qs->best_l = best_l;
-    double thr = best - delta;
-    qs->thr64 = thr;
-    double c = thr > 1.0 ? 1.0 : (thr < -1.0 ? -1.0 : thr);
+    if (valid && (!a.valid || rec_better(rho, l, a.rho, a.l))) {
+        a.rho = rho;
+        a.l = l;
+        a.valid = 1;
+    }
+}
+
+__device__ Best reduce_best(const RecPod *recs, int lo, int hi, Best *red)
+{
+    Best b = {-2.0, INT64_MAX, 0};
+    for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        const RecPod *p = recs + k;
+        best_merge(b, p->rho, p->l, p->valid);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        double r = __shfl_xor(b.rho, off);
+        long long l = __shfl_xor((long long)b.l, off);
+        int v = __shfl_xor(b.valid, off);
+        best_merge(b, r, (int64_t)l, v);
+    }
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    Best out = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+        best_merge(out, red[w].rho, red[w].l, red[w].valid);
+    __syncthreads();
+    return out;
+}
+
+// The scan-2 threshold computed inside the kernels that need it, from the
+// per-block records of scan 1 [0, n1) and of the refinement window [n1, n1 +
+// n2); with include_best0 the scan-1 best competes with the window's.
+struct Thr {
+    double best0;
+    int64_t best0_l;
+    double best;
+    int64_t best_l;
+    double thr64;
+    float lo, hi;
+};
+
+__device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_best0, double delta, Best *red)
+{
+    Thr r;
+    Best f0 = reduce_best(recs, 0, n1, red);
+    r.best0 = f0.rho;
+    r.best0_l = f0.l;
+    Best bw = {-2.0, INT64_MAX, 0};
+    if (n2 > 0) {
+        bw = reduce_best(recs, n1, n1 + n2, red);
+        if (include_best0)
+            best_merge(bw, f0.rho, f0.l, 1);
+    } else {
+        bw = f0;
+    }
+    r.best = bw.rho;
+    r.best_l = bw.l;
+    r.thr64 = bw.rho - delta;
+    double c = r.thr64 > 1.0 ? 1.0 : (r.thr64 < -1.0 ? -1.0 : r.thr64);
     float th = (float)acos(c);
-    qs->thr_lo = th - kEpsTheta;
-    qs->thr_hi = th + kEpsTheta;
+    r.lo = th - kEpsTheta;
+    r.hi = th + kEpsTheta;
+    return r;
+}
+
+__device__ void store_threshold(QState *qs, const Thr &r)
+{
+    qs->best0 = r.best0;
+    qs->best0_l = r.best0_l;
+    qs->best = r.best;
+    qs->best_l = r.best_l;
+    qs->thr64 = r.thr64;
+    qs->thr_lo = r.lo;
+    qs->thr_hi = r.hi;
 }
 
 __device__ __forceinline__ void group_geom(int g, int Gx, int Ly, int Lx, int h, int w, int &oy, int &ox, int &hh,
@@ -477,6 +568,163 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
     }
 }
 
+// Scan 1 on int8 MFMA: M = 16 centre columns (stride w), N = 16 centre rows
+// (stride h), K = 4 image rows x 16 columns.  A block holds 16 centre rows x
+// 64 centre columns, one M-tile per wave.  The image region its windows
+// cover streams through LDS in chunks of kCmChunk rows (one copy; A fragments
+// are realigned with v_alignbyte), so a block waits on a few global loads
+// only.  For image row y, lane (j, g) of the B fragment carries template row
+// y - cy_j (the zero row outside the template).  Outputs equal k_centres'.
+constexpr int kCmChunk = 32;
+constexpr int kCmLd = 24;   // staged words per thread and chunk, at most
+
+// Template rows flipped to int8 at row stride tstr, then one zero row; the
+// block sums of t' and t'^2.  Whole words are loaded when the rows are
+// word-aligned (bytes past column n are masked to int8 zero).
+__device__ void load_template_rows(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int nw16, int tstr,
+                                   uint32_t *lds, int *red, int64_t *st, int64_t *sq)
+{
+    const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
+    const uint32_t ones = 0x01010101u;
+    int s = 0, s2 = 0;
+    for (int idx = threadIdx.x; idx < (m + 1) * nw16; idx += blockDim.x) {
+        int r = idx / nw16, j = idx - r * nw16;
+        uint32_t w = 0;
+        if (r < m) {
+            w = tpl_word(tpl, ts, n, r, j, words);
+            s = dot4(w, ones, s);
+            s2 = dot4(w, w, s2);
+        }
+        lds[r * tstr + j] = w;
+    }
+    *st = block_sum_int(s, red);
+    *sq = block_sum_int(s2, red);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_centres_mfma(ScanArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[8];
+    __shared__ RecPod rred[256];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int m = a.m, n = a.n, n16 = (n + 15) & ~15, nw16 = n16 >> 2, nb16 = n16 >> 4;
+    const int tstr = batch_tstride(nw16), CWd = a.cwd, CW = kCmChunk * CWd;
+    uint32_t *tpl_l = smem;                         // m rows and the zero row m, stride tstr
+    uint32_t *buf0 = smem + (m + 1) * tstr;         // two chunk buffers of CW dwords
+    int64_t st, sq;
+    load_template_rows(a.tpl, a.ts, m, n, nw16, tstr, tpl_l, red, &st, &sq);
+    const int64_t mn = (int64_t)m * n;
+    const int64_t dt = mn * sq - st * st;
+    if (dt == 0) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
+            a.qs->degenerate = 1;
+        return;
+    }
+    auto ccol = [&](int gx) { int ox = gx * a.w; return ox + (min(a.w, a.Lx - ox) - 1) / 2; };
+    auto crow = [&](int gy) { int oy = gy * a.h; return oy + (min(a.h, a.Ly - oy) - 1) / 2; };
+    const int gx0 = blockIdx.x * 64, gy0 = blockIdx.y * 16;
+    const int nx = min(64, a.Gx - gx0), ny = min(16, a.Gy - gy0);
+    const int xw0 = ccol(gx0) >> 2;                 // first staged word of the region's rows
+    const int ylo = crow(gy0), yhi = crow(gy0 + ny - 1) + m;
+    const int nchunk = (yhi - ylo + kCmChunk - 1) / kCmChunk;
+    const uint32_t *img32 = (const uint32_t *)a.img;
+    const int64_t pw = a.pitch >> 2;
+    // staging: 8 threads per chunk row, thread (r, q) copies words q, q + 8, ...
+    static_assert(kCmChunk * 8 == 256, "8 threads per staged row");
+    const int sr = t >> 3, sq8 = t & 7;
+    uint32_t rv[kCmLd];
+    auto cload = [&](int c) {
+        const int y = ylo + kCmChunk * c + sr;
+        const uint32_t *row = img32 + (int64_t)min(y, yhi - 1) * pw + xw0;
+        const bool yok = y < yhi;
+#pragma unroll
+        for (int k = 0; k < kCmLd; k++) {
+            int wd = sq8 + 8 * k;
+            rv[k] = 0x80808080u;
+            if (yok && wd < CWd && xw0 + wd < pw)
+                rv[k] = *gptr(row + wd);
+        }
+    };
+    auto cstore = [&](int c) {
+        uint32_t *b = buf0 + (c & 1) * CW + sr * CWd;
+#pragma unroll
+        for (int k = 0; k < kCmLd; k++) {
+            int wd = sq8 + 8 * k;
+            if (wd < CWd)
+                b[wd] = flip4(rv[k]);
+        }
+    };
+    const int g = lane >> 4, jr = lane & 15;
+    const int cxa = ccol(min(gx0 + 16 * wv + jr, a.Gx - 1)) - 4 * xw0;  // A lane: its centre column in the region
+    const int cyb = crow(min(gy0 + jr, a.Gy - 1));                        // B lane: its centre row
+    const bool jok = jr < ny;
+    v4i acc = v4i{0, 0, 0, 0};
+    cload(0);
+    cstore(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; c++) {
+        if (c + 1 < nchunk)
+            cload(c + 1);
+        const uint32_t *b = buf0 + (c & 1) * CW;
+        const int rows = min(kCmChunk, yhi - ylo - kCmChunk * c);
+        for (int k = 0; 4 * k < rows; k++) {
+            const int yr = 4 * k + g;                      // row of the chunk for this lane group
+            const int tr = ylo + kCmChunk * c + yr - cyb;  // template row for B lane (jr, g)
+            const int brow = jok && (unsigned)tr < (unsigned)m ? tr : m;
+            const uint32_t *pa = b + yr * CWd;
+#pragma unroll 4
+            for (int cb = 0; cb < nb16; cb++) {
+                int bo = cxa + 16 * cb;
+                const uint32_t *pw5 = pa + (bo >> 2);
+                uint32_t w0 = pw5[0], w1 = pw5[1], w2 = pw5[2], w3 = pw5[3], w4 = pw5[4];
+                uint32_t sh = (uint32_t)(bo & 3);
+                v4i A;
+                A[0] = (int)bytes_at(w1, w0, sh);
+                A[1] = (int)bytes_at(w2, w1, sh);
+                A[2] = (int)bytes_at(w3, w2, sh);
+                A[3] = (int)bytes_at(w4, w3, sh);
+                v4i B = *(const v4i *)(tpl_l + brow * tstr + 4 * cb);
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
+            }
+        }
+        if (c + 1 < nchunk)
+            cstore(c + 1);
+        __syncthreads();
+    }
+    // lane holds centre row gy0 + (lane & 15) and centre columns
+    // gx0 + 16 wv + 4 (lane >> 4) + v
+    RecPod rec = rec_empty();
+    const int gyy = gy0 + jr;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int gxx = gx0 + 16 * wv + 4 * g + v;
+        if (gyy < a.Gy && gxx < a.Gx) {
+            const int cy = crow(gyy), cx = ccol(gxx);
+            const int64_t l = (int64_t)cy * a.Lx + cx;
+            const int2 sc = ld_int2(a.stat + l);
+            const int64_t dc = var_num(mn, sc);
+            const int64_t num = mn * (int64_t)acc[v] - st * (int64_t)sc.x;
+            const int gi = gyy * a.Gx + gxx;
+            a.g_num[gi] = num;
+            a.g_theta[gi] = theta32(num, dt, dc);
+            rec_offer(rec, rho32(num, dt, dc), l, num, dt, dc);
+            if (a.dec)
+                a.dec[l] = 1;
+        }
+    }
+    RecPod bb = block_rec(rec, rred);
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    if (t == 0) {
+        a.recs[bid] = bb;
+        if (bid == 0) {
+            a.qs->st = st;
+            a.qs->dt = dt;
+        }
+    }
+    (void)nx;
+}
+
 // ============================================================== refinement window
 
 // Matches the template on the original image at every location within
@@ -489,6 +737,7 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
     __shared__ int red[8];
     __shared__ RecPod wrec[4];
     __shared__ unsigned long long ured[8];
+    __shared__ Best bred[4];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (a.qs->degenerate)
         return;
@@ -497,7 +746,7 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
     load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t dt = mn * sq - st * st;
-    int64_t c0 = a.qs->best0_l;
+    const int64_t c0 = reduce_best(a.recs, 0, a.rec_off, bred).l;  // best scan-1 centre
     int cy0 = (int)(c0 / a.Lx), cx0 = (int)(c0 - (c0 / a.Lx) * a.Lx);
     int W = 2 * a.radius + 1;
     int total = W * W;
@@ -545,16 +794,10 @@ __device__ __forceinline__ bool in_window(int y, int x, int wy, int wx, int radi
 __device__ void load_template_words(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int n4,
                                     uint32_t *lds)
 {
+    const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
     for (int idx = threadIdx.x; idx < m * n4; idx += blockDim.x) {
         int r = idx / n4, j = idx - (idx / n4) * n4;
-        uint32_t w = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            int c = 4 * j + b;
-            if (c < n)
-                w |= ((uint32_t)(((int)tpl[(int64_t)r * ts + c] - 128) & 0xff)) << (8 * b);
-        }
-        lds[idx] = w;
+        lds[idx] = tpl_word(tpl, ts, n, r, j, words);
     }
 }
 
@@ -633,19 +876,23 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ int s_nsurv, s_tpl;
     __shared__ RecPod wrec[4];
     __shared__ unsigned long long ured[8];
+    __shared__ Best bred[4];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (a.qs->degenerate)
         return;
+    const Thr thr = block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, bred);
+    if (blockIdx.x == 0 && t == 0)
+        store_threshold(a.qs, thr);
     const int n4 = (a.n + 3) >> 2;
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t st = a.qs->st, dt = a.qs->dt;
-    const float lo = a.qs->thr_lo, hi = a.qs->thr_hi;
-    const double thr64 = a.qs->thr64;
+    const float lo = thr.lo, hi = thr.hi;
+    const double thr64 = thr.thr64;
     const int hw = a.h * a.w;
     const int G = a.Gy * a.Gx;
     int wy = -1, wx = -1;
     if (a.radius >= 0) {
-        int64_t c0 = a.qs->best0_l;
+        int64_t c0 = thr.best0_l;
         wy = (int)(c0 / a.Lx);
         wx = (int)(c0 - (c0 / a.Lx) * a.Lx);
     }
@@ -1066,7 +1313,6 @@ __global__ __launch_bounds__(256) void k_revert(const uint8_t *__restrict__ colm
 
 // ============================================================== batched templates on int8 MFMA
 
-typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Template statistics of a batch: one block per template (layout [T][m][n16],
 // columns past n hold 0x80, i.e. int8 zero): tst[2t] = sum(t'), tst[2t+1] = D_t.
@@ -1124,15 +1370,6 @@ constexpr int kBatchEpiList = 2 * kBatchRows * 256 + 68;
 constexpr int kBatchEpiWords = kBatchEpiList + 4 * kBatchCandCap + 6 * kBatchCandCap;
 static_assert(kBatchEpiList % 4 == 0, "candidate list is 16-byte aligned");
 
-// Dword stride of one template row in the LDS ring: an odd number of 16-byte
-// units, so the 16 lanes of a B-fragment read (16 templates, one row) fall
-// on distinct banks.
-__host__ __device__ inline int batch_tstride(int nw16) { return ((nw16 >> 2) & 1) ? nw16 : nw16 + 4; }
-
-// Dword stride of one byte-shifted image row copy: 8 mod 16, so the 16 lanes
-// of an A-fragment read (4 copies x 4 consecutive words, 2 dwords each) and
-// the next 16 lanes (next row, 4 strides on) fall on distinct banks.
-__host__ __device__ inline int batch_copy_stride(int ww) { return ww + ((8 - ww) & 15); }
 
 template <int R>
 __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ jobs, int njobs)
@@ -1777,13 +2014,10 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 
 // ============================================================== record reductions
 
-// One block folds a range of per-block records after the kernel that wrote
-// them has finished (the kernel boundary makes them visible on every XCD).
-//   RD_BEST0: the scan-1 best -> best0 (and the threshold when set_thr);
-//   RD_WINDOW: the window best, with best0 when include_best0 -> threshold;
-//   RD_FINAL: the answer.
-__global__ __launch_bounds__(256) void k_reduce(RecPod *__restrict__ recs, int lo, int hi, QState *qs, int stage,
-                                                int flag, double delta)
+// One block folds the per-block records of the final scan (and of the window
+// when it counts) into the answer, after the kernels that wrote them have
+// finished (the kernel boundary makes them visible on every XCD).
+__global__ __launch_bounds__(256) void k_reduce(RecPod *__restrict__ recs, int lo, int hi, QState *qs)
 {
     __shared__ RecPod rred[256];
     if (qs->degenerate)
@@ -1791,35 +2025,20 @@ __global__ __launch_bounds__(256) void k_reduce(RecPod *__restrict__ recs, int l
     RecPod f = reduce_records(recs, lo, hi, rred);
     if (threadIdx.x != 0)
         return;
-    if (stage == RD_BEST0) {
-        qs->best0 = f.rho;
-        qs->best0_l = f.l;
-        if (flag)
-            set_threshold(qs, f.rho, f.l, delta);
-    } else if (stage == RD_WINDOW) {
-        double best = f.valid ? f.rho : -2.0;
-        int64_t bl = f.valid ? f.l : INT64_MAX;
-        if (flag && rec_better(qs->best0, qs->best0_l, best, bl)) {
-            best = qs->best0;
-            bl = qs->best0_l;
-        }
-        set_threshold(qs, best, bl, delta);
-    } else {
-        qs->fin = f;
-        qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
-        qs->n_elim = f.n_elim;
-        qs->n_surv = f.n_surv;
-        qs->n_window = f.n_window;
-    }
+    qs->fin = f;
+    qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
+    qs->n_elim = f.n_elim;
+    qs->n_surv = f.n_surv;
+    qs->n_window = f.n_window;
 }
 
 // ============================================================== launch wrappers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, int stage, int flag, double delta, hipStream_t s)
+hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, recs, lo, hi, qs, stage, flag, delta);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, recs, lo, hi, qs);
     return hipGetLastError();
 }
 
@@ -1889,13 +2108,36 @@ static int centre_rows(int m, int n, int h)
     return 1;
 }
 
-int centres_record_count(int Gy, int Gx, int m, int n, int h)
+// Dwords per staged row of k_centres_mfma's region (64 centre columns of
+// stride w, the template width, realignment slack), or 0 when its LDS or
+// staging registers would not suffice.
+static int centres_mfma_cwd(int m, int n, int w)
 {
+    int n16 = (n + 15) / 16 * 16;
+    int cwd = (63 * w + w / 2 + n16 + 12) / 4 + 2;
+    size_t lds = ((size_t)(m + 1) * batch_tstride(n16 / 4) + (size_t)2 * kCmChunk * cwd) * 4;
+    if (n16 > 128 || lds > 48 * 1024 || cwd > kCmLd * 8)
+        return 0;
+    return cwd;
+}
+
+int centres_record_count(int Gy, int Gx, int m, int n, int h, int w)
+{
+    if (centres_mfma_cwd(m, n, w))
+        return (int)(blocks_for(Gx, 64) * blocks_for(Gy, 16));
     return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(m, n, h)));
 }
 
 hipError_t launch_centres(ScanArgs a, hipStream_t s)
 {
+    if (int cwd = centres_mfma_cwd(a.m, a.n, a.w)) {
+        a.cwd = cwd;
+        int n16 = (a.n + 15) / 16 * 16;
+        size_t lds = ((size_t)(a.m + 1) * batch_tstride(n16 / 4) + (size_t)2 * kCmChunk * cwd) * 4;
+        dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, 16));
+        hipLaunchKernelGGL(k_centres_mfma, grid, dim3(256), lds, s, a);
+        return hipGetLastError();
+    }
     a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
     int nw = centre_waves(a.n);
     int R = centre_rows(a.m, a.n, a.h);
@@ -1914,7 +2156,7 @@ hipError_t launch_centres(ScanArgs a, hipStream_t s)
 int window_record_count(int radius)
 {
     int W = 2 * radius + 1;
-    int nb = (int)blocks_for(W * W, 16);
+    int nb = (int)blocks_for(W * W, 4);  // one location per wave
     return nb < 1 ? 1 : nb;
 }
 

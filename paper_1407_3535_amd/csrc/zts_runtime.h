@@ -193,9 +193,10 @@ void unpin_query(QueryPlan &q);
 // of the batched MFMA kernels.
 struct BatchItem {
     Image *im;
-    const uint8_t *tpl;
+    const uint8_t *tpl;  // host memory, or device memory when `device`
     int m, n;
     int64_t stride;
+    bool device = false;
 };
 struct BatchPlan {
     std::vector<BatchItem> items;

@@ -118,7 +118,7 @@ def test_blur_bit_exact(S, taps):
 
 
 @pytest.mark.parametrize("k", range(len(CASES)))
-@pytest.mark.parametrize("hw,radius", [((3, 3), 0), ((4, 6), 0), ((5, 5), 2), ((1, 1), 0), ((2, 3), 1)])
+@pytest.mark.parametrize("hw,radius", [((3, 3), 0), ((4, 6), 0), ((5, 5), 2), ((1, 1), 0), ((2, 3), 1), ((12, 14), 1)])
 def test_te_fixed_parity(S, k, hw, radius):
     img, tpl = CASES[k]
     h, w = hw
@@ -234,6 +234,14 @@ def test_device_entry_points_match_host_ones(S):
     b = Z.zts_search_device(S.ctx, j, t, "egs")
     for k in KEYS + ("n_eliminated", "n_survivors", "n_computed"):
         assert a[k] == b[k]
+    # int8 MFMA from a device template whose rows are strided (a column slice of a wider tensor)
+    wide = torch.zeros((24, 40), dtype=torch.uint8, device="cuda")
+    wide[:, 5:29] = t
+    c = Z.zts_search_device(S.ctx, j, wide[:, 5:29], "full_mfma")
+    d = S.search(i, tpl, "full_mfma")
+    o = O.full_search(img, tpl)
+    for k in KEYS:
+        assert c[k] == d[k] == o[k]
     S.unload(i)
     S.unload(j)
 
