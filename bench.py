@@ -118,22 +118,30 @@ def main():
     tdev = torch.from_numpy(tpl).cuda()
     torch.cuda.synchronize()
 
-    def query(mode, refine=0, **kw):
-        return Z.zts_search_device(S.ctx, i, tdev, mode, Z.zts_params_default(refine_radius=refine, **kw))
+    def query(mode, refine=0, timing=0, **kw):
+        return Z.zts_search_device(S.ctx, i, tdev, mode,
+                                   Z.zts_params_default(refine_radius=refine, timing=timing, **kw))
 
     def run(mode, refine, steps, warmup, **kw):
         for _ in range(warmup):
             query(mode, refine, **kw)
         torch.cuda.synchronize()
-        lat, phases = [], []
+        lat = []
         t0 = time.perf_counter()
         for _ in range(steps):
             a = time.perf_counter()
             r = query(mode, refine, **kw)
             lat.append((time.perf_counter() - a) * 1e3)
-            phases.append(r["phase_ms"])
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
+        # Per-kernel times of the same query, from HIP events after each
+        # kernel on the library's stream (the timed loop replays a captured
+        # graph, which carries no events).
+        phases = []
+        for _ in range(min(steps, 20)):
+            rt = query(mode, refine, timing=1, **kw)
+            assert (rt["y"], rt["x"], rt["rho"]) == (r["y"], r["x"], r["rho"])
+            phases.append(rt["phase_ms"])
         return r, ms, lat, np.mean(np.array(phases), axis=0)
 
     r, ms, lat, ph = run(args.mode, args.refine, args.steps, args.warmup)
@@ -267,7 +275,7 @@ def bench_batch(args):
         Z.zts_search_device(S.ctx, i, t, "full")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    valu = [Z.zts_search_device(S.ctx, i, t, "full") for t in tdev]
+    valu = [Z.zts_search_device(S.ctx, i, t, "full", Z.zts_params_default(timing=1)) for t in tdev]
     torch.cuda.synchronize()
     valu_ms = (time.perf_counter() - t1) * 1e3
     for r, b in zip(valu, res):

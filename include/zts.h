@@ -111,6 +111,10 @@ typedef struct {
                                threshold; exactness unaffected).  0: section VI as printed.
                                In ZTS_OPTA the window radius is max(this, cumulative blur
                                radius, capped at 8). */
+    int32_t timing;         /* 1: run the query's kernels one by one with an event after
+                               each, filling zts_result.phase_ms.  0 (default): a launch
+                               sequence met before on the same slot replays a captured
+                               HIP graph and phase_ms stays 0. */
 } zts_params;
 
 /* Result of one search.  Valid only when status == ZTS_OK. */
@@ -134,8 +138,8 @@ typedef struct {
                                 ZTS_FULL: [0] dense kernel; ZTS_FULL_MFMA: [0] the batched launch;
                                 other modes: [0] scan 1 (centres), [1] refinement window,
                                 [2] scan 2 (members and survivors; each block derives the
-                                threshold from the earlier kernels' records), [3] the
-                                one-block reduction to the answer */
+                                threshold from the earlier kernels' records); [3] the
+                                one-block reduction to the answer (ZTS_FULL too) */
     float latency_ms;        /* submitted requests: submission to result ready (host clock) */
     float queue_ms;          /* submitted requests: submission to the start of its launch */
     int32_t batch_size;      /* templates in the launch that produced this result */

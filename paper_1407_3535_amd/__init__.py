@@ -56,7 +56,7 @@ class Params(C.Structure):
                 ("group_h", C.c_int32), ("group_w", C.c_int32), ("h0", C.c_int32), ("w0", C.c_int32),
                 ("dh", C.c_int32), ("dw", C.c_int32), ("h_max", C.c_int32), ("blur_kind", C.c_int32),
                 ("sigma_step", C.c_double), ("sigma_max", C.c_double), ("max_iters", C.c_int32),
-                ("refine_radius", C.c_int32)]
+                ("refine_radius", C.c_int32), ("timing", C.c_int32)]
 
 
 class Result(C.Structure):

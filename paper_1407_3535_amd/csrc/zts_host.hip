@@ -15,11 +15,11 @@ namespace zts {
 
 // ------------------------------------------------------------------ errors and buffers
 
-void hip_check(hipError_t e)
+void hip_check_at(hipError_t e, const char *file, int line)
 {
     if (e != hipSuccess) {
         if (std::getenv("ZTS_DEBUG"))
-            std::fprintf(stderr, "zts: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
+            std::fprintf(stderr, "zts: HIP error %d (%s) at %s:%d\n", (int)e, hipGetErrorString(e), file, line);
         throw ZtsError{ZTS_E_DEVICE};
     }
 }
@@ -71,13 +71,23 @@ void Slot::init()
     hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     hip_check(hipEventCreate(&ev0));
     hip_check(hipEventCreate(&ev1));
+    hip_check(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
     for (auto &e : evp)
         hip_check(hipEventCreate(&e));
     h_qs.grow(sizeof(QState));
 }
 
+void Slot::drop_graphs()
+{
+    for (auto &g : graphs)
+        if (g.exec)
+            (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+}
+
 void Slot::release_scratch()
 {
+    drop_graphs();
     qs.reset();
     recs.reset();
     gnum.reset();
@@ -101,13 +111,15 @@ void Slot::destroy()
         (void)hipEventDestroy(ev0);
     if (ev1)
         (void)hipEventDestroy(ev1);
+    if (ev_in)
+        (void)hipEventDestroy(ev_in);
     for (auto &e : evp)
         if (e)
             (void)hipEventDestroy(e);
     if (stream)
         (void)hipStreamDestroy(stream);
     stream = nullptr;
-    ev0 = ev1 = nullptr;
+    ev0 = ev1 = ev_in = nullptr;
     for (auto &e : evp)
         e = nullptr;
 }
@@ -233,6 +245,7 @@ void fill_default(zts_params *p)
     p->sigma_max = 3.0;
     p->max_iters = 6;
     p->refine_radius = 0;
+    p->timing = 0;
 }
 
 // Gaussian weights on [-d, d], d = ceil(3 sigma), quantised to integers that
@@ -817,16 +830,9 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
     return q;
 }
 
-void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride, bool device, hipStream_t caller)
+void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride)
 {
     size_t bytes = (size_t)m * n;
-    if (device) {
-        hip_check(hipMemcpy2DAsync(S.tpl.ptr, n, tpl, stride, n, m, hipMemcpyDeviceToDevice,
-                                   caller ? caller : S.stream));
-        if (caller && caller != S.stream)
-            hip_check(hipStreamSynchronize(caller));
-        return;
-    }
     S.h_stage.grow(bytes);
     uint8_t *h = S.h_stage.as<uint8_t>();
     for (int i = 0; i < m; i++)
@@ -834,38 +840,46 @@ void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride, b
     hip_check(hipMemcpyAsync(S.tpl.ptr, h, bytes, hipMemcpyHostToDevice, S.stream));
 }
 
-// Enqueues one query on S.stream: scan 1 and its reduction, the optional
-// refinement window, scan 2 with survivors, the final reduction, and the copy
-// of the query state to pinned host memory.
-void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
+// Every argument of one query's launches.  The struct is zeroed before it is
+// filled, so two launches with equal bytes enqueue identical work: the bytes
+// are the key of the slot's graph cache.
+struct QueryLaunch {
+    int32_t full;
+    int32_t radius, n1, n2, n3, opta;
+    FullArgs fa;
+    ScanArgs sa;
+    WinArgs wa;
+    MemArgs ma;
+    QState *qs;
+    RecPod *recs;
+    void *h_qs;
+};
+
+static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, QueryLaunch &Q)
 {
+    std::memset(&Q, 0, sizeof Q);
     Image *im = q.im;
     const int m = q.m, n = q.n, Ly = q.Ly, Lx = q.Lx;
-    const int64_t L = (int64_t)Ly * Lx;
     const zts_params &pr = q.pr;
     const Prepared *P = q.P;
     const int2 *statI = q.st->stat.as<int2>();
-    hipStream_t st = S.stream;
-    hip_check(hipMemsetAsync(S.qs.ptr, 0, sizeof(QState), st));
-    int8_t *d_dec = nullptr;
-    if (q.want_dec) {
-        hip_check(hipMemsetAsync(S.dec.ptr, 0x7f, (size_t)L, st));
-        d_dec = S.dec.as<int8_t>();
-    }
     QState *qs = S.qs.as<QState>();
-    const uint8_t *tpl = S.tpl.as<uint8_t>();
+    const uint8_t *tpl = q.tpl ? q.tpl : S.tpl.as<uint8_t>();
+    const int64_t ts = q.tpl ? q.ts : n;
     RecPod *recs = S.recs.as<RecPod>();
-    hip_check(hipEventRecord(S.ev0, st));
+    Q.qs = qs;
+    Q.recs = recs;
+    Q.h_qs = S.h_qs.ptr;
     if (q.mode == ZTS_FULL) {
-        FullArgs a;
-        std::memset(&a, 0, sizeof a);
+        Q.full = 1;
+        FullArgs &a = Q.fa;
         a.img = im->img.as<uint8_t>();
         a.pitch = im->pitch;
         a.p = im->rows;
         a.q = im->cols;
         a.stat = statI;
         a.tpl = tpl;
-        a.ts = n;
+        a.ts = ts;
         a.m = m;
         a.n = n;
         a.Ly = Ly;
@@ -876,107 +890,203 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
         a.dr_map = q.dr_map;
         a.rho_map = q.rho_map;
         a.dec = d_dec;
-        hip_check(launch_full(a, st));
-        hip_check(hipEventRecord(S.evp[0], st));
-        hip_check(launch_reduce(recs, 0, full_record_count(Ly, Lx), qs, st));
-        hip_check(hipEventRecord(S.evp[1], st));
+        Q.n3 = full_record_count(Ly, Lx);
+        return;
+    }
+    const bool opta = q.mode == ZTS_OPTA;
+    const int radius = query_radius(q);
+    Q.opta = opta;
+    Q.radius = radius;
+    Q.n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
+    Q.n2 = radius >= 0 ? window_record_count(radius) : 0;
+    Q.n3 = members_record_count(P->Gy, P->Gx);
+    const uint8_t *spx = opta ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
+    const int2 *sstat = opta ? P->Jstat.as<int2>() : statI;
+    ScanArgs &s = Q.sa;
+    s.img = spx;
+    s.pitch = im->pitch;
+    s.stat = sstat;
+    s.tpl = tpl;
+    s.ts = ts;
+    s.m = m;
+    s.n = n;
+    s.Ly = Ly;
+    s.Lx = Lx;
+    s.h = P->h;
+    s.w = P->w;
+    s.Gy = P->Gy;
+    s.Gx = P->Gx;
+    s.g_num = S.gnum.as<int64_t>();
+    s.g_theta = S.gtheta.as<float>();
+    s.recs = recs;
+    s.qs = qs;
+    s.dec = opta ? nullptr : d_dec;
+    s.delta = pr.margin;
+    if (radius >= 0) {
+        WinArgs &wa = Q.wa;
+        wa.img = im->img.as<uint8_t>();
+        wa.pitch = im->pitch;
+        wa.stat = statI;
+        wa.tpl = tpl;
+        wa.ts = ts;
+        wa.m = m;
+        wa.n = n;
+        wa.Ly = Ly;
+        wa.Lx = Lx;
+        wa.h = P->h;
+        wa.w = P->w;
+        wa.radius = radius;
+        wa.skip_centres = !opta;
+        wa.include_best0 = !opta;
+        wa.recs = recs;
+        wa.rec_off = Q.n1;
+        wa.qs = qs;
+        wa.dec = d_dec;
+        wa.delta = pr.margin;
+    }
+    MemArgs &ma = Q.ma;
+    ma.I = im->img.as<uint8_t>();
+    ma.pI = im->pitch;
+    ma.statI = statI;
+    ma.statS = sstat;
+    ma.tpl = tpl;
+    ma.ts = ts;
+    ma.m = m;
+    ma.n = n;
+    ma.Ly = Ly;
+    ma.Lx = Lx;
+    ma.h = P->h;
+    ma.w = P->w;
+    ma.Gy = P->Gy;
+    ma.Gx = P->Gx;
+    ma.g_num = S.gnum.as<int64_t>();
+    ma.g_theta = S.gtheta.as<float>();
+    ma.gsum = P->gsum.as<GroupSum>();
+    ma.theta_b = P->theta_b.as<float>();
+    ma.x_b = P->x_b.as<int32_t>();
+    ma.theta_c = opta ? P->theta_cg.as<float>() : nullptr;
+    ma.x_c = opta ? P->x_cg.as<int32_t>() : nullptr;
+    ma.opta = opta;
+    ma.radius = radius;
+    ma.recs = recs;
+    ma.rec_off = Q.n1 + Q.n2;
+    ma.final_from = opta ? Q.n1 : 0;
+    ma.qs = qs;
+    ma.dec = d_dec;
+    ma.n_best0 = Q.n1;
+    ma.n_win = Q.n2;
+    ma.include_best0 = !opta;
+    ma.delta = pr.margin;
+}
+
+// The kernels of one query and the copy of its state to pinned host memory.
+// The scan kernels initialise the query state themselves (no fill), so the
+// sequence can be captured into a graph.  With `events`, an event follows
+// each kernel (per-kernel times; never captured: event-record nodes made
+// graph replays slower than eager launches).
+static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool events)
+{
+    auto mark = [&](hipEvent_t e) {
+        if (events)
+            hip_check(hipEventRecord(e, st));
+    };
+    if (Q.full) {
+        hip_check(launch_full(Q.fa, st));
+        mark(S.evp[0]);
+        hip_check(launch_reduce(Q.recs, 0, Q.n3, Q.qs, st));
+        mark(S.evp[1]);
     } else {
-        bool opta = q.mode == ZTS_OPTA;
-        int radius = query_radius(q);
-        int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
-        int n2 = radius >= 0 ? window_record_count(radius) : 0;
-        int n3 = members_record_count(P->Gy, P->Gx);
-        const uint8_t *spx = opta ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
-        const int2 *sstat = opta ? P->Jstat.as<int2>() : statI;
-        ScanArgs s;
-        std::memset(&s, 0, sizeof s);
-        s.img = spx;
-        s.pitch = im->pitch;
-        s.stat = sstat;
-        s.tpl = tpl;
-        s.ts = n;
-        s.m = m;
-        s.n = n;
-        s.Ly = Ly;
-        s.Lx = Lx;
-        s.h = P->h;
-        s.w = P->w;
-        s.Gy = P->Gy;
-        s.Gx = P->Gx;
-        s.g_num = S.gnum.as<int64_t>();
-        s.g_theta = S.gtheta.as<float>();
-        s.recs = recs;
-        s.qs = qs;
-        s.dec = opta ? nullptr : d_dec;
-        s.delta = pr.margin;
-        hip_check(launch_centres(s, st));
-        hip_check(hipEventRecord(S.evp[0], st));
-        if (radius >= 0) {
-            WinArgs wa;
-            std::memset(&wa, 0, sizeof wa);
-            wa.img = im->img.as<uint8_t>();
-            wa.pitch = im->pitch;
-            wa.stat = statI;
-            wa.tpl = tpl;
-            wa.ts = n;
-            wa.m = m;
-            wa.n = n;
-            wa.Ly = Ly;
-            wa.Lx = Lx;
-            wa.h = P->h;
-            wa.w = P->w;
-            wa.radius = radius;
-            wa.skip_centres = !opta;
-            wa.include_best0 = !opta;
-            wa.recs = recs;
-            wa.rec_off = n1;
-            wa.qs = qs;
-            wa.dec = d_dec;
-            wa.delta = pr.margin;
-            hip_check(launch_window(wa, st));
+        hip_check(launch_centres(Q.sa, st));
+        mark(S.evp[0]);
+        if (Q.radius >= 0)
+            hip_check(launch_window(Q.wa, st));
+        mark(S.evp[1]);
+        hip_check(launch_members(Q.ma, st));
+        mark(S.evp[2]);
+        hip_check(launch_reduce(Q.recs, Q.opta ? Q.n1 : 0, Q.n1 + Q.n2 + Q.n3, Q.qs, st));
+        mark(S.evp[3]);
+    }
+    hip_check(hipMemcpyAsync(Q.h_qs, Q.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+}
+
+// Graph cache of a slot: a launch sequence is run eagerly the first time its
+// key is seen, captured the second time and replayed from then on (shapes
+// that come once are never captured).
+static const int kGraphCache = 16;
+
+static hipGraphExec_t graph_for(Slot &S, const QueryLaunch &Q, bool *capture)
+{
+    std::string key((const char *)&Q, sizeof Q);
+    *capture = false;
+    S.graph_clock++;
+    for (auto &g : S.graphs)
+        if (g.key == key) {
+            g.stamp = S.graph_clock;
+            if (!g.exec)
+                *capture = true;
+            return g.exec;
         }
-        hip_check(hipEventRecord(S.evp[1], st));
-        MemArgs ma;
-        std::memset(&ma, 0, sizeof ma);
-        ma.I = im->img.as<uint8_t>();
-        ma.pI = im->pitch;
-        ma.statI = statI;
-        ma.statS = sstat;
-        ma.tpl = tpl;
-        ma.ts = n;
-        ma.m = m;
-        ma.n = n;
-        ma.Ly = Ly;
-        ma.Lx = Lx;
-        ma.h = P->h;
-        ma.w = P->w;
-        ma.Gy = P->Gy;
-        ma.Gx = P->Gx;
-        ma.g_num = S.gnum.as<int64_t>();
-        ma.g_theta = S.gtheta.as<float>();
-        ma.gsum = P->gsum.as<GroupSum>();
-        ma.theta_b = P->theta_b.as<float>();
-        ma.x_b = P->x_b.as<int32_t>();
-        ma.theta_c = opta ? P->theta_cg.as<float>() : nullptr;
-        ma.x_c = opta ? P->x_cg.as<int32_t>() : nullptr;
-        ma.opta = opta;
-        ma.radius = radius;
-        ma.recs = recs;
-        ma.rec_off = n1 + n2;
-        ma.final_from = opta ? n1 : 0;
-        ma.qs = qs;
-        ma.dec = d_dec;
-        ma.n_best0 = n1;
-        ma.n_win = n2;
-        ma.include_best0 = !opta;
-        ma.delta = pr.margin;
-        hip_check(launch_members(ma, st));
-        hip_check(hipEventRecord(S.evp[2], st));
-        hip_check(launch_reduce(recs, opta ? n1 : 0, n1 + n2 + n3, qs, st));
-        hip_check(hipEventRecord(S.evp[3], st));
+    if ((int)S.graphs.size() >= kGraphCache) {
+        auto old = S.graphs.begin();
+        for (auto it = S.graphs.begin(); it != S.graphs.end(); ++it)
+            if (it->stamp < old->stamp)
+                old = it;
+        if (old->exec)
+            (void)hipGraphExecDestroy(old->exec);
+        S.graphs.erase(old);
+    }
+    S.graphs.push_back(SlotGraph{key, nullptr, S.graph_clock});
+    return nullptr;
+}
+
+// Enqueues one query on S.stream: scan 1, the optional refinement window,
+// scan 2 with survivors, the final reduction, and the copy of the query state
+// to pinned host memory.  Repeated launch sequences run as a replayed graph.
+void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
+{
+    const int64_t L = (int64_t)q.Ly * q.Lx;
+    hipStream_t st = S.stream;
+    int8_t *d_dec = nullptr;
+    if (q.want_dec) {
+        hip_check(hipMemsetAsync(S.dec.ptr, 0x7f, (size_t)L, st));
+        d_dec = S.dec.as<int8_t>();
+    }
+    QueryLaunch Q;
+    build_query_launch(q, S, d_dec, Q);
+    const bool timing = q.pr.timing != 0;
+    const bool graphable = S.use_graphs && !timing && !q.want_dec && !q.num_map && !q.dr_map && !q.rho_map;
+    S.timed = timing;
+    hip_check(hipEventRecord(S.ev0, st));
+    if (graphable) {
+        bool capture = false;
+        hipGraphExec_t exec = graph_for(S, Q, &capture);
+        if (capture) {
+            hipGraph_t g = nullptr;
+            hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue_query(Q, S, st, false);
+            } catch (...) {
+                (void)hipStreamEndCapture(st, &g);
+                if (g)
+                    (void)hipGraphDestroy(g);
+                throw;
+            }
+            hip_check(hipStreamEndCapture(st, &g));
+            hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            hip_check(e);
+            for (auto &sg : S.graphs)
+                if (sg.stamp == S.graph_clock)
+                    sg.exec = exec;
+        }
+        if (exec)
+            hip_check(hipGraphLaunch(exec, st));
+        else
+            enqueue_query(Q, S, st, false);
+    } else {
+        enqueue_query(Q, S, st, timing);
     }
     hip_check(hipEventRecord(S.ev1, st));
-    hip_check(hipMemcpyAsync(S.h_qs.ptr, S.qs.ptr, sizeof(QState), hipMemcpyDeviceToHost, st));
     if (dec_host)
         hip_check(hipMemcpyAsync(dec_host, S.dec.ptr, (size_t)L, hipMemcpyDeviceToHost, st));
 }
@@ -1025,14 +1135,16 @@ zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out)
     float ms = 0.0f;
     hip_check(hipEventElapsedTime(&ms, S.ev0, S.ev1));
     r.device_ms = ms;
-    if (q.mode == ZTS_FULL) {
-        hip_check(hipEventElapsedTime(&r.phase_ms[0], S.ev0, S.evp[0]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[3], S.evp[0], S.evp[1]));
-    } else {
-        hip_check(hipEventElapsedTime(&r.phase_ms[0], S.ev0, S.evp[0]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[1], S.evp[0], S.evp[1]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[2], S.evp[1], S.evp[2]));
-        hip_check(hipEventElapsedTime(&r.phase_ms[3], S.evp[2], S.evp[3]));
+    // per-kernel times, when the query was launched with its events
+    auto span = [](float *out, hipEvent_t a, hipEvent_t b) { hip_check(hipEventElapsedTime(out, a, b)); };
+    if (S.timed && q.mode == ZTS_FULL) {
+        span(&r.phase_ms[0], S.ev0, S.evp[0]);
+        span(&r.phase_ms[3], S.evp[0], S.evp[1]);
+    } else if (S.timed) {
+        span(&r.phase_ms[0], S.ev0, S.evp[0]);
+        span(&r.phase_ms[1], S.evp[0], S.evp[1]);
+        span(&r.phase_ms[2], S.evp[1], S.evp[2]);
+        span(&r.phase_ms[3], S.evp[2], S.evp[3]);
     }
     r.status = ZTS_OK;
     *out = r;
@@ -1280,7 +1392,20 @@ void run_query_main(Ctx *c, Image *im, const uint8_t *tpl, int m, int n, int64_t
     q.rho_map = rho_map;
     zts_status st;
     try {
-        stage_template(c->main, tpl, m, n, stride, device, caller);
+        if (device) {
+            // the kernels read the caller's template in place, after the
+            // caller's stream has reached this call (nothing to wait for when
+            // that stream is idle)
+            q.tpl = tpl;
+            q.ts = stride;
+            if (caller != c->main.stream && hipStreamQuery(caller) != hipSuccess) {
+                (void)hipGetLastError();  // hipErrorNotReady: work is pending
+                hip_check(hipEventRecord(c->main.ev_in, caller));
+                hip_check(hipStreamWaitEvent(c->main.stream, c->main.ev_in, 0));
+            }
+        } else {
+            stage_template(c->main, tpl, m, n, stride);
+        }
         launch_query(q, c->main, dec);
         st = finish_query(q, c->main, out);
     } catch (...) {

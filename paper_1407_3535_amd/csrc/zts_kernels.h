@@ -40,7 +40,9 @@ struct ScanArgs {
     QState *qs;
     int8_t *dec;
     double delta;
-    int cwd;      // MFMA form: dwords per staged image row of a block's region
+    int cwd;      // MFMA form: dword stride of the staged image rows of a block's region
+    int cwn;      // MFMA form: dwords of each staged row that are read
+    int crows_log2;  // MFMA form: log2 of the rows of a staged chunk
 };
 
 // Refinement window on the original image.
@@ -173,7 +175,6 @@ size_t batch_job_records(const BatchJob &j);
 // table lists the BATCH_MULTI jobs first, then the BATCH_SINGLE ones.
 hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s);
 
-hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, hipStream_t s);
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);
 hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s);
 
@@ -185,6 +186,7 @@ hipError_t launch_full(FullArgs a, hipStream_t s);
 // cover fits its LDS budget, else on v_dot4 (k_centres); both write one
 // record per block.
 int centres_record_count(int Gy, int Gx, int m, int n, int h, int w);
+hipError_t launch_reduce(const RecPod *recs, int lo, int hi, QState *qs, hipStream_t s);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);

@@ -4,6 +4,9 @@
 #include "zts_kernels.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "zts_device.h"
 
@@ -99,6 +102,42 @@ __device__ RecPod block_rec(RecPod r, RecPod *red)
     return out;
 }
 
+// Merges the records of a wave: a butterfly over the 64 lanes, after which
+// every lane holds the merged record (the merge is commutative and
+// associative: best by (rho, smallest index), max of r32max, sums of counts).
+__device__ RecPod wave_rec(RecPod r)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        RecPod b;
+        b.rho = __shfl_xor(r.rho, off);
+        b.l = (int64_t)__shfl_xor((long long)r.l, off);
+        b.num = (int64_t)__shfl_xor((long long)r.num, off);
+        b.dr = (int64_t)__shfl_xor((long long)r.dr, off);
+        b.r32max = __shfl_xor(r.r32max, off);
+        b.valid = __shfl_xor(r.valid, off);
+        b.n_elim = __shfl_xor(r.n_elim, off);
+        b.n_surv = __shfl_xor(r.n_surv, off);
+        b.n_window = __shfl_xor(r.n_window, off);
+        rec_merge(r, b);
+    }
+    return r;
+}
+
+// Block reduction through one record per wave; thread 0 gets the result.
+__device__ RecPod block_rec4(RecPod r, RecPod *red)
+{
+    r = wave_rec(r);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    RecPod out = red[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++)
+        rec_merge(out, red[k]);
+    __syncthreads();
+    return out;
+}
+
 // Whole-block reduction of a record range (run by the last block only).
 __device__ RecPod reduce_records(const RecPod *recs, int lo, int hi, RecPod *red)
 {
@@ -167,21 +206,44 @@ struct Thr {
 
 __device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_best0, double delta, Best *red)
 {
+    // one pass over both record ranges: every load is issued before the
+    // wave and block merges (red holds two entries per wave)
+    Best b0 = {-2.0, INT64_MAX, 0}, bw = {-2.0, INT64_MAX, 0};
+    for (int k = threadIdx.x; k < n1 + n2; k += blockDim.x) {
+        const RecPod *p = recs + k;
+        best_merge(k < n1 ? b0 : bw, p->rho, p->l, p->valid);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        double r0 = __shfl_xor(b0.rho, off), r1 = __shfl_xor(bw.rho, off);
+        long long l0 = __shfl_xor((long long)b0.l, off), l1 = __shfl_xor((long long)bw.l, off);
+        int v0 = __shfl_xor(b0.valid, off), v1 = __shfl_xor(bw.valid, off);
+        best_merge(b0, r0, (int64_t)l0, v0);
+        best_merge(bw, r1, (int64_t)l1, v1);
+    }
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = b0;
+        red[nw + (threadIdx.x >> 6)] = bw;
+    }
+    __syncthreads();
+    Best f0 = red[0], fw = red[nw];
+    for (int w = 1; w < nw; w++) {
+        best_merge(f0, red[w].rho, red[w].l, red[w].valid);
+        best_merge(fw, red[nw + w].rho, red[nw + w].l, red[nw + w].valid);
+    }
+    __syncthreads();
     Thr r;
-    Best f0 = reduce_best(recs, 0, n1, red);
     r.best0 = f0.rho;
     r.best0_l = f0.l;
-    Best bw = {-2.0, INT64_MAX, 0};
     if (n2 > 0) {
-        bw = reduce_best(recs, n1, n1 + n2, red);
         if (include_best0)
-            best_merge(bw, f0.rho, f0.l, 1);
+            best_merge(fw, f0.rho, f0.l, 1);
     } else {
-        bw = f0;
+        fw = f0;
     }
-    r.best = bw.rho;
-    r.best_l = bw.l;
-    r.thr64 = bw.rho - delta;
+    r.best = fw.rho;
+    r.best_l = fw.l;
+    r.thr64 = fw.rho - delta;
     double c = r.thr64 > 1.0 ? 1.0 : (r.thr64 < -1.0 ? -1.0 : r.thr64);
     float th = (float)acos(c);
     r.lo = th - kEpsTheta;
@@ -421,14 +483,15 @@ __global__ __launch_bounds__(256) void k_full(FullArgs a)
         }
     }
     __syncthreads();
-    RecPod *rred = (RecPod *)smem;
-    RecPod b = block_rec(rec, rred);
+    __shared__ RecPod red4[4];
+    RecPod b = block_rec4(rec, red4);
     int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if (t == 0) {
         a.recs[bid] = b;
-        if (bid == 0) {
+        if (bid == 0) {  // the query state needs no fill before the scans
             a.qs->st = st;
             a.qs->dt = dt;
+            a.qs->degenerate = 0;
         }
     }
 }
@@ -561,22 +624,27 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
     int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if (t == 0) {
         a.recs[bid] = b;
-        if (bid == 0) {
+        if (bid == 0) {  // the query state needs no fill before the scans
             a.qs->st = st;
             a.qs->dt = dt;
+            a.qs->degenerate = 0;
         }
     }
 }
 
 // Scan 1 on int8 MFMA: M = 16 centre columns (stride w), N = 16 centre rows
 // (stride h), K = 4 image rows x 16 columns.  A block holds 16 centre rows x
-// 64 centre columns, one M-tile per wave.  The image region its windows
-// cover streams through LDS in chunks of kCmChunk rows (one copy; A fragments
-// are realigned with v_alignbyte), so a block waits on a few global loads
-// only.  For image row y, lane (j, g) of the B fragment carries template row
-// y - cy_j (the zero row outside the template).  Outputs equal k_centres'.
-constexpr int kCmChunk = 32;
-constexpr int kCmLd = 24;   // staged words per thread and chunk, at most
+// 64 centre columns: one M-tile per wave, and two waves per M-tile that take
+// alternate groups of 4 image rows (their sums are added at the end).  The
+// image region its windows cover streams through LDS in chunks of 32 or 16
+// rows (one copy, A fragments are realigned with v_alignbyte),
+// double-buffered so that a chunk's loads are in flight while the previous
+// chunk is multiplied.  Each wave of an M-tile finishes two of its four
+// accumulator columns.  For image row y, lane (j, g) of the B
+// fragment carries template row y - cy_j (the zero row outside the
+// template).  Outputs equal k_centres'.
+constexpr int kCmThreads = 512;
+constexpr int kCmLd = 12;   // staged words per thread and chunk, at most
 
 // Template rows flipped to int8 at row stride tstr, then one zero row; the
 // block sums of t' and t'^2.  Whole words are loaded when the rows are
@@ -602,127 +670,204 @@ __device__ void load_template_rows(const uint8_t *__restrict__ tpl, int64_t ts, 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_centres_mfma(ScanArgs a)
+template <int NB>  // 16-byte column blocks of the template row (n16 = 16 NB)
+__global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
-    __shared__ RecPod rred[256];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int m = a.m, n = a.n, n16 = (n + 15) & ~15, nw16 = n16 >> 2, nb16 = n16 >> 4;
-    const int tstr = batch_tstride(nw16), CWd = a.cwd, CW = kCmChunk * CWd;
+    __shared__ RecPod rred[kCmThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, mt = wv & 3, kh = wv >> 2;
+    const int m = a.m, n = a.n;
+    constexpr int nw16 = 4 * NB;
+    const int tstr = batch_tstride(nw16), CWd = a.cwd, CWn = a.cwn;
+    const int crl = a.crows_log2, crows = 1 << crl, CW = crows * CWd;
     uint32_t *tpl_l = smem;                         // m rows and the zero row m, stride tstr
     uint32_t *buf0 = smem + (m + 1) * tstr;         // two chunk buffers of CW dwords
-    int64_t st, sq;
-    load_template_rows(a.tpl, a.ts, m, n, nw16, tstr, tpl_l, red, &st, &sq);
-    const int64_t mn = (int64_t)m * n;
-    const int64_t dt = mn * sq - st * st;
-    if (dt == 0) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
-            a.qs->degenerate = 1;
-        return;
-    }
     auto ccol = [&](int gx) { int ox = gx * a.w; return ox + (min(a.w, a.Lx - ox) - 1) / 2; };
     auto crow = [&](int gy) { int oy = gy * a.h; return oy + (min(a.h, a.Ly - oy) - 1) / 2; };
     const int gx0 = blockIdx.x * 64, gy0 = blockIdx.y * 16;
-    const int nx = min(64, a.Gx - gx0), ny = min(16, a.Gy - gy0);
+    const int ny = min(16, a.Gy - gy0);
     const int xw0 = ccol(gx0) >> 2;                 // first staged word of the region's rows
     const int ylo = crow(gy0), yhi = crow(gy0 + ny - 1) + m;
-    const int nchunk = (yhi - ylo + kCmChunk - 1) / kCmChunk;
+    const int nchunk = (yhi - ylo + crows - 1) >> crl;
     const uint32_t *img32 = (const uint32_t *)a.img;
     const int64_t pw = a.pitch >> 2;
-    // staging: 8 threads per chunk row, thread (r, q) copies words q, q + 8, ...
-    static_assert(kCmChunk * 8 == 256, "8 threads per staged row");
-    const int sr = t >> 3, sq8 = t & 7;
+    // staging: 512 / crows threads per chunk row; thread (r, q) copies words
+    // q, q + 512 / crows, ... of the CWn that the A reads can reach (the rest
+    // of the CWd stride is bank padding, never read).  Loads come from
+    // clamped, in-image addresses: a staged byte that is not a pixel of a
+    // centre's window (past the image row, or a row past the region) only
+    // ever meets a zero template byte (a column past n, or the zero row), so
+    // its value does not matter.
+    const int tpl2 = 9 - crl, tpr = 1 << tpl2;  // threads per row
+    const int sr = t >> tpl2, sq = t & (tpr - 1);
+    const int wlim = (int)min((int64_t)CWn, pw - xw0);  // >= 1: the first centre lies in the row
     uint32_t rv[kCmLd];
     auto cload = [&](int c) {
-        const int y = ylo + kCmChunk * c + sr;
-        const uint32_t *row = img32 + (int64_t)min(y, yhi - 1) * pw + xw0;
-        const bool yok = y < yhi;
+        const int y = min(ylo + (c << crl) + sr, yhi - 1);
+        const uint32_t *row = img32 + (int64_t)y * pw + xw0;
 #pragma unroll
-        for (int k = 0; k < kCmLd; k++) {
-            int wd = sq8 + 8 * k;
-            rv[k] = 0x80808080u;
-            if (yok && wd < CWd && xw0 + wd < pw)
-                rv[k] = *gptr(row + wd);
-        }
+        for (int k = 0; k < kCmLd; k++)
+            if (k * tpr < CWn)
+                rv[k] = *gptr(row + min(sq + k * tpr, wlim - 1));
     };
     auto cstore = [&](int c) {
         uint32_t *b = buf0 + (c & 1) * CW + sr * CWd;
 #pragma unroll
         for (int k = 0; k < kCmLd; k++) {
-            int wd = sq8 + 8 * k;
-            if (wd < CWd)
+            int wd = sq + k * tpr;
+            if (wd < CWn)
                 b[wd] = flip4(rv[k]);
         }
     };
     const int g = lane >> 4, jr = lane & 15;
-    const int cxa = ccol(min(gx0 + 16 * wv + jr, a.Gx - 1)) - 4 * xw0;  // A lane: its centre column in the region
+    const int cxa = ccol(min(gx0 + 16 * mt + jr, a.Gx - 1)) - 4 * xw0;  // A lane: its centre column in the region
     const int cyb = crow(min(gy0 + jr, a.Gy - 1));                        // B lane: its centre row
     const bool jok = jr < ny;
-    v4i acc = v4i{0, 0, 0, 0};
+    // The first chunk and the epilogue's centre statistics are in flight
+    // while the template loads.
     cload(0);
+    // accumulator lane: centre row gy0 + (lane & 15), centre columns
+    // gx0 + 16 mt + 4 (lane >> 4) + v; this wave finishes v = 2 kh, 2 kh + 1
+    const int gyy = gy0 + jr;
+    int2 sc[2];
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
+        sc[e] = make_int2(0, 0);
+        if (gyy < a.Gy && gxx < a.Gx)
+            sc[e] = ld_int2(a.stat + (int64_t)crow(gyy) * a.Lx + ccol(gxx));
+    }
+    int64_t st, sq2;
+    load_template_rows(a.tpl, a.ts, m, n, nw16, tstr, tpl_l, red, &st, &sq2);
+    const int64_t mn = (int64_t)m * n;
+    const int64_t dt = mn * sq2 - st * st;
+    if (dt == 0) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
+            a.qs->degenerate = 1;
+        return;
+    }
     cstore(0);
     __syncthreads();
+    v4i acc = v4i{0, 0, 0, 0};
+    const int aw = cxa >> 2;
+    const uint32_t ash = (uint32_t)(cxa & 3);
     for (int c = 0; c < nchunk; c++) {
         if (c + 1 < nchunk)
             cload(c + 1);
         const uint32_t *b = buf0 + (c & 1) * CW;
-        const int rows = min(kCmChunk, yhi - ylo - kCmChunk * c);
-        for (int k = 0; 4 * k < rows; k++) {
+        const int rows = min(crows, yhi - ylo - (c << crl));
+        for (int k = kh; 4 * k < rows; k += 2) {
             const int yr = 4 * k + g;                      // row of the chunk for this lane group
-            const int tr = ylo + kCmChunk * c + yr - cyb;  // template row for B lane (jr, g)
+            const int tr = ylo + (c << crl) + yr - cyb;    // template row for B lane (jr, g)
             const int brow = jok && (unsigned)tr < (unsigned)m ? tr : m;
-            const uint32_t *pa = b + yr * CWd;
-#pragma unroll 4
-            for (int cb = 0; cb < nb16; cb++) {
-                int bo = cxa + 16 * cb;
-                const uint32_t *pw5 = pa + (bo >> 2);
-                uint32_t w0 = pw5[0], w1 = pw5[1], w2 = pw5[2], w3 = pw5[3], w4 = pw5[4];
-                uint32_t sh = (uint32_t)(bo & 3);
+            const uint32_t *pa = b + yr * CWd + aw;
+            const uint32_t *pb = tpl_l + brow * tstr;
+            // bytes cxa + 16 cb .. + 15 of the row are words 4 cb .. 4 cb + 4
+            uint32_t wd[4 * NB + 1];
+            v4i B[NB];
+#pragma unroll
+            for (int i = 0; i <= 4 * NB; i++)
+                wd[i] = pa[i];
+#pragma unroll
+            for (int cb = 0; cb < NB; cb++)
+                B[cb] = *(const v4i *)(pb + 4 * cb);
+#pragma unroll
+            for (int cb = 0; cb < NB; cb++) {
                 v4i A;
-                A[0] = (int)bytes_at(w1, w0, sh);
-                A[1] = (int)bytes_at(w2, w1, sh);
-                A[2] = (int)bytes_at(w3, w2, sh);
-                A[3] = (int)bytes_at(w4, w3, sh);
-                v4i B = *(const v4i *)(tpl_l + brow * tstr + 4 * cb);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
+                A[0] = (int)bytes_at(wd[4 * cb + 1], wd[4 * cb], ash);
+                A[1] = (int)bytes_at(wd[4 * cb + 2], wd[4 * cb + 1], ash);
+                A[2] = (int)bytes_at(wd[4 * cb + 3], wd[4 * cb + 2], ash);
+                A[3] = (int)bytes_at(wd[4 * cb + 4], wd[4 * cb + 3], ash);
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B[cb], acc, 0, 0, 0);
             }
         }
         if (c + 1 < nchunk)
             cstore(c + 1);
         __syncthreads();
     }
-    // lane holds centre row gy0 + (lane & 15) and centre columns
-    // gx0 + 16 wv + 4 (lane >> 4) + v
-    RecPod rec = rec_empty();
-    const int gyy = gy0 + jr;
+    // the two waves of an M-tile swap the partial sums of the columns the
+    // other one finishes (the chunk buffers are free: the loop ended with a
+    // barrier)
+    int2 *xch = (int2 *)buf0;
+    xch[(kh * 4 + mt) * 64 + lane] = kh ? make_int2(acc[0], acc[1]) : make_int2(acc[2], acc[3]);
+    __syncthreads();
+    const int2 o = xch[((1 - kh) * 4 + mt) * 64 + lane];
+    int64_t num[2], dc[2];
+    float r32[2];
+    bool ok[2];
+    float lmax = -2.0f;
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-        const int gxx = gx0 + 16 * wv + 4 * g + v;
-        if (gyy < a.Gy && gxx < a.Gx) {
-            const int cy = crow(gyy), cx = ccol(gxx);
-            const int64_t l = (int64_t)cy * a.Lx + cx;
-            const int2 sc = ld_int2(a.stat + l);
-            const int64_t dc = var_num(mn, sc);
-            const int64_t num = mn * (int64_t)acc[v] - st * (int64_t)sc.x;
+    for (int e = 0; e < 2; e++) {
+        const int v = 2 * kh + e;
+        const int gxx = gx0 + 16 * mt + 4 * g + v;
+        ok[e] = gyy < a.Gy && gxx < a.Gx;
+        const int x = (kh ? acc[2 + e] : acc[e]) + (e ? o.y : o.x);
+        dc[e] = var_num(mn, sc[e]);
+        num[e] = mn * (int64_t)x - st * (int64_t)sc[e].x;
+        r32[e] = rho32(num[e], dt, dc[e]);
+        if (ok[e]) {
             const int gi = gyy * a.Gx + gxx;
-            a.g_num[gi] = num;
-            a.g_theta[gi] = theta32(num, dt, dc);
-            rec_offer(rec, rho32(num, dt, dc), l, num, dt, dc);
+            a.g_num[gi] = num[e];
+            a.g_theta[gi] = theta32(num[e], dt, dc[e]);
+            lmax = fmaxf(lmax, r32[e]);
             if (a.dec)
-                a.dec[l] = 1;
+                a.dec[(int64_t)crow(gyy) * a.Lx + ccol(gxx)] = 1;
         }
     }
-    RecPod bb = block_rec(rec, rred);
+    // Only centres within kEpsRho of the wave's largest binary32 rho can be
+    // the block's best: they alone are evaluated in binary64, and the wave's
+    // record is picked among those lanes (usually one) in lane order.
+    float wmax = lmax;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        wmax = fmaxf(wmax, __shfl_xor(wmax, off));
+    double brho = -2.0;
+    int64_t bl = INT64_MAX, bnum = 0, bdr = 0;
+    bool bv = false;
+#pragma unroll
+    for (int e = 0; e < 2; e++)
+        if (ok[e] && r32[e] >= wmax - kEpsRho) {
+            const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
+            const int64_t l = (int64_t)crow(gyy) * a.Lx + ccol(gxx);
+            const double r = rho64(num[e], dt, dc[e]);
+            if (!bv || rec_better(r, l, brho, bl)) {
+                brho = r;
+                bl = l;
+                bnum = num[e];
+                bdr = dc[e];
+                bv = true;
+            }
+        }
+    RecPod rec = rec_empty();
+    rec.r32max = wmax;
+    for (uint64_t msk = __ballot(bv); msk; msk &= msk - 1) {
+        const int src = __ffsll((unsigned long long)msk) - 1;
+        const double r = __shfl(brho, src);
+        const int64_t l = (int64_t)__shfl((long long)bl, src);
+        if (!rec.valid || rec_better(r, l, rec.rho, rec.l)) {
+            rec.rho = r;
+            rec.l = l;
+            rec.num = (int64_t)__shfl((long long)bnum, src);
+            rec.dr = (int64_t)__shfl((long long)bdr, src);
+            rec.valid = 1;
+        }
+    }
+    if (lane == 0)
+        rred[wv] = rec;
+    __syncthreads();
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
     if (t == 0) {
+        RecPod bb = rred[0];
+        for (int k = 1; k < kCmThreads / 64; k++)
+            rec_merge(bb, rred[k]);
         a.recs[bid] = bb;
-        if (bid == 0) {
+        if (bid == 0) {  // the query state needs no fill before the scans
             a.qs->st = st;
             a.qs->dt = dt;
+            a.qs->degenerate = 0;
         }
     }
-    (void)nx;
 }
 
 // ============================================================== refinement window
@@ -739,14 +884,16 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
     __shared__ unsigned long long ured[8];
     __shared__ Best bred[4];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (a.qs->degenerate)
-        return;
+    // the query state, the template and the scan-1 records in one round trip
+    const int degenerate = a.qs->degenerate;
     int n4 = (a.n + 3) >> 2;
     int64_t st, sq;
     load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t dt = mn * sq - st * st;
     const int64_t c0 = reduce_best(a.recs, 0, a.rec_off, bred).l;  // best scan-1 centre
+    if (degenerate)
+        return;
     int cy0 = (int)(c0 / a.Lx), cx0 = (int)(c0 - (c0 / a.Lx) * a.Lx);
     int W = 2 * a.radius + 1;
     int total = W * W;
@@ -784,6 +931,8 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
 }
 
 // ============================================================== scan 2: members
+
+constexpr int kMemGroups = 512;  // groups per k_members block (two per thread)
 
 __device__ __forceinline__ bool in_window(int y, int x, int wy, int wx, int radius)
 {
@@ -867,20 +1016,34 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
 // block reduces every record of the query.
 __global__ __launch_bounds__(256) void k_members(MemArgs a)
 {
-    constexpr int CAP = 2048;
+    constexpr int CAP = 1024;  // members per pass: 4 per thread
+    constexpr int GB = kMemGroups;
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int s_pref[257];
+    __shared__ int s_pref[GB + 1];
     __shared__ int s_tmp[4];
-    __shared__ int s_geo[256][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
+    __shared__ int s_geo[GB][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
     __shared__ int s_list[CAP];
     __shared__ int s_nsurv, s_tpl;
     __shared__ RecPod wrec[4];
     __shared__ unsigned long long ured[8];
-    __shared__ Best bred[4];
+    __shared__ Best bred[8];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (a.qs->degenerate)
-        return;
+    // This thread's two groups (2t, 2t + 1 of the block), the query state and
+    // the earlier kernels' records are all read in the first round trip.
+    const int G = a.Gy * a.Gx;
+    const int g0 = blockIdx.x * GB;
+    float A2[2] = {0.0f, 0.0f};
+    GroupSum gs2[2] = {{0.0f, 0.0f, 0.0f, 1}, {0.0f, 0.0f, 0.0f, 1}};
+#pragma unroll
+    for (int e = 0; e < 2; e++)
+        if (g0 + 2 * t + e < G) {
+            A2[e] = a.g_theta[g0 + 2 * t + e];
+            gs2[e] = a.gsum[g0 + 2 * t + e];
+        }
+    const int degenerate = a.qs->degenerate;
     const Thr thr = block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, bred);
+    if (degenerate)
+        return;
     if (blockIdx.x == 0 && t == 0)
         store_threshold(a.qs, thr);
     const int n4 = (a.n + 3) >> 2;
@@ -889,7 +1052,6 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     const float lo = thr.lo, hi = thr.hi;
     const double thr64 = thr.thr64;
     const int hw = a.h * a.w;
-    const int G = a.Gy * a.Gx;
     int wy = -1, wx = -1;
     if (a.radius >= 0) {
         int64_t c0 = thr.best0_l;
@@ -897,20 +1059,21 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         wx = (int)(c0 - (c0 / a.Lx) * a.Lx);
     }
     unsigned long long n_elim = 0, n_surv = 0;
-    const int g0 = blockIdx.x * 256;
 
-    int cnt = 0;
-    {
-        int g = g0 + t;
+    int cnt2[2] = {0, 0};
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const int u = 2 * t + e, g = g0 + u;
+        const float A = A2[e];
+        const GroupSum gs = gs2[e];
+        int &cnt = cnt2[e];
         if (g < G) {
             int oy, ox, hh, ww, cy, cx;
             group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
-            float A = a.g_theta[g];
-            s_geo[t][0] = (oy << 16) | ox;
-            s_geo[t][1] = (hh << 16) | ww;
-            s_geo[t][2] = (cy << 16) | cx;
-            s_geo[t][3] = __float_as_int(A);
-            GroupSum gs = a.gsum[g];
+            s_geo[u][0] = (oy << 16) | ox;
+            s_geo[u][1] = (hh << 16) | ww;
+            s_geo[u][2] = (cy << 16) | cx;
+            s_geo[u][3] = __float_as_int(A);
             bool drop = false;
             if (!(gs.flags & 1)) {
                 float d = 0.0f;
@@ -947,9 +1110,11 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         }
     }
     int total;
-    s_pref[t] = block_excl_scan(cnt, s_tmp, &total);
+    const int off = block_excl_scan(cnt2[0] + cnt2[1], s_tmp, &total);
+    s_pref[2 * t] = off;
+    s_pref[2 * t + 1] = off + cnt2[0];
     if (t == 0) {
-        s_pref[256] = total;
+        s_pref[GB] = total;
         s_nsurv = 0;
         s_tpl = 0;
     }
@@ -957,8 +1122,10 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     RecPod rec = rec_empty();
     for (int base = 0; base < total; base += CAP) {
         int end = min(total, base + CAP);
-        // locate this thread's (up to 8) members and load their angles first
-        int64_t o8[CAP / 256], sl8[CAP / 256];
+        // locate this thread's (up to 4) members and load their angles first
+        // (locations and slots fit 32 bits: image sides are at most 32767,
+        // so the tables hold fewer than 2^31 entries)
+        int o8[CAP / 256], sl8[CAP / 256];
         int u8[CAP / 256];
         float B8[CAP / 256], C8[CAP / 256];
 #pragma unroll
@@ -968,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             if (idx >= end)
                 continue;
             int u = 0;
-            for (int step = 128; step > 0; step >>= 1)
+            for (int step = GB / 2; step > 0; step >>= 1)
                 if (s_pref[u + step] <= idx)
                     u += step;
             int k = idx - s_pref[u];
@@ -979,8 +1146,8 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             int y = oy + my, x = ox + mx;
             if ((!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius))
                 continue;
-            o8[q] = (int64_t)y * a.Lx + x;
-            sl8[q] = (int64_t)(g0 + u) * hw + my * a.w + mx;
+            o8[q] = y * a.Lx + x;
+            sl8[q] = (g0 + u) * hw + my * a.w + mx;
             u8[q] = u;
             B8[q] = a.theta_b[sl8[q]];
             C8[q] = a.opta ? a.theta_c[sl8[q]] : 0.0f;
@@ -2014,33 +2181,42 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 
 // ============================================================== record reductions
 
+// ============================================================== final reduction
+
 // One block folds the per-block records of the final scan (and of the window
 // when it counts) into the answer, after the kernels that wrote them have
-// finished (the kernel boundary makes them visible on every XCD).
-__global__ __launch_bounds__(256) void k_reduce(RecPod *__restrict__ recs, int lo, int hi, QState *qs)
+// finished: the kernel boundary makes the records visible on every XCD
+// without a device-scope fence in each writing block.
+__global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi, QState *qs)
 {
-    __shared__ RecPod rred[256];
-    if (qs->degenerate)
+    __shared__ RecPod red[16];
+    const int degenerate = qs->degenerate;
+    // up to four records per thread are loaded before they are merged
+    RecPod r = rec_empty();
+    for (int k0 = lo + threadIdx.x; k0 < hi; k0 += 4 * blockDim.x) {
+        RecPod b[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            b[j] = k0 + j * (int)blockDim.x < hi ? recs[k0 + j * blockDim.x] : rec_empty();
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            rec_merge(r, b[j]);
+    }
+    RecPod f = block_rec4(r, red);
+    if (degenerate)
         return;
-    RecPod f = reduce_records(recs, lo, hi, rred);
-    if (threadIdx.x != 0)
-        return;
-    qs->fin = f;
-    qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
-    qs->n_elim = f.n_elim;
-    qs->n_surv = f.n_surv;
-    qs->n_window = f.n_window;
+    if (threadIdx.x == 0) {
+        qs->fin = f;
+        qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
+        qs->n_elim = f.n_elim;
+        qs->n_surv = f.n_surv;
+        qs->n_window = f.n_window;
+    }
 }
 
 // ============================================================== launch wrappers
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
-
-hipError_t launch_reduce(RecPod *recs, int lo, int hi, QState *qs, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, recs, lo, hi, qs);
-    return hipGetLastError();
-}
 
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s)
 {
@@ -2061,14 +2237,18 @@ hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, i
 
 static constexpr int kFullR = 8;
 
+hipError_t launch_reduce(const RecPod *recs, int lo, int hi, QState *qs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, recs, lo, hi, qs);
+    return hipGetLastError();
+}
+
 int full_record_count(int Ly, int Lx) { return (int)(blocks_for(Lx, 256) * blocks_for(Ly, 4 * kFullR)); }
 
 size_t full_lds_bytes(int m, int n)
 {
     int n4w = (((n + 3) / 4) + 3) / 4 * 4;
-    size_t tile = (size_t)(4 * kFullR + m - 1) * (64 + n4w) * 4 + (size_t)(m + 2 * kFullR - 2) * n4w * 4;
-    size_t red = 256 * sizeof(RecPod);
-    return tile > red ? tile : red;
+    return (size_t)(4 * kFullR + m - 1) * (64 + n4w) * 4 + (size_t)(m + 2 * kFullR - 2) * n4w * 4;
 }
 
 hipError_t launch_full(FullArgs a, hipStream_t s)
@@ -2108,34 +2288,129 @@ static int centre_rows(int m, int n, int h)
     return 1;
 }
 
-// Dwords per staged row of k_centres_mfma's region (64 centre columns of
-// stride w, the template width, realignment slack), or 0 when its LDS or
-// staging registers would not suffice.
-static int centres_mfma_cwd(int m, int n, int w)
+// Dwords of a staged row of k_centres_mfma's region that the A reads can
+// reach (64 centre columns of stride w, the template width, realignment
+// slack).
+static int centres_mfma_cwn(int n, int w)
 {
     int n16 = (n + 15) / 16 * 16;
-    int cwd = (63 * w + w / 2 + n16 + 12) / 4 + 2;
-    size_t lds = ((size_t)(m + 1) * batch_tstride(n16 / 4) + (size_t)2 * kCmChunk * cwd) * 4;
-    if (n16 > 128 || lds > 48 * 1024 || cwd > kCmLd * 8)
-        return 0;
-    return cwd;
+    return (63 * w + w / 2 + n16 + 12) / 4 + 2;
+}
+
+// LDS bank cost of the A reads for a staged-row stride of cwd dwords: lane
+// (j, g) of wave v reads dword g cwd + ((r + (16 v + j) w) >> 2) plus a
+// common offset, r being the byte offset of the region's first centre in its
+// word.  The cost is the largest number of distinct dwords that fall in one
+// of the 64 four-byte banks, summed over r and v.
+static int centres_bank_cost(int cwd, int w)
+{
+    int cost = 0;
+    for (int r = 0; r < 4; r++)
+        for (int v = 0; v < 4; v++) {
+            int words[64], nw = 0, cnt[64] = {0};
+            for (int g = 0; g < 4; g++)
+                for (int j = 0; j < 16; j++) {
+                    int d = g * cwd + ((r + (16 * v + j) * w) >> 2);
+                    bool dup = false;
+                    for (int k = 0; k < nw; k++)
+                        dup |= words[k] == d;
+                    if (!dup) {
+                        words[nw++] = d;
+                        cnt[d & 63]++;
+                    }
+                }
+            int worst = 0;
+            for (int b = 0; b < 64; b++)
+                worst = cnt[b] > worst ? cnt[b] : worst;
+            cost += worst;
+        }
+    return cost;
+}
+
+static size_t centres_mfma_lds(int m, int n, int cwd, int crows)
+{
+    int n16 = (n + 15) / 16 * 16;
+    return ((size_t)(m + 1) * batch_tstride(n16 / 4) + (size_t)2 * crows * cwd) * 4;
+}
+
+// Staging shape of k_centres_mfma: chunk rows (32 or 16, the most that
+// fit 60 KB of LDS with the reachable width staged by 512 / rows threads
+// per row, kCmLd words each) and the row stride with the least bank cost
+// among the reachable width and up to 63 dwords more.  cwd = 0 when the
+// MFMA form does not apply (n > 128, or no chunk height fits).  The chunk
+// buffers also hold the 4 x 64 accumulator exchange (1024 dwords).
+struct CmShape {
+    int cwd, cwn, crows;
+};
+
+static CmShape centres_mfma_shape_search(int m, int n, int w)
+{
+    const size_t kLds = 60 * 1024;
+    int n16 = (n + 15) / 16 * 16;
+    int cwn = centres_mfma_cwn(n, w);
+    CmShape r = {0, cwn, 0};
+    if (n16 > 128)
+        return r;
+    for (int crows = 32; crows >= 16 && !r.crows; crows >>= 1)
+        if (cwn <= kCmLd * (kCmThreads / crows) && 2 * crows * cwn >= 1024 &&
+            centres_mfma_lds(m, n, cwn, crows) <= kLds)
+            r.crows = crows;
+    if (!r.crows)
+        return r;
+    int best = cwn, best_cost = centres_bank_cost(cwn, w);
+    for (int cwd = cwn + 1; cwd < cwn + 64 && centres_mfma_lds(m, n, cwd, r.crows) <= kLds; cwd++) {
+        int c = centres_bank_cost(cwd, w);
+        if (c < best_cost) {
+            best = cwd;
+            best_cost = c;
+        }
+    }
+    r.cwd = best;
+    return r;
+}
+
+// The search above, memoised per (m, n, w): it runs once per shape, not per
+// query (callers may be on several threads).
+static CmShape centres_mfma_shape(int m, int n, int w)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, CmShape> memo;
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_tuple(m, n, w);
+    auto it = memo.find(key);
+    if (it != memo.end())
+        return it->second;
+    CmShape r = centres_mfma_shape_search(m, n, w);
+    memo.emplace(key, r);
+    return r;
 }
 
 int centres_record_count(int Gy, int Gx, int m, int n, int h, int w)
 {
-    if (centres_mfma_cwd(m, n, w))
+    if (centres_mfma_shape(m, n, w).cwd)
         return (int)(blocks_for(Gx, 64) * blocks_for(Gy, 16));
     return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(m, n, h)));
 }
 
 hipError_t launch_centres(ScanArgs a, hipStream_t s)
 {
-    if (int cwd = centres_mfma_cwd(a.m, a.n, a.w)) {
-        a.cwd = cwd;
-        int n16 = (a.n + 15) / 16 * 16;
-        size_t lds = ((size_t)(a.m + 1) * batch_tstride(n16 / 4) + (size_t)2 * kCmChunk * cwd) * 4;
-        dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, 16));
-        hipLaunchKernelGGL(k_centres_mfma, grid, dim3(256), lds, s, a);
+    CmShape sh = centres_mfma_shape(a.m, a.n, a.w);
+    if (sh.cwd) {
+        a.cwd = sh.cwd;
+        a.cwn = sh.cwn;
+        a.crows_log2 = sh.crows == 32 ? 5 : 4;
+        size_t lds = centres_mfma_lds(a.m, a.n, sh.cwd, sh.crows);
+        dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, 16)), blk(kCmThreads);
+        switch ((a.n + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_centres_mfma<1>, grid, blk, lds, s, a); break;
+        case 2: hipLaunchKernelGGL(k_centres_mfma<2>, grid, blk, lds, s, a); break;
+        case 3: hipLaunchKernelGGL(k_centres_mfma<3>, grid, blk, lds, s, a); break;
+        case 4: hipLaunchKernelGGL(k_centres_mfma<4>, grid, blk, lds, s, a); break;
+        case 5: hipLaunchKernelGGL(k_centres_mfma<5>, grid, blk, lds, s, a); break;
+        case 6: hipLaunchKernelGGL(k_centres_mfma<6>, grid, blk, lds, s, a); break;
+        case 7: hipLaunchKernelGGL(k_centres_mfma<7>, grid, blk, lds, s, a); break;
+        default: hipLaunchKernelGGL(k_centres_mfma<8>, grid, blk, lds, s, a); break;
+        }
         return hipGetLastError();
     }
     a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
@@ -2167,7 +2442,7 @@ hipError_t launch_window(WinArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-int members_record_count(int Gy, int Gx) { return (int)blocks_for((int64_t)Gy * Gx, 256); }
+int members_record_count(int Gy, int Gx) { return (int)blocks_for((int64_t)Gy * Gx, kMemGroups); }
 
 hipError_t launch_members(MemArgs a, hipStream_t s)
 {

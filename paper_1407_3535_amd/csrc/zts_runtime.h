@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <tuple>
 #include <unordered_map>
@@ -25,7 +26,10 @@ struct ZtsError {
     zts_status st;
 };
 
-void hip_check(hipError_t e);
+void hip_check_at(hipError_t e, const char *file, int line);
+// Throws ZTS_E_DEVICE on a HIP error (printed with its call site when the
+// environment sets ZTS_DEBUG).
+#define hip_check(e) ::zts::hip_check_at((e), __FILE__, __LINE__)
 
 struct Ctx;
 
@@ -67,16 +71,29 @@ struct HostBuf {
 // priority, non-blocking), its timing events, device scratch grown on demand
 // and pinned host staging.  The synchronous entry points use the context's
 // main slot; every serving worker owns one.
+// A captured query launch sequence (see launch_query).
+struct SlotGraph {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t stamp = 0;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_in = nullptr;  // orders the slot's stream after a caller's stream
     hipEvent_t evp[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     DBuf qs, recs, gnum, gtheta, tpl, dec;       // one query
     DBuf bdata, bres, brec;                      // one batched launch
     HostBuf h_qs, h_stage, h_out;
+    bool use_graphs = true;
+    bool timed = false;             // the last query recorded its per-kernel events
+    std::vector<SlotGraph> graphs;  // keyed by the launch arguments
+    uint64_t graph_clock = 0;
     void init();      // throws ZTS_E_DEVICE
     void destroy();   // waits for the stream first
     void release_scratch();
+    void drop_graphs();
 };
 
 struct Stats {
@@ -180,11 +197,15 @@ struct QueryPlan {
     zts_mode mode = ZTS_FULL;
     zts_params pr;
     bool want_dec = false;
+    const uint8_t *tpl = nullptr;   // template read in place (device memory), else the slot's copy
+    int64_t ts = 0;                 // its row stride
     int64_t *num_map = nullptr, *dr_map = nullptr;
     float *rho_map = nullptr;
 };
 QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, const zts_params &pr, bool want_dec);
-void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride, bool device, hipStream_t caller);
+// Copies a host template into the slot's device buffer (pitch n) through its
+// pinned staging, on the slot's stream.
+void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride);
 void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host);
 zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out);
 void unpin_query(QueryPlan &q);

@@ -34,7 +34,6 @@ struct QState {
     float thr_lo, thr_hi;  // acos(thr64) -/+ guard band, binary32
     // counters
     unsigned long long n_centres, n_window, n_elim, n_surv;
-    unsigned int done[4];  // last-block tickets, reset by the last block
     // answer
     RecPod fin;
     float fin_r32;
