@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 # Derived VALU peak for the int8 dot-product kernels (v_dot4c_i32_i8): 256 CUs
 # x 4 SIMDs x 16 lanes x 4 multiply-adds per lane per clock x 2 ops x 2.4 GHz.
 PEAK_DOT4_TOPS = 256 * 4 * 16 * 4 * 2 * 2.4e9 / 1e12
+# Dense int8 MFMA peak of MI355X (5.0 POP/s) and its HBM3E bandwidth (8 TB/s).
+PEAK_MFMA_I8_TOPS = 5000.0
+PEAK_HBM_GBS = 8000.0
 
 
 def measured_traffic(kernel):
@@ -161,19 +164,28 @@ def main():
                            "answer": [rr["y"], rr["x"], rr["rho"]]}
     full_ms = modes.get("full", {}).get("ms_per_query")
 
-    # dominant kernel of the timed mode and its algorithmic int8 work
+    # Dominant kernel of the timed mode (by its HIP-event time) and its
+    # algorithmic work.  Scan 1 on int8 MFMA: 2 mn ops per group centre,
+    # against the dense int8 MFMA peak.  Scan 2: HBM bytes it must read at
+    # least, 20 per group (its angle and range summary) plus mn + 8 per
+    # window or survivor location it matches.  The plain full kernel (VALU
+    # dot4): 2 mn ops per location against the derived dot4 peak.
     mn = m * n
     if args.mode == "full":
-        kernels = [("k_full", ph[0], L)]
+        kernels = [("k_full", ph[0], "alu", PEAK_DOT4_TOPS, "TOP/s", 2.0 * mn * L)]
     else:
-        window = r["n_computed"] - r["n_survivors"] - (0 if args.mode == "opta" else r["n_centres"])
-        kernels = [("k_centres", ph[0], r["n_centres"]), ("k_window", ph[1], window),
-                   ("k_members", ph[2], r["n_survivors"])]
-    name, kms, locs = max(kernels, key=lambda k: k[1])
-    achieved = 2.0 * mn * locs / (kms / 1e3) / 1e12 if kms > 0 else 0.0
-    roofline = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_DOT4_TOPS, 1),
-                "unit": "TOP/s", "frac": round(achieved / PEAK_DOT4_TOPS, 4), "traffic": measured_traffic(name),
-                "kernel_ms": round(float(kms), 4), "algorithmic_ops": 2 * mn * locs}
+        G = r["n_centres"]
+        matched = r["n_computed"] - (0 if args.mode == "opta" else G)
+        kernels = [("k_centres_mfma", ph[0], "mfma", PEAK_MFMA_I8_TOPS, "TOP/s", 2.0 * mn * G),
+                   ("k_members", ph[2], "hbm", PEAK_HBM_GBS, "GB/s", 20.0 * G + (mn + 8.0) * matched)]
+    name, kms, bound, peak, unit, work = max(kernels, key=lambda k: k[1])
+    scale = 1e12 if unit == "TOP/s" else 1e9
+    achieved = work / (kms / 1e3) / scale if kms > 0 else 0.0
+    roofline = {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 1),
+                "unit": unit, "frac": round(achieved / peak, 4), "traffic": measured_traffic(name),
+                "kernel_ms": round(float(kms), 4),
+                ("algorithmic_ops" if unit == "TOP/s" else "algorithmic_bytes"): work,
+                "other_kernels_ms": {k[0]: round(float(k[1]), 4) for k in kernels if k[0] != name}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -232,8 +244,6 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# Dense int8 MFMA peak of MI355X (5.0 POP/s).
-PEAK_MFMA_I8_TOPS = 5000.0
 
 
 def bench_batch(args):

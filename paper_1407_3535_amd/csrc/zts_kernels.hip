@@ -874,60 +874,72 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 
 // Matches the template on the original image at every location within
 // `radius` of the best scan-1 centre (skipping locations scan 1 already
-// matched when it ran on the same image), then sets the scan-2 threshold to
-// the best rho among the window (and the centres, when they were on I).
+// matched when it ran on the same image), one block per location; scan 2
+// forms its threshold from these records.
+constexpr int kWinWords = 16;  // template words per thread read ahead (all of a 128 x 128 template)
+
 __global__ __launch_bounds__(256) void k_window(WinArgs a)
 {
-    extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
-    __shared__ RecPod wrec[4];
-    __shared__ unsigned long long ured[8];
     __shared__ Best bred[4];
-    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    // the query state, the template and the scan-1 records in one round trip
+    const int t = threadIdx.x;
+    // The query state (template statistics from scan 1), this thread's
+    // template words and the scan-1 records are read in one round trip; the
+    // block's window location and its image words in a second one.
     const int degenerate = a.qs->degenerate;
-    int n4 = (a.n + 3) >> 2;
-    int64_t st, sq;
-    load_template(a.tpl, a.ts, a.m, a.n, n4, 0, a.m, smem, red, &st, &sq);
-    const int64_t mn = (int64_t)a.m * a.n;
-    const int64_t dt = mn * sq - st * st;
-    const int64_t c0 = reduce_best(a.recs, 0, a.rec_off, bred).l;  // best scan-1 centre
+    const int64_t st = a.qs->st, dt = a.qs->dt;
+    const int n4 = (a.n + 3) >> 2, nwords = a.m * n4;
+    const bool aligned = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
+    uint32_t tw[kWinWords];
+#pragma unroll
+    for (int q = 0; q < kWinWords; q++) {
+        const int idx = t + 256 * q;
+        tw[q] = idx < nwords ? tpl_word(a.tpl, a.ts, a.n, idx / n4, idx % n4, aligned) : 0u;
+    }
+    const int64_t c0 = reduce_best(a.recs, 0, a.rec_off, bred).l;  // best scan-1 centre (has barriers)
     if (degenerate)
         return;
-    int cy0 = (int)(c0 / a.Lx), cx0 = (int)(c0 - (c0 / a.Lx) * a.Lx);
-    int W = 2 * a.radius + 1;
-    int total = W * W;
+    const int W = 2 * a.radius + 1, k = blockIdx.x;
+    const int y = (int)(c0 / a.Lx) - a.radius + k / W, x = (int)(c0 % a.Lx) - a.radius + k % W;
+    const int64_t l = (int64_t)y * a.Lx + x;
+    const bool live = y >= 0 && y < a.Ly && x >= 0 && x < a.Lx &&
+                      !(a.skip_centres && centre_of(y, x, a.Ly, a.Lx, a.h, a.w) == l);
     RecPod rec = rec_empty();
-    unsigned long long cnt = 0;
-    int waves = gridDim.x * 4;
-    for (int k = blockIdx.x * 4 + wv; k < total; k += waves) {
-        int y = cy0 - a.radius + k / W, x = cx0 - a.radius + (k - (k / W) * W);
-        if (y < 0 || y >= a.Ly || x < 0 || x >= a.Lx)
-            continue;
-        int64_t l = (int64_t)y * a.Lx + x;
-        if (a.skip_centres && centre_of(y, x, a.Ly, a.Lx, a.h, a.w) == l)
-            continue;
-        int X = wave_dot_tpl(smem, n4, a.img, a.pitch, y, x, a.m, lane);
-        if (lane == 0) {
-            int2 so = a.stat[l];
-            int64_t dr = var_num(mn, so);
-            int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
+    if (live) {  // uniform over the block
+        int2 so = make_int2(0, 0);
+        if (t == 0)
+            so = a.stat[l];
+        const uint32_t sh = (uint32_t)(x & 3);
+        const int64_t pw = a.pitch >> 2;
+        const uint32_t *row0 = (const uint32_t *)(a.img + (((int64_t)y * a.pitch + x) & ~(int64_t)3));
+        int acc = 0;
+#pragma unroll
+        for (int q = 0; q < kWinWords; q++) {
+            const int idx = t + 256 * q;
+            if (idx < nwords) {
+                const int i = idx / n4, j = idx % n4;
+                const uint32_t *pr = row0 + (int64_t)i * pw + j;  // rows carry >= 64 bytes of padding
+                acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), tw[q], acc);
+            }
+        }
+        for (int idx = t + 256 * kWinWords; idx < nwords; idx += 256) {  // tall, narrow templates
+            const int i = idx / n4, j = idx % n4;
+            const uint32_t *pr = row0 + (int64_t)i * pw + j;
+            acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), tpl_word(a.tpl, a.ts, a.n, i, j, aligned), acc);
+        }
+        const int X = block_sum_int(acc, red);
+        if (t == 0) {
+            const int64_t mn = (int64_t)a.m * a.n;
+            const int64_t dr = var_num(mn, so);
+            const int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
             rec_offer(rec, rho32(num, dt, dr), l, num, dt, dr);
-            cnt++;
+            rec.n_window = 1;
             if (a.dec)
                 a.dec[l] = 3;
         }
     }
-    if (lane == 0)
-        wrec[wv] = rec;
-    unsigned long long c = block_sum_u64(lane == 0 ? cnt : 0ull, ured);
-    if (t == 0) {
-        RecPod b = wrec[0];
-        for (int k = 1; k < 4; k++)
-            rec_merge(b, wrec[k]);
-        b.n_window = c;
-        a.recs[a.rec_off + blockIdx.x] = b;
-    }
+    if (t == 0)
+        a.recs[a.rec_off + blockIdx.x] = rec;
 }
 
 // ============================================================== scan 2: members
@@ -2431,14 +2443,12 @@ hipError_t launch_centres(ScanArgs a, hipStream_t s)
 int window_record_count(int radius)
 {
     int W = 2 * radius + 1;
-    int nb = (int)blocks_for(W * W, 4);  // one location per wave
-    return nb < 1 ? 1 : nb;
+    return W * W;  // one block per location
 }
 
 hipError_t launch_window(WinArgs a, hipStream_t s)
 {
-    size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
-    hipLaunchKernelGGL(k_window, dim3(window_record_count(a.radius)), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_window, dim3(window_record_count(a.radius)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
