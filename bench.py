@@ -263,8 +263,14 @@ def bench_batch(args):
     macs = sum(L * t.shape[0] * t.shape[1] for L, t in zip(Ls, tpls))
     S = Z.Searcher(0)
     i = S.load(img)
-    for t in {t.shape for t in tpls}:
+    shapes = sorted({t.shape for t in tpls})
+    for t in shapes:
         S.prepare(i, t[0], t[1], "full")
+    # autotuner: both batched kernels timed per size on this image; the
+    # measured crossovers route the timed batches
+    t_tune = time.perf_counter()
+    tuned = S.tune_batch(i, shapes)
+    tune_s = time.perf_counter() - t_tune
     for _ in range(max(1, args.warmup)):
         res = S.search_batch(i, tpls)
     torch.cuda.synchronize()
@@ -299,7 +305,12 @@ def bench_batch(args):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int8", "data": "synthetic",
         "config": {"workload": "4096x4096 uint8 image, 64 templates of sizes drawn from {16,32,48,64,96,128}, "
-                               "cut + N(0,6)", "templates": len(tpls), "int8_macs": macs},
+                               "cut + N(0,6)", "templates": len(tpls), "int8_macs": macs,
+                   "bucket_sizes": {f"{m}x{n}": sum(1 for t in tpls if t.shape == (m, n)) for m, n in shapes}},
+        "tuned_routes": {f"{e['m']}x{e['n']}": {"single_ms": round(e["single_ms"], 4),
+                                                "shared_ms": round(e["shared_ms"], 4),
+                                                "multi_min": e["multi_min"]} for e in tuned},
+        "tune_seconds": round(tune_s, 3),
         "vs_per_template_valu": valu_ms / ms,
         "per_template_valu_ms": valu_ms, "per_template_valu_device_ms": valu_dev,
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},

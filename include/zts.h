@@ -91,6 +91,9 @@ typedef struct {
                                   stream each), 0 = 4, at most 64 */
     int32_t max_queued;        /* serving: submitted requests not yet started beyond which
                                   zts_submit returns ZTS_E_AGAIN, 0 = 4096 */
+    const char *tune_cache;    /* file of measured batch routes (zts_tune_batch) for this GPU
+                                  model: read at creation, rewritten after each tuning; NULL =
+                                  none.  The string is copied. */
 } zts_ctx_params;
 
 /* Method parameters; zts_params_default fills the paper's values. */
@@ -234,17 +237,40 @@ ZTS_API zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tp
                              zts_result *out);
 
 /* Exhaustive search (ZTS_FULL semantics, Eq. 1 at every location) of `count`
- * host templates against one image in one call.  Templates are grouped by
- * size; each group of up to 16 runs as an implicit GEMM on int8 MFMA
- * (v_mfma_i32_16x16x64_i8, int32 accumulation): M = 16 locations of a row,
- * N = 16 templates, K = 4 image rows x 16 columns.  tpls[k] points to an
- * m[k] x n[k] template with row pitch strides[k] bytes.  out[k] receives
- * template k's answer; a template with zero variance gets
- * out[k].status = ZTS_E_DEGENERATE while the call returns ZTS_OK.  Counts:
- * every location computed.  device_ms of every entry is the device time of
- * the whole call. */
+ * host templates against one image in one fused launch on int8 MFMA
+ * (v_mfma_i32_16x16x64_i8, int32 accumulation).  Templates are grouped by
+ * size.  A group large enough shares 16-template tiles (M = 16 locations of a
+ * row, N = 16 templates, K = 4 image rows x 16 columns); a smaller one runs
+ * each template on its own (N = 16 output rows).  The route of a size comes
+ * from zts_tune_batch's measurements when the context has them, else from a
+ * built-in estimate.  tpls[k] points to an m[k] x n[k] template with row pitch
+ * strides[k] bytes.  out[k] receives template k's answer; a template with
+ * zero variance gets out[k].status = ZTS_E_DEGENERATE while the call returns
+ * ZTS_OK.  Counts: every location computed.  device_ms of every entry is the
+ * device time of the whole call. */
 ZTS_API zts_status zts_search_batch(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
                             const int32_t *n, const int64_t *strides, zts_result *out);
+
+/* Measured cost of one template size on the two batched MFMA kernels. */
+typedef struct {
+    int32_t m, n;
+    float single_ms;   /* one template on its own (0 when the size only runs on shared tiles) */
+    float shared_ms;   /* one shared 16-template tile */
+    int32_t multi_min; /* smallest group of this size that shares tiles: the least T with
+                          ceil(T / 16) * shared_ms < T * single_ms (at least 2; INT32_MAX
+                          when sharing never wins, 1 when the size only runs shared) */
+    int32_t pad;
+} zts_tune_entry;
+
+/* Autotuner of the batched search: for each size (m[k], n[k]) times a shared
+ * 16-template tile and a lone template on image `image` (templates cut from
+ * the image itself; median of three launches after a warm-up) and keeps the
+ * result in the context, where it routes later batches and served requests of
+ * that size.  The measurements are written to the context's tune_cache file
+ * when one was given.  out[k] receives size k's entry when out is not NULL.
+ * ZTS_E_SIZE when a size exceeds the image. */
+ZTS_API zts_status zts_tune_batch(zts_ctx *ctx, int32_t image, int32_t count, const int32_t *m, const int32_t *n,
+                                  zts_tune_entry *out);
 
 /* ---- serving ------------------------------------------------------------ */
 

@@ -36,7 +36,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template"
 
 EXPORTS = ["zts_params_default", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
            "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
-           "zts_search", "zts_search_device", "zts_search_batch", "zts_submit", "zts_submit_batch", "zts_poll",
+           "zts_search", "zts_search_device", "zts_search_batch", "zts_tune_batch", "zts_submit", "zts_submit_batch", "zts_poll",
            "zts_wait", "zts_cancel", "zts_pending", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
 
 
@@ -48,7 +48,12 @@ class ZtsError(RuntimeError):
 
 class CtxParams(C.Structure):
     _fields_ = [("device", C.c_int32), ("hbm_budget_bytes", C.c_uint64), ("max_inflight", C.c_int32),
-                ("max_queued", C.c_int32)]
+                ("max_queued", C.c_int32), ("tune_cache", C.c_char_p)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("single_ms", C.c_float), ("shared_ms", C.c_float),
+                ("multi_min", C.c_int32), ("pad", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -127,6 +132,7 @@ def lib():
         L.zts_search_device.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), vp,
                                         C.POINTER(Result)]
         L.zts_search_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.zts_tune_batch.argtypes = [vp, i32, i32, vp, vp, vp]
         L.zts_submit.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.zts_submit_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.zts_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
@@ -172,11 +178,25 @@ def zts_status_str(code: int) -> str:
     return lib().zts_status_str(code).decode()
 
 
-def zts_create(device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0, max_queued: int = 0):
+def zts_create(device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0, max_queued: int = 0,
+               tune_cache: str | None = None):
     h = C.c_void_p()
-    _check(lib().zts_create(C.byref(CtxParams(device, hbm_budget_bytes, max_inflight, max_queued)), C.byref(h)),
-           "zts_create")
+    cache = tune_cache.encode() if tune_cache else None
+    _check(lib().zts_create(C.byref(CtxParams(device, hbm_budget_bytes, max_inflight, max_queued, cache)),
+                            C.byref(h)), "zts_create")
     return h
+
+
+def zts_tune_batch(ctx, image: int, sizes) -> list:
+    """Times the two batched MFMA kernels for each (m, n) and keeps the routes in the context."""
+    sizes = [(int(m), int(n)) for m, n in sizes]
+    k = len(sizes)
+    ms = (C.c_int32 * k)(*[s[0] for s in sizes])
+    ns = (C.c_int32 * k)(*[s[1] for s in sizes])
+    out = (TuneEntry * k)()
+    _check(lib().zts_tune_batch(ctx, image, k, ms, ns, out), "zts_tune_batch")
+    return [{"m": e.m, "n": e.n, "single_ms": e.single_ms, "shared_ms": e.shared_ms, "multi_min": e.multi_min}
+            for e in out]
 
 
 def zts_destroy(ctx) -> None:
@@ -360,8 +380,9 @@ def zts_debug_blur(ctx, img, taps) -> np.ndarray:
 class Searcher:
     """Convenience owner of one context: load images, search templates."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0, max_queued: int = 0):
-        self.ctx = zts_create(device, hbm_budget_bytes, max_inflight, max_queued)
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0, max_queued: int = 0,
+                 tune_cache: str | None = None):
+        self.ctx = zts_create(device, hbm_budget_bytes, max_inflight, max_queued, tune_cache)
         self.shapes = {}
 
     def close(self):
@@ -410,6 +431,9 @@ class Searcher:
 
     def search_batch(self, image, tpls):
         return zts_search_batch(self.ctx, image, tpls)
+
+    def tune_batch(self, image, sizes):
+        return zts_tune_batch(self.ctx, image, sizes)
 
     def submit(self, image, tpl, mode="full_mfma", **params):
         return zts_submit(self.ctx, image, tpl, mode, zts_params_default(**params))

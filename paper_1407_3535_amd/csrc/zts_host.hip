@@ -1164,7 +1164,31 @@ void unpin_batch(BatchPlan &b)
 // Groups the items by (image, m, n) into jobs, pins their statistics, sizes
 // the slot's batch buffers and fills the job table with device addresses.
 // Device data layout of S.bdata: [job table][templates of every job][tst].
-BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items)
+// Smallest group of one size that shares 16-template tiles.  Measured
+// (zts_tune_batch): the least T >= 2 with ceil(T / 16) shared < T single.
+// Otherwise a fit of such measurements on MI355X: a shared tile costs as much
+// as 3 + 0.055 s single searches, s = sqrt(m n16) (square sizes 16..128 on a
+// 4096x4096 image).
+static int multi_min_of(const Ctx *c, int m, int n)
+{
+    auto it = c->tuned.find(std::make_pair(m, n));
+    if (it != c->tuned.end())
+        return it->second.multi_min;
+    double sz = std::sqrt((double)m * ((n + 15) / 16 * 16));
+    return std::max(2, (int)std::ceil(3.0 + 0.055 * sz));
+}
+
+static int multi_min_from(float single_ms, float shared_ms)
+{
+    if (!(single_ms > 0.0f))
+        return 1;
+    for (int T = 2; T <= 16; T++)
+        if (shared_ms < T * single_ms)
+            return T;
+    return INT32_MAX;  // a tile of 16 costs more than 16 lone templates
+}
+
+BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items, int force)
 {
     BatchPlan b;
     b.items = std::move(items);
@@ -1185,13 +1209,8 @@ BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items)
     }
     // A bucket of enough templates shares 16-wide template tiles (k_batch);
     // smaller ones run each template on its own (k_single, no empty template
-    // columns).  On MI355X a shared tile costs as much as 3 + 0.055 s single
-    // searches, s = sqrt(m n16) (measured for square sizes 16..128 on a
-    // 4096x4096 image).  BATCH_MULTI jobs come first in the table.
-    auto multi_min = [](int m, int n) {
-        double sz = std::sqrt((double)m * ((n + 15) / 16 * 16));
-        return std::max(2, (int)std::ceil(3.0 + 0.055 * sz));
-    };
+    // columns); multi_min_of gives the crossover.  BATCH_MULTI jobs come first
+    // in the table.
     auto add_job = [&](const std::vector<int> &mem, int kind) {
         const BatchItem &it = b.items[mem[0]];
         BatchJob J;
@@ -1211,7 +1230,8 @@ BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items)
     for (int pass = 0; pass < 2; pass++)
         for (auto &bk : buckets) {
             const BatchItem &it = b.items[bk[0]];
-            bool multi = (int)bk.size() >= multi_min(it.m, it.n) || !batch_single_fits(it.m, it.n);
+            bool multi = force == BATCH_MULTI || !batch_single_fits(it.m, it.n) ||
+                         (force != BATCH_SINGLE && (int)bk.size() >= multi_min_of(c, it.m, it.n));
             if (pass == 0 && multi)
                 add_job(bk, BATCH_MULTI);
             if (pass == 1 && !multi)
@@ -1502,6 +1522,8 @@ ZTS_API const char *zts_status_str(zts_status s)
     return "unknown status";
 }
 
+static void load_tune_cache(Ctx *c);
+
 ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
 {
     if (!out)
@@ -1525,6 +1547,15 @@ ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
     }
     try {
         hip_check(hipSetDevice(c.device));
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, c.device));
+        c.arch = prop.gcnArchName;
+        for (auto &ch : c.arch)
+            if (ch == ' ')
+                ch = '_';
+        if (params && params->tune_cache)
+            c.tune_cache = params->tune_cache;
+        load_tune_cache(&c);
         c.main.init();
         c.stream = c.main.stream;
         c.h_cnt.grow(64);
@@ -1733,6 +1764,123 @@ ZTS_API zts_status zts_search_batch(zts_ctx *z, int32_t image, int32_t count, co
             if (r.status == ZTS_E_DEVICE)
                 throw ZtsError{ZTS_E_DEVICE};
         std::copy(res.begin(), res.end(), out);
+    });
+}
+
+// ------------------------------------------------------------------ autotuner
+
+// tune_cache lines: "<arch> <m> <n> <single_ms> <shared_ms>".
+static void load_tune_cache(Ctx *c)
+{
+    if (c->tune_cache.empty())
+        return;
+    FILE *f = std::fopen(c->tune_cache.c_str(), "r");
+    if (!f)
+        return;
+    char arch[128];
+    int m, n;
+    float s1, s16;
+    while (std::fscanf(f, "%127s %d %d %f %f", arch, &m, &n, &s1, &s16) == 5)
+        if (c->arch == arch && m > 0 && n > 0) {
+            zts_tune_entry e;
+            std::memset(&e, 0, sizeof e);
+            e.m = m;
+            e.n = n;
+            e.single_ms = s1;
+            e.shared_ms = s16;
+            e.multi_min = multi_min_from(s1, s16);
+            c->tuned[std::make_pair(m, n)] = e;
+        }
+    std::fclose(f);
+}
+
+// Rewrites the file: other architectures' lines are kept, this one's are the
+// context's table.  Written to a temporary file and renamed.
+static void save_tune_cache(Ctx *c)
+{
+    if (c->tune_cache.empty())
+        return;
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(c->tune_cache.c_str(), "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+            char arch[128];
+            if (std::sscanf(line, "%127s", arch) == 1 && c->arch != arch)
+                keep.push_back(line);
+        }
+        std::fclose(f);
+    }
+    std::string tmp = c->tune_cache + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f)
+        return;
+    for (auto &l : keep)
+        std::fputs(l.c_str(), f);
+    for (auto &kv : c->tuned)
+        std::fprintf(f, "%s %d %d %.6g %.6g\n", c->arch.c_str(), kv.second.m, kv.second.n, kv.second.single_ms,
+                     kv.second.shared_ms);
+    bool ok = std::fclose(f) == 0;
+    if (ok)
+        std::rename(tmp.c_str(), c->tune_cache.c_str());
+}
+
+// Median device time of a batch plan's kernels over three launches after a
+// warm-up (context lock held, main slot).
+static float time_batch(Ctx *c, const std::vector<BatchItem> &items, int force)
+{
+    float ms[3];
+    for (int rep = 0; rep < 4; rep++) {
+        BatchPlan b = plan_batch(c, c->main, items, force);
+        try {
+            launch_batch_plan(b, c->main);
+            hip_check(hipStreamSynchronize(c->main.stream));
+        } catch (...) {
+            unpin_batch(b);
+            throw;
+        }
+        unpin_batch(b);
+        float t = 0.0f;
+        hip_check(hipEventElapsedTime(&t, c->main.ev0, c->main.ev1));
+        if (rep > 0)
+            ms[rep - 1] = t;
+    }
+    std::sort(ms, ms + 3);
+    return ms[1];
+}
+
+ZTS_API zts_status zts_tune_batch(zts_ctx *z, int32_t image, int32_t count, const int32_t *m, const int32_t *n,
+                                  zts_tune_entry *out)
+{
+    if (!z || !m || !n || count < 1)
+        return ZTS_E_ARG;
+    return guarded(&z->c, [&] {
+        Ctx *c = &z->c;
+        Image *im = find_image(c, image);
+        for (int k = 0; k < count; k++)
+            if (m[k] < 1 || n[k] < 1 || m[k] > im->rows || n[k] > im->cols || n[k] > 128 ||
+                (int64_t)m[k] * n[k] > 16384)
+                throw ZtsError{ZTS_E_SIZE};
+        for (int k = 0; k < count; k++) {
+            // 16 templates cut from the image at spread offsets, read in place
+            const int Ly = im->rows - m[k] + 1, Lx = im->cols - n[k] + 1;
+            std::vector<BatchItem> items;
+            for (int t = 0; t < 16; t++) {
+                int64_t y = (int64_t)t * 7919 % Ly, x = (int64_t)t * 104729 % Lx;
+                items.push_back(BatchItem{im, im->img.as<uint8_t>() + y * im->pitch + x, m[k], n[k], im->pitch, true});
+            }
+            zts_tune_entry e;
+            std::memset(&e, 0, sizeof e);
+            e.m = m[k];
+            e.n = n[k];
+            e.shared_ms = time_batch(c, items, BATCH_MULTI);
+            if (batch_single_fits(m[k], n[k]))
+                e.single_ms = time_batch(c, std::vector<BatchItem>{items[0]}, BATCH_SINGLE);
+            e.multi_min = multi_min_from(e.single_ms, e.shared_ms);
+            c->tuned[std::make_pair(m[k], n[k])] = e;
+            if (out)
+                out[k] = e;
+        }
+        save_tune_cache(c);
     });
 }
 

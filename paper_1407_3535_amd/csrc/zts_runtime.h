@@ -177,6 +177,10 @@ struct Ctx {
     int max_inflight = 4;
     int max_queued = 4096;
     std::unique_ptr<Server> srv;
+    // batch routes measured by zts_tune_batch, by (m, n); the device's
+    // architecture name keys the tune_cache file
+    std::map<std::pair<int, int>, zts_tune_entry> tuned;
+    std::string tune_cache, arch;
 };
 
 Image *find_image(Ctx *c, int id);
@@ -227,7 +231,10 @@ struct BatchPlan {
     size_t table_bytes = 0, tpl_bytes = 0, nrec = 0;
     int ntpl = 0;
 };
-BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items);
+// force: -1 routes every size group by the tuned measurements (or the
+// built-in estimate); BATCH_MULTI or BATCH_SINGLE puts every group on that
+// kernel (the autotuner's timing runs).
+BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items, int force = -1);
 void launch_batch_plan(BatchPlan &b, Slot &S);
 void finish_batch(const BatchPlan &b, Slot &S, zts_result *out);  // out[k] for items[k]
 void unpin_batch(BatchPlan &b);

@@ -34,14 +34,15 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_the_header(tmp_path):
     Z = pytest.importorskip("paper_1407_3535_amd")
     prog = tmp_path / "sz.c"
-    prog.write_text('#include <stdio.h>\n#include "%s"\nint main(void){printf("%%zu %%zu %%zu %%zu %%zu %%zu\\n",'
+    prog.write_text('#include <stdio.h>\n#include "%s"\nint main(void){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu\\n",'
                     'sizeof(zts_result), sizeof(zts_prep_info), sizeof(zts_params), sizeof(zts_ctx_params),'
-                    'sizeof(zts_egs_step), sizeof(zts_opta_step));return 0;}\n' % HEADER)
+                    'sizeof(zts_egs_step), sizeof(zts_opta_step), sizeof(zts_tune_entry));return 0;}\n' % HEADER)
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", str(prog), "-o", str(exe)])
     sizes = list(map(int, subprocess.check_output([str(exe)]).split()))
     assert sizes == [ctypes.sizeof(Z.Result), ctypes.sizeof(Z.PrepInfo), ctypes.sizeof(Z.Params),
-                     ctypes.sizeof(Z.CtxParams), ctypes.sizeof(Z.EgsStep), ctypes.sizeof(Z.OptaStep)]
+                     ctypes.sizeof(Z.CtxParams), ctypes.sizeof(Z.EgsStep), ctypes.sizeof(Z.OptaStep),
+                     ctypes.sizeof(Z.TuneEntry)]
 
 
 def test_defaults_are_the_papers():
