@@ -1011,12 +1011,12 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
 
 // Graph cache of a slot: a launch sequence is run eagerly the first time its
 // key is seen, captured the second time and replayed from then on (shapes
-// that come once are never captured).
+// that come once are never captured).  The key holds every argument of the
+// sequence, so equal keys mean identical work.
 static const int kGraphCache = 16;
 
-static hipGraphExec_t graph_for(Slot &S, const QueryLaunch &Q, bool *capture)
+static hipGraphExec_t graph_for(Slot &S, const std::string &key, bool *capture)
 {
-    std::string key((const char *)&Q, sizeof Q);
     *capture = false;
     S.graph_clock++;
     for (auto &g : S.graphs)
@@ -1039,6 +1039,36 @@ static hipGraphExec_t graph_for(Slot &S, const QueryLaunch &Q, bool *capture)
     return nullptr;
 }
 
+// Runs `enqueue` (work on st only, no fills) through the slot's graph cache.
+template <class F> static void run_cached(Slot &S, const std::string &key, hipStream_t st, F &&enqueue)
+{
+    bool capture = false;
+    hipGraphExec_t exec = graph_for(S, key, &capture);
+    if (capture) {
+        hipGraph_t g = nullptr;
+        hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue();
+        } catch (...) {
+            (void)hipStreamEndCapture(st, &g);
+            if (g)
+                (void)hipGraphDestroy(g);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(st, &g));
+        hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hip_check(e);
+        for (auto &sg : S.graphs)
+            if (sg.stamp == S.graph_clock)
+                sg.exec = exec;
+    }
+    if (exec)
+        hip_check(hipGraphLaunch(exec, st));
+    else
+        enqueue();
+}
+
 // Enqueues one query on S.stream: scan 1, the optional refinement window,
 // scan 2 with survivors, the final reduction, and the copy of the query state
 // to pinned host memory.  Repeated launch sequences run as a replayed graph.
@@ -1057,35 +1087,10 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
     const bool graphable = S.use_graphs && !timing && !q.want_dec && !q.num_map && !q.dr_map && !q.rho_map;
     S.timed = timing;
     hip_check(hipEventRecord(S.ev0, st));
-    if (graphable) {
-        bool capture = false;
-        hipGraphExec_t exec = graph_for(S, Q, &capture);
-        if (capture) {
-            hipGraph_t g = nullptr;
-            hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            try {
-                enqueue_query(Q, S, st, false);
-            } catch (...) {
-                (void)hipStreamEndCapture(st, &g);
-                if (g)
-                    (void)hipGraphDestroy(g);
-                throw;
-            }
-            hip_check(hipStreamEndCapture(st, &g));
-            hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            hip_check(e);
-            for (auto &sg : S.graphs)
-                if (sg.stamp == S.graph_clock)
-                    sg.exec = exec;
-        }
-        if (exec)
-            hip_check(hipGraphLaunch(exec, st));
-        else
-            enqueue_query(Q, S, st, false);
-    } else {
+    if (graphable)
+        run_cached(S, std::string((const char *)&Q, sizeof Q), st, [&] { enqueue_query(Q, S, st, false); });
+    else
         enqueue_query(Q, S, st, timing);
-    }
     hip_check(hipEventRecord(S.ev1, st));
     if (dec_host)
         hip_check(hipMemcpyAsync(dec_host, S.dec.ptr, (size_t)L, hipMemcpyDeviceToHost, st));
@@ -1332,7 +1337,15 @@ void launch_batch_plan(BatchPlan &b, Slot &S)
         }
     }
     hip_check(hipEventRecord(S.ev0, st));
-    hip_check(launch_batch_jobs(S.bdata.as<BatchJob>(), b.jobs.data(), (int)b.jobs.size(), st));
+    // the kernels of a repeated plan (same jobs, same buffers) replay a graph
+    std::string key((const char *)b.jobs.data(), b.jobs.size() * sizeof(BatchJob));
+    key.append((const char *)&S.bdata.ptr, sizeof S.bdata.ptr);
+    key.append("batch");
+    auto kernels = [&] { hip_check(launch_batch_jobs(S.bdata.as<BatchJob>(), b.jobs.data(), (int)b.jobs.size(), st)); };
+    if (S.use_graphs)
+        run_cached(S, key, st, kernels);
+    else
+        kernels();
     hip_check(hipEventRecord(S.ev1, st));
     uint8_t *ho = S.h_out.as<uint8_t>();
     hip_check(hipMemcpyAsync(ho, S.bres.ptr, sizeof(RecPod) * (size_t)b.ntpl, hipMemcpyDeviceToHost, st));

@@ -76,3 +76,22 @@ def test_graph_replays_match_oracle():
                 if k == 3:
                     rb = S.search_batch(i, [t, t])
                     assert (rb[0]["y"], rb[0]["x"]) == (full["y"], full["x"])
+
+
+def test_batch_graph_replays_match_oracle():
+    """A repeated batch plan (same sizes and buffers) replays its captured
+    kernels; new template contents are staged each call."""
+    gpu_or_skip()
+    img = aerial_image(180, 210, 93)
+    with Z.Searcher(0) as S:
+        i = S.load(img)
+        shapes = [(16, 16), (16, 16), (16, 16), (20, 36), (33, 17)]
+        for rep in range(4):
+            tpls = [cut_template(img, m, n, 700 + 13 * rep + k, 5.0)[0] for k, (m, n) in enumerate(shapes)]
+            print(f"batch rep {rep}", flush=True)
+            res = S.search_batch(i, tpls)
+            for t, r in zip(tpls, res):
+                o = O.full_search(img, t)
+                for key in KEYS:
+                    assert r[key] == o[key], (rep, t.shape, key)
+            S.search(i, tpls[0], "full")  # eager work between the replays
