@@ -133,6 +133,8 @@ def lib():
         L.orc_opta_search.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int,
                                       C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double, _i64p, _i64p,
                                       _i64p, _i64p, _i64p, _i64p, C.c_int, C.c_void_p, C.POINTER(Result)]
+        L.orc_window_search.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int, C.c_int,
+                                        C.c_int64, C.c_int, C.c_int, C.c_int, C.POINTER(Result)]
         _lib = L
     return _lib
 
@@ -355,4 +357,32 @@ def opta_search(I, J, tpl, h, w, radius, delta=1e-9, decision=False, nthreads=No
     out = res.as_dict()
     if decision:
         out["decision"] = dec.reshape(p - m + 1, q - n + 1)
+    return out
+
+
+def window_search(img, tpl, cy, cx, radius):
+    """Section IV-C's localisation stage: the best of the locations within Chebyshev distance `radius` of
+    (cy, cx), matched by the plain definition (C1)."""
+    img, tpl = _u8(img), _u8(tpl)
+    p, q = img.shape
+    m, n = tpl.shape
+    res = Result()
+    _check(lib().orc_window_search(img.ctypes.data, p, q, img.strides[0], tpl.ctypes.data, m, n, tpl.strides[0],
+                                   int(cy), int(cx), int(radius), C.byref(res)))
+    return res.as_dict()
+
+
+def opta_paper_search(I, J, tpl, h, w, radius, delta=1e-9, nthreads=None):
+    """The paper's own OptA search (sections IV-C, V and VI, Alg. 3): transitive elimination on the
+    conditioned image J with J's auto-correlation and the two-scan threshold, which finds J's best
+    location exactly, then the localisation window on I around it.  Not exact on I when blurring moved or
+    suppressed the peak (section V reports offsets of up to 4 pixels).  Counts: those of the search on J;
+    n_computed adds the window's matches.  blurred = J's best (y, x, rho)."""
+    te = te_search(J, tpl, h, w, delta=delta, nthreads=nthreads)
+    win = window_search(I, tpl, te["y"], te["x"], radius)
+    out = dict(win)
+    out.update(n_centres=te["n_centres"], n_eliminated=te["n_eliminated"], n_survivors=te["n_survivors"],
+               n_computed=te["n_computed"] + win["n_computed"], n_window=win["n_computed"],
+               group_h=te["group_h"], group_w=te["group_w"], best0=te["best0"], best0_y=te["best0_y"],
+               best0_x=te["best0_x"], blurred=(te["y"], te["x"], te["rho"]))
     return out

@@ -1282,3 +1282,51 @@ int orc_opta_search(const uint8_t *I, const uint8_t *J, int p, int q, int64_t st
     free(need); free(dec);
     return ORC_OK;
 }
+
+/* The localisation stage of section IV-C: the template is matched on `img`
+ * at every location within Chebyshev distance `radius` of (cy, cx), clipped
+ * to the location grid, by the plain definition (Eq. 1 through C1's exact
+ * sums); the answer is the best of them, ties to the smaller linear index.
+ * n_computed = the number of matched locations. */
+int orc_window_search(const uint8_t *img, int p, int q, int64_t is, const uint8_t *tpl, int m, int n, int64_t ts,
+                      int cy, int cx, int radius, orc_result *out)
+{
+    if (!img || !tpl || !out || radius < 0)
+        return ORC_E_ARG;
+    if (m > p || n > q || m < 1 || n < 1)
+        return ORC_E_SIZE;
+    int Ly = p - m + 1, Lx = q - n + 1;
+    if (cy < 0 || cy >= Ly || cx < 0 || cx >= Lx)
+        return ORC_E_ARG;
+    int64_t st, st2, dt;
+    int rc = template_stats(tpl, ts, m, n, &st, &st2, &dt);
+    if (rc)
+        return rc;
+    const int64_t mn = (int64_t)m * n;
+    memset(out, 0, sizeof *out);
+    best_rec b = {-1, 0.0};
+    int64_t bnum = 0, bdr = 0, cnt = 0;
+    for (int y = cy - radius; y <= cy + radius; y++)
+        for (int x = cx - radius; x <= cx + radius; x++) {
+            if (y < 0 || y >= Ly || x < 0 || x >= Lx)
+                continue;
+            int64_t s, s2;
+            block_sums(img, is, y, x, m, n, &s, &s2);
+            int64_t dr = mn * s2 - s * s;
+            int64_t num = mn * block_cross(tpl, ts, 0, 0, img, is, y, x, m, n) - st * s;
+            double r = orc_rho(num, dt, dr);
+            int64_t l = (int64_t)y * Lx + x;
+            best_rec prev = b;
+            best_update(&b, l, r);
+            if (b.l != prev.l) {
+                bnum = num;
+                bdr = dr;
+            }
+            cnt++;
+        }
+    fill_best(out, b.l, Lx, b.rho, bnum, dt, bdr);
+    out->n_locations = (int64_t)Ly * Lx;
+    out->n_computed = cnt;
+    out->group_h = out->group_w = 1;
+    return ORC_OK;
+}

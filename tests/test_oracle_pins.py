@@ -483,3 +483,43 @@ def test_opta_search_with_a_forced_blur_is_exact():
         for (h, w, r) in [(3, 3, 0), (5, 5, 2), (4, 6, 1)]:
             s = O.opta_search(I, J, tpl, h, w, r)
             assert (s["y"], s["x"], s["rho"]) == (full["y"], full["x"], full["rho"])
+
+
+def test_window_search_is_the_full_map_restricted_to_the_window():
+    """Section IV-C's localisation stage against the full map: every window location's rho is the map's,
+    the best is the window slice's argmax with ties to the smallest index, clipped at the grid edges."""
+    img = aerial_image(50, 61, 17, beta=2.4)
+    tpl, _ = cut_template(img, 9, 11, 4, 6.0)
+    f = O.full_search(img, tpl, maps=True)
+    R = f["rho_map"]
+    Ly, Lx = R.shape
+    for cy, cx, r in [(20, 20, 2), (0, 0, 3), (Ly - 1, Lx - 1, 4), (f["y"], f["x"], 0), (10, Lx - 2, 8)]:
+        w = O.window_search(img, tpl, cy, cx, r)
+        y0, y1, x0, x1 = max(0, cy - r), min(Ly, cy + r + 1), max(0, cx - r), min(Lx, cx + r + 1)
+        sl = R[y0:y1, x0:x1]
+        k = int(np.argmax(sl == sl.max()))  # first maximum in row-major order = smallest index
+        assert (w["y"], w["x"]) == (y0 + k // sl.shape[1], x0 + k % sl.shape[1])
+        assert w["rho"] == R[w["y"], w["x"]] and w["num"] == f["num_map"][w["y"], w["x"]]
+        assert w["n_computed"] == sl.size
+
+
+def test_paper_opta_search_pins():
+    """The paper's OptA search: J's best location is J's exact argmax (the search on J is transitive
+    elimination, exact for J); the answer is the localisation window's best on I around it; with J = I
+    (nothing blurred) it is the exact full-search answer."""
+    I = aerial_image(70, 80, 23, beta=2.2)
+    m, n = 12, 10
+    taps, _ = O.gauss_taps(1.5)
+    J, _, _ = O.revert(I, O.blur(I, taps), m, n, O.lambda_(0.8, 0.95))
+    for k in range(4):
+        tpl, _ = cut_template(I, m, n, 1300 + k, 7.0)
+        full = O.full_search(I, tpl)
+        same = O.opta_paper_search(I, I, tpl, 3, 3, 2)
+        assert (same["y"], same["x"], same["rho"]) == (full["y"], full["x"], full["rho"])
+        fj = O.full_search(J, tpl)
+        s = O.opta_paper_search(I, J, tpl, 3, 3, 2)
+        assert s["blurred"] == (fj["y"], fj["x"], fj["rho"])
+        w = O.window_search(I, tpl, fj["y"], fj["x"], 2)
+        assert (s["y"], s["x"], s["rho"], s["num"]) == (w["y"], w["x"], w["rho"], w["num"])
+        te = O.te_search(J, tpl, 3, 3)
+        assert s["n_eliminated"] == te["n_eliminated"] and s["n_computed"] == te["n_computed"] + w["n_computed"]
