@@ -155,6 +155,7 @@ def main():
         for name, mode, ref, kw in [("full", "full", 0, {}), ("full_mfma", "full_mfma", 0, {}),
                                     ("egs", "egs", 0, {}), ("egs_refine2", "egs", 2, {}),
                                     ("opta", "opta", 0, {}), ("opta_refine2", "opta", 2, {}),
+                                    ("opta_paper", "opta_paper", 0, {}),
                                     ("egs_rho_th0.95_refine2", "egs", 2, {"rho_th": 0.95})]:
             rr, mms, ll, pp = run(mode, ref, 20, 3, **kw)
             modes[name] = {"ms_per_query": round(mms, 4), "locations_per_s": L / (mms / 1e3),
@@ -163,6 +164,37 @@ def main():
                            "n_eliminated": rr["n_eliminated"], "group": [rr["group_h"], rr["group_w"]],
                            "answer": [rr["y"], rr["x"], rr["rho"]]}
     full_ms = modes.get("full", {}).get("ms_per_query")
+
+    # The paper's own OptA search (inexact) against the exact one over more
+    # templates cut from the same image (sizes and noise of the workload):
+    # how often it returns the exact answer, how far off it is otherwise, and
+    # the per-query times of both (device templates, graph replays).
+    paper = None
+    if not args.no_modes:
+        from synth import cut_template
+        agree, offsets, t_paper, t_exact = 0, [], [], []
+        nt = 32
+        for k in range(nt):
+            t, _ = cut_template(img, m, n, 14073535 + 2100 + k, 8.0)
+            tk = torch.from_numpy(t).cuda()
+            for _ in range(2):  # the second call of a new template replays nothing new; warm both paths
+                Z.zts_search_device(S.ctx, i, tk, "opta_paper", Z.zts_params_default())
+                Z.zts_search_device(S.ctx, i, tk, "opta", Z.zts_params_default(refine_radius=args.refine))
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            gp = Z.zts_search_device(S.ctx, i, tk, "opta_paper", Z.zts_params_default())
+            b = time.perf_counter()
+            ge = Z.zts_search_device(S.ctx, i, tk, "opta", Z.zts_params_default(refine_radius=args.refine))
+            c2 = time.perf_counter()
+            t_paper.append((b - a) * 1e3)
+            t_exact.append((c2 - b) * 1e3)
+            if (gp["y"], gp["x"]) == (ge["y"], ge["x"]):
+                agree += 1
+            else:
+                offsets.append(max(abs(gp["y"] - ge["y"]), abs(gp["x"] - ge["x"])))
+        paper = {"templates": nt, "exact_answers": agree, "offsets_px_when_not": sorted(offsets),
+                 "ms_per_query_paper_p50": percentile(t_paper, 50), "ms_per_query_exact_p50": percentile(t_exact, 50),
+                 "note": "exact = OptA with the composite bound (same answer as full ZNCC)"}
 
     # Dominant kernel of the timed mode (by its HIP-event time) and its
     # algorithmic work.  Scan 1 on int8 MFMA: 2 mn ops per group centre,
@@ -237,6 +269,7 @@ def main():
                    "n_survivors": r["n_survivors"], "group": [r["group_h"], r["group_w"]]},
         "prepare": prep,
         "modes": modes,
+        "paper_opta_vs_exact": paper,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -81,8 +81,18 @@ typedef enum {
  *                 image around the best one (section IV-C) and bounds every
  *                 original location through the triangle inequality on
  *                 angles (Eq. 2 with Prop. 4.3's blur correlation added), so
- *                 the result is still exact. */
-typedef enum { ZTS_FULL = 0, ZTS_FULL_MFMA = 1, ZTS_TE_FIXED = 2, ZTS_EGS = 3, ZTS_OPTA = 4 } zts_mode;
+ *                 the result is still exact.
+ *   ZTS_OPTA_PAPER the paper's own OptA search (sections IV-C, V, VI): the
+ *                 same conditioned image and tables as ZTS_OPTA; transitive
+ *                 elimination on the conditioned image finds its best location,
+ *                 then the template is matched on the original image within
+ *                 the cumulative blur radius (capped at 8, or refine_radius
+ *                 when larger) of it.  Not exact: the answer is the
+ *                 window's best.  n_centres, n_eliminated and n_survivors
+ *                 are those of the search on the conditioned image;
+ *                 n_computed adds the window's matches. */
+typedef enum { ZTS_FULL = 0, ZTS_FULL_MFMA = 1, ZTS_TE_FIXED = 2, ZTS_EGS = 3, ZTS_OPTA = 4,
+               ZTS_OPTA_PAPER = 5 } zts_mode;
 
 typedef struct {
     int32_t device;            /* HIP device ordinal */

@@ -27,8 +27,9 @@ except Exception:  # pragma: no cover
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzts.so")
 
-ZTS_FULL, ZTS_FULL_MFMA, ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA = 0, 1, 2, 3, 4
-MODES = {"full": ZTS_FULL, "full_mfma": ZTS_FULL_MFMA, "te_fixed": ZTS_TE_FIXED, "egs": ZTS_EGS, "opta": ZTS_OPTA}
+ZTS_FULL, ZTS_FULL_MFMA, ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA, ZTS_OPTA_PAPER = 0, 1, 2, 3, 4, 5
+MODES = {"full": ZTS_FULL, "full_mfma": ZTS_FULL_MFMA, "te_fixed": ZTS_TE_FIXED, "egs": ZTS_EGS, "opta": ZTS_OPTA,
+         "opta_paper": ZTS_OPTA_PAPER}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template", -4: "unknown image",
           -5: "HBM budget exhausted", -6: "not ready", -7: "busy", -8: "timed out", -9: "cancelled",

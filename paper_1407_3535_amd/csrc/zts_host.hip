@@ -505,6 +505,13 @@ void build_tables(Ctx *c, Prepared &P, const Searched &S, int Ly, int Lx)
     g.opta = P.mode == ZTS_OPTA;
     g.gsum = P.gsum.as<GroupSum>();
     hip_check(launch_gsum(g, c->stream));
+    if (P.mode == ZTS_OPTA) {  // the paper's search bounds with the conditioned image's angles only
+        dalloc(c, P.gsum_b, sizeof(GroupSum) * (size_t)P.Gy * P.Gx);
+        g.theta_c = nullptr;
+        g.opta = 0;
+        g.gsum = P.gsum_b.as<GroupSum>();
+        hip_check(launch_gsum(g, c->stream));
+    }
 }
 
 // Blur correlation of every block of J against the same block of I.
@@ -770,7 +777,7 @@ namespace {
 
 int query_radius(const QueryPlan &q)
 {
-    if (q.mode == ZTS_OPTA)
+    if (q.mode == ZTS_OPTA || q.mode == ZTS_OPTA_PAPER)
         return std::max(q.P->radius, std::max(q.pr.refine_radius, 0));
     return q.pr.refine_radius > 0 ? q.pr.refine_radius : -1;
 }
@@ -802,7 +809,9 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
     q.st->pins++;
     try {
         if (mode != ZTS_FULL) {
-            q.P = prepare(c, im, m, n, mode, pr);
+            if (want_dec && mode == ZTS_OPTA_PAPER)  // no decision map for the paper's search
+                throw ZtsError{ZTS_E_ARG};
+            q.P = prepare(c, im, m, n, mode == ZTS_OPTA_PAPER ? ZTS_OPTA : mode, pr);
             q.P->pins++;
             q.P->last_use = ++c->clock;
         }
@@ -846,6 +855,8 @@ void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride)
 struct QueryLaunch {
     int32_t full;
     int32_t radius, n1, n2, n3, opta;
+    int32_t paper;  // ZTS_OPTA_PAPER: scans on J, then the window on I after scan 2
+    int32_t red_lo, red_hi, count_lo;  // final reduction: best over [lo, hi), counts over [count_lo, hi)
     FullArgs fa;
     ScanArgs sa;
     WinArgs wa;
@@ -891,17 +902,28 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
         a.rho_map = q.rho_map;
         a.dec = d_dec;
         Q.n3 = full_record_count(Ly, Lx);
+        Q.red_lo = Q.count_lo = 0;
+        Q.red_hi = Q.n3;
         return;
     }
+    const bool paper = q.mode == ZTS_OPTA_PAPER;
     const bool opta = q.mode == ZTS_OPTA;
+    const bool onJ = opta || paper;  // the scans run on the conditioned image
     const int radius = query_radius(q);
     Q.opta = opta;
+    Q.paper = paper;
     Q.radius = radius;
     Q.n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
     Q.n2 = radius >= 0 ? window_record_count(radius) : 0;
     Q.n3 = members_record_count(P->Gy, P->Gx);
-    const uint8_t *spx = opta ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
-    const int2 *sstat = opta ? P->Jstat.as<int2>() : statI;
+    // records: [0, n1) scan 1, then the window and scan 2 (ZTS_OPTA_PAPER:
+    // scan 2, then the window on I, whose best is the answer)
+    const int win_off = paper ? Q.n1 + Q.n3 : Q.n1, mem_off = paper ? Q.n1 : Q.n1 + Q.n2;
+    Q.red_lo = paper ? win_off : (opta ? Q.n1 : 0);
+    Q.red_hi = Q.n1 + Q.n2 + Q.n3;
+    Q.count_lo = paper ? Q.n1 : Q.red_lo;
+    const uint8_t *spx = onJ ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
+    const int2 *sstat = onJ ? P->Jstat.as<int2>() : statI;
     ScanArgs &s = Q.sa;
     s.img = spx;
     s.pitch = im->pitch;
@@ -920,7 +942,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     s.g_theta = S.gtheta.as<float>();
     s.recs = recs;
     s.qs = qs;
-    s.dec = opta ? nullptr : d_dec;
+    s.dec = onJ ? nullptr : d_dec;
     s.delta = pr.margin;
     if (radius >= 0) {
         WinArgs &wa = Q.wa;
@@ -936,18 +958,18 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
         wa.h = P->h;
         wa.w = P->w;
         wa.radius = radius;
-        wa.skip_centres = !opta;
-        wa.include_best0 = !opta;
+        wa.skip_centres = !onJ;
+        wa.include_best0 = !onJ;
         wa.recs = recs;
-        wa.rec_off = Q.n1;
+        wa.rec_off = win_off;  // its centre: the best of the records before it
         wa.qs = qs;
         wa.dec = d_dec;
         wa.delta = pr.margin;
     }
     MemArgs &ma = Q.ma;
-    ma.I = im->img.as<uint8_t>();
+    ma.I = paper ? P->J.as<uint8_t>() : im->img.as<uint8_t>();  // where survivors are matched
     ma.pI = im->pitch;
-    ma.statI = statI;
+    ma.statI = paper ? sstat : statI;
     ma.statS = sstat;
     ma.tpl = tpl;
     ma.ts = ts;
@@ -961,20 +983,20 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.Gx = P->Gx;
     ma.g_num = S.gnum.as<int64_t>();
     ma.g_theta = S.gtheta.as<float>();
-    ma.gsum = P->gsum.as<GroupSum>();
+    ma.gsum = paper ? P->gsum_b.as<GroupSum>() : P->gsum.as<GroupSum>();
     ma.theta_b = P->theta_b.as<float>();
     ma.x_b = P->x_b.as<int32_t>();
     ma.theta_c = opta ? P->theta_cg.as<float>() : nullptr;
     ma.x_c = opta ? P->x_cg.as<int32_t>() : nullptr;
     ma.opta = opta;
-    ma.radius = radius;
+    ma.radius = paper ? -1 : radius;  // the paper's search has no window before scan 2
     ma.recs = recs;
-    ma.rec_off = Q.n1 + Q.n2;
+    ma.rec_off = mem_off;
     ma.final_from = opta ? Q.n1 : 0;
     ma.qs = qs;
-    ma.dec = d_dec;
+    ma.dec = paper ? nullptr : d_dec;
     ma.n_best0 = Q.n1;
-    ma.n_win = Q.n2;
+    ma.n_win = paper ? 0 : Q.n2;
     ma.include_best0 = !opta;
     ma.delta = pr.margin;
 }
@@ -993,17 +1015,19 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
     if (Q.full) {
         hip_check(launch_full(Q.fa, st));
         mark(S.evp[0]);
-        hip_check(launch_reduce(Q.recs, 0, Q.n3, Q.qs, st));
+        hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, st));
         mark(S.evp[1]);
     } else {
         hip_check(launch_centres(Q.sa, st));
         mark(S.evp[0]);
-        if (Q.radius >= 0)
+        if (Q.radius >= 0 && !Q.paper)
             hip_check(launch_window(Q.wa, st));
         mark(S.evp[1]);
         hip_check(launch_members(Q.ma, st));
+        if (Q.paper)  // localisation on I around the conditioned image's best
+            hip_check(launch_window(Q.wa, st));
         mark(S.evp[2]);
-        hip_check(launch_reduce(Q.recs, Q.opta ? Q.n1 : 0, Q.n1 + Q.n2 + Q.n3, Q.qs, st));
+        hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, st));
         mark(S.evp[3]);
     }
     hip_check(hipMemcpyAsync(Q.h_qs, Q.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
@@ -1134,7 +1158,9 @@ zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out)
         r.best0 = h.best;
         r.best0_y = (int32_t)(h.best0_l / Lx);
         r.best0_x = (int32_t)(h.best0_l % Lx);
-        if (r.n_computed + r.n_eliminated != L)
+        // ZTS_OPTA_PAPER: the window's locations on I were also counted on J
+        const int64_t expect = L + (q.mode == ZTS_OPTA_PAPER ? (int64_t)h.n_window : 0);
+        if (r.n_computed + r.n_eliminated != expect)
             return ZTS_E_DEVICE;
     }
     float ms = 0.0f;
@@ -1496,7 +1522,8 @@ zts_status load_common(Ctx *c, const void *src, int rows, int cols, int64_t stri
 
 bool valid_mode(zts_mode mode)
 {
-    return mode == ZTS_FULL || mode == ZTS_FULL_MFMA || mode == ZTS_TE_FIXED || mode == ZTS_EGS || mode == ZTS_OPTA;
+    return mode == ZTS_FULL || mode == ZTS_FULL_MFMA || mode == ZTS_TE_FIXED || mode == ZTS_EGS || mode == ZTS_OPTA ||
+           mode == ZTS_OPTA_PAPER;
 }
 
 }  // namespace
@@ -1658,7 +1685,7 @@ ZTS_API zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, 
             hip_check(hipStreamSynchronize(c->stream));
             return;
         }
-        prepare(c, im, m, n, mode, pr);
+        prepare(c, im, m, n, mode == ZTS_OPTA_PAPER ? ZTS_OPTA : mode, pr);  // the same tables
     });
 }
 
@@ -1669,7 +1696,7 @@ ZTS_API zts_status zts_prep_query(zts_ctx *z, int32_t image, int32_t m, int32_t 
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Image *im = find_image(&z->c, image);
-        auto it = im->prep.find(std::make_tuple(m, n, (int)mode));
+        auto it = im->prep.find(std::make_tuple(m, n, (int)(mode == ZTS_OPTA_PAPER ? ZTS_OPTA : mode)));
         if (it == im->prep.end())
             throw ZtsError{ZTS_E_NOTPREPARED};
         *out = it->second->info;

@@ -2199,17 +2199,26 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 // when it counts) into the answer, after the kernels that wrote them have
 // finished: the kernel boundary makes the records visible on every XCD
 // without a device-scope fence in each writing block.
-__global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi, QState *qs)
+__global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi, int count_lo,
+                                                 QState *qs)
 {
     __shared__ RecPod red[16];
     const int degenerate = qs->degenerate;
-    // up to four records per thread are loaded before they are merged
+    // Best over [lo, hi), counts over [count_lo, hi); up to four records per
+    // thread are loaded before they are merged.
     RecPod r = rec_empty();
-    for (int k0 = lo + threadIdx.x; k0 < hi; k0 += 4 * blockDim.x) {
+    const int start = min(lo, count_lo);
+    for (int k0 = start + threadIdx.x; k0 < hi; k0 += 4 * blockDim.x) {
         RecPod b[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++)
-            b[j] = k0 + j * (int)blockDim.x < hi ? recs[k0 + j * blockDim.x] : rec_empty();
+        for (int j = 0; j < 4; j++) {
+            const int k = k0 + j * (int)blockDim.x;
+            b[j] = k < hi ? recs[k] : rec_empty();
+            if (k < lo)
+                b[j].valid = 0;
+            if (k < count_lo)
+                b[j].n_elim = b[j].n_surv = b[j].n_window = 0;
+        }
 #pragma unroll
         for (int j = 0; j < 4; j++)
             rec_merge(r, b[j]);
@@ -2249,9 +2258,9 @@ hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, i
 
 static constexpr int kFullR = 8;
 
-hipError_t launch_reduce(const RecPod *recs, int lo, int hi, QState *qs, hipStream_t s)
+hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, recs, lo, hi, qs);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, recs, lo, hi, count_lo, qs);
     return hipGetLastError();
 }
 

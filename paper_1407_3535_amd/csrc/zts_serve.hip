@@ -194,7 +194,8 @@ std::unique_ptr<Request> make_request(Ctx *c, int image, const uint8_t *tpl, int
 
 bool serve_mode(zts_mode mode)
 {
-    return mode == ZTS_FULL || mode == ZTS_FULL_MFMA || mode == ZTS_TE_FIXED || mode == ZTS_EGS || mode == ZTS_OPTA;
+    return mode == ZTS_FULL || mode == ZTS_FULL_MFMA || mode == ZTS_TE_FIXED || mode == ZTS_EGS || mode == ZTS_OPTA ||
+           mode == ZTS_OPTA_PAPER;
 }
 
 template <class F> zts_status locked(zts_ctx *z, F &&f)

@@ -390,3 +390,29 @@ def test_batch_mfma_flat_regions(S):
             o = O.full_search(img, t)
             same_answer(res[k], o, f"flat-region template {k}")
         S.unload(i)
+
+
+@pytest.mark.parametrize("seed,blur_kind", [(0, 1), (1, 1), (2, 0)])
+def test_opta_paper_parity(S, seed, blur_kind):
+    """The paper's own OptA search against the oracle's: the same answer (the localisation window's best
+    on I around the conditioned image's best) and the same counts; for templates whose peak survives the
+    blur it is the exact answer."""
+    img = aerial_image(140, 150, 500 + seed, beta=2.8 if seed else 2.2)
+    m = n = 12
+    i = S.load(img)
+    S.prepare(i, m, n, "opta_paper", blur_kind=blur_kind, max_iters=4)
+    oo = O.opta(img, m, n, blur_kind=blur_kind, max_iters=4)
+    exact = 0
+    for k in range(4):
+        tpl, _ = cut_template(img, m, n, 70 + k, 8.0, affine=True)
+        for extra in (0, 3):
+            radius = max(oo["radius"], extra)
+            g = S.search(i, tpl, "opta_paper", blur_kind=blur_kind, max_iters=4, refine_radius=extra)
+            o = O.opta_paper_search(img, oo["image"], tpl, oo["h"], oo["w"], radius)
+            same_answer(g, o, f"paper opta seed {seed} tpl {k} r {radius}")
+            for key in ("n_locations", "n_centres", "n_eliminated", "n_survivors", "n_computed"):
+                assert g[key] == o[key], (key, g[key], o[key])
+            full = O.full_search(img, tpl)
+            exact += (g["y"], g["x"]) == (full["y"], full["x"])
+    assert exact >= 4
+    S.unload(i)
