@@ -335,7 +335,7 @@ void alloc_image(Ctx *c, DBuf &b, int rows, int64_t pitch)
 
 void build_sat(Ctx *c, const uint8_t *img, int64_t pitch, int rows, int cols, DBuf &sat)
 {
-    dalloc(c, sat, sizeof(uint2) * (size_t)(rows + 1) * (cols + 1));
+    dalloc(c, sat, sizeof(uint2) * sat_elems(rows, cols));
     hip_check(launch_sat(img, pitch, rows, cols, sat.as<uint2>(), c->stream));
 }
 
@@ -544,7 +544,8 @@ void blurcorr(Ctx *c, const uint8_t *J, const int2 *statJ, const uint8_t *I, con
         zero_counter(c);
         a.counter = c->counter.as<unsigned long long>();
     }
-    hip_check(launch_blurcorr(a, c->stream));
+    dalloc(c, c->psat, sizeof(uint32_t) * sat_elems(Ly + m - 1, Lx + n - 1));
+    hip_check(launch_blurcorr(a, c->psat.as<uint32_t>(), c->stream));
 }
 
 // One OptA candidate image with its tables.
@@ -1624,6 +1625,7 @@ ZTS_API void zts_destroy(zts_ctx *z)
         c.tmp32.reset();
         c.viol.reset();
         c.colmask.reset();
+        c.psat.reset();
         c.h_cnt.reset();
         c.main.destroy();
         release_free_blocks(&c);

@@ -139,6 +139,8 @@ struct BcArgs {
     float *theta_c;
     int32_t *x_c;
     int64_t *num_out, *dj_out, *di_out;
+    const uint32_t *psat;  // running sums of J' I' ((p+1) x (q+1)), set by launch_blurcorr
+    int q;
 };
 
 // One bucket of a batched launch: the templates of one size searched in one
@@ -175,6 +177,9 @@ size_t batch_job_records(const BatchJob &j);
 // table lists the BATCH_MULTI jobs first, then the BATCH_SINGLE ones.
 hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s);
 
+// Running-sum tables are allocated with sat_elems(p, q) elements: the
+// (p+1) x (q+1) table followed by the column pass's per-chunk totals.
+size_t sat_elems(int p, int q);
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);
 hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s);
 
@@ -199,7 +204,8 @@ hipError_t launch_autocorr(AcArgs a, hipStream_t s);
 hipError_t launch_gsum(GsumArgs a, hipStream_t s);
 hipError_t launch_blur(const uint8_t *src, uint8_t *dst, int64_t pitch, int p, int q, const Taps &tp,
                        uint32_t *tmp, hipStream_t s);
-hipError_t launch_blurcorr(BcArgs a, hipStream_t s);
+// psat: scratch of sat_elems(p, q) uint32 for the running sums of J' I'.
+hipError_t launch_blurcorr(BcArgs a, uint32_t *psat, hipStream_t s);
 hipError_t launch_revert(const uint8_t *viol, uint8_t *colmask, int p, int q, int Ly, int Lx, int m, int n,
                          const uint8_t *I, uint8_t *J, int64_t pitch, unsigned long long *counter, hipStream_t s);
 

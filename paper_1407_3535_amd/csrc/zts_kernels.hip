@@ -332,37 +332,96 @@ __global__ __launch_bounds__(256) void k_sat_rows(const uint8_t *__restrict__ im
     }
 }
 
-// Column pass: 64 columns by 16 row chunks per block.
-__global__ __launch_bounds__(1024) void k_sat_cols(uint2 *__restrict__ sat, int p, int q)
+// Row pass of the running sums of the product image J' I' (both shifted to
+// int8; products up to 2^14): row y + 1 of `sat` holds the prefix along x,
+// modulo 2^32.  A box sum of the finished table is exact when the true sum
+// fits in int32, which |sum| <= m n 2^14 <= 2^28 guarantees.
+__global__ __launch_bounds__(256) void k_prod_rows(const uint8_t *__restrict__ J, const uint8_t *__restrict__ I,
+                                                   int64_t pitch, int p, int q, uint32_t *__restrict__ sat)
 {
-    __shared__ uint2 tot[16][64];
-    int tx = threadIdx.x, k = threadIdx.y;
-    int c = blockIdx.x * 64 + tx;
-    int per = (p + 15) / 16;
-    int r0 = 1 + k * per, r1 = min(p + 1, r0 + per);
-    int64_t W = q + 1;
-    uint32_t a = 0, b = 0;
-    if (c <= q)
-        for (int r = r0; r < r1; r++) {
-            uint2 v = sat[(int64_t)r * W + c];
-            a += v.x;
-            b += v.y;
-        }
-    tot[k][tx] = make_uint2(a, b);
-    __syncthreads();
-    uint32_t ea = 0, eb = 0;
-    for (int kk = 0; kk < k; kk++) {
-        ea += tot[kk][tx].x;
-        eb += tot[kk][tx].y;
+    __shared__ uint32_t wa[4];
+    int y = blockIdx.x;
+    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint8_t *rj = J + (int64_t)y * pitch, *ri = I + (int64_t)y * pitch;
+    uint32_t *out = sat + (int64_t)(y + 1) * (q + 1);
+    if (t == 0)
+        out[0] = 0u;
+    uint32_t ca = 0;
+    for (int base = 0; base < q; base += 256) {
+        int x = base + t;
+        int v = x < q ? ((int)rj[x] - 128) * ((int)ri[x] - 128) : 0;
+        uint32_t a = wave_incl_scan((uint32_t)v, lane);
+        if (lane == 63)
+            wa[wv] = a;
+        __syncthreads();
+        uint32_t pa = ca;
+        for (int k = 0; k < wv; k++)
+            pa += wa[k];
+        if (x < q)
+            out[x + 1] = pa + a;
+        for (int k = 0; k < 4; k++)
+            ca += wa[k];
+        __syncthreads();
     }
+}
+
+// Column pass of a running-sum table (rows 1..p, row 0 is zero), in two
+// kernels over blocks of 64 columns x 64 rows so that the grid fills the
+// chip: the first writes each block's column totals, the second adds the
+// totals of the chunks above and scans its own rows.  A thread owns one
+// column and 16 consecutive rows.
+constexpr int kColChunk = 64;
+
+__device__ __forceinline__ uint2 add_el(uint2 a, uint2 b) { return make_uint2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ uint32_t add_el(uint32_t a, uint32_t b) { return a + b; }
+template <class T> __device__ __forceinline__ T zero_el();
+template <> __device__ __forceinline__ uint2 zero_el<uint2>() { return make_uint2(0u, 0u); }
+template <> __device__ __forceinline__ uint32_t zero_el<uint32_t>() { return 0u; }
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cols_total(const T *__restrict__ sat, int p, int q, T *__restrict__ tot)
+{
+    __shared__ T part[4][64];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int c = blockIdx.x * 64 + tx, k = blockIdx.y;
+    const int64_t W = q + 1;
+    const int r0 = 1 + k * kColChunk + ty * 16, r1 = min(p + 1, r0 + 16);
+    T acc = zero_el<T>();
     if (c <= q)
-        for (int r = r0; r < r1; r++) {
-            int64_t i = (int64_t)r * W + c;
-            uint2 v = sat[i];
-            ea += v.x;
-            eb += v.y;
-            sat[i] = make_uint2(ea, eb);
-        }
+        for (int r = r0; r < r1; r++)
+            acc = add_el(acc, sat[(int64_t)r * W + c]);
+    part[ty][tx] = acc;
+    __syncthreads();
+    if (ty == 0 && c <= q)
+        tot[(int64_t)k * W + c] = add_el(add_el(part[0][tx], part[1][tx]), add_el(part[2][tx], part[3][tx]));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cols_apply(T *__restrict__ sat, int p, int q, const T *__restrict__ tot)
+{
+    __shared__ T part[4][64];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int c = blockIdx.x * 64 + tx, k = blockIdx.y;
+    const int64_t W = q + 1;
+    const int r0 = 1 + k * kColChunk + ty * 16, r1 = min(p + 1, r0 + 16);
+    T mine = zero_el<T>();
+    if (c <= q)
+        for (int r = r0; r < r1; r++)
+            mine = add_el(mine, sat[(int64_t)r * W + c]);
+    part[ty][tx] = mine;
+    __syncthreads();
+    if (c > q)
+        return;
+    T run = zero_el<T>();
+    for (int kk = 0; kk < k; kk++)
+        run = add_el(run, tot[(int64_t)kk * W + c]);
+    for (int j = 0; j < ty; j++)
+        run = add_el(run, part[j][tx]);
+    for (int r = r0; r < r1; r++) {
+        int64_t i = (int64_t)r * W + c;
+        run = add_el(run, sat[i]);
+        sat[i] = run;
+    }
 }
 
 // Per-location box statistics for an m x n block from four table entries.
@@ -1397,24 +1456,25 @@ __global__ __launch_bounds__(256) void k_blur_v(const uint32_t *__restrict__ tmp
 // ============================================================== blur correlation and revert (Alg. 3)
 
 // One wave per location: the m x n block of J against the same block of I.
+// Blur correlation of every block of J with the same block of I (Eq. 28's
+// rho between a conditioned block and its original), one thread per
+// location: the exact cross sum comes from the running sums of J' I' (four
+// entries, modulo 2^32), the block statistics from the two images' tables.
 __global__ __launch_bounds__(256) void k_blurcorr(BcArgs a)
 {
     __shared__ unsigned long long ured[8];
-    int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t L = (int64_t)a.Ly * a.Lx;
     const int64_t mn = (int64_t)a.m * a.n;
+    const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long cnt = 0;
-    for (int k = 0; k < 16; k++) {
-        int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
-        if (o >= L)
-            break;
-        int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
-        int X = wave_dot_img(a.J, a.pitch, y, x, a.I, a.pitch, y, x, a.m, a.n, lane);
-        if (lane != 0)
-            continue;
-        int2 sj = a.statJ[o], si = a.statI[o];
-        int64_t dj = var_num(mn, sj), di = var_num(mn, si);
-        int64_t num = mn * (int64_t)X - (int64_t)sj.x * (int64_t)si.x;
+    if (o < L) {
+        const int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        const int64_t W = a.q + 1;
+        const uint32_t *s0 = a.psat + (int64_t)y * W + x, *s1 = s0 + (int64_t)a.m * W;
+        const int X = (int)(s1[a.n] - s1[0] - s0[a.n] + s0[0]);
+        const int2 sj = a.statJ[o], si = a.statI[o];
+        const int64_t dj = var_num(mn, sj), di = var_num(mn, si);
+        const int64_t num = mn * (int64_t)X - (int64_t)sj.x * (int64_t)si.x;
         if (a.mode == BC_VIOL) {
             bool v;
             if (dj == 0 || di == 0)
@@ -1429,7 +1489,7 @@ __global__ __launch_bounds__(256) void k_blurcorr(BcArgs a)
                     v = rho64(num, dj, di) < a.lambda;
             }
             a.viol[o] = v ? 1 : 0;
-            cnt += v;
+            cnt = v;
         } else if (a.mode == BC_BUILD) {
             a.theta_c[o] = theta32(num, dj, di);
             a.x_c[o] = X;
@@ -1441,7 +1501,7 @@ __global__ __launch_bounds__(256) void k_blurcorr(BcArgs a)
     }
     if (a.mode == BC_VIOL) {
         unsigned long long s = block_sum_u64(cnt, ured);
-        if (t == 0 && s)
+        if (threadIdx.x == 0 && s)
             atomicAdd(a.counter, s);
     }
 }
@@ -2239,13 +2299,26 @@ __global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+size_t sat_elems(int p, int q)
+{
+    return (size_t)(p + 1) * (q + 1) + (size_t)blocks_for(p, kColChunk) * (q + 1);
+}
+
+template <class T> static void launch_cols(T *sat, int p, int q, hipStream_t s)
+{
+    T *tot = sat + (size_t)(p + 1) * (q + 1);
+    dim3 grid(blocks_for(q + 1, 64), blocks_for(p, kColChunk)), blk(64, 4);
+    hipLaunchKernelGGL(k_cols_total<T>, grid, blk, 0, s, (const T *)sat, p, q, tot);
+    hipLaunchKernelGGL(k_cols_apply<T>, grid, blk, 0, s, sat, p, q, (const T *)tot);
+}
+
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s)
 {
     hipError_t e = hipMemsetAsync(sat, 0, sizeof(uint2) * (size_t)(q + 1), s);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_sat_rows, dim3(p), dim3(256), 0, s, img, pitch, p, q, sat);
-    hipLaunchKernelGGL(k_sat_cols, dim3(blocks_for(q + 1, 64)), dim3(64, 16), 0, s, sat, p, q);
+    launch_cols(sat, p, q, s);
     return hipGetLastError();
 }
 
@@ -2502,9 +2575,17 @@ hipError_t launch_blur(const uint8_t *src, uint8_t *dst, int64_t pitch, int p, i
     return hipGetLastError();
 }
 
-hipError_t launch_blurcorr(BcArgs a, hipStream_t s)
+hipError_t launch_blurcorr(BcArgs a, uint32_t *psat, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_blurcorr, dim3(blocks_for((int64_t)a.Ly * a.Lx, 64)), dim3(256), 0, s, a);
+    const int p = a.Ly + a.m - 1, q = a.Lx + a.n - 1;
+    hipError_t e = hipMemsetAsync(psat, 0, sizeof(uint32_t) * (size_t)(q + 1), s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_prod_rows, dim3(p), dim3(256), 0, s, a.J, a.I, a.pitch, p, q, psat);
+    launch_cols(psat, p, q, s);
+    a.psat = psat;
+    a.q = q;
+    hipLaunchKernelGGL(k_blurcorr, dim3(blocks_for((int64_t)a.Ly * a.Lx, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

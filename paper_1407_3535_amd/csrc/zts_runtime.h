@@ -171,7 +171,7 @@ struct Ctx {
     uint64_t clock = 0;           // LRU stamps
     Slot main;
     hipStream_t stream = nullptr; // main.stream: loads, preparation, synchronous searches
-    DBuf counter, tmp32, viol, colmask;  // preparation scratch
+    DBuf counter, tmp32, viol, colmask, psat;  // preparation scratch
     HostBuf h_cnt;
     int next_id = 1;
     std::map<int, std::unique_ptr<Image>> images;
