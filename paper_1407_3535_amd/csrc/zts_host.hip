@@ -339,6 +339,14 @@ void build_sat(Ctx *c, const uint8_t *img, int64_t pitch, int rows, int cols, DB
     hip_check(launch_sat(img, pitch, rows, cols, sat.as<uint2>(), c->stream));
 }
 
+// Preparation scratch for the running sums of a product image over the
+// whole image of an (Ly + m - 1) x (Lx + n - 1) search.
+uint32_t *psat_for(Ctx *c, int Ly, int Lx, int m, int n)
+{
+    dalloc(c, c->psat, sizeof(uint32_t) * sat_elems(Ly + m - 1, Lx + n - 1));
+    return c->psat.as<uint32_t>();
+}
+
 Stats *stats_entry(Ctx *c, Image *im, int m, int n, hipStream_t s)
 {
     auto key = std::make_pair(m, n);
@@ -421,7 +429,7 @@ int64_t retained_count(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, 
     a.mode = theta_c ? AC_COUNT_BLUR : AC_COUNT;
     zero_counter(c);
     a.counter = c->counter.as<unsigned long long>();
-    hip_check(launch_autocorr(a, c->stream));
+    hip_check(launch_autocorr(a, psat_for(c, Ly, Lx, m, n), c->stream));
     return (int64_t)read_counter(c);
 }
 
@@ -491,7 +499,7 @@ void build_tables(Ctx *c, Prepared &P, const Searched &S, int Ly, int Lx)
     a.mode = AC_BUILD;
     a.theta_b = P.theta_b.as<float>();
     a.x_b = P.x_b.as<int32_t>();
-    hip_check(launch_autocorr(a, c->stream));
+    hip_check(launch_autocorr(a, psat_for(c, Ly, Lx, P.m, P.n), c->stream));
     dalloc(c, P.gsum, sizeof(GroupSum) * (size_t)P.Gy * P.Gx);
     GsumArgs g;
     g.theta_b = P.theta_b.as<float>();
@@ -544,8 +552,7 @@ void blurcorr(Ctx *c, const uint8_t *J, const int2 *statJ, const uint8_t *I, con
         zero_counter(c);
         a.counter = c->counter.as<unsigned long long>();
     }
-    dalloc(c, c->psat, sizeof(uint32_t) * sat_elems(Ly + m - 1, Lx + n - 1));
-    hip_check(launch_blurcorr(a, c->psat.as<uint32_t>(), c->stream));
+    hip_check(launch_blurcorr(a, psat_for(c, Ly, Lx, m, n), c->stream));
 }
 
 // One OptA candidate image with its tables.
@@ -1992,7 +1999,7 @@ ZTS_API zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int3
         a.num_out = a1.as<int64_t>();
         a.dc_out = a2.as<int64_t>();
         a.do_out = a3.as<int64_t>();
-        hip_check(launch_autocorr(a, c->stream));
+        hip_check(launch_autocorr(a, psat_for(c, Ly, Lx, m, n), c->stream));
         hip_check(hipStreamSynchronize(c->stream));
         hip_check(hipMemcpy(num_out, a1.ptr, L * 8, hipMemcpyDeviceToHost));
         hip_check(hipMemcpy(dc_out, a2.ptr, L * 8, hipMemcpyDeviceToHost));

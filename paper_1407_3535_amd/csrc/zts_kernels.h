@@ -200,7 +200,11 @@ int members_record_count(int Gy, int Gx);
 hipError_t launch_members(MemArgs a, hipStream_t s);
 hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int w, hipStream_t s);
 
-hipError_t launch_autocorr(AcArgs a, hipStream_t s);
+// Alg. 1: direct dot products per location, or, when cheaper
+// (autocorr_by_shifts), running sums of one product image per member offset
+// (psat: scratch of sat_elems(p, q) uint32).
+bool autocorr_by_shifts(int m, int n, int h, int w);
+hipError_t launch_autocorr(AcArgs a, uint32_t *psat, hipStream_t s);
 hipError_t launch_gsum(GsumArgs a, hipStream_t s);
 hipError_t launch_blur(const uint8_t *src, uint8_t *dst, int64_t pitch, int p, int q, const Taps &tp,
                        uint32_t *tmp, hipStream_t s);

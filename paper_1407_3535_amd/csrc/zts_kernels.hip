@@ -332,24 +332,27 @@ __global__ __launch_bounds__(256) void k_sat_rows(const uint8_t *__restrict__ im
     }
 }
 
-// Row pass of the running sums of the product image J' I' (both shifted to
-// int8; products up to 2^14): row y + 1 of `sat` holds the prefix along x,
+// Row pass of the running sums of the product image J'(y, x) I'(y + dy,
+// x + dx) (both shifted to int8, products up to 2^14; 0 where (y + dy,
+// x + dx) leaves the image): row y + 1 of `sat` holds the prefix along x,
 // modulo 2^32.  A box sum of the finished table is exact when the true sum
 // fits in int32, which |sum| <= m n 2^14 <= 2^28 guarantees.
 __global__ __launch_bounds__(256) void k_prod_rows(const uint8_t *__restrict__ J, const uint8_t *__restrict__ I,
-                                                   int64_t pitch, int p, int q, uint32_t *__restrict__ sat)
+                                                   int64_t pitch, int p, int q, int dy, int dx,
+                                                   uint32_t *__restrict__ sat)
 {
     __shared__ uint32_t wa[4];
     int y = blockIdx.x;
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint8_t *rj = J + (int64_t)y * pitch, *ri = I + (int64_t)y * pitch;
+    const bool rowok = y + dy >= 0 && y + dy < p;
+    const uint8_t *rj = J + (int64_t)y * pitch, *ri = I + (int64_t)(rowok ? y + dy : y) * pitch;
     uint32_t *out = sat + (int64_t)(y + 1) * (q + 1);
     if (t == 0)
         out[0] = 0u;
     uint32_t ca = 0;
     for (int base = 0; base < q; base += 256) {
         int x = base + t;
-        int v = x < q ? ((int)rj[x] - 128) * ((int)ri[x] - 128) : 0;
+        int v = x < q && rowok && x + dx >= 0 && x + dx < q ? ((int)rj[x] - 128) * ((int)ri[x + dx] - 128) : 0;
         uint32_t a = wave_incl_scan((uint32_t)v, lane);
         if (lane == 63)
             wa[wv] = a;
@@ -1308,12 +1311,65 @@ __global__ __launch_bounds__(256) void k_regroup(const uint32_t *__restrict__ in
 // One wave per location: sum(r_c' r_o') over the m x n blocks of the
 // location and its group centre, then per mode: exact integers out (debug),
 // retained count (EGS, Eq. 15), or angle and exact sum (scan-2 tables).
+// The per-location step of Alg. 1 once X = sum r_c' r_o' is known: exact
+// integers out (debug), the angle and exact sum in the group-major tables
+// (build), or the retained count of Eq. 15 (count; with the blur angle C
+// added in the OptA form).  Returns the location's contribution to the count.
+__device__ unsigned ac_finish(const AcArgs &a, int64_t o, int64_t c, int X)
+{
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int2 sc = a.statJ[c], so = a.statJ[o];
+    const int64_t dc = var_num(mn, sc), dov = var_num(mn, so);
+    const int64_t num = mn * (int64_t)X - (int64_t)sc.x * (int64_t)so.x;
+    if (a.mode == AC_DEBUG) {
+        a.num_out[o] = num;
+        a.dc_out[o] = dc;
+        a.do_out[o] = dov;
+        return 0;
+    }
+    if (a.mode == AC_BUILD) {
+        const int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        const int gy = y / a.h, gx = x / a.w;
+        const int64_t sl = ((int64_t)gy * ((a.Lx + a.w - 1) / a.w) + gx) * (a.h * a.w) + (y - gy * a.h) * a.w +
+                           (x - gx * a.w);
+        a.theta_b[sl] = theta32(num, dc, dov);
+        a.x_b[sl] = X;
+        return 0;
+    }
+    if (a.mode == AC_COUNT) {
+        if (c == o)
+            return 0;
+        if (dc == 0 || dov == 0)
+            return 1;
+        const float r = rho32(num, dc, dov);
+        if (r < a.thr_lo)
+            return 1;
+        if (r > a.thr_hi)
+            return 0;
+        return rho64(num, dc, dov) < a.thr;
+    }
+    // AC_COUNT_BLUR: every location, angle to the original added
+    const int2 si = a.statI[o];
+    const int64_t di = var_num(mn, si);
+    if (dc == 0 || dov == 0 || di == 0)
+        return 1;
+    const float s = theta32(num, dc, dov) + a.theta_c[o];
+    if (s > a.alo_hi && s < a.ahi_lo)
+        return 1;
+    if (s < a.alo_lo || s > a.ahi_hi)
+        return 0;
+    const int64_t noo = mn * (int64_t)a.x_c[o] - (int64_t)so.x * (int64_t)si.x;
+    const double rb = rho64(num, dc, dov), sb = sin64(num, dc, dov);
+    const double rc = rho64(noo, dov, di), sc2 = sin64(noo, dov, di);
+    return (rb * rc - sb * sc2) < a.thr;
+}
+
+// Alg. 1 by direct dot products: one wave per location.
 __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
 {
     __shared__ unsigned long long ured[8];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t L = (int64_t)a.Ly * a.Lx;
-    const int64_t mn = (int64_t)a.m * a.n;
     unsigned long long cnt = 0;
     for (int k = 0; k < 16; k++) {
         int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
@@ -1322,67 +1378,52 @@ __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
         int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
         int64_t c = centre_of(y, x, a.Ly, a.Lx, a.h, a.w);
         int cy = (int)(c / a.Lx), cx = (int)(c - (c / a.Lx) * a.Lx);
-        int2 sc = a.statJ[c], so = a.statJ[o];
         int X;
         if (c == o)
-            X = sc.y;  // sum of squares of the centre block
+            X = a.statJ[c].y;  // sum of squares of the centre block
         else
             X = wave_dot_img(a.J, a.pJ, cy, cx, a.J, a.pJ, y, x, a.m, a.n, lane);
-        if (lane != 0)
-            continue;
-        int64_t dc = var_num(mn, sc), dov = var_num(mn, so);
-        int64_t num = mn * (int64_t)X - (int64_t)sc.x * (int64_t)so.x;
-        if (a.mode == AC_DEBUG) {
-            a.num_out[o] = num;
-            a.dc_out[o] = dc;
-            a.do_out[o] = dov;
-        } else if (a.mode == AC_BUILD) {
-            int gy = y / a.h, gx = x / a.w;
-            int64_t sl = ((int64_t)gy * ((a.Lx + a.w - 1) / a.w) + gx) * (a.h * a.w) + (y - gy * a.h) * a.w +
-                         (x - gx * a.w);
-            a.theta_b[sl] = theta32(num, dc, dov);
-            a.x_b[sl] = X;
-        } else if (a.mode == AC_COUNT) {
-            if (c == o)
-                continue;
-            bool ret;
-            if (dc == 0 || dov == 0)
-                ret = true;
-            else {
-                float r = rho32(num, dc, dov);
-                if (r < a.thr_lo)
-                    ret = true;
-                else if (r > a.thr_hi)
-                    ret = false;
-                else
-                    ret = rho64(num, dc, dov) < a.thr;
-            }
-            cnt += ret;
-        } else {  // AC_COUNT_BLUR: every location, angle to the original added
-            int2 si = a.statI[o];
-            int64_t di = var_num(mn, si);
-            bool ret;
-            if (dc == 0 || dov == 0 || di == 0)
-                ret = true;
-            else {
-                float s = theta32(num, dc, dov) + a.theta_c[o];
-                if (s > a.alo_hi && s < a.ahi_lo)
-                    ret = true;
-                else if (s < a.alo_lo || s > a.ahi_hi)
-                    ret = false;
-                else {
-                    int64_t noo = mn * (int64_t)a.x_c[o] - (int64_t)so.x * (int64_t)si.x;
-                    double rb = rho64(num, dc, dov), sb = sin64(num, dc, dov);
-                    double rc = rho64(noo, dov, di), sc2 = sin64(noo, dov, di);
-                    ret = (rb * rc - sb * sc2) < a.thr;
-                }
-            }
-            cnt += ret;
-        }
+        if (lane == 0)
+            cnt += ac_finish(a, o, c, X);
     }
     if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR) {
         unsigned long long s = block_sum_u64(cnt, ured);
         if (t == 0 && s)
+            atomicAdd(a.counter, s);
+    }
+}
+
+// Alg. 1 by running sums: for one offset (dy, dx) of a member from its group
+// centre, X = the box sum at the centre of the product image
+// r'(y, x) r'(y + dy, x + dx), read from its running sums (psat, row width
+// q + 1).  One thread per group; the centre itself ((0, 0)) takes its sum of
+// squares from the statistics.
+__global__ __launch_bounds__(256) void k_ac_shift(AcArgs a, int dy, int dx, const uint32_t *__restrict__ psat, int q)
+{
+    __shared__ unsigned long long ured[8];
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    const int Gx = (a.Lx + a.w - 1) / a.w, G = ((a.Ly + a.h - 1) / a.h) * Gx;
+    unsigned long long cnt = 0;
+    if (g < G) {
+        int oy, ox, hh, ww, cy, cx;
+        group_geom(g, Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
+        const int y = cy + dy, x = cx + dx;
+        if (y >= oy && y < oy + hh && x >= ox && x < ox + ww) {
+            const int64_t c = (int64_t)cy * a.Lx + cx, o = (int64_t)y * a.Lx + x;
+            int X;
+            if (dy == 0 && dx == 0) {
+                X = a.statJ[c].y;
+            } else {
+                const int64_t W = q + 1;
+                const uint32_t *s0 = psat + (int64_t)cy * W + cx, *s1 = s0 + (int64_t)a.m * W;
+                X = (int)(s1[a.n] - s1[0] - s0[a.n] + s0[0]);
+            }
+            cnt = ac_finish(a, o, c, X);
+        }
+    }
+    if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR) {
+        unsigned long long s = block_sum_u64(cnt, ured);
+        if (threadIdx.x == 0 && s)
             atomicAdd(a.counter, s);
     }
 }
@@ -2550,9 +2591,35 @@ hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int 
     return hipGetLastError();
 }
 
-hipError_t launch_autocorr(AcArgs a, hipStream_t s)
+bool autocorr_by_shifts(int m, int n, int h, int w)
 {
-    hipLaunchKernelGGL(k_autocorr, dim3(blocks_for((int64_t)a.Ly * a.Lx, 64)), dim3(256), 0, s, a);
+    // measured on MI355X (2048x2048): one offset's product running sums and
+    // gather cost about as much per pixel as 46 multiply-adds of the direct
+    // form, which spends m n per location
+    return (int64_t)(h * w - 1) * 46 < (int64_t)m * n;
+}
+
+hipError_t launch_autocorr(AcArgs a, uint32_t *psat, hipStream_t s)
+{
+    if (!autocorr_by_shifts(a.m, a.n, a.h, a.w)) {
+        hipLaunchKernelGGL(k_autocorr, dim3(blocks_for((int64_t)a.Ly * a.Lx, 64)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    const int p = a.Ly + a.m - 1, q = a.Lx + a.n - 1;
+    const int64_t G = (int64_t)((a.Ly + a.h - 1) / a.h) * ((a.Lx + a.w - 1) / a.w);
+    // every member offset of a full group (a partial group's are a subset)
+    for (int dy = -(a.h - 1) / 2; dy <= a.h - 1 - (a.h - 1) / 2; dy++)
+        for (int dx = -(a.w - 1) / 2; dx <= a.w - 1 - (a.w - 1) / 2; dx++) {
+            if (dy != 0 || dx != 0) {
+                hipError_t e = hipMemsetAsync(psat, 0, sizeof(uint32_t) * (size_t)(q + 1), s);
+                if (e != hipSuccess)
+                    return e;
+                hipLaunchKernelGGL(k_prod_rows, dim3(p), dim3(256), 0, s, a.J, a.J, a.pJ, p, q, dy, dx, psat);
+                launch_cols(psat, p, q, s);
+            }
+            hipLaunchKernelGGL(k_ac_shift, dim3(blocks_for(G, 256)), dim3(256), 0, s, a, dy, dx,
+                               (const uint32_t *)psat, q);
+        }
     return hipGetLastError();
 }
 
@@ -2581,7 +2648,7 @@ hipError_t launch_blurcorr(BcArgs a, uint32_t *psat, hipStream_t s)
     hipError_t e = hipMemsetAsync(psat, 0, sizeof(uint32_t) * (size_t)(q + 1), s);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_prod_rows, dim3(p), dim3(256), 0, s, a.J, a.I, a.pitch, p, q, psat);
+    hipLaunchKernelGGL(k_prod_rows, dim3(p), dim3(256), 0, s, a.J, a.I, a.pitch, p, q, 0, 0, psat);
     launch_cols(psat, p, q, s);
     a.psat = psat;
     a.q = q;
