@@ -145,7 +145,10 @@ typedef struct {
     int32_t group_h, group_w;
     double best0;            /* threshold used by scan 2 (an attained rho) */
     int32_t best0_y, best0_x;/* best group centre of scan 1 */
-    float device_ms;         /* device time of the search (HIP events) */
+    float device_ms;         /* device time of the search: the device clock from the start of its
+                                first kernel to the end of its last one (HIP events around the
+                                launches when params.timing = 1; batches: events around the
+                                batched kernels) */
     zts_status status;
     float phase_ms[4];       /* device time per kernel, HIP events on the library's stream:
                                 ZTS_FULL: [0] dense kernel; ZTS_FULL_MFMA: [0] the batched launch;

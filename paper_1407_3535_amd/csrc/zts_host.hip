@@ -3,6 +3,8 @@
 // synchronous entry points of zts.h.  The serving loop (submit / poll / wait)
 // is in zts_serve.hip.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -53,13 +55,13 @@ void HostBuf::reset()
     bytes = 0;
 }
 
-void HostBuf::grow(size_t n)
+void HostBuf::grow(size_t n, unsigned flags)
 {
     if (ptr && bytes >= n)
         return;
     reset();
     n = (std::max(n, (size_t)64) + 4095) & ~(size_t)4095;
-    if (hipHostMalloc(&ptr, n, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&ptr, n, flags) != hipSuccess) {
         ptr = nullptr;
         throw ZtsError{ZTS_E_NOMEM};
     }
@@ -74,7 +76,8 @@ void Slot::init()
     hip_check(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
     for (auto &e : evp)
         hip_check(hipEventCreate(&e));
-    h_qs.grow(sizeof(QState));
+    h_qs.grow(sizeof(QState), hipHostMallocCoherent);  // written by the final reduction
+    std::memset(h_qs.ptr, 0, sizeof(QState));
 }
 
 void Slot::drop_graphs()
@@ -824,7 +827,13 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
             q.P->last_use = ++c->clock;
         }
         int64_t L = (int64_t)q.Ly * q.Lx;
+        void *old_qs = S.qs.ptr;
         dalloc(c, S.qs, sizeof(QState));
+        if (S.qs.ptr != old_qs) {  // a fresh state: both sequence numbers start at 0
+            hip_check(hipMemsetAsync(S.qs.ptr, 0, sizeof(QState), S.stream));
+            S.h_qs.as<QState>()->seq = 0;
+            S.qseq = 0;
+        }
         dalloc(c, S.tpl, (size_t)m * n);
         if (want_dec)
             dalloc(c, S.dec, (size_t)L);
@@ -1009,7 +1018,8 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.delta = pr.margin;
 }
 
-// The kernels of one query and the copy of its state to pinned host memory.
+// The kernels of one query; the last one publishes the query state to the
+// slot's pinned host mirror.
 // The scan kernels initialise the query state themselves (no fill), so the
 // sequence can be captured into a graph.  With `events`, an event follows
 // each kernel (per-kernel times; never captured: event-record nodes made
@@ -1023,7 +1033,7 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
     if (Q.full) {
         hip_check(launch_full(Q.fa, st));
         mark(S.evp[0]);
-        hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, st));
+        hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, (QState *)Q.h_qs, st));
         mark(S.evp[1]);
     } else {
         hip_check(launch_centres(Q.sa, st));
@@ -1035,10 +1045,9 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
         if (Q.paper)  // localisation on I around the conditioned image's best
             hip_check(launch_window(Q.wa, st));
         mark(S.evp[2]);
-        hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, st));
+        hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, (QState *)Q.h_qs, st));
         mark(S.evp[3]);
     }
-    hip_check(hipMemcpyAsync(Q.h_qs, Q.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
 }
 
 // Graph cache of a slot: a launch sequence is run eagerly the first time its
@@ -1118,20 +1127,49 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
     const bool timing = q.pr.timing != 0;
     const bool graphable = S.use_graphs && !timing && !q.want_dec && !q.num_map && !q.dr_map && !q.rho_map;
     S.timed = timing;
-    hip_check(hipEventRecord(S.ev0, st));
+    S.qseq++;  // the sequence number this query's final reduction publishes
+    if (timing)
+        hip_check(hipEventRecord(S.ev0, st));
     if (graphable)
         run_cached(S, std::string((const char *)&Q, sizeof Q), st, [&] { enqueue_query(Q, S, st, false); });
     else
         enqueue_query(Q, S, st, timing);
-    hip_check(hipEventRecord(S.ev1, st));
+    if (timing)
+        hip_check(hipEventRecord(S.ev1, st));
     if (dec_host)
         hip_check(hipMemcpyAsync(dec_host, S.dec.ptr, (size_t)L, hipMemcpyDeviceToHost, st));
 }
 
-// Waits for the query on S.stream and assembles its result.
-zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out)
+// Waits until the slot's host mirror carries the sequence number of the last
+// launched query (the final reduction writes it after the rest of the state).
+// The stream is polled every 50 us so that a failed launch ends the wait with
+// its error.
+static void wait_published(Slot &S)
 {
-    hip_check(hipStreamSynchronize(S.stream));
+    const volatile unsigned long long *seq = &S.h_qs.as<QState>()->seq;
+    auto next = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
+    while (*seq != S.qseq) {
+        if (std::chrono::steady_clock::now() < next)
+            continue;
+        hipError_t e = hipStreamQuery(S.stream);
+        if (e == hipSuccess) {
+            if (*seq == S.qseq)
+                break;
+            throw ZtsError{ZTS_E_DEVICE};  // the stream finished without publishing
+        }
+        if (e != hipErrorNotReady)
+            hip_check(e);
+        next = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+}
+
+// Waits for the query on S.stream and assembles its result.
+zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out, double wall_khz)
+{
+    if (S.timed || q.want_dec)
+        hip_check(hipStreamSynchronize(S.stream));  // events, or the decision map's copy
+    wait_published(S);
     const QState &h = *S.h_qs.as<QState>();
     if (h.degenerate)
         return ZTS_E_DEGENERATE;
@@ -1171,8 +1209,11 @@ zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out)
         if (r.n_computed + r.n_eliminated != expect)
             return ZTS_E_DEVICE;
     }
-    float ms = 0.0f;
-    hip_check(hipEventElapsedTime(&ms, S.ev0, S.ev1));
+    // device time: HIP events when timed, else the device clock stamps of
+    // the first kernel's start and the final reduction
+    float ms = (float)((double)(h.t1 - h.t0) / wall_khz);
+    if (S.timed)
+        hip_check(hipEventElapsedTime(&ms, S.ev0, S.ev1));
     r.device_ms = ms;
     // per-kernel times, when the query was launched with its events
     auto span = [](float *out, hipEvent_t a, hipEvent_t b) { hip_check(hipEventElapsedTime(out, a, b)); };
@@ -1474,7 +1515,7 @@ void run_query_main(Ctx *c, Image *im, const uint8_t *tpl, int m, int n, int64_t
             stage_template(c->main, tpl, m, n, stride);
         }
         launch_query(q, c->main, dec);
-        st = finish_query(q, c->main, out);
+        st = finish_query(q, c->main, out, c->wall_khz);
     } catch (...) {
         unpin_query(q);
         throw;
@@ -1597,6 +1638,9 @@ ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
         hip_check(hipSetDevice(c.device));
         hipDeviceProp_t prop;
         hip_check(hipGetDeviceProperties(&prop, c.device));
+        int khz = 0;
+        hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device));
+        c.wall_khz = khz > 0 ? khz : 100000;
         c.arch = prop.gcnArchName;
         for (auto &ch : c.arch)
             if (ch == ' ')

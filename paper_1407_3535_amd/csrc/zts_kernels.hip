@@ -454,6 +454,8 @@ __global__ __launch_bounds__(256) void k_stats(const uint2 *__restrict__ sat, in
 template <int R>
 __global__ __launch_bounds__(256) void k_full(FullArgs a)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
     const int n4w = a.n4w;
@@ -570,6 +572,8 @@ __global__ __launch_bounds__(256) void k_full(FullArgs a)
 template <int R>
 __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
     __shared__ RecPod rred[256];
@@ -735,6 +739,8 @@ __device__ void load_template_rows(const uint8_t *__restrict__ tpl, int64_t ts, 
 template <int NB>  // 16-byte column blocks of the template row (n16 = 16 NB)
 __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
     __shared__ RecPod rred[kCmThreads / 64];
@@ -2300,8 +2306,37 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 // when it counts) into the answer, after the kernels that wrote them have
 // finished: the kernel boundary makes the records visible on every XCD
 // without a device-scope fence in each writing block.
+// Publishes the query state to its host mirror (pinned, coherent): every
+// word but the sequence number, a system-scope fence, then the sequence
+// number, so a host that sees the new number reads a complete state.
+__device__ void publish_state(QState *qs, QState *host)
+{
+    qs->t1 = __builtin_amdgcn_s_memrealtime();
+    const unsigned long long seq = qs->seq + 1;
+    qs->seq = seq;
+    const uint64_t *__restrict__ src = (const uint64_t *)qs;
+    uint64_t *__restrict__ dst = (uint64_t *)host;
+    constexpr int kWords = (int)(sizeof(QState) / 8), kSeqWord = (int)(offsetof(QState, seq) / 8);
+    static_assert(sizeof(QState) % 8 == 0 && offsetof(QState, seq) % 8 == 0, "8-byte words");
+    uint64_t w[kWords];
+#pragma unroll
+    for (int k = 0; k < kWords; k++)  // every load in flight before the stores
+        w[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < kWords; k++)
+        if (k != kSeqWord)
+            dst[k] = w[k];
+    __threadfence_system();
+    __hip_atomic_store(&host->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// One block folds the per-block records of the final scan (and of the window
+// when it counts) into the answer, after the kernels that wrote them have
+// finished: the kernel boundary makes the records visible on every XCD
+// without a device-scope fence in each writing block.  It then publishes the
+// query state to the host mirror.
 __global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi, int count_lo,
-                                                 QState *qs)
+                                                 QState *qs, QState *host)
 {
     __shared__ RecPod red[16];
     const int degenerate = qs->degenerate;
@@ -2325,14 +2360,15 @@ __global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs
             rec_merge(r, b[j]);
     }
     RecPod f = block_rec4(r, red);
-    if (degenerate)
-        return;
     if (threadIdx.x == 0) {
-        qs->fin = f;
-        qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
-        qs->n_elim = f.n_elim;
-        qs->n_surv = f.n_surv;
-        qs->n_window = f.n_window;
+        if (!degenerate) {
+            qs->fin = f;
+            qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
+            qs->n_elim = f.n_elim;
+            qs->n_surv = f.n_surv;
+            qs->n_window = f.n_window;
+        }
+        publish_state(qs, host);
     }
 }
 
@@ -2372,9 +2408,9 @@ hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, i
 
 static constexpr int kFullR = 8;
 
-hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, hipStream_t s)
+hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, recs, lo, hi, count_lo, qs);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, recs, lo, hi, count_lo, qs, host);
     return hipGetLastError();
 }
 

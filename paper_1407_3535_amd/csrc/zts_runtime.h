@@ -63,7 +63,7 @@ struct HostBuf {
     HostBuf &operator=(const HostBuf &) = delete;
     ~HostBuf() { reset(); }
     void reset();
-    void grow(size_t n);
+    void grow(size_t n, unsigned flags = hipHostMallocDefault);
     template <class T> T *as() const { return (T *)ptr; }
 };
 
@@ -88,6 +88,7 @@ struct Slot {
     HostBuf h_qs, h_stage, h_out;
     bool use_graphs = true;
     bool timed = false;             // the last query recorded its per-kernel events
+    unsigned long long qseq = 0;    // queries launched on this slot's state (published sequence)
     std::vector<SlotGraph> graphs;  // keyed by the launch arguments
     uint64_t graph_clock = 0;
     void init();      // throws ZTS_E_DEVICE
@@ -182,6 +183,7 @@ struct Ctx {
     // architecture name keys the tune_cache file
     std::map<std::pair<int, int>, zts_tune_entry> tuned;
     std::string tune_cache, arch;
+    double wall_khz = 100000.0;   // device realtime clock (hipDeviceAttributeWallClockRate)
 };
 
 Image *find_image(Ctx *c, int id);
@@ -212,7 +214,9 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
 // pinned staging, on the slot's stream.
 void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride);
 void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host);
-zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out);
+// Waits for the query (its state published to the slot's host mirror) and
+// assembles the result; wall_khz: the device clock rate for device_ms.
+zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out, double wall_khz);
 void unpin_query(QueryPlan &q);
 
 // Many templates, possibly of several sizes and images, in one fused launch

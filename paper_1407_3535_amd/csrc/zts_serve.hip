@@ -84,7 +84,7 @@ void execute(Ctx *c, Slot &S, std::unique_lock<std::mutex> &lk, const std::vecto
     try {
         stage_template(S, r0->tpl.data(), r0->m, r0->n, r0->n);
         launch_query(q, S, nullptr);
-        st = finish_query(q, S, &res[0]);
+        st = finish_query(q, S, &res[0], c->wall_khz);
     } catch (...) {
         lk.lock();
         unpin_query(q);

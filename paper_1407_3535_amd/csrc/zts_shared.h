@@ -38,6 +38,11 @@ struct QState {
     RecPod fin;
     float fin_r32;
     int32_t pad1;
+    // device realtime clock at the first kernel's start and the last one's end
+    unsigned long long t0, t1;
+    // completed queries of this state; the final reduction copies the state
+    // to the host mirror and writes this last
+    unsigned long long seq;
 };
 
 // Taps of one separable integer blur pass.
