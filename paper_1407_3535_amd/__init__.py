@@ -75,9 +75,19 @@ class Result(C.Structure):
                 ("latency_ms", C.c_float), ("queue_ms", C.c_float), ("batch_size", C.c_int32), ("pad1", C.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
+        d = {k: getattr(self, k) for k in Result._names}
         d["phase_ms"] = list(self.phase_ms)
         return d
+
+
+Result._names = [k for k, _ in Result._fields_ if not k.startswith("pad") and k != "phase_ms"]
+
+
+def _current_stream(device=None) -> int:
+    """Handle of torch's current HIP stream on `device` (the current device when None)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    return torch._C._cuda_getCurrentRawStream(device)
 
 
 class EgsStep(C.Structure):
@@ -215,7 +225,7 @@ def zts_image_load(ctx, img) -> int:
 def zts_image_load_device(ctx, tensor, stream=None) -> int:
     """tensor: a 2-D uint8 torch tensor on the GPU (rows may be strided)."""
     rows, cols = tensor.shape
-    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    s = stream if stream is not None else _current_stream(tensor.device.index)
     i = C.c_int32()
     _check(lib().zts_image_load_device(ctx, tensor.data_ptr(), rows, cols, tensor.stride(0), s, C.byref(i)),
            "zts_image_load_device")
@@ -270,7 +280,7 @@ def zts_search_decision(ctx, image: int, image_shape, tpl, mode, params: Params 
 
 def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None = None, stream=None) -> dict:
     p = params if params is not None else zts_params_default()
-    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    s = stream if stream is not None else _current_stream(tpl_tensor.device.index)
     r = Result()
     m, n = tpl_tensor.shape
     _check(lib().zts_search_device(ctx, image, tpl_tensor.data_ptr(), m, n, tpl_tensor.stride(0), _mode(mode),
