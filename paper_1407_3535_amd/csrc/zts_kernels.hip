@@ -1103,7 +1103,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ int s_tmp[4];
     __shared__ int s_geo[GB][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
     __shared__ int s_list[CAP];
-    __shared__ int s_nsurv, s_tpl;
+    __shared__ int s_nsurv;
     __shared__ RecPod wrec[4];
     __shared__ unsigned long long ured[8];
     __shared__ Best bred[8];
@@ -1121,12 +1121,15 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             gs2[e] = a.gsum[g0 + 2 * t + e];
         }
     const int degenerate = a.qs->degenerate;
+    const int n4 = (a.n + 3) >> 2;
+    // the template words for survivors, in the same round trip (the
+    // threshold's barriers make them visible)
+    load_template_words(a.tpl, a.ts, a.m, a.n, n4, smem);
     const Thr thr = block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, bred);
     if (degenerate)
         return;
     if (blockIdx.x == 0 && t == 0)
         store_threshold(a.qs, thr);
-    const int n4 = (a.n + 3) >> 2;
     const int64_t mn = (int64_t)a.m * a.n;
     const int64_t st = a.qs->st, dt = a.qs->dt;
     const float lo = thr.lo, hi = thr.hi;
@@ -1196,7 +1199,6 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     if (t == 0) {
         s_pref[GB] = total;
         s_nsurv = 0;
-        s_tpl = 0;
     }
     __syncthreads();
     RecPod rec = rec_empty();
@@ -1261,18 +1263,12 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         }
         __syncthreads();
         int ns = s_nsurv;
-        if (ns > 0 && !s_tpl) {
-            load_template_words(a.tpl, a.ts, a.m, a.n, n4, smem);
-            __syncthreads();
-            if (t == 0)
-                s_tpl = 1;
-        }
         for (int k = wv; k < ns; k += 4) {
             int64_t o = s_list[k];
             int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+            const int2 so = lane == 0 ? a.statI[o] : make_int2(0, 0);  // with the image words
             int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, lane);
             if (lane == 0) {
-                int2 so = a.statI[o];
                 int64_t dr = var_num(mn, so);
                 int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
                 rec_offer(rec, rho32(num, dt, dr), o, num, dt, dr);
