@@ -160,14 +160,16 @@ struct BatchJob {
     int block0, fold0, tmpl0;  // block0 counts within the kernel that runs the job
     int kind;             // BATCH_MULTI: up to 16 templates of one size per tile (N = templates);
                           // BATCH_SINGLE: one template (N = 16 output rows)
+    int rg;               // BATCH_SINGLE: 16-row groups per block (8, 4 or 2; one value per table)
     RecPod *recs;         // batch_job_records(job) records: [gz][gy*gx][16], then [gz][chunks][16]
     RecPod *out;          // [T] answers
 };
 
 enum { BATCH_MULTI = 0, BATCH_SINGLE = 1 };
 
-// Fills n16, gx, gy, gz and chunks from kind, T, m, n, Ly, Lx; false when
-// n > 128 (or, for BATCH_SINGLE, T != 1 or the template does not fit LDS).
+// Fills n16, gx, gy, gz and chunks from kind, T, m, n, Ly, Lx (and rg for
+// BATCH_SINGLE); false when n > 128 (or, for BATCH_SINGLE, T != 1, rg not
+// 8, 4 or 2, or the template does not fit LDS).
 bool batch_job_geometry(BatchJob &j);
 // Whether one m x n template fits the single-template kernel's LDS.
 bool batch_single_fits(int m, int n);

@@ -105,10 +105,12 @@ __device__ RecPod block_rec(RecPod r, RecPod *red)
 // Merges the records of a wave: a butterfly over the 64 lanes, after which
 // every lane holds the merged record (the merge is commutative and
 // associative: best by (rho, smallest index), max of r32max, sums of counts).
+// With SPAN < 64, lanes merge within aligned groups of SPAN lanes.
+template <int SPAN = 64>
 __device__ RecPod wave_rec(RecPod r)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = SPAN / 2; off > 0; off >>= 1) {
         RecPod b;
         b.rho = __shfl_xor(r.rho, off);
         b.l = (int64_t)__shfl_xor((long long)r.l, off);
@@ -702,7 +704,7 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 // (stride h), K = 4 image rows x 16 columns.  A block holds 16 centre rows x
 // 64 centre columns: one M-tile per wave, and two waves per M-tile that take
 // alternate groups of 4 image rows (their sums are added at the end).  The
-// image region its windows cover streams through LDS in chunks of 32 or 16
+// image region its windows cover streams through LDS in chunks of 64, 32 or 16
 // rows (one copy, A fragments are realigned with v_alignbyte),
 // double-buffered so that a chunk's loads are in flight while the previous
 // chunk is multiplied.  Each wave of an M-tile finishes two of its four
@@ -925,15 +927,15 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         rred[wv] = rec;
     __syncthreads();
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (t == 0) {
-        RecPod bb = rred[0];
-        for (int k = 1; k < kCmThreads / 64; k++)
-            rec_merge(bb, rred[k]);
-        a.recs[bid] = bb;
-        if (bid == 0) {  // the query state needs no fill before the scans
-            a.qs->st = st;
-            a.qs->dt = dt;
-            a.qs->degenerate = 0;
+    if (wv == 0) {  // the eight wave records merged by shuffles in lanes 0..7
+        RecPod bb = wave_rec<kCmThreads / 64>(lane < kCmThreads / 64 ? rred[lane] : rec_empty());
+        if (lane == 0) {
+            a.recs[bid] = bb;
+            if (bid == 0) {  // the query state needs no fill before the scans
+                a.qs->st = st;
+                a.qs->dt = dt;
+                a.qs->degenerate = 0;
+            }
         }
     }
 }
@@ -1000,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
             const int64_t mn = (int64_t)a.m * a.n;
             const int64_t dr = var_num(mn, so);
             const int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
-            rec_offer(rec, rho32(num, dt, dr), l, num, dt, dr);
+            rec_offer_inline(rec, rho32(num, dt, dr), l, num, dt, dr);
             rec.n_window = 1;
             if (a.dec)
                 a.dec[l] = 3;
@@ -1271,7 +1273,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             if (lane == 0) {
                 int64_t dr = var_num(mn, so);
                 int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
-                rec_offer(rec, rho32(num, dt, dr), o, num, dt, dr);
+                rec_offer_inline(rec, rho32(num, dt, dr), o, num, dt, dr);
             }
         }
         __syncthreads();
@@ -1283,13 +1285,13 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         wrec[wv] = rec;
     unsigned long long ce = block_sum_u64(n_elim, ured);
     unsigned long long cs = block_sum_u64(n_surv, ured);
-    if (t == 0) {
-        RecPod b = wrec[0];
-        for (int k = 1; k < 4; k++)
-            rec_merge(b, wrec[k]);
-        b.n_elim = ce;
-        b.n_surv = cs;
-        a.recs[a.rec_off + blockIdx.x] = b;
+    if (wv == 0) {  // the four wave records merged by shuffles in lanes 0..3
+        RecPod b = wave_rec<4>(lane < 4 ? wrec[lane] : rec_empty());
+        if (lane == 0) {
+            b.n_elim = ce;
+            b.n_surv = cs;
+            a.recs[a.rec_off + blockIdx.x] = b;
+        }
     }
 }
 
@@ -1962,9 +1964,9 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
 // The template is staged whole in LDS once; the image streams through LDS
 // in 4-row steps as in k_batch.  A wave holds RG row groups x MT M-tiles; the
 // block's four waves sit side by side: 16 RG rows x 256 columns per block.
-// Row groups that meet no template row in a step skip their MFMAs.
-constexpr int kSingleRG = 8;
-constexpr int kSingleRows = 16 * kSingleRG;
+// Row groups that meet no template row in a step skip their MFMAs.  RG is 8
+// when the image gives enough blocks to fill the chip, else 4 or 2 (more,
+// shorter blocks; each A fragment then feeds fewer row groups).
 constexpr int kSingleCap = 256;   // candidate list entries (one per thread)
 // Epilogue LDS (dwords): per wave a 16 x 64 value slice (overflow path) and a
 // statistics buffer of 64 lanes x 36 dwords (a lane's 16 int2 contiguous, the
@@ -1983,8 +1985,8 @@ __host__ __device__ inline int single_tpl_words(int m, int n16) { return (m + 1)
 template <int RG>
 __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ jobs, int njobs)
 {
-    static_assert(RG * 16 == kSingleRows, "block rows");
-    constexpr int MT = 4;
+    static_assert(RG == 2 || RG == 4 || RG == 8, "row groups per block");
+    constexpr int MT = 4, ROWS = 16 * RG;
     extern __shared__ __align__(16) uint32_t smem[];
     const BatchJob a = jobs[batch_job_of<0>(jobs, njobs, blockIdx.x)];
     const int lb = blockIdx.x - a.block0, bx = lb % a.gx, by = lb / a.gx;
@@ -1995,8 +1997,8 @@ __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ 
     const int tstr = batch_tstride(nw16);
     uint32_t *tpl_l = smem + 2 * IMGW;  // rows 0..m-1, then the zero row m
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int x0 = bx * 256, y0 = by * kSingleRows;
-    const int steps = (kSingleRows + m - 1 + 3) >> 2;
+    const int x0 = bx * 256, y0 = by * ROWS;
+    const int steps = (ROWS + m - 1 + 3) >> 2;
     const uint32_t *tplg = (const uint32_t *)a.tpl;
 
     for (int idx = t; idx < m * nw16; idx += 256) {
@@ -2138,10 +2140,13 @@ __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ 
         _Pragma("unroll") for (int r = 0; r < 16; r++)                                           \
             *(int2 *)(stb + kSingleLaneStride * (4 * r + cg) + 2 * cq) = sv[r];                  \
     }
-    // one row group's 16 accumulators into this wave's slice ([value][lane])
+    // one row group's 16 accumulators into this wave's slice ([value][lane]);
+    // a switch of constant indices, so that acc stays in registers
 #define ZTS_SLICE_CASE(r)                                                                        \
     case r:                                                                                      \
-        _Pragma("unroll") for (int q = 0; q < 16; q++) slice[q * 64 + lane] = acc[r][q >> 2][q & 3]; \
+        if constexpr ((r) < RG) {                                                                \
+            _Pragma("unroll") for (int q = 0; q < 16; q++) slice[q * 64 + lane] = acc[r][q >> 2][q & 3]; \
+        }                                                                                        \
         break;
     auto to_slice = [&](int rg) {
         switch (rg) {
@@ -2156,7 +2161,6 @@ __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ 
         }
     };
 #undef ZTS_SLICE_CASE
-    static_assert(RG == 8, "to_slice has one case per row group");
     if (t == 0)
         *ccnt = 0;
     // pass 1: block maximum (a rolled loop, so that loads of later row groups
@@ -2500,7 +2504,7 @@ static size_t centres_mfma_lds(int m, int n, int cwd, int crows)
     return ((size_t)(m + 1) * batch_tstride(n16 / 4) + (size_t)2 * crows * cwd) * 4;
 }
 
-// Staging shape of k_centres_mfma: chunk rows (32 or 16, the most that
+// Staging shape of k_centres_mfma: chunk rows (64, 32 or 16, the most that
 // fit 60 KB of LDS with the reachable width staged by 512 / rows threads
 // per row, kCmLd words each) and the row stride with the least bank cost
 // among the reachable width and up to 63 dwords more.  cwd = 0 when the
@@ -2518,7 +2522,7 @@ static CmShape centres_mfma_shape_search(int m, int n, int w)
     CmShape r = {0, cwn, 0};
     if (n16 > 128)
         return r;
-    for (int crows = 32; crows >= 16 && !r.crows; crows >>= 1)
+    for (int crows = 64; crows >= 16 && !r.crows; crows >>= 1)
         if (cwn <= kCmLd * (kCmThreads / crows) && 2 * crows * cwn >= 1024 &&
             centres_mfma_lds(m, n, cwn, crows) <= kLds)
             r.crows = crows;
@@ -2565,7 +2569,7 @@ hipError_t launch_centres(ScanArgs a, hipStream_t s)
     if (sh.cwd) {
         a.cwd = sh.cwd;
         a.cwn = sh.cwn;
-        a.crows_log2 = sh.crows == 32 ? 5 : 4;
+        a.crows_log2 = sh.crows == 64 ? 6 : sh.crows == 32 ? 5 : 4;
         size_t lds = centres_mfma_lds(a.m, a.n, sh.cwd, sh.crows);
         dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, 16)), blk(kCmThreads);
         switch ((a.n + 15) / 16) {
@@ -2720,7 +2724,9 @@ bool batch_job_geometry(BatchJob &j)
     if (j.kind == BATCH_SINGLE) {
         if (j.T != 1 || !batch_single_fits(j.m, j.n))
             return false;
-        j.gy = (int)blocks_for(j.Ly, kSingleRows);
+        if (j.rg != 2 && j.rg != 4 && j.rg != 8)
+            return false;
+        j.gy = (int)blocks_for(j.Ly, 16 * j.rg);
         j.gz = 1;
     } else {
         j.gy = (int)blocks_for(j.Ly, kBatchR);
@@ -2755,10 +2761,11 @@ hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int
     while (nm < njobs && h_jobs[nm].kind == BATCH_MULTI)
         nm++;
     size_t lds_m = 0, lds_s = 0;
+    const int rg = nm < njobs ? h_jobs[nm].rg : 0;
     int64_t blocks_m = 0, blocks_s = 0;
     for (int k = 0; k < njobs; k++) {
         const BatchJob &j = h_jobs[k];
-        if (j.n16 > 128 || (k >= nm && j.kind != BATCH_SINGLE))
+        if (j.n16 > 128 || (k >= nm && (j.kind != BATCH_SINGLE || j.rg != rg)))
             return hipErrorInvalidValue;
         int64_t end = (int64_t)j.block0 + (int64_t)j.gx * j.gy * j.gz;
         if (k < nm) {
@@ -2777,9 +2784,10 @@ hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int
     hipLaunchKernelGGL(k_tstats, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
     if (nm > 0)
         hipLaunchKernelGGL(k_batch<kBatchR>, dim3((unsigned)blocks_m), dim3(256), lds_m, s, d_jobs, nm);
-    if (nm < njobs)
-        hipLaunchKernelGGL(k_single<kSingleRG>, dim3((unsigned)blocks_s), dim3(256), lds_s, s, d_jobs + nm,
-                           njobs - nm);
+    if (nm < njobs) {
+        auto ks = rg == 8 ? k_single<8> : rg == 4 ? k_single<4> : k_single<2>;
+        hipLaunchKernelGGL(ks, dim3((unsigned)blocks_s), dim3(256), lds_s, s, d_jobs + nm, njobs - nm);
+    }
     hipLaunchKernelGGL(k_fold_batch, dim3((unsigned)nfold), dim3(256), 0, s, d_jobs, njobs);
     hipLaunchKernelGGL(k_reduce_batch, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
     return hipGetLastError();

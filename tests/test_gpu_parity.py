@@ -77,6 +77,24 @@ def test_full_maps_bit_exact(S, k):
     g = S.search(i, tpl, "full")
     same_answer(g, o, f"full case {k}")
     assert g["n_computed"] == g["n_locations"] == o["rho_map"].size
+    same_answer(S.search(i, tpl, "full_mfma"), o, f"full_mfma case {k}")
+    S.unload(i)
+
+
+def test_full_mfma_four_row_groups(S):
+    """A 2048x4096 image with one 64x64 template: the single-template MFMA kernel runs 64-row blocks
+    here (128-row blocks from 4096x4096 up, 32-row blocks on the small cases).  The answer equals the
+    v_dot4 exhaustive search's, and the oracle recomputes the exact sums at it."""
+    img = spectral_image(2048, 4096, 2.0, 4096)
+    tpl, _ = cut_template(img, 64, 64, 4097, 6.0)
+    i = S.load(img)
+    g = S.search(i, tpl, "full_mfma")
+    f = S.search(i, tpl, "full")
+    for k in KEYS:
+        assert g[k] == f[k], k
+    y, x = g["y"], g["x"]
+    sub = O.full_search(img[y:y + 64, x:x + 64], tpl)
+    assert (g["num"], g["den_t"], g["den_r"], g["rho"]) == (sub["num"], sub["den_t"], sub["den_r"], sub["rho"])
     S.unload(i)
 
 
