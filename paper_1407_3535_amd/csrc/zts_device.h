@@ -339,16 +339,18 @@ __device__ __forceinline__ void rec_take(RecPod &r, int64_t l, int64_t num, int6
 }
 
 // Out of line for the kernels that offer many values per thread (the
-// binary64 evaluation stays out of their register budget).
-__device__ __noinline__ void rec_offer_band(RecPod &r, int64_t l, int64_t num, int64_t dt, int64_t dr)
+// binary64 evaluation stays out of their register budget).  The record goes
+// in and out by value, so the caller's copy can stay in registers.
+__device__ __noinline__ RecPod rec_offer_band(RecPod r, int64_t l, int64_t num, int64_t dt, int64_t dr)
 {
     rec_take(r, l, num, dt, dr);
+    return r;
 }
 
 __device__ __forceinline__ void rec_offer(RecPod &r, float r32, int64_t l, int64_t num, int64_t dt, int64_t dr)
 {
     if (r32 >= r.r32max - kEpsRho)
-        rec_offer_band(r, l, num, dt, dr);
+        r = rec_offer_band(r, l, num, dt, dr);
     r.r32max = fmaxf(r.r32max, r32);
 }
 
