@@ -2306,49 +2306,39 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 // when it counts) into the answer, after the kernels that wrote them have
 // finished: the kernel boundary makes the records visible on every XCD
 // without a device-scope fence in each writing block.
-// Publishes the query state to its host mirror (pinned, coherent): every
-// word but the sequence number, a system-scope fence, then the sequence
-// number, so a host that sees the new number reads a complete state.
-__device__ void publish_state(QState *qs, QState *host)
-{
-    qs->t1 = __builtin_amdgcn_s_memrealtime();
-    const unsigned long long seq = qs->seq + 1;
-    qs->seq = seq;
-    const uint64_t *__restrict__ src = (const uint64_t *)qs;
-    uint64_t *__restrict__ dst = (uint64_t *)host;
-    constexpr int kWords = (int)(sizeof(QState) / 8), kSeqWord = (int)(offsetof(QState, seq) / 8);
-    static_assert(sizeof(QState) % 8 == 0 && offsetof(QState, seq) % 8 == 0, "8-byte words");
-    uint64_t w[kWords];
-#pragma unroll
-    for (int k = 0; k < kWords; k++)  // every load in flight before the stores
-        w[k] = src[k];
-#pragma unroll
-    for (int k = 0; k < kWords; k++)
-        if (k != kSeqWord)
-            dst[k] = w[k];
-    __threadfence_system();
-    __hip_atomic_store(&host->seq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 // One block folds the per-block records of the final scan (and of the window
 // when it counts) into the answer, after the kernels that wrote them have
 // finished: the kernel boundary makes the records visible on every XCD
 // without a device-scope fence in each writing block.  It then publishes the
-// query state to the host mirror.
-__global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi, int count_lo,
-                                                 QState *qs, QState *host)
+// query state to its host mirror (pinned, coherent): every word but the
+// sequence number, a system-scope fence, then the sequence number, so a host
+// that sees the new number reads a complete state.  The state the earlier
+// kernels wrote is loaded by thread 0 together with the records, and the
+// mirror is written from registers.
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi,
+                                                        int count_lo, QState *qs, QState *host)
 {
-    __shared__ RecPod red[16];
-    const int degenerate = qs->degenerate;
-    // Best over [lo, hi), counts over [count_lo, hi); up to four records per
-    // thread are loaded before they are merged.
+    __shared__ RecPod red[kRedThreads / 64];
+    constexpr int kWords = (int)(sizeof(QState) / 8), kSeqWord = (int)(offsetof(QState, seq) / 8);
+    static_assert(sizeof(QState) % 8 == 0 && offsetof(QState, seq) % 8 == 0, "8-byte words");
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint64_t w[kWords];
+    if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < kWords; k++)
+            w[k] = ((const uint64_t *)qs)[k];
+    }
+    // best over [lo, hi), counts over [count_lo, hi); up to four records per
+    // thread are loaded before they are merged
     RecPod r = rec_empty();
     const int start = min(lo, count_lo);
-    for (int k0 = start + threadIdx.x; k0 < hi; k0 += 4 * blockDim.x) {
+    for (int k0 = start + t; k0 < hi; k0 += 4 * kRedThreads) {
         RecPod b[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            const int k = k0 + j * (int)blockDim.x;
+            const int k = k0 + j * kRedThreads;
             b[j] = k < hi ? recs[k] : rec_empty();
             if (k < lo)
                 b[j].valid = 0;
@@ -2359,17 +2349,43 @@ __global__ __launch_bounds__(1024) void k_reduce(const RecPod *__restrict__ recs
         for (int j = 0; j < 4; j++)
             rec_merge(r, b[j]);
     }
-    RecPod f = block_rec4(r, red);
-    if (threadIdx.x == 0) {
-        if (!degenerate) {
-            qs->fin = f;
-            qs->fin_r32 = rho32(f.num, qs->dt, f.dr);
-            qs->n_elim = f.n_elim;
-            qs->n_surv = f.n_surv;
-            qs->n_window = f.n_window;
-        }
-        publish_state(qs, host);
+    r = wave_rec(r);
+    if (lane == 0)
+        red[wv] = r;
+    __syncthreads();
+    if (wv != 0)
+        return;
+    const RecPod f = wave_rec<kRedThreads / 64>(lane < kRedThreads / 64 ? red[lane] : rec_empty());
+    if (lane != 0)
+        return;
+    QState q;
+    __builtin_memcpy(&q, w, sizeof q);
+    if (!q.degenerate) {
+        q.fin = f;
+        q.fin_r32 = rho32(f.num, q.dt, f.dr);
+        q.n_elim = f.n_elim;
+        q.n_surv = f.n_surv;
+        q.n_window = f.n_window;
     }
+    q.t1 = __builtin_amdgcn_s_memrealtime();
+    q.seq += 1;
+    // the device copy keeps the answer and the sequence (the next query
+    // continues from it)
+    qs->fin = q.fin;
+    qs->fin_r32 = q.fin_r32;
+    qs->n_elim = q.n_elim;
+    qs->n_surv = q.n_surv;
+    qs->n_window = q.n_window;
+    qs->t1 = q.t1;
+    qs->seq = q.seq;
+    __builtin_memcpy(w, &q, sizeof q);
+    uint64_t *__restrict__ dst = (uint64_t *)host;
+#pragma unroll
+    for (int k = 0; k < kWords; k++)
+        if (k != kSeqWord)
+            dst[k] = w[k];
+    __threadfence_system();
+    __hip_atomic_store(&host->seq, q.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ============================================================== launch wrappers
@@ -2410,7 +2426,7 @@ static constexpr int kFullR = 8;
 
 hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, recs, lo, hi, count_lo, qs, host);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, recs, lo, hi, count_lo, qs, host);
     return hipGetLastError();
 }
 
