@@ -503,6 +503,8 @@ void build_tables(Ctx *c, Prepared &P, const Searched &S, int Ly, int Lx)
     a.theta_b = P.theta_b.as<float>();
     a.x_b = P.x_b.as<int32_t>();
     hip_check(launch_autocorr(a, psat_for(c, Ly, Lx, P.m, P.n), c->stream));
+    dalloc(c, P.cstat, sizeof(int2) * (size_t)P.Gy * P.Gx);
+    hip_check(launch_centre_stats(S.stat, Ly, Lx, P.h, P.w, P.Gy, P.Gx, P.cstat.as<int2>(), c->stream));
     dalloc(c, P.gsum, sizeof(GroupSum) * (size_t)P.Gy * P.Gx);
     GsumArgs g;
     g.theta_b = P.theta_b.as<float>();
@@ -945,6 +947,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     s.img = spx;
     s.pitch = im->pitch;
     s.stat = sstat;
+    s.cstat = P->cstat.as<int2>();
     s.tpl = tpl;
     s.ts = ts;
     s.m = m;

@@ -31,6 +31,7 @@ struct ScanArgs {
     const uint8_t *img;
     int64_t pitch;
     const int2 *stat;
+    const int2 *cstat;  // MFMA form: statistics of each group centre's block, [Gy][Gx]
     const uint8_t *tpl;
     int64_t ts;
     int m, n, n4w, pad, Ly, Lx, h, w, Gy, Gx;
@@ -209,6 +210,10 @@ hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int 
 bool autocorr_by_shifts(int m, int n, int h, int w);
 hipError_t launch_autocorr(AcArgs a, uint32_t *psat, hipStream_t s);
 hipError_t launch_gsum(GsumArgs a, hipStream_t s);
+// Statistics of every group centre's block, gathered from the per-location
+// map into [Gy][Gx] (centres as scan 1 places them).
+hipError_t launch_centre_stats(const int2 *stat, int Ly, int Lx, int h, int w, int Gy, int Gx, int2 *out,
+                               hipStream_t s);
 hipError_t launch_blur(const uint8_t *src, uint8_t *dst, int64_t pitch, int p, int q, const Taps &tp,
                        uint32_t *tmp, hipStream_t s);
 // psat: scratch of sat_elems(p, q) uint32 for the running sums of J' I'.

@@ -714,28 +714,29 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 constexpr int kCmThreads = 512;
 constexpr int kCmLd = 12;   // staged words per thread and chunk, at most
 
-// Template rows flipped to int8 at row stride tstr, then one zero row; the
-// block sums of t' and t'^2.  Whole words are loaded when the rows are
-// word-aligned (bytes past column n are masked to int8 zero).
-__device__ void load_template_rows(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int nw16, int tstr,
-                                   uint32_t *lds, int *red, int64_t *st, int64_t *sq)
+// Template rows flipped to int8 at row stride tstr, then one zero row, and
+// this thread's partial sums of t' and t'^2 (no barrier: the caller's next
+// barrier publishes the rows, and the sums are reduced where they are
+// needed).  Whole words are loaded when the rows are word-aligned (bytes
+// past column n are masked to int8 zero).
+__device__ __forceinline__ void load_template_rows(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n,
+                                                   int nw16, int tstr, uint32_t *lds, int *s, int *s2)
 {
     const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
     const uint32_t ones = 0x01010101u;
-    int s = 0, s2 = 0;
+    int a = 0, a2 = 0;
     for (int idx = threadIdx.x; idx < (m + 1) * nw16; idx += blockDim.x) {
         int r = idx / nw16, j = idx - r * nw16;
         uint32_t w = 0;
         if (r < m) {
             w = tpl_word(tpl, ts, n, r, j, words);
-            s = dot4(w, ones, s);
-            s2 = dot4(w, w, s2);
+            a = dot4(w, ones, a);
+            a2 = dot4(w, w, a2);
         }
         lds[r * tstr + j] = w;
     }
-    *st = block_sum_int(s, red);
-    *sq = block_sum_int(s2, red);
-    __syncthreads();
+    *s = a;
+    *s2 = a2;
 }
 
 template <int NB>  // 16-byte column blocks of the template row (n16 = 16 NB)
@@ -744,7 +745,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[8];
+    __shared__ int red[2 * (kCmThreads / 64)];
     __shared__ RecPod rred[kCmThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, mt = wv & 3, kh = wv >> 2;
     const int m = a.m, n = a.n;
@@ -806,17 +807,12 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
         sc[e] = make_int2(0, 0);
         if (gyy < a.Gy && gxx < a.Gx)
-            sc[e] = ld_int2(a.stat + (int64_t)crow(gyy) * a.Lx + ccol(gxx));
+            sc[e] = ld_int2(a.cstat + (int64_t)gyy * a.Gx + gxx);
     }
-    int64_t st, sq2;
-    load_template_rows(a.tpl, a.ts, m, n, nw16, tstr, tpl_l, red, &st, &sq2);
-    const int64_t mn = (int64_t)m * n;
-    const int64_t dt = mn * sq2 - st * st;
-    if (dt == 0) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
-            a.qs->degenerate = 1;
-        return;
-    }
+    // the template statistics are reduced after the main loop, which needs
+    // only the rows (published by the barrier below)
+    int ps, ps2;
+    load_template_rows(a.tpl, a.ts, m, n, nw16, tstr, tpl_l, &ps, &ps2);
     cstore(0);
     __syncthreads();
     v4i acc = v4i{0, 0, 0, 0};
@@ -861,8 +857,27 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     // barrier)
     int2 *xch = (int2 *)buf0;
     xch[(kh * 4 + mt) * 64 + lane] = kh ? make_int2(acc[0], acc[1]) : make_int2(acc[2], acc[3]);
+    ps = wave_sum(ps);
+    ps2 = wave_sum(ps2);
+    if (lane == 0) {
+        red[wv] = ps;
+        red[kCmThreads / 64 + wv] = ps2;
+    }
     __syncthreads();
     const int2 o = xch[((1 - kh) * 4 + mt) * 64 + lane];
+    int64_t st = 0, sq2 = 0;
+#pragma unroll
+    for (int k = 0; k < kCmThreads / 64; k++) {
+        st += red[k];
+        sq2 += red[kCmThreads / 64 + k];
+    }
+    const int64_t mn = (int64_t)m * n;
+    const int64_t dt = mn * sq2 - st * st;
+    if (dt == 0) {  // uniform over the block
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
+            a.qs->degenerate = 1;
+        return;
+    }
     int64_t num[2], dc[2];
     float r32[2];
     bool ok[2];
@@ -2672,6 +2687,26 @@ hipError_t launch_autocorr(AcArgs a, uint32_t *psat, hipStream_t s)
             hipLaunchKernelGGL(k_ac_shift, dim3(blocks_for(G, 256)), dim3(256), 0, s, a, dy, dx,
                                (const uint32_t *)psat, q);
         }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_centre_stats(const int2 *__restrict__ stat, int Ly, int Lx, int h, int w,
+                                                      int Gy, int Gx, int2 *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)Gy * Gx)
+        return;
+    const int gy = (int)(g / Gx), gx = (int)(g - (g / Gx) * Gx);
+    const int oy = gy * h, ox = gx * w;
+    const int cy = oy + (min(h, Ly - oy) - 1) / 2, cx = ox + (min(w, Lx - ox) - 1) / 2;
+    out[g] = stat[(int64_t)cy * Lx + cx];
+}
+
+hipError_t launch_centre_stats(const int2 *stat, int Ly, int Lx, int h, int w, int Gy, int Gx, int2 *out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_centre_stats, dim3(blocks_for((int64_t)Gy * Gx, 256)), dim3(256), 0, s, stat, Ly, Lx, h, w,
+                       Gy, Gx, out);
     return hipGetLastError();
 }
 

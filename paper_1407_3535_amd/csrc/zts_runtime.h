@@ -110,6 +110,7 @@ struct Prepared {
     int m, n, h, w, Gy, Gx, radius;
     zts_params params;
     DBuf theta_b, x_b, gsum;       // member vs centre on the searched image
+    DBuf cstat;                    // statistics of each group centre's block on the searched image
     DBuf gsum_b;                   // OptA: group summaries of theta_b alone (the paper's search)
     DBuf J, Jsat, Jstat;           // OptA: conditioned image and its statistics
     DBuf theta_c, x_c;             // OptA: conditioned block vs original block (row-major)
