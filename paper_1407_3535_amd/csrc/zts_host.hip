@@ -848,7 +848,7 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
             int n2 = radius >= 0 ? window_record_count(radius) : 0;
             int n3 = members_record_count(P->Gy, P->Gx);
             dalloc(c, S.recs, sizeof(RecPod) * (size_t)(n1 + n2 + n3));
-            dalloc(c, S.gnum, sizeof(int64_t) * (size_t)P->Gy * P->Gx);
+            dalloc(c, S.gnum, sizeof(int32_t) * (size_t)P->Gy * P->Gx);
             dalloc(c, S.gtheta, sizeof(float) * (size_t)P->Gy * P->Gx);
         }
     } catch (...) {
@@ -958,7 +958,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     s.w = P->w;
     s.Gy = P->Gy;
     s.Gx = P->Gx;
-    s.g_num = S.gnum.as<int64_t>();
+    s.g_x = S.gnum.as<int32_t>();
     s.g_theta = S.gtheta.as<float>();
     s.recs = recs;
     s.qs = qs;
@@ -1001,7 +1001,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.w = P->w;
     ma.Gy = P->Gy;
     ma.Gx = P->Gx;
-    ma.g_num = S.gnum.as<int64_t>();
+    ma.g_x = S.gnum.as<int32_t>();
     ma.g_theta = S.gtheta.as<float>();
     ma.gsum = paper ? P->gsum_b.as<GroupSum>() : P->gsum.as<GroupSum>();
     ma.theta_b = P->theta_b.as<float>();

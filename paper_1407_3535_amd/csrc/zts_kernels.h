@@ -35,7 +35,7 @@ struct ScanArgs {
     const uint8_t *tpl;
     int64_t ts;
     int m, n, n4w, pad, Ly, Lx, h, w, Gy, Gx;
-    int64_t *g_num;
+    int32_t *g_x;  // per group: the centre's exact sum of t' r' (N_tc = mn X - S_t S_c)
     float *g_theta;
     RecPod *recs;
     QState *qs;
@@ -73,7 +73,7 @@ struct MemArgs {
     const uint8_t *tpl;
     int64_t ts;
     int m, n, Ly, Lx, h, w, Gy, Gx;
-    const int64_t *g_num;
+    const int32_t *g_x;
     const float *g_theta;
     const GroupSum *gsum;
     const float *theta_b;   // member vs its centre on the searched image (group-major)

@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
             int2 sc = a.stat[l];
             int64_t dc = var_num(mn, sc);
             int64_t num = mn * (int64_t)X - st * (int64_t)sc.x;
-            a.g_num[g] = num;
+            a.g_x[g] = X;
             a.g_theta[g] = theta32(num, dt, dc);
             rec_offer(rec, rho32(num, dt, dc), l, num, dt, dc);
             if (a.dec)
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         r32[e] = rho32(num[e], dt, dc[e]);
         if (ok[e]) {
             const int gi = gyy * a.Gx + gxx;
-            a.g_num[gi] = num[e];
+            a.g_x[gi] = x;
             a.g_theta[gi] = theta32(num[e], dt, dc[e]);
             lmax = fmaxf(lmax, r32[e]);
             if (a.dec)
@@ -1050,8 +1050,8 @@ __device__ void load_template_words(const uint8_t *__restrict__ tpl, int64_t ts,
 // Canonical binary64 elimination test (the transitive bound of Eq. 2, or
 // its angle-triangle form with the blur angle C when a.opta).  True: keep.
 // o: location, s: its slot in the group-major tables, c: centre location.
-__device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t s, int64_t c, int g, int64_t mn, int64_t dt,
-                               double thr64)
+__device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t s, int64_t c, int g, int64_t mn, int64_t st,
+                               int64_t dt, double thr64)
 {
     int2 sc = a.statS[c], so = a.statS[o];
     int64_t dc = var_num(mn, sc), dso = var_num(mn, so);
@@ -1063,7 +1063,7 @@ __device__ bool keep_canonical(const MemArgs &a, int64_t o, int64_t s, int64_t c
     }
     if (dc == 0 || dso == 0 || dio == 0)
         return true;
-    int64_t ntc = a.g_num[g];
+    int64_t ntc = mn * (int64_t)a.g_x[g] - st * (int64_t)sc.x;
     double ra = rho64(ntc, dt, dc), sa = sin64(ntc, dt, dc);
     int64_t nco = mn * (int64_t)a.x_b[s] - (int64_t)sc.x * (int64_t)so.x;
     double rb = rho64(nco, dc, dso), sb = sin64(nco, dc, dso);
@@ -1266,7 +1266,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
                 keep = true;
             else {
                 int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
-                keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g0 + u, mn, dt, thr64);
+                keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g0 + u, mn, st, dt, thr64);
             }
             if (keep) {
                 int pos = atomicAdd(&s_nsurv, 1);
