@@ -980,6 +980,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
         wa.radius = radius;
         wa.skip_centres = !onJ;
         wa.include_best0 = !onJ;
+        wa.thr_out = !paper;  // scan 2 runs next and takes the scan-1 best from here
         wa.recs = recs;
         wa.rec_off = win_off;  // its centre: the best of the records before it
         wa.qs = qs;
@@ -1018,6 +1019,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.n_best0 = Q.n1;
     ma.n_win = paper ? 0 : Q.n2;
     ma.include_best0 = !opta;
+    ma.thr_ready = radius >= 0 && !paper;
     ma.delta = pr.margin;
 }
 

@@ -57,6 +57,7 @@ struct WinArgs {
     int radius;
     int skip_centres;   // scan 1 ran on this image: its centres are already matched
     int include_best0;  // the scan-1 best is an original-image rho
+    int thr_out;        // scan 2 runs next: block 0 writes the scan-1 best into the query state
     RecPod *recs;       // scan-1 records [0, rec_off), then this kernel's
     int rec_off;
     QState *qs;
@@ -91,6 +92,8 @@ struct MemArgs {
     // window [n_best0, n_best0 + n_win); include_best0: the scan-1 best is an
     // original-image rho and competes with the window's
     int n_best0, n_win, include_best0;
+    int thr_ready;  // the window kernel wrote the scan-1 best into the query state: only the window
+                    // records are reduced, by each wave
     double delta;
 };
 

@@ -206,6 +206,29 @@ struct Thr {
     float lo, hi;
 };
 
+// The threshold from the scan-1 best f0 and the window best fw (n2 window
+// records; none: the scan-1 best alone).
+__device__ Thr make_threshold(Best f0, Best fw, int n2, int include_best0, double delta)
+{
+    Thr r;
+    r.best0 = f0.rho;
+    r.best0_l = f0.l;
+    if (n2 > 0) {
+        if (include_best0)
+            best_merge(fw, f0.rho, f0.l, 1);
+    } else {
+        fw = f0;
+    }
+    r.best = fw.rho;
+    r.best_l = fw.l;
+    r.thr64 = fw.rho - delta;
+    double c = r.thr64 > 1.0 ? 1.0 : (r.thr64 < -1.0 ? -1.0 : r.thr64);
+    float th = (float)acos(c);
+    r.lo = th - kEpsTheta;
+    r.hi = th + kEpsTheta;
+    return r;
+}
+
 __device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_best0, double delta, Best *red)
 {
     // one pass over both record ranges: every load is issued before the
@@ -234,23 +257,7 @@ __device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_b
         best_merge(fw, red[nw + w].rho, red[nw + w].l, red[nw + w].valid);
     }
     __syncthreads();
-    Thr r;
-    r.best0 = f0.rho;
-    r.best0_l = f0.l;
-    if (n2 > 0) {
-        if (include_best0)
-            best_merge(fw, f0.rho, f0.l, 1);
-    } else {
-        fw = f0;
-    }
-    r.best = fw.rho;
-    r.best_l = fw.l;
-    r.thr64 = fw.rho - delta;
-    double c = r.thr64 > 1.0 ? 1.0 : (r.thr64 < -1.0 ? -1.0 : r.thr64);
-    float th = (float)acos(c);
-    r.lo = th - kEpsTheta;
-    r.hi = th + kEpsTheta;
-    return r;
+    return make_threshold(f0, fw, n2, include_best0, delta);
 }
 
 __device__ void store_threshold(QState *qs, const Thr &r)
@@ -262,6 +269,24 @@ __device__ void store_threshold(QState *qs, const Thr &r)
     qs->thr64 = r.thr64;
     qs->thr_lo = r.lo;
     qs->thr_hi = r.hi;
+}
+
+// The threshold from the scan-1 best that the window kernel wrote into the
+// query state and the n2 window records, formed by each wave on its own
+// (lanes over the records, then shuffles; no block barrier).
+__device__ Thr wave_threshold(const QState *qs, const RecPod *wrecs, int n2, int include_best0, double delta)
+{
+    const Best f0 = {qs->best0, qs->best0_l, 1};
+    Best fw = {-2.0, INT64_MAX, 0};
+    for (int k = threadIdx.x & 63; k < n2; k += 64)
+        best_merge(fw, wrecs[k].rho, wrecs[k].l, wrecs[k].valid);
+    for (int off = 32; off > 0; off >>= 1) {
+        double r = __shfl_xor(fw.rho, off);
+        long long l = __shfl_xor((long long)fw.l, off);
+        int v = __shfl_xor(fw.valid, off);
+        best_merge(fw, r, (int64_t)l, v);
+    }
+    return make_threshold(f0, fw, n2, include_best0, delta);
 }
 
 __device__ __forceinline__ void group_geom(int g, int Gx, int Ly, int Lx, int h, int w, int &oy, int &ox, int &hh,
@@ -960,7 +985,9 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 // Matches the template on the original image at every location within
 // `radius` of the best scan-1 centre (skipping locations scan 1 already
 // matched when it ran on the same image), one block per location; scan 2
-// forms its threshold from these records.
+// forms its threshold from these records and, when thr_out is set, from the
+// scan-1 best that block 0 writes into the query state (so that scan 2 does
+// not reduce the scan-1 records again).
 constexpr int kWinWords = 16;  // template words per thread read ahead (all of a 128 x 128 template)
 
 __global__ __launch_bounds__(256) void k_window(WinArgs a)
@@ -981,9 +1008,14 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
         const int idx = t + 256 * q;
         tw[q] = idx < nwords ? tpl_word(a.tpl, a.ts, a.n, idx / n4, idx % n4, aligned) : 0u;
     }
-    const int64_t c0 = reduce_best(a.recs, 0, a.rec_off, bred).l;  // best scan-1 centre (has barriers)
+    const Best b0 = reduce_best(a.recs, 0, a.rec_off, bred);  // best scan-1 centre (has barriers)
     if (degenerate)
         return;
+    const int64_t c0 = b0.l;
+    if (a.thr_out && blockIdx.x == 0 && t == 0) {  // scan 2 takes the scan-1 best from here
+        a.qs->best0 = b0.rho;
+        a.qs->best0_l = b0.l;
+    }
     const int W = 2 * a.radius + 1, k = blockIdx.x;
     const int y = (int)(c0 / a.Lx) - a.radius + k / W, x = (int)(c0 % a.Lx) - a.radius + k % W;
     const int64_t l = (int64_t)y * a.Lx + x;
@@ -1142,7 +1174,8 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     // the template words for survivors, in the same round trip (the
     // threshold's barriers make them visible)
     load_template_words(a.tpl, a.ts, a.m, a.n, n4, smem);
-    const Thr thr = block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, bred);
+    const Thr thr = a.thr_ready ? wave_threshold(a.qs, a.recs + a.n_best0, a.n_win, a.include_best0, a.delta)
+                                : block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, bred);
     if (degenerate)
         return;
     if (blockIdx.x == 0 && t == 0)
