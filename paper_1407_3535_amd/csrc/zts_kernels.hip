@@ -1131,8 +1131,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
         tot += tmp[k];
     }
     *total = tot;
-    __syncthreads();
-    return base + incl - v;
+    return base + incl - v;  // tmp must not be written again before the caller's next barrier
 }
 
 // 256 consecutive groups per block.  Phase 1: one thread per group drops the
@@ -1154,7 +1153,6 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ int s_list[CAP];
     __shared__ int s_nsurv;
     __shared__ RecPod wrec[4];
-    __shared__ unsigned long long ured[8];
     __shared__ Best bred[8];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     // This thread's two groups (2t, 2t + 1 of the block), the query state and
@@ -1324,22 +1322,29 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
                 rec_offer_inline(rec, rho32(num, dt, dr), o, num, dt, dr);
             }
         }
-        __syncthreads();
-        if (t == 0)
-            s_nsurv = 0;
-        __syncthreads();
+        if (base + CAP < total) {  // another pass reuses the survivor list
+            __syncthreads();
+            if (t == 0)
+                s_nsurv = 0;
+            __syncthreads();
+        }
     }
-    if (lane == 0)
+    // the counts ride in the wave records (merging sums them): one barrier
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        n_elim += __shfl_xor(n_elim, off);
+        n_surv += __shfl_xor(n_surv, off);
+    }
+    if (lane == 0) {
+        rec.n_elim = n_elim;
+        rec.n_surv = n_surv;
         wrec[wv] = rec;
-    unsigned long long ce = block_sum_u64(n_elim, ured);
-    unsigned long long cs = block_sum_u64(n_surv, ured);
+    }
+    __syncthreads();
     if (wv == 0) {  // the four wave records merged by shuffles in lanes 0..3
         RecPod b = wave_rec<4>(lane < 4 ? wrec[lane] : rec_empty());
-        if (lane == 0) {
-            b.n_elim = ce;
-            b.n_surv = cs;
+        if (lane == 0)
             a.recs[a.rec_off + blockIdx.x] = b;
-        }
     }
 }
 
