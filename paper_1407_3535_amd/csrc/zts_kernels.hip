@@ -781,7 +781,19 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     uint32_t *buf0 = smem + (m + 1) * tstr;         // two chunk buffers of CW dwords
     auto ccol = [&](int gx) { int ox = gx * a.w; return ox + (min(a.w, a.Lx - ox) - 1) / 2; };
     auto crow = [&](int gy) { int oy = gy * a.h; return oy + (min(a.h, a.Ly - oy) - 1) / 2; };
-    const int gx0 = blockIdx.x * 64, gy0 = blockIdx.y * 16;
+    // XCD-aware placement: the hardware deals workgroup ids round-robin over
+    // the 8 XCDs; each XCD's ids are mapped to a contiguous run of blocks in
+    // column-major order, so vertically adjacent regions (which overlap by
+    // m - h image rows) are mostly read through the same L2
+    int bxl, byl;
+    {
+        const int nb = gridDim.x * gridDim.y, hw = blockIdx.y * gridDim.x + blockIdx.x;
+        const int q8 = nb >> 3, r8 = nb & 7, xcd = hw & 7;
+        const int j = xcd * q8 + min(xcd, r8) + (hw >> 3);
+        bxl = j / gridDim.y;
+        byl = j - bxl * gridDim.y;
+    }
+    const int gx0 = bxl * 64, gy0 = byl * 16;
     const int ny = min(16, a.Gy - gy0);
     const int xw0 = ccol(gx0) >> 2;                 // first staged word of the region's rows
     const int ylo = crow(gy0), yhi = crow(gy0 + ny - 1) + m;
