@@ -200,6 +200,40 @@ def test_opta_parity(S, seed, blur_kind):
     S.unload(i)
 
 
+@pytest.mark.parametrize("radius", [3, 5, 9])
+def test_large_refinement_windows(S, radius):
+    """Refinement windows of 49 to 361 locations (more than one wave's lanes for scan 2's threshold), with
+    and without the decision map (the graphed and the eager launch), TE on the original image and OptA on
+    the conditioned one: answer, counts and decisions equal the oracle's."""
+    img = aerial_image(130, 160, 900 + radius, beta=2.4)
+    m = n = 14
+    i = S.load(img)
+    oo = O.opta(img, m, n, max_iters=3)
+    S.prepare(i, m, n, "opta", max_iters=3)
+    for k in range(2):
+        tpl, _ = cut_template(img, m, n, 1900 + 10 * radius + k, 10.0, affine=True)
+        full = O.full_search(img, tpl)
+        ot = O.te_search(img, tpl, 3, 4, decision=True, radius=radius)
+        for want_dec in (False, True):
+            if want_dec:
+                g, dec = S.search(i, tpl, "te_fixed", decision=True, group_h=3, group_w=4, refine_radius=radius)
+                assert np.array_equal(dec, ot["decision"])
+            else:
+                for _ in range(3):  # eager, captured, replayed
+                    g = S.search(i, tpl, "te_fixed", group_h=3, group_w=4, refine_radius=radius)
+                    same_answer(g, full, f"te radius {radius}")
+                    same_counts(g, ot, f"te radius {radius}")
+            same_answer(g, full, f"te radius {radius}")
+            same_counts(g, ot, f"te radius {radius}")
+        rad = max(oo["radius"], radius)
+        os_ = O.opta_search(img, oo["image"], tpl, oo["h"], oo["w"], rad, decision=True)
+        for _ in range(3):
+            g = S.search(i, tpl, "opta", max_iters=3, refine_radius=radius)
+            same_answer(g, full, f"opta radius {radius}")
+            same_counts(g, os_, f"opta radius {radius}")
+    S.unload(i)
+
+
 def test_ties_go_to_smallest_index(S):
     rng = np.random.default_rng(3)
     tile = rng.integers(0, 256, (6, 7), dtype=np.uint8)
