@@ -278,14 +278,17 @@ def zts_search_decision(ctx, image: int, image_shape, tpl, mode, params: Params 
     return r.as_dict(), dec
 
 
-def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None = None, stream=None) -> dict:
+def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None = None, stream=None,
+                      out: Result | None = None):
+    """One search of a device template (read in place after the caller's stream).  Returns a dict, or, with
+    `out`, fills that Result and returns it (no per-call allocation: for loops that search repeatedly)."""
     p = params if params is not None else zts_params_default()
     s = stream if stream is not None else _current_stream(tpl_tensor.device.index)
-    r = Result()
+    r = out if out is not None else Result()
     m, n = tpl_tensor.shape
     _check(lib().zts_search_device(ctx, image, tpl_tensor.data_ptr(), m, n, tpl_tensor.stride(0), _mode(mode),
                                    C.byref(p), s, C.byref(r)), "zts_search_device")
-    return r.as_dict()
+    return r if out is not None else r.as_dict()
 
 
 def zts_search_batch(ctx, image: int, tpls) -> list:
