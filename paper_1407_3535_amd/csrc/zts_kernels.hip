@@ -1324,8 +1324,9 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         __syncthreads();
         int ns = s_nsurv;
         for (int k = wv; k < ns; k += 4) {
-            int64_t o = s_list[k];
-            int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+            const int o32 = s_list[k];  // locations fit 31 bits (sides of at most 32767)
+            const int64_t o = o32;
+            const int y = o32 / a.Lx, x = o32 - y * a.Lx;
             const int2 so = lane == 0 ? a.statI[o] : make_int2(0, 0);  // with the image words
             int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, lane);
             if (lane == 0) {
@@ -1397,7 +1398,7 @@ __device__ unsigned ac_finish(const AcArgs &a, int64_t o, int64_t c, int X)
         return 0;
     }
     if (a.mode == AC_BUILD) {
-        const int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        const int y = (int)o / a.Lx, x = (int)o - y * a.Lx;
         const int gy = y / a.h, gx = x / a.w;
         const int64_t sl = ((int64_t)gy * ((a.Lx + a.w - 1) / a.w) + gx) * (a.h * a.w) + (y - gy * a.h) * a.w +
                            (x - gx * a.w);
@@ -1444,9 +1445,9 @@ __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
         int64_t o = (int64_t)blockIdx.x * 64 + wv * 16 + k;
         if (o >= L)
             break;
-        int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        int y = (int)o / a.Lx, x = (int)o - y * a.Lx;
         int64_t c = centre_of(y, x, a.Ly, a.Lx, a.h, a.w);
-        int cy = (int)(c / a.Lx), cx = (int)(c - (c / a.Lx) * a.Lx);
+        int cy = (int)c / a.Lx, cx = (int)c - cy * a.Lx;
         int X;
         if (c == o)
             X = a.statJ[c].y;  // sum of squares of the centre block
@@ -1578,7 +1579,7 @@ __global__ __launch_bounds__(256) void k_blurcorr(BcArgs a)
     const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long cnt = 0;
     if (o < L) {
-        const int y = (int)(o / a.Lx), x = (int)(o - (o / a.Lx) * a.Lx);
+        const int y = (int)o / a.Lx, x = (int)o - y * a.Lx;
         const int64_t W = a.q + 1;
         const uint32_t *s0 = a.psat + (int64_t)y * W + x, *s1 = s0 + (int64_t)a.m * W;
         const int X = (int)(s1[a.n] - s1[0] - s0[a.n] + s0[0]);
