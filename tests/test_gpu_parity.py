@@ -286,6 +286,13 @@ def test_device_entry_points_match_host_ones(S):
     b = Z.zts_search_device(S.ctx, j, t, "egs")
     for k in KEYS + ("n_eliminated", "n_survivors", "n_computed"):
         assert a[k] == b[k]
+    # the same call filling a caller's result record, repeatedly (the record is overwritten each time)
+    res = Z.Result()
+    for _ in range(3):
+        out = Z.zts_search_device(S.ctx, j, t, "egs", Z.zts_params_default(), 0, out=res)
+        assert out is res
+        for k in KEYS + ("n_eliminated", "n_survivors", "n_computed"):
+            assert getattr(res, k) == a[k]
     # int8 MFMA from a device template whose rows are strided (a column slice of a wider tensor)
     wide = torch.zeros((24, 40), dtype=torch.uint8, device="cuda")
     wide[:, 5:29] = t
