@@ -205,14 +205,18 @@ __device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, i
     int r0 = lane / n4, j = lane - r0 * n4;
     int acc = 0;
     if (r0 < rp) {
-        int64_t a0 = (int64_t)y * pitch + x + 4 * j;
-        uint32_t sh = (uint32_t)(x & 3);
-        const uint32_t *base = (const uint32_t *)(img + (a0 & ~(int64_t)3));
-        int64_t pw = pitch >> 2;
+        // image and template pointers advance by rp rows per step (the pitch
+        // is a multiple of 4, so the aligned row starts differ by whole words)
+        const uint32_t sh = (uint32_t)(x & 3);
+        const uint32_t *pr = (const uint32_t *)(img + ((((int64_t)y + r0) * pitch + x + 4 * j) & ~(int64_t)3));
+        const int64_t step = (int64_t)rp * (pitch >> 2);
+        const uint32_t *tp = tplw + r0 * n4 + j;
+        const int tstep = rp * n4;
 #pragma unroll 4
         for (int i = r0; i < m; i += rp) {
-            const uint32_t *pr = base + (int64_t)i * pw;
-            acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), tplw[i * n4 + j], acc);
+            acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), *tp, acc);
+            pr += step;
+            tp += tstep;
         }
     }
     return wave_sum(acc);
