@@ -1323,16 +1323,26 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         }
         __syncthreads();
         int ns = s_nsurv;
-        for (int k = wv; k < ns; k += 4) {
-            const int o32 = s_list[k];  // locations fit 31 bits (sides of at most 32767)
-            const int64_t o = o32;
-            const int y = o32 / a.Lx, x = o32 - y * a.Lx;
-            const int2 so = lane == 0 ? a.statI[o] : make_int2(0, 0);  // with the image words
-            int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, lane);
-            if (lane == 0) {
-                int64_t dr = var_num(mn, so);
-                int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
-                rec_offer_inline(rec, rho32(num, dt, dr), o, num, dt, dr);
+        // this wave's survivors wv, wv + 4, ... in batches of 64: lane L reads
+        // the location and statistics of the batch's survivor L in one round
+        // trip, then the wave matches the batch's survivors one after another
+        // (locations fit 31 bits: sides of at most 32767)
+        for (int kb = wv; kb < ns; kb += 4 * 64) {
+            const int ks = kb + 4 * lane;
+            const int ol = ks < ns ? s_list[ks] : 0;
+            const int2 sol = ks < ns ? a.statI[ol] : make_int2(0, 0);
+            const int nbat = min(64, (ns - kb + 3) >> 2);
+            for (int q = 0; q < nbat; q++) {
+                const int o32 = __shfl(ol, q);
+                const int64_t o = o32;
+                const int y = o32 / a.Lx, x = o32 - y * a.Lx;
+                const int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, lane);
+                const int2 so = make_int2(__shfl(sol.x, q), __shfl(sol.y, q));
+                if (lane == 0) {
+                    int64_t dr = var_num(mn, so);
+                    int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
+                    rec_offer_inline(rec, rho32(num, dt, dr), o, num, dt, dr);
+                }
             }
         }
         if (base + CAP < total) {  // another pass reuses the survivor list
