@@ -212,7 +212,7 @@ __device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, i
         const int64_t step = (int64_t)rp * (pitch >> 2);
         const uint32_t *tp = tplw + r0 * n4 + j;
         const int tstep = rp * n4;
-#pragma unroll 4
+#pragma unroll 8
         for (int i = r0; i < m; i += rp) {
             acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), *tp, acc);
             pr += step;
