@@ -195,15 +195,17 @@ __device__ __forceinline__ int64_t var_num(int64_t mn, int2 st)
 // block is the same for every lane and row (pitch is a multiple of 4), so
 // one v_alignbyte per word realigns it.
 
-// sum over the m x n block at (y, x) of t' * r'; the template is in LDS as
-// flipped int8 words, n4 = ceil(n/4) per row, zero past column n.  Every
-// lane returns the full sum.
-__device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, int n4, const uint8_t *__restrict__ img,
-                                            int64_t pitch, int y, int x, int m, int lane)
+// sum over the m x n block at (y, x) of t * r on the unshifted uint8 values
+// (v_dot4_u32_u8, no byte flips); the template is in LDS as raw words,
+// n4 = ceil(n/4) per row, zero past column n.  Exact in 32 bits for
+// m n <= 65536 (255^2 m n < 2^32).  Every lane returns the full sum.
+__device__ __forceinline__ uint32_t wave_dot_tpl_u8(const uint32_t *__restrict__ tplw, int n4,
+                                                    const uint8_t *__restrict__ img, int64_t pitch, int y, int x,
+                                                    int m, int lane)
 {
     int rp = kWave / n4;
     int r0 = lane / n4, j = lane - r0 * n4;
-    int acc = 0;
+    uint32_t acc = 0;
     if (r0 < rp) {
         // image and template pointers advance by rp rows per step (the pitch
         // is a multiple of 4, so the aligned row starts differ by whole words)
@@ -214,12 +216,12 @@ __device__ __forceinline__ int wave_dot_tpl(const uint32_t *__restrict__ tplw, i
         const int tstep = rp * n4;
 #pragma unroll 8
         for (int i = r0; i < m; i += rp) {
-            acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), *tp, acc);
+            acc = __builtin_amdgcn_udot4(bytes_at(pr[1], pr[0], sh), *tp, acc, false);
             pr += step;
             tp += tstep;
         }
     }
-    return wave_sum(acc);
+    return (uint32_t)wave_sum((int)acc);
 }
 
 // sum over m x n of a' * b' for the block of A at (ya, xa) and of B at

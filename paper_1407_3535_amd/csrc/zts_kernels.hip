@@ -1080,14 +1080,19 @@ __device__ __forceinline__ bool in_window(int y, int x, int wy, int wx, int radi
     return radius >= 0 && abs(y - wy) <= radius && abs(x - wx) <= radius;
 }
 
-// Loads the template words only (statistics come from scan 1).
+// Loads the template words only (statistics come from scan 1), as raw
+// uint8 bytes with zeros past column n: survivors are matched with unsigned
+// dot products, N being the same from unsigned sums (it is shift-invariant).
 __device__ void load_template_words(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int n4,
                                     uint32_t *lds)
 {
     const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
     for (int idx = threadIdx.x; idx < m * n4; idx += blockDim.x) {
         int r = idx / n4, j = idx - (idx / n4) * n4;
-        lds[idx] = tpl_word(tpl, ts, n, r, j, words);
+        const uint32_t w = tpl_word(tpl, ts, n, r, j, words);  // int8 view, zero past column n
+        const int nb = min(4, n - 4 * j);
+        const uint32_t keep = nb < 4 ? (1u << (8 * nb)) - 1u : 0xffffffffu;
+        lds[idx] = (w ^ 0x80808080u) & keep;
     }
 }
 
@@ -1336,11 +1341,13 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
                 const int o32 = __shfl(ol, q);
                 const int64_t o = o32;
                 const int y = o32 / a.Lx, x = o32 - y * a.Lx;
-                const int X = wave_dot_tpl(smem, n4, a.I, a.pI, y, x, a.m, lane);
+                const uint32_t Xu = wave_dot_tpl_u8(smem, n4, a.I, a.pI, y, x, a.m, lane);
                 const int2 so = make_int2(__shfl(sol.x, q), __shfl(sol.y, q));
                 if (lane == 0) {
+                    // N = mn sum(t r) - sum(t) sum(r) on unshifted values; the
+                    // shifted sums S' become sum(x) = S' + 128 mn
                     int64_t dr = var_num(mn, so);
-                    int64_t num = mn * (int64_t)X - st * (int64_t)so.x;
+                    int64_t num = mn * (int64_t)Xu - (st + 128 * mn) * ((int64_t)so.x + 128 * mn);
                     rec_offer_inline(rec, rho32(num, dt, dr), o, num, dt, dr);
                 }
             }
