@@ -203,23 +203,34 @@ __device__ __forceinline__ uint32_t wave_dot_tpl_u8(const uint32_t *__restrict__
                                                     const uint8_t *__restrict__ img, int64_t pitch, int y, int x,
                                                     int m, int lane)
 {
-    int rp = kWave / n4;
-    int r0 = lane / n4, j = lane - r0 * n4;
     uint32_t acc = 0;
-    if (r0 < rp) {
-        // image and template pointers advance by rp rows per step (the pitch
-        // is a multiple of 4, so the aligned row starts differ by whole words)
-        const uint32_t sh = (uint32_t)(x & 3);
-        const uint32_t *pr = (const uint32_t *)(img + ((((int64_t)y + r0) * pitch + x + 4 * j) & ~(int64_t)3));
-        const int64_t step = (int64_t)rp * (pitch >> 2);
-        const uint32_t *tp = tplw + r0 * n4 + j;
-        const int tstep = rp * n4;
+    const uint32_t sh = (uint32_t)(x & 3);
+    if (n4 <= kWave) {
+        const int rp = kWave / n4;
+        const int r0 = lane / n4, j = lane - r0 * n4;
+        if (r0 < rp) {
+            // image and template pointers advance by rp rows per step (the
+            // pitch is a multiple of 4, so the aligned row starts differ by
+            // whole words)
+            const uint32_t *pr = (const uint32_t *)(img + ((((int64_t)y + r0) * pitch + x + 4 * j) & ~(int64_t)3));
+            const int64_t step = (int64_t)rp * (pitch >> 2);
+            const uint32_t *tp = tplw + r0 * n4 + j;
+            const int tstep = rp * n4;
 #pragma unroll 8
-        for (int i = r0; i < m; i += rp) {
-            acc = __builtin_amdgcn_udot4(bytes_at(pr[1], pr[0], sh), *tp, acc, false);
-            pr += step;
-            tp += tstep;
+            for (int i = r0; i < m; i += rp) {
+                acc = __builtin_amdgcn_udot4(bytes_at(pr[1], pr[0], sh), *tp, acc, false);
+                pr += step;
+                tp += tstep;
+            }
         }
+    } else {
+        // rows wider than 64 words: the lanes walk each row 64 words at a time
+        const int64_t pw = pitch >> 2;
+        const uint32_t *row = (const uint32_t *)(img + (((int64_t)y * pitch + x) & ~(int64_t)3));
+#pragma unroll 1
+        for (int i = 0; i < m; i++, row += pw)
+            for (int j = lane; j < n4; j += kWave)
+                acc = __builtin_amdgcn_udot4(bytes_at(row[j + 1], row[j], sh), tplw[i * n4 + j], acc, false);
     }
     return (uint32_t)wave_sum((int)acc);
 }
@@ -230,25 +241,29 @@ __device__ __forceinline__ int wave_dot_img(const uint8_t *__restrict__ A, int64
                                             const uint8_t *__restrict__ B, int64_t pb, int yb, int xb, int m, int n,
                                             int lane)
 {
-    int n4 = (n + 3) >> 2;
-    int rp = kWave / n4;
-    int r0 = lane / n4, j = lane - r0 * n4;
-    uint32_t mask = (j == n4 - 1 && (n & 3)) ? ((1u << (8 * (n & 3))) - 1u) : 0xffffffffu;
+    const int n4 = (n + 3) >> 2;
     int acc = 0;
-    if (r0 < rp) {
-        int64_t a0 = (int64_t)ya * pa + xa + 4 * j;
-        int64_t b0 = (int64_t)yb * pb + xb + 4 * j;
-        uint32_t sa = (uint32_t)(xa & 3), sb = (uint32_t)(xb & 3);
-        const uint32_t *ba = (const uint32_t *)(A + (a0 & ~(int64_t)3));
-        const uint32_t *bb = (const uint32_t *)(B + (b0 & ~(int64_t)3));
-        int64_t pwa = pa >> 2, pwb = pb >> 2;
+    // rows wider than 64 words are taken 64 words at a time
+    for (int c0 = 0; c0 < n4; c0 += kWave) {
+        const int nc = min(kWave, n4 - c0);
+        const int rp = kWave / nc;
+        const int r0 = lane / nc, j = c0 + lane - r0 * nc;
+        const uint32_t mask = (j == n4 - 1 && (n & 3)) ? ((1u << (8 * (n & 3))) - 1u) : 0xffffffffu;
+        if (r0 < rp) {
+            int64_t a0 = (int64_t)ya * pa + xa + 4 * j;
+            int64_t b0 = (int64_t)yb * pb + xb + 4 * j;
+            uint32_t sa = (uint32_t)(xa & 3), sb = (uint32_t)(xb & 3);
+            const uint32_t *ba = (const uint32_t *)(A + (a0 & ~(int64_t)3));
+            const uint32_t *bb = (const uint32_t *)(B + (b0 & ~(int64_t)3));
+            int64_t pwa = pa >> 2, pwb = pb >> 2;
 #pragma unroll 4
-        for (int i = r0; i < m; i += rp) {
-            const uint32_t *pA = ba + (int64_t)i * pwa;
-            const uint32_t *pB = bb + (int64_t)i * pwb;
-            uint32_t va = flip4(bytes_at(pA[1], pA[0], sa)) & mask;
-            uint32_t vb = flip4(bytes_at(pB[1], pB[0], sb));
-            acc = dot4(va, vb, acc);
+            for (int i = r0; i < m; i += rp) {
+                const uint32_t *pA = ba + (int64_t)i * pwa;
+                const uint32_t *pB = bb + (int64_t)i * pwb;
+                uint32_t va = flip4(bytes_at(pA[1], pA[0], sa)) & mask;
+                uint32_t vb = flip4(bytes_at(pB[1], pB[0], sb));
+                acc = dot4(va, vb, acc);
+            }
         }
     }
     return wave_sum(acc);

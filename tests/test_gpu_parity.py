@@ -234,6 +234,35 @@ def test_large_refinement_windows(S, radius):
     S.unload(i)
 
 
+@pytest.mark.parametrize("shape", [(6, 300), (3, 520), (40, 260)])
+def test_wide_templates(S, shape):
+    """Templates wider than 256 pixels (rows of more than 64 words, so the wave dot products take a row in
+    several passes): dense search, TE with and without a refinement window, EGS, and Alg. 1 in its direct
+    form (large groups), all against the oracle."""
+    m, n = shape
+    img = aerial_image(110, 720, 4000 + n)
+    tpl, _ = cut_template(img, m, n, 4100 + n, 6.0)
+    i = S.load(img)
+    full = O.full_search(img, tpl)
+    same_answer(S.search(i, tpl, "full"), full, f"full {shape}")
+    for radius in (0, 2):
+        ot = O.te_search(img, tpl, 3, 3, radius=radius)
+        g = S.search(i, tpl, "te_fixed", group_h=3, group_w=3, refine_radius=radius)
+        same_answer(g, full, f"te {shape} r={radius}")
+        same_counts(g, ot, f"te {shape} r={radius}")
+    oe = O.egs(img, m, n)
+    ge = S.search(i, tpl, "egs")
+    same_answer(ge, full, f"egs {shape}")
+    assert (ge["group_h"], ge["group_w"]) == (oe["h"], oe["w"])
+    hw = (5, 9) if m * n < 2024 else (9, 9)  # (h w - 1) 46 >= m n: the direct form of Alg. 1
+    if (hw[0] * hw[1] - 1) * 46 >= m * n:
+        g = Z.zts_debug_autocorr(S.ctx, i, img.shape, m, n, *hw)
+        o = O.autocorr(img, m, n, *hw)
+        for a_, b_ in zip(g, o):
+            assert np.array_equal(a_, b_)
+    S.unload(i)
+
+
 def test_ties_go_to_smallest_index(S):
     rng = np.random.default_rng(3)
     tile = rng.integers(0, 256, (6, 7), dtype=np.uint8)
