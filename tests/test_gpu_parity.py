@@ -254,6 +254,15 @@ def test_wide_templates(S, shape):
     ge = S.search(i, tpl, "egs")
     same_answer(ge, full, f"egs {shape}")
     assert (ge["group_h"], ge["group_w"]) == (oe["h"], oe["w"])
+    if shape == (6, 300):  # OptA: conditioning traces, the conditioned image, the exact search
+        oo = O.opta(img, m, n, max_iters=3)
+        info = S.prepare(i, m, n, "opta", max_iters=3)
+        assert (info["h"], info["w"], info["cost"]) == (oo["h"], oo["w"], oo["cost"])
+        assert np.array_equal(S.prep_image(i, m, n), oo["image"])
+        go = S.search(i, tpl, "opta", max_iters=3, refine_radius=2)
+        os_ = O.opta_search(img, oo["image"], tpl, oo["h"], oo["w"], max(oo["radius"], 2))
+        same_answer(go, full, f"opta {shape}")
+        same_counts(go, os_, f"opta {shape}")
     hw = (5, 9) if m * n < 2024 else (9, 9)  # (h w - 1) 46 >= m n: the direct form of Alg. 1
     if (hw[0] * hw[1] - 1) * 46 >= m * n:
         g = Z.zts_debug_autocorr(S.ctx, i, img.shape, m, n, *hw)
