@@ -272,6 +272,40 @@ def test_wide_templates(S, shape):
     S.unload(i)
 
 
+def _sweep_cases():
+    rng = np.random.default_rng(20261203)
+    out = []
+    for k in range(16):
+        p, q = int(rng.integers(40, 200)), int(rng.integers(40, 260))
+        m, n = int(rng.integers(2, min(p, 48))), int(rng.integers(2, min(q, 140)))
+        hw = (int(rng.integers(1, 8)), int(rng.integers(1, 8)))
+        radius = int(rng.integers(0, 4))
+        out.append((k, p, q, m, n, hw, radius))
+    return out
+
+
+@pytest.mark.parametrize("case", _sweep_cases(), ids=lambda c: "c%d_%dx%d_t%dx%d" % c[:5])
+def test_random_sweep(S, case):
+    """Seeded random shapes (image, template, group size, refinement radius): TE and the int8-MFMA
+    exhaustive search against the oracle, decisions included."""
+    k, p, q, m, n, (h, w), radius = case
+    img = spectral_image(p, q, float(1.6 + 0.1 * (k % 8)), 7000 + k)
+    tpl, _ = cut_template(img, m, n, 7100 + k, 5.0)
+    if tpl.min() == tpl.max():
+        tpl[0, 0] ^= 1
+    print(f"sweep case {case}", flush=True)
+    i = S.load(img)
+    full = O.full_search(img, tpl)
+    ot = O.te_search(img, tpl, h, w, decision=True, radius=radius)
+    g, dec = S.search(i, tpl, "te_fixed", decision=True, group_h=h, group_w=w, refine_radius=radius)
+    same_answer(g, full, f"te {case}")
+    same_counts(g, ot, f"te {case}")
+    assert np.array_equal(dec, ot["decision"])
+    if n <= 128:
+        same_answer(S.search(i, tpl, "full_mfma"), full, f"full_mfma {case}")
+    S.unload(i)
+
+
 def test_ties_go_to_smallest_index(S):
     rng = np.random.default_rng(3)
     tile = rng.integers(0, 256, (6, 7), dtype=np.uint8)
