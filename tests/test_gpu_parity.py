@@ -306,6 +306,39 @@ def test_random_sweep(S, case):
     S.unload(i)
 
 
+@pytest.mark.parametrize("k", range(8))
+def test_random_sweep_opta_and_batch(S, k):
+    """Seeded random shapes for the prepared modes: EGS and OptA (conditioning traces and the exact search
+    with refinement radius 0..2) and one batched call of mixed template sizes, against the oracle."""
+    rng = np.random.default_rng(880 + k)
+    p, q = int(rng.integers(60, 170)), int(rng.integers(60, 220))
+    m, n = int(rng.integers(4, 24)), int(rng.integers(4, 40))
+    img = aerial_image(p, q, 8800 + k, beta=float(rng.uniform(1.8, 2.8)))
+    tpl, _ = cut_template(img, m, n, 8900 + k, 6.0, affine=bool(k & 1))
+    print(f"opta sweep {k}: image {p}x{q} template {m}x{n}", flush=True)
+    i = S.load(img)
+    full = O.full_search(img, tpl)
+    oe = O.egs(img, m, n)
+    ge = S.search(i, tpl, "egs")
+    same_answer(ge, full, f"egs sweep {k}")
+    assert (ge["group_h"], ge["group_w"]) == (oe["h"], oe["w"])
+    oo = O.opta(img, m, n, max_iters=3)
+    info = S.prepare(i, m, n, "opta", max_iters=3)
+    assert (info["h"], info["w"], info["cost"], info["radius"]) == (oo["h"], oo["w"], oo["cost"], oo["radius"])
+    assert np.array_equal(S.prep_image(i, m, n), oo["image"])
+    radius = int(rng.integers(0, 3))
+    go = S.search(i, tpl, "opta", max_iters=3, refine_radius=radius)
+    os_ = O.opta_search(img, oo["image"], tpl, oo["h"], oo["w"], max(oo["radius"], radius))
+    same_answer(go, full, f"opta sweep {k}")
+    same_counts(go, os_, f"opta sweep {k}")
+    sizes = [(int(rng.integers(3, 30)), int(rng.integers(3, 60))) for _ in range(int(rng.integers(2, 9)))]
+    tpls = [cut_template(img, a_, b_, 9000 + 10 * k + e, 4.0)[0] for e, (a_, b_) in enumerate(sizes)]
+    tpls = [t for t in tpls if t.min() != t.max()]
+    for r, t in zip(S.search_batch(i, tpls), tpls):
+        same_answer(r, O.full_search(img, t), f"batch sweep {k} {t.shape}")
+    S.unload(i)
+
+
 def test_ties_go_to_smallest_index(S):
     rng = np.random.default_rng(3)
     tile = rng.integers(0, 256, (6, 7), dtype=np.uint8)
