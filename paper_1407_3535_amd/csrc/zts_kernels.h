@@ -184,7 +184,8 @@ size_t batch_job_records(const BatchJob &j);
 hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int njobs, hipStream_t s);
 
 // Running-sum tables are allocated with sat_elems(p, q) elements: the
-// (p+1) x (q+1) table followed by the column pass's per-chunk totals.
+// (p+1) x (q+1) table followed by the column pass's per-chunk totals and
+// per-part (16-row) totals.
 size_t sat_elems(int p, int q);
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s);
 hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, int2 *stat, hipStream_t s);

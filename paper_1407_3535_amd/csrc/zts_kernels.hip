@@ -397,8 +397,9 @@ __global__ __launch_bounds__(256) void k_prod_rows(const uint8_t *__restrict__ J
 
 // Column pass of a running-sum table (rows 1..p, row 0 is zero), in two
 // kernels over blocks of 64 columns x 64 rows so that the grid fills the
-// chip: the first writes each block's column totals, the second adds the
-// totals of the chunks above and scans its own rows.  A thread owns one
+// chip: the first writes each block's column totals and the totals of its
+// four 16-row parts, the second adds the totals of the chunks and parts
+// above and scans its own rows, reading the table once.  A thread owns one
 // column and 16 consecutive rows.
 constexpr int kColChunk = 64;
 
@@ -409,7 +410,8 @@ template <> __device__ __forceinline__ uint2 zero_el<uint2>() { return make_uint
 template <> __device__ __forceinline__ uint32_t zero_el<uint32_t>() { return 0u; }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cols_total(const T *__restrict__ sat, int p, int q, T *__restrict__ tot)
+__global__ __launch_bounds__(256) void k_cols_total(const T *__restrict__ sat, int p, int q, T *__restrict__ tot,
+                                                    T *__restrict__ parts)
 {
     __shared__ T part[4][64];
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -417,41 +419,48 @@ __global__ __launch_bounds__(256) void k_cols_total(const T *__restrict__ sat, i
     const int64_t W = q + 1;
     const int r0 = 1 + k * kColChunk + ty * 16, r1 = min(p + 1, r0 + 16);
     T acc = zero_el<T>();
-    if (c <= q)
-        for (int r = r0; r < r1; r++)
-            acc = add_el(acc, sat[(int64_t)r * W + c]);
+    if (c <= q) {
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            if (r0 + j < r1)
+                acc = add_el(acc, sat[(int64_t)(r0 + j) * W + c]);
+    }
     part[ty][tx] = acc;
+    if (c <= q)
+        parts[((int64_t)k * 4 + ty) * W + c] = acc;
     __syncthreads();
     if (ty == 0 && c <= q)
         tot[(int64_t)k * W + c] = add_el(add_el(part[0][tx], part[1][tx]), add_el(part[2][tx], part[3][tx]));
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cols_apply(T *__restrict__ sat, int p, int q, const T *__restrict__ tot)
+__global__ __launch_bounds__(256) void k_cols_apply(T *__restrict__ sat, int p, int q, const T *__restrict__ tot,
+                                                    const T *__restrict__ parts)
 {
-    __shared__ T part[4][64];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int c = blockIdx.x * 64 + tx, k = blockIdx.y;
     const int64_t W = q + 1;
     const int r0 = 1 + k * kColChunk + ty * 16, r1 = min(p + 1, r0 + 16);
-    T mine = zero_el<T>();
-    if (c <= q)
-        for (int r = r0; r < r1; r++)
-            mine = add_el(mine, sat[(int64_t)r * W + c]);
-    part[ty][tx] = mine;
-    __syncthreads();
     if (c > q)
         return;
+    // this thread's 16 rows are loaded first, in flight with the totals above
+    T v[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+        if (r0 + j < r1)
+            v[j] = sat[(int64_t)(r0 + j) * W + c];
     T run = zero_el<T>();
+#pragma unroll 4
     for (int kk = 0; kk < k; kk++)
         run = add_el(run, tot[(int64_t)kk * W + c]);
     for (int j = 0; j < ty; j++)
-        run = add_el(run, part[j][tx]);
-    for (int r = r0; r < r1; r++) {
-        int64_t i = (int64_t)r * W + c;
-        run = add_el(run, sat[i]);
-        sat[i] = run;
-    }
+        run = add_el(run, parts[((int64_t)k * 4 + j) * W + c]);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+        if (r0 + j < r1) {
+            run = add_el(run, v[j]);
+            sat[(int64_t)(r0 + j) * W + c] = run;
+        }
 }
 
 // Per-location box statistics for an m x n block from four table entries.
@@ -2477,15 +2486,16 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 
 size_t sat_elems(int p, int q)
 {
-    return (size_t)(p + 1) * (q + 1) + (size_t)blocks_for(p, kColChunk) * (q + 1);
+    return (size_t)(p + 1) * (q + 1) + (size_t)5 * blocks_for(p, kColChunk) * (q + 1);
 }
 
 template <class T> static void launch_cols(T *sat, int p, int q, hipStream_t s)
 {
-    T *tot = sat + (size_t)(p + 1) * (q + 1);
+    T *tot = sat + (size_t)(p + 1) * (q + 1);                         // [chunks][q + 1]
+    T *parts = tot + (size_t)blocks_for(p, kColChunk) * (q + 1);      // [chunks][4][q + 1]
     dim3 grid(blocks_for(q + 1, 64), blocks_for(p, kColChunk)), blk(64, 4);
-    hipLaunchKernelGGL(k_cols_total<T>, grid, blk, 0, s, (const T *)sat, p, q, tot);
-    hipLaunchKernelGGL(k_cols_apply<T>, grid, blk, 0, s, sat, p, q, (const T *)tot);
+    hipLaunchKernelGGL(k_cols_total<T>, grid, blk, 0, s, (const T *)sat, p, q, tot, parts);
+    hipLaunchKernelGGL(k_cols_apply<T>, grid, blk, 0, s, sat, p, q, (const T *)tot, (const T *)parts);
 }
 
 hipError_t launch_sat(const uint8_t *img, int64_t pitch, int p, int q, uint2 *sat, hipStream_t s)
