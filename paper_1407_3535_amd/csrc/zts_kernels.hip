@@ -368,7 +368,11 @@ __global__ __launch_bounds__(256) void k_prod_rows(const uint8_t *__restrict__ J
                                                    int64_t pitch, int p, int q, int dy, int dx,
                                                    uint32_t *__restrict__ sat)
 {
+    // 2048 columns per step: a thread forms and scans 8 consecutive
+    // products, the block scans the thread totals, and the row segment goes
+    // out through LDS so that the stores are coalesced
     __shared__ uint32_t wa[4];
+    __shared__ uint32_t seg[2048];
     int y = blockIdx.x;
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const bool rowok = y + dy >= 0 && y + dy < p;
@@ -377,20 +381,35 @@ __global__ __launch_bounds__(256) void k_prod_rows(const uint8_t *__restrict__ J
     if (t == 0)
         out[0] = 0u;
     uint32_t ca = 0;
-    for (int base = 0; base < q; base += 256) {
-        int x = base + t;
-        int v = x < q && rowok && x + dx >= 0 && x + dx < q ? ((int)rj[x] - 128) * ((int)ri[x + dx] - 128) : 0;
-        uint32_t a = wave_incl_scan((uint32_t)v, lane);
+    for (int base = 0; base < q; base += 2048) {
+        const int x0 = base + 8 * t;
+        uint32_t v[8], s = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int x = x0 + k;
+            const int pr = x < q && rowok && x + dx >= 0 && x + dx < q ? ((int)rj[x] - 128) * ((int)ri[x + dx] - 128)
+                                                                       : 0;
+            s += (uint32_t)pr;
+            v[k] = s;
+        }
+        const uint32_t incl = wave_incl_scan(s, lane);
         if (lane == 63)
-            wa[wv] = a;
+            wa[wv] = incl;
         __syncthreads();
-        uint32_t pa = ca;
+        uint32_t pre = ca + incl - s;
         for (int k = 0; k < wv; k++)
-            pa += wa[k];
-        if (x < q)
-            out[x + 1] = pa + a;
-        for (int k = 0; k < 4; k++)
-            ca += wa[k];
+            pre += wa[k];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            seg[8 * t + k] = pre + v[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int x = base + t + 256 * k;
+            if (x < q)
+                out[x + 1] = seg[t + 256 * k];
+        }
+        ca += wa[0] + wa[1] + wa[2] + wa[3];
         __syncthreads();
     }
 }
