@@ -2409,14 +2409,8 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
     }
 }
 
-// ============================================================== record reductions
-
 // ============================================================== final reduction
 
-// One block folds the per-block records of the final scan (and of the window
-// when it counts) into the answer, after the kernels that wrote them have
-// finished: the kernel boundary makes the records visible on every XCD
-// without a device-scope fence in each writing block.
 // One block folds the per-block records of the final scan (and of the window
 // when it counts) into the answer, after the kernels that wrote them have
 // finished: the kernel boundary makes the records visible on every XCD
