@@ -25,9 +25,18 @@
  *     keeps ownership.  Device pointers are borrowed for the duration of the
  *     call only.  The library owns every device buffer it allocates and frees
  *     them in zts_destroy / zts_image_unload.
- *   - NULL or out-of-range arguments return ZTS_E_ARG; m > rows or n > cols
- *     returns ZTS_E_SIZE; a template with zero variance returns
- *     ZTS_E_DEGENERATE.  Nothing is written to outputs on error.
+ *   - NULL or out-of-range arguments return ZTS_E_ARG; a template with zero
+ *     variance returns ZTS_E_DEGENERATE.  ZTS_E_SIZE: an image with more than
+ *     32767 rows or columns; a template with m > rows, n > cols or m*n > 16384;
+ *     or a template shape the chosen mode's kernels cannot stage in the
+ *     160 KB of LDS of one workgroup, refused before anything is launched:
+ *     ZTS_FULL stages (31 + m) * (256 + w) + (m + 14) * w bytes with
+ *     w = 16*ceil(n/16) (so m <= 537 for n <= 16, m <= 481 for n <= 32, and
+ *     n <= 2048 or so: 512x32 and 1x16384 are refused); ZTS_FULL_MFMA needs
+ *     n <= 128; the eliminating modes stage m * w bytes plus about 17 KB,
+ *     which refuses only single-column templates taller than 9198 rows.
+ *     Every shape up to 128x128 is accepted by every mode.
+ *     Nothing is written to outputs on error.
  *   - A `void* stream` is a hipStream_t (NULL = the context's own stream).
  *   - Every entry point is thread safe.  Synchronous calls on one context are
  *     serialised; submitted requests run concurrently on the context's worker

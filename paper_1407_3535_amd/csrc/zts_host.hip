@@ -784,6 +784,13 @@ void check_template_args(Image *im, const void *tpl, int m, int n, int64_t strid
         throw ZtsError{ZTS_E_SIZE};
 }
 
+void check_mode_shape(zts_mode mode, int m, int n)
+{
+    const bool ok = mode == ZTS_FULL ? full_fits(m, n) : mode == ZTS_FULL_MFMA ? n <= 128 : scan_fits(m, n);
+    if (!ok)
+        throw ZtsError{ZTS_E_SIZE};
+}
+
 // ------------------------------------------------------------------ one query
 
 namespace {
@@ -1753,6 +1760,7 @@ ZTS_API zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, 
             throw ZtsError{ZTS_E_ARG};
         if (m > im->rows || n > im->cols || (int64_t)m * n > 16384)
             throw ZtsError{ZTS_E_SIZE};
+        check_mode_shape(mode, m, n);
         zts_params pr;
         if (params)
             pr = *params;
@@ -1806,6 +1814,7 @@ ZTS_API zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int
         Ctx *c = &z->c;
         Image *im = find_image(c, image);
         check_template_args(im, tpl, m, n, stride);
+        check_mode_shape(mode, m, n);
         zts_params pr;
         if (params)
             pr = *params;
@@ -1837,6 +1846,7 @@ ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_
         Ctx *c = &z->c;
         Image *im = find_image(c, image);
         check_template_args(im, tpl_dev, m, n, stride);
+        check_mode_shape(mode, m, n);
         zts_params pr;
         if (params)
             pr = *params;
@@ -2011,6 +2021,7 @@ ZTS_API zts_status zts_debug_full_map(zts_ctx *z, int32_t image, const uint8_t *
         Ctx *c = &z->c;
         Image *im = find_image(c, image);
         check_template_args(im, tpl, m, n, stride);
+        check_mode_shape(ZTS_FULL, m, n);
         size_t L = (size_t)(im->rows - m + 1) * (im->cols - n + 1);
         DBuf dn, dd, dr;
         if (num_out)

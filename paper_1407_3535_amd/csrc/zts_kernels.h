@@ -192,6 +192,8 @@ hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, i
 
 int full_record_count(int Ly, int Lx);
 size_t full_lds_bytes(int m, int n);
+// Whether k_full can stage a template of m x n (LDS of one workgroup).
+bool full_fits(int m, int n);
 hipError_t launch_full(FullArgs a, hipStream_t s);
 
 // Scan 1 runs on int8 MFMA (k_centres_mfma) when the region a block's windows
@@ -206,6 +208,8 @@ int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);
 int members_record_count(int Gy, int Gx);
 hipError_t launch_members(MemArgs a, hipStream_t s);
+// Whether scan 1 (either form) and scan 2 can stage a template of m x n.
+bool scan_fits(int m, int n);
 hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int w, hipStream_t s);
 
 // Alg. 1: direct dot products per location, or, when cheaper

@@ -2544,21 +2544,71 @@ size_t full_lds_bytes(int m, int n)
     return (size_t)(4 * kFullR + m - 1) * (64 + n4w) * 4 + (size_t)(m + 2 * kFullR - 2) * n4w * 4;
 }
 
+// LDS of one workgroup on gfx950.  A kernel whose static LDS plus the
+// dynamic LDS a template shape needs exceeds it cannot run that shape: the
+// host rejects such shapes before launching (full_fits, scan_fits).
+constexpr size_t kLdsMax = 160 * 1024;
+
+// Static LDS of a kernel on the current device (queried once per kernel and
+// device; a failed query counts as the whole LDS, so nothing is launched).
+static size_t static_lds(const void *f)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> memo;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return kLdsMax;
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_pair(f, dev);
+    auto it = memo.find(key);
+    if (it != memo.end())
+        return it->second;
+    hipFuncAttributes at{};
+    size_t v = hipFuncGetAttributes(&at, f) == hipSuccess ? at.sharedSizeBytes : kLdsMax;
+    memo.emplace(key, v);
+    return v;
+}
+
+// Raises a kernel's dynamic-LDS allowance to `bytes` on the current device
+// when that is above 64 KB, once per (kernel, device, high-water mark), so a
+// repeated launch (including one under graph capture) makes no further call.
+static hipError_t allow_lds(const void *f, size_t bytes)
+{
+    if (bytes <= 64 * 1024)
+        return hipSuccess;
+    if (bytes + static_lds(f) > kLdsMax)
+        return hipErrorInvalidValue;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> raised;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t &hw = raised[std::make_pair(f, dev)];
+    if (bytes <= hw)
+        return hipSuccess;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        hw = bytes;
+    return e;
+}
+
+bool full_fits(int m, int n)
+{
+    return full_lds_bytes(m, n) + static_lds((const void *)k_full<kFullR>) <= kLdsMax;
+}
+
 hipError_t launch_full(FullArgs a, hipStream_t s)
 {
     a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
     dim3 grid(blocks_for(a.Lx, 256), blocks_for(a.Ly, 4 * kFullR));
     size_t lds = full_lds_bytes(a.m, a.n);
-    if (lds > 160 * 1024)
+    if (!full_fits(a.m, a.n))
         return hipErrorInvalidValue;
-    static size_t attr_bytes = 64 * 1024;
-    if (lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_full<kFullR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess)
-            return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = allow_lds((const void *)k_full<kFullR>, lds);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_full<kFullR>, grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }
@@ -2567,6 +2617,14 @@ static int centre_waves(int n)
 {
     int nch = ((((n + 3) / 4) + 3) / 4 * 4) / 4;
     return nch >= 4 ? 4 : (nch >= 2 ? 2 : 1);
+}
+
+// Dynamic LDS of k_centres: the template rows a block's R centre rows reach
+// (pad rows above and below) and the per-wave partial sums.
+static size_t centres_lds_bytes(int m, int n, int R, int pad)
+{
+    int n4w = (((n + 3) / 4) + 3) / 4 * 4;
+    return (size_t)(m + 2 * pad) * n4w * 4 + (size_t)centre_waves(n) * R * 64 * 4;
 }
 
 // Centre rows per wave: the most (8, 4, 2 or 1) whose zero-padded template
@@ -2710,7 +2768,13 @@ hipError_t launch_centres(ScanArgs a, hipStream_t s)
     int nw = centre_waves(a.n);
     int R = centre_rows(a.m, a.n, a.h);
     a.pad = (R - 1) * a.h;
-    size_t lds = (size_t)(a.m + 2 * a.pad) * a.n4w * 4 + (size_t)nw * R * 64 * 4;
+    size_t lds = centres_lds_bytes(a.m, a.n, R, a.pad);
+    const void *f = R == 8 ? (const void *)k_centres<8>
+                  : R == 4 ? (const void *)k_centres<4>
+                  : R == 2 ? (const void *)k_centres<2> : (const void *)k_centres<1>;
+    hipError_t e = allow_lds(f, lds);
+    if (e != hipSuccess)
+        return e;
     dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, R));
     switch (R) {
     case 8: hipLaunchKernelGGL(k_centres<8>, grid, dim3(64 * nw), lds, s, a); break;
@@ -2735,11 +2799,27 @@ hipError_t launch_window(WinArgs a, hipStream_t s)
 
 int members_record_count(int Gy, int Gx) { return (int)blocks_for((int64_t)Gy * Gx, kMemGroups); }
 
+static size_t members_lds_bytes(int m, int n) { return (size_t)m * ((n + 3) / 4) * 4; }
+
 hipError_t launch_members(MemArgs a, hipStream_t s)
 {
-    size_t lds = (size_t)a.m * ((a.n + 3) / 4) * 4;
+    size_t lds = members_lds_bytes(a.m, a.n);
+    hipError_t e = allow_lds((const void *)k_members, lds);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_members, dim3(members_record_count(a.Gy, a.Gx)), dim3(256), lds, s, a);
     return hipGetLastError();
+}
+
+bool scan_fits(int m, int n)
+{
+    if (members_lds_bytes(m, n) + static_lds((const void *)k_members) > kLdsMax)
+        return false;
+    // k_centres_mfma's shape search keeps within its own budget; the v_dot4
+    // form takes R = 1 (no pad rows) whenever a taller block would need more
+    // than 48 KB, so R = 1 bounds its need from above
+    size_t cl = std::max(centres_lds_bytes(m, n, 1, 0), (size_t)48 * 1024 + centres_lds_bytes(0, n, 8, 0));
+    return cl + static_lds((const void *)k_centres<1>) <= kLdsMax;
 }
 
 hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int w, hipStream_t s)

@@ -190,6 +190,10 @@ struct Ctx {
 Image *find_image(Ctx *c, int id);
 void fill_default(zts_params *p);
 void check_template_args(Image *im, const void *tpl, int m, int n, int64_t stride);
+// ZTS_E_SIZE when a mode's kernels cannot stage an m x n template in the LDS
+// of one workgroup (ZTS_FULL: k_full's rows; ZTS_FULL_MFMA: n <= 128; the
+// eliminating modes: scan 1 and scan 2).  Needs the context's device current.
+void check_mode_shape(zts_mode mode, int m, int n);
 
 // Per-(m, n) statistics of an image, built on `s` if missing (stream `s` is
 // then ordered after the build; other streams wait on st->ready).

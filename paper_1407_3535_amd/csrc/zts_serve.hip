@@ -173,8 +173,7 @@ std::unique_ptr<Request> make_request(Ctx *c, int image, const uint8_t *tpl, int
 {
     Image *im = find_image(c, image);
     check_template_args(im, tpl, m, n, stride);
-    if (mode == ZTS_FULL_MFMA && n > 128)
-        throw ZtsError{ZTS_E_SIZE};
+    check_mode_shape(mode, m, n);
     auto r = std::make_unique<Request>();
     r->image = image;
     r->im = im;

@@ -580,3 +580,48 @@ def test_opta_paper_parity(S, seed, blur_kind):
             exact += (g["y"], g["x"]) == (full["y"], full["x"])
     assert exact >= 4
     S.unload(i)
+
+
+# Images at the 32767-pixel dimension limit and templates of the 16384-pixel limit in four aspect
+# ratios.  `refuse` lists the modes whose kernels cannot stage the shape in one workgroup's LDS
+# (ZTS_FULL stages 31 + m image rows of the template's width, the eliminating modes the whole
+# template in 16-byte rows, ZTS_FULL_MFMA takes n <= 128): they return ZTS_E_SIZE before launching.
+MAX_CASES = [
+    ("wide image", 24, 32767, 8, 8, set()),
+    ("tall image", 32767, 24, 8, 8, set()),
+    ("128x128 template", 180, 200, 128, 128, set()),
+    ("1x16384 template", 4, 16400, 1, 16384, {"full", "full_mfma"}),
+    ("2048x8 template", 2100, 40, 2048, 8, {"full"}),
+    ("16384x1 template", 16400, 4, 16384, 1, {"full", "te_fixed", "egs", "opta"}),
+]
+
+
+@pytest.mark.parametrize("case", MAX_CASES, ids=[c[0] for c in MAX_CASES])
+def test_maximum_sizes(S, case):
+    """Every mode either returns the oracle's exact answer (counts covering every location, TE's
+    counts equal to the oracle's) or refuses the shape with ZTS_E_SIZE."""
+    name, p, q, m, n, refuse = case
+    print(f"maximum sizes: {name} ({p}x{q} image, {m}x{n} template)", flush=True)
+    img = spectral_image(p, q, 2.0, 77)
+    tpl, _ = cut_template(img, m, n, 78, 5.0)
+    full = O.full_search(img, tpl)
+    L = (p - m + 1) * (q - n + 1)
+    i = S.load(img)
+    for mode, kw in [("full", {}), ("full_mfma", {}), ("te_fixed", dict(group_h=3, group_w=3)), ("egs", {}),
+                     ("opta", dict(refine_radius=2))]:
+        print(f"  {mode}", flush=True)
+        if mode in refuse:
+            with pytest.raises(Z.ZtsError) as e:
+                S.search(i, tpl, mode, **kw)
+            assert e.value.code == -2, (name, mode)
+            continue
+        g = S.search(i, tpl, mode, **kw)
+        same_answer(g, full, f"{name} {mode}")
+        assert g["n_computed"] + g["n_eliminated"] == g["n_locations"] == L, (name, mode)
+        if mode == "te_fixed":
+            same_counts(g, O.te_search(img, tpl, 3, 3, decision=False, radius=-1), f"{name} te")
+    S.unload(i)
+    if name == "wide image":  # one column more than the limit
+        with pytest.raises(Z.ZtsError) as e:
+            S.load(np.zeros((1, 32768), np.uint8))
+        assert e.value.code == -2
