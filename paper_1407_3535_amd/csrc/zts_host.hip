@@ -786,6 +786,11 @@ void check_template_args(Image *im, const void *tpl, int m, int n, int64_t strid
 
 void check_mode_shape(zts_mode mode, int m, int n)
 {
+    // The LDS needs grow with m and n, so when 128 x 128 fits every mode, so
+    // does every shape within it: those skip the per-kernel queries below.
+    static const bool small_fit = full_fits(128, 128) && scan_fits(128, 128);
+    if (m <= 128 && n <= 128 && small_fit)
+        return;
     const bool ok = mode == ZTS_FULL ? full_fits(m, n) : mode == ZTS_FULL_MFMA ? n <= 128 : scan_fits(m, n);
     if (!ok)
         throw ZtsError{ZTS_E_SIZE};
