@@ -91,15 +91,16 @@ typedef enum {
  *                 original location through the triangle inequality on
  *                 angles (Eq. 2 with Prop. 4.3's blur correlation added), so
  *                 the result is still exact.
- *   ZTS_OPTA_PAPER the paper's own OptA search (sections IV-C, V, VI): the
- *                 same conditioned image and tables as ZTS_OPTA; transitive
- *                 elimination on the conditioned image finds its best location,
- *                 then the template is matched on the original image within
- *                 the cumulative blur radius (capped at 8, or refine_radius
- *                 when larger) of it.  Not exact: the answer is the
- *                 window's best.  n_centres, n_eliminated and n_survivors
- *                 are those of the search on the conditioned image;
- *                 n_computed adds the window's matches. */
+ *   ZTS_OPTA_PAPER the paper's own OptA (sections IV-C, V, VI): the image is
+ *                 conditioned by Alg. 3 as printed (each EGS run sees only
+ *                 the blurred image and its own auto-correlation, Prop. 3.2);
+ *                 transitive elimination on the conditioned image finds its
+ *                 best location, then the template is matched on the
+ *                 original image within the cumulative blur radius (capped
+ *                 at 8, or refine_radius when larger) of it.  Not exact: the
+ *                 answer is the window's best.  n_centres, n_eliminated and
+ *                 n_survivors are those of the search on the conditioned
+ *                 image; n_computed adds the window's matches. */
 typedef enum { ZTS_FULL = 0, ZTS_FULL_MFMA = 1, ZTS_TE_FIXED = 2, ZTS_EGS = 3, ZTS_OPTA = 4,
                ZTS_OPTA_PAPER = 5 } zts_mode;
 
@@ -137,6 +138,30 @@ typedef struct {
                                each, filling zts_result.phase_ms.  0 (default): a launch
                                sequence met before on the same slot replays a captured
                                HIP graph and phase_ms stays 0. */
+    int32_t egs_estimate;   /* retained-location estimate of Alg. 2:
+                               0 (default): Prop. 3.2 / Eq. 15, a member is retained when its
+                               auto-correlation is below sqrt(1 - rho_th^2);
+                               1: Prop. 3.1 / Eq. 7 with both roots of Eq. 8 at an assumed
+                               template-to-centre correlation rho_tc: retained unless the
+                               bound of Eq. 2 through the centre is at most rho_th */
+    double rho_tc;          /* the assumed rho_tc of egs_estimate 1, in (-1, 1), default 0 */
+    int32_t egs_shape;      /* group-size ascent of Alg. 2: 0 (default) square steps
+                               (h + dh, w + dw) as printed; 1: from the last accepted size the
+                               cheapest of (h + dh, w), (h, w + dw), (h + dh, w + dw) */
+    int32_t pad0;
+    double accept_xi;       /* Alg. 3's acceptance margin: a blurred iterate is kept when the
+                               estimated cost fell by more than accept_xi times its new cost
+                               (0.005, section V); in (-1, 1): a negative value keeps iterates
+                               whose cost rose by less than that fraction */
+    double rho_floor;       /* detection floor of the result (section VII's threshold):
+                               zts_result.above_floor reports rho >= rho_floor.  Default -2
+                               (off). */
+    int32_t floor_prune;    /* 1: the floor also prunes: scan 2 eliminates against
+                               max(best0, rho_floor).  The answer stays exact whenever the
+                               true maximum reaches the floor; otherwise above_floor = 0 and
+                               the answer is the best computed location (no exactness claim).
+                               0 (default): the floor only labels the result. */
+    int32_t pad1;
 } zts_params;
 
 /* Result of one search.  Valid only when status == ZTS_OK. */
@@ -168,7 +193,7 @@ typedef struct {
     float latency_ms;        /* submitted requests: submission to result ready (host clock) */
     float queue_ms;          /* submitted requests: submission to the start of its launch */
     int32_t batch_size;      /* templates in the launch that produced this result */
-    int32_t pad1;
+    int32_t above_floor;     /* 1 when rho >= params.rho_floor (always 1 with the floor off) */
 } zts_result;
 
 typedef struct {
@@ -188,9 +213,9 @@ typedef struct {
 typedef struct {
     int32_t mode, m, n, group_h, group_w, radius;
     int64_t cost;
-    int32_t n_egs;           /* trace of the final EGS run */
+    int32_t n_egs;           /* trace of the final EGS run (every evaluated candidate) */
     int32_t n_opta;          /* OptA iterations (entry 0 = the unblurred image) */
-    zts_egs_step egs[32];
+    zts_egs_step egs[64];
     zts_opta_step opta[16];
     float prepare_ms;        /* wall time of zts_prepare */
     int32_t pad0;
@@ -200,6 +225,17 @@ typedef struct {
 
 /* Fills *p with the paper's parameters. */
 ZTS_API void zts_params_default(zts_params *p);
+
+/* ZTS_OK when every field of *p is in range, else ZTS_E_ARG (host only, no
+ * device use).  Every entry point that takes parameters applies this check
+ * first: rho_th and rho_tc in (-1, 1); rho_max in (-1, 1]; margin finite and
+ * >= 0 (a negative margin could eliminate the true maximum); xi finite and
+ * >= 0; accept_xi in (-1, 1); group_h, group_w, h0, w0, h_max in
+ * [1, 32767]; dh, dw >= 0 and not both 0; blur_kind 0 or 1; sigma_step
+ * finite and > 0, sigma_max finite and >= 0 (blur_kind 1); max_iters in
+ * [0, 15]; refine_radius in [0, 255]; egs_estimate and egs_shape 0 or 1;
+ * rho_floor finite; floor_prune 0 or 1. */
+ZTS_API zts_status zts_params_check(const zts_params *p);
 
 /* Creates a context on params->device (NULL params: device 0, no budget). */
 ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out);
@@ -240,9 +276,10 @@ ZTS_API zts_status zts_prepare(zts_ctx *ctx, int32_t image, int32_t m, int32_t n
 /* Reports what zts_prepare decided (group size, EGS and OptA traces). */
 ZTS_API zts_status zts_prep_query(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode, zts_prep_info *out);
 
-/* Copies the conditioned image of a ZTS_OPTA preparation to host memory
- * (rows*cols bytes, pitch cols). */
-ZTS_API zts_status zts_prep_image(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, uint8_t *host_out);
+/* Copies the conditioned image of a ZTS_OPTA or ZTS_OPTA_PAPER preparation
+ * to host memory (rows*cols bytes, pitch cols). */
+ZTS_API zts_status zts_prep_image(zts_ctx *ctx, int32_t image, int32_t m, int32_t n, zts_mode mode,
+                                  uint8_t *host_out);
 
 /* ---- search ------------------------------------------------------------ */
 

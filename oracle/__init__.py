@@ -48,7 +48,9 @@ class OptaParams(C.Structure):
     _fields_ = [("rho_th", C.c_double), ("rho_max", C.c_double), ("xi", C.c_double),
                 ("h0", C.c_int32), ("w0", C.c_int32), ("dh", C.c_int32), ("dw", C.c_int32),
                 ("hmax", C.c_int32), ("blur_kind", C.c_int32), ("sigma_step", C.c_double),
-                ("sigma_max", C.c_double), ("max_iters", C.c_int32), ("nthreads", C.c_int32)]
+                ("sigma_max", C.c_double), ("max_iters", C.c_int32), ("nthreads", C.c_int32),
+                ("paper", C.c_int32), ("estimate", C.c_int32), ("rho_tc", C.c_double), ("shape", C.c_int32),
+                ("accept_xi", C.c_double)]
 
 
 class OptaStep(C.Structure):
@@ -113,7 +115,8 @@ def lib():
         L.orc_autocorr_lsa.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
                                        C.c_int, C.c_int, _i64p, _i64p, _i64p]
         L.orc_te_search.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int, C.c_int,
-                                    C.c_int64, C.c_int, C.c_int, C.c_double, C.c_int, _i64p, _i64p, _i64p,
+                                    C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _i64p, _i64p,
+                                    _i64p,
                                     C.c_int, C.c_void_p, C.POINTER(Result)]
         L.orc_blurcorr.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int,
                                    _i64p, _i64p, _i64p]
@@ -124,14 +127,15 @@ def lib():
                                  C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int64)]
         L.orc_egs.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                               C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
-                              C.c_void_p, C.c_int, C.POINTER(EgsStep), C.c_int, C.POINTER(C.c_int),
-                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64)]
+                              C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(EgsStep), C.c_int,
+                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int64)]
         L.orc_opta.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int,
                                C.POINTER(OptaParams), C.c_void_p, C.POINTER(OptaStep), C.c_int,
                                C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int64), C.POINTER(C.c_int)]
         L.orc_opta_search.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int,
-                                      C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double, _i64p, _i64p,
+                                      C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _i64p,
+                                      _i64p,
                                       _i64p, _i64p, _i64p, _i64p, C.c_int, C.c_void_p, C.POINTER(Result)]
         L.orc_window_search.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64, C.c_void_p, C.c_int, C.c_int,
                                         C.c_int64, C.c_int, C.c_int, C.c_int, C.POINTER(Result)]
@@ -249,7 +253,7 @@ def autocorr(img, m, n, h, w, method="lsa", nthreads=None):
     return num, dc, do
 
 
-def te_search(img, tpl, h, w, delta=1e-9, ac=None, decision=False, nthreads=None, radius=0):
+def te_search(img, tpl, h, w, delta=1e-9, ac=None, decision=False, nthreads=None, radius=0, floor=-2.0):
     img, tpl = _u8(img), _u8(tpl)
     p, q = img.shape
     m, n = tpl.shape
@@ -259,7 +263,7 @@ def te_search(img, tpl, h, w, delta=1e-9, ac=None, decision=False, nthreads=None
     dec = np.zeros(L, np.int8) if decision else None
     res = Result()
     _check(lib().orc_te_search(img.ctypes.data, p, q, img.strides[0], tpl.ctypes.data, m, n, tpl.strides[0],
-                               h, w, delta, radius, ac[0], ac[1], ac[2], nthreads or default_threads(),
+                               h, w, delta, float(floor), radius, ac[0], ac[1], ac[2], nthreads or default_threads(),
                                dec.ctypes.data if dec is not None else None, C.byref(res)))
     out = res.as_dict()
     if decision:
@@ -308,26 +312,34 @@ def revert(I, J, m, n, lam):
     return J2, passes.value, rev.value
 
 
-def egs(img, m, n, h0=3, w0=3, dh=2, dw=2, hmax=33, rho_th=0.8, xi=0.005, c=None, nthreads=None):
+def egs(img, m, n, h0=3, w0=3, dh=2, dw=2, hmax=33, rho_th=0.8, xi=0.005, c=None, estimate=0, rho_tc=0.0, shape=0,
+        nthreads=None):
+    """Alg. 2.  estimate 0: Prop. 3.2 / Eq. 15; 1: Prop. 3.1 (Eq. 7, both roots) at an assumed rho_tc.
+    shape 0: square steps as printed; 1: the cheapest of (h+dh, w), (h, w+dw), (h+dh, w+dw) each step.
+    c: blur correlation (num, dj, di) of the searched image against the original (the exact OptA count)."""
     img = _u8(img)
     p, q = img.shape
     trace = (EgsStep * 64)()
     nt, he, we, cost = C.c_int(), C.c_int(), C.c_int(), C.c_int64()
     cp = [a.ctypes.data for a in c] if c is not None else [None, None, None]
     _check(lib().orc_egs(img.ctypes.data, p, q, img.strides[0], m, n, h0, w0, dh, dw, hmax, rho_th, xi, *cp,
-                         nthreads or default_threads(), trace, 64, C.byref(nt), C.byref(he), C.byref(we),
-                         C.byref(cost)))
+                         estimate, float(rho_tc), shape, nthreads or default_threads(), trace, 64, C.byref(nt),
+                         C.byref(he), C.byref(we), C.byref(cost)))
     tr = [dict(h=s.h, w=s.w, cc=s.cc, cr=s.cr, ct=s.ct, accepted=bool(s.accepted)) for s in trace[:nt.value]]
     return {"h": he.value, "w": we.value, "cost": cost.value, "trace": tr}
 
 
 def opta_params(rho_th=0.8, rho_max=0.95, xi=0.005, h0=3, w0=3, dh=2, dw=2, hmax=33, blur_kind=1,
-                sigma_step=0.5, sigma_max=3.0, max_iters=6, nthreads=None):
+                sigma_step=0.5, sigma_max=3.0, max_iters=6, nthreads=None, paper=False, estimate=0, rho_tc=0.0,
+                shape=0, accept_xi=0.005):
     return OptaParams(rho_th, rho_max, xi, h0, w0, dh, dw, hmax, blur_kind, sigma_step, sigma_max, max_iters,
-                      nthreads or default_threads())
+                      nthreads or default_threads(), int(bool(paper)), estimate, float(rho_tc), shape,
+                      float(accept_xi))
 
 
 def opta(I, m, n, **kw):
+    """Alg. 3.  paper=False: the exact search's conditioning (EGS counts add each location's angle to its
+    original block); paper=True: Alg. 3 as printed (EGS on each blurred image alone, Prop. 3.2)."""
     I = _u8(I)
     p, q = I.shape
     pr = opta_params(**kw)
@@ -342,7 +354,7 @@ def opta(I, m, n, **kw):
     return {"image": out, "h": he.value, "w": we.value, "cost": cost.value, "radius": rad.value, "trace": tr}
 
 
-def opta_search(I, J, tpl, h, w, radius, delta=1e-9, decision=False, nthreads=None):
+def opta_search(I, J, tpl, h, w, radius, delta=1e-9, decision=False, nthreads=None, floor=-2.0):
     I, J, tpl = (np.ascontiguousarray(_u8(a)) for a in (I, J, tpl))
     p, q = I.shape
     m, n = tpl.shape
@@ -352,7 +364,7 @@ def opta_search(I, J, tpl, h, w, radius, delta=1e-9, decision=False, nthreads=No
     dec = np.zeros(L, np.int8) if decision else None
     res = Result()
     _check(lib().orc_opta_search(I.ctypes.data, J.ctypes.data, p, q, q, tpl.ctypes.data, m, n, n, h, w, radius,
-                                 delta, b[0], b[1], b[2], c[0], c[1], c[2], nthreads or default_threads(),
+                                 delta, float(floor), b[0], b[1], b[2], c[0], c[1], c[2], nthreads or default_threads(),
                                  dec.ctypes.data if dec is not None else None, C.byref(res)))
     out = res.as_dict()
     if decision:
@@ -372,13 +384,13 @@ def window_search(img, tpl, cy, cx, radius):
     return res.as_dict()
 
 
-def opta_paper_search(I, J, tpl, h, w, radius, delta=1e-9, nthreads=None):
+def opta_paper_search(I, J, tpl, h, w, radius, delta=1e-9, nthreads=None, floor=-2.0):
     """The paper's own OptA search (sections IV-C, V and VI, Alg. 3): transitive elimination on the
     conditioned image J with J's auto-correlation and the two-scan threshold, which finds J's best
     location exactly, then the localisation window on I around it.  Not exact on I when blurring moved or
     suppressed the peak (section V reports offsets of up to 4 pixels).  Counts: those of the search on J;
     n_computed adds the window's matches.  blurred = J's best (y, x, rho)."""
-    te = te_search(J, tpl, h, w, delta=delta, nthreads=nthreads)
+    te = te_search(J, tpl, h, w, delta=delta, nthreads=nthreads, floor=floor)
     win = window_search(I, tpl, te["y"], te["x"], radius)
     out = dict(win)
     out.update(n_centres=te["n_centres"], n_eliminated=te["n_eliminated"], n_survivors=te["n_survivors"],

@@ -640,11 +640,16 @@ static void eval_rows(void *vctx, int64_t lo, int64_t hi, int tid)
  * section IV-C used to raise the threshold; radius 0 is section VI as
  * printed).  Window locations count as computed.
  *
+ * floor_ (detection semantics, section VII's threshold; -2 = off): the
+ * elimination threshold is max(best0, floor_) - delta.  When the true maximum
+ * reaches the floor the answer is unchanged; otherwise every eliminated
+ * location lies below the floor and the answer is the best computed one.
+ *
  * ac_num/ac_dc/ac_do: auto-correlation of every location with its centre
  * (orc_autocorr_*).  decision (nullable, L entries): 1 centre, 3 window,
  * 2 survivor, 0 eliminated. */
 int orc_te_search(const uint8_t *img, int p, int q, int64_t is, const uint8_t *tpl, int m, int n, int64_t ts, int h,
-                  int w, double delta, int radius, const int64_t *ac_num, const int64_t *ac_dc,
+                  int w, double delta, double floor_, int radius, const int64_t *ac_num, const int64_t *ac_dc,
                   const int64_t *ac_do, int nthreads, int8_t *decision, orc_result *out)
 {
     if (!img || !tpl || !out || !ac_num || !ac_dc || !ac_do || h < 1 || w < 1)
@@ -704,7 +709,7 @@ int orc_te_search(const uint8_t *img, int p, int q, int64_t is, const uint8_t *t
                 best_update(&bt, l, rho[l]);
             }
     }
-    double thr = bt.rho - delta;
+    double thr = (floor_ > bt.rho ? floor_ : bt.rho) - delta;
     for (int64_t l = 0; l < L; l++) {
         if (dec[l] == 1 || dec[l] == 3)
             continue;
@@ -934,27 +939,50 @@ typedef struct {
     int32_t accepted;
 } orc_egs_step;
 
-/* Retained-location count for group size (h, w) (Eq. 15 via Prop. 3.2: a
- * member is retained when rho_co < sqrt(1 - rho_th^2)).  Members with a flat
- * block or a flat centre count as retained.
+/* Retained-location count for group size (h, w).
  *
- * With the blur-correlation arrays (c_*) given, every location o of the
- * searched image J (centres included) is counted with the angle to its
- * original block added: retained when cos(B + C) < thr, B = angle(centre,
- * o in J), C = angle(o in J, o in I), i.e. rho_B rho_C - s_B s_C < thr; flat
- * blocks in J or I count as retained. */
+ * estimate 0 (Eq. 15 via Prop. 3.2): a member is retained when
+ * rho_co < sqrt(1 - rho_th^2).  Members with a flat block or a flat centre
+ * count as retained.  With the blur-correlation arrays (c_*) given, every
+ * location o of the searched image J (centres included) is counted with the
+ * angle to its original block added: retained when cos(B + C) < thr,
+ * B = angle(centre, o in J), C = angle(o in J, o in I), i.e.
+ * rho_B rho_C - s_B s_C < thr; flat blocks in J or I count as retained.
+ *
+ * estimate 1 (Prop. 3.1, Eq. 7, both roots of Eq. 8): the template is
+ * assumed to correlate rho_tc with every group centre.  A member is
+ * eliminated when the bound of Eq. 2 through that centre is at most the
+ * threshold, rho_tc rho_co + s_tc s_co <= rho_th, which holds above the
+ * upper root and below the lower root of Eq. 8; otherwise it is retained.
+ * With blur arrays the angle C to the original block is added (every
+ * location, centres included, with B = 0 at a centre): the bound is
+ * cos(|A - B| - C), A = acos(rho_tc), and no bound (retained) when
+ * |A - B| <= C.  Flat blocks count as retained. */
 static int64_t retained_count(int Ly, int Lx, int h, int w, const int64_t *num, const int64_t *dc,
                               const int64_t *dov, const int64_t *c_num, const int64_t *c_dj, const int64_t *c_di,
-                              double thr)
+                              double rho_th, int estimate, double rho_tc)
 {
     int64_t L = (int64_t)Ly * Lx, cr = 0;
+    double thr = sqrt(1.0 - rho_th * rho_th);
+    double ra = rho_tc, sa = sqrt(1.0 - rho_tc * rho_tc);
     for (int64_t l = 0; l < L; l++) {
         int is_centre = orc_centre_of(Ly, Lx, h, w, l) == l;
         if (!c_num) {
             if (is_centre)
                 continue;
-            if (dc[l] == 0 || dov[l] == 0 || orc_rho(num[l], dc[l], dov[l]) < thr)
+            if (dc[l] == 0 || dov[l] == 0) {
                 cr++;
+                continue;
+            }
+            double rb = orc_rho(num[l], dc[l], dov[l]);
+            if (estimate == 0) {
+                if (rb < thr)
+                    cr++;
+            } else {
+                double sb = orc_sin(num[l], dc[l], dov[l]), ub;
+                if (!orc_ub_general(ra, sa, rb, sb, 1.0, 0.0, &ub) || ub > rho_th)
+                    cr++;
+            }
         } else {
             if (dc[l] == 0 || dov[l] == 0 || c_dj[l] == 0 || c_di[l] == 0) {
                 cr++;
@@ -962,29 +990,46 @@ static int64_t retained_count(int Ly, int Lx, int h, int w, const int64_t *num, 
             }
             double rb = orc_rho(num[l], dc[l], dov[l]), sb = orc_sin(num[l], dc[l], dov[l]);
             double rc = orc_rho(c_num[l], c_dj[l], c_di[l]), sc = orc_sin(c_num[l], c_dj[l], c_di[l]);
-            if (rb * rc - sb * sc < thr)
-                cr++;
+            if (estimate == 0) {
+                if (rb * rc - sb * sc < thr)
+                    cr++;
+            } else {
+                double ub;
+                if (!orc_ub_general(ra, sa, rb, sb, rc, sc, &ub) || ub > rho_th)
+                    cr++;
+            }
         }
     }
     return cr;
 }
 
-/* Greedy ascent over square-stepped group sizes (h0 + k dh, w0 + k dw),
- * capped at hmax and the grid: c_t = mn (c_c + c_r) with c_c the exact
- * number of groups; the next size is tried while the cost fell by more than
- * xi times the previous cost.  The start cost is mn*L (every location a
- * centre, group size 1x1).  Returns the last accepted size (1x1 if none). */
+/* Greedy descent of the total cost c_t = mn (c_c + c_r) of Eq. 16 over
+ * group sizes (Alg. 2, objective Eq. 17), c_c the exact number of groups.
+ * The start cost is mn*L (every location a centre, group size 1x1); the
+ * first candidate is (h0, w0).
+ *
+ * shape 0 (Alg. 2 as printed): the next candidate is (h + dh, w + dw), tried
+ * while the cost fell by more than xi times the previous cost.
+ * shape 1 (groups need not be square): from the last accepted (h, w) the
+ * candidates (h + dh, w), (h, w + dw) and (h + dh, w + dw) within the caps
+ * are all evaluated and the cheapest (first listed on ties) is accepted when
+ * it lowers the cost by more than xi times the previous cost.
+ *
+ * Sizes are capped at hmax and at the location grid.  Returns the last
+ * accepted size (1x1 if none); the trace lists every evaluated candidate,
+ * marking the ones accepted. */
 int orc_egs(const uint8_t *img, int p, int q, int64_t st, int m, int n, int h0, int w0, int dh, int dw, int hmax,
-            double rho_th, double xi, const int64_t *c_num, const int64_t *c_dj, const int64_t *c_di, int nthreads,
-            orc_egs_step *trace, int trace_cap, int *ntrace, int *he, int *we, int64_t *cost)
+            double rho_th, double xi, const int64_t *c_num, const int64_t *c_dj, const int64_t *c_di, int estimate,
+            double rho_tc, int shape, int nthreads, orc_egs_step *trace, int trace_cap, int *ntrace, int *he,
+            int *we, int64_t *cost)
 {
-    if (!img || m < 1 || n < 1 || h0 < 1 || w0 < 1 || dh < 0 || dw < 0 || (dh == 0 && dw == 0))
+    if (!img || m < 1 || n < 1 || h0 < 1 || w0 < 1 || dh < 0 || dw < 0 || (dh == 0 && dw == 0) ||
+        estimate < 0 || estimate > 1 || shape < 0 || shape > 1 || !(rho_tc > -1.0 && rho_tc < 1.0))
         return ORC_E_ARG;
     if (m > p || n > q)
         return ORC_E_SIZE;
     int Ly = p - m + 1, Lx = q - n + 1;
     int64_t L = (int64_t)Ly * Lx, mn = (int64_t)m * n;
-    double thr = sqrt(1.0 - rho_th * rho_th);
     int64_t *num = malloc(sizeof(int64_t) * L), *dc = malloc(sizeof(int64_t) * L),
             *dov = malloc(sizeof(int64_t) * L);
     if (!num || !dc || !dov) {
@@ -992,35 +1037,68 @@ int orc_egs(const uint8_t *img, int p, int q, int64_t st, int m, int n, int h0, 
         return ORC_E_NOMEM;
     }
     int64_t prev = mn * L;
-    int bh = 1, bw = 1, k = 0;
-    for (int h = h0, w = w0; h <= hmax && w <= hmax && h <= Ly && w <= Lx; h += dh, w += dw) {
-        int rc = orc_autocorr_lsa(img, p, q, st, m, n, h, w, nthreads, num, dc, dov);
-        if (rc) {
-            free(num); free(dc); free(dov);
-            return rc;
+    int bh = 1, bw = 1, k = 0, rc = ORC_OK;
+    for (int first = 1;; first = 0) {
+        int ch[3], cw[3], nc = 0;
+        if (first) {
+            ch[0] = h0; cw[0] = w0; nc = 1;
+        } else if (shape == 0) {
+            ch[0] = bh + dh; cw[0] = bw + dw; nc = 1;
+        } else {
+            int cand[3][2] = {{bh + dh, bw}, {bh, bw + dw}, {bh + dh, bw + dw}};
+            for (int i = 0; i < 3; i++) {
+                int dup = cand[i][0] == bh && cand[i][1] == bw;
+                for (int j = 0; j < nc; j++)
+                    dup |= ch[j] == cand[i][0] && cw[j] == cand[i][1];
+                if (!dup) {
+                    ch[nc] = cand[i][0]; cw[nc] = cand[i][1]; nc++;
+                }
+            }
         }
-        int64_t cc = orc_group_count(Ly, Lx, h, w);
-        int64_t cr = retained_count(Ly, Lx, h, w, num, dc, dov, c_num, c_dj, c_di, thr);
-        int64_t ct = mn * (cc + cr);
-        int accept = (double)(prev - ct) > xi * (double)prev;
-        if (trace && k < trace_cap) {
-            trace[k].h = h; trace[k].w = w; trace[k].cc = cc; trace[k].cr = cr; trace[k].ct = ct;
-            trace[k].accepted = accept;
+        int best = -1, best_h = 0, best_w = 0;
+        int64_t best_ct = 0;
+        for (int i = 0; i < nc; i++) {
+            int h = ch[i], w = cw[i];
+            if (h > hmax || w > hmax || h > Ly || w > Lx)
+                continue;
+            rc = orc_autocorr_lsa(img, p, q, st, m, n, h, w, nthreads, num, dc, dov);
+            if (rc)
+                goto done;
+            int64_t cc = orc_group_count(Ly, Lx, h, w);
+            int64_t cr = retained_count(Ly, Lx, h, w, num, dc, dov, c_num, c_dj, c_di, rho_th, estimate, rho_tc);
+            int64_t ct = mn * (cc + cr);
+            if (trace && k < trace_cap) {
+                trace[k].h = h; trace[k].w = w; trace[k].cc = cc; trace[k].cr = cr; trace[k].ct = ct;
+                trace[k].accepted = 0;
+            }
+            if (best < 0 || ct < best_ct) {
+                best = k;
+                best_ct = ct;
+                best_h = h;
+                best_w = w;
+            }
+            k++;
         }
-        k++;
-        if (!accept)
+        if (best < 0)
             break;
-        prev = ct;
-        bh = h;
-        bw = w;
+        if (!((double)(prev - best_ct) > xi * (double)prev))
+            break;
+        if (trace && best < trace_cap)
+            trace[best].accepted = 1;
+        bh = best_h;
+        bw = best_w;
+        prev = best_ct;
     }
-    if (ntrace)
-        *ntrace = k;
-    *he = bh;
-    *we = bw;
-    *cost = prev;
+done:
+    if (rc == ORC_OK) {
+        if (ntrace)
+            *ntrace = k;
+        *he = bh;
+        *we = bw;
+        *cost = prev;
+    }
     free(num); free(dc); free(dov);
-    return ORC_OK;
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1034,6 +1112,14 @@ typedef struct {
     double sigma_step, sigma_max;
     int32_t max_iters;
     int32_t nthreads;
+    int32_t paper;    /* 1: Alg. 3 as printed: EGS on each blurred image from its own
+                         auto-correlation (Prop. 3.2, no angle to the original) */
+    int32_t estimate; /* EGS retention estimate (orc_egs) */
+    double rho_tc;
+    int32_t shape;    /* EGS group-size ascent (orc_egs) */
+    double accept_xi; /* Alg. 3's acceptance margin: an iterate is kept when the cost fell by
+                         more than accept_xi times the new cost (0.005 in the paper; a negative
+                         value keeps iterates whose cost rose by less than that fraction) */
 } orc_opta_params;
 
 typedef struct {
@@ -1044,10 +1130,18 @@ typedef struct {
 
 /* Iterate: blur the last accepted image (Eq. 18), copy back every block
  * whose blur correlation falls below lambda (Eq. 28) until none does, and
- * re-run EGS warm-started at the current group size with the angle to the
- * original added to each member's bound.  The iterate is accepted when the
- * estimated cost fell by more than xi times the new cost; otherwise, or when
- * the blur schedule ends, stop and return the last accepted image.
+ * re-run EGS warm-started at the current group size.  The iterate is
+ * accepted when the estimated cost fell by more than accept_xi times the new
+ * cost;
+ * otherwise, or when the blur schedule ends, stop and return the last
+ * accepted image.
+ *
+ * EGS counts: with paper = 0 (the exact search's conditioning) every
+ * location is counted with the angle to its original block added (the
+ * search bounds original locations through the blurred ones); with
+ * paper = 1 each EGS call sees only the blurred image and its own
+ * auto-correlation, as Alg. 3 prints it (the paper's search runs on the
+ * blurred image).
  *
  * Blur schedule: kind 0 applies the paper's W every iteration; kind 1
  * applies a Gaussian of standard deviation sigma_step*sqrt(2k-1) at
@@ -1074,11 +1168,14 @@ int orc_opta(const uint8_t *I, int p, int q, int64_t st, int m, int n, const orc
         memcpy(Ic + (int64_t)y * q, I + (int64_t)y * st, q);
         memcpy(cur + (int64_t)y * q, I + (int64_t)y * st, q);
     }
-    orc_blurcorr(Ic, cur, p, q, q, m, n, cn, cj, ci);
+    const int with_c = !pr->paper;
+    if (with_c)
+        orc_blurcorr(Ic, cur, p, q, q, m, n, cn, cj, ci);
     int h, w, nt, rad = 0;
     int64_t c_prev;
-    int rc = orc_egs(cur, p, q, q, m, n, pr->h0, pr->w0, pr->dh, pr->dw, pr->hmax, pr->rho_th, pr->xi, cn, cj, ci,
-                     pr->nthreads, NULL, 0, &nt, &h, &w, &c_prev);
+    int rc = orc_egs(cur, p, q, q, m, n, pr->h0, pr->w0, pr->dh, pr->dw, pr->hmax, pr->rho_th, pr->xi,
+                     with_c ? cn : NULL, with_c ? cj : NULL, with_c ? ci : NULL, pr->estimate, pr->rho_tc,
+                     pr->shape, pr->nthreads, NULL, 0, &nt, &h, &w, &c_prev);
     int k = 0;
     if (trace && cap > 0) {
         memset(&trace[0], 0, sizeof trace[0]);
@@ -1110,16 +1207,19 @@ int orc_opta(const uint8_t *I, int p, int q, int64_t st, int m, int n, const orc
         rc = orc_revert(Ic, J, p, q, q, m, n, lambda, &passes, &reverted);
         if (rc)
             break;
-        rc = orc_blurcorr(Ic, J, p, q, q, m, n, cn, cj, ci);
-        if (rc)
-            break;
+        if (with_c) {
+            rc = orc_blurcorr(Ic, J, p, q, q, m, n, cn, cj, ci);
+            if (rc)
+                break;
+        }
         int h2, w2;
         int64_t c_new;
-        rc = orc_egs(J, p, q, q, m, n, h, w, pr->dh, pr->dw, pr->hmax, pr->rho_th, pr->xi, cn, cj, ci, pr->nthreads,
+        rc = orc_egs(J, p, q, q, m, n, h, w, pr->dh, pr->dw, pr->hmax, pr->rho_th, pr->xi, with_c ? cn : NULL,
+                     with_c ? cj : NULL, with_c ? ci : NULL, pr->estimate, pr->rho_tc, pr->shape, pr->nthreads,
                      NULL, 0, &nt, &h2, &w2, &c_new);
         if (rc)
             break;
-        int accept = (double)(c_prev - c_new) > pr->xi * (double)c_new;
+        int accept = (double)(c_prev - c_new) > pr->accept_xi * (double)c_new;
         if (trace && k < cap) {
             trace[k].k = it; trace[k].d = d; trace[k].sigma = sigma; trace[k].passes = passes;
             trace[k].reverted = reverted; trace[k].h = h2; trace[k].w = w2; trace[k].cost = c_new;
@@ -1163,11 +1263,13 @@ int orc_opta(const uint8_t *I, int p, int q, int64_t st, int m, int n, const orc
  * whose bound falls strictly below threshold - delta are skipped; the rest
  * are matched on I, so the answer is the exact full-search answer.
  *
+ * floor_: as in orc_te_search.
  * b_*: auto-correlation of J (every location with its J-group centre).
  * c_*: blur correlation (o in J vs o in I).  decision: 1 window, 2 survivor,
  * 0 eliminated.  n_centres counts the blurred centres matched. */
 int orc_opta_search(const uint8_t *I, const uint8_t *J, int p, int q, int64_t st, const uint8_t *tpl, int m, int n,
-                    int64_t ts, int h, int w, int radius, double delta, const int64_t *b_num, const int64_t *b_dc,
+                    int64_t ts, int h, int w, int radius, double delta, double floor_, const int64_t *b_num,
+                    const int64_t *b_dc,
                     const int64_t *b_do, const int64_t *c_num, const int64_t *c_dj, const int64_t *c_di,
                     int nthreads, int8_t *decision, orc_result *out)
 {
@@ -1230,7 +1332,7 @@ int orc_opta_search(const uint8_t *I, const uint8_t *J, int p, int q, int64_t st
             dec[l] = 1;
             best_update(&bw, l, rhoI[l]);
         }
-    double thr = bw.rho - delta;
+    double thr = (floor_ > bw.rho ? floor_ : bw.rho) - delta;
 
     /* scan 2 over every other original location */
     int64_t n_surv = 0, n_elim = 0, n_win = 0;

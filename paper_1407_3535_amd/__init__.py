@@ -35,7 +35,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template"
           -5: "HBM budget exhausted", -6: "not ready", -7: "busy", -8: "timed out", -9: "cancelled",
           -10: "device error", -11: "out of memory", -12: "not prepared"}
 
-EXPORTS = ["zts_params_default", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
+EXPORTS = ["zts_params_default", "zts_params_check", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
            "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
            "zts_search", "zts_search_device", "zts_search_batch", "zts_tune_batch", "zts_submit", "zts_submit_batch", "zts_poll",
            "zts_wait", "zts_cancel", "zts_pending", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
@@ -62,7 +62,9 @@ class Params(C.Structure):
                 ("group_h", C.c_int32), ("group_w", C.c_int32), ("h0", C.c_int32), ("w0", C.c_int32),
                 ("dh", C.c_int32), ("dw", C.c_int32), ("h_max", C.c_int32), ("blur_kind", C.c_int32),
                 ("sigma_step", C.c_double), ("sigma_max", C.c_double), ("max_iters", C.c_int32),
-                ("refine_radius", C.c_int32), ("timing", C.c_int32)]
+                ("refine_radius", C.c_int32), ("timing", C.c_int32), ("egs_estimate", C.c_int32),
+                ("rho_tc", C.c_double), ("egs_shape", C.c_int32), ("pad0", C.c_int32), ("accept_xi", C.c_double),
+                ("rho_floor", C.c_double), ("floor_prune", C.c_int32), ("pad1", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -72,7 +74,8 @@ class Result(C.Structure):
                 ("n_survivors", C.c_int64), ("n_computed", C.c_int64), ("group_h", C.c_int32),
                 ("group_w", C.c_int32), ("best0", C.c_double), ("best0_y", C.c_int32), ("best0_x", C.c_int32),
                 ("device_ms", C.c_float), ("status", C.c_int32), ("phase_ms", C.c_float * 4),
-                ("latency_ms", C.c_float), ("queue_ms", C.c_float), ("batch_size", C.c_int32), ("pad1", C.c_int32)]
+                ("latency_ms", C.c_float), ("queue_ms", C.c_float), ("batch_size", C.c_int32),
+                ("above_floor", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in Result._names}
@@ -103,7 +106,7 @@ class OptaStep(C.Structure):
 class PrepInfo(C.Structure):
     _fields_ = [("mode", C.c_int32), ("m", C.c_int32), ("n", C.c_int32), ("group_h", C.c_int32),
                 ("group_w", C.c_int32), ("radius", C.c_int32), ("cost", C.c_int64), ("n_egs", C.c_int32),
-                ("n_opta", C.c_int32), ("egs", EgsStep * 32), ("opta", OptaStep * 16), ("prepare_ms", C.c_float),
+                ("n_opta", C.c_int32), ("egs", EgsStep * 64), ("opta", OptaStep * 16), ("prepare_ms", C.c_float),
                 ("pad0", C.c_int32)]
 
     def as_dict(self):
@@ -128,6 +131,7 @@ def lib():
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.zts_params_default.argtypes = [C.POINTER(Params)]
         L.zts_params_default.restype = None
+        L.zts_params_check.argtypes = [C.POINTER(Params)]
         L.zts_create.argtypes = [C.POINTER(CtxParams), C.POINTER(vp)]
         L.zts_destroy.argtypes = [vp]
         L.zts_destroy.restype = None
@@ -138,7 +142,7 @@ def lib():
         L.zts_image_unload.argtypes = [vp, i32]
         L.zts_prepare.argtypes = [vp, i32, i32, i32, i32, C.POINTER(Params), vp]
         L.zts_prep_query.argtypes = [vp, i32, i32, i32, i32, C.POINTER(PrepInfo)]
-        L.zts_prep_image.argtypes = [vp, i32, i32, i32, vp]
+        L.zts_prep_image.argtypes = [vp, i32, i32, i32, i32, vp]
         L.zts_search.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(Result), vp]
         L.zts_search_device.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), vp,
                                         C.POINTER(Result)]
@@ -183,6 +187,11 @@ def zts_params_default(**overrides) -> Params:
     for k, v in overrides.items():
         setattr(p, k, v)
     return p
+
+
+def zts_params_check(params: Params) -> int:
+    """ZTS_OK (0) when every field is in range, else ZTS_E_ARG (-1); host only."""
+    return lib().zts_params_check(C.byref(params))
 
 
 def zts_status_str(code: int) -> str:
@@ -247,9 +256,9 @@ def zts_prep_query(ctx, image: int, m: int, n: int, mode) -> dict:
     return info.as_dict()
 
 
-def zts_prep_image(ctx, image: int, m: int, n: int, shape) -> np.ndarray:
+def zts_prep_image(ctx, image: int, m: int, n: int, shape, mode="opta") -> np.ndarray:
     out = np.zeros(shape, np.uint8)
-    _check(lib().zts_prep_image(ctx, image, m, n, out.ctypes.data), "zts_prep_image")
+    _check(lib().zts_prep_image(ctx, image, m, n, _mode(mode), out.ctypes.data), "zts_prep_image")
     return out
 
 
@@ -467,5 +476,5 @@ class Searcher:
     def pending(self):
         return zts_pending(self.ctx)
 
-    def prep_image(self, image, m, n):
-        return zts_prep_image(self.ctx, image, m, n, self.shapes[image])
+    def prep_image(self, image, m, n, mode="opta"):
+        return zts_prep_image(self.ctx, image, m, n, self.shapes[image], mode)

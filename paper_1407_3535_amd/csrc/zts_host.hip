@@ -249,6 +249,48 @@ void fill_default(zts_params *p)
     p->max_iters = 6;
     p->refine_radius = 0;
     p->timing = 0;
+    p->egs_estimate = 0;
+    p->rho_tc = 0.0;
+    p->egs_shape = 0;
+    p->pad0 = 0;
+    p->accept_xi = 0.005;
+    p->rho_floor = -2.0;
+    p->floor_prune = 0;
+    p->pad1 = 0;
+}
+
+zts_status params_status(const zts_params &p)
+{
+    auto fin = [](double v) { return std::isfinite(v); };
+    auto in_dim = [](int v) { return v >= 1 && v <= 32767; };
+    bool ok = fin(p.rho_th) && p.rho_th > -1.0 && p.rho_th < 1.0;
+    ok = ok && fin(p.rho_max) && p.rho_max > -1.0 && p.rho_max <= 1.0;
+    ok = ok && fin(p.margin) && p.margin >= 0.0;
+    ok = ok && fin(p.xi) && p.xi >= 0.0;
+    ok = ok && fin(p.accept_xi) && p.accept_xi > -1.0 && p.accept_xi < 1.0;
+    ok = ok && in_dim(p.group_h) && in_dim(p.group_w) && in_dim(p.h0) && in_dim(p.w0) && in_dim(p.h_max);
+    ok = ok && p.dh >= 0 && p.dw >= 0 && (p.dh > 0 || p.dw > 0) && p.dh <= 32767 && p.dw <= 32767;
+    ok = ok && (p.blur_kind == 0 || p.blur_kind == 1);
+    if (p.blur_kind == 1)
+        ok = ok && fin(p.sigma_step) && p.sigma_step > 0.0 && fin(p.sigma_max) && p.sigma_max >= 0.0;
+    ok = ok && p.max_iters >= 0 && p.max_iters <= 15;
+    ok = ok && p.refine_radius >= 0 && p.refine_radius <= 255;
+    ok = ok && (p.egs_estimate == 0 || p.egs_estimate == 1) && (p.egs_shape == 0 || p.egs_shape == 1);
+    ok = ok && fin(p.rho_tc) && p.rho_tc > -1.0 && p.rho_tc < 1.0;
+    ok = ok && fin(p.rho_floor) && (p.floor_prune == 0 || p.floor_prune == 1);
+    return ok ? ZTS_OK : ZTS_E_ARG;
+}
+
+zts_params params_or_default(const zts_params *params)
+{
+    zts_params pr;
+    if (params)
+        pr = *params;
+    else
+        fill_default(&pr);
+    if (params_status(pr) != ZTS_OK)
+        throw ZtsError{ZTS_E_ARG};
+    return pr;
 }
 
 // Gaussian weights on [-d, d], d = ceil(3 sigma), quantised to integers that
@@ -399,10 +441,11 @@ struct Searched {
     const int2 *stat;
 };
 
-// Retained-member count of Alg. 2 / Eq. 15 for group size (h, w) on image S.
-// With blur data (theta_c, x_c, statI) every location counts with the angle
-// to its original block added.
-int64_t retained_count(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, int h, int w, double rho_th,
+// Retained-member count of Alg. 2 for group size (h, w) on image S: Eq. 15
+// (Prop. 3.2) or, with pr.egs_estimate = 1, Prop. 3.1 at the assumed rho_tc
+// (both roots).  With blur data (theta_c, x_c, statI) every location counts
+// with the angle to its original block added.
+int64_t retained_count(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, int h, int w, const zts_params &pr,
                        const float *theta_c, const int32_t *x_c, const int2 *statI)
 {
     AcArgs a;
@@ -417,7 +460,7 @@ int64_t retained_count(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, 
     a.Lx = Lx;
     a.h = h;
     a.w = w;
-    a.thr = std::sqrt(1.0 - rho_th * rho_th);
+    a.thr = std::sqrt(1.0 - pr.rho_th * pr.rho_th);
     const float eps = 1e-5f;
     a.thr_lo = (float)a.thr - eps;
     a.thr_hi = (float)a.thr + eps;
@@ -429,46 +472,80 @@ int64_t retained_count(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, 
     a.ahi_hi = ah + eps;
     a.theta_c = theta_c;
     a.x_c = x_c;
-    a.mode = theta_c ? AC_COUNT_BLUR : AC_COUNT;
+    a.rho_th = pr.rho_th;
+    a.ra = pr.rho_tc;
+    a.sa = std::sqrt(1.0 - pr.rho_tc * pr.rho_tc);
+    if (pr.egs_estimate == 1)
+        a.mode = theta_c ? AC_COUNT31_BLUR : AC_COUNT31;
+    else
+        a.mode = theta_c ? AC_COUNT_BLUR : AC_COUNT;
     zero_counter(c);
     a.counter = c->counter.as<unsigned long long>();
     hip_check(launch_autocorr(a, psat_for(c, Ly, Lx, m, n), c->stream));
     return (int64_t)read_counter(c);
 }
 
-// Alg. 2: greedy ascent over group sizes.  Fills trace/ntrace (up to 32).
+// Alg. 2: greedy descent of the estimated cost over group sizes, starting at
+// (h0, w0): square steps (egs_shape 0) or the cheapest of the three
+// neighbouring sizes (egs_shape 1).  Fills trace/ntrace (up to 64 evaluated
+// candidates).
 void run_egs(Ctx *c, const Searched &S, int m, int n, int Ly, int Lx, const zts_params &pr, int h0, int w0,
              const float *theta_c, const int32_t *x_c, const int2 *statI, int &he, int &we, int64_t &cost,
              zts_egs_step *trace, int &ntrace)
 {
+    const int kTrace = 64;
     int64_t mn = (int64_t)m * n;
     int64_t prev = mn * (int64_t)Ly * Lx;
     int bh = 1, bw = 1, k = 0;
     if (pr.dh < 0 || pr.dw < 0 || (pr.dh == 0 && pr.dw == 0) || h0 < 1 || w0 < 1)
         throw ZtsError{ZTS_E_ARG};
-    for (int h = h0, w = w0; h <= pr.h_max && w <= pr.h_max && h <= Ly && w <= Lx; h += pr.dh, w += pr.dw) {
-        int64_t cc = (int64_t)((Ly + h - 1) / h) * ((Lx + w - 1) / w);
-        int64_t cr = retained_count(c, S, m, n, Ly, Lx, h, w, pr.rho_th, theta_c, x_c, statI);
-        int64_t ct = mn * (cc + cr);
-        bool accept = (double)(prev - ct) > pr.xi * (double)prev;
-        if (trace && k < 32) {
-            zts_egs_step &s = trace[k];
-            std::memset(&s, 0, sizeof s);
-            s.h = h;
-            s.w = w;
-            s.cc = cc;
-            s.cr = cr;
-            s.ct = ct;
-            s.accepted = accept;
+    for (bool first = true;; first = false) {
+        int ch[3], cw[3], nc = 0;
+        if (first) {
+            ch[0] = h0, cw[0] = w0, nc = 1;
+        } else if (pr.egs_shape == 0) {
+            ch[0] = bh + pr.dh, cw[0] = bw + pr.dw, nc = 1;
+        } else {
+            const int cand[3][2] = {{bh + pr.dh, bw}, {bh, bw + pr.dw}, {bh + pr.dh, bw + pr.dw}};
+            for (int i = 0; i < 3; i++) {
+                bool dup = cand[i][0] == bh && cand[i][1] == bw;
+                for (int j = 0; j < nc; j++)
+                    dup = dup || (ch[j] == cand[i][0] && cw[j] == cand[i][1]);
+                if (!dup)
+                    ch[nc] = cand[i][0], cw[nc] = cand[i][1], nc++;
+            }
         }
-        k++;
-        if (!accept)
+        int best = -1, best_h = 0, best_w = 0;
+        int64_t best_ct = 0;
+        for (int i = 0; i < nc; i++) {
+            const int h = ch[i], w = cw[i];
+            if (h > pr.h_max || w > pr.h_max || h > Ly || w > Lx)
+                continue;
+            int64_t cc = (int64_t)((Ly + h - 1) / h) * ((Lx + w - 1) / w);
+            int64_t cr = retained_count(c, S, m, n, Ly, Lx, h, w, pr, theta_c, x_c, statI);
+            int64_t ct = mn * (cc + cr);
+            if (trace && k < kTrace) {
+                zts_egs_step &s = trace[k];
+                std::memset(&s, 0, sizeof s);
+                s.h = h;
+                s.w = w;
+                s.cc = cc;
+                s.cr = cr;
+                s.ct = ct;
+            }
+            if (best < 0 || ct < best_ct)
+                best = k, best_ct = ct, best_h = h, best_w = w;
+            k++;
+        }
+        if (best < 0 || !((double)(prev - best_ct) > pr.xi * (double)prev))
             break;
-        prev = ct;
-        bh = h;
-        bw = w;
+        if (trace && best < kTrace)
+            trace[best].accepted = 1;
+        prev = best_ct;
+        bh = best_h;
+        bw = best_w;
     }
-    ntrace = std::min(k, 32);
+    ntrace = std::min(k, kTrace);
     he = bh;
     we = bw;
     cost = prev;
@@ -518,13 +595,6 @@ void build_tables(Ctx *c, Prepared &P, const Searched &S, int Ly, int Lx)
     g.opta = P.mode == ZTS_OPTA;
     g.gsum = P.gsum.as<GroupSum>();
     hip_check(launch_gsum(g, c->stream));
-    if (P.mode == ZTS_OPTA) {  // the paper's search bounds with the conditioned image's angles only
-        dalloc(c, P.gsum_b, sizeof(GroupSum) * (size_t)P.Gy * P.Gx);
-        g.theta_c = nullptr;
-        g.opta = 0;
-        g.gsum = P.gsum_b.as<GroupSum>();
-        hip_check(launch_gsum(g, c->stream));
-    }
 }
 
 // Blur correlation of every block of J against the same block of I.
@@ -566,9 +636,14 @@ struct Cand {
 };
 
 // Alg. 3.  The conditioned image ends in P.J (with its running sums and
-// statistics), its blur angles in P.theta_c / P.x_c.
+// statistics), its blur angles in P.theta_c / P.x_c.  For ZTS_OPTA every EGS
+// count adds each location's angle to its original block (the search bounds
+// original locations through blurred ones); for ZTS_OPTA_PAPER each EGS run
+// sees only the blurred image, as Alg. 3 prints it, and no blur angles are
+// kept.
 void run_opta(Ctx *c, Image *im, Prepared &P, const zts_params &pr, const int2 *statI)
 {
+    const bool with_c = P.mode == ZTS_OPTA;
     int p = im->rows, q = im->cols, m = P.m, n = P.n;
     int Ly = p - m + 1, Lx = q - n + 1;
     size_t L = (size_t)Ly * Lx;
@@ -578,16 +653,20 @@ void run_opta(Ctx *c, Image *im, Prepared &P, const zts_params &pr, const int2 *
     auto setup = [&](Cand &k) {
         alloc_image(c, k.J, p, pitch);
         dalloc(c, k.Jstat, sizeof(int2) * L);
-        dalloc(c, k.theta_c, sizeof(float) * L);
-        dalloc(c, k.x_c, sizeof(int32_t) * L);
+        if (with_c) {
+            dalloc(c, k.theta_c, sizeof(float) * L);
+            dalloc(c, k.x_c, sizeof(int32_t) * L);
+        }
     };
     auto stats_of = [&](Cand &k) {
         build_sat(c, k.J.as<uint8_t>(), pitch, p, q, k.Jsat);
         hip_check(launch_stats(k.Jsat.as<uint2>(), q, Ly, Lx, m, n, k.Jstat.as<int2>(), c->stream));
     };
     auto build_c = [&](Cand &k) {
-        blurcorr(c, k.J.as<uint8_t>(), k.Jstat.as<int2>(), im->img.as<uint8_t>(), statI, pitch, m, n, Ly, Lx,
-                 BC_BUILD, lambda, nullptr, k.theta_c.as<float>(), k.x_c.as<int32_t>(), nullptr, nullptr, nullptr);
+        if (with_c)
+            blurcorr(c, k.J.as<uint8_t>(), k.Jstat.as<int2>(), im->img.as<uint8_t>(), statI, pitch, m, n, Ly, Lx,
+                     BC_BUILD, lambda, nullptr, k.theta_c.as<float>(), k.x_c.as<int32_t>(), nullptr, nullptr,
+                     nullptr);
     };
     setup(cur);
     setup(nxt);
@@ -599,10 +678,10 @@ void run_opta(Ctx *c, Image *im, Prepared &P, const zts_params &pr, const int2 *
     build_c(cur);
     int h, w, nt;
     int64_t cost;
-    zts_egs_step tr[32];
+    zts_egs_step tr[64];
     Searched S{cur.J.as<uint8_t>(), pitch, cur.Jstat.as<int2>()};
-    run_egs(c, S, m, n, Ly, Lx, pr, pr.h0, pr.w0, cur.theta_c.as<float>(), cur.x_c.as<int32_t>(), statI, h, w, cost,
-            tr, nt);
+    run_egs(c, S, m, n, Ly, Lx, pr, pr.h0, pr.w0, cur.theta_c.as<float>(), cur.x_c.as<int32_t>(),
+            with_c ? statI : nullptr, h, w, cost, tr, nt);
     zts_prep_info &info = P.info;
     info.n_opta = 1;
     std::memset(&info.opta[0], 0, sizeof info.opta[0]);
@@ -649,9 +728,9 @@ void run_opta(Ctx *c, Image *im, Prepared &P, const zts_params &pr, const int2 *
         int h2, w2;
         int64_t c2;
         Searched S2{nxt.J.as<uint8_t>(), pitch, nxt.Jstat.as<int2>()};
-        run_egs(c, S2, m, n, Ly, Lx, pr, h, w, nxt.theta_c.as<float>(), nxt.x_c.as<int32_t>(), statI, h2, w2, c2, tr,
-                nt);
-        bool accept = (double)(cost - c2) > pr.xi * (double)c2;
+        run_egs(c, S2, m, n, Ly, Lx, pr, h, w, nxt.theta_c.as<float>(), nxt.x_c.as<int32_t>(),
+                with_c ? statI : nullptr, h2, w2, c2, tr, nt);
+        bool accept = (double)(cost - c2) > pr.accept_xi * (double)c2;
         if (info.n_opta < 16) {
             zts_opta_step &s = info.opta[info.n_opta++];
             std::memset(&s, 0, sizeof s);
@@ -700,11 +779,12 @@ bool same_prep_params(const Prepared &P, zts_mode mode, const zts_params &a)
     if (mode == ZTS_TE_FIXED)
         return a.group_h == b.group_h && a.group_w == b.group_w;
     bool egs = a.rho_th == b.rho_th && a.xi == b.xi && a.h0 == b.h0 && a.w0 == b.w0 && a.dh == b.dh &&
-               a.dw == b.dw && a.h_max == b.h_max;
+               a.dw == b.dw && a.h_max == b.h_max && a.egs_estimate == b.egs_estimate &&
+               a.egs_shape == b.egs_shape && (a.egs_estimate == 0 || a.rho_tc == b.rho_tc);
     if (mode == ZTS_EGS)
         return egs;
     return egs && a.rho_max == b.rho_max && a.blur_kind == b.blur_kind && a.sigma_step == b.sigma_step &&
-           a.sigma_max == b.sigma_max && a.max_iters == b.max_iters;
+           a.sigma_max == b.sigma_max && a.max_iters == b.max_iters && a.accept_xi == b.accept_xi;
 }
 
 // Holds a pin for the lifetime of a scope.
@@ -752,7 +832,7 @@ Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_para
                 P->info.egs, nt);
         P->info.n_egs = nt;
         build_tables(c, *P, SI, Ly, Lx);
-    } else if (mode == ZTS_OPTA) {
+    } else if (mode == ZTS_OPTA || mode == ZTS_OPTA_PAPER) {
         run_opta(c, im, *P, pr, statI);
         Searched SJ{P->J.as<uint8_t>(), im->pitch, P->Jstat.as<int2>()};
         build_tables(c, *P, SJ, Ly, Lx);
@@ -836,7 +916,7 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
         if (mode != ZTS_FULL) {
             if (want_dec && mode == ZTS_OPTA_PAPER)  // no decision map for the paper's search
                 throw ZtsError{ZTS_E_ARG};
-            q.P = prepare(c, im, m, n, mode == ZTS_OPTA_PAPER ? ZTS_OPTA : mode, pr);
+            q.P = prepare(c, im, m, n, mode, pr);
             q.P->pins++;
             q.P->last_use = ++c->clock;
         }
@@ -1016,7 +1096,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.Gx = P->Gx;
     ma.g_x = S.gnum.as<int32_t>();
     ma.g_theta = S.gtheta.as<float>();
-    ma.gsum = paper ? P->gsum_b.as<GroupSum>() : P->gsum.as<GroupSum>();
+    ma.gsum = P->gsum.as<GroupSum>();
     ma.theta_b = P->theta_b.as<float>();
     ma.x_b = P->x_b.as<int32_t>();
     ma.theta_c = opta ? P->theta_cg.as<float>() : nullptr;
@@ -1033,6 +1113,7 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.include_best0 = !opta;
     ma.thr_ready = radius >= 0 && !paper;
     ma.delta = pr.margin;
+    ma.floor = pr.floor_prune ? pr.rho_floor : -2.0;
 }
 
 // The kernels of one query; the last one publishes the query state to the
@@ -1243,6 +1324,7 @@ zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out, double wal
         span(&r.phase_ms[2], S.evp[1], S.evp[2]);
         span(&r.phase_ms[3], S.evp[2], S.evp[3]);
     }
+    r.above_floor = r.rho >= q.pr.rho_floor;
     r.status = ZTS_OK;
     *out = r;
     return ZTS_OK;
@@ -1499,6 +1581,7 @@ void finish_batch(const BatchPlan &b, Slot &S, zts_result *out)
                 r.best0 = f.rho;
                 r.best0_y = r.y;
                 r.best0_x = r.x;
+                r.above_floor = 1;  // a batch has no floor (the defaults)
                 r.status = ZTS_OK;
             }
             out[b.members[j][t]] = r;
@@ -1626,6 +1709,11 @@ ZTS_API void zts_params_default(zts_params *p)
 {
     if (p)
         fill_default(p);
+}
+
+ZTS_API zts_status zts_params_check(const zts_params *p)
+{
+    return p ? params_status(*p) : ZTS_E_ARG;
 }
 
 ZTS_API const char *zts_status_str(zts_status s)
@@ -1766,17 +1854,13 @@ ZTS_API zts_status zts_prepare(zts_ctx *z, int32_t image, int32_t m, int32_t n, 
         if (m > im->rows || n > im->cols || (int64_t)m * n > 16384)
             throw ZtsError{ZTS_E_SIZE};
         check_mode_shape(mode, m, n);
-        zts_params pr;
-        if (params)
-            pr = *params;
-        else
-            fill_default(&pr);
+        const zts_params pr = params_or_default(params);
         if (mode == ZTS_FULL || mode == ZTS_FULL_MFMA) {
             stats_entry(c, im, m, n, c->stream);
             hip_check(hipStreamSynchronize(c->stream));
             return;
         }
-        prepare(c, im, m, n, mode == ZTS_OPTA_PAPER ? ZTS_OPTA : mode, pr);  // the same tables
+        prepare(c, im, m, n, mode, pr);
     });
 }
 
@@ -1787,21 +1871,22 @@ ZTS_API zts_status zts_prep_query(zts_ctx *z, int32_t image, int32_t m, int32_t 
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Image *im = find_image(&z->c, image);
-        auto it = im->prep.find(std::make_tuple(m, n, (int)(mode == ZTS_OPTA_PAPER ? ZTS_OPTA : mode)));
+        auto it = im->prep.find(std::make_tuple(m, n, (int)mode));
         if (it == im->prep.end())
             throw ZtsError{ZTS_E_NOTPREPARED};
         *out = it->second->info;
     });
 }
 
-ZTS_API zts_status zts_prep_image(zts_ctx *z, int32_t image, int32_t m, int32_t n, uint8_t *host_out)
+ZTS_API zts_status zts_prep_image(zts_ctx *z, int32_t image, int32_t m, int32_t n, zts_mode mode,
+                                  uint8_t *host_out)
 {
-    if (!z || !host_out)
+    if (!z || !host_out || (mode != ZTS_OPTA && mode != ZTS_OPTA_PAPER))
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
         Image *im = find_image(c, image);
-        auto it = im->prep.find(std::make_tuple(m, n, (int)ZTS_OPTA));
+        auto it = im->prep.find(std::make_tuple(m, n, (int)mode));
         if (it == im->prep.end())
             throw ZtsError{ZTS_E_NOTPREPARED};
         hip_check(hipMemcpy2DAsync(host_out, im->cols, it->second->J.ptr, im->pitch, im->cols, im->rows,
@@ -1820,11 +1905,7 @@ ZTS_API zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int
         Image *im = find_image(c, image);
         check_template_args(im, tpl, m, n, stride);
         check_mode_shape(mode, m, n);
-        zts_params pr;
-        if (params)
-            pr = *params;
-        else
-            fill_default(&pr);
+        const zts_params pr = params_or_default(params);
         if (mode == ZTS_FULL_MFMA) {
             if (n > 128)
                 throw ZtsError{ZTS_E_SIZE};
@@ -1832,6 +1913,7 @@ ZTS_API zts_status zts_search(zts_ctx *z, int32_t image, const uint8_t *tpl, int
             run_batch_main(c, {BatchItem{im, tpl, m, n, stride}}, &r);
             if (r.status != ZTS_OK)
                 throw ZtsError{r.status};
+            r.above_floor = r.rho >= pr.rho_floor;
             if (decision)
                 std::memset(decision, 2, (size_t)(im->rows - m + 1) * (im->cols - n + 1));
             *out = r;
@@ -1852,11 +1934,7 @@ ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_
         Image *im = find_image(c, image);
         check_template_args(im, tpl_dev, m, n, stride);
         check_mode_shape(mode, m, n);
-        zts_params pr;
-        if (params)
-            pr = *params;
-        else
-            fill_default(&pr);
+        const zts_params pr = params_or_default(params);
         if (mode == ZTS_FULL_MFMA) {
             if (n > 128)
                 throw ZtsError{ZTS_E_SIZE};
@@ -1868,6 +1946,7 @@ ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_
             run_batch_main(c, {it}, &r);
             if (r.status != ZTS_OK)
                 throw ZtsError{r.status};
+            r.above_floor = r.rho >= pr.rho_floor;
             *out = r;
             return;
         }

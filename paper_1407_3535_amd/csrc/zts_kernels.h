@@ -95,9 +95,13 @@ struct MemArgs {
     int thr_ready;  // the window kernel wrote the scan-1 best into the query state: only the window
                     // records are reduced, by each wave
     double delta;
+    double floor;   // eliminate against max(best, floor) (-2: the attained best alone)
 };
 
-enum { AC_DEBUG = 0, AC_COUNT = 1, AC_COUNT_BLUR = 2, AC_BUILD = 3 };
+// AC_COUNT / AC_COUNT_BLUR: Eq. 15 (Prop. 3.2) retained count, without and
+// with the angle to the original block; AC_COUNT31 / AC_COUNT31_BLUR: the
+// same with Prop. 3.1's bound at an assumed template-to-centre correlation.
+enum { AC_DEBUG = 0, AC_COUNT = 1, AC_COUNT_BLUR = 2, AC_BUILD = 3, AC_COUNT31 = 4, AC_COUNT31_BLUR = 5 };
 
 struct AcArgs {
     const uint8_t *J;
@@ -115,6 +119,8 @@ struct AcArgs {
     float thr_lo, thr_hi;        // thr -/+ guard band
     float alo_lo, alo_hi;        // acos(thr) -/+ guard band
     float ahi_lo, ahi_hi;        // 2 pi - acos(thr) -/+ guard band
+    double rho_th;               // AC_COUNT31*: the threshold of Prop. 3.1
+    double ra, sa;               // AC_COUNT31*: assumed rho_tc and sqrt(1 - rho_tc^2)
     unsigned long long *counter;
 };
 

@@ -208,7 +208,7 @@ struct Thr {
 
 // The threshold from the scan-1 best f0 and the window best fw (n2 window
 // records; none: the scan-1 best alone).
-__device__ Thr make_threshold(Best f0, Best fw, int n2, int include_best0, double delta)
+__device__ Thr make_threshold(Best f0, Best fw, int n2, int include_best0, double delta, double floor)
 {
     Thr r;
     r.best0 = f0.rho;
@@ -221,7 +221,7 @@ __device__ Thr make_threshold(Best f0, Best fw, int n2, int include_best0, doubl
     }
     r.best = fw.rho;
     r.best_l = fw.l;
-    r.thr64 = fw.rho - delta;
+    r.thr64 = (floor > fw.rho ? floor : fw.rho) - delta;
     double c = r.thr64 > 1.0 ? 1.0 : (r.thr64 < -1.0 ? -1.0 : r.thr64);
     float th = (float)acos(c);
     r.lo = th - kEpsTheta;
@@ -229,7 +229,8 @@ __device__ Thr make_threshold(Best f0, Best fw, int n2, int include_best0, doubl
     return r;
 }
 
-__device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_best0, double delta, Best *red)
+__device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_best0, double delta, double floor,
+                               Best *red)
 {
     // one pass over both record ranges: every load is issued before the
     // wave and block merges (red holds two entries per wave)
@@ -257,7 +258,7 @@ __device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_b
         best_merge(fw, red[nw + w].rho, red[nw + w].l, red[nw + w].valid);
     }
     __syncthreads();
-    return make_threshold(f0, fw, n2, include_best0, delta);
+    return make_threshold(f0, fw, n2, include_best0, delta, floor);
 }
 
 __device__ void store_threshold(QState *qs, const Thr &r)
@@ -274,7 +275,8 @@ __device__ void store_threshold(QState *qs, const Thr &r)
 // The threshold from the scan-1 best that the window kernel wrote into the
 // query state and the n2 window records, formed by each wave on its own
 // (lanes over the records, then shuffles; no block barrier).
-__device__ Thr wave_threshold(const QState *qs, const RecPod *wrecs, int n2, int include_best0, double delta)
+__device__ Thr wave_threshold(const QState *qs, const RecPod *wrecs, int n2, int include_best0, double delta,
+                              double floor)
 {
     const Best f0 = {qs->best0, qs->best0_l, 1};
     Best fw = {-2.0, INT64_MAX, 0};
@@ -286,7 +288,7 @@ __device__ Thr wave_threshold(const QState *qs, const RecPod *wrecs, int n2, int
         int v = __shfl_xor(fw.valid, off);
         best_merge(fw, r, (int64_t)l, v);
     }
-    return make_threshold(f0, fw, n2, include_best0, delta);
+    return make_threshold(f0, fw, n2, include_best0, delta, floor);
 }
 
 __device__ __forceinline__ void group_geom(int g, int Gx, int Ly, int Lx, int h, int w, int &oy, int &ox, int &hh,
@@ -1217,8 +1219,9 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     // the template words for survivors, in the same round trip (the
     // threshold's barriers make them visible)
     load_template_words(a.tpl, a.ts, a.m, a.n, n4, smem);
-    const Thr thr = a.thr_ready ? wave_threshold(a.qs, a.recs + a.n_best0, a.n_win, a.include_best0, a.delta)
-                                : block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, bred);
+    const Thr thr = a.thr_ready
+                        ? wave_threshold(a.qs, a.recs + a.n_best0, a.n_win, a.include_best0, a.delta, a.floor)
+                        : block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, a.floor, bred);
     if (degenerate)
         return;
     if (blockIdx.x == 0 && t == 0)
@@ -1451,6 +1454,28 @@ __device__ unsigned ac_finish(const AcArgs &a, int64_t o, int64_t c, int X)
         a.x_b[sl] = X;
         return 0;
     }
+    if (a.mode == AC_COUNT31 || a.mode == AC_COUNT31_BLUR) {
+        // Prop. 3.1: retained unless the bound through the centre, at the
+        // assumed template-to-centre angle, is at most rho_th (binary64
+        // throughout; preparation only)
+        double rc = 1.0, sc2 = 0.0, ub;
+        if (a.mode == AC_COUNT31) {
+            if (c == o)
+                return 0;
+            if (dc == 0 || dov == 0)
+                return 1;
+        } else {
+            const int2 si = a.statI[o];
+            const int64_t di = var_num(mn, si);
+            if (dc == 0 || dov == 0 || di == 0)
+                return 1;
+            const int64_t noo = mn * (int64_t)a.x_c[o] - (int64_t)so.x * (int64_t)si.x;
+            rc = rho64(noo, dov, di);
+            sc2 = sin64(noo, dov, di);
+        }
+        const double rb = rho64(num, dc, dov), sb = sin64(num, dc, dov);
+        return !ub_general(a.ra, a.sa, rb, sb, rc, sc2, &ub) || ub > a.rho_th;
+    }
     if (a.mode == AC_COUNT) {
         if (c == o)
             return 0;
@@ -1501,7 +1526,7 @@ __global__ __launch_bounds__(256) void k_autocorr(AcArgs a)
         if (lane == 0)
             cnt += ac_finish(a, o, c, X);
     }
-    if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR) {
+    if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR || a.mode == AC_COUNT31 || a.mode == AC_COUNT31_BLUR) {
         unsigned long long s = block_sum_u64(cnt, ured);
         if (t == 0 && s)
             atomicAdd(a.counter, s);
@@ -1536,7 +1561,7 @@ __global__ __launch_bounds__(256) void k_ac_shift(AcArgs a, int dy, int dx, cons
             cnt = ac_finish(a, o, c, X);
         }
     }
-    if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR) {
+    if (a.mode == AC_COUNT || a.mode == AC_COUNT_BLUR || a.mode == AC_COUNT31 || a.mode == AC_COUNT31_BLUR) {
         unsigned long long s = block_sum_u64(cnt, ured);
         if (threadIdx.x == 0 && s)
             atomicAdd(a.counter, s);

@@ -111,9 +111,8 @@ struct Prepared {
     zts_params params;
     DBuf theta_b, x_b, gsum;       // member vs centre on the searched image
     DBuf cstat;                    // statistics of each group centre's block on the searched image
-    DBuf gsum_b;                   // OptA: group summaries of theta_b alone (the paper's search)
-    DBuf J, Jsat, Jstat;           // OptA: conditioned image and its statistics
-    DBuf theta_c, x_c;             // OptA: conditioned block vs original block (row-major)
+    DBuf J, Jsat, Jstat;           // OptA (both forms): conditioned image and its statistics
+    DBuf theta_c, x_c;             // ZTS_OPTA: conditioned block vs original block (row-major)
     DBuf theta_cg, x_cg;           // the same in the group-major layout of (h, w)
     zts_prep_info info;
     int pins = 0;
@@ -189,6 +188,10 @@ struct Ctx {
 
 Image *find_image(Ctx *c, int id);
 void fill_default(zts_params *p);
+// ZTS_OK when every parameter is in range (the checks listed at zts_params_check).
+zts_status params_status(const zts_params &p);
+// *params (or the defaults when NULL), checked; throws ZTS_E_ARG when out of range.
+zts_params params_or_default(const zts_params *params);
 void check_template_args(Image *im, const void *tpl, int m, int n, int64_t stride);
 // ZTS_E_SIZE when a mode's kernels cannot stage an m x n template in the LDS
 // of one workgroup (ZTS_FULL: k_full's rows; ZTS_FULL_MFMA: n <= 128; the

@@ -28,6 +28,8 @@ void finish_request(Request *r, const zts_result &res)
     r->res = res;
     r->res.latency_ms = ms_between(r->t_submit, now);
     r->res.queue_ms = ms_between(r->t_submit, r->state == RQ_RUNNING ? r->t_start : now);
+    if (r->res.status == ZTS_OK)
+        r->res.above_floor = r->res.rho >= r->pr.rho_floor;
     r->state = RQ_DONE;
     r->im->busy--;
 }
@@ -180,10 +182,7 @@ std::unique_ptr<Request> make_request(Ctx *c, int image, const uint8_t *tpl, int
     r->m = m;
     r->n = n;
     r->mode = mode;
-    if (params)
-        r->pr = *params;
-    else
-        fill_default(&r->pr);
+    r->pr = params_or_default(params);
     r->tpl.resize((size_t)m * n);
     for (int i = 0; i < m; i++)
         std::memcpy(r->tpl.data() + (size_t)i * n, tpl + (size_t)i * stride, n);

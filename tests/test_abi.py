@@ -61,3 +61,25 @@ def test_no_device_is_a_clean_error():
     with pytest.raises(Z.ZtsError) as e:
         Z.zts_create(0)
     assert e.value.code == -10
+
+
+def test_params_check_rejects_out_of_range_values():
+    """Every entry point that takes parameters applies zts_params_check first; this exercises it on the host
+    (no device): a negative or NaN margin could eliminate the true maximum, a huge refinement radius would
+    overflow the window's record count."""
+    Z = pytest.importorskip("paper_1407_3535_amd")
+    assert Z.zts_params_check(Z.zts_params_default()) == 0
+    nan, inf = float("nan"), float("inf")
+    bad = [dict(margin=-1e-9), dict(margin=nan), dict(margin=inf), dict(refine_radius=-1),
+           dict(refine_radius=256), dict(refine_radius=23170), dict(sigma_step=0.0), dict(sigma_step=nan),
+           dict(xi=-0.01), dict(xi=nan), dict(rho_th=1.0), dict(rho_th=-1.0), dict(rho_th=nan),
+           dict(rho_max=1.0001), dict(accept_xi=1.0), dict(accept_xi=-1.0), dict(dh=0, dw=0), dict(dh=-1),
+           dict(h0=0), dict(group_h=0), dict(h_max=0), dict(blur_kind=2), dict(max_iters=16), dict(max_iters=-1),
+           dict(egs_estimate=2), dict(egs_shape=-1), dict(rho_tc=1.0), dict(rho_floor=nan), dict(floor_prune=2)]
+    for kw in bad:
+        assert Z.zts_params_check(Z.zts_params_default(**kw)) == -1, kw
+    good = [dict(margin=0.0), dict(refine_radius=255), dict(rho_max=1.0), dict(accept_xi=-0.5),
+            dict(egs_estimate=1, rho_tc=0.3), dict(egs_shape=1), dict(rho_floor=0.7, floor_prune=1),
+            dict(blur_kind=0, sigma_step=0.0)]
+    for kw in good:
+        assert Z.zts_params_check(Z.zts_params_default(**kw)) == 0, kw

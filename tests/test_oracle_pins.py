@@ -523,3 +523,249 @@ def test_paper_opta_search_pins():
         assert (s["y"], s["x"], s["rho"], s["num"]) == (w["y"], w["x"], w["rho"], w["num"])
         te = O.te_search(J, tpl, 3, 3)
         assert s["n_eliminated"] == te["n_eliminated"] and s["n_computed"] == te["n_computed"] + w["n_computed"]
+
+
+# ---------------------------------------------------------------- decision maps against an independent bound
+
+def _unit_blocks(img, m, n):
+    """Every m x n block of img, mean-centred and scaled to unit length (float64 rows, row-major location
+    order), and whether the block is flat (zero variance)."""
+    from numpy.lib.stride_tricks import sliding_window_view
+    W = sliding_window_view(img.astype(np.float64), (m, n)).reshape(-1, m * n)
+    W = W - W.mean(axis=1, keepdims=True)
+    nrm = np.linalg.norm(W, axis=1)
+    flat = nrm < 1e-9
+    U = W / np.where(flat, 1.0, nrm)[:, None]
+    return U, flat
+
+
+def _angle(a, b):
+    """Angle between unit vectors (rows), well conditioned everywhere: 2 atan2(|a - b|, |a + b|)."""
+    return 2.0 * np.arctan2(np.linalg.norm(a - b, axis=-1), np.linalg.norm(a + b, axis=-1))
+
+
+def _centres(Ly, Lx, h, w):
+    """Linear index of each location's group centre: groups of h x w tile the grid from (0, 0), partial last
+    groups allowed, centre = origin + floor((extent - 1) / 2) (the centre rule pinned above)."""
+    y, x = np.divmod(np.arange(Ly * Lx), Lx)
+    gy, gx = (y // h) * h, (x // w) * w
+    cy = gy + (np.minimum(h, Ly - gy) - 1) // 2
+    cx = gx + (np.minimum(w, Lx - gx) - 1) // 2
+    return cy * Lx + cx
+
+
+BAND = 1e-7  # decisions of the float bound closer than this to the threshold are not compared
+
+
+@pytest.mark.parametrize("p,q,m,n,h,w,radius,kind", [
+    (40, 44, 6, 7, 3, 3, 0, "spectral"), (40, 44, 6, 7, 4, 5, 2, "spectral"),
+    (36, 50, 8, 5, 5, 3, 0, "flat_patches"), (33, 41, 5, 5, 3, 4, 1, "periodic"),
+    (56, 56, 16, 16, 5, 5, 0, "spectral")])
+def test_te_decisions_equal_an_independent_bound(p, q, m, n, h, w, radius, kind):
+    """Scan 2's decision map against the bound of Eq. 2 recomputed independently: unit blocks in float64 and
+    the angle form cos|angle(t, c) - angle(c, o)|.  Every location whose independent bound lies clearly below
+    the threshold must be eliminated (completeness) and every one clearly above must be matched
+    (soundness); flat blocks are never eliminated."""
+    img = tiny_image(p, q, 31 + p + q, kind)
+    tpl, _ = cut_template(img, m, n, 7 + h, 1.0)
+    te = O.te_search(img, tpl, h, w, decision=True, radius=radius)
+    Ly, Lx = p - m + 1, q - n + 1
+    U, flat = _unit_blocks(img, m, n)
+    T, tflat = _unit_blocks(tpl, m, n)
+    assert not tflat[0]
+    rho = U @ T[0]
+    cen = _centres(Ly, Lx, h, w)
+    is_c = cen == np.arange(Ly * Lx)
+    dec = te["decision"].ravel()
+    assert ((dec == 1) == is_c).all()
+    # the threshold: the best of the centres (and the window), an attained rho
+    cand = is_c | (dec == 3)
+    best0 = np.max(np.where(flat, 0.0, rho)[cand])
+    assert abs(best0 - te["best0"]) <= 1e-12
+    thr = te["best0"] - 1e-9
+    A = _angle(T[0][None, :], U[cen])
+    B = _angle(U[cen], U)
+    ub = np.cos(np.abs(A - B))
+    member = ~cand
+    never = flat | flat[cen]
+    must_go = member & ~never & (ub < thr - BAND)
+    must_stay = member & (never | (ub > thr + BAND))
+    assert (dec[must_go] == 0).all(), "an eliminable location was kept"
+    assert (dec[must_stay] == 2).all(), "a location the bound cannot exclude was eliminated"
+    assert must_go.sum() > 0 and must_stay.sum() > 0
+    assert (must_go | must_stay | ~member).sum() >= Ly * Lx - 2  # the band holds (almost) nothing
+    assert te["n_eliminated"] == (dec == 0).sum()
+
+
+@pytest.mark.parametrize("seed,sigma,h,w,radius", [(0, 1.0, 3, 3, 2), (1, 1.5, 4, 5, 0), (2, 0.8, 5, 5, 3)])
+def test_opta_decisions_equal_an_independent_bound(seed, sigma, h, w, radius):
+    """The exact OptA search's decisions against the angle triangle recomputed independently: with
+    A = angle(t, centre in J), B = angle(centre in J, o in J), C = angle(o in J, o in I), a location is
+    eliminable iff |A - B| > C and cos(|A - B| - C) lies below the threshold (the window's best on I)."""
+    I = aerial_image(44, 52, 60 + seed, beta=2.8)
+    m, n = 8, 7
+    taps, _ = O.gauss_taps(sigma)
+    J, _, _ = O.revert(I, O.blur(I, taps), m, n, O.lambda_(0.8, 1.0))
+    assert (J != I).mean() > 0.1
+    tpl, _ = cut_template(I, m, n, 80 + seed, 5.0)
+    s = O.opta_search(I, J, tpl, h, w, radius, decision=True)
+    Ly, Lx = 44 - m + 1, 52 - n + 1
+    UI, fI = _unit_blocks(I, m, n)
+    UJ, fJ = _unit_blocks(J, m, n)
+    T, _ = _unit_blocks(tpl, m, n)
+    cen = _centres(Ly, Lx, h, w)
+    dec = s["decision"].ravel()
+    win = dec == 1
+    best = np.max((UI @ T[0])[win & ~fI])
+    assert abs(best - s["best0"]) <= 1e-12
+    thr = s["best0"] - 1e-9
+    A = _angle(T[0][None, :], UJ[cen])
+    B = _angle(UJ[cen], UJ)
+    C = _angle(UJ, UI)
+    gap = np.abs(A - B) - C
+    ub = np.where(gap > 0, np.cos(np.maximum(gap, 0.0)), 2.0)
+    never = fI | fJ | fJ[cen]
+    must_go = ~win & ~never & (gap > 1e-7) & (ub < thr - BAND)
+    must_stay = ~win & (never | (gap < -1e-7) | (ub > thr + BAND))
+    assert (dec[must_go] == 0).all()
+    assert (dec[must_stay] == 2).all()
+    assert must_go.sum() > 0 and must_stay.sum() > 0
+    assert (must_go | must_stay | win).sum() >= Ly * Lx - 2
+
+
+def _count_retained(U, flat, Ly, Lx, h, w, rho_th, C=None, fI=None, estimate=0, rho_tc=0.0):
+    """Retained-location count of EGS recomputed from unit blocks (the reading of each estimate stated in
+    the oracle).  Returns (count, locations within the band of the threshold)."""
+    cen = _centres(Ly, Lx, h, w)
+    is_c = cen == np.arange(Ly * Lx)
+    B = _angle(U[cen], U)
+    never = flat | flat[cen]
+    if C is not None:
+        never = never | fI
+    if estimate == 0:
+        thr = math.sqrt(1.0 - rho_th * rho_th)
+        val = np.cos(B + (C if C is not None else 0.0))
+        kept, near = val < thr, np.abs(val - thr) < BAND
+    else:
+        A = math.acos(rho_tc)
+        gap = np.abs(A - B) - (C if C is not None else 0.0)
+        val = np.where(gap > 0, np.cos(np.maximum(gap, 0.0)), 2.0)
+        kept, near = val > rho_th, (np.abs(val - rho_th) < BAND) | (np.abs(gap) < 1e-7)
+    counted = np.ones(Ly * Lx, bool) if C is not None else ~is_c
+    kept = counted & (never | kept)
+    near = counted & ~never & near
+    return int(kept.sum()), int(near.sum())
+
+
+@pytest.mark.parametrize("estimate,rho_tc", [(0, 0.0), (1, 0.0), (1, 0.35), (1, -0.2)])
+def test_egs_counts_equal_an_independent_count(estimate, rho_tc):
+    """EGS's retained counts, without blur (Prop. 3.2, Eq. 15) and with the angle to the original added
+    (the exact OptA search's count), and Prop. 3.1's two-root estimate at an assumed rho_tc, against counts
+    recomputed from unit blocks."""
+    I = aerial_image(48, 56, 91, beta=2.8)
+    m, n = 8, 8
+    taps, _ = O.gauss_taps(1.0)
+    J, _, _ = O.revert(I, O.blur(I, taps), m, n, O.lambda_(0.8, 1.0))
+    assert (J != I).mean() > 0.1
+    Ly, Lx = 48 - m + 1, 56 - n + 1
+    UJ, fJ = _unit_blocks(J, m, n)
+    UI, fI = _unit_blocks(I, m, n)
+    for use_c in (False, True):
+        c = O.blurcorr(I, J, m, n) if use_c else None
+        e = O.egs(J, m, n, c=c, estimate=estimate, rho_tc=rho_tc)
+        assert e["trace"]
+        for step in e["trace"]:
+            want, near = _count_retained(UJ, fJ, Ly, Lx, step["h"], step["w"], 0.8,
+                                         C=_angle(UJ, UI) if use_c else None, fI=fI, estimate=estimate,
+                                         rho_tc=rho_tc)
+            assert want - near <= step["cr"] <= want + near
+            assert near <= 2
+
+
+def test_egs_two_dimensional_ascent():
+    """shape 1 evaluates (h+dh, w), (h, w+dw), (h+dh, w+dw) from the last accepted size and accepts the
+    cheapest when it lowers the cost by more than xi; each candidate's cost is mn (groups + retained)."""
+    img = aerial_image(72, 80, 5, beta=2.6)
+    m = n = 10
+    Ly, Lx = 72 - m + 1, 80 - n + 1
+    U, flat = _unit_blocks(img, m, n)
+    e = O.egs(img, m, n, shape=1)
+    tr = e["trace"]
+    prev, cur, i = m * n * Ly * Lx, None, 0
+    while i < len(tr):
+        if cur is None:
+            cands = [(3, 3)]
+        else:
+            cands = [(cur[0] + 2, cur[1]), (cur[0], cur[1] + 2), (cur[0] + 2, cur[1] + 2)]
+        cands = [c for c in cands if c[0] <= min(33, Ly) and c[1] <= min(33, Lx)]
+        rows = tr[i:i + len(cands)]
+        assert [(r["h"], r["w"]) for r in rows] == cands
+        for r in rows:
+            gy, gx = -(-Ly // r["h"]), -(-Lx // r["w"])
+            assert r["cc"] == gy * gx
+            want, near = _count_retained(U, flat, Ly, Lx, r["h"], r["w"], 0.8)
+            assert want - near <= r["cr"] <= want + near
+            assert r["ct"] == m * n * (r["cc"] + r["cr"])
+        i += len(cands)
+        best = min(range(len(rows)), key=lambda k: (rows[k]["ct"], k))
+        ok = (prev - rows[best]["ct"]) > 0.005 * prev
+        assert [r["accepted"] for r in rows] == [ok and k == best for k in range(len(rows))]
+        if not ok:
+            break
+        prev, cur = rows[best]["ct"], (rows[best]["h"], rows[best]["w"])
+    assert i == len(tr)
+    assert (e["h"], e["w"]) == (cur if cur else (1, 1)) and e["cost"] == prev
+    assert any(r["h"] != r["w"] for r in tr)
+
+
+def test_paper_conditioning_is_alg3_as_printed():
+    """paper=True: every accepted iterate's EGS is EGS on the blurred image alone (no angle to the original),
+    warm-started at the previous size; the final image keeps every blur correlation >= lambda; the paper's
+    conditioning differs from the exact one's on an input where blur is accepted."""
+    I = aerial_image(96, 96, 7002, beta=2.6)
+    m = n = 24
+    kw = dict(rho_max=1.0, nthreads=4)
+    op = O.opta(I, m, n, paper=True, **kw)
+    acc = [s for s in op["trace"] if s["accepted"]]
+    assert len(acc) >= 3 and len({s["h"] for s in acc}) >= 2
+    J = op["image"]
+    num, dj, di = O.blurcorr(I, J, m, n)
+    lam = O.lambda_(0.8, 1.0)
+    for l in range(len(num)):
+        assert dj[l] != 0 and di[l] != 0 and O.rho(num[l], dj[l], di[l]) >= lam
+    prev_h = acc[-2]["h"]
+    e = O.egs(J, m, n, h0=prev_h, w0=prev_h)
+    assert (e["h"], e["w"], e["cost"]) == (op["h"], op["w"], op["cost"])
+    ex = O.opta(I, m, n, paper=False, **kw)
+    assert ex["trace"] != op["trace"]
+
+
+def test_detection_floor_semantics():
+    """With a floor the threshold is max(best0, floor): at or below the true maximum the answer is the
+    full search's and nothing eliminated reaches the floor; above it every eliminated location lies below the
+    floor (the full map says so), and elimination only grows with the floor."""
+    img = aerial_image(64, 72, 77, beta=2.2)
+    m, n = 10, 9
+    for k in range(3):
+        tpl, _ = cut_template(img, m, n, 300 + k, 12.0, affine=True)
+        full = O.full_search(img, tpl, maps=True)
+        rho = full["rho_map"].ravel()
+        base = O.te_search(img, tpl, 3, 3, decision=True)
+        prev = base["n_eliminated"]
+        for fl in sorted((full["rho"] - 0.05, full["rho"], full["rho"] + 1e-6, 0.95, 0.999)):
+            s = O.te_search(img, tpl, 3, 3, decision=True, floor=fl)
+            dec = s["decision"].ravel()
+            assert (rho[dec == 0] < max(fl, s["best0"])).all()
+            assert s["n_eliminated"] >= prev
+            prev = s["n_eliminated"]
+            if fl <= full["rho"]:
+                assert (s["y"], s["x"], s["rho"]) == (full["y"], full["x"], full["rho"])
+            assert s["rho"] <= full["rho"]
+        J = O.blur(img, O.gauss_taps(0.8)[0])
+        J, _, _ = O.revert(img, J, m, n, O.lambda_(0.8, 1.0))
+        for fl in (full["rho"] - 0.1, 0.999):
+            s = O.opta_search(img, J, tpl, 3, 3, 2, decision=True, floor=fl)
+            dec = s["decision"].ravel()
+            assert (rho[dec == 0] < max(fl, s["best0"])).all()
+            if fl <= full["rho"]:
+                assert (s["y"], s["x"], s["rho"]) == (full["y"], full["x"], full["rho"])
