@@ -868,10 +868,26 @@ void check_mode_shape(zts_mode mode, int m, int n)
 {
     // The LDS needs grow with m and n, so when 128 x 128 fits every mode, so
     // does every shape within it: those skip the per-kernel queries below.
-    static const bool small_fit = full_fits(128, 128) && scan_fits(128, 128);
-    if (m <= 128 && n <= 128 && small_fit)
-        return;
+    // The answer is kept only once the queries behind it have succeeded; a
+    // failed query is a device error, not a size refusal.
+    static std::atomic<int> small_fit{-1};
+    if (m <= 128 && n <= 128) {
+        int sf = small_fit.load(std::memory_order_relaxed);
+        if (sf < 0) {
+            (void)lds_query_failed();
+            const bool v = full_fits(128, 128) && scan_fits(128, 128);
+            if (lds_query_failed())
+                throw ZtsError{ZTS_E_DEVICE};
+            sf = v ? 1 : 0;
+            small_fit.store(sf, std::memory_order_relaxed);
+        }
+        if (sf == 1)
+            return;
+    }
+    (void)lds_query_failed();
     const bool ok = mode == ZTS_FULL ? full_fits(m, n) : mode == ZTS_FULL_MFMA ? n <= 128 : scan_fits(m, n);
+    if (lds_query_failed())
+        throw ZtsError{ZTS_E_DEVICE};
     if (!ok)
         throw ZtsError{ZTS_E_SIZE};
 }

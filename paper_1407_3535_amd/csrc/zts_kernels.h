@@ -216,6 +216,10 @@ int members_record_count(int Gy, int Gx);
 hipError_t launch_members(MemArgs a, hipStream_t s);
 // Whether scan 1 (either form) and scan 2 can stage a template of m x n.
 bool scan_fits(int m, int n);
+// Whether a static-LDS query behind full_fits / scan_fits failed on this
+// thread since the last call (a failed query answers "does not fit" and is not
+// cached); clears the flag.
+bool lds_query_failed();
 hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int w, hipStream_t s);
 
 // Alg. 1: direct dot products per location, or, when cheaper

@@ -2574,24 +2574,42 @@ size_t full_lds_bytes(int m, int n)
 // host rejects such shapes before launching (full_fits, scan_fits).
 constexpr size_t kLdsMax = 160 * 1024;
 
-// Static LDS of a kernel on the current device (queried once per kernel and
-// device; a failed query counts as the whole LDS, so nothing is launched).
+// Set when a static-LDS query fails on this thread (read and cleared by
+// lds_query_failed).
+static thread_local bool t_lds_failed = false;
+
+bool lds_query_failed()
+{
+    const bool f = t_lds_failed;
+    t_lds_failed = false;
+    return f;
+}
+
+// Static LDS of a kernel on the current device, cached per kernel and device
+// once a query succeeds.  A failed query is not cached: it counts as the
+// whole LDS (so nothing is launched) and flags lds_query_failed.
 static size_t static_lds(const void *f)
 {
     static std::mutex mu;
     static std::map<std::pair<const void *, int>, size_t> memo;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess)
+    if (hipGetDevice(&dev) != hipSuccess) {
+        t_lds_failed = true;
         return kLdsMax;
+    }
     std::lock_guard<std::mutex> lk(mu);
     auto key = std::make_pair(f, dev);
     auto it = memo.find(key);
     if (it != memo.end())
         return it->second;
     hipFuncAttributes at{};
-    size_t v = hipFuncGetAttributes(&at, f) == hipSuccess ? at.sharedSizeBytes : kLdsMax;
-    memo.emplace(key, v);
-    return v;
+    if (hipFuncGetAttributes(&at, f) != hipSuccess) {
+        (void)hipGetLastError();
+        t_lds_failed = true;
+        return kLdsMax;
+    }
+    memo.emplace(key, at.sharedSizeBytes);
+    return at.sharedSizeBytes;
 }
 
 // Raises a kernel's dynamic-LDS allowance to `bytes` on the current device
