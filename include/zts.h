@@ -295,6 +295,34 @@ ZTS_API zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tp
                              int64_t stride, zts_mode mode, const zts_params *params, void *stream,
                              zts_result *out);
 
+/* zts_search_device for callers that cannot allocate device memory (code
+ * that runs while a caller captures a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc): the same search, the same kernels and the
+ * same result, but the call allocates nothing (no hipMalloc, hipFree or
+ * other allocating routine, host or device).  Its query state, per-block
+ * records and per-group centre sums and angles live in a static device array
+ * of 64 MiB that each GPU the library runs on holds until the process ends.
+ *   - Everything else must already be resident: the image's statistics for
+ *     (m, n) (zts_prepare with any mode, or an earlier search of that size)
+ *     and, for ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA and ZTS_OPTA_PAPER, tables
+ *     prepared for (m, n, mode) with the same preparation parameters;
+ *     otherwise ZTS_E_NOTPREPARED.
+ *   - ZTS_E_SIZE when the query needs more than 64 MiB of scratch: 8 bytes
+ *     per group (so at most about 8 million groups, e.g. a 3 x 3 tiling of a
+ *     8192 x 8192 image fits) plus 64 bytes per block record.
+ *   - ZTS_FULL_MFMA is not offered (ZTS_E_ARG); params->timing is ignored
+ *     (phase_ms stays 0, device_ms comes from the device clock).
+ *   - The template is read in place after `stream` (NULL: the context's
+ *     stream) has reached the call; the call returns with the result.
+ *   - Every call on one GPU uses that GPU's one array, which keeps the last
+ *     call's contents (the call clears what must start at zero).  Calls on
+ *     one GPU, from any context, are serialised by the library; device work
+ *     that another process or a graph replay puts on the same GPU while a call
+ *     runs does not touch the array. */
+ZTS_API zts_status zts_search_device_noalloc(zts_ctx *ctx, int32_t image, const void *tpl_dev, int32_t m, int32_t n,
+                                             int64_t stride, zts_mode mode, const zts_params *params, void *stream,
+                                             zts_result *out);
+
 /* Exhaustive search (ZTS_FULL semantics, Eq. 1 at every location) of `count`
  * host templates against one image in one fused launch on int8 MFMA
  * (v_mfma_i32_16x16x64_i8, int32 accumulation).  Templates are grouped by

@@ -37,7 +37,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template"
 
 EXPORTS = ["zts_params_default", "zts_params_check", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
            "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
-           "zts_search", "zts_search_device", "zts_search_batch", "zts_tune_batch", "zts_submit", "zts_submit_batch", "zts_poll",
+           "zts_search", "zts_search_device", "zts_search_device_noalloc", "zts_search_batch", "zts_tune_batch", "zts_submit", "zts_submit_batch", "zts_poll",
            "zts_wait", "zts_cancel", "zts_pending", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
 
 
@@ -146,6 +146,7 @@ def lib():
         L.zts_search.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(Result), vp]
         L.zts_search_device.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), vp,
                                         C.POINTER(Result)]
+        L.zts_search_device_noalloc.argtypes = L.zts_search_device.argtypes
         L.zts_search_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.zts_tune_batch.argtypes = [vp, i32, i32, vp, vp, vp]
         L.zts_submit.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
@@ -297,6 +298,19 @@ def zts_search_device(ctx, image: int, tpl_tensor, mode, params: Params | None =
     m, n = tpl_tensor.shape
     _check(lib().zts_search_device(ctx, image, tpl_tensor.data_ptr(), m, n, tpl_tensor.stride(0), _mode(mode),
                                    C.byref(p), s, C.byref(r)), "zts_search_device")
+    return r if out is not None else r.as_dict()
+
+
+def zts_search_device_noalloc(ctx, image: int, tpl_tensor, mode, params: Params | None = None, stream=None,
+                              out: Result | None = None):
+    """zts_search_device with the query's scratch in the library's static device array (allocates nothing;
+    the image's statistics and the mode's tables must be resident already)."""
+    p = params if params is not None else zts_params_default()
+    s = stream if stream is not None else _current_stream(tpl_tensor.device.index)
+    r = out if out is not None else Result()
+    m, n = tpl_tensor.shape
+    _check(lib().zts_search_device_noalloc(ctx, image, tpl_tensor.data_ptr(), m, n, tpl_tensor.stride(0),
+                                           _mode(mode), C.byref(p), s, C.byref(r)), "zts_search_device_noalloc")
     return r if out is not None else r.as_dict()
 
 

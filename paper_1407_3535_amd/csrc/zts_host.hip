@@ -993,7 +993,23 @@ struct QueryLaunch {
     void *h_qs;
 };
 
-static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, QueryLaunch &Q)
+// Device scratch of one query (and the pinned host mirror of its state).
+struct QueryBufs {
+    QState *qs;
+    RecPod *recs;
+    int32_t *gnum;
+    float *gtheta;
+    const uint8_t *tpl;  // the staged template (pitch n) when the plan reads none in place
+    void *h_qs;
+};
+
+static QueryBufs slot_bufs(Slot &S)
+{
+    return QueryBufs{S.qs.as<QState>(), S.recs.as<RecPod>(), S.gnum.as<int32_t>(), S.gtheta.as<float>(),
+                     S.tpl.as<uint8_t>(), S.h_qs.ptr};
+}
+
+static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d_dec, QueryLaunch &Q)
 {
     std::memset(&Q, 0, sizeof Q);
     Image *im = q.im;
@@ -1001,13 +1017,13 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     const zts_params &pr = q.pr;
     const Prepared *P = q.P;
     const int2 *statI = q.st->stat.as<int2>();
-    QState *qs = S.qs.as<QState>();
-    const uint8_t *tpl = q.tpl ? q.tpl : S.tpl.as<uint8_t>();
+    QState *qs = B.qs;
+    const uint8_t *tpl = q.tpl ? q.tpl : B.tpl;
     const int64_t ts = q.tpl ? q.ts : n;
-    RecPod *recs = S.recs.as<RecPod>();
+    RecPod *recs = B.recs;
     Q.qs = qs;
     Q.recs = recs;
-    Q.h_qs = S.h_qs.ptr;
+    Q.h_qs = B.h_qs;
     if (q.mode == ZTS_FULL) {
         Q.full = 1;
         FullArgs &a = Q.fa;
@@ -1066,8 +1082,8 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     s.w = P->w;
     s.Gy = P->Gy;
     s.Gx = P->Gx;
-    s.g_x = S.gnum.as<int32_t>();
-    s.g_theta = S.gtheta.as<float>();
+    s.g_x = B.gnum;
+    s.g_theta = B.gtheta;
     s.recs = recs;
     s.qs = qs;
     s.dec = onJ ? nullptr : d_dec;
@@ -1110,8 +1126,8 @@ static void build_query_launch(const QueryPlan &q, Slot &S, int8_t *d_dec, Query
     ma.w = P->w;
     ma.Gy = P->Gy;
     ma.Gx = P->Gx;
-    ma.g_x = S.gnum.as<int32_t>();
-    ma.g_theta = S.gtheta.as<float>();
+    ma.g_x = B.gnum;
+    ma.g_theta = B.gtheta;
     ma.gsum = P->gsum.as<GroupSum>();
     ma.theta_b = P->theta_b.as<float>();
     ma.x_b = P->x_b.as<int32_t>();
@@ -1237,7 +1253,7 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
         d_dec = S.dec.as<int8_t>();
     }
     QueryLaunch Q;
-    build_query_launch(q, S, d_dec, Q);
+    build_query_launch(q, slot_bufs(S), d_dec, Q);
     const bool timing = q.pr.timing != 0;
     const bool graphable = S.use_graphs && !timing && !q.want_dec && !q.num_map && !q.dr_map && !q.rho_map;
     S.timed = timing;
@@ -1258,16 +1274,16 @@ void launch_query(const QueryPlan &q, Slot &S, int8_t *dec_host)
 // launched query (the final reduction writes it after the rest of the state).
 // The stream is polled every 50 us so that a failed launch ends the wait with
 // its error.
-static void wait_published(Slot &S)
+static void wait_seq(const QState *mirror, unsigned long long want, hipStream_t stream)
 {
-    const volatile unsigned long long *seq = &S.h_qs.as<QState>()->seq;
+    const volatile unsigned long long *seq = &mirror->seq;
     auto next = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
-    while (*seq != S.qseq) {
+    while (*seq != want) {
         if (std::chrono::steady_clock::now() < next)
             continue;
-        hipError_t e = hipStreamQuery(S.stream);
+        hipError_t e = hipStreamQuery(stream);
         if (e == hipSuccess) {
-            if (*seq == S.qseq)
+            if (*seq == want)
                 break;
             throw ZtsError{ZTS_E_DEVICE};  // the stream finished without publishing
         }
@@ -1278,13 +1294,25 @@ static void wait_published(Slot &S)
     std::atomic_thread_fence(std::memory_order_acquire);
 }
 
+static void wait_published(Slot &S) { wait_seq(S.h_qs.as<QState>(), S.qseq, S.stream); }
+
+static zts_status assemble_result(const QueryPlan &q, const QState &h, Slot *timed, zts_result *out,
+                                  double wall_khz);
+
 // Waits for the query on S.stream and assembles its result.
 zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out, double wall_khz)
 {
     if (S.timed || q.want_dec)
         hip_check(hipStreamSynchronize(S.stream));  // events, or the decision map's copy
     wait_published(S);
-    const QState &h = *S.h_qs.as<QState>();
+    return assemble_result(q, *S.h_qs.as<QState>(), S.timed ? &S : nullptr, out, wall_khz);
+}
+
+// The result of a query from its published state (timed: the slot whose
+// events timed its kernels, or NULL).
+static zts_status assemble_result(const QueryPlan &q, const QState &h, Slot *timed, zts_result *out,
+                                  double wall_khz)
+{
     if (h.degenerate)
         return ZTS_E_DEGENERATE;
     const int Lx = q.Lx;
@@ -1326,19 +1354,19 @@ zts_status finish_query(const QueryPlan &q, Slot &S, zts_result *out, double wal
     // device time: HIP events when timed, else the device clock stamps of
     // the first kernel's start and the final reduction
     float ms = (float)((double)(h.t1 - h.t0) / wall_khz);
-    if (S.timed)
-        hip_check(hipEventElapsedTime(&ms, S.ev0, S.ev1));
+    if (timed)
+        hip_check(hipEventElapsedTime(&ms, timed->ev0, timed->ev1));
     r.device_ms = ms;
     // per-kernel times, when the query was launched with its events
     auto span = [](float *out, hipEvent_t a, hipEvent_t b) { hip_check(hipEventElapsedTime(out, a, b)); };
-    if (S.timed && q.mode == ZTS_FULL) {
-        span(&r.phase_ms[0], S.ev0, S.evp[0]);
-        span(&r.phase_ms[3], S.evp[0], S.evp[1]);
-    } else if (S.timed) {
-        span(&r.phase_ms[0], S.ev0, S.evp[0]);
-        span(&r.phase_ms[1], S.evp[0], S.evp[1]);
-        span(&r.phase_ms[2], S.evp[1], S.evp[2]);
-        span(&r.phase_ms[3], S.evp[2], S.evp[3]);
+    if (timed && q.mode == ZTS_FULL) {
+        span(&r.phase_ms[0], timed->ev0, timed->evp[0]);
+        span(&r.phase_ms[3], timed->evp[0], timed->evp[1]);
+    } else if (timed) {
+        span(&r.phase_ms[0], timed->ev0, timed->evp[0]);
+        span(&r.phase_ms[1], timed->evp[0], timed->evp[1]);
+        span(&r.phase_ms[2], timed->evp[1], timed->evp[2]);
+        span(&r.phase_ms[3], timed->evp[2], timed->evp[3]);
     }
     r.above_floor = r.rho >= q.pr.rho_floor;
     r.status = ZTS_OK;
@@ -1605,6 +1633,151 @@ void finish_batch(const BatchPlan &b, Slot &S, zts_result *out)
     }
 }
 
+// ------------------------------------------------------------------ allocation-free search
+
+// Device scratch of zts_search_device_noalloc, one copy per GPU, held until
+// the process ends: the query state, the per-block records and the per-group
+// centre sums and angles of one query.  In host code the name `scratch` is a
+// host-side stand-in, never a device address: host code uses only the address
+// hipGetSymbolAddress returned for each device (scratch_setup).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+
+}  // namespace zts
+
+static __device__ __align__(256) uint8_t scratch[zts::kNoAllocScratchBytes];
+
+namespace zts {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_setup_mu;
+void *g_scratch_ptr[kMaxDevices];      // device address of `scratch` on each GPU, looked up once
+std::mutex g_scratch_mu[kMaxDevices];  // one allocation-free search at a time per GPU
+
+}  // namespace
+
+// Looks up the device address of `scratch` on device `dev`, which must be
+// current, once per device (zts_create calls it).
+void scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        throw ZtsError{ZTS_E_DEVICE};
+    std::lock_guard<std::mutex> lk(g_scratch_setup_mu);
+    if (g_scratch_ptr[dev])
+        return;
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr)
+        throw ZtsError{ZTS_E_DEVICE};
+    g_scratch_ptr[dev] = ptr;
+}
+
+static uint8_t *scratch_ptr(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_setup_mu);
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch_ptr[dev])
+        throw ZtsError{ZTS_E_DEVICE};
+    return (uint8_t *)g_scratch_ptr[dev];
+}
+
+// A query plan from what is already resident: the image's statistics for
+// (m, n) and, for the eliminating modes, tables prepared with the same
+// parameters.  Nothing is built or allocated; ZTS_E_NOTPREPARED otherwise.
+static QueryPlan plan_resident(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr)
+{
+    QueryPlan q;
+    q.im = im;
+    q.m = m;
+    q.n = n;
+    q.Ly = im->rows - m + 1;
+    q.Lx = im->cols - n + 1;
+    q.mode = mode;
+    q.pr = pr;
+    auto st = im->stats.find(std::make_pair(m, n));
+    if (st == im->stats.end())
+        throw ZtsError{ZTS_E_NOTPREPARED};
+    if (mode != ZTS_FULL) {
+        auto it = im->prep.find(std::make_tuple(m, n, (int)mode));
+        if (it == im->prep.end() || !same_prep_params(*it->second, mode, pr))
+            throw ZtsError{ZTS_E_NOTPREPARED};
+        q.P = it->second.get();
+    }
+    hip_check(hipStreamWaitEvent(c->stream, st->second->ready, 0));
+    q.st = st->second.get();
+    q.st->pins++;
+    q.st->last_use = ++c->clock;
+    if (q.P) {
+        q.P->pins++;
+        q.P->last_use = ++c->clock;
+    }
+    return q;
+}
+
+// One query with every buffer it needs taken from the device's `scratch`
+// (context lock held).  ZTS_E_SIZE when the query's scratch exceeds it.
+static void run_query_noalloc(Ctx *c, Image *im, const uint8_t *tpl, int m, int n, int64_t stride,
+                              hipStream_t caller, zts_mode mode, const zts_params &pr, zts_result *out)
+{
+    // scratch layout, 256-byte aligned parts: query state, records, centre sums, centre angles
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const int Ly = im->rows - m + 1, Lx = im->cols - n + 1;
+    QueryPlan q = plan_resident(c, im, m, n, mode, pr);
+    zts_status st = ZTS_OK;
+    try {
+        size_t nrec = 0, groups = 0;
+        if (mode == ZTS_FULL) {
+            nrec = (size_t)full_record_count(Ly, Lx);
+        } else {
+            const Prepared *P = q.P;
+            const int radius = query_radius(q);
+            nrec = (size_t)centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w) +
+                   (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
+                   (size_t)members_record_count(P->Gy, P->Gx);
+            groups = (size_t)P->Gy * P->Gx;
+        }
+        const size_t o_qs = take(sizeof(QState)), o_rec = take(sizeof(RecPod) * nrec);
+        const size_t o_gx = take(sizeof(int32_t) * groups), o_gt = take(sizeof(float) * groups);
+        if (off > kNoAllocScratchBytes)
+            throw ZtsError{ZTS_E_SIZE};
+        q.tpl = tpl;
+        q.ts = stride;
+        std::lock_guard<std::mutex> dl(g_scratch_mu[c->device]);
+        uint8_t *base = scratch_ptr(c->device);
+        QState *mirror = c->h_qs_noalloc.as<QState>();
+        const QueryBufs B{(QState *)(base + o_qs), (RecPod *)(base + o_rec), (int32_t *)(base + o_gx),
+                          (float *)(base + o_gt), nullptr, mirror};
+        hipStream_t s = c->stream;
+        // the kernels read the caller's template in place, after the caller's
+        // stream has reached this call
+        if (caller != s && hipStreamQuery(caller) != hipSuccess) {
+            (void)hipGetLastError();  // hipErrorNotReady: work is pending
+            hip_check(hipEventRecord(c->main.ev_in, caller));
+            hip_check(hipStreamWaitEvent(s, c->main.ev_in, 0));
+        }
+        // the state keeps the previous call's contents (any context on this
+        // GPU): it starts from zero, so the final reduction publishes 1
+        *(volatile unsigned long long *)&mirror->seq = 0;
+        hip_check(launch_qs_clear(B.qs, s));
+        QueryLaunch Q;
+        build_query_launch(q, B, nullptr, Q);
+        enqueue_query(Q, c->main, s, false);
+        wait_seq(mirror, 1, s);
+        st = assemble_result(q, *mirror, nullptr, out, c->wall_khz);
+    } catch (...) {
+        unpin_query(q);
+        throw;
+    }
+    unpin_query(q);
+    if (st != ZTS_OK)
+        throw ZtsError{st};
+}
+
 // ------------------------------------------------------------------ synchronous helpers
 
 namespace {
@@ -1792,6 +1965,9 @@ ZTS_API zts_status zts_create(const zts_ctx_params *params, zts_ctx **out)
         c.main.init();
         c.stream = c.main.stream;
         c.h_cnt.grow(64);
+        c.h_qs_noalloc.grow(sizeof(QState), hipHostMallocCoherent);  // written by the final reduction
+        std::memset(c.h_qs_noalloc.ptr, 0, sizeof(QState));
+        scratch_setup(c.device);
     } catch (const ZtsError &e) {
         c.main.destroy();
         delete z;
@@ -1819,6 +1995,7 @@ ZTS_API void zts_destroy(zts_ctx *z)
         c.colmask.reset();
         c.psat.reset();
         c.h_cnt.reset();
+        c.h_qs_noalloc.reset();
         c.main.destroy();
         release_free_blocks(&c);
     }
@@ -1968,6 +2145,23 @@ ZTS_API zts_status zts_search_device(zts_ctx *z, int32_t image, const void *tpl_
         }
         run_query_main(c, im, (const uint8_t *)tpl_dev, m, n, stride, true, (hipStream_t)stream, mode, pr, out,
                        nullptr);
+    });
+}
+
+ZTS_API zts_status zts_search_device_noalloc(zts_ctx *z, int32_t image, const void *tpl_dev, int32_t m, int32_t n,
+                                             int64_t stride, zts_mode mode, const zts_params *params, void *stream,
+                                             zts_result *out)
+{
+    if (!z || !out || !valid_mode(mode) || mode == ZTS_FULL_MFMA)
+        return ZTS_E_ARG;
+    return guarded(&z->c, [&] {
+        Ctx *c = &z->c;
+        Image *im = find_image(c, image);
+        check_template_args(im, tpl_dev, m, n, stride);
+        check_mode_shape(mode, m, n);
+        const zts_params pr = params_or_default(params);
+        hipStream_t caller = stream ? (hipStream_t)stream : c->stream;
+        run_query_noalloc(c, im, (const uint8_t *)tpl_dev, m, n, stride, caller, mode, pr, out);
     });
 }
 

@@ -209,6 +209,8 @@ int centres_record_count(int Gy, int Gx, int m, int n, int h, int w);
 // One block: the best record of [lo, hi) and the counts summed over [count_lo, hi).
 // then copies the query state to its pinned host mirror `host` and bumps qs->seq there last.
 hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s);
+// Zeroes *qs (every word, the sequence number included) with a fill kernel.
+hipError_t launch_qs_clear(QState *qs, hipStream_t s);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);

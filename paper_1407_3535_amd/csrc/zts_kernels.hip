@@ -2561,6 +2561,21 @@ hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QStat
     return hipGetLastError();
 }
 
+// Zeroes a query state (a fill kernel rather than a memset node, so the
+// launch behaves the same when a caller captures it into a graph).
+__global__ __launch_bounds__(64) void k_qs_clear(QState *qs)
+{
+    constexpr int kWords = (int)(sizeof(QState) / 8);
+    for (int k = threadIdx.x; k < kWords; k += 64)
+        ((uint64_t *)qs)[k] = 0;
+}
+
+hipError_t launch_qs_clear(QState *qs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_qs_clear, dim3(1), dim3(64), 0, s, qs);
+    return hipGetLastError();
+}
+
 int full_record_count(int Ly, int Lx) { return (int)(blocks_for(Lx, 256) * blocks_for(Ly, 4 * kFullR)); }
 
 size_t full_lds_bytes(int m, int n)

@@ -174,6 +174,7 @@ struct Ctx {
     hipStream_t stream = nullptr; // main.stream: loads, preparation, synchronous searches
     DBuf counter, tmp32, viol, colmask, psat;  // preparation scratch
     HostBuf h_cnt;
+    HostBuf h_qs_noalloc;         // host mirror of zts_search_device_noalloc's query state
     int next_id = 1;
     std::map<int, std::unique_ptr<Image>> images;
     int max_inflight = 4;
