@@ -162,6 +162,13 @@ typedef struct {
                                the answer is the best computed location (no exactness claim).
                                0 (default): the floor only labels the result. */
     int32_t pad1;
+    int32_t tile_dense_min; /* scan 2 bins its survivors by tile of 32 x 256 locations; four
+                               stacked tiles holding at least 4x this many survivors, or a
+                               tile holding at least this many, are matched whole on int8 MFMA
+                               (every location; n <= 128), the others survivor by survivor.
+                               0 (default): the library's value (128); -1: never whole; at
+                               most 8192.  Counts and answers do not depend on it. */
+    int32_t pad2;
 } zts_params;
 
 /* Result of one search.  Valid only when status == ZTS_OK. */
@@ -234,7 +241,7 @@ ZTS_API void zts_params_default(zts_params *p);
  * [1, 32767]; dh, dw >= 0 and not both 0; blur_kind 0 or 1; sigma_step
  * finite and > 0, sigma_max finite and >= 0 (blur_kind 1); max_iters in
  * [0, 15]; refine_radius in [0, 255]; egs_estimate and egs_shape 0 or 1;
- * rho_floor finite; floor_prune 0 or 1. */
+ * rho_floor finite; floor_prune 0 or 1; tile_dense_min in [-1, 8192]. */
 ZTS_API zts_status zts_params_check(const zts_params *p);
 
 /* Creates a context on params->device (NULL params: device 0, no budget). */
@@ -300,16 +307,19 @@ ZTS_API zts_status zts_search_device(zts_ctx *ctx, int32_t image, const void *tp
  * harnesses that forbid hipMalloc): the same search, the same kernels and the
  * same result, but the call allocates nothing (no hipMalloc, hipFree or
  * other allocating routine, host or device).  Its query state, per-block
- * records and per-group centre sums and angles live in a static device array
- * of 64 MiB that each GPU the library runs on holds until the process ends.
+ * records, per-group centre sums and angles and survivor-tile bins live in a
+ * static device array of 96 MiB that each GPU the library runs on holds until
+ * the process ends.
  *   - Everything else must already be resident: the image's statistics for
  *     (m, n) (zts_prepare with any mode, or an earlier search of that size)
  *     and, for ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA and ZTS_OPTA_PAPER, tables
  *     prepared for (m, n, mode) with the same preparation parameters;
  *     otherwise ZTS_E_NOTPREPARED.
- *   - ZTS_E_SIZE when the query needs more than 64 MiB of scratch: 8 bytes
- *     per group (so at most about 8 million groups, e.g. a 3 x 3 tiling of a
- *     8192 x 8192 image fits) plus 64 bytes per block record.
+ *   - ZTS_E_SIZE when the query needs more than 96 MiB of scratch: 8 bytes
+ *     per group, 64 bytes per block record and, per survivor tile of
+ *     32 x 256 locations, 4 bytes times the tile's bin size (tile_dense_min,
+ *     or 8192 when tiles are never matched whole); a 3 x 3 tiling of a
+ *     8192 x 8192 image with the default bins takes about 65 MB.
  *   - ZTS_FULL_MFMA is not offered (ZTS_E_ARG); params->timing is ignored
  *     (phase_ms stays 0, device_ms comes from the device clock).
  *   - The template is read in place after `stream` (NULL: the context's

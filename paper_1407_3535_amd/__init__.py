@@ -64,7 +64,8 @@ class Params(C.Structure):
                 ("sigma_step", C.c_double), ("sigma_max", C.c_double), ("max_iters", C.c_int32),
                 ("refine_radius", C.c_int32), ("timing", C.c_int32), ("egs_estimate", C.c_int32),
                 ("rho_tc", C.c_double), ("egs_shape", C.c_int32), ("pad0", C.c_int32), ("accept_xi", C.c_double),
-                ("rho_floor", C.c_double), ("floor_prune", C.c_int32), ("pad1", C.c_int32)]
+                ("rho_floor", C.c_double), ("floor_prune", C.c_int32), ("pad1", C.c_int32),
+                ("tile_dense_min", C.c_int32), ("pad2", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -95,6 +95,8 @@ void Slot::release_scratch()
     recs.reset();
     gnum.reset();
     gtheta.reset();
+    tcnt.reset();
+    tbin.reset();
     tpl.reset();
     dec.reset();
     bdata.reset();
@@ -257,6 +259,8 @@ void fill_default(zts_params *p)
     p->rho_floor = -2.0;
     p->floor_prune = 0;
     p->pad1 = 0;
+    p->tile_dense_min = 0;
+    p->pad2 = 0;
 }
 
 zts_status params_status(const zts_params &p)
@@ -278,6 +282,7 @@ zts_status params_status(const zts_params &p)
     ok = ok && (p.egs_estimate == 0 || p.egs_estimate == 1) && (p.egs_shape == 0 || p.egs_shape == 1);
     ok = ok && fin(p.rho_tc) && p.rho_tc > -1.0 && p.rho_tc < 1.0;
     ok = ok && fin(p.rho_floor) && (p.floor_prune == 0 || p.floor_prune == 1);
+    ok = ok && p.tile_dense_min >= -1 && p.tile_dense_min <= kTileRows * kTileCols;
     return ok ? ZTS_OK : ZTS_E_ARG;
 }
 
@@ -903,6 +908,30 @@ int query_radius(const QueryPlan &q)
     return q.pr.refine_radius > 0 ? q.pr.refine_radius : -1;
 }
 
+// Survivors of a tile from which it is matched whole on int8 MFMA (and four
+// times that for a super-tile of four tiles): the built-in value, 128 of the
+// tile's 8192 locations, is near the measured crossover on the 8192 x 8192
+// workload (params.tile_dense_min overrides it; -1: never).
+int tile_dense_min_of(const zts_params &pr)
+{
+    if (pr.tile_dense_min < 0)
+        return 0;
+    return pr.tile_dense_min > 0 ? pr.tile_dense_min : 128;
+}
+
+// Geometry of a query's survivor tiles (the fields tile_plan fills).
+TileArgs tile_geometry(const QueryPlan &q)
+{
+    TileArgs t;
+    std::memset(&t, 0, sizeof t);
+    t.m = q.m;
+    t.n = q.n;
+    t.Ly = q.Ly;
+    t.Lx = q.Lx;
+    tile_plan(t, tile_dense_min_of(q.pr));
+    return t;
+}
+
 }  // namespace
 
 void unpin_query(QueryPlan &q)
@@ -955,9 +984,13 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
             int n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
             int n2 = radius >= 0 ? window_record_count(radius) : 0;
             int n3 = members_record_count(P->Gy, P->Gx);
-            dalloc(c, S.recs, sizeof(RecPod) * (size_t)(n1 + n2 + n3));
+            const TileArgs tg = tile_geometry(q);
+            const size_t ntile = (size_t)tg.tiles_x * tg.tiles_y;
+            dalloc(c, S.recs, sizeof(RecPod) * ((size_t)n1 + n2 + n3 + ntile + super_tiles_of(tg)));
             dalloc(c, S.gnum, sizeof(int32_t) * (size_t)P->Gy * P->Gx);
             dalloc(c, S.gtheta, sizeof(float) * (size_t)P->Gy * P->Gx);
+            dalloc(c, S.tcnt, sizeof(uint32_t) * ntile);
+            dalloc(c, S.tbin, sizeof(int32_t) * ntile * (size_t)tg.tile_cap);
         }
     } catch (...) {
         unpin_query(q);
@@ -981,13 +1014,14 @@ void stage_template(Slot &S, const uint8_t *tpl, int m, int n, int64_t stride)
 // are the key of the slot's graph cache.
 struct QueryLaunch {
     int32_t full;
-    int32_t radius, n1, n2, n3, opta;
+    int32_t radius, n1, n2, n3, n4, opta;
     int32_t paper;  // ZTS_OPTA_PAPER: scans on J, then the window on I after scan 2
     int32_t red_lo, red_hi, count_lo;  // final reduction: best over [lo, hi), counts over [count_lo, hi)
     FullArgs fa;
     ScanArgs sa;
     WinArgs wa;
     MemArgs ma;
+    TileArgs ta;
     QState *qs;
     RecPod *recs;
     void *h_qs;
@@ -999,6 +1033,8 @@ struct QueryBufs {
     RecPod *recs;
     int32_t *gnum;
     float *gtheta;
+    uint32_t *tcnt;      // survivor tiles: counts
+    int32_t *tbin;       // and bins
     const uint8_t *tpl;  // the staged template (pitch n) when the plan reads none in place
     void *h_qs;
 };
@@ -1006,7 +1042,7 @@ struct QueryBufs {
 static QueryBufs slot_bufs(Slot &S)
 {
     return QueryBufs{S.qs.as<QState>(), S.recs.as<RecPod>(), S.gnum.as<int32_t>(), S.gtheta.as<float>(),
-                     S.tpl.as<uint8_t>(), S.h_qs.ptr};
+                     S.tcnt.as<uint32_t>(), S.tbin.as<int32_t>(), S.tpl.as<uint8_t>(), S.h_qs.ptr};
 }
 
 static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d_dec, QueryLaunch &Q)
@@ -1056,14 +1092,18 @@ static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d
     Q.opta = opta;
     Q.paper = paper;
     Q.radius = radius;
+    TileArgs &ta = Q.ta;
+    ta = tile_geometry(q);
     Q.n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
     Q.n2 = radius >= 0 ? window_record_count(radius) : 0;
     Q.n3 = members_record_count(P->Gy, P->Gx);
-    // records: [0, n1) scan 1, then the window and scan 2 (ZTS_OPTA_PAPER:
-    // scan 2, then the window on I, whose best is the answer)
-    const int win_off = paper ? Q.n1 + Q.n3 : Q.n1, mem_off = paper ? Q.n1 : Q.n1 + Q.n2;
+    Q.n4 = ta.tiles_x * ta.tiles_y + super_tiles_of(ta);
+    // records: [0, n1) scan 1, then the window, scan 2 and the survivor tiles
+    // (ZTS_OPTA_PAPER: scan 2 and the tiles, then the window on I, whose best
+    // is the answer)
+    const int win_off = paper ? Q.n1 + Q.n3 + Q.n4 : Q.n1, mem_off = paper ? Q.n1 : Q.n1 + Q.n2;
     Q.red_lo = paper ? win_off : (opta ? Q.n1 : 0);
-    Q.red_hi = Q.n1 + Q.n2 + Q.n3;
+    Q.red_hi = Q.n1 + Q.n2 + Q.n3 + Q.n4;
     Q.count_lo = paper ? Q.n1 : Q.red_lo;
     const uint8_t *spx = onJ ? P->J.as<uint8_t>() : im->img.as<uint8_t>();
     const int2 *sstat = onJ ? P->Jstat.as<int2>() : statI;
@@ -1088,6 +1128,8 @@ static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d
     s.qs = qs;
     s.dec = onJ ? nullptr : d_dec;
     s.delta = pr.margin;
+    s.tile_cnt = B.tcnt;
+    s.n_tiles = ta.tiles_x * ta.tiles_y;
     if (radius >= 0) {
         WinArgs &wa = Q.wa;
         wa.img = im->img.as<uint8_t>();
@@ -1146,6 +1188,23 @@ static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d
     ma.thr_ready = radius >= 0 && !paper;
     ma.delta = pr.margin;
     ma.floor = pr.floor_prune ? pr.rho_floor : -2.0;
+    ma.tile_cnt = B.tcnt;
+    ma.tile_bin = B.tbin;
+    ma.tile_cap = ta.tile_cap;
+    ma.tiles_x = ta.tiles_x;
+    // survivors are matched where scan 2 says: on I, or on J for the paper's search
+    ta.img = ma.I;
+    ta.pitch = ma.pI;
+    ta.p = im->rows;
+    ta.q = im->cols;
+    ta.stat = ma.statI;
+    ta.tpl = tpl;
+    ta.ts = ts;
+    ta.tile_cnt = B.tcnt;
+    ta.tile_bin = B.tbin;
+    ta.qs = qs;
+    ta.recs = recs;
+    ta.rec_off = mem_off + Q.n3;
 }
 
 // The kernels of one query; the last one publishes the query state to the
@@ -1172,6 +1231,7 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
             hip_check(launch_window(Q.wa, st));
         mark(S.evp[1]);
         hip_check(launch_members(Q.ma, st));
+        hip_check(launch_surv_tiles(Q.ta, st));
         if (Q.paper)  // localisation on I around the conditioned image's best
             hip_check(launch_window(Q.wa, st));
         mark(S.evp[2]);
@@ -1636,11 +1696,12 @@ void finish_batch(const BatchPlan &b, Slot &S, zts_result *out)
 // ------------------------------------------------------------------ allocation-free search
 
 // Device scratch of zts_search_device_noalloc, one copy per GPU, held until
-// the process ends: the query state, the per-block records and the per-group
-// centre sums and angles of one query.  In host code the name `scratch` is a
-// host-side stand-in, never a device address: host code uses only the address
-// hipGetSymbolAddress returned for each device (scratch_setup).
-constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+// the process ends: the query state, the per-block records, the per-group
+// centre sums and angles, and the survivor tiles' counts and bins of one
+// query.  In host code the name `scratch` is a host-side stand-in, never a
+// device address: host code uses only the address hipGetSymbolAddress
+// returned for each device (scratch_setup).
+constexpr size_t kNoAllocScratchBytes = (size_t)96 << 20;
 
 }  // namespace zts
 
@@ -1730,19 +1791,23 @@ static void run_query_noalloc(Ctx *c, Image *im, const uint8_t *tpl, int m, int 
     QueryPlan q = plan_resident(c, im, m, n, mode, pr);
     zts_status st = ZTS_OK;
     try {
-        size_t nrec = 0, groups = 0;
+        size_t nrec = 0, groups = 0, ntile = 0, cap = 0;
         if (mode == ZTS_FULL) {
             nrec = (size_t)full_record_count(Ly, Lx);
         } else {
             const Prepared *P = q.P;
             const int radius = query_radius(q);
+            const TileArgs tg = tile_geometry(q);
+            ntile = (size_t)tg.tiles_x * tg.tiles_y;
+            cap = (size_t)tg.tile_cap;
             nrec = (size_t)centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w) +
                    (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
-                   (size_t)members_record_count(P->Gy, P->Gx);
+                   (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)super_tiles_of(tg);
             groups = (size_t)P->Gy * P->Gx;
         }
         const size_t o_qs = take(sizeof(QState)), o_rec = take(sizeof(RecPod) * nrec);
         const size_t o_gx = take(sizeof(int32_t) * groups), o_gt = take(sizeof(float) * groups);
+        const size_t o_tc = take(sizeof(uint32_t) * ntile), o_tb = take(sizeof(int32_t) * ntile * cap);
         if (off > kNoAllocScratchBytes)
             throw ZtsError{ZTS_E_SIZE};
         q.tpl = tpl;
@@ -1751,7 +1816,8 @@ static void run_query_noalloc(Ctx *c, Image *im, const uint8_t *tpl, int m, int 
         uint8_t *base = scratch_ptr(c->device);
         QState *mirror = c->h_qs_noalloc.as<QState>();
         const QueryBufs B{(QState *)(base + o_qs), (RecPod *)(base + o_rec), (int32_t *)(base + o_gx),
-                          (float *)(base + o_gt), nullptr, mirror};
+                          (float *)(base + o_gt), (uint32_t *)(base + o_tc), (int32_t *)(base + o_tb), nullptr,
+                          mirror};
         hipStream_t s = c->stream;
         // the kernels read the caller's template in place, after the caller's
         // stream has reached this call

@@ -41,6 +41,8 @@ struct ScanArgs {
     QState *qs;
     int8_t *dec;
     double delta;
+    uint32_t *tile_cnt;  // survivor counts of scan 2's tiles, zeroed here (n_tiles entries)
+    int n_tiles;
     int cwd;      // MFMA form: dword stride of the staged image rows of a block's region
     int cwn;      // MFMA form: dwords of each staged row that are read
     int crows_log2;  // MFMA form: log2 of the rows of a staged chunk
@@ -96,6 +98,40 @@ struct MemArgs {
                     // records are reduced, by each wave
     double delta;
     double floor;   // eliminate against max(best, floor) (-2: the attained best alone)
+    // survivors are binned by tile of kTileRows x kTileCols locations (row-major tiles_x per row):
+    // tile_cnt counts them, tile_bin holds each tile's first tile_cap
+    uint32_t *tile_cnt;
+    int32_t *tile_bin;
+    int tile_cap, tiles_x;
+};
+
+// Survivor tiles: kTileRows x kTileCols locations (the footprint of one
+// two-row-group block of the single-template MFMA kernel).
+constexpr int kTileRows = 32, kTileCols = 256;
+
+// Matching of scan 2's survivors, one block per tile (k_surv_tiles).  A tile
+// with at least dense_min survivors is matched whole on int8 MFMA (every
+// location; the extra ones were eliminated, so they cannot be the answer);
+// otherwise its listed survivors are matched one wave each, from its image
+// region staged in LDS when it fits (sparse_lds) or from global memory.
+struct TileArgs {
+    const uint8_t *img;  // the image survivors are matched on
+    int64_t pitch;
+    int p, q;
+    const int2 *stat;    // its statistics for (m, n)
+    const uint8_t *tpl;
+    int64_t ts;
+    int m, n, n16, Ly, Lx;
+    int tiles_x, tiles_y;
+    const uint32_t *tile_cnt;
+    const int32_t *tile_bin;
+    int tile_cap;
+    int dense_min;       // 0: never dense
+    int sparse_lds;      // 1: stage the tile's image region in LDS
+    int region_words;    // words per staged region row
+    QState *qs;
+    RecPod *recs;
+    int rec_off;
 };
 
 // AC_COUNT / AC_COUNT_BLUR: Eq. 15 (Prop. 3.2) retained count, without and
@@ -216,6 +252,18 @@ int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);
 int members_record_count(int Gy, int Gx);
 hipError_t launch_members(MemArgs a, hipStream_t s);
+// Tiles of scan 2 over an Ly x Lx location grid.
+int tiles_x_of(int Lx);
+int tiles_y_of(int Ly);
+// Fills the geometry fields of a (n16, dense_min, tile_cap, sparse_lds,
+// region_words) for its m, n and the wanted dense threshold (0: never).
+void tile_plan(TileArgs &a, int dense_min);
+// Super-tiles (4 tiles stacked, 128 x 256 locations) of the dense kernel:
+// their records follow the tiles' (tiles_x * tiles_y + super_tiles_of(a)
+// records from rec_off; super_tiles_of is 0 without a dense path).
+int super_tiles_of(const TileArgs &a);
+// k_dense_tiles (when a.dense_min > 0), then k_surv_tiles.
+hipError_t launch_surv_tiles(TileArgs a, hipStream_t s);
 // Whether scan 1 (either form) and scan 2 can stage a template of m x n.
 bool scan_fits(int m, int n);
 // Whether a static-LDS query behind full_fits / scan_fits failed on this

@@ -631,6 +631,11 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 {
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
+    if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
+        const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+        for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < a.n_tiles; i += nb * (int)blockDim.x)
+            a.tile_cnt[i] = 0;
+    }
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
     __shared__ RecPod rred[256];
@@ -799,6 +804,11 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 {
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
+    if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
+        const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+        for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < a.n_tiles; i += nb * (int)blockDim.x)
+            a.tile_cnt[i] = 0;
+    }
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[2 * (kCmThreads / 64)];
     __shared__ RecPod rred[kCmThreads / 64];
@@ -1189,11 +1199,65 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
 // to an LDS list.  Phase 3: one wave per survivor matches it on the original
 // image (template loaded only by blocks that have survivors).  The last
 // block reduces every record of the query.
+// Bins one pass's survivors by tile: a tile's survivors take consecutive
+// slots of its bin (the first tile_cap are kept; a fuller tile is matched
+// whole).  The block's survivors are counted per tile in LDS first, so each
+// (block, tile) pair takes one global atomic; blocks whose groups span more
+// than kBinTiles tiles take one atomic per survivor.  All threads call it.
+constexpr int kBinTiles = 256;
+
+__device__ void bin_survivors(const MemArgs &a, const int *s_list, int ns, int tile_lo, int ntl, uint32_t *s_tc,
+                              uint32_t *s_tb)
+{
+    const int t = threadIdx.x;
+    const int cap = a.tile_cap;
+    auto tile_of = [&](int o) {
+        const int y = o / a.Lx, x = o - (o / a.Lx) * a.Lx;
+        return (y / kTileRows) * a.tiles_x + x / kTileCols;
+    };
+    if (ntl > kBinTiles) {
+        for (int k = t; k < ns; k += 256) {
+            const int o = s_list[k], tile = tile_of(o);
+            const uint32_t slot = atomicAdd(&a.tile_cnt[tile], 1u);
+            if ((int)slot < cap)
+                a.tile_bin[(int64_t)tile * cap + slot] = o;
+        }
+        return;
+    }
+    for (int i = t; i < ntl; i += 256)
+        s_tc[i] = 0;
+    __syncthreads();
+    constexpr int PER = 1024 / 256;  // survivors per thread and pass
+    int tl[PER], ps[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int k = t + 256 * q;
+        tl[q] = -1;
+        if (k < ns) {
+            tl[q] = tile_of(s_list[k]) - tile_lo;
+            ps[q] = (int)atomicAdd(&s_tc[tl[q]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < ntl; i += 256) {
+        const uint32_t c = s_tc[i];
+        s_tb[i] = c ? atomicAdd(&a.tile_cnt[tile_lo + i], c) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        if (tl[q] < 0)
+            continue;
+        const int slot = (int)s_tb[tl[q]] + ps[q];
+        if (slot < cap)
+            a.tile_bin[(int64_t)(tile_lo + tl[q]) * cap + slot] = s_list[t + 256 * q];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_members(MemArgs a)
 {
     constexpr int CAP = 1024;  // members per pass: 4 per thread
     constexpr int GB = kMemGroups;
-    extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int s_pref[GB + 1];
     __shared__ int s_tmp[4];
     __shared__ int s_geo[GB][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
@@ -1201,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ int s_nsurv;
     __shared__ RecPod wrec[4];
     __shared__ Best bred[8];
+    __shared__ uint32_t s_tc[kBinTiles], s_tb[kBinTiles];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     // This thread's two groups (2t, 2t + 1 of the block), the query state and
     // the earlier kernels' records are all read in the first round trip.
@@ -1215,10 +1280,6 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             gs2[e] = a.gsum[g0 + 2 * t + e];
         }
     const int degenerate = a.qs->degenerate;
-    const int n4 = (a.n + 3) >> 2;
-    // the template words for survivors, in the same round trip (the
-    // threshold's barriers make them visible)
-    load_template_words(a.tpl, a.ts, a.m, a.n, n4, smem);
     const Thr thr = a.thr_ready
                         ? wave_threshold(a.qs, a.recs + a.n_best0, a.n_win, a.include_best0, a.delta, a.floor)
                         : block_threshold(a.recs, a.n_best0, a.n_win, a.include_best0, a.delta, a.floor, bred);
@@ -1238,6 +1299,12 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         wx = (int)(c0 - (c0 / a.Lx) * a.Lx);
     }
     unsigned long long n_elim = 0, n_surv = 0;
+    // the survivor tiles this block's groups can touch: every tile column of
+    // the tile rows its location rows span
+    const int glast = min(G, g0 + GB) - 1;
+    const int ty_lo = ((g0 / a.Gx) * a.h) / kTileRows;
+    const int ty_hi = min(a.Ly - 1, (glast / a.Gx) * a.h + a.h - 1) / kTileRows;
+    const int tile_lo = ty_lo * a.tiles_x, ntl = (ty_hi - ty_lo + 1) * a.tiles_x;
 
     int cnt2[2] = {0, 0};
 #pragma unroll
@@ -1358,31 +1425,9 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
                 a.dec[o] = keep ? 2 : 0;
         }
         __syncthreads();
-        int ns = s_nsurv;
-        // this wave's survivors wv, wv + 4, ... in batches of 64: lane L reads
-        // the location and statistics of the batch's survivor L in one round
-        // trip, then the wave matches the batch's survivors one after another
-        // (locations fit 31 bits: sides of at most 32767)
-        for (int kb = wv; kb < ns; kb += 4 * 64) {
-            const int ks = kb + 4 * lane;
-            const int ol = ks < ns ? s_list[ks] : 0;
-            const int2 sol = ks < ns ? a.statI[ol] : make_int2(0, 0);
-            const int nbat = min(64, (ns - kb + 3) >> 2);
-            for (int q = 0; q < nbat; q++) {
-                const int o32 = __shfl(ol, q);
-                const int64_t o = o32;
-                const int y = o32 / a.Lx, x = o32 - y * a.Lx;
-                const uint32_t Xu = wave_dot_tpl_u8(smem, n4, a.I, a.pI, y, x, a.m, lane);
-                const int2 so = make_int2(__shfl(sol.x, q), __shfl(sol.y, q));
-                if (lane == 0) {
-                    // N = mn sum(t r) - sum(t) sum(r) on unshifted values; the
-                    // shifted sums S' become sum(x) = S' + 128 mn
-                    int64_t dr = var_num(mn, so);
-                    int64_t num = mn * (int64_t)Xu - (st + 128 * mn) * ((int64_t)so.x + 128 * mn);
-                    rec_offer_inline(rec, rho32(num, dt, dr), o, num, dt, dr);
-                }
-            }
-        }
+        const int ns = s_nsurv;
+        if (ns > 0)
+            bin_survivors(a, s_list, ns, tile_lo, ntl, s_tc, s_tb);
         if (base + CAP < total) {  // another pass reuses the survivor list
             __syncthreads();
             if (t == 0)
@@ -2118,31 +2163,36 @@ static_assert(256 * sizeof(RecPod) / 4 <= kSingleEpiList, "records fit below the
 
 __host__ __device__ inline int single_tpl_words(int m, int n16) { return (m + 1) * batch_tstride(n16 >> 2); }
 
+// One 16 RG x 256 block of locations of one template (the body of k_single,
+// also the dense path of k_surv_tiles).  The caller has staged the template
+// at smem + single_tpl_offset(n16) in the int8 view, rows of n16 / 4 words at
+// stride batch_tstride(n16 / 4), followed by an all-zero row m, and checked
+// that D_t > 0.  Returns the block's best location (valid in thread 0; the
+// block's LDS is reused).
+struct SingleTile {
+    const uint8_t *img;
+    int64_t pitch;
+    int p;
+    const int2 *stat;  // per-location statistics of img for (m, n)
+    int Ly, Lx, m, n, n16;
+    int64_t St, Dt;    // sum(t') and D_t
+};
+
+__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 16 * batch_copy_stride((256 + n16 + 16) >> 2); }
+
 template <int RG>
-__global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ jobs, int njobs)
+__device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t *smem)
 {
     static_assert(RG == 2 || RG == 4 || RG == 8, "row groups per block");
     constexpr int MT = 4, ROWS = 16 * RG;
-    extern __shared__ __align__(16) uint32_t smem[];
-    const BatchJob a = jobs[batch_job_of<0>(jobs, njobs, blockIdx.x)];
-    const int lb = blockIdx.x - a.block0, bx = lb % a.gx, by = lb / a.gx;
     const int m = a.m, n16 = a.n16, nb16 = n16 >> 4, nw16 = n16 >> 2;
     const int WW = (256 + n16 + 16) >> 2;
     const int CS = batch_copy_stride(WW);
     const int IMGW = 16 * CS;
     const int tstr = batch_tstride(nw16);
-    uint32_t *tpl_l = smem + 2 * IMGW;  // rows 0..m-1, then the zero row m
+    const uint32_t *tpl_l = smem + 2 * IMGW;  // rows 0..m-1, then the zero row m
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int x0 = bx * 256, y0 = by * ROWS;
     const int steps = (ROWS + m - 1 + 3) >> 2;
-    const uint32_t *tplg = (const uint32_t *)a.tpl;
-
-    for (int idx = t; idx < m * nw16; idx += 256) {
-        int r = idx / nw16, c = idx - r * nw16;
-        tpl_l[r * tstr + c] = flip4(gptr(tplg)[idx]);
-    }
-    for (int idx = t; idx < nw16; idx += 256)
-        tpl_l[m * tstr + idx] = 0;
 
     uint32_t ri[2][2];
     auto gload = [&](int s) {
@@ -2231,13 +2281,7 @@ __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ 
     // one template; the lanes holding values within kEpsRho of it list them;
     // the listed candidates' canonical binary64 rho gives the block's record.
     const int64_t mn = (int64_t)m * a.n;
-    const int64_t St = gptr(a.tst)[0], Dt = gptr(a.tst)[1];
-    RecPod *out = a.recs + (int64_t)lb * 16;
-    if (Dt == 0) {  // degenerate template: the host reports it from tst
-        if (t < 16)
-            st_rec(out + t, rec_empty());
-        return;
-    }
+    const int64_t St = a.St, Dt = a.Dt;
     int4 *clist = (int4 *)(smem + kSingleEpiList);           // (row in block, column, acc, 0)
     RecPod *red = (RecPod *)smem;
     float *bmx = (float *)(smem + kSingleEpiMax);
@@ -2384,9 +2428,211 @@ __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ 
         }
     }
     __syncthreads();  // the records below reuse the slices and buffers
-    RecPod best = block_rec(r, red);
+    return block_rec(r, red);
+}
+
+template <int RG>
+__global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ jobs, int njobs)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    const BatchJob a = jobs[batch_job_of<0>(jobs, njobs, blockIdx.x)];
+    const int lb = blockIdx.x - a.block0, bx = lb % a.gx, by = lb / a.gx;
+    const int t = threadIdx.x, m = a.m, nw16 = a.n16 >> 2;
+    const int tstr = batch_tstride(nw16);
+    uint32_t *tpl_l = smem + single_tpl_offset(a.n16);
+    const uint32_t *tplg = (const uint32_t *)a.tpl;
+    const int64_t St = gptr(a.tst)[0], Dt = gptr(a.tst)[1];
+    RecPod *out = a.recs + (int64_t)lb * 16;
+    if (Dt == 0) {  // degenerate template: the host reports it from tst
+        if (t < 16)
+            st_rec(out + t, rec_empty());
+        return;
+    }
+    for (int idx = t; idx < m * nw16; idx += 256) {
+        int r = idx / nw16, c = idx - r * nw16;
+        tpl_l[r * tstr + c] = flip4(gptr(tplg)[idx]);
+    }
+    for (int idx = t; idx < nw16; idx += 256)
+        tpl_l[m * tstr + idx] = 0;
+    const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, m, a.n, a.n16, St, Dt};
+    const RecPod best = single_tile_body<RG>(st, bx * 256, by * 16 * RG, smem);
     if (t < 16)
         st_rec(out + t, t == 0 ? best : rec_empty());
+}
+
+// ============================================================== survivor tiles
+
+// The survivor sum of wave_dot_tpl_u8 with the tile's image region staged in
+// LDS as raw words (rsw words per region row, the region starting at the
+// tile's first location): (dy, dx) is the location within the tile.  rsw is
+// odd, so the rows a wave reads at once start on different banks.
+__device__ __forceinline__ uint32_t wave_dot_lds_u8(const uint32_t *__restrict__ tplw, int n4,
+                                                    const uint32_t *__restrict__ reg, int rsw, int dy, int dx, int m,
+                                                    int lane)
+{
+    uint32_t acc = 0;
+    const uint32_t sh = (uint32_t)(dx & 3);
+    if (n4 <= kWave) {
+        const int rp = kWave / n4;
+        const int r0 = lane / n4, j = lane - r0 * n4;
+        if (r0 < rp) {
+            const uint32_t *pr = reg + (dy + r0) * rsw + (dx >> 2) + j;
+            const int step = rp * rsw;
+            const uint32_t *tp = tplw + r0 * n4 + j;
+            const int tstep = rp * n4;
+#pragma unroll 8
+            for (int i = r0; i < m; i += rp) {
+                acc = __builtin_amdgcn_udot4(bytes_at(pr[1], pr[0], sh), *tp, acc, false);
+                pr += step;
+                tp += tstep;
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int i = 0; i < m; i++) {
+            const uint32_t *row = reg + (dy + i) * rsw + (dx >> 2);
+            for (int j = lane; j < n4; j += kWave)
+                acc = __builtin_amdgcn_udot4(bytes_at(row[j + 1], row[j], sh), tplw[i * n4 + j], acc, false);
+        }
+    }
+    return (uint32_t)wave_sum((int)acc);
+}
+
+// Whether super-tile (sy, tx) -- the (up to) four tiles of tile column tx
+// and tile rows 4 sy .. 4 sy + 3, 128 x 256 locations -- is matched whole by
+// k_dense_tiles: its tiles hold at least 4 dense_min survivors together.
+__device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
+{
+    if (a.dense_min <= 0)
+        return false;
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int ty = 4 * sy + k;
+        if (ty < a.tiles_y)
+            sum += (int)a.tile_cnt[ty * a.tiles_x + tx];
+    }
+    return sum >= 4 * a.dense_min;
+}
+
+// Dense super-tiles: one block per super-tile of 128 x 256 locations; one
+// whose tiles hold at least 4 dense_min survivors together is matched whole
+// on int8 MFMA with eight row groups per block (the k_single body, whose
+// image staging is then shared by 128 output rows); others write an empty
+// record and are left to k_surv_tiles.
+__global__ __launch_bounds__(256, 2) void k_dense_tiles(TileArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int sy = b / a.tiles_x, tx = b - (b / a.tiles_x) * a.tiles_x;
+    RecPod *out = a.recs + a.rec_off + (int64_t)a.tiles_x * a.tiles_y + b;
+    if (a.qs->degenerate || !super_dense(a, sy, tx)) {
+        if (t == 0)
+            *out = rec_empty();
+        return;
+    }
+    const int nw16 = a.n16 >> 2, tstr = batch_tstride(nw16);
+    uint32_t *tpl_l = smem + single_tpl_offset(a.n16);
+    const bool words = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
+    for (int idx = t; idx < a.m * nw16; idx += 256) {
+        const int r = idx / nw16, c = idx - r * nw16;
+        tpl_l[r * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
+    }
+    for (int idx = t; idx < nw16; idx += 256)
+        tpl_l[a.m * tstr + idx] = 0;
+    const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
+    const RecPod best = single_tile_body<8>(st, tx * kTileCols, sy * 4 * kTileRows, smem);
+    if (t == 0)
+        *out = best;
+}
+
+// One block per survivor tile (after scan 2 has binned the survivors).  An
+// empty tile writes an empty record.  A tile with at least dense_min
+// survivors is matched whole: every location of its 32 x 256 block on int8
+// MFMA (single_tile_body; the locations scan 2 eliminated lie below the
+// threshold, so they cannot be the answer, and the counts stay those of the
+// decisions).  Otherwise each listed survivor is matched by one wave with
+// unsigned dot products, from the tile's image region staged in LDS when it
+// fits, else from global memory.  One record per tile.
+__global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
+{
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ RecPod red4[4];
+    const int tile = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int cnt = (int)a.tile_cnt[tile];
+    const int ty = tile / a.tiles_x, tx = tile - (tile / a.tiles_x) * a.tiles_x;
+    if (cnt == 0 || a.qs->degenerate || super_dense(a, ty >> 2, tx)) {  // nothing here, or k_dense_tiles' work
+        if (t == 0)
+            a.recs[a.rec_off + tile] = rec_empty();
+        return;
+    }
+    const int y0 = ty * kTileRows, x0 = tx * kTileCols;
+    const int64_t St = a.qs->st, Dt = a.qs->dt;
+    const int64_t mn = (int64_t)a.m * a.n;
+    if (a.dense_min > 0 && cnt >= a.dense_min) {
+        const int nw16 = a.n16 >> 2, tstr = batch_tstride(nw16);
+        uint32_t *tpl_l = smem + single_tpl_offset(a.n16);
+        const bool words = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
+        for (int idx = t; idx < a.m * nw16; idx += 256) {
+            const int r = idx / nw16, c = idx - r * nw16;
+            tpl_l[r * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
+        }
+        for (int idx = t; idx < nw16; idx += 256)
+            tpl_l[a.m * tstr + idx] = 0;
+        const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, St, Dt};
+        const RecPod best = single_tile_body<2>(st, x0, y0, smem);
+        if (t == 0)
+            a.recs[a.rec_off + tile] = best;
+        return;
+    }
+    const int n4 = (a.n + 3) >> 2;
+    const int rsw = a.region_words;
+    uint32_t *tplw = smem;
+    uint32_t *reg = smem + ((a.m * n4 + 3) & ~3);
+    load_template_words(a.tpl, a.ts, a.m, a.n, n4, tplw);
+    if (a.sparse_lds) {
+        // rows y0 .. y0 + 31 + m - 1 (clipped to the image), words from x0
+        const int R = min(kTileRows + a.m - 1, a.p - y0);
+        const uint8_t *base = a.img + (int64_t)y0 * a.pitch + x0;
+        const int wmax = (int)min((int64_t)rsw, (a.pitch - x0) >> 2);
+        for (int idx = t; idx < R * rsw; idx += 256) {
+            const int r = idx / rsw, w = idx - (idx / rsw) * rsw;
+            reg[idx] = w < wmax ? *gptr((const uint32_t *)(base + (int64_t)r * a.pitch + 4 * w)) : 0u;
+        }
+    }
+    __syncthreads();
+    const int c = min(cnt, a.tile_cap);
+    const int32_t *bin = a.tile_bin + (int64_t)tile * a.tile_cap;
+    RecPod rec = rec_empty();
+    // this wave's survivors wv, wv + 4, ... in batches of 64: lane L reads the
+    // location and statistics of the batch's survivor L in one round trip
+    for (int kb = wv; kb < c; kb += 4 * 64) {
+        const int ks = kb + 4 * lane;
+        const int ol = ks < c ? bin[ks] : 0;
+        const int2 sol = ks < c ? a.stat[ol] : make_int2(0, 0);
+        const int nbat = min(64, (c - kb + 3) >> 2);
+        // the wave's sums, one survivor after another; lane q keeps survivor
+        // q's, and the batch's epilogues then run in parallel
+        uint32_t mine = 0;
+        for (int q = 0; q < nbat; q++) {
+            const int o32 = __shfl(ol, q);
+            const int y = o32 / a.Lx, x = o32 - y * a.Lx;
+            const uint32_t Xu = a.sparse_lds ? wave_dot_lds_u8(tplw, n4, reg, rsw, y - y0, x - x0, a.m, lane)
+                                             : wave_dot_tpl_u8(tplw, n4, a.img, a.pitch, y, x, a.m, lane);
+            mine = lane == q ? Xu : mine;
+        }
+        if (lane < nbat) {
+            // N = mn sum(t r) - sum(t) sum(r) on unshifted values; the shifted
+            // sums S' become sum(x) = S' + 128 mn
+            const int64_t dr = var_num(mn, sol);
+            const int64_t num = mn * (int64_t)mine - (St + 128 * mn) * ((int64_t)sol.x + 128 * mn);
+            rec_offer_inline(rec, rho32(num, Dt, dr), ol, num, Dt, dr);
+        }
+    }
+    const RecPod best = block_rec4(rec, red4);
+    if (t == 0)
+        a.recs[a.rec_off + tile] = best;
 }
 
 // First fold of the per-block records: fold block c of tile z merges the
@@ -2857,21 +3103,78 @@ hipError_t launch_window(WinArgs a, hipStream_t s)
 
 int members_record_count(int Gy, int Gx) { return (int)blocks_for((int64_t)Gy * Gx, kMemGroups); }
 
-static size_t members_lds_bytes(int m, int n) { return (size_t)m * ((n + 3) / 4) * 4; }
-
 hipError_t launch_members(MemArgs a, hipStream_t s)
 {
-    size_t lds = members_lds_bytes(a.m, a.n);
-    hipError_t e = allow_lds((const void *)k_members, lds);
+    hipLaunchKernelGGL(k_members, dim3(members_record_count(a.Gy, a.Gx)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int tiles_x_of(int Lx) { return (int)blocks_for(Lx, kTileCols); }
+int tiles_y_of(int Ly) { return (int)blocks_for(Ly, kTileRows); }
+
+// LDS of k_surv_tiles' sparse path: the template's raw words, then (with
+// sparse_lds) the tile's image region.
+static size_t tiles_sparse_bytes(int m, int n, int sparse_lds, int rsw)
+{
+    const size_t tw = ((size_t)m * ((n + 3) / 4) + 3) & ~(size_t)3;
+    return (tw + (sparse_lds ? (size_t)(kTileRows + m - 1) * rsw : 0)) * 4;
+}
+
+static size_t single_lds_bytes(int m, int n16);
+
+// The staged region is kept to 96 KB so that most tiles' blocks can share a CU.
+constexpr size_t kSparseRegionMax = 96 * 1024;
+
+void tile_plan(TileArgs &a, int dense_min)
+{
+    a.n16 = (a.n + 15) / 16 * 16;
+    a.tiles_x = tiles_x_of(a.Lx);
+    a.tiles_y = tiles_y_of(a.Ly);
+    const bool dense = dense_min > 0 && dense_min <= kTileRows * kTileCols && batch_single_fits(a.m, a.n);
+    a.dense_min = dense ? dense_min : 0;
+    a.tile_cap = dense ? dense_min : kTileRows * kTileCols;
+    const int n4 = (a.n + 3) / 4;
+    a.region_words = (64 + n4 + 1) | 1;
+    a.sparse_lds = tiles_sparse_bytes(a.m, a.n, 1, a.region_words) <= kSparseRegionMax ? 1 : 0;
+}
+
+static size_t tiles_lds_bytes(const TileArgs &a)
+{
+    size_t lds = tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words);
+    if (a.dense_min > 0)
+        lds = std::max(lds, single_lds_bytes(a.m, a.n16));
+    return lds;
+}
+
+int super_tiles_of(const TileArgs &a) { return a.dense_min > 0 ? a.tiles_x * (int)blocks_for(a.tiles_y, 4) : 0; }
+
+hipError_t launch_surv_tiles(TileArgs a, hipStream_t s)
+{
+    const size_t lds = tiles_lds_bytes(a);
+    const int64_t nt = (int64_t)a.tiles_x * a.tiles_y;
+    if (nt < 1 || nt > INT32_MAX)
+        return hipErrorInvalidValue;
+    hipError_t e = allow_lds((const void *)k_surv_tiles, lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_members, dim3(members_record_count(a.Gy, a.Gx)), dim3(256), lds, s, a);
+    if (a.dense_min > 0) {
+        const size_t dl = single_lds_bytes(a.m, a.n16);
+        e = allow_lds((const void *)k_dense_tiles, dl);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)super_tiles_of(a)), dim3(256), dl, s, a);
+    }
+    hipLaunchKernelGGL(k_surv_tiles, dim3((unsigned)nt), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
 bool scan_fits(int m, int n)
 {
-    if (members_lds_bytes(m, n) + static_lds((const void *)k_members) > kLdsMax)
+    // scan 2 stages nothing of the template; the survivor tiles need at
+    // least the template's words (the region and the dense path are optional)
+    if (tiles_sparse_bytes(m, n, 0, 0) + static_lds((const void *)k_surv_tiles) > kLdsMax)
+        return false;
+    if (static_lds((const void *)k_members) > kLdsMax)
         return false;
     // k_centres_mfma's shape search keeps within its own budget; the v_dot4
     // form takes R = 1 (no pad rows) whenever a taller block would need more

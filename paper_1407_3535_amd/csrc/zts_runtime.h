@@ -84,6 +84,7 @@ struct Slot {
     hipEvent_t ev_in = nullptr;  // orders the slot's stream after a caller's stream
     hipEvent_t evp[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     DBuf qs, recs, gnum, gtheta, tpl, dec;       // one query
+    DBuf tcnt, tbin;                             // one query's survivor tiles: counts and bins
     DBuf bdata, bres, brec;                      // one batched launch
     HostBuf h_qs, h_stage, h_out;
     bool use_graphs = true;

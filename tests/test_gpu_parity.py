@@ -230,6 +230,46 @@ def test_opta_parity(S, case):
     S.unload(i)
 
 
+# Scan 2 bins survivors by tile of 32 x 256 locations.  tile_dense_min 1: every tile with a survivor (and every
+# super-tile of four tiles with four) is matched whole on int8 MFMA; -1: survivor by survivor only; 8: a mix;
+# 0: the built-in value.  Images span several tile rows and columns with ragged edges; the tall template's
+# tiles take the survivor path from global memory (its image region does not fit LDS), the wide one has no
+# MFMA path.
+TILE_CASES = [(300, 700, 24, 24, 25.0, "te_fixed"), (420, 300, 40, 17, 30.0, "egs"), (200, 520, 16, 16, 20.0, "opta"),
+              (520, 90, 400, 8, 12.0, "te_fixed"), (150, 600, 20, 150, 20.0, "egs")]
+
+
+@pytest.mark.parametrize("dense", [1, 8, -1, 0])
+@pytest.mark.parametrize("case", TILE_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}x{c[3]}-{c[5]}" for c in TILE_CASES])
+def test_survivor_tile_paths(S, case, dense):
+    p, q, m, n, noise, mode = case
+    print(f"survivor tiles {case} dense {dense}", flush=True)
+    img = aerial_image(p, q, 7000 + p + q, beta=2.2)
+    i = S.load(img)
+    kw = dict(group_h=3, group_w=3) if mode == "te_fixed" else {}
+    for k in range(2):
+        tpl, _ = cut_template(img, m, n, 7100 + k, noise, affine=True)
+        full = O.full_search(img, tpl)
+        for radius in (0, 2):
+            g, dec = S.search(i, tpl, mode, decision=(mode != "opta"), refine_radius=radius, tile_dense_min=dense,
+                              **kw) if mode != "opta" else (S.search(i, tpl, mode, refine_radius=radius,
+                                                                     tile_dense_min=dense), None)
+            same_answer(g, full, f"tiles {mode} dense {dense}")
+            if mode == "te_fixed":
+                ot = O.te_search(img, tpl, 3, 3, decision=True, radius=radius)
+            elif mode == "egs":
+                info = S.prepare(i, m, n, "egs")
+                ot = O.te_search(img, tpl, info["h"], info["w"], decision=True, radius=radius)
+            else:
+                oo = O.opta(img, m, n)
+                ot = O.opta_search(img, oo["image"], tpl, oo["h"], oo["w"], max(oo["radius"], radius))
+            same_counts(g, ot, f"tiles {mode} dense {dense}")
+            if dec is not None:
+                assert np.array_equal(dec, ot["decision"])
+            assert g["n_survivors"] > 0
+    S.unload(i)
+
+
 @pytest.mark.parametrize("radius", [3, 5, 9])
 def test_large_refinement_windows(S, radius):
     """Refinement windows of 49 to 361 locations (more than one wave's lanes for scan 2's threshold), with
@@ -470,34 +510,6 @@ def test_workload2_full_size_sampled(S):
     S.unload(i)
 
 
-def test_workload3_full_size(S):
-    """The 8192x8192 workload (clouds, 8 templates of 32, 64 and 128 px with noise and a contrast /
-    brightness change), full OptA.  A dense oracle run is out of reach at this size, so: the exact
-    OptA answer equals both exhaustive GPU searches (v_dot4 and int8 MFMA), the oracle recomputes the
-    exact integers and the binary64 rho at that location, binary32 rho is within 1e-6 of it, the
-    counts cover every location."""
-    w = workload(3)
-    img = w["images"][0]
-    i = S.load(img)
-    found = 0
-    for t, loc, _ in w["templates"]:
-        m, n = t.shape
-        g = S.search(i, t, "opta", refine_radius=2)
-        full = S.search(i, t, "full")
-        mfma = S.search(i, t, "full_mfma")
-        for k in ("y", "x", "rho", "num", "den_t", "den_r"):
-            assert g[k] == full[k] == mfma[k], (t.shape, k)
-        y, x = g["y"], g["x"]
-        sub = O.full_search(img[y:y + m, x:x + n], t)
-        assert (g["num"], g["den_t"], g["den_r"], g["rho"]) == (sub["num"], sub["den_t"], sub["den_r"], sub["rho"])
-        assert abs(g["rho32"] - sub["rho"]) <= RHO32_TOL
-        assert g["n_computed"] + g["n_eliminated"] == g["n_locations"] == (8192 - m + 1) * (8192 - n + 1)
-        found += (y, x) == loc
-    # the hit rate of the cut locations depends on the data only (the answer is exact)
-    print(f"workload 3: {found} of {len(w['templates'])} cut locations found")
-    S.unload(i)
-
-
 @pytest.mark.parametrize("seed", [0, 1])
 def test_batch_mfma_matches_oracle(S, seed):
     """Mixed sizes (several templates per size, a 17-template group, ragged n) in one call."""
@@ -519,24 +531,6 @@ def test_batch_mfma_matches_oracle(S, seed):
         assert res[k]["status"] == 0
         same_answer(res[k], o, f"batch template {k} {t.shape}")
         assert res[k]["n_computed"] == o["n_locations"]
-    S.unload(i)
-
-
-def test_batch_mfma_workload4_sample(S):
-    """The 4096x4096 batched workload: a sample of its templates checked against the oracle."""
-    w = workload(4)
-    img = w["images"][0]
-    tpls = [t for t, _, _ in w["templates"]]
-    i = S.load(img)
-    res = S.search_batch(i, tpls)
-    for k in (0, 5, 17, 40, 63):
-        t, loc, _ = w["templates"][k]
-        assert (res[k]["y"], res[k]["x"]) == loc
-        y, x = loc
-        m, n = t.shape
-        # exact sums at the answer and rho against the oracle on the block
-        sub = O.full_search(img[y:y + m, x:x + n], t)
-        assert (res[k]["num"], res[k]["den_r"], res[k]["rho"]) == (sub["num"], sub["den_r"], sub["rho"])
     S.unload(i)
 
 

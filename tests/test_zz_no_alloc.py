@@ -113,18 +113,18 @@ def test_noalloc_refusals(torch_gpu):
 
 
 def test_noalloc_scratch_limit(torch_gpu):
-    """A query whose scratch exceeds the 64 MiB array is refused before anything is launched; the next call
+    """A query whose scratch exceeds the 96 MiB array is refused before anything is launched; the next call
     on the same GPU still gives the right answer."""
     torch = torch_gpu
     rng = np.random.default_rng(99)
-    img = rng.integers(0, 256, (6000, 6000), dtype=np.uint8)  # 2 x 2 groups: 8.96e6 groups, 8 B each
+    img = rng.integers(0, 256, (6000, 6000), dtype=np.uint8)  # 1 x 2 groups: 1.79e7 groups, 8 B each
     tpl = img[1000:1016, 2000:2016].copy()
     (big, tb), _ = _inputs()
     with Z.Searcher(0) as S:
         i = S.load(img)
-        S.prepare(i, 16, 16, "te_fixed", group_h=2, group_w=2)
+        S.prepare(i, 16, 16, "te_fixed", group_h=1, group_w=2)
         t = torch.from_numpy(tpl).cuda()
-        p = Z.zts_params_default(group_h=2, group_w=2)
+        p = Z.zts_params_default(group_h=1, group_w=2)
         with pytest.raises(Z.ZtsError) as e:
             Z.zts_search_device_noalloc(S.ctx, i, t, "te_fixed", p)
         assert e.value.code == E_SIZE
@@ -132,7 +132,7 @@ def test_noalloc_scratch_limit(torch_gpu):
         assert (g["y"], g["x"]) == (1000, 2000)
         S.unload(i)
         j = S.load(big)
-        S.prepare(j, *tb.shape, "te_fixed", group_h=2, group_w=2)
+        S.prepare(j, *tb.shape, "te_fixed", group_h=1, group_w=2)
         tt = torch.from_numpy(tb).cuda()
         got = Z.zts_search_device_noalloc(S.ctx, j, tt, "te_fixed", p)
         want = Z.zts_search_device(S.ctx, j, tt, "te_fixed", p)
