@@ -168,7 +168,7 @@ def main():
                                     ("egs_rho_th0.95_refine2", "egs", 2, {"rho_th": 0.95})]:
             rr, mms, ll, pp = run(mode, ref, 20, 3, **kw)
             modes[name] = {"ms_per_query": round(mms, 4), "locations_per_s": L / (mms / 1e3),
-                           "device_ms": round(rr["device_ms"], 4), "phase_ms": [round(x, 4) for x in pp[:4]],
+                           "device_ms": round(rr["device_ms"], 4), "phase_ms": [round(x, 4) for x in pp[:5]],
                            "n_computed": rr["n_computed"], "n_centres": rr["n_centres"],
                            "n_eliminated": rr["n_eliminated"], "group": [rr["group_h"], rr["group_w"]],
                            "answer": [rr["y"], rr["x"], rr["rho"]]}
@@ -207,18 +207,19 @@ def main():
 
     # Dominant kernel of the timed mode (by its HIP-event time) and its
     # algorithmic work.  Scan 1 on int8 MFMA: 2 mn ops per group centre,
-    # against the dense int8 MFMA peak.  Scan 2: HBM bytes it must read at
-    # least, 20 per group (its angle and range summary) plus mn + 8 per
-    # window or survivor location it matches.  The plain full kernel (VALU
-    # dot4): 2 mn ops per location against the derived dot4 peak.
+    # against the dense int8 MFMA peak.  Scan 2's tests: the 20 B per group
+    # they must read (its angle and range summary), HBM.  Survivor tiles:
+    # 2 mn ops per location matched in dense tiles, int8 MFMA.  The plain
+    # full kernel (VALU dot4): 2 mn ops per location against the derived
+    # dot4 peak.
     mn = m * n
     if args.mode == "full":
         kernels = [("k_full", ph[0], "alu", PEAK_DOT4_TOPS, "TOP/s", 2.0 * mn * L)]
     else:
         G = r["n_centres"]
-        matched = r["n_computed"] - (0 if args.mode == "opta" else G)
         kernels = [("k_centres_mfma", ph[0], "mfma", PEAK_MFMA_I8_TOPS, "TOP/s", 2.0 * mn * G),
-                   ("k_members", ph[2], "hbm", PEAK_HBM_GBS, "GB/s", 20.0 * G + (mn + 8.0) * matched)]
+                   ("k_members", ph[2], "hbm", PEAK_HBM_GBS, "GB/s", 20.0 * G),
+                   ("survivor_tiles", ph[4], "mfma", PEAK_MFMA_I8_TOPS, "TOP/s", 2.0 * mn * r["n_dense"])]
     name, kms, bound, peak, unit, work = max(kernels, key=lambda k: k[1])
     scale = 1e12 if unit == "TOP/s" else 1e9
     achieved = work / (kms / 1e3) / scale if kms > 0 else 0.0
@@ -368,7 +369,7 @@ def bench_satellite(args):
 
     # per-kernel device times of the same queries (HIP events after each kernel on the library's stream;
     # the timed loop replays captured graphs, which carry no events)
-    phase = np.zeros((len(tpls), 4))
+    phase = np.zeros((len(tpls), 6))
     reps = 5
     for _ in range(reps):
         for k, t in enumerate(tdev):
@@ -415,32 +416,36 @@ def bench_satellite(args):
                       "phase_ms": [round(x, 4) for x in phase[k]], "group": [r["group_h"], r["group_w"]],
                       "n_centres": r["n_centres"], "n_computed": r["n_computed"],
                       "n_matched_incl_centres": r["n_computed"] + (r["n_centres"] if mode == "opta" else 0),
-                      "n_eliminated": r["n_eliminated"], "n_survivors": r["n_survivors"],
+                      "n_eliminated": r["n_eliminated"], "n_survivors": r["n_survivors"], "n_dense": r["n_dense"],
                       "answer": [r["y"], r["x"], r["rho"]], "cut_location_found": (r["y"], r["x"]) == tuple(loc)})
 
-    # dominant kernel over one step and its algorithmic work.  Scan 1 (k_centres_mfma): 2 mn int8 ops per
-    # group centre on MFMA.  Scan 2 (k_members): the group and member tests read at least 20 B per group and
-    # 8 B of statistics per survivor from HBM, and each survivor costs 2 mn int8 ops of v_dot4 on the VALU;
-    # the bound reported is the one of the two that the kernel's time comes nearer to.
+    # Per-kernel rooflines over one step (HIP-event times summed over the 8 queries) and the dominant one.
+    #   k_centres_mfma (scan 1): 2 mn int8 ops per group centre, int8 MFMA peak.
+    #   k_members (scan 2's tests): the 20 B per group it must read (angle of the centre and the group's
+    #     range summary), HBM; member angles are read only for groups that do not fall whole.
+    #   survivor tiles (k_dense_tiles + k_surv_tiles): 2 mn int8 ops per location matched in dense tiles
+    #     (n_dense) plus 2 mn per survivor outside them (at most n_survivors), int8 MFMA peak.
     kern = {"k_centres_mfma": float(phase[:, 0].sum()), "k_window": float(phase[:, 1].sum()),
-            "k_members": float(phase[:, 2].sum()), "k_reduce": float(phase[:, 3].sum())}
-    ops1 = sum(2.0 * t.size * r["n_centres"] for (t, _), r in zip(tpls, got))
-    bytes2 = sum(20.0 * r["n_centres"] + 8.0 * r["n_survivors"] for r in got)
-    ops2 = sum(2.0 * t.size * r["n_survivors"] for (t, _), r in zip(tpls, got))
-    if kern["k_centres_mfma"] >= kern["k_members"]:
-        name, kms, bound, peak, unit, work = ("k_centres_mfma", kern["k_centres_mfma"], "mfma", PEAK_MFMA_I8_TOPS,
-                                              "TOP/s", ops1)
-    elif ops2 / PEAK_DOT4_TOPS / 1e12 >= bytes2 / PEAK_HBM_GBS / 1e9:
-        name, kms, bound, peak, unit, work = ("k_members", kern["k_members"], "alu", PEAK_DOT4_TOPS, "TOP/s", ops2)
-    else:
-        name, kms, bound, peak, unit, work = ("k_members", kern["k_members"], "hbm", PEAK_HBM_GBS, "GB/s", bytes2)
-    scale = 1e12 if unit == "TOP/s" else 1e9
-    achieved = work / (kms / 1e3) / scale if kms > 0 else 0.0
-    roofline = {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(name + "@satellite"),
-                "kernel_ms_per_step": round(kms, 4), "launches_per_step": len(tpls),
-                ("algorithmic_ops" if unit == "TOP/s" else "algorithmic_bytes"): work,
-                "kernels_ms_per_step": {k: round(v, 4) for k, v in kern.items()}}
+            "k_members": float(phase[:, 2].sum()), "survivor_tiles": float(phase[:, 4].sum()),
+            "k_reduce": float(phase[:, 3].sum())}
+    work = {"k_centres_mfma": ("mfma", PEAK_MFMA_I8_TOPS, "TOP/s",
+                               sum(2.0 * t.size * r["n_centres"] for (t, _), r in zip(tpls, got))),
+            "k_members": ("hbm", PEAK_HBM_GBS, "GB/s", sum(20.0 * r["n_centres"] for r in got)),
+            "survivor_tiles": ("mfma", PEAK_MFMA_I8_TOPS, "TOP/s",
+                               sum(2.0 * t.size * r["n_dense"] for (t, _), r in zip(tpls, got)))}
+    fracs = {}
+    for k, (bound, peak, unit, wk) in work.items():
+        scale = 1e12 if unit == "TOP/s" else 1e9
+        ach = wk / (kern[k] / 1e3) / scale if kern[k] > 0 else 0.0
+        fracs[k] = {"bound": bound, "achieved": round(ach, 3), "unit": unit, "frac": round(ach / peak, 4),
+                    "ms_per_step": round(kern[k], 4)}
+    name = max(work, key=lambda k: kern[k])
+    bound, peak, unit, wk = work[name]
+    roofline = {"kernel": name, "bound": bound, "achieved": fracs[name]["achieved"], "peak": peak, "unit": unit,
+                "frac": fracs[name]["frac"], "traffic": measured_traffic(name + "@satellite"),
+                "kernel_ms_per_step": round(kern[name], 4), "launches_per_step": len(tpls),
+                ("algorithmic_ops" if unit == "TOP/s" else "algorithmic_bytes"): wk,
+                "kernels": fracs, "kernels_ms_per_step": {k: round(v, 4) for k, v in kern.items()}}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -191,16 +191,23 @@ typedef struct {
                                 launches when params.timing = 1; batches: events around the
                                 batched kernels) */
     zts_status status;
-    float phase_ms[4];       /* device time per kernel, HIP events on the library's stream:
+    float phase_ms[6];       /* device time per kernel, HIP events on the library's stream
+                                (params.timing = 1):
                                 ZTS_FULL: [0] dense kernel; ZTS_FULL_MFMA: [0] the batched launch;
                                 other modes: [0] scan 1 (centres), [1] refinement window,
-                                [2] scan 2 (members and survivors; each block derives the
-                                threshold from the earlier kernels' records); [3] the
-                                one-block reduction to the answer (ZTS_FULL too) */
+                                [2] scan 2 (group and member tests, survivors binned by tile;
+                                each block derives the threshold from the earlier kernels'
+                                records), [4] survivor tiles (dense tiles on int8 MFMA, then
+                                the others survivor by survivor); [3] the one-block reduction
+                                to the answer (ZTS_FULL too); [5] 0 */
     float latency_ms;        /* submitted requests: submission to result ready (host clock) */
     float queue_ms;          /* submitted requests: submission to the start of its launch */
     int32_t batch_size;      /* templates in the launch that produced this result */
     int32_t above_floor;     /* 1 when rho >= params.rho_floor (always 1 with the floor off) */
+    int64_t n_dense;         /* locations matched whole in dense survivor tiles (every location
+                                of a tile holding many survivors; they include eliminated
+                                locations, which are not in n_computed); 0 for ZTS_FULL and
+                                ZTS_FULL_MFMA */
 } zts_result;
 
 typedef struct {

@@ -26,6 +26,39 @@ void hip_check_at(hipError_t e, const char *file, int line)
     }
 }
 
+thread_local std::unique_lock<std::mutex> *t_ctx_lock = nullptr;
+
+// Set while this thread builds preparation buffers that no other thread can
+// reach yet (they enter the context's maps when the preparation ends): their
+// device allocations are then made with the context lock released.
+static thread_local bool t_alloc_unlocked = false;
+
+struct AllocUnlockedScope {
+    bool prev;
+    AllocUnlockedScope() : prev(t_alloc_unlocked) { t_alloc_unlocked = true; }
+    ~AllocUnlockedScope() { t_alloc_unlocked = prev; }
+};
+
+// Takes prep_mu for a thread that holds the context lock (through its
+// CtxLockScope): the context lock is released first and taken again after,
+// so the lock order is always prep_mu, then mu.
+std::unique_lock<std::mutex> take_prep_lock(Ctx *c)
+{
+    std::unique_lock<std::mutex> *lk = t_ctx_lock;
+    if (!lk || !lk->owns_lock())
+        throw ZtsError{ZTS_E_DEVICE};  // every caller holds the context lock through a CtxLockScope
+    std::unique_lock<std::mutex> plk(c->prep_mu, std::defer_lock);
+    lk->unlock();
+    try {
+        plk.lock();
+    } catch (...) {
+        lk->lock();
+        throw;
+    }
+    lk->lock();
+    return plk;
+}
+
 void DBuf::reset()
 {
     if (ptr) {
@@ -209,13 +242,24 @@ void dalloc(Ctx *c, DBuf &b, size_t bytes)
         c->free_blocks.erase(big);
     }
     if (!p) {
-        if (hipMalloc(&p, bytes) != hipSuccess) {
+        c->used += bytes;  // reserved before a possible unlock
+        hipError_t e;
+        std::unique_lock<std::mutex> *lk = t_alloc_unlocked ? t_ctx_lock : nullptr;
+        if (lk && lk->owns_lock()) {
+            lk->unlock();
+            e = hipMalloc(&p, bytes);
+            lk->lock();
+        } else {
+            e = hipMalloc(&p, bytes);
+        }
+        if (e != hipSuccess) {
             release_free_blocks(c);
-            if (hipMalloc(&p, bytes) != hipSuccess)
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                c->used -= bytes;
                 throw ZtsError{ZTS_E_NOMEM};
+            }
         }
         got = bytes;
-        c->used += bytes;
     }
     b.ctx = c;
     b.ptr = p;
@@ -422,12 +466,28 @@ Stats *stats_entry(Ctx *c, Image *im, int m, int n, hipStream_t s)
 // Statistics for work on the main stream (preparation).
 const int2 *stats_for(Ctx *c, Image *im, int m, int n) { return stats_entry(c, im, m, n, c->stream)->stat.as<int2>(); }
 
+// Waits for the main stream with the context lock released (preparation only:
+// its buffers are not reachable from the context's maps until it ends, and it
+// holds prep_mu and a pin on its image).
+void sync_main_unlocked(Ctx *c)
+{
+    std::unique_lock<std::mutex> *lk = t_ctx_lock;
+    if (!lk || !lk->owns_lock()) {
+        hip_check(hipStreamSynchronize(c->stream));
+        return;
+    }
+    lk->unlock();
+    hipError_t e = hipStreamSynchronize(c->stream);
+    lk->lock();
+    hip_check(e);
+}
+
 unsigned long long read_counter(Ctx *c)
 {
     c->h_cnt.grow(64);
     hip_check(hipMemcpyAsync(c->h_cnt.ptr, c->counter.ptr, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                              c->stream));
-    hip_check(hipStreamSynchronize(c->stream));
+    sync_main_unlocked(c);
     return *c->h_cnt.as<unsigned long long>();
 }
 
@@ -799,23 +859,65 @@ struct PinGuard {
     ~PinGuard() { pins--; }
 };
 
+// The cached tables of (m, n, mode) when they were made with these
+// parameters; drops tables made with others (ZTS_E_BUSY while pinned).
+static Prepared *cached_prep(Ctx *c, Image *im, const std::tuple<int, int, int> &key, zts_mode mode,
+                             const zts_params &pr)
+{
+    auto it = im->prep.find(key);
+    if (it == im->prep.end())
+        return nullptr;
+    if (same_prep_params(*it->second, mode, pr)) {
+        it->second->last_use = ++c->clock;
+        return it->second.get();
+    }
+    if (it->second->pins)  // running work still reads the tables made with other parameters
+        throw ZtsError{ZTS_E_BUSY};
+    im->prep.erase(it);
+    return nullptr;
+}
+
+static Prepared *build_prep(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr);
+
+// Tables of (image, m, n, mode): cached, or built.  Building holds prep_mu
+// (taken with the context lock released, then the lock again) and a pin on
+// the image; it releases the context lock while it waits for the device.
 Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr)
 {
     auto key = std::make_tuple(m, n, (int)mode);
-    auto it = im->prep.find(key);
-    if (it != im->prep.end()) {
-        if (same_prep_params(*it->second, mode, pr)) {
-            it->second->last_use = ++c->clock;
-            return it->second.get();
-        }
-        if (it->second->pins)  // running work still reads the tables made with other parameters
-            throw ZtsError{ZTS_E_BUSY};
-        im->prep.erase(it);
+    if (Prepared *P = cached_prep(c, im, key, mode, pr))
+        return P;
+    im->busy++;  // zts_image_unload refuses while the lock is released below
+    std::unique_lock<std::mutex> plk;
+    try {
+        plk = take_prep_lock(c);
+    } catch (...) {
+        im->busy--;
+        throw;
     }
+    im->busy--;
+    // another thread may have built the same tables meanwhile
+    if (Prepared *P = cached_prep(c, im, key, mode, pr))
+        return P;
+    im->busy++;
+    try {
+        Prepared *P = build_prep(c, im, m, n, mode, pr);
+        im->busy--;
+        return P;
+    } catch (...) {
+        im->busy--;
+        throw;
+    }
+}
+
+static Prepared *build_prep(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_params &pr)
+{
+    auto key = std::make_tuple(m, n, (int)mode);
     auto t0 = std::chrono::steady_clock::now();
     int Ly = im->rows - m + 1, Lx = im->cols - n + 1;
     Stats *sI = stats_entry(c, im, m, n, c->stream);
     PinGuard pin(sI->pins);  // preparation's own allocations may evict cached tables, never these
+    AllocUnlockedScope unlocked_allocs;  // from here on every buffer is the preparation's own
     const int2 *statI = sI->stat.as<int2>();
     auto P = std::make_unique<Prepared>();
     std::memset(&P->info, 0, sizeof P->info);
@@ -844,7 +946,7 @@ Prepared *prepare(Ctx *c, Image *im, int m, int n, zts_mode mode, const zts_para
     } else {
         throw ZtsError{ZTS_E_ARG};
     }
-    hip_check(hipStreamSynchronize(c->stream));
+    sync_main_unlocked(c);
     auto t1 = std::chrono::steady_clock::now();
     P->info.mode = mode;
     P->info.m = m;
@@ -1227,14 +1329,18 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
     } else {
         hip_check(launch_centres(Q.sa, st));
         mark(S.evp[0]);
-        if (Q.radius >= 0 && !Q.paper)
+        if (Q.radius >= 0 && !Q.paper) {
             hip_check(launch_window(Q.wa, st));
-        mark(S.evp[1]);
+            mark(S.evp[1]);
+        }
         hip_check(launch_members(Q.ma, st));
-        hip_check(launch_surv_tiles(Q.ta, st));
-        if (Q.paper)  // localisation on I around the conditioned image's best
-            hip_check(launch_window(Q.wa, st));
         mark(S.evp[2]);
+        hip_check(launch_surv_tiles(Q.ta, st));
+        mark(S.evp[4]);
+        if (Q.paper) {  // localisation on I around the conditioned image's best
+            hip_check(launch_window(Q.wa, st));
+            mark(S.evp[1]);
+        }
         hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, (QState *)Q.h_qs, st));
         mark(S.evp[3]);
     }
@@ -1423,12 +1529,25 @@ static zts_status assemble_result(const QueryPlan &q, const QState &h, Slot *tim
         span(&r.phase_ms[0], timed->ev0, timed->evp[0]);
         span(&r.phase_ms[3], timed->evp[0], timed->evp[1]);
     } else if (timed) {
-        span(&r.phase_ms[0], timed->ev0, timed->evp[0]);
-        span(&r.phase_ms[1], timed->evp[0], timed->evp[1]);
-        span(&r.phase_ms[2], timed->evp[1], timed->evp[2]);
-        span(&r.phase_ms[3], timed->evp[2], timed->evp[3]);
+        // launch order: scan 1, [window], scan 2, tiles, [window of the paper's search], reduction
+        hipEvent_t *e = timed->evp;
+        const bool paper = q.mode == ZTS_OPTA_PAPER, win = query_radius(q) >= 0;
+        span(&r.phase_ms[0], timed->ev0, e[0]);
+        if (paper) {
+            span(&r.phase_ms[2], e[0], e[2]);
+            span(&r.phase_ms[4], e[2], e[4]);
+            span(&r.phase_ms[1], e[4], e[1]);
+            span(&r.phase_ms[3], e[1], e[3]);
+        } else {
+            if (win)
+                span(&r.phase_ms[1], e[0], e[1]);
+            span(&r.phase_ms[2], win ? e[1] : e[0], e[2]);
+            span(&r.phase_ms[4], e[2], e[4]);
+            span(&r.phase_ms[3], e[4], e[3]);
+        }
     }
     r.above_floor = r.rho >= q.pr.rho_floor;
+    r.n_dense = q.mode == ZTS_FULL ? 0 : (int64_t)h.n_dense;
     r.status = ZTS_OK;
     *out = r;
     return ZTS_OK;
@@ -1852,7 +1971,8 @@ template <class F> zts_status guarded(Ctx *c, F &&f)
 {
     if (!c)
         return ZTS_E_ARG;
-    std::lock_guard<std::mutex> lk(c->mu);
+    std::unique_lock<std::mutex> lk(c->mu);
+    CtxLockScope scope(lk);
     try {
         hip_check(hipSetDevice(c->device));
         f();
@@ -2411,6 +2531,7 @@ ZTS_API zts_status zts_debug_autocorr(zts_ctx *z, int32_t image, int32_t m, int3
         return ZTS_E_ARG;
     return guarded(&z->c, [&] {
         Ctx *c = &z->c;
+        std::unique_lock<std::mutex> plk = take_prep_lock(c);  // it uses the preparation scratch
         Image *im = find_image(c, image);
         if (m < 1 || n < 1)
             throw ZtsError{ZTS_E_ARG};

@@ -511,8 +511,10 @@ __global__ __launch_bounds__(256) void k_stats(const uint2 *__restrict__ sat, in
 template <int R>
 __global__ __launch_bounds__(256) void k_full(FullArgs a)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
+        a.qs->n_dense = 0;
+    }
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
     const int n4w = a.n4w;
@@ -629,8 +631,10 @@ __global__ __launch_bounds__(256) void k_full(FullArgs a)
 template <int R>
 __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
+        a.qs->n_dense = 0;
+    }
     if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
         const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
         for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < a.n_tiles; i += nb * (int)blockDim.x)
@@ -802,8 +806,10 @@ __device__ __forceinline__ void load_template_rows(const uint8_t *__restrict__ t
 template <int NB>  // 16-byte column blocks of the template row (n16 = 16 NB)
 __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
+        a.qs->n_dense = 0;
+    }
     if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
         const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
         for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < a.n_tiles; i += nb * (int)blockDim.x)
@@ -1205,6 +1211,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
 // (block, tile) pair takes one global atomic; blocks whose groups span more
 // than kBinTiles tiles take one atomic per survivor.  All threads call it.
 constexpr int kBinTiles = 256;
+constexpr int kSurvList = 4096;  // survivors a k_members block collects before binning them
 
 __device__ void bin_survivors(const MemArgs &a, const int *s_list, int ns, int tile_lo, int ntl, uint32_t *s_tc,
                               uint32_t *s_tb)
@@ -1227,7 +1234,7 @@ __device__ void bin_survivors(const MemArgs &a, const int *s_list, int ns, int t
     for (int i = t; i < ntl; i += 256)
         s_tc[i] = 0;
     __syncthreads();
-    constexpr int PER = 1024 / 256;  // survivors per thread and pass
+    constexpr int PER = kSurvList / 256;  // survivors per thread
     int tl[PER], ps[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
@@ -1261,7 +1268,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ int s_pref[GB + 1];
     __shared__ int s_tmp[4];
     __shared__ int s_geo[GB][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
-    __shared__ int s_list[CAP];
+    __shared__ int s_list[kSurvList];
     __shared__ int s_nsurv;
     __shared__ RecPod wrec[4];
     __shared__ Best bred[8];
@@ -1425,14 +1432,19 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
                 a.dec[o] = keep ? 2 : 0;
         }
         __syncthreads();
+        // survivors collect over passes and are binned when the next pass
+        // might not fit the list, and after the last pass
         const int ns = s_nsurv;
-        if (ns > 0)
-            bin_survivors(a, s_list, ns, tile_lo, ntl, s_tc, s_tb);
-        if (base + CAP < total) {  // another pass reuses the survivor list
-            __syncthreads();
-            if (t == 0)
-                s_nsurv = 0;
-            __syncthreads();
+        const bool last = base + CAP >= total;
+        if (last || ns + CAP > kSurvList) {
+            if (ns > 0)
+                bin_survivors(a, s_list, ns, tile_lo, ntl, s_tc, s_tb);
+            if (!last) {
+                __syncthreads();
+                if (t == 0)
+                    s_nsurv = 0;
+                __syncthreads();
+            }
         }
     }
     // the counts ride in the wave records (merging sums them): one barrier
@@ -2541,9 +2553,12 @@ __global__ __launch_bounds__(256, 2) void k_dense_tiles(TileArgs a)
     for (int idx = t; idx < nw16; idx += 256)
         tpl_l[a.m * tstr + idx] = 0;
     const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
-    const RecPod best = single_tile_body<8>(st, tx * kTileCols, sy * 4 * kTileRows, smem);
-    if (t == 0)
+    const int x0 = tx * kTileCols, y0 = sy * 4 * kTileRows;
+    const RecPod best = single_tile_body<8>(st, x0, y0, smem);
+    if (t == 0) {
         *out = best;
+        atomicAdd(&a.qs->n_dense, (unsigned long long)min(4 * kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
+    }
 }
 
 // One block per survivor tile (after scan 2 has binned the survivors).  An
@@ -2582,8 +2597,10 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
             tpl_l[a.m * tstr + idx] = 0;
         const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, St, Dt};
         const RecPod best = single_tile_body<2>(st, x0, y0, smem);
-        if (t == 0)
+        if (t == 0) {
             a.recs[a.rec_off + tile] = best;
+            atomicAdd(&a.qs->n_dense, (unsigned long long)min(kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
+        }
         return;
     }
     const int n4 = (a.n + 3) >> 2;
@@ -2691,7 +2708,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 // that sees the new number reads a complete state.  The state the earlier
 // kernels wrote is loaded by thread 0 together with the records, and the
 // mirror is written from registers.
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi,
                                                         int count_lo, QState *qs, QState *host)
@@ -3192,10 +3209,12 @@ hipError_t launch_regroup(const void *in, void *out, int Ly, int Lx, int h, int 
 
 bool autocorr_by_shifts(int m, int n, int h, int w)
 {
-    // measured on MI355X (2048x2048): one offset's product running sums and
-    // gather cost about as much per pixel as 46 multiply-adds of the direct
-    // form, which spends m n per location
-    return (int64_t)(h * w - 1) * 46 < (int64_t)m * n;
+    // measured on MI355X: one offset's product running sums and gather cost
+    // about as much per pixel as 46 multiply-adds of the direct form (2048 x
+    // 2048, 64 x 64), whose one wave per location also has a fixed cost of
+    // about 61 offsets' worth (8192 x 8192, 16 x 16: 36 ms against 0.59 ms
+    // per offset)
+    return (int64_t)(h * w - 1) * 46 < std::max<int64_t>(61 * 46, (int64_t)m * n);
 }
 
 hipError_t launch_autocorr(AcArgs a, uint32_t *psat, hipStream_t s)

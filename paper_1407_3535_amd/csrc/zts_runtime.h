@@ -163,6 +163,11 @@ struct Server {
 
 struct Ctx {
     std::mutex mu;
+    // Serialises preparations (they share the preparation scratch below and
+    // the main stream).  Taken without mu held (order: prep_mu, then mu); a
+    // preparation releases mu while it waits for the device, so requests whose
+    // tables are ready keep being planned and launched meanwhile.
+    std::mutex prep_mu;
     int device = 0;
     uint64_t budget = 0;
     uint64_t used = 0;            // live buffers and cached free blocks
@@ -186,6 +191,16 @@ struct Ctx {
     std::map<std::pair<int, int>, zts_tune_entry> tuned;
     std::string tune_cache, arch;
     double wall_khz = 100000.0;   // device realtime clock (hipDeviceAttributeWallClockRate)
+};
+
+// The context lock held by the calling thread (a synchronous entry point's or
+// a serving worker's), so that preparation can release it while it waits for
+// the device.  Every path that may prepare sets it (CtxLockScope).
+extern thread_local std::unique_lock<std::mutex> *t_ctx_lock;
+struct CtxLockScope {
+    std::unique_lock<std::mutex> *prev;
+    explicit CtxLockScope(std::unique_lock<std::mutex> &lk) : prev(t_ctx_lock) { t_ctx_lock = &lk; }
+    ~CtxLockScope() { t_ctx_lock = prev; }
 };
 
 Image *find_image(Ctx *c, int id);

@@ -103,6 +103,7 @@ void worker_main(Ctx *c, Slot *S)
     (void)hipSetDevice(c->device);
     Server &sv = *c->srv;
     std::unique_lock<std::mutex> lk(c->mu);
+    CtxLockScope scope(lk);
     for (;;) {
         sv.cv_work.wait(lk, [&] { return sv.stop || !sv.queue.empty(); });
         if (sv.stop)

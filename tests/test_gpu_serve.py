@@ -232,3 +232,39 @@ def test_destroy_with_work_in_flight():
     for k in range(12):
         S.submit(i, cut_template(img, 48, 48, k, 4.0)[0], "full_mfma" if k % 2 else "full")
     S.close()  # cancels what has not started, waits for the rest
+
+
+def test_preparation_does_not_stall_other_slots():
+    """One slot prepares OptA tables for an unseen size of an 8192x8192 image (tens of milliseconds) while
+    another slot serves queries whose tables are ready: most of those complete before the preparing request
+    does (the preparation holds neither the context lock while it waits for the device nor the other slots'
+    streams), and every answer equals the oracle's."""
+    gpu_or_skip()
+    rng = np.random.default_rng(2024)
+    big = rng.integers(0, 256, (8192, 8192), dtype=np.uint8)
+    small = aerial_image(300, 320, 2025)
+    tb = np.clip(big[5000:5016, 3000:3016].astype(int) + rng.integers(-6, 7, (16, 16)), 0, 255).astype(np.uint8)
+    smalls = [cut_template(small, 24, 24, 2100 + k, 5.0)[0] for k in range(12)]
+    with Z.Searcher(0, max_inflight=2) as T:
+        ib, i_s = T.load(big), T.load(small)
+        T.prepare(i_s, 24, 24, "egs")
+        t_big = time.perf_counter()
+        tk = T.submit(ib, tb, "opta", refine_radius=2)
+        time.sleep(0.002)  # a worker takes it and starts preparing
+        sub = []
+        for t in smalls:
+            sub.append((time.perf_counter(), T.submit(i_s, t, "egs")))
+        got = [(ts, T.wait(k)) for ts, k in sub]
+        st, gb = T.wait(tk)
+        assert st == 0
+        big_done = t_big * 1e3 + gb["latency_ms"]
+        done = [ts * 1e3 + r["latency_ms"] for ts, (_, r) in got]
+        print(f"preparing request done after {gb['latency_ms']:.1f} ms; the others after "
+              f"{[round(d - t_big * 1e3, 1) for d in done]} ms", flush=True)
+        assert gb["latency_ms"] > 5.0  # the preparation did run in this request
+        # with a stall none would; the GPU is shared, so the last few may finish just after it
+        assert sum(d < big_done for d in done) >= len(done) // 2
+        for t, (_, (s2, r)) in zip(smalls, got):
+            assert s2 == 0
+            same_as_oracle(r, O.full_search(small, t), "served beside a preparation")
+        same_as_oracle(gb, O.full_search(big, tb), "the prepared request")
