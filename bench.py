@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=1000, help="measured queries per load level")
     ap.add_argument("--serve-slots", type=int, default=4, help="worker slots (launches in flight)")
     ap.add_argument("--serve-budget-gb", type=int, default=32, help="HBM budget of the serving context")
+    ap.add_argument("--serve-elim", type=int, default=400,
+                    help="queries of the stream also served with EGS transitive elimination (0 = skip)")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MB",
                     help="only copy MB megabytes device to device 5 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -168,7 +170,7 @@ def main():
                                     ("egs_rho_th0.95_refine2", "egs", 2, {"rho_th": 0.95})]:
             rr, mms, ll, pp = run(mode, ref, 20, 3, **kw)
             modes[name] = {"ms_per_query": round(mms, 4), "locations_per_s": L / (mms / 1e3),
-                           "device_ms": round(rr["device_ms"], 4), "phase_ms": [round(x, 4) for x in pp[:5]],
+                           "device_ms": round(rr["device_ms"], 4), "phase_ms": [round(x, 4) for x in pp],
                            "n_computed": rr["n_computed"], "n_centres": rr["n_centres"],
                            "n_eliminated": rr["n_eliminated"], "group": [rr["group_h"], rr["group_w"]],
                            "answer": [rr["y"], rr["x"], rr["rho"]]}
@@ -219,7 +221,8 @@ def main():
         G = r["n_centres"]
         kernels = [("k_centres_mfma", ph[0], "mfma", PEAK_MFMA_I8_TOPS, "TOP/s", 2.0 * mn * G),
                    ("k_members", ph[2], "hbm", PEAK_HBM_GBS, "GB/s", 20.0 * G),
-                   ("survivor_tiles", ph[4], "mfma", PEAK_MFMA_I8_TOPS, "TOP/s", 2.0 * mn * r["n_dense"])]
+                   ("k_dense_tiles", ph[4], "mfma", PEAK_MFMA_I8_TOPS, "TOP/s", 2.0 * mn * r["n_dense"]),
+                   ("k_surv_tiles", ph[5], "alu", PEAK_DOT4_TOPS, "TOP/s", 2.0 * mn * r["n_sparse"])]
     name, kms, bound, peak, unit, work = max(kernels, key=lambda k: k[1])
     scale = 1e12 if unit == "TOP/s" else 1e9
     achieved = work / (kms / 1e3) / scale if kms > 0 else 0.0
@@ -408,6 +411,28 @@ def bench_satellite(args):
     full_ms = modes.get("full", {}).get("ms_per_step")
     mfma_ms = modes.get("full_mfma", {}).get("ms_per_step")
 
+    # Sensitivity to the initial threshold rho_th (the estimates of Alg. 2 and 3 and lambda of Eq. 28): for each
+    # value the three sizes are prepared again and the 8 templates searched; total = preparation + queries,
+    # the quantity the paper reports for its threshold sweep.
+    sweep = []
+    if not args.no_modes:
+        for rt in (0.70, 0.75, 0.80, 0.85, 0.90):
+            pms, groups = 0.0, {}
+            for m, n in sizes:
+                info = S.prepare(i, m, n, mode, rho_th=rt)
+                pms += info["prepare_ms"]
+                groups[f"{m}x{n}"] = [info["h"], info["w"], len([s for s in info["opta"][1:] if s["accepted"]])]
+            qms = 0.0
+            for k in range(len(tpls)):
+                r, t_ms = timed(mode, {"refine_radius": args.refine, "rho_th": rt}, k)
+                assert (r["y"], r["x"], r["rho"]) == (got[k]["y"], got[k]["x"], got[k]["rho"])
+                qms += t_ms
+            sweep.append({"rho_th": rt, "prepare_ms": round(pms, 2), "query_ms_per_step": round(qms, 3),
+                          "total_ms": round(pms + qms, 2), "group_and_blur_iterations": groups})
+            note(f"rho_th {rt}: prepare {pms:.1f} ms, queries {qms:.2f} ms")
+        for m, n in sizes:  # the default parameters again for anything after
+            S.prepare(i, m, n, mode)
+
     per_t = []
     for k, ((t, loc), r, L) in enumerate(zip(tpls, got, Ls)):
         p50 = percentile(lat[k], 50)
@@ -416,23 +441,25 @@ def bench_satellite(args):
                       "phase_ms": [round(x, 4) for x in phase[k]], "group": [r["group_h"], r["group_w"]],
                       "n_centres": r["n_centres"], "n_computed": r["n_computed"],
                       "n_matched_incl_centres": r["n_computed"] + (r["n_centres"] if mode == "opta" else 0),
-                      "n_eliminated": r["n_eliminated"], "n_survivors": r["n_survivors"], "n_dense": r["n_dense"],
+                      "n_eliminated": r["n_eliminated"], "n_survivors": r["n_survivors"], "n_dense": r["n_dense"], "n_sparse": r["n_sparse"],
                       "answer": [r["y"], r["x"], r["rho"]], "cut_location_found": (r["y"], r["x"]) == tuple(loc)})
 
     # Per-kernel rooflines over one step (HIP-event times summed over the 8 queries) and the dominant one.
     #   k_centres_mfma (scan 1): 2 mn int8 ops per group centre, int8 MFMA peak.
     #   k_members (scan 2's tests): the 20 B per group it must read (angle of the centre and the group's
     #     range summary), HBM; member angles are read only for groups that do not fall whole.
-    #   survivor tiles (k_dense_tiles + k_surv_tiles): 2 mn int8 ops per location matched in dense tiles
-    #     (n_dense) plus 2 mn per survivor outside them (at most n_survivors), int8 MFMA peak.
+    #   k_dense_tiles: 2 mn int8 ops per location of the dense survivor tiles (n_dense), int8 MFMA peak.
+    #   k_surv_tiles: 2 mn int8 ops per survivor matched one by one (n_sparse), v_dot4 VALU peak.
     kern = {"k_centres_mfma": float(phase[:, 0].sum()), "k_window": float(phase[:, 1].sum()),
-            "k_members": float(phase[:, 2].sum()), "survivor_tiles": float(phase[:, 4].sum()),
-            "k_reduce": float(phase[:, 3].sum())}
+            "k_members": float(phase[:, 2].sum()), "k_dense_tiles": float(phase[:, 4].sum()),
+            "k_surv_tiles": float(phase[:, 5].sum()), "k_reduce": float(phase[:, 3].sum())}
     work = {"k_centres_mfma": ("mfma", PEAK_MFMA_I8_TOPS, "TOP/s",
                                sum(2.0 * t.size * r["n_centres"] for (t, _), r in zip(tpls, got))),
             "k_members": ("hbm", PEAK_HBM_GBS, "GB/s", sum(20.0 * r["n_centres"] for r in got)),
-            "survivor_tiles": ("mfma", PEAK_MFMA_I8_TOPS, "TOP/s",
-                               sum(2.0 * t.size * r["n_dense"] for (t, _), r in zip(tpls, got)))}
+            "k_dense_tiles": ("mfma", PEAK_MFMA_I8_TOPS, "TOP/s",
+                              sum(2.0 * t.size * r["n_dense"] for (t, _), r in zip(tpls, got))),
+            "k_surv_tiles": ("alu", PEAK_DOT4_TOPS, "TOP/s",
+                             sum(2.0 * t.size * r["n_sparse"] for (t, _), r in zip(tpls, got)))}
     fracs = {}
     for k, (bound, peak, unit, wk) in work.items():
         scale = 1e12 if unit == "TOP/s" else 1e9
@@ -495,6 +522,7 @@ def bench_satellite(args):
         "prepare_ms_total": round(sum(prep_ms.values()), 2),
         "value_with_preparation": L_step / ((ms + sum(prep_ms.values())) / 1e3),
         "modes": modes,
+        "rho_th_sweep": sweep,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -605,25 +633,25 @@ def bench_serve(args):
     def L_of(t, j):
         return (imgs[j].shape[0] - t.shape[0] + 1) * (imgs[j].shape[1] - t.shape[1] + 1)
 
-    def closed_loop(mode, items, window=32):
+    def closed_loop(mode, items, window=32, **kw):
         out = [None] * len(items)
         pending = []
         t0 = time.perf_counter()
         k = 0
         while k < len(items) and len(pending) < window:
             t, j, _ = items[k]
-            pending.append((k, S.submit(ids[j], t, mode)))
+            pending.append((k, S.submit(ids[j], t, mode, **kw)))
             k += 1
         while pending:
             i, tk = pending.pop(0)
             out[i] = S.wait(tk)
             if k < len(items):
                 t, j, _ = items[k]
-                pending.append((k, S.submit(ids[j], t, mode)))
+                pending.append((k, S.submit(ids[j], t, mode, **kw)))
                 k += 1
         return len(items) / (time.perf_counter() - t0), out
 
-    def open_loop(mode, items, qps, seed):
+    def open_loop(mode, items, qps, seed, **kw):
         arr = poisson_arrivals(len(items), qps, seed)
         fifo = queue.Queue()
         got = [None] * len(items)
@@ -648,7 +676,7 @@ def bench_serve(args):
                     break
                 time.sleep(d if d > 0.002 else 0)
             lag = time.perf_counter() - target
-            fifo.put((i, S.submit(ids[j], t, mode), lag))
+            fifo.put((i, S.submit(ids[j], t, mode, **kw), lag))
         fifo.put(None)
         th.join()
         wall = time.perf_counter() - t0
@@ -684,6 +712,32 @@ def bench_serve(args):
         loads.append(res)
         note(f"open loop at {frac} x capacity: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms")
     hi = loads[-1]
+
+    # The same stream served with transitive elimination (EGS, refinement radius 2): every query is exact, so
+    # its answer must equal the exhaustive one; tables are prepared on demand per (image, size) under the HBM
+    # budget (least recently used evicted), so queries of a size not seen recently pay its preparation.
+    elim = None
+    if args.serve_elim:
+        ne = min(nq, args.serve_elim)
+        items = meas[:ne]
+        seen, fresh = set(), 0
+        for t, j, _ in items:
+            fresh += (j, t.shape) not in seen
+            seen.add((j, t.shape))
+        cap_e, eres = closed_loop("egs", items, refine_radius=2)
+        for (st, r), (st0, r0) in zip(eres, cres[:ne]):
+            assert st == 0 and (r["y"], r["x"], r["rho"]) == (r0["y"], r0["x"], r0["rho"]), "served EGS differs"
+        note(f"served EGS capacity {cap_e:.1f} queries/s")
+        eloads = []
+        for frac, seed in ((0.5, 3), (0.8, 4)):
+            res, _ = open_loop("egs", items, frac * cap_e, 14073535 + 5999 + seed, refine_radius=2)
+            res["load"] = frac
+            eloads.append(res)
+            note(f"EGS open loop at {frac} x capacity: p50 {res['p50_ms']} ms, p99 {res['p99_ms']} ms")
+        elim = {"mode": "egs", "refine_radius": 2, "queries": ne, "capacity_qps": round(cap_e, 2),
+                "distinct_image_sizes": len(seen), "loads": eloads,
+                "answers_equal_to_exhaustive": True,
+                "note": "tables prepared on demand per (image, size) within the HBM budget"}
     S.close()
     achieved = ops / dev_s / 1e12
     out = {
@@ -699,6 +753,7 @@ def bench_serve(args):
         "vs_full_zncc": round(xmax / xmax_full, 3),
         "loads": loads,
         "cut_queries_found": [hits, cuts],
+        "elimination": elim,
         "roofline": {"kernel": "k_batch (fused launches, + k_tstats, k_fold_batch, k_reduce_batch)",
                      "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_MFMA_I8_TOPS, "unit": "TOP/s",
                      "frac": round(achieved / PEAK_MFMA_I8_TOPS, 4), "traffic": None,

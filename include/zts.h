@@ -159,13 +159,14 @@ typedef struct {
     int32_t floor_prune;    /* 1: the floor also prunes: scan 2 eliminates against
                                max(best0, rho_floor).  The answer stays exact whenever the
                                true maximum reaches the floor; otherwise above_floor = 0 and
-                               the answer is the best computed location (no exactness claim).
+                               the answer is the best location matched (at least as good as
+                               the best group centre and survivor; no exactness claim).
                                0 (default): the floor only labels the result. */
     int32_t pad1;
     int32_t tile_dense_min; /* scan 2 bins its survivors by tile of 32 x 256 locations; four
-                               stacked tiles holding at least 4x this many survivors, or a
-                               tile holding at least this many, are matched whole on int8 MFMA
-                               (every location; n <= 128), the others survivor by survivor.
+                               stacked tiles holding at least 4x this many survivors together,
+                               or one of them at least this many, are matched whole on int8
+                               MFMA (every location; n <= 128), the others survivor by survivor.
                                0 (default): the library's value (128); -1: never whole; at
                                most 8192.  Counts and answers do not depend on it. */
     int32_t pad2;
@@ -197,9 +198,9 @@ typedef struct {
                                 other modes: [0] scan 1 (centres), [1] refinement window,
                                 [2] scan 2 (group and member tests, survivors binned by tile;
                                 each block derives the threshold from the earlier kernels'
-                                records), [4] survivor tiles (dense tiles on int8 MFMA, then
-                                the others survivor by survivor); [3] the one-block reduction
-                                to the answer (ZTS_FULL too); [5] 0 */
+                                records), [4] dense survivor tiles on int8 MFMA, [5] the other
+                                tiles' survivors one by one; [3] the one-block reduction to
+                                the answer (ZTS_FULL too) */
     float latency_ms;        /* submitted requests: submission to result ready (host clock) */
     float queue_ms;          /* submitted requests: submission to the start of its launch */
     int32_t batch_size;      /* templates in the launch that produced this result */
@@ -208,6 +209,7 @@ typedef struct {
                                 of a tile holding many survivors; they include eliminated
                                 locations, which are not in n_computed); 0 for ZTS_FULL and
                                 ZTS_FULL_MFMA */
+    int64_t n_sparse;        /* survivors matched one by one (those outside dense tiles) */
 } zts_result;
 
 typedef struct {

@@ -76,7 +76,7 @@ class Result(C.Structure):
                 ("group_w", C.c_int32), ("best0", C.c_double), ("best0_y", C.c_int32), ("best0_x", C.c_int32),
                 ("device_ms", C.c_float), ("status", C.c_int32), ("phase_ms", C.c_float * 6),
                 ("latency_ms", C.c_float), ("queue_ms", C.c_float), ("batch_size", C.c_int32),
-                ("above_floor", C.c_int32), ("n_dense", C.c_int64)]
+                ("above_floor", C.c_int32), ("n_dense", C.c_int64), ("n_sparse", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in Result._names}

@@ -1335,8 +1335,10 @@ static void enqueue_query(const QueryLaunch &Q, Slot &S, hipStream_t st, bool ev
         }
         hip_check(launch_members(Q.ma, st));
         mark(S.evp[2]);
-        hip_check(launch_surv_tiles(Q.ta, st));
+        hip_check(launch_dense_tiles(Q.ta, st));
         mark(S.evp[4]);
+        hip_check(launch_surv_tiles(Q.ta, st));
+        mark(S.evp[5]);
         if (Q.paper) {  // localisation on I around the conditioned image's best
             hip_check(launch_window(Q.wa, st));
             mark(S.evp[1]);
@@ -1529,25 +1531,29 @@ static zts_status assemble_result(const QueryPlan &q, const QState &h, Slot *tim
         span(&r.phase_ms[0], timed->ev0, timed->evp[0]);
         span(&r.phase_ms[3], timed->evp[0], timed->evp[1]);
     } else if (timed) {
-        // launch order: scan 1, [window], scan 2, tiles, [window of the paper's search], reduction
+        // launch order: scan 1, [window], scan 2, dense tiles, sparse tiles, [window of the paper's
+        // search], reduction
         hipEvent_t *e = timed->evp;
         const bool paper = q.mode == ZTS_OPTA_PAPER, win = query_radius(q) >= 0;
         span(&r.phase_ms[0], timed->ev0, e[0]);
         if (paper) {
             span(&r.phase_ms[2], e[0], e[2]);
             span(&r.phase_ms[4], e[2], e[4]);
-            span(&r.phase_ms[1], e[4], e[1]);
+            span(&r.phase_ms[5], e[4], e[5]);
+            span(&r.phase_ms[1], e[5], e[1]);
             span(&r.phase_ms[3], e[1], e[3]);
         } else {
             if (win)
                 span(&r.phase_ms[1], e[0], e[1]);
             span(&r.phase_ms[2], win ? e[1] : e[0], e[2]);
             span(&r.phase_ms[4], e[2], e[4]);
-            span(&r.phase_ms[3], e[4], e[3]);
+            span(&r.phase_ms[5], e[4], e[5]);
+            span(&r.phase_ms[3], e[5], e[3]);
         }
     }
     r.above_floor = r.rho >= q.pr.rho_floor;
     r.n_dense = q.mode == ZTS_FULL ? 0 : (int64_t)h.n_dense;
+    r.n_sparse = q.mode == ZTS_FULL ? 0 : (int64_t)h.n_sparse;
     r.status = ZTS_OK;
     *out = r;
     return ZTS_OK;

@@ -109,11 +109,12 @@ struct MemArgs {
 // two-row-group block of the single-template MFMA kernel).
 constexpr int kTileRows = 32, kTileCols = 256;
 
-// Matching of scan 2's survivors, one block per tile (k_surv_tiles).  A tile
-// with at least dense_min survivors is matched whole on int8 MFMA (every
-// location; the extra ones were eliminated, so they cannot be the answer);
-// otherwise its listed survivors are matched one wave each, from its image
-// region staged in LDS when it fits (sparse_lds) or from global memory.
+// Matching of scan 2's survivors.  Super-tiles of four stacked tiles that
+// hold many survivors are matched whole on int8 MFMA (k_dense_tiles; every
+// location, the extra ones were eliminated so they cannot be the answer);
+// the other tiles' listed survivors are matched one wave each (k_surv_tiles),
+// from the tile's image region staged in LDS when it fits (sparse_lds) or
+// from global memory.
 struct TileArgs {
     const uint8_t *img;  // the image survivors are matched on
     int64_t pitch;
@@ -262,7 +263,8 @@ void tile_plan(TileArgs &a, int dense_min);
 // their records follow the tiles' (tiles_x * tiles_y + super_tiles_of(a)
 // records from rec_off; super_tiles_of is 0 without a dense path).
 int super_tiles_of(const TileArgs &a);
-// k_dense_tiles (when a.dense_min > 0), then k_surv_tiles.
+// k_dense_tiles (nothing when a.dense_min is 0), then k_surv_tiles.
+hipError_t launch_dense_tiles(TileArgs a, hipStream_t s);
 hipError_t launch_surv_tiles(TileArgs a, hipStream_t s);
 // Whether scan 1 (either form) and scan 2 can stage a template of m x n.
 bool scan_fits(int m, int n);

@@ -514,6 +514,7 @@ __global__ __launch_bounds__(256) void k_full(FullArgs a)
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
         a.qs->n_dense = 0;
+        a.qs->n_sparse = 0;
     }
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[8];
@@ -634,6 +635,7 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
         a.qs->n_dense = 0;
+        a.qs->n_sparse = 0;
     }
     if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
         const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
@@ -809,6 +811,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
         a.qs->n_dense = 0;
+        a.qs->n_sparse = 0;
     }
     if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
         const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
@@ -2512,26 +2515,30 @@ __device__ __forceinline__ uint32_t wave_dot_lds_u8(const uint32_t *__restrict__
 
 // Whether super-tile (sy, tx) -- the (up to) four tiles of tile column tx
 // and tile rows 4 sy .. 4 sy + 3, 128 x 256 locations -- is matched whole by
-// k_dense_tiles: its tiles hold at least 4 dense_min survivors together.
+// k_dense_tiles: its tiles hold at least 4 dense_min survivors together, or
+// one of them holds at least dense_min (so every tile left to k_surv_tiles
+// fits its bin of dense_min).
 __device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
 {
     if (a.dense_min <= 0)
         return false;
-    int sum = 0;
+    int sum = 0, most = 0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int ty = 4 * sy + k;
-        if (ty < a.tiles_y)
-            sum += (int)a.tile_cnt[ty * a.tiles_x + tx];
+        const int c = ty < a.tiles_y ? (int)a.tile_cnt[ty * a.tiles_x + tx] : 0;
+        sum += c;
+        most = max(most, c);
     }
-    return sum >= 4 * a.dense_min;
+    return sum >= 4 * a.dense_min || most >= a.dense_min;
 }
 
-// Dense super-tiles: one block per super-tile of 128 x 256 locations; one
-// whose tiles hold at least 4 dense_min survivors together is matched whole
-// on int8 MFMA with eight row groups per block (the k_single body, whose
-// image staging is then shared by 128 output rows); others write an empty
-// record and are left to k_surv_tiles.
+// Dense super-tiles: one block per super-tile of 128 x 256 locations; a
+// dense one (super_dense) is matched whole on int8 MFMA with eight row groups
+// per block (the k_single body, whose image staging is then shared by 128
+// output rows): the locations scan 2 eliminated lie below the threshold, so
+// they cannot be the answer, and the counts stay those of the decisions.
+// Others write an empty record and are left to k_surv_tiles.
 __global__ __launch_bounds__(256, 2) void k_dense_tiles(TileArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
@@ -2562,13 +2569,11 @@ __global__ __launch_bounds__(256, 2) void k_dense_tiles(TileArgs a)
 }
 
 // One block per survivor tile (after scan 2 has binned the survivors).  An
-// empty tile writes an empty record.  A tile with at least dense_min
-// survivors is matched whole: every location of its 32 x 256 block on int8
-// MFMA (single_tile_body; the locations scan 2 eliminated lie below the
-// threshold, so they cannot be the answer, and the counts stay those of the
-// decisions).  Otherwise each listed survivor is matched by one wave with
-// unsigned dot products, from the tile's image region staged in LDS when it
-// fits, else from global memory.  One record per tile.
+// empty tile, or one of a super-tile k_dense_tiles matched whole, writes an
+// empty record.  Otherwise (fewer than dense_min survivors, all in its bin)
+// each listed survivor is matched by one wave with unsigned dot products,
+// from the tile's image region staged in LDS when it fits, else from global
+// memory.  One record per tile.
 __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
@@ -2585,24 +2590,6 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
     const int y0 = ty * kTileRows, x0 = tx * kTileCols;
     const int64_t St = a.qs->st, Dt = a.qs->dt;
     const int64_t mn = (int64_t)a.m * a.n;
-    if (a.dense_min > 0 && cnt >= a.dense_min) {
-        const int nw16 = a.n16 >> 2, tstr = batch_tstride(nw16);
-        uint32_t *tpl_l = smem + single_tpl_offset(a.n16);
-        const bool words = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
-        for (int idx = t; idx < a.m * nw16; idx += 256) {
-            const int r = idx / nw16, c = idx - r * nw16;
-            tpl_l[r * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
-        }
-        for (int idx = t; idx < nw16; idx += 256)
-            tpl_l[a.m * tstr + idx] = 0;
-        const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, St, Dt};
-        const RecPod best = single_tile_body<2>(st, x0, y0, smem);
-        if (t == 0) {
-            a.recs[a.rec_off + tile] = best;
-            atomicAdd(&a.qs->n_dense, (unsigned long long)min(kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
-        }
-        return;
-    }
     const int n4 = (a.n + 3) >> 2;
     const int rsw = a.region_words;
     uint32_t *tplw = smem;
@@ -2648,8 +2635,10 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
         }
     }
     const RecPod best = block_rec4(rec, red4);
-    if (t == 0)
+    if (t == 0) {
         a.recs[a.rec_off + tile] = best;
+        atomicAdd(&a.qs->n_sparse, (unsigned long long)c);
+    }
 }
 
 // First fold of the per-block records: fold block c of tile z merges the
@@ -3155,15 +3144,21 @@ void tile_plan(TileArgs &a, int dense_min)
     a.sparse_lds = tiles_sparse_bytes(a.m, a.n, 1, a.region_words) <= kSparseRegionMax ? 1 : 0;
 }
 
-static size_t tiles_lds_bytes(const TileArgs &a)
-{
-    size_t lds = tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words);
-    if (a.dense_min > 0)
-        lds = std::max(lds, single_lds_bytes(a.m, a.n16));
-    return lds;
-}
+static size_t tiles_lds_bytes(const TileArgs &a) { return tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words); }
 
 int super_tiles_of(const TileArgs &a) { return a.dense_min > 0 ? a.tiles_x * (int)blocks_for(a.tiles_y, 4) : 0; }
+
+hipError_t launch_dense_tiles(TileArgs a, hipStream_t s)
+{
+    if (a.dense_min <= 0)
+        return hipSuccess;
+    const size_t dl = single_lds_bytes(a.m, a.n16);
+    hipError_t e = allow_lds((const void *)k_dense_tiles, dl);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)super_tiles_of(a)), dim3(256), dl, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_surv_tiles(TileArgs a, hipStream_t s)
 {
@@ -3174,13 +3169,6 @@ hipError_t launch_surv_tiles(TileArgs a, hipStream_t s)
     hipError_t e = allow_lds((const void *)k_surv_tiles, lds);
     if (e != hipSuccess)
         return e;
-    if (a.dense_min > 0) {
-        const size_t dl = single_lds_bytes(a.m, a.n16);
-        e = allow_lds((const void *)k_dense_tiles, dl);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)super_tiles_of(a)), dim3(256), dl, s, a);
-    }
     hipLaunchKernelGGL(k_surv_tiles, dim3((unsigned)nt), dim3(256), lds, s, a);
     return hipGetLastError();
 }

@@ -40,8 +40,9 @@ struct QState {
     int32_t pad1;
     // device realtime clock at the first kernel's start and the last one's end
     unsigned long long t0, t1;
-    // locations matched whole in dense survivor tiles (scan 1 zeroes it)
-    unsigned long long n_dense;
+    // locations matched whole in dense survivor tiles, and survivors matched
+    // one by one in the other tiles (scan 1 zeroes both)
+    unsigned long long n_dense, n_sparse;
     // completed queries of this state; the final reduction copies the state
     // to the host mirror and writes this last
     unsigned long long seq;

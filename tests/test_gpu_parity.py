@@ -676,3 +676,48 @@ def test_maximum_sizes(S, case):
         with pytest.raises(Z.ZtsError) as e:
             S.load(np.zeros((1, 32768), np.uint8))
         assert e.value.code == -2
+
+
+@pytest.mark.parametrize("mode", ["te_fixed", "egs", "opta"])
+def test_detection_floor(S, mode):
+    """rho_floor with floor_prune: scan 2 eliminates against max(best0, floor).  Answers, counts and decisions
+    equal the oracle's searches with the same floor; above_floor says whether rho reaches the floor; with the
+    floor at or below the true maximum the answer is the exhaustive one.  Without floor_prune the floor only
+    labels the exhaustive answer.  A noise template (no true match) is included."""
+    from synth import noise_template
+    img = aerial_image(180, 210, 4321, beta=2.2)
+    m = n = 14
+    i = S.load(img)
+    kw = dict(group_h=3, group_w=3) if mode == "te_fixed" else {}
+    info = S.prepare(i, m, n, mode, **kw) if mode != "te_fixed" else {"h": 3, "w": 3}
+    oo = O.opta(img, m, n) if mode == "opta" else None
+    tpls = [cut_template(img, m, n, 4400 + k, 10.0, affine=True)[0] for k in range(2)] + [noise_template(m, n, 4500)]
+    for k, tpl in enumerate(tpls):
+        full = O.full_search(img, tpl)
+        for fl in (full["rho"] - 0.05, full["rho"], 0.9, 0.999):
+            print(f"floor {mode} template {k} floor {fl:.4f}", flush=True)
+            if mode == "opta":
+                o = O.opta_search(img, oo["image"], tpl, oo["h"], oo["w"], oo["radius"], decision=False, floor=fl)
+            else:
+                o = O.te_search(img, tpl, info["h"], info["w"], decision=True, floor=fl)
+            if mode == "opta":
+                g = S.search(i, tpl, mode, rho_floor=fl, floor_prune=1)
+            else:
+                g, dec = S.search(i, tpl, mode, decision=True, rho_floor=fl, floor_prune=1, **kw)
+                assert np.array_equal(dec, o["decision"])
+            same_counts(g, o, f"floor {fl}")
+            assert g["above_floor"] == int(g["rho"] >= fl)
+            if fl <= full["rho"]:
+                same_answer(g, o, f"floor {fl}")
+                same_answer(g, full, "floor at or below the maximum")
+            else:
+                # below the floor nothing is claimed but that the answer is an attained location at least as
+                # good as the best centre or survivor (dense tiles may also have matched eliminated locations)
+                y, x = g["y"], g["x"]
+                at = O.full_search(img[y:y + m, x:x + n], tpl)
+                assert (g["num"], g["den_t"], g["den_r"], g["rho"]) == (at["num"], at["den_t"], at["den_r"], at["rho"])
+                assert g["rho"] >= o["rho"] and g["above_floor"] == 0
+            lab = S.search(i, tpl, mode, rho_floor=fl, **kw)
+            same_answer(lab, full, "floor as a label")
+            assert lab["above_floor"] == int(full["rho"] >= fl)
+    S.unload(i)
