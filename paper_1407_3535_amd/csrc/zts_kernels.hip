@@ -2209,8 +2209,11 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int steps = (ROWS + m - 1 + 3) >> 2;
 
-    uint32_t ri[2][2];
-    auto gload = [&](int s) {
+    // Image rows stream through two LDS buffers; their global loads are issued
+    // two steps ahead into two register sets, so each load has two steps of
+    // MFMA work to arrive in (the steps are otherwise bound by load latency).
+    uint32_t rA[2][2], rB[2][2];
+    auto gload = [&](int s, uint32_t (&ri)[2][2]) {
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             int idx = t + 256 * k;
@@ -2229,7 +2232,7 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
             }
         }
     };
-    auto lstore = [&](int s) {
+    auto lstore = [&](int s, const uint32_t (&ri)[2][2]) {
         uint32_t *b = smem + (s & 1) * IMGW;
 #pragma unroll
         for (int k = 0; k < 2; k++) {
@@ -2251,14 +2254,14 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
 #pragma unroll
         for (int mt = 0; mt < MT; mt++)
             acc[r][mt] = v4i{0, 0, 0, 0};
-    gload(0);
-    lstore(0);
+    gload(0, rA);
+    lstore(0, rA);
     __syncthreads();
+    if (1 < steps)
+        gload(1, rB);
     const int g = lane >> 4, jr = lane & 15;
-    for (int s = 0; s < steps; s++) {
+    auto compute = [&](int s) {
         const uint32_t *cur = smem + (s & 1) * IMGW;
-        if (s + 1 < steps)
-            gload(s + 1);
         for (int cb = 0; cb < nb16; cb++) {
             v4i A[MT];
 #pragma unroll
@@ -2285,8 +2288,23 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
                     acc[rg][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B[rg], acc[rg][mt], 0, 0, 0);
             }
         }
+    };
+    // step s reads buffer s & 1; the data of step s + 1 is in rB (s even) or
+    // rA (s odd) and goes to the other buffer, free since the last barrier
+    for (int s = 0; s < steps; s += 2) {
+        if (s + 2 < steps)
+            gload(s + 2, rA);
+        compute(s);
         if (s + 1 < steps)
-            lstore(s + 1);
+            lstore(s + 1, rB);
+        __syncthreads();
+        if (s + 1 >= steps)
+            break;
+        if (s + 3 < steps)
+            gload(s + 3, rB);
+        compute(s + 1);
+        if (s + 2 < steps)
+            lstore(s + 2, rA);
         __syncthreads();
     }
 
@@ -2697,7 +2715,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 // that sees the new number reads a complete state.  The state the earlier
 // kernels wrote is loaded by thread 0 together with the records, and the
 // mirror is written from registers.
-constexpr int kRedThreads = 1024;
+constexpr int kRedThreads = 256;
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi,
                                                         int count_lo, QState *qs, QState *host)
