@@ -357,6 +357,33 @@ ZTS_API zts_status zts_search_device_noalloc(zts_ctx *ctx, int32_t image, const 
 ZTS_API zts_status zts_search_batch(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls, const int32_t *m,
                             const int32_t *n, const int64_t *strides, zts_result *out);
 
+/* Transitive-elimination search (ZTS_TE_FIXED, ZTS_EGS, ZTS_OPTA or
+ * ZTS_OPTA_PAPER) of `count` host templates against one image in one call:
+ * the paper's amortisation over the templates matched against one image
+ * (section III-D, Eq. 16, the auto-correlation cost shared by n_t templates).
+ * Templates are grouped by size; each size is prepared once (the tables are
+ * shared, as for single searches), and scan 1 runs for up to 4 templates of a
+ * size in one int8-MFMA launch (the staged, realigned image fragments feed
+ * every template's MFMAs; a size whose scan 1 has no MFMA form, n > 128, runs
+ * one template per launch).  Each template then gets its own scan 2, survivor
+ * tiles and final reduction.  out[k] receives exactly what zts_search with the
+ * same mode and parameters returns for template k (location, integers,
+ * binary64 rho and counts); a template with zero variance gets
+ * out[k].status = ZTS_E_DEGENERATE while the call returns ZTS_OK.
+ * batch_size = count; device_ms is each template's own device-clock span.
+ * Argument and size errors as for zts_search; ZTS_E_ARG for other modes. */
+ZTS_API zts_status zts_search_batch_pruned(zts_ctx *ctx, int32_t image, int32_t count, const uint8_t *const *tpls,
+                                           const int32_t *m, const int32_t *n, const int64_t *strides,
+                                           zts_mode mode, const zts_params *params, zts_result *out);
+
+/* The same with the templates in device memory (tpls_dev[k] with row pitch
+ * strides[k] bytes), read in place after `stream` (NULL: the context's
+ * stream) has reached the call; returns when the results are on the host. */
+ZTS_API zts_status zts_search_batch_pruned_device(zts_ctx *ctx, int32_t image, int32_t count,
+                                                  const void *const *tpls_dev, const int32_t *m, const int32_t *n,
+                                                  const int64_t *strides, zts_mode mode, const zts_params *params,
+                                                  void *stream, zts_result *out);
+
 /* Measured cost of one template size on the two batched MFMA kernels. */
 typedef struct {
     int32_t m, n;

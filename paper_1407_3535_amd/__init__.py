@@ -37,7 +37,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "size", -3: "degenerate template"
 
 EXPORTS = ["zts_params_default", "zts_params_check", "zts_create", "zts_destroy", "zts_status_str", "zts_image_load",
            "zts_image_load_device", "zts_image_unload", "zts_prepare", "zts_prep_query", "zts_prep_image",
-           "zts_search", "zts_search_device", "zts_search_device_noalloc", "zts_search_batch", "zts_tune_batch", "zts_submit", "zts_submit_batch", "zts_poll",
+           "zts_search", "zts_search_device", "zts_search_device_noalloc", "zts_search_batch", "zts_search_batch_pruned", "zts_search_batch_pruned_device", "zts_tune_batch", "zts_submit", "zts_submit_batch", "zts_poll",
            "zts_wait", "zts_cancel", "zts_pending", "zts_debug_full_map", "zts_debug_autocorr", "zts_debug_blur"]
 
 
@@ -149,6 +149,8 @@ def lib():
                                         C.POINTER(Result)]
         L.zts_search_device_noalloc.argtypes = L.zts_search_device.argtypes
         L.zts_search_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.zts_search_batch_pruned.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, C.POINTER(Params), vp]
+        L.zts_search_batch_pruned_device.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, C.POINTER(Params), vp, vp]
         L.zts_tune_batch.argtypes = [vp, i32, i32, vp, vp, vp]
         L.zts_submit.argtypes = [vp, i32, vp, i32, i32, i64, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.zts_submit_batch.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, C.POINTER(Params), C.POINTER(C.c_uint64)]
@@ -324,6 +326,45 @@ def zts_search_batch(ctx, image: int, tpls) -> list:
     return [r.as_dict() for r in out]
 
 
+def zts_search_batch_pruned(ctx, image: int, tpls, mode, params: Params | None = None) -> list:
+    """Transitive-elimination search of many host templates in one call (scan 1 shared by the templates of
+    one size); one dict per template, each equal to zts_search's."""
+    tpls, ptrs, ms, ns, st = _tpl_arrays(tpls)
+    k = len(tpls)
+    out = (Result * k)()
+    p = params if params is not None else zts_params_default()
+    _check(lib().zts_search_batch_pruned(ctx, image, k, ptrs, ms, ns, st, _mode(mode), C.byref(p), out),
+           "zts_search_batch_pruned")
+    return [r.as_dict() for r in out]
+
+
+class DeviceBatch:
+    """Argument arrays of zts_search_batch_pruned_device for a fixed list of device templates (built once, so
+    a loop that searches the same templates repeatedly marshals nothing per call)."""
+
+    def __init__(self, tensors):
+        self.tensors = list(tensors)
+        k = len(self.tensors)
+        self.count = k
+        self.ptrs = (C.c_void_p * k)(*[t.data_ptr() for t in self.tensors])
+        self.ms = (C.c_int32 * k)(*[t.shape[0] for t in self.tensors])
+        self.ns = (C.c_int32 * k)(*[t.shape[1] for t in self.tensors])
+        self.st = (C.c_int64 * k)(*[t.stride(0) for t in self.tensors])
+        self.out = (Result * k)()
+
+
+def zts_search_batch_pruned_device(ctx, image: int, batch: DeviceBatch, mode, params: Params | None = None,
+                                   stream=None):
+    """zts_search_batch_pruned on device templates (read in place after the caller's stream); fills and
+    returns batch.out (a ctypes array of Result)."""
+    p = params if params is not None else zts_params_default()
+    s = stream if stream is not None else _current_stream(batch.tensors[0].device.index)
+    _check(lib().zts_search_batch_pruned_device(ctx, image, batch.count, batch.ptrs, batch.ms, batch.ns, batch.st,
+                                                _mode(mode), C.byref(p), s, batch.out),
+           "zts_search_batch_pruned_device")
+    return batch.out
+
+
 def _tpl_arrays(tpls):
     tpls = [_u8(t) for t in tpls]
     k = len(tpls)
@@ -469,6 +510,9 @@ class Searcher:
 
     def search_batch(self, image, tpls):
         return zts_search_batch(self.ctx, image, tpls)
+
+    def search_batch_pruned(self, image, tpls, mode="opta", **params):
+        return zts_search_batch_pruned(self.ctx, image, tpls, mode, zts_params_default(**params))
 
     def tune_batch(self, image, sizes):
         return zts_tune_batch(self.ctx, image, sizes)

@@ -2078,6 +2078,163 @@ bool valid_mode(zts_mode mode)
 
 }  // namespace
 
+// ------------------------------------------------------------------ batched pruned search
+
+namespace {
+
+// Every kernel of one query after scan 1 (the batched search runs scan 1 for
+// several templates of one size in one launch).
+void enqueue_after_scan1(const QueryLaunch &Q, hipStream_t st)
+{
+    if (Q.radius >= 0 && !Q.paper)
+        hip_check(launch_window(Q.wa, st));
+    hip_check(launch_members(Q.ma, st));
+    hip_check(launch_dense_tiles(Q.ta, st));
+    hip_check(launch_surv_tiles(Q.ta, st));
+    if (Q.paper)  // localisation on I around the conditioned image's best
+        hip_check(launch_window(Q.wa, st));
+    hip_check(launch_reduce(Q.recs, Q.red_lo, Q.red_hi, Q.count_lo, Q.qs, (QState *)Q.h_qs, st));
+}
+
+// One template's device scratch in a batched search.
+struct PrunedBufs {
+    DBuf qs, recs, gnum, gtheta, tcnt, tbin;
+};
+
+// The batched pruned search on the main slot (context lock held): every size
+// prepared and pinned first, then per size one scan-1 launch for up to
+// kScanMaxT templates at a time (one per template when its shape has no MFMA
+// form), each template's remaining kernels with its own scratch, one stream
+// synchronisation at the end.
+void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, const int32_t *ms, const int32_t *ns,
+                      const int64_t *strides, bool device, hipStream_t caller, zts_mode mode, const zts_params &pr,
+                      zts_result *out)
+{
+    Slot &S = c->main;
+    const hipStream_t st = S.stream;
+    if (device && caller != st && hipStreamQuery(caller) != hipSuccess) {
+        // the kernels read the caller's templates in place, after its stream
+        (void)hipGetLastError();  // hipErrorNotReady: work is pending
+        hip_check(hipEventRecord(S.ev_in, caller));
+        hip_check(hipStreamWaitEvent(st, S.ev_in, 0));
+    }
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int k = 0; k < count; k++)
+        groups[std::make_pair(ms[k], ns[k])].push_back(k);
+    std::vector<QueryPlan> plans(count);
+    std::vector<PrunedBufs> bufs(count);
+    std::vector<QueryLaunch> Q(count);
+    DBuf dtpl;
+    auto unpin_all = [&] {
+        for (auto &q : plans)
+            unpin_query(q);
+    };
+    try {
+        // tables and statistics of every size, pinned for the whole call
+        for (auto &gr : groups) {
+            const int m = gr.first.first, n = gr.first.second;
+            for (int k : gr.second) {
+                QueryPlan &q = plans[k];
+                q.im = im;
+                q.m = m;
+                q.n = n;
+                q.Ly = im->rows - m + 1;
+                q.Lx = im->cols - n + 1;
+                q.mode = mode;
+                q.pr = pr;
+                q.st = stats_entry(c, im, m, n, st);
+                q.st->pins++;
+                q.P = prepare(c, im, m, n, mode, pr);
+                q.P->pins++;
+                q.P->last_use = ++c->clock;
+            }
+        }
+        // host templates: packed at pitch n, through pinned staging in one copy
+        std::vector<size_t> off(count);
+        size_t total = 0;
+        uint8_t *h = nullptr;
+        if (!device) {
+            for (int k = 0; k < count; k++) {
+                off[k] = total;
+                total += ((size_t)ms[k] * ns[k] + 255) & ~(size_t)255;
+            }
+            S.h_stage.grow(total);
+            h = S.h_stage.as<uint8_t>();
+            for (int k = 0; k < count; k++)
+                for (int i = 0; i < ms[k]; i++)
+                    std::memcpy(h + off[k] + (size_t)i * ns[k], tpls[k] + (size_t)i * strides[k], ns[k]);
+            dalloc(c, dtpl, total);
+        }
+        c->h_batch_qs.grow(sizeof(QState) * (size_t)count, hipHostMallocCoherent);
+        QState *mirror = c->h_batch_qs.as<QState>();
+        for (int k = 0; k < count; k++) {
+            QueryPlan &q = plans[k];
+            const Prepared *P = q.P;
+            q.tpl = device ? tpls[k] : dtpl.as<uint8_t>() + off[k];
+            q.ts = device ? strides[k] : ns[k];
+            const int radius = query_radius(q);
+            const TileArgs tg = tile_geometry(q);
+            const size_t ntile = (size_t)tg.tiles_x * tg.tiles_y;
+            const size_t nrec = (size_t)centres_record_count(P->Gy, P->Gx, q.m, q.n, P->h, P->w) +
+                                (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
+                                (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)super_tiles_of(tg);
+            PrunedBufs &b = bufs[k];
+            dalloc(c, b.qs, sizeof(QState));
+            dalloc(c, b.recs, sizeof(RecPod) * nrec);
+            dalloc(c, b.gnum, sizeof(int32_t) * (size_t)P->Gy * P->Gx);
+            dalloc(c, b.gtheta, sizeof(float) * (size_t)P->Gy * P->Gx);
+            dalloc(c, b.tcnt, sizeof(uint32_t) * ntile);
+            dalloc(c, b.tbin, sizeof(int32_t) * ntile * (size_t)tg.tile_cap);
+            const QueryBufs B{b.qs.as<QState>(), b.recs.as<RecPod>(), b.gnum.as<int32_t>(), b.gtheta.as<float>(),
+                              b.tcnt.as<uint32_t>(), b.tbin.as<int32_t>(), nullptr, mirror + k};
+            build_query_launch(q, B, nullptr, Q[k]);
+        }
+        if (!device)
+            hip_check(hipMemcpyAsync(dtpl.ptr, h, total, hipMemcpyHostToDevice, st));
+        for (auto &gr : groups) {
+            const std::vector<int> &ks = gr.second;
+            const Prepared *P = plans[ks[0]].P;
+            const bool shared = ks.size() > 1 && centres_mfma_batchable(gr.first.first, gr.first.second, P->w, 2);
+            size_t i = 0;
+            while (i < ks.size()) {
+                int T = 1;
+                if (shared)
+                    while (T < kScanMaxT && i + T < ks.size() &&
+                           centres_mfma_batchable(gr.first.first, gr.first.second, P->w, T + 1))
+                        T++;
+                ScanArgs sa = Q[ks[i]].sa;
+                sa.ntpl = T;
+                for (int j = 1; j < T; j++) {
+                    const ScanArgs &o = Q[ks[i + j]].sa;
+                    sa.more[j - 1] = ScanTpl{o.tpl, o.ts, o.g_x, o.g_theta, o.recs, o.qs, o.tile_cnt};
+                }
+                hip_check(launch_centres(sa, st));
+                for (int j = 0; j < T; j++)
+                    enqueue_after_scan1(Q[ks[i + j]], st);
+                i += T;
+            }
+        }
+        hip_check(hipStreamSynchronize(st));
+        std::atomic_thread_fence(std::memory_order_acquire);
+        for (int k = 0; k < count; k++) {
+            zts_result r;
+            const zts_status s2 = assemble_result(plans[k], mirror[k], nullptr, &r, c->wall_khz);
+            if (s2 == ZTS_E_DEVICE)
+                throw ZtsError{ZTS_E_DEVICE};
+            if (s2 != ZTS_OK)
+                r = error_result(s2);
+            r.batch_size = count;
+            out[k] = r;
+        }
+    } catch (...) {
+        unpin_all();
+        throw;
+    }
+    unpin_all();
+}
+
+}  // namespace
+
 }  // namespace zts
 
 // ====================================================================== C ABI
@@ -2377,6 +2534,52 @@ ZTS_API zts_status zts_search_batch(zts_ctx *z, int32_t image, int32_t count, co
         for (auto &r : res)
             if (r.status == ZTS_E_DEVICE)
                 throw ZtsError{ZTS_E_DEVICE};
+        std::copy(res.begin(), res.end(), out);
+    });
+}
+
+ZTS_API zts_status zts_search_batch_pruned(zts_ctx *z, int32_t image, int32_t count, const uint8_t *const *tpls,
+                                           const int32_t *m, const int32_t *n, const int64_t *strides, zts_mode mode,
+                                           const zts_params *params, zts_result *out)
+{
+    if (!z || !tpls || !m || !n || !strides || !out || count < 1)
+        return ZTS_E_ARG;
+    if (mode != ZTS_TE_FIXED && mode != ZTS_EGS && mode != ZTS_OPTA && mode != ZTS_OPTA_PAPER)
+        return ZTS_E_ARG;
+    return guarded(&z->c, [&] {
+        Ctx *c = &z->c;
+        Image *im = find_image(c, image);
+        for (int k = 0; k < count; k++) {
+            check_template_args(im, tpls[k], m[k], n[k], strides[k]);
+            check_mode_shape(mode, m[k], n[k]);
+        }
+        const zts_params pr = params_or_default(params);
+        std::vector<zts_result> res(count);
+        run_pruned_batch(c, im, count, tpls, m, n, strides, false, nullptr, mode, pr, res.data());
+        std::copy(res.begin(), res.end(), out);
+    });
+}
+
+ZTS_API zts_status zts_search_batch_pruned_device(zts_ctx *z, int32_t image, int32_t count,
+                                                  const void *const *tpls_dev, const int32_t *m, const int32_t *n,
+                                                  const int64_t *strides, zts_mode mode, const zts_params *params,
+                                                  void *stream, zts_result *out)
+{
+    if (!z || !tpls_dev || !m || !n || !strides || !out || count < 1)
+        return ZTS_E_ARG;
+    if (mode != ZTS_TE_FIXED && mode != ZTS_EGS && mode != ZTS_OPTA && mode != ZTS_OPTA_PAPER)
+        return ZTS_E_ARG;
+    return guarded(&z->c, [&] {
+        Ctx *c = &z->c;
+        Image *im = find_image(c, image);
+        for (int k = 0; k < count; k++) {
+            check_template_args(im, tpls_dev[k], m[k], n[k], strides[k]);
+            check_mode_shape(mode, m[k], n[k]);
+        }
+        const zts_params pr = params_or_default(params);
+        std::vector<zts_result> res(count);
+        run_pruned_batch(c, im, count, (const uint8_t *const *)tpls_dev, m, n, strides, true,
+                         stream ? (hipStream_t)stream : c->stream, mode, pr, res.data());
         std::copy(res.begin(), res.end(), out);
     });
 }

@@ -26,6 +26,19 @@ struct FullArgs {
     int8_t *dec;
 };
 
+// Per-template outputs of a batched scan 1 (templates 1 .. ntpl - 1; template
+// 0 uses the scalar fields of ScanArgs).
+constexpr int kScanMaxT = 4;
+struct ScanTpl {
+    const uint8_t *tpl;
+    int64_t ts;
+    int32_t *g_x;
+    float *g_theta;
+    RecPod *recs;
+    QState *qs;
+    uint32_t *tile_cnt;
+};
+
 // Scan 1: group centres of the searched image.
 struct ScanArgs {
     const uint8_t *img;
@@ -46,6 +59,10 @@ struct ScanArgs {
     int cwd;      // MFMA form: dword stride of the staged image rows of a block's region
     int cwn;      // MFMA form: dwords of each staged row that are read
     int crows_log2;  // MFMA form: log2 of the rows of a staged chunk
+    // MFMA form, batched: ntpl templates of the same size matched in one launch
+    // (each staged image fragment feeds all of them); 1 for a single query
+    int ntpl;
+    ScanTpl more[kScanMaxT - 1];
 };
 
 // Refinement window on the original image.
@@ -249,6 +266,9 @@ hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QStat
 // Zeroes *qs (every word, the sequence number included) with a fill kernel.
 hipError_t launch_qs_clear(QState *qs, hipStream_t s);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
+// Whether scan 1 of an m x n template with group width w runs on int8 MFMA
+// (then a.ntpl templates can share one launch of launch_centres).
+bool centres_mfma_batchable(int m, int n, int w, int ntpl);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);
 int members_record_count(int Gy, int Gx);

@@ -805,29 +805,47 @@ __device__ __forceinline__ void load_template_rows(const uint8_t *__restrict__ t
     *s2 = a2;
 }
 
-template <int NB>  // 16-byte column blocks of the template row (n16 = 16 NB)
+// Per-template fields of a (batched) scan 1.
+__device__ __forceinline__ ScanTpl scan_tpl(const ScanArgs &a, int i)
+{
+    if (i == 0)
+        return ScanTpl{a.tpl, a.ts, a.g_x, a.g_theta, a.recs, a.qs, a.tile_cnt};
+    return a.more[i - 1];
+}
+
+// TM: most templates per launch (a.ntpl of them run); NB: 16-byte column
+// blocks of the template row (n16 = 16 NB).
+template <int NB, int TM>
 __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        a.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
-        a.qs->n_dense = 0;
-        a.qs->n_sparse = 0;
-    }
-    if (a.tile_cnt) {  // scan 2's survivor tile counts start from zero
-        const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
-        for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < a.n_tiles; i += nb * (int)blockDim.x)
-            a.tile_cnt[i] = 0;
+    const int T = TM == 1 ? 1 : a.ntpl;
+#pragma unroll
+    for (int ti = 0; ti < TM; ti++) {
+        if (ti >= T)
+            break;
+        const ScanTpl sp = scan_tpl(a, ti);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+            sp.qs->t0 = __builtin_amdgcn_s_memrealtime();  // the query's first kernel
+            sp.qs->n_dense = 0;
+            sp.qs->n_sparse = 0;
+        }
+        if (sp.tile_cnt) {  // scan 2's survivor tile counts start from zero
+            const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+            for (int i = b * (int)blockDim.x + (int)threadIdx.x; i < a.n_tiles; i += nb * (int)blockDim.x)
+                sp.tile_cnt[i] = 0;
+        }
     }
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[2 * (kCmThreads / 64)];
+    __shared__ int red[2 * TM * (kCmThreads / 64)];
     __shared__ RecPod rred[kCmThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, mt = wv & 3, kh = wv >> 2;
     const int m = a.m, n = a.n;
     constexpr int nw16 = 4 * NB;
     const int tstr = batch_tstride(nw16), CWd = a.cwd, CWn = a.cwn;
+    const int twords = (m + 1) * tstr;              // one template's rows in LDS
     const int crl = a.crows_log2, crows = 1 << crl, CW = crows * CWd;
-    uint32_t *tpl_l = smem;                         // m rows and the zero row m, stride tstr
-    uint32_t *buf0 = smem + (m + 1) * tstr;         // two chunk buffers of CW dwords
+    uint32_t *tpl_l = smem;                         // per template: m rows and the zero row m, stride tstr
+    uint32_t *buf0 = smem + T * twords;             // two chunk buffers of CW dwords
     auto ccol = [&](int gx) { int ox = gx * a.w; return ox + (min(a.w, a.Lx - ox) - 1) / 2; };
     auto crow = [&](int gy) { int oy = gy * a.h; return oy + (min(a.h, a.Ly - oy) - 1) / 2; };
     // XCD-aware placement: the hardware deals workgroup ids round-robin over
@@ -882,7 +900,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     const int cyb = crow(min(gy0 + jr, a.Gy - 1));                        // B lane: its centre row
     const bool jok = jr < ny;
     // The first chunk and the epilogue's centre statistics are in flight
-    // while the template loads.
+    // while the templates load.
     cload(0);
     // accumulator lane: centre row gy0 + (lane & 15), centre columns
     // gx0 + 16 mt + 4 (lane >> 4) + v; this wave finishes v = 2 kh, 2 kh + 1
@@ -897,11 +915,21 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     }
     // the template statistics are reduced after the main loop, which needs
     // only the rows (published by the barrier below)
-    int ps, ps2;
-    load_template_rows(a.tpl, a.ts, m, n, nw16, tstr, tpl_l, &ps, &ps2);
+    int ps[TM], ps2[TM];
+#pragma unroll
+    for (int ti = 0; ti < TM; ti++) {
+        ps[ti] = ps2[ti] = 0;
+        if (ti < T) {
+            const ScanTpl sp = scan_tpl(a, ti);
+            load_template_rows(sp.tpl, sp.ts, m, n, nw16, tstr, tpl_l + ti * twords, &ps[ti], &ps2[ti]);
+        }
+    }
     cstore(0);
     __syncthreads();
-    v4i acc = v4i{0, 0, 0, 0};
+    v4i acc[TM];
+#pragma unroll
+    for (int ti = 0; ti < TM; ti++)
+        acc[ti] = v4i{0, 0, 0, 0};
     const int aw = cxa >> 2;
     const uint32_t ash = (uint32_t)(cxa & 3);
     for (int c = 0; c < nchunk; c++) {
@@ -914,130 +942,148 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
             const int tr = ylo + (c << crl) + yr - cyb;    // template row for B lane (jr, g)
             const int brow = jok && (unsigned)tr < (unsigned)m ? tr : m;
             const uint32_t *pa = b + yr * CWd + aw;
-            const uint32_t *pb = tpl_l + brow * tstr;
-            // bytes cxa + 16 cb .. + 15 of the row are words 4 cb .. 4 cb + 4
+            // bytes cxa + 16 cb .. + 15 of the row are words 4 cb .. 4 cb + 4;
+            // the realigned A fragments feed every template's MFMAs
             uint32_t wd[4 * NB + 1];
-            v4i B[NB];
 #pragma unroll
             for (int i = 0; i <= 4 * NB; i++)
                 wd[i] = pa[i];
-#pragma unroll
-            for (int cb = 0; cb < NB; cb++)
-                B[cb] = *(const v4i *)(pb + 4 * cb);
+            v4i A[NB];
 #pragma unroll
             for (int cb = 0; cb < NB; cb++) {
-                v4i A;
-                A[0] = (int)bytes_at(wd[4 * cb + 1], wd[4 * cb], ash);
-                A[1] = (int)bytes_at(wd[4 * cb + 2], wd[4 * cb + 1], ash);
-                A[2] = (int)bytes_at(wd[4 * cb + 3], wd[4 * cb + 2], ash);
-                A[3] = (int)bytes_at(wd[4 * cb + 4], wd[4 * cb + 3], ash);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B[cb], acc, 0, 0, 0);
+                A[cb][0] = (int)bytes_at(wd[4 * cb + 1], wd[4 * cb], ash);
+                A[cb][1] = (int)bytes_at(wd[4 * cb + 2], wd[4 * cb + 1], ash);
+                A[cb][2] = (int)bytes_at(wd[4 * cb + 3], wd[4 * cb + 2], ash);
+                A[cb][3] = (int)bytes_at(wd[4 * cb + 4], wd[4 * cb + 3], ash);
+            }
+#pragma unroll
+            for (int ti = 0; ti < TM; ti++) {
+                if (ti >= T)
+                    break;
+                const uint32_t *pb = tpl_l + ti * twords + brow * tstr;
+                v4i B[NB];
+#pragma unroll
+                for (int cb = 0; cb < NB; cb++)
+                    B[cb] = *(const v4i *)(pb + 4 * cb);
+#pragma unroll
+                for (int cb = 0; cb < NB; cb++)
+                    acc[ti] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[cb], B[cb], acc[ti], 0, 0, 0);
             }
         }
         if (c + 1 < nchunk)
             cstore(c + 1);
         __syncthreads();
     }
-    // the two waves of an M-tile swap the partial sums of the columns the
-    // other one finishes (the chunk buffers are free: the loop ended with a
-    // barrier)
-    int2 *xch = (int2 *)buf0;
-    xch[(kh * 4 + mt) * 64 + lane] = kh ? make_int2(acc[0], acc[1]) : make_int2(acc[2], acc[3]);
-    ps = wave_sum(ps);
-    ps2 = wave_sum(ps2);
-    if (lane == 0) {
-        red[wv] = ps;
-        red[kCmThreads / 64 + wv] = ps2;
-    }
-    __syncthreads();
-    const int2 o = xch[((1 - kh) * 4 + mt) * 64 + lane];
-    int64_t st = 0, sq2 = 0;
+    // template statistics of every template at once
 #pragma unroll
-    for (int k = 0; k < kCmThreads / 64; k++) {
-        st += red[k];
-        sq2 += red[kCmThreads / 64 + k];
+    for (int ti = 0; ti < TM; ti++) {
+        const int s1 = wave_sum(ps[ti]), s2 = wave_sum(ps2[ti]);
+        if (lane == 0 && ti < T) {
+            red[(2 * ti) * (kCmThreads / 64) + wv] = s1;
+            red[(2 * ti + 1) * (kCmThreads / 64) + wv] = s2;
+        }
     }
     const int64_t mn = (int64_t)m * n;
-    const int64_t dt = mn * sq2 - st * st;
-    if (dt == 0) {  // uniform over the block
-        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
-            a.qs->degenerate = 1;
-        return;
-    }
-    int64_t num[2], dc[2];
-    float r32[2];
-    bool ok[2];
-    float lmax = -2.0f;
-#pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const int v = 2 * kh + e;
-        const int gxx = gx0 + 16 * mt + 4 * g + v;
-        ok[e] = gyy < a.Gy && gxx < a.Gx;
-        const int x = (kh ? acc[2 + e] : acc[e]) + (e ? o.y : o.x);
-        dc[e] = var_num(mn, sc[e]);
-        num[e] = mn * (int64_t)x - st * (int64_t)sc[e].x;
-        r32[e] = rho32(num[e], dt, dc[e]);
-        if (ok[e]) {
-            const int gi = gyy * a.Gx + gxx;
-            a.g_x[gi] = x;
-            a.g_theta[gi] = theta32(num[e], dt, dc[e]);
-            lmax = fmaxf(lmax, r32[e]);
-            if (a.dec)
-                a.dec[(int64_t)crow(gyy) * a.Lx + ccol(gxx)] = 1;
-        }
-    }
-    // Only centres within kEpsRho of the wave's largest binary32 rho can be
-    // the block's best: they alone are evaluated in binary64, and the wave's
-    // record is picked among those lanes (usually one) in lane order.
-    float wmax = lmax;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        wmax = fmaxf(wmax, __shfl_xor(wmax, off));
-    double brho = -2.0;
-    int64_t bl = INT64_MAX, bnum = 0, bdr = 0;
-    bool bv = false;
-#pragma unroll
-    for (int e = 0; e < 2; e++)
-        if (ok[e] && r32[e] >= wmax - kEpsRho) {
-            const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
-            const int64_t l = (int64_t)crow(gyy) * a.Lx + ccol(gxx);
-            const double r = rho64(num[e], dt, dc[e]);
-            if (!bv || rec_better(r, l, brho, bl)) {
-                brho = r;
-                bl = l;
-                bnum = num[e];
-                bdr = dc[e];
-                bv = true;
-            }
-        }
-    RecPod rec = rec_empty();
-    rec.r32max = wmax;
-    for (uint64_t msk = __ballot(bv); msk; msk &= msk - 1) {
-        const int src = __ffsll((unsigned long long)msk) - 1;
-        const double r = __shfl(brho, src);
-        const int64_t l = (int64_t)__shfl((long long)bl, src);
-        if (!rec.valid || rec_better(r, l, rec.rho, rec.l)) {
-            rec.rho = r;
-            rec.l = l;
-            rec.num = (int64_t)__shfl((long long)bnum, src);
-            rec.dr = (int64_t)__shfl((long long)bdr, src);
-            rec.valid = 1;
-        }
-    }
-    if (lane == 0)
-        rred[wv] = rec;
-    __syncthreads();
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (wv == 0) {  // the eight wave records merged by shuffles in lanes 0..7
-        RecPod bb = wave_rec<kCmThreads / 64>(lane < kCmThreads / 64 ? rred[lane] : rec_empty());
-        if (lane == 0) {
-            a.recs[bid] = bb;
-            if (bid == 0) {  // the query state needs no fill before the scans
-                a.qs->st = st;
-                a.qs->dt = dt;
-                a.qs->degenerate = 0;
+    int2 *xch = (int2 *)buf0;  // the chunk buffers are free: the loop ended with a barrier
+#pragma unroll
+    for (int ti = 0; ti < TM; ti++) {
+        if (ti >= T)
+            break;
+        const ScanTpl sp = scan_tpl(a, ti);
+        // the two waves of an M-tile swap the partial sums of the columns the
+        // other one finishes
+        xch[(kh * 4 + mt) * 64 + lane] = kh ? make_int2(acc[ti][0], acc[ti][1]) : make_int2(acc[ti][2], acc[ti][3]);
+        __syncthreads();
+        const int2 o = xch[((1 - kh) * 4 + mt) * 64 + lane];
+        int64_t st = 0, sq2 = 0;
+#pragma unroll
+        for (int k = 0; k < kCmThreads / 64; k++) {
+            st += red[(2 * ti) * (kCmThreads / 64) + k];
+            sq2 += red[(2 * ti + 1) * (kCmThreads / 64) + k];
+        }
+        const int64_t dt = mn * sq2 - st * st;
+        if (dt == 0) {  // uniform over the block
+            if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
+                sp.qs->degenerate = 1;
+            __syncthreads();  // xch is rewritten by the next template
+            continue;
+        }
+        int64_t num[2], dc[2];
+        float r32[2];
+        bool ok[2];
+        float lmax = -2.0f;
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const int v = 2 * kh + e;
+            const int gxx = gx0 + 16 * mt + 4 * g + v;
+            ok[e] = gyy < a.Gy && gxx < a.Gx;
+            const int x = (kh ? acc[ti][2 + e] : acc[ti][e]) + (e ? o.y : o.x);
+            dc[e] = var_num(mn, sc[e]);
+            num[e] = mn * (int64_t)x - st * (int64_t)sc[e].x;
+            r32[e] = rho32(num[e], dt, dc[e]);
+            if (ok[e]) {
+                const int gi = gyy * a.Gx + gxx;
+                sp.g_x[gi] = x;
+                sp.g_theta[gi] = theta32(num[e], dt, dc[e]);
+                lmax = fmaxf(lmax, r32[e]);
+                if (ti == 0 && a.dec)
+                    a.dec[(int64_t)crow(gyy) * a.Lx + ccol(gxx)] = 1;
             }
         }
+        // Only centres within kEpsRho of the wave's largest binary32 rho can be
+        // the block's best: they alone are evaluated in binary64, and the wave's
+        // record is picked among those lanes (usually one) in lane order.
+        float wmax = lmax;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            wmax = fmaxf(wmax, __shfl_xor(wmax, off));
+        double brho = -2.0;
+        int64_t bl = INT64_MAX, bnum = 0, bdr = 0;
+        bool bv = false;
+#pragma unroll
+        for (int e = 0; e < 2; e++)
+            if (ok[e] && r32[e] >= wmax - kEpsRho) {
+                const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
+                const int64_t l = (int64_t)crow(gyy) * a.Lx + ccol(gxx);
+                const double r = rho64(num[e], dt, dc[e]);
+                if (!bv || rec_better(r, l, brho, bl)) {
+                    brho = r;
+                    bl = l;
+                    bnum = num[e];
+                    bdr = dc[e];
+                    bv = true;
+                }
+            }
+        RecPod rec = rec_empty();
+        rec.r32max = wmax;
+        for (uint64_t msk = __ballot(bv); msk; msk &= msk - 1) {
+            const int src = __ffsll((unsigned long long)msk) - 1;
+            const double r = __shfl(brho, src);
+            const int64_t l = (int64_t)__shfl((long long)bl, src);
+            if (!rec.valid || rec_better(r, l, rec.rho, rec.l)) {
+                rec.rho = r;
+                rec.l = l;
+                rec.num = (int64_t)__shfl((long long)bnum, src);
+                rec.dr = (int64_t)__shfl((long long)bdr, src);
+                rec.valid = 1;
+            }
+        }
+        if (lane == 0)
+            rred[wv] = rec;
+        __syncthreads();
+        if (wv == 0) {  // the eight wave records merged by shuffles in lanes 0..7
+            RecPod bb = wave_rec<kCmThreads / 64>(lane < kCmThreads / 64 ? rred[lane] : rec_empty());
+            if (lane == 0) {
+                sp.recs[bid] = bb;
+                if (bid == 0) {  // the query state needs no fill before the scans
+                    sp.qs->st = st;
+                    sp.qs->dt = dt;
+                    sp.qs->degenerate = 0;
+                }
+            }
+        }
+        __syncthreads();  // rred and xch are rewritten by the next template
     }
 }
 
@@ -3006,10 +3052,10 @@ static int centres_bank_cost(int cwd, int w)
     return cost;
 }
 
-static size_t centres_mfma_lds(int m, int n, int cwd, int crows)
+static size_t centres_mfma_lds(int m, int n, int cwd, int crows, int ntpl = 1)
 {
     int n16 = (n + 15) / 16 * 16;
-    return ((size_t)(m + 1) * batch_tstride(n16 / 4) + (size_t)2 * crows * cwd) * 4;
+    return ((size_t)ntpl * (m + 1) * batch_tstride(n16 / 4) + (size_t)2 * crows * cwd) * 4;
 }
 
 // Staging shape of k_centres_mfma: chunk rows (64, 32 or 16, the most that
@@ -3071,24 +3117,61 @@ int centres_record_count(int Gy, int Gx, int m, int n, int h, int w)
     return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(m, n, h)));
 }
 
+// LDS of several templates' rows beside the chunk buffers of the one-template
+// shape (the chunk height stays that of a single query).
+constexpr size_t kCmBatchLds = 150 * 1024;
+
+bool centres_mfma_batchable(int m, int n, int w, int ntpl)
+{
+    const CmShape sh = centres_mfma_shape(m, n, w);
+    return sh.cwd && ntpl >= 1 && ntpl <= kScanMaxT &&
+           centres_mfma_lds(m, n, sh.cwd, sh.crows, ntpl) + static_lds((const void *)k_centres_mfma<8, kScanMaxT>) <=
+               kCmBatchLds;
+}
+
+template <int NB> static void launch_cm(const ScanArgs &a, dim3 grid, dim3 blk, size_t lds, hipStream_t s)
+{
+    if (a.ntpl <= 1)
+        hipLaunchKernelGGL((k_centres_mfma<NB, 1>), grid, blk, lds, s, a);
+    else
+        hipLaunchKernelGGL((k_centres_mfma<NB, kScanMaxT>), grid, blk, lds, s, a);
+}
+
+template <int NB> static hipError_t allow_cm(int ntpl, size_t lds)
+{
+    return ntpl <= 1 ? allow_lds((const void *)k_centres_mfma<NB, 1>, lds)
+                     : allow_lds((const void *)k_centres_mfma<NB, kScanMaxT>, lds);
+}
+
 hipError_t launch_centres(ScanArgs a, hipStream_t s)
 {
     CmShape sh = centres_mfma_shape(a.m, a.n, a.w);
+    if (a.ntpl < 1)
+        a.ntpl = 1;
+    if (a.ntpl > 1 && !centres_mfma_batchable(a.m, a.n, a.w, a.ntpl))
+        return hipErrorInvalidValue;
     if (sh.cwd) {
         a.cwd = sh.cwd;
         a.cwn = sh.cwn;
         a.crows_log2 = sh.crows == 64 ? 6 : sh.crows == 32 ? 5 : 4;
-        size_t lds = centres_mfma_lds(a.m, a.n, sh.cwd, sh.crows);
+        size_t lds = centres_mfma_lds(a.m, a.n, sh.cwd, sh.crows, a.ntpl);
         dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, 16)), blk(kCmThreads);
-        switch ((a.n + 15) / 16) {
-        case 1: hipLaunchKernelGGL(k_centres_mfma<1>, grid, blk, lds, s, a); break;
-        case 2: hipLaunchKernelGGL(k_centres_mfma<2>, grid, blk, lds, s, a); break;
-        case 3: hipLaunchKernelGGL(k_centres_mfma<3>, grid, blk, lds, s, a); break;
-        case 4: hipLaunchKernelGGL(k_centres_mfma<4>, grid, blk, lds, s, a); break;
-        case 5: hipLaunchKernelGGL(k_centres_mfma<5>, grid, blk, lds, s, a); break;
-        case 6: hipLaunchKernelGGL(k_centres_mfma<6>, grid, blk, lds, s, a); break;
-        case 7: hipLaunchKernelGGL(k_centres_mfma<7>, grid, blk, lds, s, a); break;
-        default: hipLaunchKernelGGL(k_centres_mfma<8>, grid, blk, lds, s, a); break;
+        const int nb = (a.n + 15) / 16;
+        hipError_t e = nb == 1 ? allow_cm<1>(a.ntpl, lds) : nb == 2 ? allow_cm<2>(a.ntpl, lds)
+                     : nb == 3 ? allow_cm<3>(a.ntpl, lds) : nb == 4 ? allow_cm<4>(a.ntpl, lds)
+                     : nb == 5 ? allow_cm<5>(a.ntpl, lds) : nb == 6 ? allow_cm<6>(a.ntpl, lds)
+                     : nb == 7 ? allow_cm<7>(a.ntpl, lds) : allow_cm<8>(a.ntpl, lds);
+        if (e != hipSuccess)
+            return e;
+        switch (nb) {
+        case 1: launch_cm<1>(a, grid, blk, lds, s); break;
+        case 2: launch_cm<2>(a, grid, blk, lds, s); break;
+        case 3: launch_cm<3>(a, grid, blk, lds, s); break;
+        case 4: launch_cm<4>(a, grid, blk, lds, s); break;
+        case 5: launch_cm<5>(a, grid, blk, lds, s); break;
+        case 6: launch_cm<6>(a, grid, blk, lds, s); break;
+        case 7: launch_cm<7>(a, grid, blk, lds, s); break;
+        default: launch_cm<8>(a, grid, blk, lds, s); break;
         }
         return hipGetLastError();
     }

@@ -181,6 +181,7 @@ struct Ctx {
     DBuf counter, tmp32, viol, colmask, psat;  // preparation scratch
     HostBuf h_cnt;
     HostBuf h_qs_noalloc;         // host mirror of zts_search_device_noalloc's query state
+    HostBuf h_batch_qs;           // host mirrors of zts_search_batch_pruned's query states
     int next_id = 1;
     std::map<int, std::unique_ptr<Image>> images;
     int max_inflight = 4;

@@ -721,3 +721,43 @@ def test_detection_floor(S, mode):
             same_answer(lab, full, "floor as a label")
             assert lab["above_floor"] == int(full["rho"] >= fl)
     S.unload(i)
+
+
+@pytest.mark.parametrize("mode,kw", [("te_fixed", dict(group_h=3, group_w=4)), ("egs", dict(refine_radius=2)),
+                                     ("opta", dict(refine_radius=2)), ("opta", {}), ("opta_paper", {})])
+def test_batch_pruned_equals_single_searches(S, mode, kw):
+    """zts_search_batch_pruned: templates of several sizes (groups of 1, 3 and 6 templates, so scan 1 runs for
+    4 + 2 templates in one launch, and a width over 128 that has no MFMA scan 1), a flat template, in one call;
+    every result equals the single search's (location, integers, binary64 rho, counts) and, for the exact
+    modes, the oracle's plain answer."""
+    img = aerial_image(220, 260, 5150, beta=2.3)
+    sizes = [(24, 24)] * 6 + [(17, 29)] * 3 + [(40, 40), (12, 140)]
+    tpls = [cut_template(img, m, n, 5200 + k, 9.0, affine=True)[0] for k, (m, n) in enumerate(sizes)]
+    tpls.insert(4, np.full((24, 24), 77, np.uint8))  # flat: its own status, the others unaffected
+    i = S.load(img)
+    res = S.search_batch_pruned(i, tpls, mode, **kw)
+    assert len(res) == len(tpls)
+    for k, t in enumerate(tpls):
+        print(f"batch pruned {mode} template {k} {t.shape}", flush=True)
+        if t.min() == t.max():
+            assert res[k]["status"] == -3
+            continue
+        g = S.search(i, t, mode, **kw)
+        assert res[k]["status"] == 0
+        for key in KEYS + ("rho32", "n_locations", "n_centres", "n_eliminated", "n_survivors", "n_computed",
+                           "group_h", "group_w", "best0", "n_dense", "n_sparse"):
+            assert res[k][key] == g[key], (mode, k, key, res[k][key], g[key])
+        if mode != "opta_paper":
+            same_answer(res[k], O.full_search(img, t), f"batch pruned {mode} {k}")
+    # the device form: the same templates read in place from device memory (one with strided rows)
+    import torch
+    tdev = [torch.from_numpy(t).cuda() for t in tpls]
+    wide = torch.zeros((24, 40), dtype=torch.uint8, device="cuda")
+    wide[:, 3:27] = tdev[0]
+    tdev[0] = wide[:, 3:27]
+    out = Z.zts_search_batch_pruned_device(S.ctx, i, Z.DeviceBatch(tdev), mode, Z.zts_params_default(**kw))
+    for k in range(len(tpls)):
+        d = out[k].as_dict()
+        for key in KEYS + ("status", "n_eliminated", "n_survivors", "n_computed"):
+            assert d[key] == res[k][key], (mode, k, key)
+    S.unload(i)
