@@ -1088,7 +1088,7 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
             int n3 = members_record_count(P->Gy, P->Gx);
             const TileArgs tg = tile_geometry(q);
             const size_t ntile = (size_t)tg.tiles_x * tg.tiles_y;
-            dalloc(c, S.recs, sizeof(RecPod) * ((size_t)n1 + n2 + n3 + ntile + super_tiles_of(tg)));
+            dalloc(c, S.recs, sizeof(RecPod) * ((size_t)n1 + n2 + n3 + ntile + dense_blocks_of(tg)));
             dalloc(c, S.gnum, sizeof(int32_t) * (size_t)P->Gy * P->Gx);
             dalloc(c, S.gtheta, sizeof(float) * (size_t)P->Gy * P->Gx);
             dalloc(c, S.tcnt, sizeof(uint32_t) * ntile);
@@ -1199,7 +1199,7 @@ static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d
     Q.n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
     Q.n2 = radius >= 0 ? window_record_count(radius) : 0;
     Q.n3 = members_record_count(P->Gy, P->Gx);
-    Q.n4 = ta.tiles_x * ta.tiles_y + super_tiles_of(ta);
+    Q.n4 = ta.tiles_x * ta.tiles_y + dense_blocks_of(ta);
     // records: [0, n1) scan 1, then the window, scan 2 and the survivor tiles
     // (ZTS_OPTA_PAPER: scan 2 and the tiles, then the window on I, whose best
     // is the answer)
@@ -1596,7 +1596,6 @@ static int multi_min_from(float single_ms, float shared_ms)
     return INT32_MAX;  // a tile of 16 costs more than 16 lone templates
 }
 
-static constexpr int64_t kSingleMinBlocks = 512;  // 256 CUs x 2 resident k_single blocks
 
 BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items, int force)
 {
@@ -1648,24 +1647,10 @@ BatchPlan plan_batch(Ctx *c, Slot &S, std::vector<BatchItem> items, int force)
                 for (int k : bk)
                     add_job(std::vector<int>{k}, BATCH_SINGLE);
         }
-    // Row groups per k_single block: 8 unless the single jobs then leave
-    // resident block slots of the chip empty (fewer than kSingleMinBlocks
-    // blocks), then 4 or 2.  Measured with one 16..128 px template: 2048^2
-    // runs 1.8x faster on 32-row blocks than on 128-row ones; from 4096^2 up
-    // 128-row blocks are the fastest.
-    {
-        int rg = 8;
-        for (; rg > 2; rg >>= 1) {
-            int64_t nb = 0;
-            for (const BatchJob &J : b.jobs)
-                if (J.kind == BATCH_SINGLE)
-                    nb += (int64_t)((J.Lx + 255) / 256) * ((J.Ly + 16 * rg - 1) / (16 * rg));
-            if (nb >= kSingleMinBlocks)
-                break;
-        }
-        for (BatchJob &J : b.jobs)
-            J.rg = J.kind == BATCH_SINGLE ? rg : 0;
-    }
+    // Two row groups (32 output rows) per k_single block: the body runs every
+    // row group in every step, which keeps the rows of a block few.
+    for (BatchJob &J : b.jobs)
+        J.rg = J.kind == BATCH_SINGLE ? 2 : 0;
     const size_t njobs = b.jobs.size();
     b.table_bytes = (njobs * sizeof(BatchJob) + 255) & ~(size_t)255;
     size_t off = b.table_bytes;
@@ -1927,7 +1912,7 @@ static void run_query_noalloc(Ctx *c, Image *im, const uint8_t *tpl, int m, int 
             cap = (size_t)tg.tile_cap;
             nrec = (size_t)centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w) +
                    (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
-                   (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)super_tiles_of(tg);
+                   (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)dense_blocks_of(tg);
             groups = (size_t)P->Gy * P->Gx;
         }
         const size_t o_qs = take(sizeof(QState)), o_rec = take(sizeof(RecPod) * nrec);
@@ -2177,7 +2162,7 @@ void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, 
             const size_t ntile = (size_t)tg.tiles_x * tg.tiles_y;
             const size_t nrec = (size_t)centres_record_count(P->Gy, P->Gx, q.m, q.n, P->h, P->w) +
                                 (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
-                                (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)super_tiles_of(tg);
+                                (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)dense_blocks_of(tg);
             PrunedBufs &b = bufs[k];
             dalloc(c, b.qs, sizeof(QState));
             dalloc(c, b.recs, sizeof(RecPod) * nrec);

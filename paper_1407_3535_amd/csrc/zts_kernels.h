@@ -279,10 +279,11 @@ int tiles_y_of(int Ly);
 // Fills the geometry fields of a (n16, dense_min, tile_cap, sparse_lds,
 // region_words) for its m, n and the wanted dense threshold (0: never).
 void tile_plan(TileArgs &a, int dense_min);
-// Super-tiles (4 tiles stacked, 128 x 256 locations) of the dense kernel:
-// their records follow the tiles' (tiles_x * tiles_y + super_tiles_of(a)
-// records from rec_off; super_tiles_of is 0 without a dense path).
-int super_tiles_of(const TileArgs &a);
+// Blocks of the dense kernel (one per tile; whether a tile is matched whole
+// is decided per super-tile of 4 stacked tiles, 128 x 256 locations): their
+// records follow the tiles' (tiles_x * tiles_y + dense_blocks_of(a) records
+// from rec_off; dense_blocks_of is 0 without a dense path).
+int dense_blocks_of(const TileArgs &a);
 // k_dense_tiles (nothing when a.dense_min is 0), then k_surv_tiles.
 hipError_t launch_dense_tiles(TileArgs a, hipStream_t s);
 hipError_t launch_surv_tiles(TileArgs a, hipStream_t s);

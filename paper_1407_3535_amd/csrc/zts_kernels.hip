@@ -2202,34 +2202,53 @@ __global__ __launch_bounds__(256, 2) void k_batch(const BatchJob *__restrict__ j
 // output rows and K = 4 image rows x 16 columns.  For image rows 4s..4s+3
 // and output row y0 + 16 rg + j, lane (j, g) of the B fragment carries
 // template row 4s + g - 16 rg - j (a Toeplitz arrangement; rows outside the
-// template read an all-zero row), so one A fragment feeds every row group.
-// The template is staged whole in LDS once; the image streams through LDS
-// in 4-row steps as in k_batch.  A wave holds RG row groups x MT M-tiles; the
-// block's four waves sit side by side: 16 RG rows x 256 columns per block.
-// Row groups that meet no template row in a step skip their MFMAs.  RG is 8
-// when the image gives enough blocks to fill the chip, else 4 or 2 (more,
-// shorter blocks; each A fragment then feeds fewer row groups).
-constexpr int kSingleCap = 256;   // candidate list entries (one per thread)
-// Epilogue LDS (dwords): per wave a 16 x 64 value slice (overflow path) and a
-// statistics buffer of 64 lanes x 36 dwords (a lane's 16 int2 contiguous, the
-// lane stride padded for conflict-free 16-byte reads), then the candidate
-// list, 4 maxima and a counter.  The 256 block records of the final
-// reduction reuse the slices and buffers.
-constexpr int kSingleLaneStride = 36;
-constexpr int kSingleEpiStats = 4 * 16 * 64;
-constexpr int kSingleEpiList = kSingleEpiStats + 4 * 64 * kSingleLaneStride;
-constexpr int kSingleEpiMax = kSingleEpiList + 4 * kSingleCap;
-constexpr int kSingleLdsWords = kSingleEpiMax + 8;
-static_assert(256 * sizeof(RecPod) / 4 <= kSingleEpiList, "records fit below the candidate list");
+// template read zero rows), so one A fragment feeds every row group.  The
+// template is staged whole in LDS once with zero rows around it; the image
+// streams through LDS in 4-row steps (four byte-shifted copies of each row,
+// so every A lane reads whole words).  A wave holds RG row groups x 4
+// M-tiles; the block's four waves sit side by side: 16 RG rows x 256
+// columns per block.  Every row group takes part in every step (a group that
+// meets no template row multiplies zero rows): the MFMA sequence of a step
+// is then the same for every step, so the fragment reads of the next column
+// block are issued before the MFMAs of the current one and each MFMA waits
+// only for its own operands.  With RG = 2 a block needs about 15 to 40 KB of
+// LDS and under 128 VGPRs, so four blocks share a CU and hide each other's
+// staging and epilogue latency.
+constexpr int kSingleCap = 256;   // candidate list entries
+// Epilogue LDS (dwords, reusing the image buffers): the candidate list, the
+// four wave maxima, the candidate count and the four wave records.
+constexpr int kSingleEpiMax = 4 * kSingleCap;
+constexpr int kSingleEpiRed = kSingleEpiMax + 8;
+constexpr int kSingleLdsWords = kSingleEpiRed + 4 * (int)(sizeof(RecPod) / 4);
 
-__host__ __device__ inline int single_tpl_words(int m, int n16) { return (m + 1) * batch_tstride(n16 >> 2); }
+// The staged template carries zero rows around it: B lane (j, g) of row group
+// rg at step s reads template row d + g - j with d = 4s - 16 rg clamped to
+// -4 (before the template) or m + 16 (after it) when the group meets no
+// template row, so rows -19 .. m + 19 are read without a per-lane clamp.
+constexpr int kSinglePadLo = 19, kSinglePadHi = 20;
+__host__ __device__ inline int single_tpl_words(int m, int n16)
+{
+    // 8 words of slack: the pipelined reads of the column block after the
+    // last one stay inside the allocation (their values are never used)
+    return (m + kSinglePadLo + kSinglePadHi) * batch_tstride(n16 >> 2) + 8;
+}
 
-// One 16 RG x 256 block of locations of one template (the body of k_single,
-// also the dense path of k_surv_tiles).  The caller has staged the template
-// at smem + single_tpl_offset(n16) in the int8 view, rows of n16 / 4 words at
-// stride batch_tstride(n16 / 4), followed by an all-zero row m, and checked
-// that D_t > 0.  Returns the block's best location (valid in thread 0; the
-// block's LDS is reused).
+// Zeroes the pad rows of a staged single template (tpl_l: row -kSinglePadLo).
+__device__ __forceinline__ void single_tpl_pads(uint32_t *tpl_l, int m, int nw16, int tstr)
+{
+    for (int idx = threadIdx.x; idx < (kSinglePadLo + kSinglePadHi) * nw16; idx += blockDim.x) {
+        const int r = idx / nw16, c = idx - r * nw16;
+        tpl_l[(r < kSinglePadLo ? r : r + m) * tstr + c] = 0;
+    }
+}
+
+__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 16 * batch_copy_stride((256 + n16 + 16) >> 2); }
+
+// One 16 RG x 256 block of locations of one template (the body of k_single
+// and of k_dense_tiles).  The caller has staged the template at
+// smem + single_tpl_offset(n16) in the int8 view, row r at (r + kSinglePadLo)
+// strides of batch_tstride(n16 / 4) words (n16 / 4 of them), with the pad
+// rows zeroed by single_tpl_pads, and checked that D_t > 0.
 struct SingleTile {
     const uint8_t *img;
     int64_t pitch;
@@ -2239,43 +2258,40 @@ struct SingleTile {
     int64_t St, Dt;    // sum(t') and D_t
 };
 
-__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 16 * batch_copy_stride((256 + n16 + 16) >> 2); }
-
+// Returns the block's best location (valid in thread 0; the block's LDS is
+// reused).
 template <int RG>
 __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t *smem)
 {
-    static_assert(RG == 2 || RG == 4 || RG == 8, "row groups per block");
+    static_assert(RG >= 1 && RG <= 4, "row groups per block");
     constexpr int MT = 4, ROWS = 16 * RG;
-    const int m = a.m, n16 = a.n16, nb16 = n16 >> 4, nw16 = n16 >> 2;
+    const int m = a.m, n16 = a.n16, nb16 = n16 >> 4;
     const int WW = (256 + n16 + 16) >> 2;
     const int CS = batch_copy_stride(WW);
     const int IMGW = 16 * CS;
-    const int tstr = batch_tstride(nw16);
-    const uint32_t *tpl_l = smem + 2 * IMGW;  // rows 0..m-1, then the zero row m
+    const int tstr = batch_tstride(n16 >> 2);
+    const uint32_t *tpl_l = smem + 2 * IMGW;  // row -kSinglePadLo of the padded template
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int steps = (ROWS + m - 1 + 3) >> 2;
 
     // Image rows stream through two LDS buffers; their global loads are issued
-    // two steps ahead into two register sets, so each load has two steps of
-    // MFMA work to arrive in (the steps are otherwise bound by load latency).
+    // two steps ahead into two register sets.  The loads are unconditional,
+    // from addresses clamped into the image (row p - 1, the last 8 bytes of
+    // the pitch): a staged byte that is not a pixel only meets locations past
+    // the last one, or zero template columns, so its value does not matter;
+    // and with no branch around them the compiler can wait for one register
+    // set while the other is still in flight.
     uint32_t rA[2][2], rB[2][2];
     auto gload = [&](int s, uint32_t (&ri)[2][2]) {
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-            int idx = t + 256 * k;
-            ri[k][0] = ri[k][1] = 0x80808080u;
-            if (idx < 4 * WW) {
-                int g = idx / WW, w = idx - g * WW;
-                int gy = y0 + 4 * s + g;
-                int64_t gx = (int64_t)x0 + 4 * w;
-                if (gy < a.p) {
-                    const uint8_t *rp = a.img + (int64_t)gy * a.pitch;
-                    if (gx + 4 <= a.pitch)
-                        ri[k][0] = *gptr((const uint32_t *)(rp + gx));
-                    if (gx + 8 <= a.pitch)
-                        ri[k][1] = *gptr((const uint32_t *)(rp + gx + 4));
-                }
-            }
+            const int idx = min(t + 256 * k, 4 * WW - 1);
+            const int g = idx / WW, w = idx - g * WW;
+            const int gy = min(y0 + 4 * s + g, a.p - 1);
+            const int64_t gx = min((int64_t)x0 + 4 * w, a.pitch - 8);
+            const uint8_t *rp = a.img + (int64_t)gy * a.pitch + gx;
+            ri[k][0] = *gptr((const uint32_t *)rp);
+            ri[k][1] = *gptr((const uint32_t *)(rp + 4));
         }
     };
     auto lstore = [&](int s, const uint32_t (&ri)[2][2]) {
@@ -2303,51 +2319,68 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     gload(0, rA);
     lstore(0, rA);
     __syncthreads();
-    if (1 < steps)
-        gload(1, rB);
+    gload(1, rB);
     const int g = lane >> 4, jr = lane & 15;
+    // A lane (jr, g) reads location column c = 64 wv + 16 mt + jr + 16 cb of
+    // image row g: the copy shifted by c & 3 = jr & 3 bytes, word c >> 2.  B
+    // lane (jr, g) of row group rg reads template row d + g - jr.
+    const uint32_t *tpl_b = tpl_l + (g - jr + kSinglePadLo) * tstr;
+    const int a_off = (g * 4 + (jr & 3)) * CS + 16 * wv + (jr >> 2);
     auto compute = [&](int s) {
-        const uint32_t *cur = smem + (s & 1) * IMGW;
-        for (int cb = 0; cb < nb16; cb++) {
-            v4i A[MT];
+        const uint32_t *pa = smem + (s & 1) * IMGW + a_off;
+        const uint32_t *pb[RG];
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++) {
-                int c = 64 * wv + 16 * mt + jr + 16 * cb;
-                __builtin_memcpy(&A[mt], cur + (g * 4 + (c & 3)) * CS + (c >> 2), 16);
-            }
-            // All B fragments first (rows outside the template read the zero
-            // row), so the reads overlap; then the MFMAs of the groups that
-            // meet template rows 4s - 16 rg - 15 .. 4s + 3 - 16 rg.
-            v4i B[RG];
+        for (int rg = 0; rg < RG; rg++) {
+            const int d = 4 * s - 16 * rg;
+            pb[rg] = tpl_b + (d < 0 ? -4 : d > m + 14 ? m + 16 : d) * tstr;
+        }
+        v4i A0[MT], A1[MT], B0[RG], B1[RG];
+        auto frag = [&](v4i (&A)[MT], v4i (&B)[RG], int cb) {
 #pragma unroll
-            for (int rg = 0; rg < RG; rg++) {
-                int tr = 4 * s + g - 16 * rg - jr;
-                int row = (unsigned)tr < (unsigned)m ? tr : m;
-                B[rg] = *(const v4i *)(tpl_l + row * tstr + 4 * cb);
-            }
+            for (int mt = 0; mt < MT; mt++)
+                __builtin_memcpy(&A[mt], pa + 4 * mt + 4 * cb, 16);
 #pragma unroll
-            for (int rg = 0; rg < RG; rg++) {
-                if (4 * s + 3 - 16 * rg < 0 || 4 * s - 16 * rg - 15 >= m)
-                    continue;
+            for (int rg = 0; rg < RG; rg++)
+                B[rg] = *(const v4i *)(pb[rg] + 4 * cb);
+        };
+        auto mma = [&](const v4i (&A)[MT], const v4i (&B)[RG]) {
+#pragma unroll
+            for (int rg = 0; rg < RG; rg++)
 #pragma unroll
                 for (int mt = 0; mt < MT; mt++)
                     acc[rg][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B[rg], acc[rg][mt], 0, 0, 0);
-            }
+        };
+        // two column blocks per iteration, the next one's reads issued before
+        // the current one's MFMAs
+        frag(A0, B0, 0);
+        int cb = 0;
+        for (; cb + 2 < nb16; cb += 2) {
+            frag(A1, B1, cb + 1);
+            mma(A0, B0);
+            frag(A0, B0, cb + 2);
+            mma(A1, B1);
+        }
+        if (cb + 1 < nb16) {
+            frag(A1, B1, cb + 1);
+            mma(A0, B0);
+            mma(A1, B1);
+        } else {
+            mma(A0, B0);
         }
     };
     // step s reads buffer s & 1; the data of step s + 1 is in rB (s even) or
-    // rA (s odd) and goes to the other buffer, free since the last barrier
+    // rA (s odd) and goes to the other buffer, free since the last barrier.
+    // Loads past the last step are issued too (clamped rows, never stored),
+    // so that every wait counts the same loads in flight.
     for (int s = 0; s < steps; s += 2) {
-        if (s + 2 < steps)
-            gload(s + 2, rA);
+        gload(s + 2, rA);
         compute(s);
         if (s + 1 < steps)
             lstore(s + 1, rB);
         __syncthreads();
         if (s + 1 >= steps)
             break;
-        if (s + 3 < steps)
-            gload(s + 3, rB);
+        gload(s + 3, rB);
         compute(s + 1);
         if (s + 2 < steps)
             lstore(s + 2, rA);
@@ -2356,17 +2389,15 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
 
     // Epilogue.  Lane holds rows y0 + 16 rg + (lane & 15), columns
     // x0 + 64 wv + 16 mt + 4 (lane >> 4) + v.  est = N / sqrt(D_t D_r) in
-    // binary32 from the exact N (as in k_batch); the block maximum over the
-    // one template; the lanes holding values within kEpsRho of it list them;
-    // the listed candidates' canonical binary64 rho gives the block's record.
+    // binary32 from the exact N (as in k_batch), kept in registers; the block
+    // maximum; the lanes holding values within kEpsRho of it list them; the
+    // listed candidates' canonical binary64 rho gives the block's record.
     const int64_t mn = (int64_t)m * a.n;
     const int64_t St = a.St, Dt = a.Dt;
-    int4 *clist = (int4 *)(smem + kSingleEpiList);           // (row in block, column, acc, 0)
-    RecPod *red = (RecPod *)smem;
+    int4 *clist = (int4 *)smem;  // (row in block, column, acc, 0)
     float *bmx = (float *)(smem + kSingleEpiMax);
     int *ccnt = (int *)(smem + kSingleEpiMax + 4);
-    int *slice = (int *)smem + wv * 16 * 64;
-    uint32_t *stb = smem + kSingleEpiStats + wv * 64 * kSingleLaneStride;
+    RecPod *red = (RecPod *)(smem + kSingleEpiRed);
     const double nst = -(double)St, mnd = (double)mn;
     const float irt = 1.0f / sqrtf((float)Dt);
     const float qnan = __int_as_float(0x7fc00000);
@@ -2381,63 +2412,28 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
         const double nd = fma(mnd, (double)accv, nst * S);
         return (y < a.Ly && x < a.Lx) ? (float)nd * ir * irt : qnan;
     };
-    // Statistics of this wave's 16 rows x 64 columns of a row group: lane c
-    // loads column c of every row (512 contiguous bytes per load), then they
-    // are regrouped in LDS so that lane (j, g) finds the 16 values of row j,
-    // columns 16 mt + 4 g + v, contiguous at stb[36 (4 j + g) ..].
-    const int cg = (lane >> 2) & 3, cq = 4 * (lane >> 4) + (lane & 3);
-    const uint32_t *src = stb + kSingleLaneStride * (4 * jr + g);
-    // block-uniform base and 32-bit offsets (rows and columns clamped into
-    // the map; the block's rows span at most 144 x 32767 entries)
-    const int2 *sbase = a.stat + ((int64_t)y0 * a.Lx + x0 + 64 * wv);
-    const int rmax = a.Ly - 1 - y0, lcol = min(lane, a.Lx - 1 - x0 - 64 * wv);
-#define ZTS_STAGE_STATS(rg)                                                                      \
-    {                                                                                            \
-        int2 sv[16];                                                                             \
-        _Pragma("unroll") for (int r = 0; r < 16; r++) sv[r] =                                   \
-            ld_int2(sbase + (min(16 * (rg) + r, rmax) * a.Lx + lcol));                           \
-        _Pragma("unroll") for (int r = 0; r < 16; r++)                                           \
-            *(int2 *)(stb + kSingleLaneStride * (4 * r + cg) + 2 * cq) = sv[r];                  \
-    }
-    // one row group's 16 accumulators into this wave's slice ([value][lane]);
-    // a switch of constant indices, so that acc stays in registers
-#define ZTS_SLICE_CASE(r)                                                                        \
-    case r:                                                                                      \
-        if constexpr ((r) < RG) {                                                                \
-            _Pragma("unroll") for (int q = 0; q < 16; q++) slice[q * 64 + lane] = acc[r][q >> 2][q & 3]; \
-        }                                                                                        \
-        break;
-    auto to_slice = [&](int rg) {
-        switch (rg) {
-            ZTS_SLICE_CASE(0)
-            ZTS_SLICE_CASE(1)
-            ZTS_SLICE_CASE(2)
-            ZTS_SLICE_CASE(3)
-            ZTS_SLICE_CASE(4)
-            ZTS_SLICE_CASE(5)
-            ZTS_SLICE_CASE(6)
-            ZTS_SLICE_CASE(7)
-        }
-    };
-#undef ZTS_SLICE_CASE
+    // statistics: lane (j, g) loads its 16 locations' int2 (rows and columns
+    // clamped into the map; the values at clamped positions are not used)
+    const int rmax = a.Ly - 1 - y0, cmax = a.Lx - 1 - x0;
+    const int2 *sbase = a.stat + ((int64_t)y0 * a.Lx + x0);
+    auto stat_of = [&](int r, int c) { return ld_int2(sbase + ((int64_t)min(r, rmax) * a.Lx + min(c, cmax))); };
     if (t == 0)
         *ccnt = 0;
-    // pass 1: block maximum (a rolled loop, so that loads of later row groups
-    // are not hoisted and register pressure stays that of one group)
-    float bm = -INFINITY;
-#pragma unroll 1
+    float est[RG][16];
+    float wm = -INFINITY;
+#pragma unroll
     for (int rg = 0; rg < RG; rg++) {
-        to_slice(rg);
-        ZTS_STAGE_STATS(rg)
-        const int y = y0 + 16 * rg + jr;
+        int2 sv[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++)
+            sv[q] = stat_of(16 * rg + jr, 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3));
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            int x = x0 + 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3);
-            int2 st = *(const int2 *)(src + 2 * q);
-            bm = fmaxf(bm, est_one(y, x, st, slice[q * 64 + lane]));
+            est[rg][q] = est_one(y0 + 16 * rg + jr, x0 + 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3), sv[q],
+                                 acc[rg][q >> 2][q & 3]);
+            wm = fmaxf(wm, est[rg][q]);
         }
     }
-    float wm = bm;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         wm = fmaxf(wm, __shfl_xor(wm, o));
@@ -2445,27 +2441,18 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
         bmx[wv] = wm;
     __syncthreads();
     const float thr = fmaxf(fmaxf(bmx[0], bmx[1]), fmaxf(bmx[2], bmx[3])) - kEpsRho;
-    // pass 2 in the waves holding a value near the maximum (normally one)
-    if (__any(bm >= thr)) {
-#pragma unroll 1
-        for (int rg = 0; rg < RG; rg++) {
-            to_slice(rg);
-            ZTS_STAGE_STATS(rg)
-            const int y = y0 + 16 * rg + jr;
+    if (wm >= thr) {
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                int xc = 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3);
-                int2 st = *(const int2 *)(src + 2 * q);
-                int accv = slice[q * 64 + lane];
-                if (est_one(y, x0 + xc, st, accv) >= thr) {
-                    int k = atomicAdd(ccnt, 1);
+        for (int rg = 0; rg < RG; rg++)
+#pragma unroll
+            for (int q = 0; q < 16; q++)
+                if (est[rg][q] >= thr) {
+                    const int k = atomicAdd(ccnt, 1);
                     if (k < kSingleCap)
-                        clist[k] = make_int4(16 * rg + jr, xc, accv, 0);
+                        clist[k] = make_int4(16 * rg + jr, 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3),
+                                             acc[rg][q >> 2][q & 3], 0);
                 }
-            }
-        }
     }
-#undef ZTS_STAGE_STATS
     __syncthreads();
     const int ncand = *ccnt;
     RecPod r = rec_empty();
@@ -2483,35 +2470,32 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
             r.valid = 1;
         }
     } else {
-        // overflow: streaming band selection over every value of the lane,
-        // one row group at a time through this wave's LDS slice
+        // overflow (more than kSingleCap near-equal values, e.g. a flat or
+        // periodic image): streaming band selection over every value
 #pragma unroll
-        for (int rg = 0; rg < RG; rg++) {
-#pragma unroll
-            for (int mt = 0; mt < MT; mt++)
-#pragma unroll
-                for (int v = 0; v < 4; v++)
-                    slice[(mt * 4 + v) * 64 + lane] = acc[rg][mt][v];
-            int y = y0 + 16 * rg + jr;
+        for (int rg = 0; rg < RG; rg++)
 #pragma unroll 1
-            for (int e = 0; e < 16; e++) {
-                int x = x0 + 64 * wv + 16 * (e >> 2) + 4 * g + (e & 3);
+            for (int q = 0; q < 16; q++) {
+                const int y = y0 + 16 * rg + jr, x = x0 + 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3);
                 if (y < a.Ly && x < a.Lx) {
                     int64_t l = (int64_t)y * a.Lx + x;
                     int2 st = ld_int2(a.stat + (l));
                     int64_t dr = var_num(mn, st);
-                    int64_t num = mn * (int64_t)slice[e * 64 + lane] - St * (int64_t)st.x;
+                    int accv = 0;
+#pragma unroll
+                    for (int e = 0; e < 16; e++)
+                        if (e == q)
+                            accv = acc[rg][e >> 2][e & 3];
+                    int64_t num = mn * (int64_t)accv - St * (int64_t)st.x;
                     rec_offer(r, rho32(num, Dt, dr), l, num, Dt, dr);
                 }
             }
-        }
     }
-    __syncthreads();  // the records below reuse the slices and buffers
-    return block_rec(r, red);
+    return block_rec4(r, red);
 }
 
 template <int RG>
-__global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ jobs, int njobs)
+__global__ __launch_bounds__(256, 3) void k_single(const BatchJob *__restrict__ jobs, int njobs)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     const BatchJob a = jobs[batch_job_of<0>(jobs, njobs, blockIdx.x)];
@@ -2529,10 +2513,9 @@ __global__ __launch_bounds__(256, 2) void k_single(const BatchJob *__restrict__ 
     }
     for (int idx = t; idx < m * nw16; idx += 256) {
         int r = idx / nw16, c = idx - r * nw16;
-        tpl_l[r * tstr + c] = flip4(gptr(tplg)[idx]);
+        tpl_l[(r + kSinglePadLo) * tstr + c] = flip4(gptr(tplg)[idx]);
     }
-    for (int idx = t; idx < nw16; idx += 256)
-        tpl_l[m * tstr + idx] = 0;
+    single_tpl_pads(tpl_l, m, nw16, tstr);
     const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, m, a.n, a.n16, St, Dt};
     const RecPod best = single_tile_body<RG>(st, bx * 256, by * 16 * RG, smem);
     if (t < 16)
@@ -2597,19 +2580,21 @@ __device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
     return sum >= 4 * a.dense_min || most >= a.dense_min;
 }
 
-// Dense super-tiles: one block per super-tile of 128 x 256 locations; a
-// dense one (super_dense) is matched whole on int8 MFMA with eight row groups
-// per block (the k_single body, whose image staging is then shared by 128
-// output rows): the locations scan 2 eliminated lie below the threshold, so
-// they cannot be the answer, and the counts stay those of the decisions.
-// Others write an empty record and are left to k_surv_tiles.
-__global__ __launch_bounds__(256, 2) void k_dense_tiles(TileArgs a)
+// Dense tiles: one block per survivor tile (32 x 256 locations); a tile of a
+// dense super-tile (super_dense: the decision is taken per 128 x 256
+// super-tile, so that scattered survivors do not split it) is matched whole
+// on int8 MFMA with the k_single body: the locations scan 2 eliminated lie
+// below the threshold, so they cannot be the answer, and the counts stay
+// those of the decisions.  Others write an empty record and are left to
+// k_surv_tiles.
+__global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
 {
+    static_assert(kTileRows == 32, "a dense tile is one block of two row groups");
     extern __shared__ __align__(16) uint32_t smem[];
     const int b = blockIdx.x, t = threadIdx.x;
-    const int sy = b / a.tiles_x, tx = b - (b / a.tiles_x) * a.tiles_x;
+    const int ty = b / a.tiles_x, tx = b - (b / a.tiles_x) * a.tiles_x;
     RecPod *out = a.recs + a.rec_off + (int64_t)a.tiles_x * a.tiles_y + b;
-    if (a.qs->degenerate || !super_dense(a, sy, tx)) {
+    if (a.qs->degenerate || !super_dense(a, ty >> 2, tx)) {
         if (t == 0)
             *out = rec_empty();
         return;
@@ -2619,16 +2604,15 @@ __global__ __launch_bounds__(256, 2) void k_dense_tiles(TileArgs a)
     const bool words = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
     for (int idx = t; idx < a.m * nw16; idx += 256) {
         const int r = idx / nw16, c = idx - r * nw16;
-        tpl_l[r * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
+        tpl_l[(r + kSinglePadLo) * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
     }
-    for (int idx = t; idx < nw16; idx += 256)
-        tpl_l[a.m * tstr + idx] = 0;
+    single_tpl_pads(tpl_l, a.m, nw16, tstr);
     const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
-    const int x0 = tx * kTileCols, y0 = sy * 4 * kTileRows;
-    const RecPod best = single_tile_body<8>(st, x0, y0, smem);
+    const int x0 = tx * kTileCols, y0 = ty * kTileRows;
+    const RecPod best = single_tile_body<2>(st, x0, y0, smem);
     if (t == 0) {
         *out = best;
-        atomicAdd(&a.qs->n_dense, (unsigned long long)min(4 * kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
+        atomicAdd(&a.qs->n_dense, (unsigned long long)min(kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
     }
 }
 
@@ -3247,7 +3231,7 @@ void tile_plan(TileArgs &a, int dense_min)
 
 static size_t tiles_lds_bytes(const TileArgs &a) { return tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words); }
 
-int super_tiles_of(const TileArgs &a) { return a.dense_min > 0 ? a.tiles_x * (int)blocks_for(a.tiles_y, 4) : 0; }
+int dense_blocks_of(const TileArgs &a) { return a.dense_min > 0 ? a.tiles_x * a.tiles_y : 0; }
 
 hipError_t launch_dense_tiles(TileArgs a, hipStream_t s)
 {
@@ -3257,7 +3241,7 @@ hipError_t launch_dense_tiles(TileArgs a, hipStream_t s)
     hipError_t e = allow_lds((const void *)k_dense_tiles, dl);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)super_tiles_of(a)), dim3(256), dl, s, a);
+    hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)dense_blocks_of(a)), dim3(256), dl, s, a);
     return hipGetLastError();
 }
 
@@ -3415,7 +3399,7 @@ bool batch_job_geometry(BatchJob &j)
     if (j.kind == BATCH_SINGLE) {
         if (j.T != 1 || !batch_single_fits(j.m, j.n))
             return false;
-        if (j.rg != 2 && j.rg != 4 && j.rg != 8)
+        if (j.rg != 2)
             return false;
         j.gy = (int)blocks_for(j.Ly, 16 * j.rg);
         j.gz = 1;
@@ -3476,8 +3460,9 @@ hipError_t launch_batch_jobs(const BatchJob *d_jobs, const BatchJob *h_jobs, int
     if (nm > 0)
         hipLaunchKernelGGL(k_batch<kBatchR>, dim3((unsigned)blocks_m), dim3(256), lds_m, s, d_jobs, nm);
     if (nm < njobs) {
-        auto ks = rg == 8 ? k_single<8> : rg == 4 ? k_single<4> : k_single<2>;
-        hipLaunchKernelGGL(ks, dim3((unsigned)blocks_s), dim3(256), lds_s, s, d_jobs + nm, njobs - nm);
+        if (rg != 2)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_single<2>, dim3((unsigned)blocks_s), dim3(256), lds_s, s, d_jobs + nm, njobs - nm);
     }
     hipLaunchKernelGGL(k_fold_batch, dim3((unsigned)nfold), dim3(256), 0, s, d_jobs, njobs);
     hipLaunchKernelGGL(k_reduce_batch, dim3(ntpl), dim3(256), 0, s, d_jobs, njobs);
