@@ -2179,13 +2179,13 @@ void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, 
         for (auto &gr : groups) {
             const std::vector<int> &ks = gr.second;
             const Prepared *P = plans[ks[0]].P;
-            const bool shared = ks.size() > 1 && centres_mfma_batchable(gr.first.first, gr.first.second, P->w, 2);
+            const bool shared = ks.size() > 1 && centres_mfma_batchable(P->Gy, P->Gx, gr.first.first, gr.first.second, P->w, 2);
             size_t i = 0;
             while (i < ks.size()) {
                 int T = 1;
                 if (shared)
                     while (T < kScanMaxT && i + T < ks.size() &&
-                           centres_mfma_batchable(gr.first.first, gr.first.second, P->w, T + 1))
+                           centres_mfma_batchable(P->Gy, P->Gx, gr.first.first, gr.first.second, P->w, T + 1))
                         T++;
                 ScanArgs sa = Q[ks[i]].sa;
                 sa.ntpl = T;

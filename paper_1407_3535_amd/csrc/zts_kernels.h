@@ -56,9 +56,9 @@ struct ScanArgs {
     double delta;
     uint32_t *tile_cnt;  // survivor counts of scan 2's tiles, zeroed here (n_tiles entries)
     int n_tiles;
-    int cwd;      // MFMA form: dword stride of the staged image rows of a block's region
+    int cwd;      // MFMA form: dword stride of the byte-shifted copies of a staged image row
     int cwn;      // MFMA form: dwords of each staged row that are read
-    int crows_log2;  // MFMA form: log2 of the rows of a staged chunk
+    int crows_log2;  // unused (the MFMA form stages 4-row steps)
     // MFMA form, batched: ntpl templates of the same size matched in one launch
     // (each staged image fragment feeds all of them); 1 for a single query
     int ntpl;
@@ -266,9 +266,10 @@ hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QStat
 // Zeroes *qs (every word, the sequence number included) with a fill kernel.
 hipError_t launch_qs_clear(QState *qs, hipStream_t s);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);
-// Whether scan 1 of an m x n template with group width w runs on int8 MFMA
-// (then a.ntpl templates can share one launch of launch_centres).
-bool centres_mfma_batchable(int m, int n, int w, int ntpl);
+// Whether scan 1 of an m x n template with group width w over a Gy x Gx
+// centre grid runs on int8 MFMA (then a.ntpl templates can share one launch
+// of launch_centres).
+bool centres_mfma_batchable(int Gy, int Gx, int m, int n, int w, int ntpl);
 int window_record_count(int radius);
 hipError_t launch_window(WinArgs a, hipStream_t s);
 int members_record_count(int Gy, int Gx);

@@ -768,17 +768,19 @@ __global__ __launch_bounds__(256) void k_centres(ScanArgs a)
 
 // Scan 1 on int8 MFMA: M = 16 centre columns (stride w), N = 16 centre rows
 // (stride h), K = 4 image rows x 16 columns.  A block holds 16 centre rows x
-// 64 centre columns: one M-tile per wave, and two waves per M-tile that take
-// alternate groups of 4 image rows (their sums are added at the end).  The
-// image region its windows cover streams through LDS in chunks of 64, 32 or 16
-// rows (one copy, A fragments are realigned with v_alignbyte),
-// double-buffered so that a chunk's loads are in flight while the previous
-// chunk is multiplied.  Each wave of an M-tile finishes two of its four
-// accumulator columns.  For image row y, lane (j, g) of the B
-// fragment carries template row y - cy_j (the zero row outside the
-// template).  Outputs equal k_centres'.
-constexpr int kCmThreads = 512;
-constexpr int kCmLd = 12;   // staged words per thread and chunk, at most
+// 64 MTW centre columns: each of its four waves MTW M-tiles for every
+// template of the launch (up to TM), all with their own accumulators.  The
+// image region the block's windows cover streams through LDS in 4-row steps,
+// each row staged as four byte-shifted copies so that every A lane reads
+// whole words (lane j of an M-tile reads the copy shifted by its centre's
+// byte offset mod 4); the fragments of the next column block are read before
+// the current one's MFMAs, and the sequence of reads and MFMAs is the same in
+// every step.  For image row y, lane (j, g) of the B fragment carries
+// template row y - cy_j (the zero row outside the template, and for centre
+// rows past the last).  Outputs equal k_centres'.
+constexpr int kCmThreads = 256;
+// staged words per thread and step, at most, for MTW M-tiles per wave
+__host__ __device__ constexpr int cm_words_per_thread(int mtw) { return mtw == 1 ? 2 : mtw == 2 ? 3 : 4; }
 
 // Template rows flipped to int8 at row stride tstr, then one zero row, and
 // this thread's partial sums of t' and t'^2 (no barrier: the caller's next
@@ -814,10 +816,11 @@ __device__ __forceinline__ ScanTpl scan_tpl(const ScanArgs &a, int i)
 }
 
 // TM: most templates per launch (a.ntpl of them run); NB: 16-byte column
-// blocks of the template row (n16 = 16 NB).
-template <int NB, int TM>
+// blocks of the template row (n16 = 16 NB); MTW: M-tiles per wave.
+template <int NB, int TM, int MTW>
 __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
 {
+    constexpr int KL = cm_words_per_thread(MTW);
     const int T = TM == 1 ? 1 : a.ntpl;
 #pragma unroll
     for (int ti = 0; ti < TM; ti++) {
@@ -836,16 +839,16 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         }
     }
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[2 * TM * (kCmThreads / 64)];
-    __shared__ RecPod rred[kCmThreads / 64];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, mt = wv & 3, kh = wv >> 2;
+    __shared__ int red[2 * TM * 4];
+    __shared__ RecPod rred[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int m = a.m, n = a.n;
     constexpr int nw16 = 4 * NB;
-    const int tstr = batch_tstride(nw16), CWd = a.cwd, CWn = a.cwn;
-    const int twords = (m + 1) * tstr;              // one template's rows in LDS
-    const int crl = a.crows_log2, crows = 1 << crl, CW = crows * CWd;
-    uint32_t *tpl_l = smem;                         // per template: m rows and the zero row m, stride tstr
-    uint32_t *buf0 = smem + T * twords;             // two chunk buffers of CW dwords
+    const int tstr = batch_tstride(nw16), CS = a.cwd, CWn = a.cwn;
+    const int twords = (m + 1) * tstr;       // one template's rows in LDS
+    const int IMGW = 16 * CS;                // one step: 4 rows x 4 byte-shifted copies
+    uint32_t *tpl_l = smem;                  // per template: m rows and the zero row m, stride tstr
+    uint32_t *buf0 = smem + T * twords;      // two step buffers
     auto ccol = [&](int gx) { int ox = gx * a.w; return ox + (min(a.w, a.Lx - ox) - 1) / 2; };
     auto crow = [&](int gy) { int oy = gy * a.h; return oy + (min(a.h, a.Ly - oy) - 1) / 2; };
     // XCD-aware placement: the hardware deals workgroup ids round-robin over
@@ -860,61 +863,49 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         bxl = j / gridDim.y;
         byl = j - bxl * gridDim.y;
     }
-    const int gx0 = bxl * 64, gy0 = byl * 16;
+    const int gx0 = bxl * 64 * MTW, gy0 = byl * 16;
     const int ny = min(16, a.Gy - gy0);
     const int xw0 = ccol(gx0) >> 2;                 // first staged word of the region's rows
     const int ylo = crow(gy0), yhi = crow(gy0 + ny - 1) + m;
-    const int nchunk = (yhi - ylo + crows - 1) >> crl;
-    const uint32_t *img32 = (const uint32_t *)a.img;
-    const int64_t pw = a.pitch >> 2;
-    // staging: 512 / crows threads per chunk row; thread (r, q) copies words
-    // q, q + 512 / crows, ... of the CWn that the A reads can reach (the rest
-    // of the CWd stride is bank padding, never read).  Loads come from
-    // clamped, in-image addresses: a staged byte that is not a pixel of a
-    // centre's window (past the image row, or a row past the region) only
-    // ever meets a zero template byte (a column past n, or the zero row), so
-    // its value does not matter.
-    const int tpl2 = 9 - crl, tpr = 1 << tpl2;  // threads per row
-    const int sr = t >> tpl2, sq = t & (tpr - 1);
-    const int wlim = (int)min((int64_t)CWn, pw - xw0);  // >= 1: the first centre lies in the row
-    uint32_t rv[kCmLd];
-    auto cload = [&](int c) {
-        const int y = min(ylo + (c << crl) + sr, yhi - 1);
-        const uint32_t *row = img32 + (int64_t)y * pw + xw0;
+    const int steps = (yhi - ylo + 3) >> 2;
+    const uint8_t *img = a.img;
+    // Staging: thread t takes words t, t + 256, ... of the step's 4 x CWn
+    // words (row idx / CWn), each with the word after it, from clamped
+    // in-image addresses without branches (a staged byte that is not a pixel
+    // of a centre's window only ever meets a zero template byte: a column
+    // past n, or the zero row), and writes the word's four byte-shifted
+    // copies.  The host keeps 4 CWn <= 256 KL.
+    uint32_t rA[KL][2], rB[KL][2];
+    auto gload = [&](int s, uint32_t (&ri)[KL][2]) {
 #pragma unroll
-        for (int k = 0; k < kCmLd; k++)
-            if (k * tpr < CWn)
-                rv[k] = *gptr(row + min(sq + k * tpr, wlim - 1));
-    };
-    auto cstore = [&](int c) {
-        uint32_t *b = buf0 + (c & 1) * CW + sr * CWd;
-#pragma unroll
-        for (int k = 0; k < kCmLd; k++) {
-            int wd = sq + k * tpr;
-            if (wd < CWn)
-                b[wd] = flip4(rv[k]);
+        for (int k = 0; k < KL; k++) {
+            const int idx = min(t + 256 * k, 4 * CWn - 1);
+            const int r = idx / CWn, wd = idx - r * CWn;
+            const int y = min(ylo + 4 * s + r, yhi - 1);
+            const int64_t x = min((int64_t)4 * (xw0 + wd), a.pitch - 8);
+            const uint8_t *rp = img + (int64_t)y * a.pitch + x;
+            ri[k][0] = *gptr((const uint32_t *)rp);
+            ri[k][1] = *gptr((const uint32_t *)(rp + 4));
         }
     };
-    const int g = lane >> 4, jr = lane & 15;
-    const int cxa = ccol(min(gx0 + 16 * mt + jr, a.Gx - 1)) - 4 * xw0;  // A lane: its centre column in the region
-    const int cyb = crow(min(gy0 + jr, a.Gy - 1));                        // B lane: its centre row
-    const bool jok = jr < ny;
-    // The first chunk and the epilogue's centre statistics are in flight
-    // while the templates load.
-    cload(0);
-    // accumulator lane: centre row gy0 + (lane & 15), centre columns
-    // gx0 + 16 mt + 4 (lane >> 4) + v; this wave finishes v = 2 kh, 2 kh + 1
-    const int gyy = gy0 + jr;
-    int2 sc[2];
+    auto lstore = [&](int s, const uint32_t (&ri)[KL][2]) {
+        uint32_t *b = buf0 + (s & 1) * IMGW;
 #pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
-        sc[e] = make_int2(0, 0);
-        if (gyy < a.Gy && gxx < a.Gx)
-            sc[e] = ld_int2(a.cstat + (int64_t)gyy * a.Gx + gxx);
-    }
+        for (int k = 0; k < KL; k++) {
+            const int idx = t + 256 * k;
+            if (idx < 4 * CWn) {
+                const int r = idx / CWn, wd = idx - r * CWn;
+                const uint32_t lo = flip4(ri[k][0]), hi = flip4(ri[k][1]);
+                b[(r * 4 + 0) * CS + wd] = lo;
+                b[(r * 4 + 1) * CS + wd] = bytes_at(hi, lo, 1);
+                b[(r * 4 + 2) * CS + wd] = bytes_at(hi, lo, 2);
+                b[(r * 4 + 3) * CS + wd] = bytes_at(hi, lo, 3);
+            }
+        }
+    };
+    gload(0, rA);
     // the template statistics are reduced after the main loop, which needs
-    // only the rows (published by the barrier below)
+    // only the rows (published by the first barrier)
     int ps[TM], ps2[TM];
 #pragma unroll
     for (int ti = 0; ti < TM; ti++) {
@@ -924,54 +915,80 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
             load_template_rows(sp.tpl, sp.ts, m, n, nw16, tstr, tpl_l + ti * twords, &ps[ti], &ps2[ti]);
         }
     }
-    cstore(0);
+    lstore(0, rA);
     __syncthreads();
-    v4i acc[TM];
+    gload(1, rB);
+    const int g = lane >> 4, jr = lane & 15;
+    // A lane (jr, g) of M-tile mt: centre column gx0 + 16 (MTW wv + mt) + jr
+    // (the last one for columns past Gx), byte offset o from the region's
+    // first staged word: copy o & 3 of row g, word o >> 2
+    int a_off[MTW];
+#pragma unroll
+    for (int mt = 0; mt < MTW; mt++) {
+        const int o = ccol(min(gx0 + 16 * (MTW * wv + mt) + jr, a.Gx - 1)) - 4 * xw0;
+        a_off[mt] = (g * 4 + (o & 3)) * CS + (o >> 2);
+    }
+    // B lane (jr, g): template row 4s + g - cy_jr of the step's image rows
+    const bool jok = jr < ny;
+    const int bsh = g - (crow(min(gy0 + jr, a.Gy - 1)) - ylo);
+    v4i acc[TM][MTW];
 #pragma unroll
     for (int ti = 0; ti < TM; ti++)
-        acc[ti] = v4i{0, 0, 0, 0};
-    const int aw = cxa >> 2;
-    const uint32_t ash = (uint32_t)(cxa & 3);
-    for (int c = 0; c < nchunk; c++) {
-        if (c + 1 < nchunk)
-            cload(c + 1);
-        const uint32_t *b = buf0 + (c & 1) * CW;
-        const int rows = min(crows, yhi - ylo - (c << crl));
-        for (int k = kh; 4 * k < rows; k += 2) {
-            const int yr = 4 * k + g;                      // row of the chunk for this lane group
-            const int tr = ylo + (c << crl) + yr - cyb;    // template row for B lane (jr, g)
-            const int brow = jok && (unsigned)tr < (unsigned)m ? tr : m;
-            const uint32_t *pa = b + yr * CWd + aw;
-            // bytes cxa + 16 cb .. + 15 of the row are words 4 cb .. 4 cb + 4;
-            // the realigned A fragments feed every template's MFMAs
-            uint32_t wd[4 * NB + 1];
 #pragma unroll
-            for (int i = 0; i <= 4 * NB; i++)
-                wd[i] = pa[i];
-            v4i A[NB];
+        for (int mt = 0; mt < MTW; mt++)
+            acc[ti][mt] = v4i{0, 0, 0, 0};
+    auto compute = [&](int s) {
+        const uint32_t *pa = buf0 + (s & 1) * IMGW;
+        const int tr = 4 * s + bsh;
+        const uint32_t *pb = tpl_l + (jok && (unsigned)tr < (unsigned)m ? tr : m) * tstr;
+        v4i A0[MTW], A1[MTW], B0[TM], B1[TM];
+        auto frag = [&](v4i (&A)[MTW], v4i (&B)[TM], int cb) {
 #pragma unroll
-            for (int cb = 0; cb < NB; cb++) {
-                A[cb][0] = (int)bytes_at(wd[4 * cb + 1], wd[4 * cb], ash);
-                A[cb][1] = (int)bytes_at(wd[4 * cb + 2], wd[4 * cb + 1], ash);
-                A[cb][2] = (int)bytes_at(wd[4 * cb + 3], wd[4 * cb + 2], ash);
-                A[cb][3] = (int)bytes_at(wd[4 * cb + 4], wd[4 * cb + 3], ash);
-            }
+            for (int mt = 0; mt < MTW; mt++)
+                __builtin_memcpy(&A[mt], pa + a_off[mt] + 4 * cb, 16);
 #pragma unroll
-            for (int ti = 0; ti < TM; ti++) {
-                if (ti >= T)
-                    break;
-                const uint32_t *pb = tpl_l + ti * twords + brow * tstr;
-                v4i B[NB];
+            for (int ti = 0; ti < TM; ti++)
+                if (ti < T)
+                    B[ti] = *(const v4i *)(pb + ti * twords + 4 * cb);
+        };
+        auto mma = [&](const v4i (&A)[MTW], const v4i (&B)[TM]) {
 #pragma unroll
-                for (int cb = 0; cb < NB; cb++)
-                    B[cb] = *(const v4i *)(pb + 4 * cb);
+            for (int ti = 0; ti < TM; ti++)
+                if (ti < T)
 #pragma unroll
-                for (int cb = 0; cb < NB; cb++)
-                    acc[ti] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[cb], B[cb], acc[ti], 0, 0, 0);
+                    for (int mt = 0; mt < MTW; mt++)
+                        acc[ti][mt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B[ti], acc[ti][mt], 0, 0, 0);
+        };
+        frag(A0, B0, 0);
+#pragma unroll
+        for (int cb = 0; cb < NB; cb += 2) {
+            if (cb + 1 < NB) {
+                frag(A1, B1, cb + 1);
+                mma(A0, B0);
+                if (cb + 2 < NB)
+                    frag(A0, B0, cb + 2);
+                mma(A1, B1);
+            } else {
+                mma(A0, B0);
             }
         }
-        if (c + 1 < nchunk)
-            cstore(c + 1);
+    };
+    // step s reads buffer s & 1; the data of step s + 1 is in rB (s even) or
+    // rA (s odd) and goes to the other buffer, free since the last barrier.
+    // Loads past the last step are issued too (clamped rows, never stored),
+    // so that every wait counts the same loads in flight.
+    for (int s = 0; s < steps; s += 2) {
+        gload(s + 2, rA);
+        compute(s);
+        if (s + 1 < steps)
+            lstore(s + 1, rB);
+        __syncthreads();
+        if (s + 1 >= steps)
+            break;
+        gload(s + 3, rB);
+        compute(s + 1);
+        if (s + 2 < steps)
+            lstore(s + 2, rA);
         __syncthreads();
     }
     // template statistics of every template at once
@@ -979,82 +996,101 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     for (int ti = 0; ti < TM; ti++) {
         const int s1 = wave_sum(ps[ti]), s2 = wave_sum(ps2[ti]);
         if (lane == 0 && ti < T) {
-            red[(2 * ti) * (kCmThreads / 64) + wv] = s1;
-            red[(2 * ti + 1) * (kCmThreads / 64) + wv] = s2;
+            red[(2 * ti) * 4 + wv] = s1;
+            red[(2 * ti + 1) * 4 + wv] = s2;
         }
     }
+    // accumulator lane: centre row gy0 + jr, centre columns
+    // gx0 + 16 (MTW wv + mt) + 4 g + v; their statistics in one round trip
+    const int gyy = gy0 + jr;
+    int2 sc[MTW][4];
+#pragma unroll
+    for (int mt = 0; mt < MTW; mt++)
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+            sc[mt][v] = ld_int2(a.cstat + ((int64_t)min(gyy, a.Gy - 1) * a.Gx +
+                                           min(gx0 + 16 * (MTW * wv + mt) + 4 * g + v, a.Gx - 1)));
+    __syncthreads();
     const int64_t mn = (int64_t)m * n;
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    int2 *xch = (int2 *)buf0;  // the chunk buffers are free: the loop ended with a barrier
 #pragma unroll
     for (int ti = 0; ti < TM; ti++) {
         if (ti >= T)
             break;
         const ScanTpl sp = scan_tpl(a, ti);
-        // the two waves of an M-tile swap the partial sums of the columns the
-        // other one finishes
-        xch[(kh * 4 + mt) * 64 + lane] = kh ? make_int2(acc[ti][0], acc[ti][1]) : make_int2(acc[ti][2], acc[ti][3]);
-        __syncthreads();
-        const int2 o = xch[((1 - kh) * 4 + mt) * 64 + lane];
-        int64_t st = 0, sq2 = 0;
-#pragma unroll
-        for (int k = 0; k < kCmThreads / 64; k++) {
-            st += red[(2 * ti) * (kCmThreads / 64) + k];
-            sq2 += red[(2 * ti + 1) * (kCmThreads / 64) + k];
-        }
+        const int64_t st = (int64_t)red[(2 * ti) * 4] + red[(2 * ti) * 4 + 1] + red[(2 * ti) * 4 + 2] +
+                           red[(2 * ti) * 4 + 3];
+        const int64_t sq2 = (int64_t)red[(2 * ti + 1) * 4] + red[(2 * ti + 1) * 4 + 1] +
+                            red[(2 * ti + 1) * 4 + 2] + red[(2 * ti + 1) * 4 + 3];
         const int64_t dt = mn * sq2 - st * st;
         if (dt == 0) {  // uniform over the block
             if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0)
                 sp.qs->degenerate = 1;
-            __syncthreads();  // xch is rewritten by the next template
             continue;
         }
-        int64_t num[2], dc[2];
-        float r32[2];
-        bool ok[2];
+        // Only centres within kEpsRho of the wave's largest binary32 rho can be
+        // the block's best: they alone are evaluated in binary64 (one at a
+        // time per lane, usually one in the whole wave), and the wave's
+        // record is picked among those lanes in lane order.
+        float r32[MTW][4];
         float lmax = -2.0f;
 #pragma unroll
-        for (int e = 0; e < 2; e++) {
-            const int v = 2 * kh + e;
-            const int gxx = gx0 + 16 * mt + 4 * g + v;
-            ok[e] = gyy < a.Gy && gxx < a.Gx;
-            const int x = (kh ? acc[ti][2 + e] : acc[ti][e]) + (e ? o.y : o.x);
-            dc[e] = var_num(mn, sc[e]);
-            num[e] = mn * (int64_t)x - st * (int64_t)sc[e].x;
-            r32[e] = rho32(num[e], dt, dc[e]);
-            if (ok[e]) {
-                const int gi = gyy * a.Gx + gxx;
-                sp.g_x[gi] = x;
-                sp.g_theta[gi] = theta32(num[e], dt, dc[e]);
-                lmax = fmaxf(lmax, r32[e]);
-                if (ti == 0 && a.dec)
-                    a.dec[(int64_t)crow(gyy) * a.Lx + ccol(gxx)] = 1;
+        for (int mt = 0; mt < MTW; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int gxx = gx0 + 16 * (MTW * wv + mt) + 4 * g + v;
+                const bool ok = gyy < a.Gy && gxx < a.Gx;
+                const int x = acc[ti][mt][v];
+                const int64_t dc = var_num(mn, sc[mt][v]);
+                const int64_t num = mn * (int64_t)x - st * (int64_t)sc[mt][v].x;
+                r32[mt][v] = ok ? rho32(num, dt, dc) : -2.0f;
+                if (ok) {
+                    const int gi = gyy * a.Gx + gxx;
+                    sp.g_x[gi] = x;
+                    sp.g_theta[gi] = theta32(num, dt, dc);
+                    lmax = fmaxf(lmax, r32[mt][v]);
+                    if (ti == 0 && a.dec)
+                        a.dec[(int64_t)crow(gyy) * a.Lx + ccol(gxx)] = 1;
+                }
             }
-        }
-        // Only centres within kEpsRho of the wave's largest binary32 rho can be
-        // the block's best: they alone are evaluated in binary64, and the wave's
-        // record is picked among those lanes (usually one) in lane order.
         float wmax = lmax;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
             wmax = fmaxf(wmax, __shfl_xor(wmax, off));
+        uint32_t cmask = 0;
+#pragma unroll
+        for (int mt = 0; mt < MTW; mt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                if (r32[mt][v] > -2.0f && r32[mt][v] >= wmax - kEpsRho)
+                    cmask |= 1u << (4 * mt + v);
         double brho = -2.0;
         int64_t bl = INT64_MAX, bnum = 0, bdr = 0;
         bool bv = false;
+        while (cmask) {
+            const int e = __ffs(cmask) - 1;
+            cmask &= cmask - 1;
+            int x = 0;
+            int2 scv = make_int2(0, 0);
 #pragma unroll
-        for (int e = 0; e < 2; e++)
-            if (ok[e] && r32[e] >= wmax - kEpsRho) {
-                const int gxx = gx0 + 16 * mt + 4 * g + 2 * kh + e;
-                const int64_t l = (int64_t)crow(gyy) * a.Lx + ccol(gxx);
-                const double r = rho64(num[e], dt, dc[e]);
-                if (!bv || rec_better(r, l, brho, bl)) {
-                    brho = r;
-                    bl = l;
-                    bnum = num[e];
-                    bdr = dc[e];
-                    bv = true;
+            for (int q = 0; q < 4 * MTW; q++)
+                if (q == e) {
+                    x = acc[ti][q >> 2][q & 3];
+                    scv = sc[q >> 2][q & 3];
                 }
+            const int gxx = gx0 + 16 * (MTW * wv + (e >> 2)) + 4 * g + (e & 3);
+            const int64_t l = (int64_t)crow(gyy) * a.Lx + ccol(gxx);
+            const int64_t dc = var_num(mn, scv);
+            const int64_t num = mn * (int64_t)x - st * (int64_t)scv.x;
+            const double r = rho64(num, dt, dc);
+            if (!bv || rec_better(r, l, brho, bl)) {
+                brho = r;
+                bl = l;
+                bnum = num;
+                bdr = dc;
+                bv = true;
             }
+        }
         RecPod rec = rec_empty();
         rec.r32max = wmax;
         for (uint64_t msk = __ballot(bv); msk; msk &= msk - 1) {
@@ -1072,8 +1108,8 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         if (lane == 0)
             rred[wv] = rec;
         __syncthreads();
-        if (wv == 0) {  // the eight wave records merged by shuffles in lanes 0..7
-            RecPod bb = wave_rec<kCmThreads / 64>(lane < kCmThreads / 64 ? rred[lane] : rec_empty());
+        if (wv == 0) {  // the four wave records merged by shuffles in lanes 0..3
+            RecPod bb = wave_rec<4>(lane < 4 ? rred[lane] : rec_empty());
             if (lane == 0) {
                 sp.recs[bid] = bb;
                 if (bid == 0) {  // the query state needs no fill before the scans
@@ -1083,7 +1119,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
                 }
             }
         }
-        __syncthreads();  // rred and xch are rewritten by the next template
+        __syncthreads();  // rred is rewritten by the next template
     }
 }
 
@@ -2259,7 +2295,7 @@ struct SingleTile {
 };
 
 // Returns the block's best location (valid in thread 0; the block's LDS is
-// reused).
+// reused; some threads may return before others).
 template <int RG>
 __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t *smem)
 {
@@ -2394,7 +2430,7 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     // listed candidates' canonical binary64 rho gives the block's record.
     const int64_t mn = (int64_t)m * a.n;
     const int64_t St = a.St, Dt = a.Dt;
-    int4 *clist = (int4 *)smem;  // (row in block, column, acc, 0)
+    int4 *clist = (int4 *)smem;  // (row in block << 16 | column, acc, S, Q)
     float *bmx = (float *)(smem + kSingleEpiMax);
     int *ccnt = (int *)(smem + kSingleEpiMax + 4);
     RecPod *red = (RecPod *)(smem + kSingleEpiRed);
@@ -2419,21 +2455,23 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     auto stat_of = [&](int r, int c) { return ld_int2(sbase + ((int64_t)min(r, rmax) * a.Lx + min(c, cmax))); };
     if (t == 0)
         *ccnt = 0;
+    // (all of the lane's loads are issued at once: one round trip)
     float est[RG][16];
-    float wm = -INFINITY;
+    int2 sv[RG][16];
 #pragma unroll
-    for (int rg = 0; rg < RG; rg++) {
-        int2 sv[16];
+    for (int rg = 0; rg < RG; rg++)
 #pragma unroll
         for (int q = 0; q < 16; q++)
-            sv[q] = stat_of(16 * rg + jr, 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3));
+            sv[rg][q] = stat_of(16 * rg + jr, 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3));
+    float wm = -INFINITY;
+#pragma unroll
+    for (int rg = 0; rg < RG; rg++)
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            est[rg][q] = est_one(y0 + 16 * rg + jr, x0 + 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3), sv[q],
+            est[rg][q] = est_one(y0 + 16 * rg + jr, x0 + 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3), sv[rg][q],
                                  acc[rg][q >> 2][q & 3]);
             wm = fmaxf(wm, est[rg][q]);
         }
-    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         wm = fmaxf(wm, __shfl_xor(wm, o));
@@ -2449,8 +2487,8 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
                 if (est[rg][q] >= thr) {
                     const int k = atomicAdd(ccnt, 1);
                     if (k < kSingleCap)
-                        clist[k] = make_int4(16 * rg + jr, 64 * wv + 16 * (q >> 2) + 4 * g + (q & 3),
-                                             acc[rg][q >> 2][q & 3], 0);
+                        clist[k] = make_int4(((16 * rg + jr) << 16) | (64 * wv + 16 * (q >> 2) + 4 * g + (q & 3)),
+                                             acc[rg][q >> 2][q & 3], sv[rg][q].x, sv[rg][q].y);
                 }
     }
     __syncthreads();
@@ -2458,11 +2496,10 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     RecPod r = rec_empty();
     if (ncand <= kSingleCap) {
         if (t < ncand) {
-            int4 c = clist[t];
-            int64_t l = (int64_t)(y0 + c.x) * a.Lx + x0 + c.y;
-            int2 st = ld_int2(a.stat + (l));
-            int64_t dr = var_num(mn, st);
-            int64_t num = mn * (int64_t)c.z - St * (int64_t)st.x;
+            const int4 c = clist[t];
+            const int64_t l = (int64_t)(y0 + (c.x >> 16)) * a.Lx + x0 + (c.x & 0xffff);
+            const int64_t dr = var_num(mn, make_int2(c.z, c.w));
+            const int64_t num = mn * (int64_t)c.y - St * (int64_t)c.z;
             r.rho = rho64(num, Dt, dr);
             r.l = l;
             r.num = num;
@@ -2491,6 +2528,12 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
                 }
             }
     }
+    // the candidates sit in the first ncand lanes: one needs no merge, and up
+    // to 64 are merged within wave 0 (thread 0 holds the result either way)
+    if (ncand == 1)
+        return r;
+    if (ncand <= 64)
+        return wv == 0 ? wave_rec(r) : r;
     return block_rec4(r, red);
 }
 
@@ -2998,166 +3041,169 @@ static int centre_rows(int m, int n, int h)
 }
 
 // Dwords of a staged row of k_centres_mfma's region that the A reads can
-// reach (64 centre columns of stride w, the template width, realignment
+// reach (64 MTW centre columns of stride w, the template width, realignment
 // slack).
-static int centres_mfma_cwn(int n, int w)
+static int centres_mfma_cwn(int n, int w, int mtw)
 {
     int n16 = (n + 15) / 16 * 16;
-    return (63 * w + w / 2 + n16 + 12) / 4 + 2;
+    return ((64 * mtw - 1) * w + w / 2 + n16 + 12) / 4 + 2;
 }
 
-// LDS bank cost of the A reads for a staged-row stride of cwd dwords: lane
-// (j, g) of wave v reads dword g cwd + ((r + (16 v + j) w) >> 2) plus a
-// common offset, r being the byte offset of the region's first centre in its
-// word.  The cost is the largest number of distinct dwords that fall in one
-// of the 64 four-byte banks, summed over r and v.
-static int centres_bank_cost(int cwd, int w)
+// LDS bank cost of the A reads for a staged-copy stride of cs dwords: lane
+// (j, g) of an M-tile reads dwords (4 g + (o & 3)) cs + (o >> 2) + {0, 1}
+// and {2, 3} (two ds_read2_b32), o = r + 16 w (mt) + w j being its centre's
+// byte offset from the region's first staged word.  The cost is the largest
+// number of distinct dwords in one of 128 four-byte banks among the 32 lanes
+// served together, summed over r, the first M-tiles, both reads and both
+// halves of the wave.
+static int centres_bank_cost(int cs, int w)
 {
     int cost = 0;
     for (int r = 0; r < 4; r++)
-        for (int v = 0; v < 4; v++) {
-            int words[64], nw = 0, cnt[64] = {0};
-            for (int g = 0; g < 4; g++)
-                for (int j = 0; j < 16; j++) {
-                    int d = g * cwd + ((r + (16 * v + j) * w) >> 2);
-                    bool dup = false;
-                    for (int k = 0; k < nw; k++)
-                        dup |= words[k] == d;
-                    if (!dup) {
-                        words[nw++] = d;
-                        cnt[d & 63]++;
+        for (int mt = 0; mt < 4; mt++)
+            for (int half = 0; half < 2; half++)
+                for (int pr = 0; pr < 2; pr++) {
+                    int words[64], nw = 0, cnt[128] = {0};
+                    for (int l = 32 * half; l < 32 * half + 32; l++) {
+                        const int g = l >> 4, j = l & 15, o = r + 16 * w * mt + w * j;
+                        for (int e = 0; e < 2; e++) {
+                            const int d = (4 * g + (o & 3)) * cs + (o >> 2) + 2 * pr + e;
+                            bool dup = false;
+                            for (int k = 0; k < nw; k++)
+                                dup |= words[k] == d;
+                            if (!dup) {
+                                words[nw++] = d;
+                                cnt[d & 127]++;
+                            }
+                        }
                     }
+                    int worst = 0;
+                    for (int b = 0; b < 128; b++)
+                        worst = cnt[b] > worst ? cnt[b] : worst;
+                    cost += worst;
                 }
-            int worst = 0;
-            for (int b = 0; b < 64; b++)
-                worst = cnt[b] > worst ? cnt[b] : worst;
-            cost += worst;
-        }
     return cost;
 }
 
-static size_t centres_mfma_lds(int m, int n, int cwd, int crows, int ntpl = 1)
+static size_t centres_mfma_lds(int m, int n, int cs, int ntpl = 1)
 {
     int n16 = (n + 15) / 16 * 16;
-    return ((size_t)ntpl * (m + 1) * batch_tstride(n16 / 4) + (size_t)2 * crows * cwd) * 4;
+    return ((size_t)ntpl * (m + 1) * batch_tstride(n16 / 4) + (size_t)2 * 16 * cs) * 4;
 }
 
-// Staging shape of k_centres_mfma: chunk rows (64, 32 or 16, the most that
-// fit 60 KB of LDS with the reachable width staged by 512 / rows threads
-// per row, kCmLd words each) and the row stride with the least bank cost
-// among the reachable width and up to 63 dwords more.  cwd = 0 when the
-// MFMA form does not apply (n > 128, or no chunk height fits).  The chunk
-// buffers also hold the 4 x 64 accumulator exchange (1024 dwords).
+// Shape of k_centres_mfma for a centre grid: M-tiles per wave (4, 2 or 1:
+// the most that leaves at least kCmMinBlocks blocks and whose staged width
+// fits the per-thread staging, 4 cwn <= 256 cm_words_per_thread), the
+// reachable width cwn and the copy stride cs (among cwn and up to 63 dwords
+// more, the least bank cost within 60 KB of LDS).  cs = 0 when the MFMA form
+// does not apply (n > 128, or no width fits).
 struct CmShape {
-    int cwd, cwn, crows;
+    int cs, cwn, mtw;
 };
+constexpr int64_t kCmMinBlocks = 512;
 
-static CmShape centres_mfma_shape_search(int m, int n, int w)
+static CmShape centres_mfma_shape_search(int Gy, int Gx, int m, int n, int w)
 {
     const size_t kLds = 60 * 1024;
     int n16 = (n + 15) / 16 * 16;
-    int cwn = centres_mfma_cwn(n, w);
-    CmShape r = {0, cwn, 0};
+    CmShape r = {0, 0, 0};
     if (n16 > 128)
         return r;
-    for (int crows = 64; crows >= 16 && !r.crows; crows >>= 1)
-        if (cwn <= kCmLd * (kCmThreads / crows) && 2 * crows * cwn >= 1024 &&
-            centres_mfma_lds(m, n, cwn, crows) <= kLds)
-            r.crows = crows;
-    if (!r.crows)
+    for (int mtw = 4; mtw >= 1; mtw >>= 1) {
+        const int cwn = centres_mfma_cwn(n, w, mtw);
+        if (4 * cwn > 256 * cm_words_per_thread(mtw) || centres_mfma_lds(m, n, cwn) > kLds)
+            continue;
+        const int64_t nb = blocks_for(Gx, 64 * mtw) * blocks_for(Gy, 16);
+        if (mtw > 1 && nb < kCmMinBlocks)
+            continue;
+        r.cwn = cwn;
+        r.mtw = mtw;
+        break;
+    }
+    if (!r.mtw)
         return r;
-    int best = cwn, best_cost = centres_bank_cost(cwn, w);
-    for (int cwd = cwn + 1; cwd < cwn + 64 && centres_mfma_lds(m, n, cwd, r.crows) <= kLds; cwd++) {
-        int c = centres_bank_cost(cwd, w);
+    int best = r.cwn, best_cost = centres_bank_cost(r.cwn, w);
+    for (int cs = r.cwn + 1; cs < r.cwn + 64 && centres_mfma_lds(m, n, cs) <= kLds; cs++) {
+        int c = centres_bank_cost(cs, w);
         if (c < best_cost) {
-            best = cwd;
+            best = cs;
             best_cost = c;
         }
     }
-    r.cwd = best;
+    r.cs = best;
     return r;
 }
 
-// The search above, memoised per (m, n, w): it runs once per shape, not per
-// query (callers may be on several threads).
-static CmShape centres_mfma_shape(int m, int n, int w)
+// The search above, memoised per (Gy, Gx, m, n, w): it runs once per shape,
+// not per query (callers may be on several threads).
+static CmShape centres_mfma_shape(int Gy, int Gx, int m, int n, int w)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int>, CmShape> memo;
+    static std::map<std::tuple<int, int, int, int, int>, CmShape> memo;
     std::lock_guard<std::mutex> lk(mu);
-    auto key = std::make_tuple(m, n, w);
+    auto key = std::make_tuple(Gy, Gx, m, n, w);
     auto it = memo.find(key);
     if (it != memo.end())
         return it->second;
-    CmShape r = centres_mfma_shape_search(m, n, w);
+    CmShape r = centres_mfma_shape_search(Gy, Gx, m, n, w);
     memo.emplace(key, r);
     return r;
 }
 
 int centres_record_count(int Gy, int Gx, int m, int n, int h, int w)
 {
-    if (centres_mfma_shape(m, n, w).cwd)
-        return (int)(blocks_for(Gx, 64) * blocks_for(Gy, 16));
+    const CmShape sh = centres_mfma_shape(Gy, Gx, m, n, w);
+    if (sh.cs)
+        return (int)(blocks_for(Gx, 64 * sh.mtw) * blocks_for(Gy, 16));
     return (int)(blocks_for(Gx, 64) * blocks_for(Gy, centre_rows(m, n, h)));
 }
 
-// LDS of several templates' rows beside the chunk buffers of the one-template
-// shape (the chunk height stays that of a single query).
+// LDS of several templates' rows beside the step buffers of the one-template
+// shape.
 constexpr size_t kCmBatchLds = 150 * 1024;
 
-bool centres_mfma_batchable(int m, int n, int w, int ntpl)
+bool centres_mfma_batchable(int Gy, int Gx, int m, int n, int w, int ntpl)
 {
-    const CmShape sh = centres_mfma_shape(m, n, w);
-    return sh.cwd && ntpl >= 1 && ntpl <= kScanMaxT &&
-           centres_mfma_lds(m, n, sh.cwd, sh.crows, ntpl) + static_lds((const void *)k_centres_mfma<8, kScanMaxT>) <=
+    const CmShape sh = centres_mfma_shape(Gy, Gx, m, n, w);
+    return sh.cs && ntpl >= 1 && ntpl <= kScanMaxT &&
+           centres_mfma_lds(m, n, sh.cs, ntpl) + static_lds((const void *)k_centres_mfma<8, kScanMaxT, 4>) <=
                kCmBatchLds;
 }
 
-template <int NB> static void launch_cm(const ScanArgs &a, dim3 grid, dim3 blk, size_t lds, hipStream_t s)
+template <int NB, int TM> static const void *cm_kernel(int mtw)
 {
-    if (a.ntpl <= 1)
-        hipLaunchKernelGGL((k_centres_mfma<NB, 1>), grid, blk, lds, s, a);
-    else
-        hipLaunchKernelGGL((k_centres_mfma<NB, kScanMaxT>), grid, blk, lds, s, a);
+    return mtw == 4 ? (const void *)k_centres_mfma<NB, TM, 4>
+         : mtw == 2 ? (const void *)k_centres_mfma<NB, TM, 2> : (const void *)k_centres_mfma<NB, TM, 1>;
 }
 
-template <int NB> static hipError_t allow_cm(int ntpl, size_t lds)
+template <int NB> static const void *cm_kernel(int ntpl, int mtw)
 {
-    return ntpl <= 1 ? allow_lds((const void *)k_centres_mfma<NB, 1>, lds)
-                     : allow_lds((const void *)k_centres_mfma<NB, kScanMaxT>, lds);
+    return ntpl <= 1 ? cm_kernel<NB, 1>(mtw) : cm_kernel<NB, kScanMaxT>(mtw);
 }
 
 hipError_t launch_centres(ScanArgs a, hipStream_t s)
 {
-    CmShape sh = centres_mfma_shape(a.m, a.n, a.w);
     if (a.ntpl < 1)
         a.ntpl = 1;
-    if (a.ntpl > 1 && !centres_mfma_batchable(a.m, a.n, a.w, a.ntpl))
+    const CmShape sh = centres_mfma_shape(a.Gy, a.Gx, a.m, a.n, a.w);
+    if (a.ntpl > 1 && !centres_mfma_batchable(a.Gy, a.Gx, a.m, a.n, a.w, a.ntpl))
         return hipErrorInvalidValue;
-    if (sh.cwd) {
-        a.cwd = sh.cwd;
+    if (sh.cs) {
+        a.cwd = sh.cs;
         a.cwn = sh.cwn;
-        a.crows_log2 = sh.crows == 64 ? 6 : sh.crows == 32 ? 5 : 4;
-        size_t lds = centres_mfma_lds(a.m, a.n, sh.cwd, sh.crows, a.ntpl);
-        dim3 grid(blocks_for(a.Gx, 64), blocks_for(a.Gy, 16)), blk(kCmThreads);
+        a.crows_log2 = 2;
+        const size_t lds = centres_mfma_lds(a.m, a.n, sh.cs, a.ntpl);
+        const dim3 grid(blocks_for(a.Gx, 64 * sh.mtw), blocks_for(a.Gy, 16)), blk(kCmThreads);
         const int nb = (a.n + 15) / 16;
-        hipError_t e = nb == 1 ? allow_cm<1>(a.ntpl, lds) : nb == 2 ? allow_cm<2>(a.ntpl, lds)
-                     : nb == 3 ? allow_cm<3>(a.ntpl, lds) : nb == 4 ? allow_cm<4>(a.ntpl, lds)
-                     : nb == 5 ? allow_cm<5>(a.ntpl, lds) : nb == 6 ? allow_cm<6>(a.ntpl, lds)
-                     : nb == 7 ? allow_cm<7>(a.ntpl, lds) : allow_cm<8>(a.ntpl, lds);
+        const void *f = nb == 1 ? cm_kernel<1>(a.ntpl, sh.mtw) : nb == 2 ? cm_kernel<2>(a.ntpl, sh.mtw)
+                      : nb == 3 ? cm_kernel<3>(a.ntpl, sh.mtw) : nb == 4 ? cm_kernel<4>(a.ntpl, sh.mtw)
+                      : nb == 5 ? cm_kernel<5>(a.ntpl, sh.mtw) : nb == 6 ? cm_kernel<6>(a.ntpl, sh.mtw)
+                      : nb == 7 ? cm_kernel<7>(a.ntpl, sh.mtw) : cm_kernel<8>(a.ntpl, sh.mtw);
+        hipError_t e = allow_lds(f, lds);
         if (e != hipSuccess)
             return e;
-        switch (nb) {
-        case 1: launch_cm<1>(a, grid, blk, lds, s); break;
-        case 2: launch_cm<2>(a, grid, blk, lds, s); break;
-        case 3: launch_cm<3>(a, grid, blk, lds, s); break;
-        case 4: launch_cm<4>(a, grid, blk, lds, s); break;
-        case 5: launch_cm<5>(a, grid, blk, lds, s); break;
-        case 6: launch_cm<6>(a, grid, blk, lds, s); break;
-        case 7: launch_cm<7>(a, grid, blk, lds, s); break;
-        default: launch_cm<8>(a, grid, blk, lds, s); break;
-        }
-        return hipGetLastError();
+        void *args[] = {&a};
+        return hipLaunchKernel(f, grid, blk, args, lds, s);
     }
     a.n4w = (((a.n + 3) / 4) + 3) / 4 * 4;
     int nw = centre_waves(a.n);
