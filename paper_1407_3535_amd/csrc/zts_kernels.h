@@ -260,9 +260,11 @@ hipError_t launch_full(FullArgs a, hipStream_t s);
 // cover fits its LDS budget, else on v_dot4 (k_centres); both write one
 // record per block.
 int centres_record_count(int Gy, int Gx, int m, int n, int h, int w);
-// One block: the best record of [lo, hi) and the counts summed over [count_lo, hi).
-// then copies the query state to its pinned host mirror `host` and bumps qs->seq there last.
-hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s);
+// The best record of [lo, hi) and the counts summed over [count_lo, hi) into
+// the query state, then copies the state to its pinned host mirror `host` and
+// bumps qs->seq there last.  Over more than 2048 records, chunks are merged
+// by a first launch that overwrites each chunk's first record.
+hipError_t launch_reduce(RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s);
 // Zeroes *qs (every word, the sequence number included) with a fill kernel.
 hipError_t launch_qs_clear(QState *qs, hipStream_t s);
 hipError_t launch_centres(ScanArgs a, hipStream_t s);

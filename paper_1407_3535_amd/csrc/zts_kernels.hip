@@ -2790,23 +2790,21 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const BatchJob *__restrict
 // mirror is written from registers.
 constexpr int kRedThreads = 256;
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi,
-                                                        int count_lo, QState *qs, QState *host)
+// Records of [start, hi), start = min(lo, count_lo): the best over [lo, hi)
+// and the counts over [count_lo, hi), merged into one record per thread
+// (up to four records per thread loaded before they are merged).  With
+// stride > 1 the records are the partial results k_reduce_part left at
+// start, start + stride, ... (each already follows those rules).
+__device__ RecPod reduce_range(const RecPod *__restrict__ recs, int lo, int hi, int count_lo, int stride)
 {
-    __shared__ RecPod red[kRedThreads / 64];
-    constexpr int kWords = (int)(sizeof(QState) / 8), kSeqWord = (int)(offsetof(QState, seq) / 8);
-    static_assert(sizeof(QState) % 8 == 0 && offsetof(QState, seq) % 8 == 0, "8-byte words");
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    uint64_t w[kWords];
-    if (t == 0) {
-#pragma unroll
-        for (int k = 0; k < kWords; k++)
-            w[k] = ((const uint64_t *)qs)[k];
-    }
-    // best over [lo, hi), counts over [count_lo, hi); up to four records per
-    // thread are loaded before they are merged
+    const int t = threadIdx.x;
     RecPod r = rec_empty();
     const int start = min(lo, count_lo);
+    if (stride > 1) {
+        for (int k = start + t * stride; k < hi; k += kRedThreads * stride)
+            rec_merge(r, recs[k]);
+        return r;
+    }
     for (int k0 = start + t; k0 < hi; k0 += 4 * kRedThreads) {
         RecPod b[4];
 #pragma unroll
@@ -2822,6 +2820,45 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RecPod *__restrict
         for (int j = 0; j < 4; j++)
             rec_merge(r, b[j]);
     }
+    return r;
+}
+
+// First level of the final reduction over many records: block b merges the
+// chunk [start + b chunk, start + (b + 1) chunk) and writes its partial
+// record over the chunk's first record (read by then).
+constexpr int kRedChunk = 2048;
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_part(RecPod *__restrict__ recs, int lo, int hi, int count_lo)
+{
+    __shared__ RecPod red[kRedThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int start = min(lo, count_lo), c0 = start + blockIdx.x * kRedChunk, c1 = min(hi, c0 + kRedChunk);
+    RecPod r = reduce_range(recs, max(lo, c0), c1, max(count_lo, c0), 1);
+    r = wave_rec(r);
+    if (lane == 0)
+        red[wv] = r;
+    __syncthreads();
+    if (wv == 0) {
+        const RecPod f = wave_rec<kRedThreads / 64>(lane < kRedThreads / 64 ? red[lane] : rec_empty());
+        if (lane == 0)
+            recs[c0] = f;
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const RecPod *__restrict__ recs, int lo, int hi,
+                                                        int count_lo, int stride, QState *qs, QState *host)
+{
+    __shared__ RecPod red[kRedThreads / 64];
+    constexpr int kWords = (int)(sizeof(QState) / 8), kSeqWord = (int)(offsetof(QState, seq) / 8);
+    static_assert(sizeof(QState) % 8 == 0 && offsetof(QState, seq) % 8 == 0, "8-byte words");
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint64_t w[kWords];
+    if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < kWords; k++)
+            w[k] = ((const uint64_t *)qs)[k];
+    }
+    RecPod r = reduce_range(recs, lo, hi, count_lo, stride);
     r = wave_rec(r);
     if (lane == 0)
         red[wv] = r;
@@ -2898,9 +2935,18 @@ hipError_t launch_stats(const uint2 *sat, int q, int Ly, int Lx, int m, int n, i
 
 static constexpr int kFullR = 8;
 
-hipError_t launch_reduce(const RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s)
+hipError_t launch_reduce(RecPod *recs, int lo, int hi, int count_lo, QState *qs, QState *host, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, recs, lo, hi, count_lo, qs, host);
+    const int start = std::min(lo, count_lo);
+    const unsigned parts = blocks_for(std::max(hi - start, 0), kRedChunk);
+    if (parts > 1) {  // many records: chunks merged in parallel first
+        hipLaunchKernelGGL(k_reduce_part, dim3(parts), dim3(kRedThreads), 0, s, recs, lo, hi, count_lo);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, (const RecPod *)recs, lo, hi, count_lo,
+                           kRedChunk, qs, host);
+    } else {
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, (const RecPod *)recs, lo, hi, count_lo, 1,
+                           qs, host);
+    }
     return hipGetLastError();
 }
 
