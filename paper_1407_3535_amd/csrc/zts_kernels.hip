@@ -1282,14 +1282,14 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
     return base + incl - v;  // tmp must not be written again before the caller's next barrier
 }
 
-// 256 consecutive groups per block.  Phase 1: one thread per group drops the
-// whole group when the interval of its member angles lies beyond the
-// threshold angle from A.  Phase 2: the members of the remaining groups are
-// tested one per thread, reading the group-major angle tables contiguously
-// (binary32 angles; canonical binary64 inside the guard band); survivors go
-// to an LDS list.  Phase 3: one wave per survivor matches it on the original
-// image (template loaded only by blocks that have survivors).  The last
-// block reduces every record of the query.
+// 512 consecutive groups per block (two per thread).  Phase 1: one thread
+// per group drops the whole group when the interval of its member angles
+// lies beyond the threshold angle from A.  Phase 2: the members of the
+// remaining groups are tested one per thread slot, up to 4096 per pass, each
+// slot finding its group in an owner map the group's thread wrote, reading
+// the group-major angle tables contiguously (binary32 angles; canonical
+// binary64 inside the guard band); survivors go to an LDS list and are binned
+// by survivor tile.
 // Bins one pass's survivors by tile: a tile's survivors take consecutive
 // slots of its bin (the first tile_cap are kept; a fuller tile is matched
 // whole).  The block's survivors are counted per tile in LDS first, so each
@@ -1348,9 +1348,11 @@ __device__ void bin_survivors(const MemArgs &a, const int *s_list, int ns, int t
 
 __global__ __launch_bounds__(256) void k_members(MemArgs a)
 {
-    constexpr int CAP = 1024;  // members per pass: 4 per thread
+    constexpr int CAP = kSurvList / 2;  // members per pass: 8 per thread
     constexpr int GB = kMemGroups;
+    static_assert(GB <= 65536, "group slots fit 16 bits");
     __shared__ int s_pref[GB + 1];
+    __shared__ uint16_t s_owner[CAP];  // the block group of each member slot of a pass
     __shared__ int s_tmp[4];
     __shared__ int s_geo[GB][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
     __shared__ int s_list[kSurvList];
@@ -1459,62 +1461,85 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     RecPod rec = rec_empty();
     for (int base = 0; base < total; base += CAP) {
         int end = min(total, base + CAP);
-        // locate this thread's (up to 4) members and load their angles first
+        // each thread marks the pass's slots of its two groups with the group,
+        // so that a member slot finds its group in one read (the previous
+        // pass read s_owner before its last barrier)
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const int lo = off + (e ? cnt2[0] : 0);
+            const int i0 = max(lo, base), i1 = min(lo + cnt2[e], end);
+            for (int i = i0; i < i1; i++)
+                s_owner[i - base] = (uint16_t)(2 * t + e);
+        }
+        __syncthreads();
+        // locate this thread's (up to 16) members and load their angles first
         // (locations and slots fit 32 bits: image sides are at most 32767,
-        // so the tables hold fewer than 2^31 entries)
-        int o8[CAP / 256], sl8[CAP / 256];
-        int u8[CAP / 256];
+        // so the tables hold fewer than 2^31 entries); the locations are
+        // found again from the owner map when the angles are tested, so that
+        // only the angles stay in registers meanwhile
+        auto member = [&](int idx, int &u, int &o, int &sl) {
+            u = s_owner[idx - base];
+            const int k = idx - s_pref[u];
+            const int oy = s_geo[u][0] >> 16, ox = s_geo[u][0] & 0xffff;
+            const int ww = s_geo[u][1] & 0xffff;
+            const int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+            const int my = k / ww, mx = k - my * ww;
+            const int y = oy + my, x = ox + mx;
+            sl = (g0 + u) * hw + my * a.w + mx;
+            o = ((!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius)) ? -1 : y * a.Lx + x;
+        };
         float B8[CAP / 256], C8[CAP / 256];
+        uint32_t live = 0;
 #pragma unroll
         for (int q = 0; q < CAP / 256; q++) {
-            int idx = base + t + 256 * q;
-            o8[q] = -1;
+            const int idx = base + t + 256 * q;
+            B8[q] = C8[q] = 0.0f;
             if (idx >= end)
                 continue;
-            int u = 0;
-            for (int step = GB / 2; step > 0; step >>= 1)
-                if (s_pref[u + step] <= idx)
-                    u += step;
-            int k = idx - s_pref[u];
-            int oy = s_geo[u][0] >> 16, ox = s_geo[u][0] & 0xffff;
-            int ww = s_geo[u][1] & 0xffff;
-            int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
-            int my = k / ww, mx = k - my * ww;
-            int y = oy + my, x = ox + mx;
-            if ((!a.opta && y == cy && x == cx) || in_window(y, x, wy, wx, a.radius))
+            int u, o, sl;
+            member(idx, u, o, sl);
+            if (o < 0)
                 continue;
-            o8[q] = y * a.Lx + x;
-            sl8[q] = (g0 + u) * hw + my * a.w + mx;
-            u8[q] = u;
-            B8[q] = a.theta_b[sl8[q]];
-            C8[q] = a.opta ? a.theta_c[sl8[q]] : 0.0f;
+            live |= 1u << q;
+            B8[q] = a.theta_b[(uint32_t)sl];
+            C8[q] = a.opta ? a.theta_c[(uint32_t)sl] : 0.0f;
         }
 #pragma unroll
         for (int q = 0; q < CAP / 256; q++) {
-            if (o8[q] < 0)
-                continue;
-            int u = u8[q];
-            int64_t o = o8[q], sl = sl8[q];
-            float A = __int_as_float(s_geo[u][3]);
-            float e = fabsf(A - B8[q]) - C8[q];
-            bool keep;
-            if (e > hi)
-                keep = false;
-            else if (e < lo)
-                keep = true;
-            else {
-                int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
-                keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g0 + u, mn, st, dt, thr64);
+            bool keep = false;
+            int o32 = 0;
+            if ((live >> q) & 1) {
+                int u, sl32;
+                member(base + t + 256 * q, u, o32, sl32);
+                const int64_t o = o32, sl = sl32;
+                float A = __int_as_float(s_geo[u][3]);
+                float e = fabsf(A - B8[q]) - C8[q];
+                if (e > hi)
+                    keep = false;
+                else if (e < lo)
+                    keep = true;
+                else {
+                    int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+                    keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g0 + u, mn, st, dt, thr64);
+                }
+                if (keep)
+                    n_surv++;
+                else
+                    n_elim++;
+                if (a.dec)
+                    a.dec[o] = keep ? 2 : 0;
             }
-            if (keep) {
-                int pos = atomicAdd(&s_nsurv, 1);
-                s_list[pos] = (int)o;
-                n_surv++;
-            } else {
-                n_elim++;
+            // the wave's survivors take consecutive list slots: one LDS atomic
+            // per wave, each lane's slot from the ballot
+            const uint64_t km = __ballot(keep);
+            if (km) {
+                int wbase = 0;
+                if (lane == 0)
+                    wbase = atomicAdd(&s_nsurv, (int)__popcll(km));
+                wbase = __shfl(wbase, 0);
+                if (keep)
+                    s_list[wbase + (int)__popcll(km & ((1ull << lane) - 1))] = o32;
             }
-            if (a.dec)
-                a.dec[o] = keep ? 2 : 0;
         }
         __syncthreads();
         // survivors collect over passes and are binned when the next pass
@@ -2278,7 +2303,12 @@ __device__ __forceinline__ void single_tpl_pads(uint32_t *tpl_l, int m, int nw16
     }
 }
 
-__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 16 * batch_copy_stride((256 + n16 + 16) >> 2); }
+// Staged image rows of the single-template body: 256 + n16 + 16 bytes from
+// the block's first column, as eight copies shifted by 0..7 bytes (so that
+// every A lane reads 16 bytes at an 8-byte boundary), of single_copy_stride
+// dwords each; two buffers of 4 rows.
+__host__ __device__ inline int single_copy_stride(int n16) { return (((256 + n16 + 16) >> 2) + 1) & ~1; }
+__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 32 * single_copy_stride(n16); }
 
 // One 16 RG x 256 block of locations of one template (the body of k_single
 // and of k_dense_tiles).  The caller has staged the template at
@@ -2302,9 +2332,8 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     static_assert(RG >= 1 && RG <= 4, "row groups per block");
     constexpr int MT = 4, ROWS = 16 * RG;
     const int m = a.m, n16 = a.n16, nb16 = n16 >> 4;
-    const int WW = (256 + n16 + 16) >> 2;
-    const int CS = batch_copy_stride(WW);
-    const int IMGW = 16 * CS;
+    const int CS = single_copy_stride(n16), WP = CS >> 1;  // staged dword pairs per row
+    const int IMGW = 32 * CS;
     const int tstr = batch_tstride(n16 >> 2);
     const uint32_t *tpl_l = smem + 2 * IMGW;  // row -kSinglePadLo of the padded template
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -2317,32 +2346,30 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     // the last one, or zero template columns, so its value does not matter;
     // and with no branch around them the compiler can wait for one register
     // set while the other is still in flight.
-    uint32_t rA[2][2], rB[2][2];
-    auto gload = [&](int s, uint32_t (&ri)[2][2]) {
+    // Thread t stages dword pair t of the step (row t / WP, bytes 8p .. 8p + 7
+    // of each copy, from the 16 row bytes at 8p; 4 WP <= 256).
+    const int sidx = min(t, 4 * WP - 1), srow = sidx / WP, spair = sidx - srow * WP;
+    uint32_t rA[4], rB[4];
+    auto gload = [&](int s, uint32_t (&ri)[4]) {
+        const int gy = min(y0 + 4 * s + srow, a.p - 1);
+        const int64_t gx = min((int64_t)x0 + 8 * spair, a.pitch - 16);
+        const uint32_t *rp = (const uint32_t *)(a.img + (int64_t)gy * a.pitch + gx);
 #pragma unroll
-        for (int k = 0; k < 2; k++) {
-            const int idx = min(t + 256 * k, 4 * WW - 1);
-            const int g = idx / WW, w = idx - g * WW;
-            const int gy = min(y0 + 4 * s + g, a.p - 1);
-            const int64_t gx = min((int64_t)x0 + 4 * w, a.pitch - 8);
-            const uint8_t *rp = a.img + (int64_t)gy * a.pitch + gx;
-            ri[k][0] = *gptr((const uint32_t *)rp);
-            ri[k][1] = *gptr((const uint32_t *)(rp + 4));
-        }
+        for (int k = 0; k < 4; k++)
+            ri[k] = *gptr(rp + k);
     };
-    auto lstore = [&](int s, const uint32_t (&ri)[2][2]) {
-        uint32_t *b = smem + (s & 1) * IMGW;
-#pragma unroll
-        for (int k = 0; k < 2; k++) {
-            int idx = t + 256 * k;
-            if (idx < 4 * WW) {
-                int g = idx / WW, w = idx - g * WW;
-                uint32_t lo = flip4(ri[k][0]), hi = flip4(ri[k][1]);
-                b[(g * 4 + 0) * CS + w] = lo;
-                b[(g * 4 + 1) * CS + w] = bytes_at(hi, lo, 1);
-                b[(g * 4 + 2) * CS + w] = bytes_at(hi, lo, 2);
-                b[(g * 4 + 3) * CS + w] = bytes_at(hi, lo, 3);
-            }
+    auto lstore = [&](int s, const uint32_t (&ri)[4]) {
+        if (t < 4 * WP) {
+            uint32_t *b = smem + (s & 1) * IMGW + srow * 8 * CS + 2 * spair;
+            const uint32_t w0 = flip4(ri[0]), w1 = flip4(ri[1]), w2 = flip4(ri[2]), w3 = flip4(ri[3]);
+            *(uint2 *)(b + 0 * CS) = make_uint2(w0, w1);
+            *(uint2 *)(b + 1 * CS) = make_uint2(bytes_at(w1, w0, 1), bytes_at(w2, w1, 1));
+            *(uint2 *)(b + 2 * CS) = make_uint2(bytes_at(w1, w0, 2), bytes_at(w2, w1, 2));
+            *(uint2 *)(b + 3 * CS) = make_uint2(bytes_at(w1, w0, 3), bytes_at(w2, w1, 3));
+            *(uint2 *)(b + 4 * CS) = make_uint2(w1, w2);
+            *(uint2 *)(b + 5 * CS) = make_uint2(bytes_at(w2, w1, 1), bytes_at(w3, w2, 1));
+            *(uint2 *)(b + 6 * CS) = make_uint2(bytes_at(w2, w1, 2), bytes_at(w3, w2, 2));
+            *(uint2 *)(b + 7 * CS) = make_uint2(bytes_at(w2, w1, 3), bytes_at(w3, w2, 3));
         }
     };
 
@@ -2358,10 +2385,11 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     gload(1, rB);
     const int g = lane >> 4, jr = lane & 15;
     // A lane (jr, g) reads location column c = 64 wv + 16 mt + jr + 16 cb of
-    // image row g: the copy shifted by c & 3 = jr & 3 bytes, word c >> 2.  B
-    // lane (jr, g) of row group rg reads template row d + g - jr.
+    // image row g: the copy shifted by c & 7 = jr & 7 bytes, from byte
+    // c & ~7 (two 8-byte reads).  B lane (jr, g) of row group rg reads
+    // template row d + g - jr.
     const uint32_t *tpl_b = tpl_l + (g - jr + kSinglePadLo) * tstr;
-    const int a_off = (g * 4 + (jr & 3)) * CS + 16 * wv + (jr >> 2);
+    const int a_off = (g * 8 + (jr & 7)) * CS + 16 * wv + 2 * (jr >> 3);
     auto compute = [&](int s) {
         const uint32_t *pa = smem + (s & 1) * IMGW + a_off;
         const uint32_t *pb[RG];
@@ -2373,8 +2401,11 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
         v4i A0[MT], A1[MT], B0[RG], B1[RG];
         auto frag = [&](v4i (&A)[MT], v4i (&B)[RG], int cb) {
 #pragma unroll
-            for (int mt = 0; mt < MT; mt++)
-                __builtin_memcpy(&A[mt], pa + 4 * mt + 4 * cb, 16);
+            for (int mt = 0; mt < MT; mt++) {
+                const uint64_t *q = (const uint64_t *)(pa + 4 * mt + 4 * cb);
+                const uint64_t lo = q[0], hi = q[1];
+                A[mt] = v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi, (int)(uint32_t)(hi >> 32)};
+            }
 #pragma unroll
             for (int rg = 0; rg < RG; rg++)
                 B[rg] = *(const v4i *)(pb[rg] + 4 * cb);
@@ -3477,8 +3508,7 @@ bool batch_single_fits(int m, int n)
     int n16 = (n + 15) / 16 * 16;
     if (n16 > 128 || m < 1 || m > 2048)
         return false;
-    int WW = (256 + n16 + 16) / 4;
-    size_t words = (size_t)2 * 16 * batch_copy_stride(WW) + (size_t)single_tpl_words(m, n16);
+    size_t words = (size_t)single_tpl_offset(n16) + (size_t)single_tpl_words(m, n16);
     return words * 4 <= 64 * 1024;
 }
 
@@ -3515,8 +3545,7 @@ static size_t batch_lds_bytes(int n16)
 
 static size_t single_lds_bytes(int m, int n16)
 {
-    int WW = (256 + n16 + 16) / 4;
-    size_t lds = ((size_t)2 * 16 * batch_copy_stride(WW) + (size_t)single_tpl_words(m, n16)) * 4;
+    size_t lds = ((size_t)single_tpl_offset(n16) + (size_t)single_tpl_words(m, n16)) * 4;
     return std::max(lds, (size_t)kSingleLdsWords * 4);
 }
 
