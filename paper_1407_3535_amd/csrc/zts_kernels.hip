@@ -2694,8 +2694,11 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
 // empty tile, or one of a super-tile k_dense_tiles matched whole, writes an
 // empty record.  Otherwise (fewer than dense_min survivors, all in its bin)
 // each listed survivor is matched by one wave with unsigned dot products,
-// from the tile's image region staged in LDS when it fits, else from global
-// memory.  One record per tile.
+// from the tile's image region staged in LDS when it fits and the tile has
+// more than kSparseDirect survivors, else from global memory.  One record per
+// tile.
+constexpr int kSparseDirect = 16;  // survivors of a tile matched without staging its region
+
 __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
@@ -2717,7 +2720,10 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
     uint32_t *tplw = smem;
     uint32_t *reg = smem + ((a.m * n4 + 3) & ~3);
     load_template_words(a.tpl, a.ts, a.m, a.n, n4, tplw);
-    if (a.sparse_lds) {
+    // a few survivors read their windows from global memory: staging the
+    // whole region would cost more than it saves
+    const bool staged = a.sparse_lds && cnt > kSparseDirect;
+    if (staged) {
         // rows y0 .. y0 + 31 + m - 1 (clipped to the image), words from x0
         const int R = min(kTileRows + a.m - 1, a.p - y0);
         const uint8_t *base = a.img + (int64_t)y0 * a.pitch + x0;
@@ -2744,8 +2750,8 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
         for (int q = 0; q < nbat; q++) {
             const int o32 = __shfl(ol, q);
             const int y = o32 / a.Lx, x = o32 - y * a.Lx;
-            const uint32_t Xu = a.sparse_lds ? wave_dot_lds_u8(tplw, n4, reg, rsw, y - y0, x - x0, a.m, lane)
-                                             : wave_dot_tpl_u8(tplw, n4, a.img, a.pitch, y, x, a.m, lane);
+            const uint32_t Xu = staged ? wave_dot_lds_u8(tplw, n4, reg, rsw, y - y0, x - x0, a.m, lane)
+                                       : wave_dot_tpl_u8(tplw, n4, a.img, a.pitch, y, x, a.m, lane);
             mine = lane == q ? Xu : mine;
         }
         if (lane < nbat) {
