@@ -2304,11 +2304,20 @@ __device__ __forceinline__ void single_tpl_pads(uint32_t *tpl_l, int m, int nw16
 }
 
 // Staged image rows of the single-template body: 256 + n16 + 16 bytes from
-// the block's first column, as eight copies shifted by 0..7 bytes (so that
-// every A lane reads 16 bytes at an 8-byte boundary), of single_copy_stride
-// dwords each; two buffers of 4 rows.
-__host__ __device__ inline int single_copy_stride(int n16) { return (((256 + n16 + 16) >> 2) + 1) & ~1; }
-__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 32 * single_copy_stride(n16); }
+// the block's first column, as copies shifted by 0..CP-1 bytes, of
+// single_copy_stride dwords each; two buffers of 4 rows.  Templates 48 or 64
+// wide take 16 copies (every A lane reads its 16 bytes in one aligned read;
+// the copy stride, 4 mod 8 dwords, puts the 64 lanes' rows on distinct
+// banks), the others 8 copies (two 8-byte reads at 8-byte boundaries): for
+// 16 or 32 columns the extra staging costs more than the aligned reads save
+// (measured), and wider templates keep their LDS within three blocks per CU.
+__host__ __device__ inline int single_copies(int n16) { return n16 == 48 || n16 == 64 ? 16 : 8; }
+__host__ __device__ inline int single_copy_stride(int n16)
+{
+    const int ww = (256 + n16 + 16) >> 2;
+    return single_copies(n16) == 16 ? (ww + 3) / 8 * 8 + 4 : (ww + 1) & ~1;
+}
+__host__ __device__ inline int single_tpl_offset(int n16) { return 2 * 4 * single_copies(n16) * single_copy_stride(n16); }
 
 // One 16 RG x 256 block of locations of one template (the body of k_single
 // and of k_dense_tiles).  The caller has staged the template at
@@ -2326,14 +2335,16 @@ struct SingleTile {
 
 // Returns the block's best location (valid in thread 0; the block's LDS is
 // reused; some threads may return before others).
-template <int RG>
+template <int RG, int CP>
 __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t *smem)
 {
     static_assert(RG >= 1 && RG <= 4, "row groups per block");
+    static_assert(CP == 8 || CP == 16, "byte-shifted copies");
     constexpr int MT = 4, ROWS = 16 * RG;
     const int m = a.m, n16 = a.n16, nb16 = n16 >> 4;
-    const int CS = single_copy_stride(n16), WP = CS >> 1;  // staged dword pairs per row
-    const int IMGW = 32 * CS;
+    const int CS = single_copy_stride(n16);
+    const int WP = ((256 + n16 + 16) / 4 + 1) >> 1;  // staged dword pairs per row
+    const int IMGW = 4 * CP * CS;
     const int tstr = batch_tstride(n16 >> 2);
     const uint32_t *tpl_l = smem + 2 * IMGW;  // row -kSinglePadLo of the padded template
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -2347,29 +2358,31 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     // and with no branch around them the compiler can wait for one register
     // set while the other is still in flight.
     // Thread t stages dword pair t of the step (row t / WP, bytes 8p .. 8p + 7
-    // of each copy, from the 16 row bytes at 8p; 4 WP <= 256).
+    // of each copy, from the CP / 4 + 2 row words at 8p; 4 WP <= 256).
+    constexpr int NW = CP / 4 + 2;
     const int sidx = min(t, 4 * WP - 1), srow = sidx / WP, spair = sidx - srow * WP;
-    uint32_t rA[4], rB[4];
-    auto gload = [&](int s, uint32_t (&ri)[4]) {
+    uint32_t rA[NW], rB[NW];
+    auto gload = [&](int s, uint32_t (&ri)[NW]) {
         const int gy = min(y0 + 4 * s + srow, a.p - 1);
-        const int64_t gx = min((int64_t)x0 + 8 * spair, a.pitch - 16);
+        const int64_t gx = min((int64_t)x0 + 8 * spair, a.pitch - 4 * NW);
         const uint32_t *rp = (const uint32_t *)(a.img + (int64_t)gy * a.pitch + gx);
 #pragma unroll
-        for (int k = 0; k < 4; k++)
+        for (int k = 0; k < NW; k++)
             ri[k] = *gptr(rp + k);
     };
-    auto lstore = [&](int s, const uint32_t (&ri)[4]) {
+    auto lstore = [&](int s, const uint32_t (&ri)[NW]) {
         if (t < 4 * WP) {
-            uint32_t *b = smem + (s & 1) * IMGW + srow * 8 * CS + 2 * spair;
-            const uint32_t w0 = flip4(ri[0]), w1 = flip4(ri[1]), w2 = flip4(ri[2]), w3 = flip4(ri[3]);
-            *(uint2 *)(b + 0 * CS) = make_uint2(w0, w1);
-            *(uint2 *)(b + 1 * CS) = make_uint2(bytes_at(w1, w0, 1), bytes_at(w2, w1, 1));
-            *(uint2 *)(b + 2 * CS) = make_uint2(bytes_at(w1, w0, 2), bytes_at(w2, w1, 2));
-            *(uint2 *)(b + 3 * CS) = make_uint2(bytes_at(w1, w0, 3), bytes_at(w2, w1, 3));
-            *(uint2 *)(b + 4 * CS) = make_uint2(w1, w2);
-            *(uint2 *)(b + 5 * CS) = make_uint2(bytes_at(w2, w1, 1), bytes_at(w3, w2, 1));
-            *(uint2 *)(b + 6 * CS) = make_uint2(bytes_at(w2, w1, 2), bytes_at(w3, w2, 2));
-            *(uint2 *)(b + 7 * CS) = make_uint2(bytes_at(w2, w1, 3), bytes_at(w3, w2, 3));
+            uint32_t *b = smem + (s & 1) * IMGW + srow * CP * CS + 2 * spair;
+            uint32_t w[NW];
+#pragma unroll
+            for (int k = 0; k < NW; k++)
+                w[k] = flip4(ri[k]);
+#pragma unroll
+            for (int c = 0; c < CP; c++) {  // copy c: row bytes shifted by c
+                const int q = c >> 2, r = c & 3;
+                *(uint2 *)(b + c * CS) = r == 0 ? make_uint2(w[q], w[q + 1])
+                                                : make_uint2(bytes_at(w[q + 1], w[q], r), bytes_at(w[q + 2], w[q + 1], r));
+            }
         }
     };
 
@@ -2385,11 +2398,11 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     gload(1, rB);
     const int g = lane >> 4, jr = lane & 15;
     // A lane (jr, g) reads location column c = 64 wv + 16 mt + jr + 16 cb of
-    // image row g: the copy shifted by c & 7 = jr & 7 bytes, from byte
-    // c & ~7 (two 8-byte reads).  B lane (jr, g) of row group rg reads
-    // template row d + g - jr.
+    // image row g: the copy shifted by c mod CP bytes (jr, or jr & 7), from
+    // byte c rounded down to CP (one 16-byte read, or two 8-byte reads).  B
+    // lane (jr, g) of row group rg reads template row d + g - jr.
     const uint32_t *tpl_b = tpl_l + (g - jr + kSinglePadLo) * tstr;
-    const int a_off = (g * 8 + (jr & 7)) * CS + 16 * wv + 2 * (jr >> 3);
+    const int a_off = CP == 16 ? (g * 16 + jr) * CS + 16 * wv : (g * 8 + (jr & 7)) * CS + 16 * wv + 2 * (jr >> 3);
     auto compute = [&](int s) {
         const uint32_t *pa = smem + (s & 1) * IMGW + a_off;
         const uint32_t *pb[RG];
@@ -2402,9 +2415,14 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
         auto frag = [&](v4i (&A)[MT], v4i (&B)[RG], int cb) {
 #pragma unroll
             for (int mt = 0; mt < MT; mt++) {
-                const uint64_t *q = (const uint64_t *)(pa + 4 * mt + 4 * cb);
-                const uint64_t lo = q[0], hi = q[1];
-                A[mt] = v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi, (int)(uint32_t)(hi >> 32)};
+                if constexpr (CP == 16) {
+                    A[mt] = *(const v4i *)(pa + 4 * mt + 4 * cb);
+                } else {
+                    const uint64_t *q = (const uint64_t *)(pa + 4 * mt + 4 * cb);
+                    const uint64_t lo = q[0], hi = q[1];
+                    A[mt] = v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
+                                (int)(uint32_t)(hi >> 32)};
+                }
             }
 #pragma unroll
             for (int rg = 0; rg < RG; rg++)
@@ -2568,6 +2586,15 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     return block_rec4(r, red);
 }
 
+// The body with the copy count of the template's width.
+template <int RG>
+__device__ RecPod single_tile(const SingleTile &a, int x0, int y0, uint32_t *smem)
+{
+    if (single_copies(a.n16) == 16)
+        return single_tile_body<RG, 16>(a, x0, y0, smem);
+    return single_tile_body<RG, 8>(a, x0, y0, smem);
+}
+
 template <int RG>
 __global__ __launch_bounds__(256, 3) void k_single(const BatchJob *__restrict__ jobs, int njobs)
 {
@@ -2591,7 +2618,7 @@ __global__ __launch_bounds__(256, 3) void k_single(const BatchJob *__restrict__ 
     }
     single_tpl_pads(tpl_l, m, nw16, tstr);
     const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, m, a.n, a.n16, St, Dt};
-    const RecPod best = single_tile_body<RG>(st, bx * 256, by * 16 * RG, smem);
+    const RecPod best = single_tile<RG>(st, bx * 256, by * 16 * RG, smem);
     if (t < 16)
         st_rec(out + t, t == 0 ? best : rec_empty());
 }
@@ -2683,7 +2710,7 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
     single_tpl_pads(tpl_l, a.m, nw16, tstr);
     const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
     const int x0 = tx * kTileCols, y0 = ty * kTileRows;
-    const RecPod best = single_tile_body<2>(st, x0, y0, smem);
+    const RecPod best = single_tile<2>(st, x0, y0, smem);
     if (t == 0) {
         *out = best;
         atomicAdd(&a.qs->n_dense, (unsigned long long)min(kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
