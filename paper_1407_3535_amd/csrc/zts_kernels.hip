@@ -1204,7 +1204,8 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
 
 // ============================================================== scan 2: members
 
-constexpr int kMemGroups = 512;  // groups per k_members block (two per thread)
+constexpr int kMemGPT = 4;                 // groups per k_members thread
+constexpr int kMemGroups = 256 * kMemGPT;  // groups per k_members block
 
 __device__ __forceinline__ bool in_window(int y, int x, int wy, int wx, int radius)
 {
@@ -1282,7 +1283,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
     return base + incl - v;  // tmp must not be written again before the caller's next barrier
 }
 
-// 512 consecutive groups per block (two per thread).  Phase 1: one thread
+// kMemGroups consecutive groups per block (kMemGPT per thread).  Phase 1: one thread
 // per group drops the whole group when the interval of its member angles
 // lies beyond the threshold angle from A.  Phase 2: the members of the
 // remaining groups are tested one per thread slot, up to 4096 per pass, each
@@ -1361,18 +1362,21 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ Best bred[8];
     __shared__ uint32_t s_tc[kBinTiles], s_tb[kBinTiles];
     int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    // This thread's two groups (2t, 2t + 1 of the block), the query state and
+    // This thread's groups (kMemGPT t .. of the block), the query state and
     // the earlier kernels' records are all read in the first round trip.
     const int G = a.Gy * a.Gx;
     const int g0 = blockIdx.x * GB;
-    float A2[2] = {0.0f, 0.0f};
-    GroupSum gs2[2] = {{0.0f, 0.0f, 0.0f, 1}, {0.0f, 0.0f, 0.0f, 1}};
+    float A2[kMemGPT];
+    GroupSum gs2[kMemGPT];
 #pragma unroll
-    for (int e = 0; e < 2; e++)
-        if (g0 + 2 * t + e < G) {
-            A2[e] = a.g_theta[g0 + 2 * t + e];
-            gs2[e] = a.gsum[g0 + 2 * t + e];
+    for (int e = 0; e < kMemGPT; e++) {
+        A2[e] = 0.0f;
+        gs2[e] = GroupSum{0.0f, 0.0f, 0.0f, 1};
+        if (g0 + kMemGPT * t + e < G) {
+            A2[e] = a.g_theta[g0 + kMemGPT * t + e];
+            gs2[e] = a.gsum[g0 + kMemGPT * t + e];
         }
+    }
     const int degenerate = a.qs->degenerate;
     const Thr thr = a.thr_ready
                         ? wave_threshold(a.qs, a.recs + a.n_best0, a.n_win, a.include_best0, a.delta, a.floor)
@@ -1400,10 +1404,11 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     const int ty_hi = min(a.Ly - 1, (glast / a.Gx) * a.h + a.h - 1) / kTileRows;
     const int tile_lo = ty_lo * a.tiles_x, ntl = (ty_hi - ty_lo + 1) * a.tiles_x;
 
-    int cnt2[2] = {0, 0};
+    int cnt2[kMemGPT];
 #pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const int u = 2 * t + e, g = g0 + u;
+    for (int e = 0; e < kMemGPT; e++) {
+        cnt2[e] = 0;
+        const int u = kMemGPT * t + e, g = g0 + u;
         const float A = A2[e];
         const GroupSum gs = gs2[e];
         int &cnt = cnt2[e];
@@ -1450,9 +1455,19 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         }
     }
     int total;
-    const int off = block_excl_scan(cnt2[0] + cnt2[1], s_tmp, &total);
-    s_pref[2 * t] = off;
-    s_pref[2 * t + 1] = off + cnt2[0];
+    int csum = 0;
+#pragma unroll
+    for (int e = 0; e < kMemGPT; e++)
+        csum += cnt2[e];
+    const int off = block_excl_scan(csum, s_tmp, &total);
+    {
+        int o = off;
+#pragma unroll
+        for (int e = 0; e < kMemGPT; e++) {
+            s_pref[kMemGPT * t + e] = o;
+            o += cnt2[e];
+        }
+    }
     if (t == 0) {
         s_pref[GB] = total;
         s_nsurv = 0;
@@ -1461,15 +1476,14 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     RecPod rec = rec_empty();
     for (int base = 0; base < total; base += CAP) {
         int end = min(total, base + CAP);
-        // each thread marks the pass's slots of its two groups with the group,
+        // each thread marks the pass's slots of its groups with the group,
         // so that a member slot finds its group in one read (the previous
         // pass read s_owner before its last barrier)
 #pragma unroll
-        for (int e = 0; e < 2; e++) {
-            const int lo = off + (e ? cnt2[0] : 0);
+        for (int e = 0, lo = off; e < kMemGPT; lo += cnt2[e], e++) {
             const int i0 = max(lo, base), i1 = min(lo + cnt2[e], end);
             for (int i = i0; i < i1; i++)
-                s_owner[i - base] = (uint16_t)(2 * t + e);
+                s_owner[i - base] = (uint16_t)(kMemGPT * t + e);
         }
         __syncthreads();
         // locate this thread's (up to 16) members and load their angles first
@@ -1504,30 +1518,51 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             B8[q] = a.theta_b[(uint32_t)sl];
             C8[q] = a.opta ? a.theta_c[(uint32_t)sl] : 0.0f;
         }
+        // binary32 decisions; members inside the guard band are decided after
+        // the loop by the canonical test, one at a time (they are rare; one
+        // copy of that code keeps the loop small)
+        uint32_t keepm = 0, band = 0;
 #pragma unroll
         for (int q = 0; q < CAP / 256; q++) {
-            bool keep = false;
+            if (!((live >> q) & 1))
+                continue;
+            int u, o32, sl32;
+            member(base + t + 256 * q, u, o32, sl32);
+            const float A = __int_as_float(s_geo[u][3]);
+            const float e = fabsf(A - B8[q]) - C8[q];
+            if (e > hi)
+                continue;  // eliminated
+            if (e < lo)
+                keepm |= 1u << q;
+            else
+                band |= 1u << q;  // inside the guard band, or undefined (a flat block's angle)
+        }
+        while (band) {
+            const int q = __ffs(band) - 1;
+            band &= band - 1;
+            int u, o32, sl32;
+            member(base + t + 256 * q, u, o32, sl32);
+            const int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+            if (keep_canonical(a, o32, sl32, (int64_t)cy * a.Lx + cx, g0 + u, mn, st, dt, thr64))
+                keepm |= 1u << q;
+        }
+#pragma unroll
+        for (int q = 0; q < CAP / 256; q++) {
+            const bool keep = (keepm >> q) & 1;
             int o32 = 0;
             if ((live >> q) & 1) {
-                int u, sl32;
-                member(base + t + 256 * q, u, o32, sl32);
-                const int64_t o = o32, sl = sl32;
-                float A = __int_as_float(s_geo[u][3]);
-                float e = fabsf(A - B8[q]) - C8[q];
-                if (e > hi)
-                    keep = false;
-                else if (e < lo)
-                    keep = true;
-                else {
-                    int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
-                    keep = keep_canonical(a, o, sl, (int64_t)cy * a.Lx + cx, g0 + u, mn, st, dt, thr64);
-                }
-                if (keep)
+                if (keep) {
+                    int u, sl32;
+                    member(base + t + 256 * q, u, o32, sl32);
                     n_surv++;
-                else
+                } else {
                     n_elim++;
-                if (a.dec)
-                    a.dec[o] = keep ? 2 : 0;
+                }
+                if (a.dec) {
+                    int u, sl32;
+                    member(base + t + 256 * q, u, o32, sl32);
+                    a.dec[o32] = keep ? 2 : 0;
+                }
             }
             // the wave's survivors take consecutive list slots: one LDS atomic
             // per wave, each lane's slot from the ballot
