@@ -2176,6 +2176,18 @@ void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, 
         }
         if (!device)
             hip_check(hipMemcpyAsync(dtpl.ptr, h, total, hipMemcpyHostToDevice, st));
+        // The scan-1 launches go to the main stream, one after another; the
+        // templates' own chains (window, scan 2, tiles, reduction) take the
+        // auxiliary streams in turn, each after an event recorded behind its
+        // scan 1, so that one chain's tail overlaps the next one's start.
+        if (!c->aux[0]) {
+            for (int k = 0; k < Ctx::kAuxStreams; k++)
+                hip_check(hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking));
+            for (hipEvent_t &e : c->aux_ev)
+                hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        int next_lane = 0;
+        bool used[Ctx::kAuxStreams] = {};
         for (auto &gr : groups) {
             const std::vector<int> &ks = gr.second;
             const Prepared *P = plans[ks[0]].P;
@@ -2194,11 +2206,24 @@ void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, 
                     sa.more[j - 1] = ScanTpl{o.tpl, o.ts, o.g_x, o.g_theta, o.recs, o.qs, o.tile_cnt};
                 }
                 hip_check(launch_centres(sa, st));
-                for (int j = 0; j < T; j++)
-                    enqueue_after_scan1(Q[ks[i + j]], st);
+                // the scan-1 event of this launch (events are reused: a wait
+                // takes the event's state at the time it is enqueued)
+                hip_check(hipEventRecord(c->aux_ev[0], st));
+                for (int j = 0; j < T; j++) {
+                    const int ln = next_lane;
+                    next_lane = (next_lane + 1) % Ctx::kAuxStreams;
+                    hip_check(hipStreamWaitEvent(c->aux[ln], c->aux_ev[0], 0));
+                    used[ln] = true;
+                    enqueue_after_scan1(Q[ks[i + j]], c->aux[ln]);
+                }
                 i += T;
             }
         }
+        for (int k = 0; k < Ctx::kAuxStreams; k++)
+            if (used[k]) {
+                hip_check(hipEventRecord(c->aux_ev[k + 1], c->aux[k]));
+                hip_check(hipStreamWaitEvent(st, c->aux_ev[k + 1], 0));
+            }
         hip_check(hipStreamSynchronize(st));
         std::atomic_thread_fence(std::memory_order_acquire);
         for (int k = 0; k < count; k++) {
@@ -2330,6 +2355,14 @@ ZTS_API void zts_destroy(zts_ctx *z)
         c.psat.reset();
         c.h_cnt.reset();
         c.h_qs_noalloc.reset();
+        for (int k = 0; k < Ctx::kAuxStreams; k++)
+            if (c.aux[k]) {
+                (void)hipStreamSynchronize(c.aux[k]);
+                (void)hipStreamDestroy(c.aux[k]);
+            }
+        for (hipEvent_t e : c.aux_ev)
+            if (e)
+                (void)hipEventDestroy(e);
         c.main.destroy();
         release_free_blocks(&c);
     }

@@ -192,6 +192,13 @@ struct Ctx {
     std::map<std::pair<int, int>, zts_tune_entry> tuned;
     std::string tune_cache, arch;
     double wall_khz = 100000.0;   // device realtime clock (hipDeviceAttributeWallClockRate)
+    // Streams beside the main one (default priority, non-blocking) for the
+    // batched pruned search, whose templates' kernel chains are independent:
+    // spread over them, one chain's tail overlaps the next chain's start.
+    // Created on first use; events order them against the main stream.
+    static constexpr int kAuxStreams = 3;
+    hipStream_t aux[kAuxStreams] = {};
+    hipEvent_t aux_ev[kAuxStreams + 1] = {};
 };
 
 // The context lock held by the calling thread (a synchronous entry point's or
