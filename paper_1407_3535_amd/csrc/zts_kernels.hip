@@ -1355,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
     __shared__ int s_pref[GB + 1];
     __shared__ uint16_t s_owner[CAP];  // the block group of each member slot of a pass
     __shared__ int s_tmp[4];
-    __shared__ int s_geo[GB][4];  // packed (oy, ox), (hh, ww), (cy, cx), A bits
+    __shared__ int s_geo[GB][2];  // packed (oy, ox), A bits (extents and centre follow from the origin)
     __shared__ int s_list[kSurvList];
     __shared__ int s_nsurv;
     __shared__ RecPod wrec[4];
@@ -1416,9 +1416,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             int oy, ox, hh, ww, cy, cx;
             group_geom(g, a.Gx, a.Ly, a.Lx, a.h, a.w, oy, ox, hh, ww, cy, cx);
             s_geo[u][0] = (oy << 16) | ox;
-            s_geo[u][1] = (hh << 16) | ww;
-            s_geo[u][2] = (cy << 16) | cx;
-            s_geo[u][3] = __float_as_int(A);
+            s_geo[u][1] = __float_as_int(A);
             bool drop = false;
             if (!(gs.flags & 1)) {
                 float d = 0.0f;
@@ -1491,12 +1489,18 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
         // so the tables hold fewer than 2^31 entries); the locations are
         // found again from the owner map when the angles are tested, so that
         // only the angles stay in registers meanwhile
+        auto centre = [&](int u, int &cy, int &cx) {
+            const int oy = s_geo[u][0] >> 16, ox = s_geo[u][0] & 0xffff;
+            cy = oy + (min(a.h, a.Ly - oy) - 1) / 2;
+            cx = ox + (min(a.w, a.Lx - ox) - 1) / 2;
+        };
         auto member = [&](int idx, int &u, int &o, int &sl) {
             u = s_owner[idx - base];
             const int k = idx - s_pref[u];
             const int oy = s_geo[u][0] >> 16, ox = s_geo[u][0] & 0xffff;
-            const int ww = s_geo[u][1] & 0xffff;
-            const int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+            const int ww = min(a.w, a.Lx - ox);
+            int cy, cx;
+            centre(u, cy, cx);
             const int my = k / ww, mx = k - my * ww;
             const int y = oy + my, x = ox + mx;
             sl = (g0 + u) * hw + my * a.w + mx;
@@ -1528,7 +1532,7 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
                 continue;
             int u, o32, sl32;
             member(base + t + 256 * q, u, o32, sl32);
-            const float A = __int_as_float(s_geo[u][3]);
+            const float A = __int_as_float(s_geo[u][1]);
             const float e = fabsf(A - B8[q]) - C8[q];
             if (e > hi)
                 continue;  // eliminated
@@ -1542,7 +1546,8 @@ __global__ __launch_bounds__(256) void k_members(MemArgs a)
             band &= band - 1;
             int u, o32, sl32;
             member(base + t + 256 * q, u, o32, sl32);
-            const int cy = s_geo[u][2] >> 16, cx = s_geo[u][2] & 0xffff;
+            int cy, cx;
+            centre(u, cy, cx);
             if (keep_canonical(a, o32, sl32, (int64_t)cy * a.Lx + cx, g0 + u, mn, st, dt, thr64))
                 keepm |= 1u << q;
         }
