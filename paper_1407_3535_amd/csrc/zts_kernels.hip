@@ -1297,7 +1297,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
 // (block, tile) pair takes one global atomic; blocks whose groups span more
 // than kBinTiles tiles take one atomic per survivor.  All threads call it.
 constexpr int kBinTiles = 256;
-constexpr int kSurvList = 4096;  // survivors a k_members block collects before binning them
+constexpr int kSurvList = 3072;  // survivors a k_members block collects before binning them
 
 __device__ void bin_survivors(const MemArgs &a, const int *s_list, int ns, int tile_lo, int ntl, uint32_t *s_tc,
                               uint32_t *s_tb)
@@ -1347,9 +1347,12 @@ __device__ void bin_survivors(const MemArgs &a, const int *s_list, int ns, int t
     }
 }
 
-__global__ __launch_bounds__(256) void k_members(MemArgs a)
+// Five blocks per CU (96 VGPRs, 31 KB of LDS): the passes wait on their
+// angle loads, so the resident waves set the time.
+__global__ __launch_bounds__(256, 5) void k_members(MemArgs a)
 {
-    constexpr int CAP = kSurvList / 2;  // members per pass: 8 per thread
+    constexpr int CAP = 2048;  // members per pass: 8 per thread
+    static_assert(CAP <= kSurvList, "a pass's survivors fit the list");
     constexpr int GB = kMemGroups;
     static_assert(GB <= 65536, "group slots fit 16 bits");
     __shared__ int s_pref[GB + 1];
