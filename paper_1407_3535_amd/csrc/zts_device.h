@@ -130,11 +130,21 @@ __device__ __forceinline__ bool ub_general(double ra, double sa, double rb, doub
 // rho in binary32: N (D_a D_b)^(-1/2) with v_rsq_f32 (1 ulp); the three
 // conversions, the product and the final multiply round once each, so the
 // absolute error is below 5e-7.  A flat block has rho := 0.
-__device__ __forceinline__ float rho32(int64_t num, int64_t da, int64_t db)
+// The same from the integers held exactly in binary64 (every N and D of a
+// template of at most 16384 pixels is below 2^53): rounding the binary64
+// value to binary32 equals rounding the integer, so both forms agree bit for
+// bit, and kernels that form N and D in binary64 skip the int64 products
+// and conversions.
+__device__ __forceinline__ float rho32_exact(double num, double da, double db)
 {
-    if (da == 0 || db == 0)
+    if (da == 0.0 || db == 0.0)
         return 0.0f;
     return (float)num * __builtin_amdgcn_rsqf((float)da * (float)db);
+}
+
+__device__ __forceinline__ float rho32(int64_t num, int64_t da, int64_t db)
+{
+    return rho32_exact((double)num, (double)da, (double)db);
 }
 
 // atan(z) for z in [0, 1]: z P(z^2) with P of degree 7, coefficients fitted
@@ -161,20 +171,25 @@ __device__ __forceinline__ float atan01(float z)
 // octant of atan2 by atan01 and its reflections.  Absolute error below 1e-6
 // rad (4.5e-7 over 2e5 sampled integer triples, with 1-ulp approximate
 // reciprocal, square root and rsqrt).
-__device__ __forceinline__ float theta32(int64_t num, int64_t da, int64_t db)
+__device__ __forceinline__ float theta32_exact(double nd, double da, double db)
 {
-    if (da == 0 || db == 0)
+    if (da == 0.0 || db == 0.0)
         return __int_as_float(0x7fc00000);
-    const double P = (double)da * (double)db, nd = (double)num;
+    const double P = da * db;
     const double d = P - nd * nd;
     const float pf = (float)P;
     const float s = __builtin_amdgcn_sqrtf(fmaxf((float)d, 0.0f) * __builtin_amdgcn_rcpf(pf));
-    const float r = (float)num * __builtin_amdgcn_rsqf(pf);
+    const float r = (float)nd * __builtin_amdgcn_rsqf(pf);
     const float ar = fabsf(r), lo = fminf(s, ar), hi = fmaxf(s, ar);
     float t = hi > 0.0f ? atan01(lo * __builtin_amdgcn_rcpf(hi)) : 0.0f;
     if (s > ar)
         t = 1.57079633f - t;
     return r < 0.0f ? 3.14159265f - t : t;
+}
+
+__device__ __forceinline__ float theta32(int64_t num, int64_t da, int64_t db)
+{
+    return theta32_exact((double)num, (double)da, (double)db);
 }
 
 // ---------------------------------------------------------------- block statistics

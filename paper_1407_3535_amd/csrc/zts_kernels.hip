@@ -1032,8 +1032,11 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
         // the block's best: they alone are evaluated in binary64 (one at a
         // time per lane, usually one in the whole wave), and the wave's
         // record is picked among those lanes in lane order.
+        // N and D_c formed in binary64, where they are exact (no int64
+        // products or conversions per centre)
         float r32[MTW][4];
         float lmax = -2.0f;
+        const double mnd = (double)mn, dtd = (double)dt, std_ = (double)st;
 #pragma unroll
         for (int mt = 0; mt < MTW; mt++)
 #pragma unroll
@@ -1041,13 +1044,14 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
                 const int gxx = gx0 + 16 * (MTW * wv + mt) + 4 * g + v;
                 const bool ok = gyy < a.Gy && gxx < a.Gx;
                 const int x = acc[ti][mt][v];
-                const int64_t dc = var_num(mn, sc[mt][v]);
-                const int64_t num = mn * (int64_t)x - st * (int64_t)sc[mt][v].x;
-                r32[mt][v] = ok ? rho32(num, dt, dc) : -2.0f;
+                const double S = (double)sc[mt][v].x;
+                const double dc = fma(mnd, (double)(uint32_t)sc[mt][v].y, -S * S);
+                const double num = fma(mnd, (double)x, -std_ * S);
+                r32[mt][v] = ok ? rho32_exact(num, dtd, dc) : -2.0f;
                 if (ok) {
                     const int gi = gyy * a.Gx + gxx;
                     sp.g_x[gi] = x;
-                    sp.g_theta[gi] = theta32(num, dt, dc);
+                    sp.g_theta[gi] = theta32_exact(num, dtd, dc);
                     lmax = fmaxf(lmax, r32[mt][v]);
                     if (ti == 0 && a.dec)
                         a.dec[(int64_t)crow(gyy) * a.Lx + ccol(gxx)] = 1;
