@@ -231,11 +231,22 @@ __device__ __forceinline__ uint32_t wave_dot_tpl_u8(const uint32_t *__restrict__
             const int64_t step = (int64_t)rp * (pitch >> 2);
             const uint32_t *tp = tplw + r0 * n4 + j;
             const int tstep = rp * n4;
-#pragma unroll 8
-            for (int i = r0; i < m; i += rp) {
-                acc = __builtin_amdgcn_udot4(bytes_at(pr[1], pr[0], sh), *tp, acc, false);
-                pr += step;
-                tp += tstep;
+            const int nit = max(0, (m - r0 + rp - 1) / rp);  // rows r0, r0 + rp, ... below m
+            // eight rows' loads issued together (clamped rows, no branch
+            // around a load), then their products: one round trip per eight
+            for (int i0 = 0; i0 < nit; i0 += 8) {
+                uint32_t lo[8], hi[8], tv[8];
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const int i = min(i0 + k, nit - 1);
+                    lo[k] = pr[i * step];
+                    hi[k] = pr[i * step + 1];
+                    tv[k] = tp[i * tstep];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; k++)
+                    if (i0 + k < nit)
+                        acc = __builtin_amdgcn_udot4(bytes_at(hi[k], lo[k], sh), tv[k], acc, false);
             }
         }
     } else {

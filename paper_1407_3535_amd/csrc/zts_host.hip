@@ -1088,7 +1088,7 @@ QueryPlan plan_query(Ctx *c, Slot &S, Image *im, int m, int n, zts_mode mode, co
             int n3 = members_record_count(P->Gy, P->Gx);
             const TileArgs tg = tile_geometry(q);
             const size_t ntile = (size_t)tg.tiles_x * tg.tiles_y;
-            dalloc(c, S.recs, sizeof(RecPod) * ((size_t)n1 + n2 + n3 + ntile + dense_blocks_of(tg)));
+            dalloc(c, S.recs, sizeof(RecPod) * ((size_t)n1 + n2 + n3 + (size_t)tile_record_count(tg)));
             dalloc(c, S.gnum, sizeof(int32_t) * (size_t)P->Gy * P->Gx);
             dalloc(c, S.gtheta, sizeof(float) * (size_t)P->Gy * P->Gx);
             dalloc(c, S.tcnt, sizeof(uint32_t) * ntile);
@@ -1199,7 +1199,7 @@ static void build_query_launch(const QueryPlan &q, const QueryBufs &B, int8_t *d
     Q.n1 = centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w);
     Q.n2 = radius >= 0 ? window_record_count(radius) : 0;
     Q.n3 = members_record_count(P->Gy, P->Gx);
-    Q.n4 = ta.tiles_x * ta.tiles_y + dense_blocks_of(ta);
+    Q.n4 = tile_record_count(ta);
     // records: [0, n1) scan 1, then the window, scan 2 and the survivor tiles
     // (ZTS_OPTA_PAPER: scan 2 and the tiles, then the window on I, whose best
     // is the answer)
@@ -1912,7 +1912,7 @@ static void run_query_noalloc(Ctx *c, Image *im, const uint8_t *tpl, int m, int 
             cap = (size_t)tg.tile_cap;
             nrec = (size_t)centres_record_count(P->Gy, P->Gx, m, n, P->h, P->w) +
                    (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
-                   (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)dense_blocks_of(tg);
+                   (size_t)members_record_count(P->Gy, P->Gx) + (size_t)tile_record_count(tg);
             groups = (size_t)P->Gy * P->Gx;
         }
         const size_t o_qs = take(sizeof(QState)), o_rec = take(sizeof(RecPod) * nrec);
@@ -2162,7 +2162,7 @@ void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, 
             const size_t ntile = (size_t)tg.tiles_x * tg.tiles_y;
             const size_t nrec = (size_t)centres_record_count(P->Gy, P->Gx, q.m, q.n, P->h, P->w) +
                                 (size_t)(radius >= 0 ? window_record_count(radius) : 0) +
-                                (size_t)members_record_count(P->Gy, P->Gx) + ntile + (size_t)dense_blocks_of(tg);
+                                (size_t)members_record_count(P->Gy, P->Gx) + (size_t)tile_record_count(tg);
             PrunedBufs &b = bufs[k];
             dalloc(c, b.qs, sizeof(QState));
             dalloc(c, b.recs, sizeof(RecPod) * nrec);

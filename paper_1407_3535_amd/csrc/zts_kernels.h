@@ -147,6 +147,8 @@ struct TileArgs {
     int dense_min;       // 0: never dense
     int sparse_lds;      // 1: stage the tile's image region in LDS
     int region_words;    // words per staged region row
+    int surv_blocks;     // persistent grids: k_surv_tiles' records come first,
+    int dense_blocks;    // then k_dense_tiles' (0 without a dense path)
     QState *qs;
     RecPod *recs;
     int rec_off;
@@ -280,13 +282,13 @@ hipError_t launch_members(MemArgs a, hipStream_t s);
 int tiles_x_of(int Lx);
 int tiles_y_of(int Ly);
 // Fills the geometry fields of a (n16, dense_min, tile_cap, sparse_lds,
-// region_words) for its m, n and the wanted dense threshold (0: never).
+// region_words, the persistent grids) for its m, n and the wanted dense
+// threshold (0: never), on the current device.
 void tile_plan(TileArgs &a, int dense_min);
-// Blocks of the dense kernel (one per tile; whether a tile is matched whole
-// is decided per super-tile of 4 stacked tiles, 128 x 256 locations): their
-// records follow the tiles' (tiles_x * tiles_y + dense_blocks_of(a) records
-// from rec_off; dense_blocks_of is 0 without a dense path).
-int dense_blocks_of(const TileArgs &a);
+// Records of the two tile kernels from rec_off: one per k_surv_tiles block,
+// then one per k_dense_tiles block (whether a tile is matched whole is
+// decided per super-tile of 4 stacked tiles, 128 x 256 locations).
+int tile_record_count(const TileArgs &a);
 // k_dense_tiles (nothing when a.dense_min is 0), then k_surv_tiles.
 hipError_t launch_dense_tiles(TileArgs a, hipStream_t s);
 hipError_t launch_surv_tiles(TileArgs a, hipStream_t s);

@@ -65,6 +65,38 @@ __device__ __forceinline__ uint32_t tpl_word(const uint8_t *__restrict__ tpl, in
     return nb < 4 ? (w & ((1u << (8 * nb)) - 1u)) : w;
 }
 
+// Word j of template row r as raw uint8 bytes (zero past column n) for
+// word-aligned rows, with no branch around the load (the word index is
+// clamped into the row), so that a caller's unrolled loads stay in flight
+// together.  flip4 of it, masked the same way, is tpl_word's int8 view.
+__device__ __forceinline__ uint32_t tpl_raw_word(const uint8_t *__restrict__ tpl, int64_t ts, int n, int r, int j)
+{
+    const int jj = min(j, (n - 1) >> 2);
+    const uint32_t w = *gptr((const uint32_t *)(tpl + (int64_t)r * ts + 4 * jj));
+    const int nb = n - 4 * j;
+    return nb >= 4 ? w : nb <= 0 ? 0u : w & ((1u << (8 * nb)) - 1u);
+}
+
+// put(i, load(i)) for i = threadIdx.x + k blockDim.x < total, K at a time:
+// each batch's K loads are issued (from clamped indices, without branches)
+// before any of them is used, so they are in flight together instead of
+// one round trip each.
+template <int K, typename Load, typename Put>
+__device__ __forceinline__ void batched_loads(int total, Load load, Put put)
+{
+    const int nt = blockDim.x;
+    for (int base = threadIdx.x; base < total; base += K * nt) {
+        uint32_t v[K];
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            v[k] = load(min(base + k * nt, total - 1));
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (base + k * nt < total)
+                put(base + k * nt, v[k]);
+    }
+}
+
 __device__ void load_template(const uint8_t *__restrict__ tpl, int64_t ts, int m, int n, int n4w, int off,
                               int rows_lds, uint32_t *lds, int *red, int64_t *st, int64_t *sq)
 {
@@ -793,15 +825,34 @@ __device__ __forceinline__ void load_template_rows(const uint8_t *__restrict__ t
     const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
     const uint32_t ones = 0x01010101u;
     int a = 0, a2 = 0;
-    for (int idx = threadIdx.x; idx < (m + 1) * nw16; idx += blockDim.x) {
-        int r = idx / nw16, j = idx - r * nw16;
-        uint32_t w = 0;
-        if (r < m) {
-            w = tpl_word(tpl, ts, n, r, j, words);
-            a = dot4(w, ones, a);
-            a2 = dot4(w, w, a2);
+    if (words) {
+        batched_loads<8>(
+            m * nw16,
+            [&](int idx) {
+                const int r = idx / nw16;
+                return flip4(tpl_raw_word(tpl, ts, n, r, idx - r * nw16));
+            },
+            [&](int idx, uint32_t w) {
+                const int r = idx / nw16, j = idx - r * nw16;
+                const int nb = n - 4 * j;  // flip4 turned the zero bytes past column n into 0x80
+                w = nb >= 4 ? w : nb <= 0 ? 0u : w & ((1u << (8 * nb)) - 1u);
+                a = dot4(w, ones, a);
+                a2 = dot4(w, w, a2);
+                lds[r * tstr + j] = w;
+            });
+        for (int j = threadIdx.x; j < nw16; j += blockDim.x)
+            lds[m * tstr + j] = 0u;
+    } else {
+        for (int idx = threadIdx.x; idx < (m + 1) * nw16; idx += blockDim.x) {
+            int r = idx / nw16, j = idx - r * nw16;
+            uint32_t w = 0;
+            if (r < m) {
+                w = tpl_word(tpl, ts, n, r, j, words);
+                a = dot4(w, ones, a);
+                a2 = dot4(w, w, a2);
+            }
+            lds[r * tstr + j] = w;
         }
-        lds[r * tstr + j] = w;
     }
     *s = a;
     *s2 = a2;
@@ -1153,7 +1204,14 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
 #pragma unroll
     for (int q = 0; q < kWinWords; q++) {
         const int idx = t + 256 * q;
-        tw[q] = idx < nwords ? tpl_word(a.tpl, a.ts, a.n, idx / n4, idx % n4, aligned) : 0u;
+        if (aligned) {  // clamped, so the loads are in flight together
+            const int ci = min(idx, nwords - 1);
+            const uint32_t w = flip4(tpl_raw_word(a.tpl, a.ts, a.n, ci / n4, ci % n4));
+            const int nb = a.n - 4 * (ci % n4);
+            tw[q] = idx < nwords ? (nb >= 4 ? w : w & ((1u << (8 * nb)) - 1u)) : 0u;
+        } else {
+            tw[q] = idx < nwords ? tpl_word(a.tpl, a.ts, a.n, idx / n4, idx % n4, aligned) : 0u;
+        }
     }
     const Best b0 = reduce_best(a.recs, 0, a.rec_off, bred);  // best scan-1 centre (has barriers)
     if (degenerate)
@@ -1223,6 +1281,16 @@ __device__ void load_template_words(const uint8_t *__restrict__ tpl, int64_t ts,
                                     uint32_t *lds)
 {
     const bool words = ((ts | (int64_t)(uintptr_t)tpl) & 3) == 0 && (n & 3) == 0;
+    if (words) {
+        batched_loads<8>(
+            m * n4,
+            [&](int idx) {
+                const int r = idx / n4;
+                return tpl_raw_word(tpl, ts, n, r, idx - r * n4);
+            },
+            [&](int idx, uint32_t w) { lds[idx] = w; });
+        return;
+    }
     for (int idx = threadIdx.x; idx < m * n4; idx += blockDim.x) {
         int r = idx / n4, j = idx - (idx / n4) * n4;
         const uint32_t w = tpl_word(tpl, ts, n, r, j, words);  // int8 view, zero past column n
@@ -2383,7 +2451,7 @@ struct SingleTile {
 // Returns the block's best location (valid in thread 0; the block's LDS is
 // reused; some threads may return before others).
 template <int RG, int CP>
-__device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t *smem)
+__device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t *smem, int t)
 {
     static_assert(RG >= 1 && RG <= 4, "row groups per block");
     static_assert(CP == 8 || CP == 16, "byte-shifted copies");
@@ -2394,7 +2462,7 @@ __device__ RecPod single_tile_body(const SingleTile &a, int x0, int y0, uint32_t
     const int IMGW = 4 * CP * CS;
     const int tstr = batch_tstride(n16 >> 2);
     const uint32_t *tpl_l = smem + 2 * IMGW;  // row -kSinglePadLo of the padded template
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int lane = t & 63, wv = t >> 6;
     const int steps = (ROWS + m - 1 + 3) >> 2;
 
     // Image rows stream through two LDS buffers; their global loads are issued
@@ -2638,8 +2706,8 @@ template <int RG>
 __device__ RecPod single_tile(const SingleTile &a, int x0, int y0, uint32_t *smem)
 {
     if (single_copies(a.n16) == 16)
-        return single_tile_body<RG, 16>(a, x0, y0, smem);
-    return single_tile_body<RG, 8>(a, x0, y0, smem);
+        return single_tile_body<RG, 16>(a, x0, y0, smem, threadIdx.x);
+    return single_tile_body<RG, 8>(a, x0, y0, smem, threadIdx.x);
 }
 
 template <int RG>
@@ -2690,11 +2758,21 @@ __device__ __forceinline__ uint32_t wave_dot_lds_u8(const uint32_t *__restrict__
             const int step = rp * rsw;
             const uint32_t *tp = tplw + r0 * n4 + j;
             const int tstep = rp * n4;
-#pragma unroll 8
-            for (int i = r0; i < m; i += rp) {
-                acc = __builtin_amdgcn_udot4(bytes_at(pr[1], pr[0], sh), *tp, acc, false);
-                pr += step;
-                tp += tstep;
+            const int nit = max(0, (m - r0 + rp - 1) / rp);  // rows r0, r0 + rp, ... below m
+            // eight rows' reads issued together (clamped), then their products
+            for (int i0 = 0; i0 < nit; i0 += 8) {
+                uint32_t lo[8], hi[8], tv[8];
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const int i = min(i0 + k, nit - 1);
+                    lo[k] = pr[i * step];
+                    hi[k] = pr[i * step + 1];
+                    tv[k] = tp[i * tstep];
+                }
+#pragma unroll
+                for (int k = 0; k < 8; k++)
+                    if (i0 + k < nit)
+                        acc = __builtin_amdgcn_udot4(bytes_at(hi[k], lo[k], sh), tv[k], acc, false);
             }
         }
     } else {
@@ -2728,118 +2806,202 @@ __device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
     return sum >= 4 * a.dense_min || most >= a.dense_min;
 }
 
-// Dense tiles: one block per survivor tile (32 x 256 locations); a tile of a
-// dense super-tile (super_dense: the decision is taken per 128 x 256
-// super-tile, so that scattered survivors do not split it) is matched whole
-// on int8 MFMA with the k_single body: the locations scan 2 eliminated lie
-// below the threshold, so they cannot be the answer, and the counts stay
-// those of the decisions.  Others write an empty record and are left to
-// k_surv_tiles.
+// The tiles of a persistent tile-kernel block: b, b + G, b + 2G, ... (G
+// blocks, at most 256 tiles each, so that clustered work spreads over the
+// blocks).  One round trip: thread k asks `want` about tile b + kG, and the
+// tiles it accepts (value > 0) are listed in tile order with their values.
+// Returns how many; all threads call it (s_tv may be null).
+template <typename F>
+__device__ int block_tiles(int ntiles, F want, int *s_tl, int *s_tv, int *s_tmp)
+{
+    const int tile = (int)blockIdx.x + (int)threadIdx.x * (int)gridDim.x;
+    const int v = tile < ntiles ? want(tile) : 0;
+    int total;
+    const int off = block_excl_scan(v > 0 ? 1 : 0, s_tmp, &total);
+    if (v > 0) {
+        s_tl[off] = tile;
+        if (s_tv)
+            s_tv[off] = v;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Dense tiles (32 x 256 locations): a tile of a dense super-tile (super_dense:
+// the decision is taken per 128 x 256 super-tile, so that scattered
+// survivors do not split it) is matched whole on int8 MFMA with the k_single
+// body: the locations scan 2 eliminated lie below the threshold, so they
+// cannot be the answer, and the counts stay those of the decisions.  The
+// grid is persistent (as many blocks as the device holds at once): each
+// block lists its dense tiles in one round trip, stages the template once
+// and matches the tiles one after another, writing one record.
+template <int CP>
 __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
 {
     static_assert(kTileRows == 32, "a dense tile is one block of two row groups");
     extern __shared__ __align__(16) uint32_t smem[];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int ty = b / a.tiles_x, tx = b - (b / a.tiles_x) * a.tiles_x;
-    RecPod *out = a.recs + a.rec_off + (int64_t)a.tiles_x * a.tiles_y + b;
-    if (a.qs->degenerate || !super_dense(a, ty >> 2, tx)) {
-        if (t == 0)
-            *out = rec_empty();
-        return;
+    __shared__ int s_tl[256], s_tmp[4];
+    const int t = threadIdx.x;
+    const int degenerate = a.qs->degenerate;
+    const int nd = block_tiles(
+        a.tiles_x * a.tiles_y,
+        [&](int tile) {
+            const int ty = tile / a.tiles_x;
+            return !degenerate && super_dense(a, ty >> 2, tile - ty * a.tiles_x) ? 1 : 0;
+        },
+        s_tl, (int *)nullptr, s_tmp);
+    // the block's record and area stay in LDS, so that no register is live
+    // across the tiles' main loops
+    __shared__ RecPod s_best;
+    if (t == 0)
+        s_best = rec_empty();
+    if (nd > 0) {
+        const int nw16 = a.n16 >> 2, tstr = batch_tstride(nw16);
+        uint32_t *tpl_l = smem + single_tpl_offset(a.n16);
+        const bool words = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
+        if (words) {
+            batched_loads<8>(
+                a.m * nw16,
+                [&](int idx) {
+                    const int r = idx / nw16;
+                    return tpl_raw_word(a.tpl, a.ts, a.n, r, idx - r * nw16);
+                },
+                [&](int idx, uint32_t w) {
+                    const int r = idx / nw16, c = idx - r * nw16, nb = a.n - 4 * c;
+                    w = flip4(w);  // int8 view; the bytes past column n back to zero
+                    tpl_l[(r + kSinglePadLo) * tstr + c] = nb >= 4 ? w : nb <= 0 ? 0u : w & ((1u << (8 * nb)) - 1u);
+                });
+        } else {
+            for (int idx = t; idx < a.m * nw16; idx += 256) {
+                const int r = idx / nw16, c = idx - r * nw16;
+                tpl_l[(r + kSinglePadLo) * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
+            }
+        }
+        single_tpl_pads(tpl_l, a.m, nw16, tstr);
+        const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
+#pragma unroll 1
+        for (int i = 0; i < nd; i++) {
+            const int tile = s_tl[i];
+            const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+            // the thread index passes through an empty asm, so that nothing
+            // the body derives from it is hoisted out of this loop (it would
+            // stay live across the main loop and spill)
+            int tv = t;
+            asm volatile("" : "+v"(tv));
+            const RecPod r = single_tile_body<2, CP>(st, tx * kTileCols, ty * kTileRows, smem, tv);
+            if (t == 0)
+                rec_merge(s_best, r);  // thread 0 holds the tile's record
+            __syncthreads();  // the next tile restages the LDS this one's epilogue read
+        }
     }
-    const int nw16 = a.n16 >> 2, tstr = batch_tstride(nw16);
-    uint32_t *tpl_l = smem + single_tpl_offset(a.n16);
-    const bool words = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
-    for (int idx = t; idx < a.m * nw16; idx += 256) {
-        const int r = idx / nw16, c = idx - r * nw16;
-        tpl_l[(r + kSinglePadLo) * tstr + c] = tpl_word(a.tpl, a.ts, a.n, r, c, words);
-    }
-    single_tpl_pads(tpl_l, a.m, nw16, tstr);
-    const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
-    const int x0 = tx * kTileCols, y0 = ty * kTileRows;
-    const RecPod best = single_tile<2>(st, x0, y0, smem);
     if (t == 0) {
-        *out = best;
-        atomicAdd(&a.qs->n_dense, (unsigned long long)min(kTileRows, a.Ly - y0) * min(kTileCols, a.Lx - x0));
+        unsigned long long area = 0;
+        for (int i = 0; i < nd; i++) {
+            const int ty = s_tl[i] / a.tiles_x, tx = s_tl[i] - ty * a.tiles_x;
+            area += (unsigned long long)min(kTileRows, a.Ly - ty * kTileRows) * min(kTileCols, a.Lx - tx * kTileCols);
+        }
+        a.recs[a.rec_off + a.surv_blocks + blockIdx.x] = s_best;
+        if (area)
+            atomicAdd(&a.qs->n_dense, area);
     }
 }
 
-// One block per survivor tile (after scan 2 has binned the survivors).  An
-// empty tile, or one of a super-tile k_dense_tiles matched whole, writes an
-// empty record.  Otherwise (fewer than dense_min survivors, all in its bin)
-// each listed survivor is matched by one wave with unsigned dot products,
-// from the tile's image region staged in LDS when it fits and the tile has
-// more than kSparseDirect survivors, else from global memory.  One record per
-// tile.
+// Sparse tiles (after scan 2 has binned the survivors): a tile with
+// survivors that is not part of a dense super-tile (fewer than dense_min
+// survivors, all in its bin) has each listed survivor matched by one wave
+// with unsigned dot products, from the tile's image region staged in LDS
+// when it fits and the tile has more than kSparseDirect survivors, else from
+// global memory.  Persistent grid as in k_dense_tiles: each block lists its
+// sparse tiles in one round trip (empty and dense tiles cost nothing more),
+// stages the template once and writes one record.
 constexpr int kSparseDirect = 16;  // survivors of a tile matched without staging its region
 
 __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
 {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ RecPod red4[4];
-    const int tile = blockIdx.x;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int cnt = (int)a.tile_cnt[tile];
-    const int ty = tile / a.tiles_x, tx = tile - (tile / a.tiles_x) * a.tiles_x;
-    if (cnt == 0 || a.qs->degenerate || super_dense(a, ty >> 2, tx)) {  // nothing here, or k_dense_tiles' work
-        if (t == 0)
-            a.recs[a.rec_off + tile] = rec_empty();
-        return;
-    }
-    const int y0 = ty * kTileRows, x0 = tx * kTileCols;
-    const int64_t St = a.qs->st, Dt = a.qs->dt;
-    const int64_t mn = (int64_t)a.m * a.n;
-    const int n4 = (a.n + 3) >> 2;
-    const int rsw = a.region_words;
-    uint32_t *tplw = smem;
-    uint32_t *reg = smem + ((a.m * n4 + 3) & ~3);
-    load_template_words(a.tpl, a.ts, a.m, a.n, n4, tplw);
-    // a few survivors read their windows from global memory: staging the
-    // whole region would cost more than it saves
-    const bool staged = a.sparse_lds && cnt > kSparseDirect;
-    if (staged) {
-        // rows y0 .. y0 + 31 + m - 1 (clipped to the image), words from x0
-        const int R = min(kTileRows + a.m - 1, a.p - y0);
-        const uint8_t *base = a.img + (int64_t)y0 * a.pitch + x0;
-        const int wmax = (int)min((int64_t)rsw, (a.pitch - x0) >> 2);
-        for (int idx = t; idx < R * rsw; idx += 256) {
-            const int r = idx / rsw, w = idx - (idx / rsw) * rsw;
-            reg[idx] = w < wmax ? *gptr((const uint32_t *)(base + (int64_t)r * a.pitch + 4 * w)) : 0u;
-        }
-    }
-    __syncthreads();
-    const int c = min(cnt, a.tile_cap);
-    const int32_t *bin = a.tile_bin + (int64_t)tile * a.tile_cap;
+    __shared__ int s_tl[256], s_tv[256], s_tmp[4];
+    const int t = threadIdx.x;
+    const int degenerate = a.qs->degenerate;
+    const int ns = block_tiles(
+        a.tiles_x * a.tiles_y,
+        [&](int tile) {
+            const int ty = tile / a.tiles_x;
+            const bool sd = super_dense(a, ty >> 2, tile - ty * a.tiles_x);
+            const int cnt = (int)a.tile_cnt[tile];
+            return degenerate || sd ? 0 : cnt;  // nothing here, or k_dense_tiles' work
+        },
+        s_tl, s_tv, s_tmp);
     RecPod rec = rec_empty();
-    // this wave's survivors wv, wv + 4, ... in batches of 64: lane L reads the
-    // location and statistics of the batch's survivor L in one round trip
-    for (int kb = wv; kb < c; kb += 4 * 64) {
-        const int ks = kb + 4 * lane;
-        const int ol = ks < c ? bin[ks] : 0;
-        const int2 sol = ks < c ? a.stat[ol] : make_int2(0, 0);
-        const int nbat = min(64, (c - kb + 3) >> 2);
-        // the wave's sums, one survivor after another; lane q keeps survivor
-        // q's, and the batch's epilogues then run in parallel
-        uint32_t mine = 0;
-        for (int q = 0; q < nbat; q++) {
-            const int o32 = __shfl(ol, q);
-            const int y = o32 / a.Lx, x = o32 - y * a.Lx;
-            const uint32_t Xu = staged ? wave_dot_lds_u8(tplw, n4, reg, rsw, y - y0, x - x0, a.m, lane)
-                                       : wave_dot_tpl_u8(tplw, n4, a.img, a.pitch, y, x, a.m, lane);
-            mine = lane == q ? Xu : mine;
-        }
-        if (lane < nbat) {
-            // N = mn sum(t r) - sum(t) sum(r) on unshifted values; the shifted
-            // sums S' become sum(x) = S' + 128 mn
-            const int64_t dr = var_num(mn, sol);
-            const int64_t num = mn * (int64_t)mine - (St + 128 * mn) * ((int64_t)sol.x + 128 * mn);
-            rec_offer_inline(rec, rho32(num, Dt, dr), ol, num, Dt, dr);
+    unsigned long long matched = 0;
+    if (ns > 0) {
+        const int64_t St = a.qs->st, Dt = a.qs->dt;
+        const int64_t mn = (int64_t)a.m * a.n;
+        const int n4 = (a.n + 3) >> 2;
+        const int rsw = a.region_words;
+        uint32_t *tplw = smem;
+        uint32_t *reg = smem + ((a.m * n4 + 3) & ~3);
+        load_template_words(a.tpl, a.ts, a.m, a.n, n4, tplw);
+        const int lane = t & 63, wv = t >> 6;
+        for (int i = 0; i < ns; i++) {
+            const int tile = s_tl[i], cnt = s_tv[i];
+            const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+            const int y0 = ty * kTileRows, x0 = tx * kTileCols;
+            // a few survivors read their windows from global memory: staging
+            // the whole region would cost more than it saves
+            const bool staged = a.sparse_lds && cnt > kSparseDirect;
+            if (staged) {
+                // rows y0 .. y0 + 31 + m - 1 (clipped to the image), words from x0
+                const int R = min(kTileRows + a.m - 1, a.p - y0);
+                const uint8_t *base = a.img + (int64_t)y0 * a.pitch + x0;
+                const int wmax = (int)min((int64_t)rsw, (a.pitch - x0) >> 2);
+                batched_loads<8>(
+                    R * rsw,
+                    [&](int idx) {
+                        const int r = idx / rsw, w = idx - r * rsw;
+                        const uint32_t v =
+                            *gptr((const uint32_t *)(base + (int64_t)r * a.pitch + 4 * max(0, min(w, wmax - 1))));
+                        return w < wmax ? v : 0u;
+                    },
+                    [&](int idx, uint32_t v) { reg[idx] = v; });
+            }
+            __syncthreads();  // the template (first tile) and the region are in LDS
+            const int c = min(cnt, a.tile_cap);
+            const int32_t *bin = a.tile_bin + (int64_t)tile * a.tile_cap;
+            // this wave's survivors wv, wv + 4, ... in batches of 64: lane L reads
+            // the location and statistics of the batch's survivor L in one round trip
+            for (int kb = wv; kb < c; kb += 4 * 64) {
+                const int ks = kb + 4 * lane;
+                const int ol = ks < c ? bin[ks] : 0;
+                const int2 sol = ks < c ? a.stat[ol] : make_int2(0, 0);
+                const int nbat = min(64, (c - kb + 3) >> 2);
+                // the wave's sums, one survivor after another; lane q keeps
+                // survivor q's, and the batch's epilogues then run in parallel
+                uint32_t mine = 0;
+                for (int q = 0; q < nbat; q++) {
+                    const int o32 = __shfl(ol, q);
+                    const int y = o32 / a.Lx, x = o32 - y * a.Lx;
+                    const uint32_t Xu = staged ? wave_dot_lds_u8(tplw, n4, reg, rsw, y - y0, x - x0, a.m, lane)
+                                               : wave_dot_tpl_u8(tplw, n4, a.img, a.pitch, y, x, a.m, lane);
+                    mine = lane == q ? Xu : mine;
+                }
+                if (lane < nbat) {
+                    // N = mn sum(t r) - sum(t) sum(r) on unshifted values; the
+                    // shifted sums S' become sum(x) = S' + 128 mn
+                    const int64_t dr = var_num(mn, sol);
+                    const int64_t num = mn * (int64_t)mine - (St + 128 * mn) * ((int64_t)sol.x + 128 * mn);
+                    rec_offer_inline(rec, rho32(num, Dt, dr), ol, num, Dt, dr);
+                }
+            }
+            matched += (unsigned long long)c;
+            __syncthreads();  // the next tile restages the region
         }
     }
     const RecPod best = block_rec4(rec, red4);
     if (t == 0) {
-        a.recs[a.rec_off + tile] = best;
-        atomicAdd(&a.qs->n_sparse, (unsigned long long)c);
+        a.recs[a.rec_off + blockIdx.x] = best;
+        if (matched)
+            atomicAdd(&a.qs->n_sparse, matched);
     }
 }
 
@@ -3416,6 +3578,45 @@ static size_t tiles_sparse_bytes(int m, int n, int sparse_lds, int rsw)
 
 static size_t single_lds_bytes(int m, int n16);
 
+// Blocks of a persistent tile kernel: as many as the device holds at once
+// (occupancy at this dynamic LDS times the CUs, cached per kernel, device
+// and size once the queries succeed), at least one per 256 tiles and at
+// most one per tile.  Without an answer, one block per tile.
+static int tile_blocks(const void *f, size_t lds, int ntiles)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t>, int> memo;
+    int dev = 0, g = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto key = std::make_tuple(f, dev, lds);
+        auto it = memo.find(key);
+        if (it != memo.end()) {
+            g = it->second;
+        } else {
+            int per_cu = 0, cus = 0;
+            if (allow_lds(f, lds) == hipSuccess &&
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, lds) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                per_cu > 0 && cus > 0) {
+                g = per_cu * cus;
+                memo.emplace(key, g);
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+    }
+    if (g <= 0)
+        g = ntiles;
+    return std::max((ntiles + 255) / 256, std::min(g, ntiles));
+}
+
+// The dense-tile kernel with the single-template body's copy count for n16.
+static const void *dense_tiles_kernel(int n16)
+{
+    return single_copies(n16) == 16 ? (const void *)k_dense_tiles<16> : (const void *)k_dense_tiles<8>;
+}
+
 // The staged region is kept to 96 KB so that most tiles' blocks can share a CU.
 constexpr size_t kSparseRegionMax = 96 * 1024;
 
@@ -3430,21 +3631,29 @@ void tile_plan(TileArgs &a, int dense_min)
     const int n4 = (a.n + 3) / 4;
     a.region_words = (64 + n4 + 1) | 1;
     a.sparse_lds = tiles_sparse_bytes(a.m, a.n, 1, a.region_words) <= kSparseRegionMax ? 1 : 0;
+    const int nt = a.tiles_x * a.tiles_y;
+    a.surv_blocks = tile_blocks((const void *)k_surv_tiles, tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words),
+                                nt);
+    a.dense_blocks = a.dense_min > 0 ? tile_blocks(dense_tiles_kernel(a.n16), single_lds_bytes(a.m, a.n16), nt) : 0;
 }
 
 static size_t tiles_lds_bytes(const TileArgs &a) { return tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words); }
 
-int dense_blocks_of(const TileArgs &a) { return a.dense_min > 0 ? a.tiles_x * a.tiles_y : 0; }
+int tile_record_count(const TileArgs &a) { return a.surv_blocks + a.dense_blocks; }
 
 hipError_t launch_dense_tiles(TileArgs a, hipStream_t s)
 {
     if (a.dense_min <= 0)
         return hipSuccess;
     const size_t dl = single_lds_bytes(a.m, a.n16);
-    hipError_t e = allow_lds((const void *)k_dense_tiles, dl);
+    const void *f = dense_tiles_kernel(a.n16);
+    hipError_t e = allow_lds(f, dl);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)dense_blocks_of(a)), dim3(256), dl, s, a);
+    if (a.dense_blocks < 1 || (int64_t)a.dense_blocks * 256 < (int64_t)a.tiles_x * a.tiles_y)
+        return hipErrorInvalidValue;
+    void *args[] = {&a};
+    return hipLaunchKernel(f, dim3((unsigned)a.dense_blocks), dim3(256), args, dl, s);
     return hipGetLastError();
 }
 
@@ -3452,12 +3661,12 @@ hipError_t launch_surv_tiles(TileArgs a, hipStream_t s)
 {
     const size_t lds = tiles_lds_bytes(a);
     const int64_t nt = (int64_t)a.tiles_x * a.tiles_y;
-    if (nt < 1 || nt > INT32_MAX)
+    if (nt < 1 || nt > INT32_MAX || a.surv_blocks < 1 || (int64_t)a.surv_blocks * 256 < nt)
         return hipErrorInvalidValue;
     hipError_t e = allow_lds((const void *)k_surv_tiles, lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_surv_tiles, dim3((unsigned)nt), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_surv_tiles, dim3((unsigned)a.surv_blocks), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
