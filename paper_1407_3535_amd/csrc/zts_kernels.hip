@@ -312,8 +312,17 @@ __device__ Thr wave_threshold(const QState *qs, const RecPod *wrecs, int n2, int
 {
     const Best f0 = {qs->best0, qs->best0_l, 1};
     Best fw = {-2.0, INT64_MAX, 0};
-    for (int k = threadIdx.x & 63; k < n2; k += 64)
-        best_merge(fw, wrecs[k].rho, wrecs[k].l, wrecs[k].valid);
+    for (int k = threadIdx.x & 63; k < n2; k += 64) {
+        // flag and value loaded together (a select, not a branch, takes the
+        // record), so that one round trip brings both
+        const double r = wrecs[k].rho;
+        const int64_t l = wrecs[k].l;
+        const int v = wrecs[k].valid;
+        const bool take = (v != 0) & (!fw.valid | rec_better(r, l, fw.rho, fw.l));
+        fw.rho = take ? r : fw.rho;
+        fw.l = take ? l : fw.l;
+        fw.valid = take ? 1 : fw.valid;
+    }
     for (int off = 32; off > 0; off >>= 1) {
         double r = __shfl_xor(fw.rho, off);
         long long l = __shfl_xor((long long)fw.l, off);
@@ -1445,12 +1454,10 @@ __global__ __launch_bounds__(256, 5) void k_members(MemArgs a)
     GroupSum gs2[kMemGPT];
 #pragma unroll
     for (int e = 0; e < kMemGPT; e++) {
-        A2[e] = 0.0f;
-        gs2[e] = GroupSum{0.0f, 0.0f, 0.0f, 1};
-        if (g0 + kMemGPT * t + e < G) {
-            A2[e] = a.g_theta[g0 + kMemGPT * t + e];
-            gs2[e] = a.gsum[g0 + kMemGPT * t + e];
-        }
+        // clamped, unconditional loads: all of them in flight at once
+        const int gc = min(g0 + kMemGPT * t + e, G - 1);
+        A2[e] = a.g_theta[gc];
+        gs2[e] = a.gsum[gc];
     }
     const int degenerate = a.qs->degenerate;
     const Thr thr = a.thr_ready
