@@ -203,12 +203,36 @@ __device__ __forceinline__ void best_merge(Best &a, double rho, int64_t l, int v
     }
 }
 
+// best_merge by selects: the record's flag and value are both loaded
+// before the decision, so a caller's loads need no branch between them.
+__device__ __forceinline__ void best_take(Best &a, double rho, int64_t l, int valid)
+{
+    const bool take = (valid != 0) & (!a.valid | rec_better(rho, l, a.rho, a.l));
+    a.rho = take ? rho : a.rho;
+    a.l = take ? l : a.l;
+    a.valid = take ? 1 : a.valid;
+}
+
 __device__ Best reduce_best(const RecPod *recs, int lo, int hi, Best *red)
 {
     Best b = {-2.0, INT64_MAX, 0};
-    for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        const RecPod *p = recs + k;
-        best_merge(b, p->rho, p->l, p->valid);
+    // four records per thread in flight at once (clamped, unconditional)
+    constexpr int K = 4;
+    const int nt = blockDim.x;
+    for (int k0 = lo + (int)threadIdx.x; k0 < hi; k0 += K * nt) {
+        double r[K];
+        int64_t l[K];
+        int v[K];
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const RecPod *p = recs + min(k0 + q * nt, hi - 1);
+            r[q] = p->rho;
+            l[q] = p->l;
+            v[q] = p->valid;
+        }
+#pragma unroll
+        for (int q = 0; q < K; q++)
+            best_take(b, r[q], l[q], k0 + q * nt < hi ? v[q] : 0);
     }
     for (int off = 32; off > 0; off >>= 1) {
         double r = __shfl_xor(b.rho, off);
@@ -315,13 +339,7 @@ __device__ Thr wave_threshold(const QState *qs, const RecPod *wrecs, int n2, int
     for (int k = threadIdx.x & 63; k < n2; k += 64) {
         // flag and value loaded together (a select, not a branch, takes the
         // record), so that one round trip brings both
-        const double r = wrecs[k].rho;
-        const int64_t l = wrecs[k].l;
-        const int v = wrecs[k].valid;
-        const bool take = (v != 0) & (!fw.valid | rec_better(r, l, fw.rho, fw.l));
-        fw.rho = take ? r : fw.rho;
-        fw.l = take ? l : fw.l;
-        fw.valid = take ? 1 : fw.valid;
+        best_take(fw, wrecs[k].rho, wrecs[k].l, wrecs[k].valid);
     }
     for (int off = 32; off > 0; off >>= 1) {
         double r = __shfl_xor(fw.rho, off);
@@ -1210,15 +1228,18 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
     const int n4 = (a.n + 3) >> 2, nwords = a.m * n4;
     const bool aligned = ((a.ts | (int64_t)(uintptr_t)a.tpl) & 3) == 0 && (a.n & 3) == 0;
     uint32_t tw[kWinWords];
+    if (aligned) {  // clamped indices, no branch around a load: all in flight together
 #pragma unroll
-    for (int q = 0; q < kWinWords; q++) {
-        const int idx = t + 256 * q;
-        if (aligned) {  // clamped, so the loads are in flight together
-            const int ci = min(idx, nwords - 1);
+        for (int q = 0; q < kWinWords; q++) {
+            const int idx = t + 256 * q, ci = min(idx, nwords - 1);
             const uint32_t w = flip4(tpl_raw_word(a.tpl, a.ts, a.n, ci / n4, ci % n4));
             const int nb = a.n - 4 * (ci % n4);
             tw[q] = idx < nwords ? (nb >= 4 ? w : w & ((1u << (8 * nb)) - 1u)) : 0u;
-        } else {
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kWinWords; q++) {
+            const int idx = t + 256 * q;
             tw[q] = idx < nwords ? tpl_word(a.tpl, a.ts, a.n, idx / n4, idx % n4, aligned) : 0u;
         }
     }
@@ -1244,15 +1265,20 @@ __global__ __launch_bounds__(256) void k_window(WinArgs a)
         const int64_t pw = a.pitch >> 2;
         const uint32_t *row0 = (const uint32_t *)(a.img + (((int64_t)y * a.pitch + x) & ~(int64_t)3));
         int acc = 0;
+        // every word from a clamped index (tw is zero past the template), so
+        // that the loads are in flight together
+        uint32_t lo[kWinWords], hi[kWinWords];
 #pragma unroll
         for (int q = 0; q < kWinWords; q++) {
-            const int idx = t + 256 * q;
-            if (idx < nwords) {
-                const int i = idx / n4, j = idx % n4;
-                const uint32_t *pr = row0 + (int64_t)i * pw + j;  // rows carry >= 64 bytes of padding
-                acc = dot4(flip4(bytes_at(pr[1], pr[0], sh)), tw[q], acc);
-            }
+            const int ci = min(t + 256 * q, nwords - 1);
+            const int i = ci / n4, j = ci % n4;
+            const uint32_t *pr = row0 + (int64_t)i * pw + j;  // rows carry >= 64 bytes of padding
+            lo[q] = pr[0];
+            hi[q] = pr[1];
         }
+#pragma unroll
+        for (int q = 0; q < kWinWords; q++)
+            acc = dot4(flip4(bytes_at(hi[q], lo[q], sh)), tw[q], acc);
         for (int idx = t + 256 * kWinWords; idx < nwords; idx += 256) {  // tall, narrow templates
             const int i = idx / n4, j = idx % n4;
             const uint32_t *pr = row0 + (int64_t)i * pw + j;
