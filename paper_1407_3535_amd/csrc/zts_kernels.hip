@@ -953,7 +953,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     // of a centre's window only ever meets a zero template byte: a column
     // past n, or the zero row), and writes the word's four byte-shifted
     // copies.  The host keeps 4 CWn <= 256 KL.
-    uint32_t rA[KL][2], rB[KL][2];
+    uint32_t rA[KL][2], rB[KL][2], rC[KL][2];
     auto gload = [&](int s, uint32_t (&ri)[KL][2]) {
 #pragma unroll
         for (int k = 0; k < KL; k++) {
@@ -996,6 +996,7 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
     lstore(0, rA);
     __syncthreads();
     gload(1, rB);
+    gload(2, rC);
     const int g = lane >> 4, jr = lane & 15;
     // A lane (jr, g) of M-tile mt: centre column gx0 + 16 (MTW wv + mt) + jr
     // (the last one for columns past Gx), byte offset o from the region's
@@ -1051,22 +1052,29 @@ __global__ __launch_bounds__(kCmThreads) void k_centres_mfma(ScanArgs a)
             }
         }
     };
-    // step s reads buffer s & 1; the data of step s + 1 is in rB (s even) or
-    // rA (s odd) and goes to the other buffer, free since the last barrier.
-    // Loads past the last step are issued too (clamped rows, never stored),
-    // so that every wait counts the same loads in flight.
-    for (int s = 0; s < steps; s += 2) {
-        gload(s + 2, rA);
+    // step s reads buffer s & 1; the data of step s + 1 (loaded three steps
+    // ahead, into rA, rB, rC by turns) goes to the other buffer, free since
+    // the last barrier.  Loads past the last step are issued too (clamped
+    // rows, never stored), so that every wait counts the same loads in flight.
+    for (int s = 0; s < steps; s += 3) {
+        gload(s + 3, rA);
         compute(s);
         if (s + 1 < steps)
             lstore(s + 1, rB);
         __syncthreads();
         if (s + 1 >= steps)
             break;
-        gload(s + 3, rB);
+        gload(s + 4, rB);
         compute(s + 1);
         if (s + 2 < steps)
-            lstore(s + 2, rA);
+            lstore(s + 2, rC);
+        __syncthreads();
+        if (s + 2 >= steps)
+            break;
+        gload(s + 5, rC);
+        compute(s + 2);
+        if (s + 3 < steps)
+            lstore(s + 3, rA);
         __syncthreads();
     }
     // template statistics of every template at once
