@@ -2188,7 +2188,10 @@ void run_pruned_batch(Ctx *c, Image *im, int count, const uint8_t *const *tpls, 
         }
         int next_lane = 0;
         bool used[Ctx::kAuxStreams] = {};
-        for (auto &gr : groups) {
+        // the largest templates first: their scan 1 is the longest, and the
+        // smaller sizes' scans then overlap with the larger ones' chains
+        for (auto git = groups.rbegin(); git != groups.rend(); ++git) {
+            auto &gr = *git;
             const std::vector<int> &ks = gr.second;
             const Prepared *P = plans[ks[0]].P;
             const bool shared = ks.size() > 1 && centres_mfma_batchable(P->Gy, P->Gx, gr.first.first, gr.first.second, P->w, 2);

@@ -291,9 +291,27 @@ __device__ Thr block_threshold(const RecPod *recs, int n1, int n2, int include_b
     // one pass over both record ranges: every load is issued before the
     // wave and block merges (red holds two entries per wave)
     Best b0 = {-2.0, INT64_MAX, 0}, bw = {-2.0, INT64_MAX, 0};
-    for (int k = threadIdx.x; k < n1 + n2; k += blockDim.x) {
-        const RecPod *p = recs + k;
-        best_merge(k < n1 ? b0 : bw, p->rho, p->l, p->valid);
+    // four records per thread in flight at once (clamped, unconditional
+    // loads; the merges are selects)
+    constexpr int K = 4;
+    const int nt = blockDim.x, hi = n1 + n2;
+    for (int k0 = (int)threadIdx.x; k0 < hi; k0 += K * nt) {
+        double r[K];
+        int64_t l[K];
+        int v[K];
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const RecPod *p = recs + min(k0 + q * nt, hi - 1);
+            r[q] = p->rho;
+            l[q] = p->l;
+            v[q] = p->valid;
+        }
+#pragma unroll
+        for (int q = 0; q < K; q++) {
+            const int k = k0 + q * nt;
+            best_take(b0, r[q], l[q], k < n1 ? v[q] : 0);
+            best_take(bw, r[q], l[q], k >= n1 && k < hi ? v[q] : 0);
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         double r0 = __shfl_xor(b0.rho, off), r1 = __shfl_xor(bw.rho, off);
