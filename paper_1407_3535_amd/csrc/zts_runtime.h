@@ -196,7 +196,7 @@ struct Ctx {
     // batched pruned search, whose templates' kernel chains are independent:
     // spread over them, one chain's tail overlaps the next chain's start.
     // Created on first use; events order them against the main stream.
-    static constexpr int kAuxStreams = 3;
+    static constexpr int kAuxStreams = 8;
     hipStream_t aux[kAuxStreams] = {};
     hipEvent_t aux_ev[kAuxStreams + 1] = {};
 };
