@@ -149,6 +149,7 @@ struct TileArgs {
     int region_words;    // words per staged region row
     int surv_blocks;     // persistent grids: k_surv_tiles' records come first,
     int dense_blocks;    // then k_dense_tiles' (0 without a dense path)
+    int surv_parts;      // parts a sparse tile's survivors may be split into
     QState *qs;
     RecPod *recs;
     int rec_off;

@@ -2970,10 +2970,23 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
 // survivors, all in its bin) has each listed survivor matched by one wave
 // with unsigned dot products, from the tile's image region staged in LDS
 // when it fits and the tile has more than kSparseDirect survivors, else from
-// global memory.  Persistent grid as in k_dense_tiles: each block lists its
-// sparse tiles in one round trip (empty and dense tiles cost nothing more),
-// stages the template once and writes one record.
-constexpr int kSparseDirect = 16;  // survivors of a tile matched without staging its region
+// global memory.  Persistent grid as in k_dense_tiles over (tile, part)
+// items: for templates of at least kSurvSplitArea pixels a tile's survivors
+// are split into up to kSurvParts parts of at least kSurvPartMin, each
+// matched by the block that draws the item (so the survivors near the answer
+// are not one block's serial work; for smaller templates the restaging
+// costs more than the split saves); each block lists its items in one round
+// trip (empty and dense tiles cost nothing more), stages the template once
+// and writes one record.
+constexpr int kSparseDirect = 16;  // survivors of a part matched without staging its region
+constexpr int kSurvParts = 4;
+constexpr int kSurvPartMin = 24;
+constexpr int kSurvSplitArea = 64 * 64;
+
+__host__ __device__ inline int surv_parts_of(int c, int parts)
+{
+    return min(parts, max(1, (c + kSurvPartMin - 1) / kSurvPartMin));
+}
 
 __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
 {
@@ -2982,13 +2995,16 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
     __shared__ int s_tl[256], s_tv[256], s_tmp[4];
     const int t = threadIdx.x;
     const int degenerate = a.qs->degenerate;
+    const int P = a.surv_parts;
     const int ns = block_tiles(
-        a.tiles_x * a.tiles_y,
-        [&](int tile) {
+        a.tiles_x * a.tiles_y * P,
+        [&](int item) {
+            const int tile = item / P, part = item - tile * P;
             const int ty = tile / a.tiles_x;
             const bool sd = super_dense(a, ty >> 2, tile - ty * a.tiles_x);
-            const int cnt = (int)a.tile_cnt[tile];
-            return degenerate || sd ? 0 : cnt;  // nothing here, or k_dense_tiles' work
+            const int cnt = min((int)a.tile_cnt[tile], a.tile_cap);
+            // nothing here, k_dense_tiles' work, or a part the tile does not have
+            return degenerate || sd || part >= surv_parts_of(cnt, P) ? 0 : cnt;
         },
         s_tl, s_tv, s_tmp);
     RecPod rec = rec_empty();
@@ -3003,12 +3019,14 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
         load_template_words(a.tpl, a.ts, a.m, a.n, n4, tplw);
         const int lane = t & 63, wv = t >> 6;
         for (int i = 0; i < ns; i++) {
-            const int tile = s_tl[i], cnt = s_tv[i];
+            const int tile = s_tl[i] / P, part = s_tl[i] - tile * P, cnt = s_tv[i];
+            const int np = surv_parts_of(cnt, P);
+            const int k0 = (int)((int64_t)cnt * part / np), k1 = (int)((int64_t)cnt * (part + 1) / np);
             const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
             const int y0 = ty * kTileRows, x0 = tx * kTileCols;
             // a few survivors read their windows from global memory: staging
             // the whole region would cost more than it saves
-            const bool staged = a.sparse_lds && cnt > kSparseDirect;
+            const bool staged = a.sparse_lds && k1 - k0 > kSparseDirect;
             if (staged) {
                 // rows y0 .. y0 + 31 + m - 1 (clipped to the image), words from x0
                 const int R = min(kTileRows + a.m - 1, a.p - y0);
@@ -3024,9 +3042,9 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
                     },
                     [&](int idx, uint32_t v) { reg[idx] = v; });
             }
-            __syncthreads();  // the template (first tile) and the region are in LDS
-            const int c = min(cnt, a.tile_cap);
-            const int32_t *bin = a.tile_bin + (int64_t)tile * a.tile_cap;
+            __syncthreads();  // the template (first item) and the region are in LDS
+            const int c = k1 - k0;  // this part's survivors: bin slots k0 .. k1 - 1
+            const int32_t *bin = a.tile_bin + (int64_t)tile * a.tile_cap + k0;
             // this wave's survivors wv, wv + 4, ... in batches of 64: lane L reads
             // the location and statistics of the batch's survivor L in one round trip
             for (int kb = wv; kb < c; kb += 4 * 64) {
@@ -3053,7 +3071,7 @@ __global__ __launch_bounds__(256) void k_surv_tiles(TileArgs a)
                 }
             }
             matched += (unsigned long long)c;
-            __syncthreads();  // the next tile restages the region
+            __syncthreads();  // the next item restages the region
         }
     }
     const RecPod best = block_rec4(rec, red4);
@@ -3691,8 +3709,9 @@ void tile_plan(TileArgs &a, int dense_min)
     a.region_words = (64 + n4 + 1) | 1;
     a.sparse_lds = tiles_sparse_bytes(a.m, a.n, 1, a.region_words) <= kSparseRegionMax ? 1 : 0;
     const int nt = a.tiles_x * a.tiles_y;
+    a.surv_parts = a.m * a.n >= kSurvSplitArea ? kSurvParts : 1;
     a.surv_blocks = tile_blocks((const void *)k_surv_tiles, tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words),
-                                nt);
+                                nt * a.surv_parts);
     a.dense_blocks = a.dense_min > 0 ? tile_blocks(dense_tiles_kernel(a.n16), single_lds_bytes(a.m, a.n16), nt) : 0;
 }
 
@@ -3720,7 +3739,8 @@ hipError_t launch_surv_tiles(TileArgs a, hipStream_t s)
 {
     const size_t lds = tiles_lds_bytes(a);
     const int64_t nt = (int64_t)a.tiles_x * a.tiles_y;
-    if (nt < 1 || nt > INT32_MAX || a.surv_blocks < 1 || (int64_t)a.surv_blocks * 256 < nt)
+    if (nt < 1 || a.surv_parts < 1 || a.surv_parts > kSurvParts || nt * a.surv_parts > INT32_MAX ||
+        a.surv_blocks < 1 || (int64_t)a.surv_blocks * 256 < nt * a.surv_parts)
         return hipErrorInvalidValue;
     hipError_t e = allow_lds((const void *)k_surv_tiles, lds);
     if (e != hipSuccess)
