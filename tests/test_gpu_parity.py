@@ -234,9 +234,10 @@ def test_opta_parity(S, case):
 # super-tile of four tiles with four) is matched whole on int8 MFMA; -1: survivor by survivor only; 8: a mix;
 # 0: the built-in value.  Images span several tile rows and columns with ragged edges; the tall template's
 # tiles take the survivor path from global memory (its image region does not fit LDS), the wide one has no
-# MFMA path.
+# MFMA path; the 64 x 64 template's tiles split their survivors into parts matched by different blocks.
 TILE_CASES = [(300, 700, 24, 24, 25.0, "te_fixed"), (420, 300, 40, 17, 30.0, "egs"), (200, 520, 16, 16, 20.0, "opta"),
-              (520, 90, 400, 8, 12.0, "te_fixed"), (150, 600, 20, 150, 20.0, "egs")]
+              (520, 90, 400, 8, 12.0, "te_fixed"), (150, 600, 20, 150, 20.0, "egs"),
+              (230, 600, 64, 64, 30.0, "te_fixed")]
 
 
 @pytest.mark.parametrize("dense", [1, 8, -1, 0])
