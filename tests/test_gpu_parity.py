@@ -271,6 +271,26 @@ def test_survivor_tile_paths(S, case, dense):
     S.unload(i)
 
 
+@pytest.mark.parametrize("dense", [1, -1])
+def test_persistent_tile_grids(S, dense):
+    """More survivor tiles than the tile kernels' persistent grids hold blocks (2600 x 4200 image, 16 x 16
+    template: 1,377 tiles of 32 x 256 locations), so blocks match several tiles in turn, all dense (1) or all
+    survivor by survivor (-1): answer, counts and decision map equal the oracle's."""
+    print(f"persistent tile grids dense {dense}", flush=True)
+    img = aerial_image(2600, 4200, 4242, beta=2.2)
+    i = S.load(img)
+    tpl, _ = cut_template(img, 16, 16, 4243, 20.0, affine=True)
+    full = O.full_search(img, tpl)
+    g, dec = S.search(i, tpl, "te_fixed", decision=True, group_h=3, group_w=3, refine_radius=2,
+                      tile_dense_min=dense)
+    same_answer(g, full, f"persistent tiles dense {dense}")
+    ot = O.te_search(img, tpl, 3, 3, decision=True, radius=2)
+    same_counts(g, ot, f"persistent tiles dense {dense}")
+    assert np.array_equal(dec, ot["decision"])
+    assert g["n_survivors"] > 100000
+    S.unload(i)
+
+
 @pytest.mark.parametrize("radius", [3, 5, 9])
 def test_large_refinement_windows(S, radius):
     """Refinement windows of 49 to 361 locations (more than one wave's lanes for scan 2's threshold), with
