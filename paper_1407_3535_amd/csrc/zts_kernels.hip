@@ -2871,9 +2871,9 @@ __device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
 // tiles it accepts (value > 0) are listed in tile order with their values.
 // Returns how many; all threads call it (s_tv may be null).
 template <typename F>
-__device__ int block_tiles(int ntiles, F want, int *s_tl, int *s_tv, int *s_tmp)
+__device__ int block_tiles(int ntiles, F want, int *s_tl, int *s_tv, int *s_tmp, int base = -1)
 {
-    const int tile = (int)blockIdx.x + (int)threadIdx.x * (int)gridDim.x;
+    const int tile = (base < 0 ? (int)blockIdx.x : base) + (int)threadIdx.x * (int)gridDim.x;
     const int v = tile < ntiles ? want(tile) : 0;
     int total;
     const int off = block_excl_scan(v > 0 ? 1 : 0, s_tmp, &total);
@@ -2902,13 +2902,29 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
     __shared__ int s_tl[256], s_tmp[4];
     const int t = threadIdx.x;
     const int degenerate = a.qs->degenerate;
+    // Items run down the tile columns (item k: tile row k mod tiles_y of tile
+    // column k / tiles_y), and the blocks an XCD holds (the hardware deals
+    // block ids round-robin over the 8 XCDs) take consecutive items, so the
+    // tiles in flight on one XCD are vertical neighbours whose image rows
+    // overlap in its L2.
+    int vb;
+    {
+        const int nb = gridDim.x, hw = blockIdx.x;
+        const int q8 = nb >> 3, r8 = nb & 7, xcd = hw & 7;
+        vb = xcd * q8 + min(xcd, r8) + (hw >> 3);
+    }
+    auto tile_of = [&](int item) {
+        const int tx = item / a.tiles_y;
+        return (item - tx * a.tiles_y) * a.tiles_x + tx;
+    };
     const int nd = block_tiles(
         a.tiles_x * a.tiles_y,
-        [&](int tile) {
+        [&](int item) {
+            const int tile = tile_of(item);
             const int ty = tile / a.tiles_x;
             return !degenerate && super_dense(a, ty >> 2, tile - ty * a.tiles_x) ? 1 : 0;
         },
-        s_tl, (int *)nullptr, s_tmp);
+        s_tl, (int *)nullptr, s_tmp, vb);
     // the block's record and area stay in LDS, so that no register is live
     // across the tiles' main loops
     __shared__ RecPod s_best;
@@ -2940,7 +2956,7 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
         const SingleTile st{a.img, a.pitch, a.p, a.stat, a.Ly, a.Lx, a.m, a.n, a.n16, a.qs->st, a.qs->dt};
 #pragma unroll 1
         for (int i = 0; i < nd; i++) {
-            const int tile = s_tl[i];
+            const int tile = tile_of(s_tl[i]);
             const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
             // the thread index passes through an empty asm, so that nothing
             // the body derives from it is hoisted out of this loop (it would
@@ -2956,7 +2972,8 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
     if (t == 0) {
         unsigned long long area = 0;
         for (int i = 0; i < nd; i++) {
-            const int ty = s_tl[i] / a.tiles_x, tx = s_tl[i] - ty * a.tiles_x;
+            const int tile = tile_of(s_tl[i]);
+            const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
             area += (unsigned long long)min(kTileRows, a.Ly - ty * kTileRows) * min(kTileCols, a.Lx - tx * kTileCols);
         }
         a.recs[a.rec_off + a.surv_blocks + blockIdx.x] = s_best;
