@@ -2870,6 +2870,24 @@ __device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
 // blocks).  One round trip: thread k asks `want` about tile b + kG, and the
 // tiles it accepts (value > 0) are listed in tile order with their values.
 // Returns how many; all threads call it (s_tv may be null).
+// This block's place among the blocks its XCD holds: the hardware deals
+// block ids round-robin over the 8 XCDs, and this index gives each XCD's
+// blocks a contiguous run (a permutation of the block ids).
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, hw = blockIdx.x;
+    const int q8 = nb >> 3, r8 = nb & 7, xcd = hw & 7;
+    return xcd * q8 + min(xcd, r8) + (hw >> 3);
+}
+
+// Tile k of the column-major order (down each tile column in turn) as a
+// row-major tile index.
+__device__ __forceinline__ int tile_down_columns(int k, int tiles_x, int tiles_y)
+{
+    const int tx = k / tiles_y;
+    return (k - tx * tiles_y) * tiles_x + tx;
+}
+
 template <typename F>
 __device__ int block_tiles(int ntiles, F want, int *s_tl, int *s_tv, int *s_tmp, int base = -1)
 {
@@ -2907,16 +2925,7 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
     // block ids round-robin over the 8 XCDs) take consecutive items, so the
     // tiles in flight on one XCD are vertical neighbours whose image rows
     // overlap in its L2.
-    int vb;
-    {
-        const int nb = gridDim.x, hw = blockIdx.x;
-        const int q8 = nb >> 3, r8 = nb & 7, xcd = hw & 7;
-        vb = xcd * q8 + min(xcd, r8) + (hw >> 3);
-    }
-    auto tile_of = [&](int item) {
-        const int tx = item / a.tiles_y;
-        return (item - tx * a.tiles_y) * a.tiles_x + tx;
-    };
+    auto tile_of = [&](int item) { return tile_down_columns(item, a.tiles_x, a.tiles_y); };
     const int nd = block_tiles(
         a.tiles_x * a.tiles_y,
         [&](int item) {
@@ -2924,7 +2933,7 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
             const int ty = tile / a.tiles_x;
             return !degenerate && super_dense(a, ty >> 2, tile - ty * a.tiles_x) ? 1 : 0;
         },
-        s_tl, (int *)nullptr, s_tmp, vb);
+        s_tl, (int *)nullptr, s_tmp, xcd_block());
     // the block's record and area stay in LDS, so that no register is live
     // across the tiles' main loops
     __shared__ RecPod s_best;
