@@ -3714,6 +3714,8 @@ static int tile_blocks(const void *f, size_t lds, int ntiles)
     return std::max((ntiles + 255) / 256, std::min(g, ntiles));
 }
 
+constexpr int kDenseTilesPerBlock = 4;
+
 // The dense-tile kernel with the single-template body's copy count for n16.
 static const void *dense_tiles_kernel(int n16)
 {
@@ -3738,7 +3740,12 @@ void tile_plan(TileArgs &a, int dense_min)
     a.surv_parts = a.m * a.n >= kSurvSplitArea ? kSurvParts : 1;
     a.surv_blocks = tile_blocks((const void *)k_surv_tiles, tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words),
                                 nt * a.surv_parts);
-    a.dense_blocks = a.dense_min > 0 ? tile_blocks(dense_tiles_kernel(a.n16), single_lds_bytes(a.m, a.n16), nt) : 0;
+    // at most kDenseTilesPerBlock tiles per block: beyond what the device
+    // holds at once, the later blocks start as earlier ones finish, which
+    // evens out the blocks' unequal work
+    a.dense_blocks = a.dense_min > 0 ? std::max(tile_blocks(dense_tiles_kernel(a.n16), single_lds_bytes(a.m, a.n16), nt),
+                                                std::min(nt, (nt + kDenseTilesPerBlock - 1) / kDenseTilesPerBlock))
+                                     : 0;
 }
 
 static size_t tiles_lds_bytes(const TileArgs &a) { return tiles_sparse_bytes(a.m, a.n, a.sparse_lds, a.region_words); }
