@@ -147,7 +147,7 @@ struct TileArgs {
     int dense_min;       // 0: never dense
     int sparse_lds;      // 1: stage the tile's image region in LDS
     int region_words;    // words per staged region row
-    int surv_blocks;     // persistent grids: k_surv_tiles' records come first,
+    int surv_blocks;     // the tile kernels' grids (blocks loop over tiles): k_surv_tiles' records first,
     int dense_blocks;    // then k_dense_tiles' (0 without a dense path)
     int surv_parts;      // parts a sparse tile's survivors may be split into
     QState *qs;
@@ -283,7 +283,7 @@ hipError_t launch_members(MemArgs a, hipStream_t s);
 int tiles_x_of(int Lx);
 int tiles_y_of(int Ly);
 // Fills the geometry fields of a (n16, dense_min, tile_cap, sparse_lds,
-// region_words, the persistent grids) for its m, n and the wanted dense
+// region_words, the tile kernels' grids) for its m, n and the wanted dense
 // threshold (0: never), on the current device.
 void tile_plan(TileArgs &a, int dense_min);
 // Records of the two tile kernels from rec_off: one per k_surv_tiles block,

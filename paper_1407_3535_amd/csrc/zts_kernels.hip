@@ -2865,11 +2865,6 @@ __device__ __forceinline__ bool super_dense(const TileArgs &a, int sy, int tx)
     return sum >= 4 * a.dense_min || most >= a.dense_min;
 }
 
-// The tiles of a persistent tile-kernel block: b, b + G, b + 2G, ... (G
-// blocks, at most 256 tiles each, so that clustered work spreads over the
-// blocks).  One round trip: thread k asks `want` about tile b + kG, and the
-// tiles it accepts (value > 0) are listed in tile order with their values.
-// Returns how many; all threads call it (s_tv may be null).
 // This block's place among the blocks its XCD holds: the hardware deals
 // block ids round-robin over the 8 XCDs, and this index gives each XCD's
 // blocks a contiguous run (a permutation of the block ids).
@@ -2888,6 +2883,12 @@ __device__ __forceinline__ int tile_down_columns(int k, int tiles_x, int tiles_y
     return (k - tx * tiles_y) * tiles_x + tx;
 }
 
+// The items of a tile-kernel block: b, b + G, b + 2G, ... (G blocks, at
+// most 256 items each, so that clustered work spreads over the blocks; b is
+// the block id, or `base` when given).  One round trip: thread k asks `want`
+// about item b + kG, and the items it accepts (value > 0) are listed in
+// order with their values.  Returns how many; all threads call it (s_tv may
+// be null).
 template <typename F>
 __device__ int block_tiles(int ntiles, F want, int *s_tl, int *s_tv, int *s_tmp, int base = -1)
 {
@@ -2909,9 +2910,10 @@ __device__ int block_tiles(int ntiles, F want, int *s_tl, int *s_tv, int *s_tmp,
 // survivors do not split it) is matched whole on int8 MFMA with the k_single
 // body: the locations scan 2 eliminated lie below the threshold, so they
 // cannot be the answer, and the counts stay those of the decisions.  The
-// grid is persistent (as many blocks as the device holds at once): each
-// block lists its dense tiles in one round trip, stages the template once
-// and matches the tiles one after another, writing one record.
+// grid has as many blocks as the device holds at once, and at least one per
+// kDenseTilesPerBlock tiles: each block lists its dense tiles in one round
+// trip, stages the template once and matches the tiles one after another,
+// writing one record.
 template <int CP>
 __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
 {
@@ -2996,8 +2998,8 @@ __global__ __launch_bounds__(256, 3) void k_dense_tiles(TileArgs a)
 // survivors, all in its bin) has each listed survivor matched by one wave
 // with unsigned dot products, from the tile's image region staged in LDS
 // when it fits and the tile has more than kSparseDirect survivors, else from
-// global memory.  Persistent grid as in k_dense_tiles over (tile, part)
-// items: for templates of at least kSurvSplitArea pixels a tile's survivors
+// global memory.  As many blocks as the device holds at once, over (tile,
+// part) items: for templates of at least kSurvSplitArea pixels a tile's survivors
 // are split into up to kSurvParts parts of at least kSurvPartMin, each
 // matched by the block that draws the item (so the survivors near the answer
 // are not one block's serial work; for smaller templates the restaging
@@ -3681,7 +3683,7 @@ static size_t tiles_sparse_bytes(int m, int n, int sparse_lds, int rsw)
 
 static size_t single_lds_bytes(int m, int n16);
 
-// Blocks of a persistent tile kernel: as many as the device holds at once
+// Blocks of a tile kernel that loops over its tiles: as many as the device holds at once
 // (occupancy at this dynamic LDS times the CUs, cached per kernel, device
 // and size once the queries succeed), at least one per 256 tiles and at
 // most one per tile.  Without an answer, one block per tile.
